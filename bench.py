@@ -1,0 +1,206 @@
+"""Throughput of coupled RFA time steps on one MI355X: FP64 Jacobi-PCG vs FP32-inner / FP64-refined.
+
+Workload: the 101^3-node hex cube (1,030,301 DOF, 27,270,901 nnz per matrix), coupled
+potential + bioheat steps of dt = 1 s from the seeded synthetic problem.  A step is one
+pass of the whole hot path: sigma(T) and colour-by-colour assembly of the potential
+matrix, Dirichlet lifting, potential PCG, Joule + bioheat right-hand side, bioheat PCG
+(the bioheat matrix does not depend on T and is assembled once, before timing).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 101]
+
+Prints one JSON line.  value = coupled steps/s of the mixed-precision path when its
+state stays within 1e-8 of the FP64 path's, else of the FP64 path.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TOL = 1e-12
+
+
+def spmv_bytes(n: int, nnz: int, fp32: bool) -> int:
+    """Algorithmic bytes of one CSR SpMV fused with p.Ap: values + column ids + row
+    pointers + x read once + y written once."""
+    w = 4 if fp32 else 8
+    return (w + 4) * nnz + 4 * (n + 1) + 2 * w * n
+
+
+def kernel_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2409_13036_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    entry = data.get(kernel)
+    if not entry or entry.get("kernels_sha") != kernel_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def cpu_baseline_child(n: int) -> None:
+    """Time one coupled step of the CPU oracle (run in a child process, 1 thread)."""
+    import numpy as np
+    import rafem_inputs as ri
+    from oracle.rafem import Model
+
+    p = ri.config1(n=n, steps=1)
+    t0 = time.perf_counter()
+    m = Model(p)
+    setup = time.perf_counter() - t0
+    bio = m.bioheat_system()
+    t0 = time.perf_counter()
+    T, V, info = m.step(p.initial_T(), p.initial_V(), TOL, bioheat=bio)
+    dt = time.perf_counter() - t0
+    print(json.dumps({"step_s": dt, "setup_s": setup, "V_iters": info.V.iters,
+                      "T_iters": info.T.iters}), flush=True)
+
+
+def cpu_baseline(n: int) -> dict:
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                          "--n", str(n)], env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                         text=True, timeout=900)
+    if out.returncode != 0:
+        raise RuntimeError(f"cpu baseline failed:\n{out.stderr[-2000:]}")
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    return {"value": 1.0 / r["step_s"], "unit": "coupled steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one coupled step (potential + bioheat PCG to tol {TOL:g}, "
+                       f"{r['V_iters']}+{r['T_iters']} iterations) of the {n}^3 hex workload from "
+                       f"its initial state, NumPy/SciPy FP64 oracle, 1 thread; mesh setup "
+                       f"({r['setup_s']:.1f} s) excluded"),
+            "host_cpus": len(os.sched_getaffinity(0))}
+
+
+def run_path(dp, precision: str, steps: int, warmup: int, profile_steps: int):
+    import torch
+    from paper_2409_13036_amd import _lib as R
+    dp.reset()
+    for _ in range(warmup):
+        dp.step(TOL, precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(steps):
+        infos.append(dp.step(TOL, precision))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    T_end, V_end = dp.T.clone(), dp.V.clone()
+    # measurement pass: the same kind of steps again, with every PCG SpMV bracketed by events
+    R.profile_enable(dp.mesh, True)
+    R.profile_read(dp.mesh, precision, reset=True)
+    for _ in range(profile_steps):
+        dp.step(TOL, precision)
+    torch.cuda.synchronize()
+    mean_us, count = R.profile_read(dp.mesh, precision, reset=True)
+    R.profile_enable(dp.mesh, False)
+    return elapsed, infos, (T_end, V_end), (mean_us, count)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=101)
+    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-child", action="store_true")
+    args = ap.parse_args()
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args.n)
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the solve is not sharded across GPUs); "
+              f"got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+
+    # CPU oracle first, before this process touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.n)
+    print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
+
+    import numpy as np
+    import torch
+    import rafem_inputs as ri
+    from paper_2409_13036_amd.sim import DeviceProblem
+
+    p = ri.config1(n=args.n, steps=args.steps)
+    dp = DeviceProblem(p)
+    N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
+    res = {}
+    for precision in ("fp64", "mixed"):
+        el, infos, state, (mean_us, count) = run_path(dp, precision, args.steps, args.warmup,
+                                                      args.profile_steps)
+        it_v = float(np.mean([i["V"]["iters"] for i in infos]))
+        it_t = float(np.mean([i["T"]["iters"] for i in infos]))
+        res[precision] = {"elapsed": el, "state": state, "spmv_us": mean_us, "spmv_count": count,
+                          "V_iters": it_v, "T_iters": it_t,
+                          "V_outer": float(np.mean([i["V"]["outer"] for i in infos])),
+                          "relres_true_max": max(max(i["V"]["relres_true"], i["T"]["relres_true"])
+                                                 for i in infos)}
+        print(f"[bench] {precision}: {args.steps / el:.2f} steps/s, V iters {it_v:.1f}, "
+              f"T iters {it_t:.1f}, spmv {mean_us:.1f} us x {count}", file=sys.stderr, flush=True)
+    T64, V64 = res["fp64"]["state"]
+    Tm, Vm = res["mixed"]["state"]
+    errT = float(torch.linalg.norm(Tm - T64) / torch.linalg.norm(T64))
+    errV = float(torch.linalg.norm(Vm - V64) / torch.linalg.norm(V64))
+    mixed_ok = errT <= 1e-8 and errV <= 1e-8
+    head = "mixed" if mixed_ok else "fp64"
+    r = res[head]
+    sps = args.steps / r["elapsed"]
+    fp32 = head == "mixed"
+    kernel = "k_rows<float,4,ROW_DOT>" if fp32 else "k_rows<double,4,ROW_DOT>"
+    per_launch = spmv_bytes(N, nnz, fp32)
+    achieved = per_launch / (r["spmv_us"] * 1e-6) / 1e9 if r["spmv_us"] > 0 else 0.0
+    line = {
+        "metric": "coupled time-step solves/s at 1M DOF (101^3 hex), FP64 vs mixed at 1e-8 rel err; SpMV HBM GB/s",
+        "value": sps, "unit": "coupled steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 / sps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-inner/f64-refined" if fp32 else "f64", "data": "synthetic",
+        "config": {"workload": f"C1 coupled RFA step, {args.n}^3-node hex cube", "n_nodes": N,
+                   "nnz": nnz, "dt_s": p.dt, "tol": TOL, "path": head},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel),
+                     "kernel": kernel, "bytes_per_launch": per_launch,
+                     "mean_launch_us": r["spmv_us"], "launches_measured": r["spmv_count"]},
+        "cpu_baseline": cpu,
+        "fp64": {"steps_per_s": args.steps / res["fp64"]["elapsed"],
+                 "V_iters": res["fp64"]["V_iters"], "T_iters": res["fp64"]["T_iters"],
+                 "spmv_us": res["fp64"]["spmv_us"],
+                 "spmv_GBs": spmv_bytes(N, nnz, False) / (res["fp64"]["spmv_us"] * 1e-6) / 1e9
+                 if res["fp64"]["spmv_us"] > 0 else None,
+                 "relres_true_max": res["fp64"]["relres_true_max"]},
+        "mixed": {"steps_per_s": args.steps / res["mixed"]["elapsed"],
+                  "V_inner_iters": res["mixed"]["V_iters"], "V_outer": res["mixed"]["V_outer"],
+                  "T_inner_iters": res["mixed"]["T_iters"], "spmv_us": res["mixed"]["spmv_us"],
+                  "spmv_GBs": spmv_bytes(N, nnz, True) / (res["mixed"]["spmv_us"] * 1e-6) / 1e9
+                  if res["mixed"]["spmv_us"] > 0 else None,
+                  "relres_true_max": res["mixed"]["relres_true_max"],
+                  "rel_err_vs_fp64": {"T": errT, "V": errV}},
+    }
+    if cpu:
+        line["speedup_vs_cpu_oracle"] = sps / cpu["value"]
+    dp.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,262 @@
+/*
+ * rafem.h -- C ABI of the MI355X (gfx950) library for the per-time-step sparse
+ * solves of a radiofrequency-ablation finite-element model.
+ *
+ * The operations follow the paper's problem statement:
+ *   - each time step assembles the element equations of a tetrahedral (here
+ *     also hexahedral) mesh into one global sparse matrix and solves A x = b
+ *     (Sec. II-A, Fig. 1; Sec. II-B);
+ *   - the global matrix is stored in CSR (Sec. III-A) and its sparsity
+ *     structure does not change between steps, so it is analysed once per mesh
+ *     and reused (Sec. III-B);
+ *   - the solution stays in device memory between assembly and solve
+ *     (Sec. III-A).
+ * Each step is split into two symmetric positive-definite solves: the
+ * quasi-static potential with temperature-dependent conductivity, then the
+ * backward-Euler Pennes bioheat equation; both are solved with
+ * Jacobi-preconditioned conjugate gradients (the paper names CG for SPD
+ * systems and preconditioning in Sec. II-B).
+ *
+ * Conventions (all entry points):
+ *   - Pointers ending in _h are host memory, pointers ending in _d are device
+ *     memory on the current HIP device.  All _d buffers belong to the caller and
+ *     must stay alive until the stream work that uses them has completed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *     is enqueued on it in stream order.  The solve entry points poll a few
+ *     device scalars on that stream and return only when the solve has finished.
+ *   - Opaque handles (rafem_mesh) and their workspaces belong to the library:
+ *     they are allocated in rafem_mesh_create and freed by rafem_mesh_destroy.
+ *     No other entry point allocates device memory.
+ *   - Argument and mesh errors are detected on the host before anything is
+ *     enqueued; on such an error nothing is enqueued and the outputs are
+ *     untouched.  Numerical failures (no convergence, breakdown) are reported in
+ *     the info structs and by the return value; outputs then hold the last
+ *     iterate.  No C++ exception crosses this boundary and the library never
+ *     aborts the process.
+ *   - A handle may be used by one host thread at a time.
+ *   - Integer index arrays are int32, zero-based.  Node ids index [0, n_nodes).
+ */
+#ifndef RAFEM_H
+#define RAFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RAFEM_ABI_VERSION 1
+
+typedef int32_t rafem_status;
+#define RAFEM_OK            0  /* success */
+#define RAFEM_E_ARG         1  /* bad argument: null pointer, size, option value */
+#define RAFEM_E_MESH        2  /* bad mesh: node id out of range, element with detJ <= 0 */
+#define RAFEM_E_NOCONV      3  /* iteration limit reached; outputs hold the last iterate */
+#define RAFEM_E_BREAKDOWN   4  /* p.Ap <= 0 or a non-finite scalar: matrix not SPD or corrupt input */
+#define RAFEM_E_HIP         5  /* a HIP runtime call failed (message from rafem_last_error) */
+#define RAFEM_E_NOMEM       6  /* device or pinned host allocation failed */
+#define RAFEM_E_STATE       7  /* call out of order (e.g. reuse requested before a first assembly) */
+
+/* Message of the last failed call on this host thread; valid until the next call on it. */
+const char* rafem_last_error(void);
+
+/* RAFEM_ABI_VERSION of the loaded library. */
+int32_t rafem_abi_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Host-only mesh analysis (no GPU needed).  Sec. III-B: the matrix structure is
+ * the same at every step, so it is computed once per mesh.
+ * ------------------------------------------------------------------------- */
+
+/* CSR pattern of the node graph of a mesh: entry (i, j) exists iff nodes i and j
+ * share an element; every node's row holds its diagonal; columns ascending.
+ * The pattern does not depend on boundary conditions.
+ *   conn_h     [n_elems * npe] host, element-major node ids; npe is 8 (hex) or 4 (tet)
+ *   nnz_out    receives the number of entries
+ *   row_ptr_h  [n_nodes + 1] host output, or NULL to query nnz only
+ *   col_idx_h  [nnz] host output, or NULL to query nnz only
+ * Errors: E_ARG (sizes, null conn), E_MESH (node id outside [0, n_nodes), nnz > INT32_MAX). */
+rafem_status rafem_csr_structure(int64_t n_nodes, int64_t n_elems, int32_t npe,
+                                 const int32_t* conn_h, int64_t* nnz_out,
+                                 int32_t* row_ptr_h, int32_t* col_idx_h);
+
+/* Element colouring used for race-free assembly: elements of one colour share no
+ * node, so their contributions to the global matrix can be added concurrently
+ * without atomics.  Greedy first-fit in element order (at most 64 colours).
+ *   colour_h       [n_elems] host output, colour of each element
+ *   n_colours_out  receives the number of colours
+ * Errors: E_ARG, E_MESH (node id out of range; more than 64 colours needed). */
+rafem_status rafem_colour_elements(int64_t n_nodes, int64_t n_elems, int32_t npe,
+                                   const int32_t* conn_h, int32_t* colour_h,
+                                   int32_t* n_colours_out);
+
+/* ---------------------------------------------------------------------------
+ * Mesh handle: structure, colouring, geometry and all device workspaces.
+ * ------------------------------------------------------------------------- */
+typedef struct rafem_mesh_s* rafem_mesh;
+
+typedef struct {
+    int64_t n_nodes;
+    int64_t n_elems;
+    int64_t nnz;
+    int64_t n_dirichlet;
+    int32_t nodes_per_elem;
+    int32_t n_colours;
+} rafem_mesh_stats;
+
+/* Build a mesh on the current device.
+ *   xyz_h      [n_nodes * 3] host, node coordinates (x, y, z) in metres
+ *   conn_h     [n_elems * npe] host; hex local order (0,0,0),(1,0,0),(1,1,0),(0,1,0),
+ *              (0,0,1),(1,0,1),(1,1,1),(0,1,1) of the reference cube; tets positively oriented
+ *   dir_ids_h  [n_dir] host, Dirichlet node ids, strictly increasing; n_dir may be 0
+ *   out        receives the handle
+ * Every element must have positive Jacobian determinant at its quadrature points
+ * (E_MESH otherwise).  Allocates all device memory the other calls use. */
+rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe,
+                               const double* xyz_h, const int32_t* conn_h,
+                               const int32_t* dir_ids_h, int64_t n_dir, rafem_mesh* out);
+
+/* Free a mesh and its device memory (synchronises the device first).  NULL is a no-op. */
+rafem_status rafem_mesh_destroy(rafem_mesh mesh);
+
+rafem_status rafem_mesh_get_stats(rafem_mesh mesh, rafem_mesh_stats* out);
+
+/* ---------------------------------------------------------------------------
+ * Assembly (Sec. III-A: element equations gathered into the global CSR matrix).
+ * ------------------------------------------------------------------------- */
+
+/* A = sum_e (mass_coef[e] M_e + stiff_coef[e] K_e) on the mesh's CSR structure,
+ * with consistent mass M_e and stiffness K_e of the element (hex: 2x2x2 Gauss;
+ * tet: exact), assembled element-parallel colour by colour (no atomics).
+ * If dir_vals_d is given, Dirichlet conditions on the mesh's Dirichlet nodes are
+ * applied by symmetric lifting that keeps the structure: rhs_lift[f] =
+ * -sum_{d in D} A_fd g_d on free rows, rhs_lift[d] = g_d on Dirichlet rows; then
+ * rows and columns of D are zeroed (entries stay stored) and A_dd = 1.
+ * The right-hand side of the lifted system is b_phys (zero on D) + rhs_lift.
+ *   mass_coef_d   [n_elems] device, or NULL for zero
+ *   stiff_coef_d  [n_elems] device, or NULL for zero
+ *   dir_vals_d    [n_dir] device, values on the Dirichlet nodes in dir_ids order, or NULL
+ *                 for no lifting
+ *   row_ptr_d     [n_nodes + 1] device output of the structure, or NULL
+ *   col_idx_d     [nnz] device output of the structure, or NULL
+ *   vals_d        [nnz] device output, FP64 values (required)
+ *   vals32_d      [nnz] device output, FP32 copy of the values, or NULL
+ *   rhs_lift_d    [n_nodes] device output, or NULL (required if dir_vals_d is given) */
+rafem_status rafem_assemble_csr(rafem_mesh mesh, const double* mass_coef_d,
+                                const double* stiff_coef_d, const double* dir_vals_d,
+                                int32_t* row_ptr_d, int32_t* col_idx_d, double* vals_d,
+                                float* vals32_d, double* rhs_lift_d, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Solve (Sec. II-B: CG for SPD systems, with a preconditioner).
+ * ------------------------------------------------------------------------- */
+#define RAFEM_FP64   0  /* FP64 Jacobi-PCG */
+#define RAFEM_MIXED  1  /* FP32-value / FP32-vector inner PCG inside FP64 iterative refinement */
+
+typedef struct {
+    double  tol;         /* stop when ||b - A x||_2 <= tol ||b||_2 (recursive residual in FP64 PCG,
+                            FP64 true residual of the refinement in MIXED) */
+    int32_t maxit;       /* limit on (inner) PCG iterations per solve; <= 0 means 20000 */
+    int32_t precision;   /* RAFEM_FP64 or RAFEM_MIXED */
+    double  inner_tol;   /* MIXED: relative tolerance of each inner solve (0 means 1e-4) */
+    int32_t max_outer;   /* MIXED: refinement limit (<= 0 means 30) */
+    int32_t poll_every;  /* iterations enqueued between host polls (<= 0 means adaptive) */
+} rafem_solve_opts;
+
+typedef struct {
+    int32_t status;      /* RAFEM_OK, RAFEM_E_NOCONV or RAFEM_E_BREAKDOWN */
+    int32_t iters;       /* PCG iterations (FP64) or total inner iterations (MIXED) */
+    int32_t outer;       /* refinement steps (MIXED), 0 for FP64 */
+    int32_t launched;    /* iterations enqueued, including ones skipped after convergence */
+    double  relres;      /* residual norm the stopping test saw, over ||b|| */
+    double  relres_true; /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit */
+} rafem_solve_info;
+
+/* Solve A x = b with Jacobi-PCG, x holding the initial guess on entry.
+ * A is any square CSR matrix with n_nodes rows, sorted or unsorted columns,
+ * a nonzero diagonal and symmetric positive definite values (not checked).
+ *   row_ptr_d, col_idx_d, vals_d  CSR of A on the device (int32, int32, FP64)
+ *   vals32_d   FP32 copy of vals (required for RAFEM_MIXED, ignored otherwise)
+ *   b_d        [n_nodes] right-hand side
+ *   x_d        [n_nodes] in: initial guess, out: solution (last iterate on failure)
+ *   opts       NULL for defaults (tol 1e-10, FP64)
+ *   info       NULL or receives iteration counts and residuals
+ * The mesh handle provides the workspaces.  Returns info->status. */
+rafem_status rafem_solve(rafem_mesh mesh, const int32_t* row_ptr_d, const int32_t* col_idx_d,
+                         const double* vals_d, const float* vals32_d, const double* b_d,
+                         double* x_d, const rafem_solve_opts* opts, rafem_solve_info* info,
+                         void* stream);
+
+/* Adjoint solve A^T lambda = g for a matrix assembled by rafem_assemble_csr.
+ * The lifted matrices are symmetric, so this runs the same PCG on A with the
+ * right-hand side g with its Dirichlet rows zeroed (the adjoint of a prescribed
+ * value is zero).  Arguments as rafem_solve; g_d [n_nodes] is not modified;
+ * lambda_d [n_nodes] holds the initial guess on entry and the solution on exit. */
+rafem_status rafem_solve_adjoint(rafem_mesh mesh, const int32_t* row_ptr_d,
+                                 const int32_t* col_idx_d, const double* vals_d,
+                                 const float* vals32_d, const double* g_d, double* lambda_d,
+                                 const rafem_solve_opts* opts, rafem_solve_info* info,
+                                 void* stream);
+
+/* y = A x on the device, with the same kernel the FP64 solver uses
+ * (the FP32 one when vals_d is NULL and vals32_d, x32_d, y32_d are given).
+ * Returns without synchronising.  Mainly for measurement and tests. */
+rafem_status rafem_spmv(rafem_mesh mesh, const int32_t* row_ptr_d, const int32_t* col_idx_d,
+                        const double* vals_d, const double* x_d, double* y_d,
+                        const float* vals32_d, const float* x32_d, float* y32_d, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Measurement.  While enabled, the SpMV of every PCG iteration that the solves on
+ * this mesh enqueue is bracketed by a pair of HIP events on the solve's stream
+ * (at most 2048 per chunk of iterations); after each chunk the durations of the
+ * launches that performed an iteration are accumulated, launches skipped after
+ * convergence are not.  Enabling creates the events, disabling destroys them.
+ * ------------------------------------------------------------------------- */
+rafem_status rafem_profile_enable(rafem_mesh mesh, int32_t enable);
+
+/* Mean duration in microseconds and number of the SpMV launches measured since the
+ * last reset, for the FP64 kernel (precision RAFEM_FP64) or the FP32 kernel of the
+ * inner iterations (RAFEM_MIXED).  reset != 0 clears the accumulators after reading. */
+rafem_status rafem_profile_read(rafem_mesh mesh, int32_t precision, double* mean_us,
+                                int64_t* count, int32_t reset);
+
+/* ---------------------------------------------------------------------------
+ * One coupled time step (Sec. II-A, Fig. 1: assemble + solve for voltage and heat).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double  rho_c;        /* volumetric heat capacity [J/m^3/K] */
+    double  dt;           /* time step [s] */
+    double  T_a;          /* arterial temperature of the perfusion term [C] */
+    double  alpha_sigma;  /* sigma = sigma0 (1 + alpha_sigma (Tbar_e - T_ref)) */
+    double  T_ref;
+    int32_t coupled;      /* 0: bioheat step only, with zero Joule source and V untouched */
+    int32_t reuse_bioheat;/* nonzero: reuse the bioheat matrix assembled by the previous call
+                             (k, perfusion, rho_c, dt unchanged); E_STATE if there is none */
+} rafem_phys;
+
+typedef struct {
+    rafem_solve_info V;   /* potential solve (zeroed if not coupled) */
+    rafem_solve_info T;   /* bioheat solve */
+} rafem_step_info;
+
+/* Advance (T^n, V^n) to (T^{n+1}, V^{n+1}):
+ *   sigma_e = sigma0_e (1 + alpha (mean of T^n over the element - T_ref));
+ *   [sum_e sigma_e K_e] V = 0 with V = dir_V on D                      (potential);
+ *   F_i = sum_e int N_i sigma_e grad V . grad V                         (Joule source);
+ *   [sum_e (rho_c/dt + perf_e) M_e + k_e K_e] T^{n+1}
+ *        = (rho_c/dt) M T^n + T_a sum_e perf_e M_e 1 + F,  T = dir_T on D  (bioheat).
+ *   k_e_d, perf_e_d, sigma0_e_d  [n_elems] device
+ *   dir_V_d, dir_T_d             [n_dir] device, values on D in dir_ids order
+ *   T_d  [n_nodes] in: T^n, out: T^{n+1}
+ *   V_d  [n_nodes] in: initial guess (previous potential), out: V^{n+1}
+ *   opts applies to both solves (NULL: tol 1e-12, FP64). */
+rafem_status rafem_step(rafem_mesh mesh, const rafem_phys* phys, const double* k_e_d,
+                        const double* perf_e_d, const double* sigma0_e_d,
+                        const double* dir_V_d, const double* dir_T_d, double* T_d, double* V_d,
+                        const rafem_solve_opts* opts, rafem_step_info* info, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAFEM_H */

@@ -1,0 +1,338 @@
+"""ctypes binding of librafem.so (argument marshalling only).
+
+Every function here checks dtypes, devices and contiguity, then calls the C ABI
+of the same name.  All computation happens in the library's HIP kernels; there
+is no Python or CPU fallback: if the shared library is missing or fails to
+load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librafem.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_2409_13036_amd.build)")
+_lib = C.CDLL(LIB_PATH)
+
+OK, E_ARG, E_MESH, E_NOCONV, E_BREAKDOWN, E_HIP, E_NOMEM, E_STATE = range(8)
+FP64, MIXED = 0, 1
+STATUS_NAMES = {OK: "OK", E_ARG: "E_ARG", E_MESH: "E_MESH", E_NOCONV: "E_NOCONV",
+                E_BREAKDOWN: "E_BREAKDOWN", E_HIP: "E_HIP", E_NOMEM: "E_NOMEM", E_STATE: "E_STATE"}
+
+# names every declaration in include/rafem.h maps to
+EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafem_colour_elements",
+           "rafem_mesh_create", "rafem_mesh_destroy", "rafem_mesh_get_stats", "rafem_assemble_csr",
+           "rafem_solve", "rafem_solve_adjoint", "rafem_spmv", "rafem_profile_enable",
+           "rafem_profile_read", "rafem_step")
+
+
+class RafemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class MeshStats(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_elems", C.c_int64), ("nnz", C.c_int64),
+                ("n_dirichlet", C.c_int64), ("nodes_per_elem", C.c_int32), ("n_colours", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("precision", C.c_int32),
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("poll_every", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("outer", C.c_int32),
+                ("launched", C.c_int32), ("relres", C.c_double), ("relres_true", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Phys(C.Structure):
+    _fields_ = [("rho_c", C.c_double), ("dt", C.c_double), ("T_a", C.c_double),
+                ("alpha_sigma", C.c_double), ("T_ref", C.c_double), ("coupled", C.c_int32),
+                ("reuse_bioheat", C.c_int32)]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("V", SolveInfo), ("T", SolveInfo)]
+
+
+_p = C.c_void_p
+_i64, _i32 = C.c_int64, C.c_int32
+_lib.rafem_last_error.restype = C.c_char_p
+_lib.rafem_abi_version.restype = C.c_int32
+_lib.rafem_csr_structure.argtypes = [_i64, _i64, _i32, _p, C.POINTER(C.c_int64), _p, _p]
+_lib.rafem_colour_elements.argtypes = [_i64, _i64, _i32, _p, _p, C.POINTER(C.c_int32)]
+_lib.rafem_mesh_create.argtypes = [_i64, _i64, _i32, _p, _p, _p, _i64, C.POINTER(_p)]
+_lib.rafem_mesh_destroy.argtypes = [_p]
+_lib.rafem_mesh_get_stats.argtypes = [_p, C.POINTER(MeshStats)]
+_lib.rafem_assemble_csr.argtypes = [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
+_lib.rafem_solve.argtypes = [_p, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _p]
+_lib.rafem_solve_adjoint.argtypes = [_p, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts),
+                                     C.POINTER(SolveInfo), _p]
+_lib.rafem_spmv.argtypes = [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
+_lib.rafem_profile_enable.argtypes = [_p, _i32]
+_lib.rafem_profile_read.argtypes = [_p, _i32, C.POINTER(C.c_double), C.POINTER(C.c_int64), _i32]
+_lib.rafem_step.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts),
+                            C.POINTER(StepInfo), _p]
+for _name in EXPORTS:
+    if _name not in ("rafem_last_error", "rafem_abi_version"):
+        getattr(_lib, _name).restype = C.c_int32
+
+
+def lib():
+    return _lib
+
+
+def last_error() -> str:
+    return _lib.rafem_last_error().decode(errors="replace")
+
+
+def _check(status: int, allow=(OK,)):
+    if status not in allow:
+        raise RafemError(status, last_error())
+    return status
+
+
+def abi_version() -> int:
+    return int(_lib.rafem_abi_version())
+
+
+# --------------------------------------------------------------------------------------
+# host-only analysis
+# --------------------------------------------------------------------------------------
+def _host_i32(a) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a
+
+
+def csr_structure(conn: np.ndarray, n_nodes: int):
+    """rafem_csr_structure: CSR pattern of the node graph -> (row_ptr, col_idx) int32 arrays."""
+    conn = _host_i32(conn)
+    E, npe = conn.shape
+    nnz = C.c_int64(0)
+    _check(_lib.rafem_csr_structure(n_nodes, E, npe, conn.ctypes.data, C.byref(nnz), None, None))
+    rp = np.empty(n_nodes + 1, dtype=np.int32)
+    ci = np.empty(nnz.value, dtype=np.int32)
+    _check(_lib.rafem_csr_structure(n_nodes, E, npe, conn.ctypes.data, C.byref(nnz),
+                                    rp.ctypes.data, ci.ctypes.data))
+    return rp, ci
+
+
+def colour_elements(conn: np.ndarray, n_nodes: int):
+    """rafem_colour_elements -> (colour int32 [E], n_colours)."""
+    conn = _host_i32(conn)
+    E, npe = conn.shape
+    col = np.empty(E, dtype=np.int32)
+    nc = C.c_int32(0)
+    _check(_lib.rafem_colour_elements(n_nodes, E, npe, conn.ctypes.data, col.ctypes.data, C.byref(nc)))
+    return col, int(nc.value)
+
+
+# --------------------------------------------------------------------------------------
+# device entry points (torch tensors for device memory and streams)
+# --------------------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(t, dtype, n: Optional[int] = None, name: str = "tensor", allow_none: bool = False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device (cuda) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def make_opts(tol=1e-10, maxit=0, precision="fp64", inner_tol=0.0, max_outer=0, poll_every=0):
+    prec = {"fp64": FP64, "mixed": MIXED}.get(precision, precision)
+    return SolveOpts(tol, maxit, prec, inner_tol, max_outer, poll_every)
+
+
+class Mesh:
+    """rafem_mesh_create / rafem_mesh_destroy: structure, colouring and workspaces on the device."""
+
+    def __init__(self, xyz: np.ndarray, conn: np.ndarray, dir_ids: np.ndarray):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("rafem needs a HIP device")
+        torch.cuda.init()
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        conn = _host_i32(conn)
+        dir_ids = _host_i32(dir_ids)
+        self.n_nodes = int(xyz.shape[0])
+        self.n_elems, self.npe = (int(v) for v in conn.shape)
+        self.n_dir = int(dir_ids.size)
+        h = C.c_void_p()
+        _check(_lib.rafem_mesh_create(self.n_nodes, self.n_elems, self.npe, xyz.ctypes.data,
+                                      conn.ctypes.data, dir_ids.ctypes.data if dir_ids.size else None,
+                                      self.n_dir, C.byref(h)))
+        self.handle = h
+        st = MeshStats()
+        _check(_lib.rafem_mesh_get_stats(self.handle, C.byref(st)))
+        self.nnz = int(st.nnz)
+        self.n_colours = int(st.n_colours)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.rafem_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def profile_enable(mesh: Mesh, enable: bool = True):
+    """rafem_profile_enable: bracket every PCG SpMV launch with HIP events."""
+    _check(_lib.rafem_profile_enable(mesh.handle, 1 if enable else 0))
+
+
+def profile_read(mesh: Mesh, precision: str = "fp64", reset: bool = True):
+    """rafem_profile_read -> (mean SpMV kernel duration in us, number of launches measured)."""
+    mean = C.c_double(0.0)
+    cnt = C.c_int64(0)
+    prec = {"fp64": FP64, "mixed": MIXED}.get(precision, precision)
+    _check(_lib.rafem_profile_read(mesh.handle, prec, C.byref(mean), C.byref(cnt), 1 if reset else 0))
+    return float(mean.value), int(cnt.value)
+
+
+def assemble_csr(mesh: Mesh, stiff_coef=None, mass_coef=None, dir_vals=None, *, want_structure=True,
+                 want_f32=False, stream=None):
+    """rafem_assemble_csr -> dict(row_ptr, col_idx, vals, vals32, rhs_lift) of device tensors."""
+    torch = _torch()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stiff_coef = _dev(stiff_coef, torch.float64, mesh.n_elems, "stiff_coef", allow_none=True)
+    mass_coef = _dev(mass_coef, torch.float64, mesh.n_elems, "mass_coef", allow_none=True)
+    dir_vals = _dev(dir_vals, torch.float64, mesh.n_dir, "dir_vals", allow_none=True)
+    out = {"vals": torch.empty(mesh.nnz, dtype=torch.float64, device=dev)}
+    if want_structure:
+        out["row_ptr"] = torch.empty(mesh.n_nodes + 1, dtype=torch.int32, device=dev)
+        out["col_idx"] = torch.empty(mesh.nnz, dtype=torch.int32, device=dev)
+    if want_f32:
+        out["vals32"] = torch.empty(mesh.nnz, dtype=torch.float32, device=dev)
+    if dir_vals is not None:
+        out["rhs_lift"] = torch.empty(mesh.n_nodes, dtype=torch.float64, device=dev)
+    _check(_lib.rafem_assemble_csr(mesh.handle, _ptr(mass_coef), _ptr(stiff_coef), _ptr(dir_vals),
+                                   _ptr(out.get("row_ptr")), _ptr(out.get("col_idx")), _ptr(out["vals"]),
+                                   _ptr(out.get("vals32")), _ptr(out.get("rhs_lift")), _stream(stream)))
+    return out
+
+
+def solve(mesh: Mesh, row_ptr, col_idx, vals, b, x, *, vals32=None, tol=1e-10, precision="fp64",
+          maxit=0, inner_tol=0.0, max_outer=0, poll_every=0, stream=None, check=True):
+    """rafem_solve: Jacobi-PCG (FP64 or mixed) on A x = b, x in/out.  Returns the info dict."""
+    torch = _torch()
+    n = mesh.n_nodes
+    row_ptr = _dev(row_ptr, torch.int32, n + 1, "row_ptr")
+    col_idx = _dev(col_idx, torch.int32, None, "col_idx")
+    vals = _dev(vals, torch.float64, col_idx.numel(), "vals")
+    vals32 = _dev(vals32, torch.float32, col_idx.numel(), "vals32", allow_none=True)
+    b = _dev(b, torch.float64, n, "b")
+    x = _dev(x, torch.float64, n, "x")
+    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every)
+    info = SolveInfo()
+    st = _lib.rafem_solve(mesh.handle, _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(vals32), _ptr(b),
+                          _ptr(x), C.byref(opts), C.byref(info), _stream(stream))
+    if check:
+        _check(st)
+    return info.as_dict()
+
+
+def solve_adjoint(mesh: Mesh, row_ptr, col_idx, vals, g, lam, *, vals32=None, tol=1e-10,
+                  precision="fp64", maxit=0, inner_tol=0.0, max_outer=0, poll_every=0, stream=None,
+                  check=True):
+    """rafem_solve_adjoint: A^T lambda = g (g zeroed on Dirichlet rows), lambda in/out."""
+    torch = _torch()
+    n = mesh.n_nodes
+    row_ptr = _dev(row_ptr, torch.int32, n + 1, "row_ptr")
+    col_idx = _dev(col_idx, torch.int32, None, "col_idx")
+    vals = _dev(vals, torch.float64, col_idx.numel(), "vals")
+    vals32 = _dev(vals32, torch.float32, col_idx.numel(), "vals32", allow_none=True)
+    g = _dev(g, torch.float64, n, "g")
+    lam = _dev(lam, torch.float64, n, "lambda")
+    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every)
+    info = SolveInfo()
+    st = _lib.rafem_solve_adjoint(mesh.handle, _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(vals32),
+                                  _ptr(g), _ptr(lam), C.byref(opts), C.byref(info), _stream(stream))
+    if check:
+        _check(st)
+    return info.as_dict()
+
+
+def spmv(mesh: Mesh, row_ptr, col_idx, vals, x, y, *, stream=None):
+    """rafem_spmv: y = A x (FP64 if vals is float64, else the FP32 kernel)."""
+    torch = _torch()
+    n = mesh.n_nodes
+    row_ptr = _dev(row_ptr, torch.int32, n + 1, "row_ptr")
+    col_idx = _dev(col_idx, torch.int32, None, "col_idx")
+    if vals.dtype == torch.float64:
+        vals = _dev(vals, torch.float64, col_idx.numel(), "vals")
+        x, y = _dev(x, torch.float64, n, "x"), _dev(y, torch.float64, n, "y")
+        _check(_lib.rafem_spmv(mesh.handle, _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(x), _ptr(y),
+                               None, None, None, _stream(stream)))
+    else:
+        vals = _dev(vals, torch.float32, col_idx.numel(), "vals32")
+        x, y = _dev(x, torch.float32, n, "x32"), _dev(y, torch.float32, n, "y32")
+        _check(_lib.rafem_spmv(mesh.handle, _ptr(row_ptr), _ptr(col_idx), None, None, None, _ptr(vals),
+                               _ptr(x), _ptr(y), _stream(stream)))
+
+
+def step(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T, V, *, tol=1e-12,
+         precision="fp64", maxit=0, inner_tol=0.0, max_outer=0, poll_every=0, stream=None, check=True):
+    """rafem_step: one coupled step, T and V updated in place.  Returns {"V": info, "T": info}."""
+    torch = _torch()
+    E, n = mesh.n_elems, mesh.n_nodes
+    k_e = _dev(k_e, torch.float64, E, "k_e")
+    perf_e = _dev(perf_e, torch.float64, E, "perf_e")
+    sigma0_e = _dev(sigma0_e, torch.float64, E, "sigma0_e", allow_none=not phys.coupled)
+    dir_V = _dev(dir_V, torch.float64, mesh.n_dir, "dir_V", allow_none=not phys.coupled)
+    dir_T = _dev(dir_T, torch.float64, mesh.n_dir, "dir_T")
+    T = _dev(T, torch.float64, n, "T")
+    V = _dev(V, torch.float64, n, "V", allow_none=not phys.coupled)
+    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every)
+    info = StepInfo()
+    st = _lib.rafem_step(mesh.handle, C.byref(phys), _ptr(k_e), _ptr(perf_e), _ptr(sigma0_e),
+                         _ptr(dir_V), _ptr(dir_T), _ptr(T), _ptr(V), C.byref(opts), C.byref(info),
+                         _stream(stream))
+    if check:
+        _check(st)
+    return {"status": st, "V": info.V.as_dict(), "T": info.T.as_dict()}

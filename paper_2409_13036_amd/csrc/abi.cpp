@@ -1,0 +1,476 @@
+// C ABI of the rafem library: argument checking, mesh lifetime, and the
+// orchestration of assembly, solves and coupled time steps.  Every entry point
+// catches all exceptions and turns them into a status code plus a thread-local
+// message; nothing is enqueued after a failed host-side check.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "solver.hpp"
+
+namespace rafem {
+
+namespace {
+thread_local std::string g_error;
+
+template <typename F>
+rafem_status guard(F&& f) {
+    try {
+        clear_error();
+        return f();
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return RAFEM_E_NOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return RAFEM_E_HIP;
+    } catch (...) {
+        set_error("unknown error");
+        return RAFEM_E_HIP;
+    }
+}
+
+void require(bool ok, const char* what) {
+    if (!ok) throw Error{RAFEM_E_ARG, what};
+}
+
+template <typename T>
+T* dalloc(rafem_mesh m, size_t count) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{RAFEM_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    m->allocations.push_back(p);
+    return static_cast<T*>(p);
+}
+
+void profile_off(rafem_mesh m) {
+    for (hipEvent_t e : m->prof_ev) (void)hipEventDestroy(e);
+    m->prof_ev.clear();
+    m->prof_on = false;
+}
+
+void free_mesh(rafem_mesh m) {
+    if (!m) return;
+    (void)hipDeviceSynchronize();
+    profile_off(m);
+    for (void* p : m->allocations) (void)hipFree(p);
+    if (m->st_host) (void)hipHostFree(m->st_host);
+    delete m;
+}
+
+void check_device(rafem_mesh m) {
+    require(m != nullptr, "mesh is NULL");
+    int d = -1;
+    RAFEM_HIP(hipGetDevice(&d));
+    if (d != m->device) throw Error{RAFEM_E_ARG, "the current HIP device is not the mesh's device"};
+}
+
+void assemble_into(rafem_mesh m, const double* mass, const double* stiff, double* vals,
+                   hipStream_t s) {
+    launch_fill(vals, m->nnz, 0.0, s);
+    for (int c = 0; c < m->n_colours; ++c) {
+        const int off = m->colour_off[c], cnt = m->colour_off[c + 1] - off;
+        launch_assemble_colour(m->npe, m->colour_elems + off, cnt, m->conn, m->xyz, m->rp, m->ci,
+                               mass, stiff, vals, s);
+    }
+}
+
+void solve_any(rafem_mesh m, const SolveOpts& o, const double* vals, const float* vals32,
+               const double* dinv, const float* dinv32, const double* b, double* x,
+               rafem_solve_info* info, hipStream_t s, int hint, int* iters) {
+    Csr64 A{m->rp, m->ci, vals, (int32_t)m->n};
+    if (o.precision == RAFEM_MIXED) {
+        Csr32 A32{m->rp, m->ci, vals32, (int32_t)m->n};
+        pcg_mixed(m, A, A32, dinv, dinv32, b, x, o, info, s, hint, iters);
+    } else {
+        pcg64(m, A, dinv, b, x, o, info, s, hint, iters);
+    }
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+void clear_error() { g_error.clear(); }
+
+}  // namespace rafem
+
+using namespace rafem;
+
+extern "C" {
+
+const char* rafem_last_error(void) { return g_error.c_str(); }
+
+int32_t rafem_abi_version(void) { return RAFEM_ABI_VERSION; }
+
+rafem_status rafem_csr_structure(int64_t n_nodes, int64_t n_elems, int32_t npe,
+                                 const int32_t* conn_h, int64_t* nnz_out, int32_t* row_ptr_h,
+                                 int32_t* col_idx_h) {
+    return guard([&]() -> rafem_status {
+        require(nnz_out != nullptr, "nnz_out is NULL");
+        check_conn(n_nodes, n_elems, npe, conn_h);
+        HostStructure S = build_structure(n_nodes, n_elems, npe, conn_h);
+        *nnz_out = (int64_t)S.col_idx.size();
+        if (row_ptr_h && col_idx_h) {
+            std::memcpy(row_ptr_h, S.row_ptr.data(), S.row_ptr.size() * sizeof(int32_t));
+            std::memcpy(col_idx_h, S.col_idx.data(), S.col_idx.size() * sizeof(int32_t));
+        }
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_colour_elements(int64_t n_nodes, int64_t n_elems, int32_t npe,
+                                   const int32_t* conn_h, int32_t* colour_h,
+                                   int32_t* n_colours_out) {
+    return guard([&]() -> rafem_status {
+        require(colour_h != nullptr && n_colours_out != nullptr, "output is NULL");
+        check_conn(n_nodes, n_elems, npe, conn_h);
+        *n_colours_out = colour_elements(n_nodes, n_elems, npe, conn_h, colour_h);
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, const double* xyz_h,
+                               const int32_t* conn_h, const int32_t* dir_ids_h, int64_t n_dir,
+                               rafem_mesh* out) {
+    return guard([&]() -> rafem_status {
+        require(out != nullptr, "out is NULL");
+        require(xyz_h != nullptr, "xyz is NULL");
+        require(n_dir >= 0 && n_dir <= n_nodes, "n_dir out of range");
+        require(n_dir == 0 || dir_ids_h != nullptr, "dir_ids is NULL");
+        *out = nullptr;
+        check_conn(n_nodes, n_elems, npe, conn_h);
+        for (int64_t k = 0; k < n_dir; ++k) {
+            if (dir_ids_h[k] < 0 || dir_ids_h[k] >= n_nodes)
+                throw Error{RAFEM_E_ARG, "Dirichlet id outside [0, n_nodes)"};
+            if (k > 0 && dir_ids_h[k] <= dir_ids_h[k - 1])
+                throw Error{RAFEM_E_ARG, "Dirichlet ids must be strictly increasing"};
+        }
+        for (int64_t i = 0; i < 3 * n_nodes; ++i)
+            if (!std::isfinite(xyz_h[i])) throw Error{RAFEM_E_MESH, "non-finite node coordinate"};
+        check_geometry(n_elems, npe, conn_h, xyz_h);
+        HostStructure S = build_structure(n_nodes, n_elems, npe, conn_h);
+        std::vector<int32_t> colour(n_elems);
+        const int ncol = colour_elements(n_nodes, n_elems, npe, conn_h, colour.data());
+
+        rafem_mesh m = new rafem_mesh_s();
+        try {
+            RAFEM_HIP(hipGetDevice(&m->device));
+            m->n = n_nodes;
+            m->E = n_elems;
+            m->npe = npe;
+            m->nnz = (int64_t)S.col_idx.size();
+            m->nD = n_dir;
+            m->n_colours = ncol;
+            m->spmv = choose_spmv_config(m->n, m->nnz);
+            // elements grouped by colour, ascending id within a colour
+            m->colour_off.assign(ncol + 1, 0);
+            for (int64_t e = 0; e < n_elems; ++e) m->colour_off[colour[e] + 1]++;
+            for (int c = 0; c < ncol; ++c) m->colour_off[c + 1] += m->colour_off[c];
+            std::vector<int32_t> order(n_elems);
+            std::vector<int32_t> fill(m->colour_off.begin(), m->colour_off.end() - 1);
+            for (int64_t e = 0; e < n_elems; ++e) order[fill[colour[e]]++] = (int32_t)e;
+            std::vector<uint8_t> isD(n_nodes, 0);
+            for (int64_t k = 0; k < n_dir; ++k) isD[dir_ids_h[k]] = 1;
+
+            const size_t N = (size_t)n_nodes, E = (size_t)n_elems, NNZ = (size_t)m->nnz;
+            m->rp = dalloc<int32_t>(m, N + 1);
+            m->ci = dalloc<int32_t>(m, NNZ);
+            m->conn = dalloc<int32_t>(m, E * npe);
+            m->xyz = dalloc<double>(m, 3 * N);
+            m->colour_elems = dalloc<int32_t>(m, E);
+            m->dir_ids = dalloc<int32_t>(m, (size_t)n_dir);
+            m->isD = dalloc<uint8_t>(m, N);
+            m->gV = dalloc<double>(m, N);
+            m->gT = dalloc<double>(m, N);
+            m->gtmp = dalloc<double>(m, N);
+            m->sigma = dalloc<double>(m, E);
+            m->coefT = dalloc<double>(m, E);
+            m->valsV = dalloc<double>(m, NNZ);
+            m->valsT = dalloc<double>(m, NNZ);
+            m->valsV32 = dalloc<float>(m, NNZ);
+            m->valsT32 = dalloc<float>(m, NNZ);
+            m->liftV = dalloc<double>(m, N);
+            m->liftT = dalloc<double>(m, N);
+            m->dinvV = dalloc<double>(m, N);
+            m->dinvT = dalloc<double>(m, N);
+            m->dinvV32 = dalloc<float>(m, N);
+            m->dinvT32 = dalloc<float>(m, N);
+            m->rhs = dalloc<double>(m, N);
+            m->bT = dalloc<double>(m, N);
+            m->r = dalloc<double>(m, N);
+            m->p = dalloc<double>(m, N);
+            m->q = dalloc<double>(m, N);
+            m->dinv = dalloc<double>(m, N);
+            m->r64 = dalloc<double>(m, N);
+            m->r32 = dalloc<float>(m, N);
+            m->p32 = dalloc<float>(m, N);
+            m->q32 = dalloc<float>(m, N);
+            m->d32 = dalloc<float>(m, N);
+            m->dinv32 = dalloc<float>(m, N);
+            m->partials = dalloc<double>(m, 3 * (N / 64 + 64));
+            m->st = dalloc<PcgState>(m, 3);
+            if (hipHostMalloc((void**)&m->st_host, 3 * sizeof(PcgState), hipHostMallocDefault) !=
+                hipSuccess) {
+                (void)hipGetLastError();
+                m->st_host = nullptr;
+                throw Error{RAFEM_E_NOMEM, "pinned host allocation failed"};
+            }
+            std::memset(m->st_host, 0, 3 * sizeof(PcgState));
+            RAFEM_HIP(hipMemcpy(m->rp, S.row_ptr.data(), (N + 1) * 4, hipMemcpyHostToDevice));
+            RAFEM_HIP(hipMemcpy(m->ci, S.col_idx.data(), NNZ * 4, hipMemcpyHostToDevice));
+            RAFEM_HIP(hipMemcpy(m->conn, conn_h, E * npe * 4, hipMemcpyHostToDevice));
+            RAFEM_HIP(hipMemcpy(m->xyz, xyz_h, 3 * N * 8, hipMemcpyHostToDevice));
+            RAFEM_HIP(hipMemcpy(m->colour_elems, order.data(), E * 4, hipMemcpyHostToDevice));
+            if (n_dir > 0)
+                RAFEM_HIP(hipMemcpy(m->dir_ids, dir_ids_h, (size_t)n_dir * 4, hipMemcpyHostToDevice));
+            RAFEM_HIP(hipMemcpy(m->isD, isD.data(), N, hipMemcpyHostToDevice));
+            RAFEM_HIP(hipMemcpy(m->st, m->st_host, 3 * sizeof(PcgState), hipMemcpyHostToDevice));
+            // ticket counters must start at zero; later kernels keep them at zero between launches
+            RAFEM_HIP(hipDeviceSynchronize());
+        } catch (...) {
+            free_mesh(m);
+            throw;
+        }
+        *out = m;
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_mesh_destroy(rafem_mesh mesh) {
+    return guard([&]() -> rafem_status {
+        free_mesh(mesh);
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_mesh_get_stats(rafem_mesh m, rafem_mesh_stats* out) {
+    return guard([&]() -> rafem_status {
+        require(m != nullptr && out != nullptr, "NULL argument");
+        out->n_nodes = m->n;
+        out->n_elems = m->E;
+        out->nnz = m->nnz;
+        out->n_dirichlet = m->nD;
+        out->nodes_per_elem = m->npe;
+        out->n_colours = m->n_colours;
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_assemble_csr(rafem_mesh m, const double* mass_coef_d, const double* stiff_coef_d,
+                                const double* dir_vals_d, int32_t* row_ptr_d, int32_t* col_idx_d,
+                                double* vals_d, float* vals32_d, double* rhs_lift_d,
+                                void* stream) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        require(vals_d != nullptr, "vals is NULL");
+        require(dir_vals_d == nullptr || rhs_lift_d != nullptr, "rhs_lift is required with dir_vals");
+        require(dir_vals_d == nullptr || m->nD > 0, "dir_vals given but the mesh has no Dirichlet nodes");
+        hipStream_t s = (hipStream_t)stream;
+        if (row_ptr_d)
+            RAFEM_HIP(hipMemcpyAsync(row_ptr_d, m->rp, (m->n + 1) * 4, hipMemcpyDeviceToDevice, s));
+        if (col_idx_d)
+            RAFEM_HIP(hipMemcpyAsync(col_idx_d, m->ci, m->nnz * 4, hipMemcpyDeviceToDevice, s));
+        assemble_into(m, mass_coef_d, stiff_coef_d, vals_d, s);
+        const int do_lift = dir_vals_d != nullptr;
+        if (do_lift) launch_scatter_dirichlet(m->dir_ids, dir_vals_d, m->nD, m->gtmp, s);
+        if (do_lift || vals32_d)
+            launch_lift((int)m->n, m->rp, m->ci, vals_d, vals32_d, m->isD, m->gtmp,
+                        do_lift ? rhs_lift_d : nullptr, nullptr, nullptr, do_lift, s);
+        RAFEM_HIP(hipGetLastError());
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_solve(rafem_mesh m, const int32_t* row_ptr_d, const int32_t* col_idx_d,
+                         const double* vals_d, const float* vals32_d, const double* b_d,
+                         double* x_d, const rafem_solve_opts* opts, rafem_solve_info* info,
+                         void* stream) {
+    rafem_status st = RAFEM_OK;
+    rafem_status rc = guard([&]() -> rafem_status {
+        check_device(m);
+        require(row_ptr_d && col_idx_d && vals_d && b_d && x_d, "NULL matrix or vector argument");
+        SolveOpts o = resolve_opts(opts, 1e-10);
+        require(o.precision != RAFEM_MIXED || vals32_d != nullptr, "MIXED precision needs vals32");
+        hipStream_t s = (hipStream_t)stream;
+        Csr64 A{row_ptr_d, col_idx_d, vals_d, (int32_t)m->n};
+        if (o.precision == RAFEM_MIXED) {
+            Csr32 A32{row_ptr_d, col_idx_d, vals32_d, (int32_t)m->n};
+            st = pcg_mixed(m, A, A32, nullptr, nullptr, b_d, x_d, o, info, s, 0, nullptr);
+        } else {
+            st = pcg64(m, A, nullptr, b_d, x_d, o, info, s, 0, nullptr);
+        }
+        if (st != RAFEM_OK)
+            set_error(st == RAFEM_E_NOCONV ? "iteration limit reached" : "PCG breakdown (p.Ap <= 0 or non-finite)");
+        return st;
+    });
+    return rc;
+}
+
+rafem_status rafem_solve_adjoint(rafem_mesh m, const int32_t* row_ptr_d, const int32_t* col_idx_d,
+                                 const double* vals_d, const float* vals32_d, const double* g_d,
+                                 double* lambda_d, const rafem_solve_opts* opts,
+                                 rafem_solve_info* info, void* stream) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        require(row_ptr_d && col_idx_d && vals_d && g_d && lambda_d, "NULL matrix or vector argument");
+        SolveOpts o = resolve_opts(opts, 1e-10);
+        require(o.precision != RAFEM_MIXED || vals32_d != nullptr, "MIXED precision needs vals32");
+        hipStream_t s = (hipStream_t)stream;
+        // right-hand side with Dirichlet rows zeroed; the adjoint of a prescribed value is 0
+        RAFEM_HIP(hipMemcpyAsync(m->bT, g_d, m->n * 8, hipMemcpyDeviceToDevice, s));
+        launch_fill(m->gtmp, m->n, 0.0, s);
+        launch_set_dirichlet(m->dir_ids, m->gtmp, m->nD, m->bT, s);
+        launch_set_dirichlet(m->dir_ids, m->gtmp, m->nD, lambda_d, s);
+        Csr64 A{row_ptr_d, col_idx_d, vals_d, (int32_t)m->n};
+        rafem_status st;
+        if (o.precision == RAFEM_MIXED) {
+            Csr32 A32{row_ptr_d, col_idx_d, vals32_d, (int32_t)m->n};
+            st = pcg_mixed(m, A, A32, nullptr, nullptr, m->bT, lambda_d, o, info, s, 0, nullptr);
+        } else {
+            st = pcg64(m, A, nullptr, m->bT, lambda_d, o, info, s, 0, nullptr);
+        }
+        if (st != RAFEM_OK)
+            set_error(st == RAFEM_E_NOCONV ? "iteration limit reached" : "PCG breakdown (p.Ap <= 0 or non-finite)");
+        return st;
+    });
+}
+
+rafem_status rafem_spmv(rafem_mesh m, const int32_t* row_ptr_d, const int32_t* col_idx_d,
+                        const double* vals_d, const double* x_d, double* y_d,
+                        const float* vals32_d, const float* x32_d, float* y32_d, void* stream) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        require(row_ptr_d && col_idx_d, "NULL structure");
+        hipStream_t s = (hipStream_t)stream;
+        if (vals_d) {
+            require(x_d && y_d, "NULL x or y");
+            launch_spmv64(Csr64{row_ptr_d, col_idx_d, vals_d, (int32_t)m->n}, m->spmv, x_d, y_d, s);
+        } else {
+            require(vals32_d && x32_d && y32_d, "NULL FP32 arguments");
+            launch_spmv32(Csr32{row_ptr_d, col_idx_d, vals32_d, (int32_t)m->n}, m->spmv, x32_d, y32_d, s);
+        }
+        RAFEM_HIP(hipGetLastError());
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_profile_enable(rafem_mesh m, int32_t enable) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        if (enable && !m->prof_on) {
+            m->prof_ev.resize(2 * kProfCap);
+            for (auto& e : m->prof_ev) e = nullptr;
+            for (auto& e : m->prof_ev) {
+                if (hipEventCreate(&e) != hipSuccess) {
+                    e = nullptr;
+                    profile_off(m);
+                    throw Error{RAFEM_E_HIP, "hipEventCreate failed"};
+                }
+            }
+            m->prof_on = true;
+        } else if (!enable && m->prof_on) {
+            RAFEM_HIP(hipDeviceSynchronize());
+            profile_off(m);
+        }
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_profile_read(rafem_mesh m, int32_t precision, double* mean_us, int64_t* count,
+                                int32_t reset) {
+    return guard([&]() -> rafem_status {
+        require(m != nullptr, "mesh is NULL");
+        require(precision == RAFEM_FP64 || precision == RAFEM_MIXED, "bad precision");
+        const int k = precision == RAFEM_MIXED ? 1 : 0;
+        if (mean_us) *mean_us = m->prof_cnt[k] ? m->prof_sum_us[k] / (double)m->prof_cnt[k] : 0.0;
+        if (count) *count = m->prof_cnt[k];
+        if (reset) {
+            m->prof_sum_us[k] = 0.0;
+            m->prof_cnt[k] = 0;
+        }
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_d,
+                        const double* perf_e_d, const double* sigma0_e_d, const double* dir_V_d,
+                        const double* dir_T_d, double* T_d, double* V_d,
+                        const rafem_solve_opts* opts, rafem_step_info* info, void* stream) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        require(phys != nullptr, "phys is NULL");
+        require(k_e_d && perf_e_d && T_d, "NULL k, perfusion or T");
+        require(m->nD == 0 || dir_T_d != nullptr, "dir_T is NULL");
+        require(phys->dt > 0.0 && std::isfinite(phys->dt), "dt must be > 0");
+        require(std::isfinite(phys->rho_c) && std::isfinite(phys->T_a), "non-finite physics constant");
+        if (phys->coupled) {
+            require(sigma0_e_d && V_d, "coupled step needs sigma0 and V");
+            require(m->nD == 0 || dir_V_d != nullptr, "dir_V is NULL");
+        }
+        if (phys->reuse_bioheat && !m->bioheat_ready)
+            throw Error{RAFEM_E_STATE, "reuse_bioheat set but no bioheat matrix has been assembled"};
+        SolveOpts o = resolve_opts(opts, 1e-12);
+        hipStream_t s = (hipStream_t)stream;
+        const bool mixed = o.precision == RAFEM_MIXED;
+        rafem_step_info local{};
+        rafem_step_info& inf = info ? *info : local;
+        std::memset(&inf, 0, sizeof(inf));
+
+        launch_scatter_dirichlet(m->dir_ids, dir_T_d, m->nD, m->gT, s);
+        if (!phys->reuse_bioheat) {
+            launch_coef(perf_e_d, phys->rho_c / phys->dt, m->coefT, m->E, s);
+            assemble_into(m, m->coefT, k_e_d, m->valsT, s);
+            launch_lift((int)m->n, m->rp, m->ci, m->valsT, m->valsT32, m->isD, m->gT, m->liftT,
+                        m->dinvT, m->dinvT32, m->nD > 0, s);
+            m->bioheat_ready = true;
+        }
+        if (phys->coupled) {
+            launch_scatter_dirichlet(m->dir_ids, dir_V_d, m->nD, m->gV, s);
+            launch_sigma(m->npe, m->E, m->conn, T_d, sigma0_e_d, phys->alpha_sigma, phys->T_ref,
+                         m->sigma, s);
+            assemble_into(m, nullptr, m->sigma, m->valsV, s);
+            launch_lift((int)m->n, m->rp, m->ci, m->valsV, m->valsV32, m->isD, m->gV, m->liftV,
+                        m->dinvV, m->dinvV32, m->nD > 0, s);
+            launch_set_dirichlet(m->dir_ids, m->gV, m->nD, V_d, s);
+            RAFEM_HIP(hipGetLastError());
+            int it = 0;
+            solve_any(m, o, m->valsV, m->valsV32, m->dinvV, m->dinvV32, m->liftV, V_d, &inf.V, s,
+                      mixed ? 0 : m->hint_V, &it);
+            if (!mixed) m->hint_V = it;
+            if (inf.V.status != RAFEM_OK) {
+                set_error("potential solve failed");
+                return inf.V.status;
+            }
+        }
+        launch_fill(m->rhs, m->n, 0.0, s);
+        for (int c = 0; c < m->n_colours; ++c) {
+            const int off = m->colour_off[c], cnt = m->colour_off[c + 1] - off;
+            launch_bioheat_rhs_colour(m->npe, m->colour_elems + off, cnt, m->conn, m->xyz, T_d,
+                                      phys->coupled ? V_d : nullptr, m->sigma, perf_e_d,
+                                      phys->rho_c / phys->dt, phys->T_a, phys->coupled ? 1 : 0,
+                                      m->rhs, s);
+        }
+        launch_finish_rhs((int)m->n, m->rhs, m->liftT, m->isD, m->bT, s);
+        launch_set_dirichlet(m->dir_ids, m->gT, m->nD, T_d, s);
+        RAFEM_HIP(hipGetLastError());
+        int it = 0;
+        solve_any(m, o, m->valsT, m->valsT32, m->dinvT, m->dinvT32, m->bT, T_d, &inf.T, s,
+                  mixed ? 0 : m->hint_T, &it);
+        if (!mixed) m->hint_T = it;
+        if (inf.T.status != RAFEM_OK) {
+            set_error("bioheat solve failed");
+            return inf.T.status;
+        }
+        return RAFEM_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,910 @@
+// HIP kernels for gfx950 (CDNA4, wave64): Jacobi-PCG building blocks and
+// element-parallel, colour-by-colour FEM assembly.
+//
+// Everything here is HBM-bound (sparse matrix-vector products and vector
+// updates at ~0.1-0.2 flop/byte), so the kernels are organised for coalesced
+// streaming and few passes over memory, not for matrix cores:
+//   * row kernels: a group of LANES consecutive lanes owns one CSR row, so a
+//     wave streams a contiguous range of values/column indices; the group sum
+//     is a wave shuffle; dot products are fused into the same pass;
+//   * workgroups own contiguous row ranges and are remapped so each of the 8
+//     XCDs (own L2) walks one contiguous eighth of the rows, which keeps the
+//     x-gathers of neighbouring rows in that XCD's L2;
+//   * reductions are deterministic: per-block partial sums in a fixed slot,
+//     then the last block to arrive (integer ticket) adds the partials in
+//     index order and updates the solver scalars in device memory, so no
+//     floating-point atomics and no host round trip per iteration.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace rafem {
+namespace {
+
+constexpr int WG = 256;
+constexpr int WAVE = 64;
+constexpr int NWAVES = WG / WAVE;
+constexpr int NXCD = 8;
+
+// Workgroups are dispatched round-robin over the XCDs; give XCD x the x-th contiguous
+// share of the logical block indices.
+__device__ __forceinline__ int xcd_block(int bid, int nb) {
+    const int xcd = bid % NXCD, idx = bid / NXCD;
+    const int q = nb / NXCD, r = nb % NXCD;
+    return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+// Sum K values over the block in a fixed order; result in thread 0.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K]) {
+    __shared__ double lds[K][NWAVES];
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        v[k] = wave_sum(v[k]);
+        if (lane == 0) lds[k][w] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int j = 0; j < NWAVES; ++j) s += lds[k][j];
+            v[k] = s;
+        }
+    }
+}
+
+// Store this block's K partial sums (thread 0), then take a ticket.  Returns true in
+// every thread of the last block to arrive; tot[] then holds the fixed-order totals in
+// thread 0 of that block, and the ticket has been reset to 0.
+template <int K>
+__device__ bool reduce_grid(double (&v)[K], double* partials, int slot, int nb, PcgState* st,
+                            double (&tot)[K]) {
+    block_sum<K>(v);
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) partials[k * nb + slot] = v[k];
+        __threadfence();
+        const unsigned t = atomicAdd(&st->ticket, 1u);
+        is_last = (t == (unsigned)(nb - 1));
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nb; i += WG) s += partials[k * nb + i];
+        tot[k] = s;
+    }
+    block_sum<K>(tot);
+    if (threadIdx.x == 0) st->ticket = 0u;
+    return true;
+}
+
+__device__ __forceinline__ bool finite(double x) { return isfinite(x); }
+
+// ---------------------------------------------------------------------------
+// Solver state
+// ---------------------------------------------------------------------------
+__global__ void k_state_init(PcgState* st, double tol, int maxit) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->rz = st->pq = st->alpha = st->beta = st->rr = st->bb = 0.0;
+        st->tol = tol;
+        st->tol2 = 0.0;
+        st->scale = 1.0;
+        st->rr_first = 0.0;
+        st->iters = 0;
+        st->maxit = maxit;
+        st->done = 0;
+        st->status = RAFEM_E_NOCONV;
+        st->bad_diag = 0;
+        st->ticket = 0u;
+    }
+}
+
+// dinv = 1 / diag(A) (also as FP32).  A missing or non-positive diagonal marks the state.
+__global__ __launch_bounds__(WG) void k_diag_inv(const int* __restrict__ rp,
+                                                 const int* __restrict__ ci,
+                                                 const double* __restrict__ v, int n,
+                                                 double* __restrict__ dinv,
+                                                 float* __restrict__ dinv32, PcgState* st) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (ci[k] == i) d += v[k];
+    const double inv = (d > 0.0 && finite(d)) ? 1.0 / d : 0.0;
+    if (!(d > 0.0) || !finite(d)) st->bad_diag = 1;
+    dinv[i] = inv;
+    if (dinv32) dinv32[i] = (float)inv;
+}
+
+// ---------------------------------------------------------------------------
+// Row kernels (CSR, LANES lanes per row)
+// ---------------------------------------------------------------------------
+enum RowMode : int {
+    ROW_PLAIN = 0,  // y = A x
+    ROW_DOT = 1,    // y = A x, sum x.y -> alpha (PCG step; early exit when done)
+    ROW_START = 2,  // y = b - A x, p = D^-1 y, sums y.p, y.y, b.b (PCG start)
+    ROW_RESID = 3,  // y = b - A x, sums y.y, b.b (refinement residual / true residual)
+};
+
+template <typename T>
+struct RowArgs {
+    const int* __restrict__ rp;
+    const int* __restrict__ ci;
+    const T* __restrict__ val;
+    const T* __restrict__ x;
+    T* __restrict__ y;
+    const double* __restrict__ b;
+    const double* __restrict__ dinv;
+    double* __restrict__ pout;
+    double* partials;
+    PcgState* st;
+    int n;
+    int rows_per_block;
+    int outer_mode;
+};
+
+template <typename T, int LANES, int MODE>
+__global__ __launch_bounds__(WG) void k_rows(RowArgs<T> a) {
+    if constexpr (MODE == ROW_DOT) {
+        if (a.st->done) return;
+    }
+    const int nb = gridDim.x;
+    const int blk = xcd_block(blockIdx.x, nb);
+    const int row0 = blk * a.rows_per_block;
+    const int row1 = min(row0 + a.rows_per_block, a.n);
+    const int g = threadIdx.x / LANES, sub = threadIdx.x % LANES;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int r = row0 + g; r < row1; r += WG / LANES) {
+        const int s = a.rp[r], e = a.rp[r + 1];
+        T sum = T(0);
+#pragma unroll 4
+        for (int k = s + sub; k < e; k += LANES) sum += a.val[k] * a.x[a.ci[k]];
+#pragma unroll
+        for (int off = LANES / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, LANES);
+        if (sub == 0) {
+            if constexpr (MODE == ROW_PLAIN) {
+                a.y[r] = sum;
+            } else if constexpr (MODE == ROW_DOT) {
+                a.y[r] = sum;
+                acc[0] += (double)a.x[r] * (double)sum;
+            } else {
+                const double bi = a.b[r];
+                const double ri = bi - (double)sum;
+                a.y[r] = (T)ri;
+                acc[1] += ri * ri;
+                acc[2] += bi * bi;
+                if constexpr (MODE == ROW_START) {
+                    const double zi = a.dinv[r] * ri;
+                    a.pout[r] = zi;
+                    acc[0] += ri * zi;
+                }
+            }
+        }
+    }
+    if constexpr (MODE == ROW_PLAIN) return;
+    double tot[3];
+    if (!reduce_grid<3>(acc, a.partials, blk, nb, a.st, tot)) return;
+    if (threadIdx.x != 0) return;
+    PcgState* st = a.st;
+    if constexpr (MODE == ROW_DOT) {
+        const double pq = tot[0];
+        st->pq = pq;
+        if (!(pq > 0.0) || !finite(pq)) {
+            st->status = RAFEM_E_BREAKDOWN;
+            st->done = 1;
+        } else {
+            st->alpha = st->rz / pq;
+        }
+    } else if constexpr (MODE == ROW_START) {
+        st->rz = tot[0];
+        st->rr = tot[1];
+        st->bb = tot[2];
+        st->rr_first = tot[1];
+        st->tol2 = st->tol * st->tol * tot[2];
+        st->iters = 0;
+        if (st->bad_diag || !finite(tot[0]) || !finite(tot[1]) || !finite(tot[2])) {
+            st->status = RAFEM_E_BREAKDOWN;
+            st->done = 1;
+        } else if (tot[1] <= st->tol2) {
+            st->status = RAFEM_OK;
+            st->done = 1;
+        } else {
+            st->status = RAFEM_E_NOCONV;
+            st->done = 0;
+        }
+    } else {  // ROW_RESID
+        st->rr = tot[1];
+        st->bb = tot[2];
+        if (a.outer_mode) {
+            st->tol2 = st->tol * st->tol * tot[2];
+            if (st->iters == 0) st->rr_first = tot[1];
+            if (st->bad_diag || !finite(tot[1]) || !finite(tot[2])) {
+                st->status = RAFEM_E_BREAKDOWN;
+                st->done = 1;
+            } else if (tot[1] <= st->tol2) {
+                st->status = RAFEM_OK;
+                st->done = 1;
+            } else if (st->iters >= st->maxit) {
+                st->status = RAFEM_E_NOCONV;
+                st->done = 1;
+            } else {
+                st->scale = 1.0 / sqrt(tot[1]);
+                st->iters += 1;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels (4 rows per thread, contiguous block ranges)
+// ---------------------------------------------------------------------------
+constexpr int VPT = kVecRowsPerBlock / WG;
+
+// x += alpha p; r -= alpha q; z = D^-1 r; sums r.z, r.r; convergence and beta.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_update(int n, T* __restrict__ x, T* __restrict__ r,
+                                               const T* __restrict__ p,
+                                               const T* __restrict__ q,
+                                               const T* __restrict__ dinv, double* partials,
+                                               PcgState* st) {
+    if (st->done) return;
+    const T alpha = (T)st->alpha;
+    const int nb = gridDim.x;
+    const int blk = xcd_block(blockIdx.x, nb);
+    const int i0 = blk * kVecRowsPerBlock + threadIdx.x;
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+        const int i = i0 + j * WG;
+        if (i < n) {
+            const T xi = x[i] + alpha * p[i];
+            const T ri = r[i] - alpha * q[i];
+            x[i] = xi;
+            r[i] = ri;
+            const T zi = dinv[i] * ri;
+            acc[0] += (double)ri * (double)zi;
+            acc[1] += (double)ri * (double)ri;
+        }
+    }
+    double tot[2];
+    if (!reduce_grid<2>(acc, partials, blk, nb, st, tot)) return;
+    if (threadIdx.x != 0) return;
+    st->iters += 1;
+    st->rr = tot[1];
+    if (!finite(tot[0]) || !finite(tot[1]) || tot[0] < 0.0) {
+        st->status = RAFEM_E_BREAKDOWN;
+        st->done = 1;
+    } else if (tot[1] <= st->tol2) {
+        st->status = RAFEM_OK;
+        st->done = 1;
+    } else if (st->iters >= st->maxit) {
+        st->status = RAFEM_E_NOCONV;
+        st->done = 1;
+    } else {
+        st->beta = tot[0] / st->rz;
+        st->rz = tot[0];
+    }
+}
+
+// p = D^-1 r + beta p
+template <typename T>
+__global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
+                                                const T* __restrict__ r,
+                                                const T* __restrict__ dinv, PcgState* st) {
+    if (st->done) return;
+    const T beta = (T)st->beta;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int i0 = blk * kVecRowsPerBlock + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+        const int i = i0 + j * WG;
+        if (i < n) p[i] = dinv[i] * r[i] + beta * p[i];
+    }
+}
+
+// Mixed refinement: inner right-hand side r32 = r64 / ||r64||, d32 = 0, p32 = D^-1 r32.
+__global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restrict__ r64,
+                                                    const PcgState* outer,
+                                                    float* __restrict__ r32,
+                                                    float* __restrict__ d32,
+                                                    float* __restrict__ p32,
+                                                    const float* __restrict__ dinv32,
+                                                    double inner_tol, int maxit,
+                                                    double* partials, PcgState* inner) {
+    const bool skip = outer->done != 0;
+    const double scale = outer->scale;
+    const int nb = gridDim.x;
+    const int blk = xcd_block(blockIdx.x, nb);
+    const int i0 = blk * kVecRowsPerBlock + threadIdx.x;
+    double acc[2] = {0.0, 0.0};
+    if (!skip) {
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) {
+            const int i = i0 + j * WG;
+            if (i < n) {
+                const float ri = (float)(r64[i] * scale);
+                const float zi = dinv32[i] * ri;
+                r32[i] = ri;
+                d32[i] = 0.0f;
+                p32[i] = zi;
+                acc[0] += (double)ri * (double)zi;
+                acc[1] += (double)ri * (double)ri;
+            }
+        }
+    }
+    double tot[2];
+    if (!reduce_grid<2>(acc, partials, blk, nb, inner, tot)) return;
+    if (threadIdx.x != 0) return;
+    inner->rz = tot[0];
+    inner->rr = tot[1];
+    inner->bb = tot[1];
+    inner->rr_first = tot[1];
+    inner->tol = inner_tol;
+    inner->tol2 = inner_tol * inner_tol * tot[1];
+    inner->iters = 0;
+    inner->maxit = maxit;
+    inner->bad_diag = 0;
+    if (skip || !(tot[1] > 0.0)) {
+        inner->status = RAFEM_OK;
+        inner->done = 1;
+    } else if (!finite(tot[0]) || !finite(tot[1])) {
+        inner->status = RAFEM_E_BREAKDOWN;
+        inner->done = 1;
+    } else {
+        inner->status = RAFEM_E_NOCONV;
+        inner->done = 0;
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_refine_update(int n, double* __restrict__ x,
+                                                      const float* __restrict__ d32,
+                                                      const PcgState* outer) {
+    if (outer->done) return;
+    const double norm = 1.0 / outer->scale;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int i0 = blk * kVecRowsPerBlock + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+        const int i = i0 + j * WG;
+        if (i < n) x[i] += (double)d32[i] * norm;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Assembly helpers
+// ---------------------------------------------------------------------------
+__global__ void k_fill(double* __restrict__ v, int64_t n, double value) {
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i < n) v[i] = value;
+}
+
+__global__ void k_cast32(const double* __restrict__ v, float* __restrict__ v32, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i < n) v32[i] = (float)v[i];
+}
+
+__global__ void k_coef(const double* __restrict__ perf, double c0, double* __restrict__ coef,
+                       int64_t E) {
+    const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (e < E) coef[e] = c0 + perf[e];
+}
+
+__global__ void k_scatter_dirichlet(const int* __restrict__ ids, const double* __restrict__ vals,
+                                    int64_t nD, double* __restrict__ gnode) {
+    const int64_t k = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (k < nD) gnode[ids[k]] = vals[k];
+}
+
+__global__ void k_set_dirichlet(const int* __restrict__ ids, const double* __restrict__ gnode,
+                                int64_t nD, double* __restrict__ x) {
+    const int64_t k = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (k < nD) x[ids[k]] = gnode[ids[k]];
+}
+
+// Position of column `col` in the sorted column list [s, e) of a row.
+__device__ __forceinline__ int find_slot(const int* __restrict__ ci, int s, int e, int col) {
+    while (s < e) {
+        const int m = (s + e) >> 1;
+        if (ci[m] < col) s = m + 1;
+        else e = m;
+    }
+    return s;
+}
+
+// Reference-cube corner signs of hex local node a in the ABI order
+// (0,0,0),(1,0,0),(1,1,0),(0,1,0),(0,0,1),(1,0,1),(1,1,1),(0,1,1).
+__device__ __forceinline__ double hsx(int a) { return ((a + 1) & 2) ? 1.0 : -1.0; }
+__device__ __forceinline__ double hsy(int a) { return (a & 2) ? 1.0 : -1.0; }
+__device__ __forceinline__ double hsz(int a) { return (a & 4) ? 1.0 : -1.0; }
+
+// Trilinear shape function b and its reference gradient at (xi, et, ze).
+__device__ __forceinline__ void hex_shape(int b, double xi, double et, double ze, double& N,
+                                          double& d0, double& d1, double& d2) {
+    const double sx = hsx(b), sy = hsy(b), sz = hsz(b);
+    const double f0 = 1.0 + sx * xi, f1 = 1.0 + sy * et, f2 = 1.0 + sz * ze;
+    N = 0.125 * f0 * f1 * f2;
+    d0 = 0.125 * sx * f1 * f2;
+    d1 = 0.125 * sy * f0 * f2;
+    d2 = 0.125 * sz * f0 * f1;
+}
+
+// J[i][d] = dx_i/dxi_d at a Gauss point; returns det and Jinv[d][i] = dxi_d/dx_i.
+__device__ __forceinline__ double hex_jacobian(const double (&X)[8][3], double xi, double et,
+                                               double ze, double (&Ji)[3][3]) {
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        double N, d0, d1, d2;
+        hex_shape(b, xi, et, ze, N, d0, d1, d2);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            J[i][0] += X[b][i] * d0;
+            J[i][1] += X[b][i] * d1;
+            J[i][2] += X[b][i] * d2;
+        }
+    }
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double id = 1.0 / det;
+    // inverse of J: (J^-1)[d][i]
+    Ji[0][0] = c00 * id;
+    Ji[1][0] = c01 * id;
+    Ji[2][0] = c02 * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    return det;
+}
+
+__device__ __forceinline__ void grad_x(const double (&Ji)[3][3], double d0, double d1, double d2,
+                                       double (&g)[3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g[i] = Ji[0][i] * d0 + Ji[1][i] * d1 + Ji[2][i] * d2;
+}
+
+constexpr double kGauss = 0.57735026918962576451;  // 1/sqrt(3)
+
+__device__ __forceinline__ void gauss_point(int q, double& xi, double& et, double& ze) {
+    xi = (q & 1) ? kGauss : -kGauss;
+    et = (q & 2) ? kGauss : -kGauss;
+    ze = (q & 4) ? kGauss : -kGauss;
+}
+
+// Row a of the stiffness and mass of hex element with corner coordinates X.
+__device__ void hex_rows(const double (&X)[8][3], int a, double (&Kr)[8], double (&Mr)[8]) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) Kr[b] = Mr[b] = 0.0;
+    for (int q = 0; q < 8; ++q) {
+        double xi, et, ze;
+        gauss_point(q, xi, et, ze);
+        double Ji[3][3];
+        const double det = hex_jacobian(X, xi, et, ze, Ji);
+        double Na, a0, a1, a2, ga[3];
+        hex_shape(a, xi, et, ze, Na, a0, a1, a2);
+        grad_x(Ji, a0, a1, a2, ga);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            double Nb, b0, b1, b2, gb[3];
+            hex_shape(b, xi, et, ze, Nb, b0, b1, b2);
+            grad_x(Ji, b0, b1, b2, gb);
+            Kr[b] += det * (ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2]);
+            Mr[b] += det * Na * Nb;
+        }
+    }
+}
+
+// Tet: volume and constant gradients of the barycentric coordinates.
+__device__ __forceinline__ double tet_geometry(const double (&X)[4][3], double (&G)[4][3]) {
+    double J[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) J[i][c] = X[c + 1][i] - X[0][i];
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double id = 1.0 / det;
+    // rows of J^-1 are the gradients of barycentric coordinates 1..3
+    G[1][0] = c00 * id;
+    G[1][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    G[1][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    G[2][0] = c01 * id;
+    G[2][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    G[2][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    G[3][0] = c02 * id;
+    G[3][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    G[3][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) G[0][i] = -(G[1][i] + G[2][i] + G[3][i]);
+    return det / 6.0;
+}
+
+// One thread per (element of this colour, local row a): add row a of
+// mass[e] M_e + stiff[e] K_e into the CSR values.  Elements of one colour share no
+// node, so no two threads of a launch touch the same row.
+template <int NPE>
+__global__ __launch_bounds__(WG) void k_assemble(const int* __restrict__ elems, int count,
+                                                 const int* __restrict__ conn,
+                                                 const double* __restrict__ xyz,
+                                                 const int* __restrict__ rp,
+                                                 const int* __restrict__ ci,
+                                                 const double* __restrict__ mass,
+                                                 const double* __restrict__ stiff,
+                                                 double* __restrict__ vals) {
+    const int t = blockIdx.x * WG + threadIdx.x;
+    if (t >= count * NPE) return;
+    const int e = elems[t / NPE];
+    const int a = t % NPE;
+    int nodes[NPE];
+    double X[NPE][3];
+#pragma unroll
+    for (int b = 0; b < NPE; ++b) {
+        nodes[b] = conn[(int64_t)e * NPE + b];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) X[b][i] = xyz[(int64_t)nodes[b] * 3 + i];
+    }
+    const double m = mass ? mass[e] : 0.0;
+    const double c = stiff ? stiff[e] : 0.0;
+    double Kr[NPE], Mr[NPE];
+    if constexpr (NPE == 8) {
+        hex_rows(X, a, Kr, Mr);
+    } else {
+        double G[4][3];
+        const double V = tet_geometry(X, G);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            Kr[b] = V * (G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2]);
+            Mr[b] = (a == b ? 2.0 : 1.0) * V / 20.0;
+        }
+    }
+    const int row = nodes[a];
+    const int s = rp[row], en = rp[row + 1];
+#pragma unroll
+    for (int b = 0; b < NPE; ++b) {
+        const int k = find_slot(ci, s, en, nodes[b]);
+        vals[k] += m * Mr[b] + c * Kr[b];
+    }
+}
+
+// Symmetric lifting of Dirichlet rows/columns, Jacobi inverse and FP32 copy.
+__global__ __launch_bounds__(WG) void k_lift(int n, const int* __restrict__ rp,
+                                             const int* __restrict__ ci,
+                                             double* __restrict__ vals,
+                                             float* __restrict__ vals32,
+                                             const uint8_t* __restrict__ isD,
+                                             const double* __restrict__ gnode,
+                                             double* __restrict__ lift, double* __restrict__ dinv,
+                                             float* __restrict__ dinv32, int do_lift) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= n) return;
+    const int s = rp[i], e = rp[i + 1];
+    double diag = 0.0;
+    if (do_lift && isD[i]) {
+        for (int k = s; k < e; ++k) {
+            const double v = (ci[k] == i) ? 1.0 : 0.0;
+            vals[k] = v;
+            if (vals32) vals32[k] = (float)v;
+        }
+        diag = 1.0;
+        if (lift) lift[i] = gnode[i];
+    } else {
+        double acc = 0.0;
+        for (int k = s; k < e; ++k) {
+            const int c = ci[k];
+            double v = vals[k];
+            if (do_lift && isD[c]) {
+                acc += v * gnode[c];
+                v = 0.0;
+                vals[k] = 0.0;
+            }
+            if (c == i) diag = v;
+            if (vals32) vals32[k] = (float)v;
+        }
+        if (do_lift && lift) lift[i] = -acc;
+    }
+    if (dinv) {
+        const double inv = 1.0 / diag;
+        dinv[i] = inv;
+        if (dinv32) dinv32[i] = (float)inv;
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_sigma(int npe, int64_t E, const int* __restrict__ conn,
+                                              const double* __restrict__ T,
+                                              const double* __restrict__ sigma0, double alpha,
+                                              double T_ref, double* __restrict__ sigma) {
+    const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (e >= E) return;
+    double s = 0.0;
+    for (int a = 0; a < npe; ++a) s += T[conn[e * npe + a]];
+    sigma[e] = sigma0[e] * (1.0 + alpha * (s / npe - T_ref));
+}
+
+// Bioheat right-hand side, one thread per (element of this colour, local node a):
+// rhs[node a] += sum_b M_ab (rho_c_dt T_b + perf_e T_a) + int N_a sigma_e |grad V|^2.
+template <int NPE>
+__global__ __launch_bounds__(WG) void k_bioheat_rhs(const int* __restrict__ elems, int count,
+                                                    const int* __restrict__ conn,
+                                                    const double* __restrict__ xyz,
+                                                    const double* __restrict__ T,
+                                                    const double* __restrict__ V,
+                                                    const double* __restrict__ sigma,
+                                                    const double* __restrict__ perf,
+                                                    double rho_c_dt, double T_a, int with_joule,
+                                                    double* __restrict__ rhs) {
+    const int t = blockIdx.x * WG + threadIdx.x;
+    if (t >= count * NPE) return;
+    const int e = elems[t / NPE];
+    const int a = t % NPE;
+    int nodes[NPE];
+    double X[NPE][3], Tw[NPE], Vb[NPE];
+    const double src = perf[e] * T_a;
+#pragma unroll
+    for (int b = 0; b < NPE; ++b) {
+        nodes[b] = conn[(int64_t)e * NPE + b];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) X[b][i] = xyz[(int64_t)nodes[b] * 3 + i];
+        Tw[b] = rho_c_dt * T[nodes[b]] + src;
+        Vb[b] = with_joule ? V[nodes[b]] : 0.0;
+    }
+    const double sg = with_joule ? sigma[e] : 0.0;
+    double f = 0.0;
+    if constexpr (NPE == 8) {
+        for (int q = 0; q < 8; ++q) {
+            double xi, et, ze;
+            gauss_point(q, xi, et, ze);
+            double Ji[3][3];
+            const double det = hex_jacobian(X, xi, et, ze, Ji);
+            double Nw = 0.0, gv0 = 0.0, gv1 = 0.0, gv2 = 0.0, Na = 0.0;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                double Nb, d0, d1, d2;
+                hex_shape(b, xi, et, ze, Nb, d0, d1, d2);
+                if (b == a) Na = Nb;
+                Nw += Nb * Tw[b];
+                gv0 += Vb[b] * d0;
+                gv1 += Vb[b] * d1;
+                gv2 += Vb[b] * d2;
+            }
+            double gV[3];
+            grad_x(Ji, gv0, gv1, gv2, gV);
+            f += det * Na * (Nw + sg * (gV[0] * gV[0] + gV[1] * gV[1] + gV[2] * gV[2]));
+        }
+    } else {
+        double G[4][3];
+        const double vol = tet_geometry(X, G);
+        double sumw = 0.0, gV[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            sumw += Tw[b];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) gV[i] += Vb[b] * G[b][i];
+        }
+        f = vol / 20.0 * (sumw + Tw[a]) +
+            sg * (gV[0] * gV[0] + gV[1] * gV[1] + gV[2] * gV[2]) * vol / 4.0;
+    }
+    rhs[nodes[a]] += f;
+}
+
+__global__ void k_finish_rhs(int n, const double* __restrict__ rhs,
+                             const double* __restrict__ lift, const uint8_t* __restrict__ isD,
+                             double* __restrict__ b) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i < n) b[i] = isD[i] ? lift[i] : rhs[i] + lift[i];
+}
+
+inline int grid1(int64_t n) { return (int)((n + WG - 1) / WG); }
+
+template <typename T, int MODE>
+void launch_rows(const SpmvConfig& c, const RowArgs<T>& a, hipStream_t s) {
+    const int nb = blocks_for(a.n, c.rows_per_block);
+    if (nb == 0) return;
+    switch (c.lanes) {
+        case 2: hipLaunchKernelGGL((k_rows<T, 2, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_rows<T, 8, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_rows<T, 16, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_rows<T, 4, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
+    }
+}
+
+inline int vec_blocks(int n) { return (n + kVecRowsPerBlock - 1) / kVecRowsPerBlock; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+int blocks_for(int64_t n, int rows_per_block) {
+    return (int)((n + rows_per_block - 1) / rows_per_block);
+}
+
+SpmvConfig choose_spmv_config(int64_t n, int64_t nnz) {
+    const double avg = n > 0 ? (double)nnz / (double)n : 1.0;
+    SpmvConfig c;
+    c.lanes = avg > 20.0 ? 4 : (avg > 6.0 ? 4 : 2);
+    const int rows_per_pass = WG / c.lanes;
+    int passes = 8;
+    // keep at least ~4 blocks per CU when the matrix is small
+    while (passes > 1 && blocks_for(n, rows_per_pass * passes) < 1024) passes /= 2;
+    c.rows_per_block = rows_per_pass * passes;
+    return c;
+}
+
+void launch_state_init(PcgState* st, double tol, int maxit, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, tol, maxit);
+}
+
+void launch_diag_inv(const Csr64& A, double* dinv, float* dinv32, PcgState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_inv, dim3(grid1(A.n)), dim3(WG), 0, s, A.rp, A.ci, A.v, A.n, dinv,
+                       dinv32, st);
+}
+
+void launch_pcg_start(const Csr64& A, const SpmvConfig& c, const double* b, const double* x,
+                      const double* dinv, double* r, double* p, double* partials, PcgState* st,
+                      hipStream_t s) {
+    RowArgs<double> a{A.rp, A.ci, A.v, x, r, b, dinv, p, partials, st, A.n, c.rows_per_block, 0};
+    launch_rows<double, ROW_START>(c, a, s);
+}
+
+void launch_spmv_dot64(const Csr64& A, const SpmvConfig& c, const double* p, double* q,
+                       double* partials, PcgState* st, hipStream_t s) {
+    RowArgs<double> a{A.rp, A.ci, A.v, p, q, nullptr, nullptr, nullptr, partials, st, A.n,
+                      c.rows_per_block, 0};
+    launch_rows<double, ROW_DOT>(c, a, s);
+}
+
+void launch_spmv_dot32(const Csr32& A, const SpmvConfig& c, const float* p, float* q,
+                       double* partials, PcgState* st, hipStream_t s) {
+    RowArgs<float> a{A.rp, A.ci, A.v, p, q, nullptr, nullptr, nullptr, partials, st, A.n,
+                     c.rows_per_block, 0};
+    launch_rows<float, ROW_DOT>(c, a, s);
+}
+
+void launch_spmv64(const Csr64& A, const SpmvConfig& c, const double* x, double* y,
+                   hipStream_t s) {
+    RowArgs<double> a{A.rp, A.ci, A.v, x, y, nullptr, nullptr, nullptr, nullptr, nullptr, A.n,
+                      c.rows_per_block, 0};
+    launch_rows<double, ROW_PLAIN>(c, a, s);
+}
+
+void launch_spmv32(const Csr32& A, const SpmvConfig& c, const float* x, float* y,
+                   hipStream_t s) {
+    RowArgs<float> a{A.rp, A.ci, A.v, x, y, nullptr, nullptr, nullptr, nullptr, nullptr, A.n,
+                     c.rows_per_block, 0};
+    launch_rows<float, ROW_PLAIN>(c, a, s);
+}
+
+void launch_residual64(const Csr64& A, const SpmvConfig& c, const double* b, const double* x,
+                       double* r, double* partials, PcgState* st, int outer_mode, hipStream_t s) {
+    RowArgs<double> a{A.rp, A.ci, A.v, x, r, b, nullptr, nullptr, partials, st, A.n,
+                      c.rows_per_block, outer_mode};
+    launch_rows<double, ROW_RESID>(c, a, s);
+}
+
+void launch_update64(int n, double* x, double* r, const double* p, const double* q,
+                     const double* dinv, double* partials, PcgState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_update<double>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, x, r, p, q,
+                       dinv, partials, st);
+}
+
+void launch_update32(int n, float* x, float* r, const float* p, const float* q,
+                     const float* dinv, double* partials, PcgState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_update<float>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, x, r, p, q, dinv,
+                       partials, st);
+}
+
+void launch_pupdate64(int n, double* p, const double* r, const double* dinv, PcgState* st,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_pupdate<double>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv,
+                       st);
+}
+
+void launch_pupdate32(int n, float* p, const float* r, const float* dinv, PcgState* st,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_pupdate<float>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv, st);
+}
+
+void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,
+                        float* p32, const float* dinv32, double inner_tol, int maxit,
+                        double* partials, PcgState* inner, hipStream_t s) {
+    hipLaunchKernelGGL(k_inner_start, dim3(vec_blocks(n)), dim3(WG), 0, s, n, r64, outer, r32,
+                       d32, p32, dinv32, inner_tol, maxit, partials, inner);
+}
+
+void launch_refine_update(int n, double* x, const float* d32, const PcgState* outer,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_refine_update, dim3(vec_blocks(n)), dim3(WG), 0, s, n, x, d32, outer);
+}
+
+void launch_fill(double* v, int64_t n, double value, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid1(n)), dim3(WG), 0, s, v, n, value);
+}
+
+void launch_cast32(const double* v, float* v32, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_cast32, dim3(grid1(n)), dim3(WG), 0, s, v, v32, n);
+}
+
+void launch_coef(const double* perf, double c0, double* coef, int64_t E, hipStream_t s) {
+    if (E > 0) hipLaunchKernelGGL(k_coef, dim3(grid1(E)), dim3(WG), 0, s, perf, c0, coef, E);
+}
+
+void launch_scatter_dirichlet(const int32_t* ids, const double* vals, int64_t nD, double* gnode,
+                              hipStream_t s) {
+    if (nD > 0)
+        hipLaunchKernelGGL(k_scatter_dirichlet, dim3(grid1(nD)), dim3(WG), 0, s, ids, vals, nD,
+                           gnode);
+}
+
+void launch_set_dirichlet(const int32_t* ids, const double* gnode, int64_t nD, double* x,
+                          hipStream_t s) {
+    if (nD > 0)
+        hipLaunchKernelGGL(k_set_dirichlet, dim3(grid1(nD)), dim3(WG), 0, s, ids, gnode, nD, x);
+}
+
+void launch_assemble_colour(int npe, const int32_t* elems, int count, const int32_t* conn,
+                            const double* xyz, const int32_t* rp, const int32_t* ci,
+                            const double* mass, const double* stiff, double* vals,
+                            hipStream_t s) {
+    if (count <= 0) return;
+    const int grid = grid1((int64_t)count * npe);
+    if (npe == 8)
+        hipLaunchKernelGGL(k_assemble<8>, dim3(grid), dim3(WG), 0, s, elems, count, conn, xyz, rp,
+                           ci, mass, stiff, vals);
+    else
+        hipLaunchKernelGGL(k_assemble<4>, dim3(grid), dim3(WG), 0, s, elems, count, conn, xyz, rp,
+                           ci, mass, stiff, vals);
+}
+
+void launch_lift(int n, const int32_t* rp, const int32_t* ci, double* vals, float* vals32,
+                 const uint8_t* isD, const double* gnode, double* lift, double* dinv,
+                 float* dinv32, int do_lift, hipStream_t s) {
+    hipLaunchKernelGGL(k_lift, dim3(grid1(n)), dim3(WG), 0, s, n, rp, ci, vals, vals32, isD, gnode,
+                       lift, dinv, dinv32, do_lift);
+}
+
+void launch_sigma(int npe, int64_t E, const int32_t* conn, const double* T, const double* sigma0,
+                  double alpha, double T_ref, double* sigma, hipStream_t s) {
+    hipLaunchKernelGGL(k_sigma, dim3(grid1(E)), dim3(WG), 0, s, npe, E, conn, T, sigma0, alpha,
+                       T_ref, sigma);
+}
+
+void launch_bioheat_rhs_colour(int npe, const int32_t* elems, int count, const int32_t* conn,
+                               const double* xyz, const double* T, const double* V,
+                               const double* sigma, const double* perf, double rho_c_dt,
+                               double T_a, int with_joule, double* rhs, hipStream_t s) {
+    if (count <= 0) return;
+    const int grid = grid1((int64_t)count * npe);
+    if (npe == 8)
+        hipLaunchKernelGGL(k_bioheat_rhs<8>, dim3(grid), dim3(WG), 0, s, elems, count, conn, xyz, T,
+                           V, sigma, perf, rho_c_dt, T_a, with_joule, rhs);
+    else
+        hipLaunchKernelGGL(k_bioheat_rhs<4>, dim3(grid), dim3(WG), 0, s, elems, count, conn, xyz, T,
+                           V, sigma, perf, rho_c_dt, T_a, with_joule, rhs);
+}
+
+void launch_finish_rhs(int n, const double* rhs, const double* lift, const uint8_t* isD,
+                       double* b, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish_rhs, dim3(grid1(n)), dim3(WG), 0, s, n, rhs, lift, isD, b);
+}
+
+}  // namespace rafem

@@ -1,0 +1,30 @@
+// Host drivers of the PCG solves (solver.cpp).
+#pragma once
+
+#include "internal.hpp"
+
+namespace rafem {
+
+struct SolveOpts {
+    double tol = 1e-10;
+    int maxit = 20000;
+    int precision = RAFEM_FP64;
+    double inner_tol = 1e-4;
+    int max_outer = 30;
+    int poll_every = 0;
+};
+
+SolveOpts resolve_opts(const rafem_solve_opts* o, double default_tol);
+
+// FP64 Jacobi-PCG on A from x (in/out).  dinv may be NULL (computed from A's diagonal).
+// hint: expected iteration count (0 = unknown).  Fills info, returns its status.
+rafem_status pcg64(rafem_mesh m, const Csr64& A, const double* dinv, const double* b, double* x,
+                   const SolveOpts& o, rafem_solve_info* info, hipStream_t s, int hint,
+                   int* iters_out);
+
+// FP32 inner PCG inside FP64 iterative refinement.  dinv/dinv32 may be NULL.
+rafem_status pcg_mixed(rafem_mesh m, const Csr64& A, const Csr32& A32, const double* dinv,
+                       const float* dinv32, const double* b, double* x, const SolveOpts& o,
+                       rafem_solve_info* info, hipStream_t s, int hint, int* iters_out);
+
+}  // namespace rafem

@@ -1,0 +1,177 @@
+// Host-side mesh analysis: CSR structure of the node graph, greedy element
+// colouring, and element validity checks.  Done once per mesh: the paper reuses
+// the matrix structure across all time steps (Sec. III-B).
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "internal.hpp"
+
+namespace rafem {
+
+namespace {
+
+template <typename F>
+void parallel_for(int64_t n, F&& f) {
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 1, 16));
+    if (n < 100000) nt = 1;
+    if (nt == 1) {
+        f(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t chunk = (n + nt - 1) / nt;
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t lo = t * chunk, hi = std::min(n, lo + chunk);
+        if (lo >= hi) break;
+        th.emplace_back([&f, lo, hi] { f(lo, hi); });
+    }
+    for (auto& x : th) x.join();
+}
+
+// node -> incident elements, as CSR (n2e_ptr [n+1], n2e [E*npe])
+void node_to_elements(int64_t n, int64_t E, int npe, const int32_t* conn,
+                      std::vector<int64_t>& ptr, std::vector<int32_t>& adj) {
+    ptr.assign(n + 1, 0);
+    for (int64_t i = 0; i < E * npe; ++i) ptr[conn[i] + 1]++;
+    for (int64_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+    adj.resize(E * npe);
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int64_t e = 0; e < E; ++e)
+        for (int a = 0; a < npe; ++a) adj[fill[conn[e * npe + a]]++] = (int32_t)e;
+}
+
+}  // namespace
+
+void check_conn(int64_t n_nodes, int64_t n_elems, int npe, const int32_t* conn) {
+    if (n_nodes <= 0 || n_nodes > INT32_MAX - 1) throw Error{RAFEM_E_ARG, "n_nodes out of range"};
+    if (n_elems <= 0 || n_elems > INT32_MAX / 8) throw Error{RAFEM_E_ARG, "n_elems out of range"};
+    if (npe != 8 && npe != 4) throw Error{RAFEM_E_ARG, "nodes_per_elem must be 8 (hex) or 4 (tet)"};
+    if (!conn) throw Error{RAFEM_E_ARG, "conn is NULL"};
+    for (int64_t i = 0; i < n_elems * npe; ++i)
+        if (conn[i] < 0 || conn[i] >= n_nodes)
+            throw Error{RAFEM_E_MESH, "element " + std::to_string(i / npe) +
+                                          " refers to node " + std::to_string(conn[i]) +
+                                          " outside [0, n_nodes)"};
+    for (int64_t e = 0; e < n_elems; ++e)
+        for (int a = 0; a < npe; ++a)
+            for (int b = a + 1; b < npe; ++b)
+                if (conn[e * npe + a] == conn[e * npe + b])
+                    throw Error{RAFEM_E_MESH, "element " + std::to_string(e) + " repeats a node"};
+}
+
+HostStructure build_structure(int64_t n, int64_t E, int npe, const int32_t* conn) {
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> adj;
+    node_to_elements(n, E, npe, conn, ptr, adj);
+
+    // Pass 1: row lengths.  Pass 2: sorted unique columns.
+    std::vector<int64_t> len(n + 1, 0);
+    auto row_cols = [&](int64_t i, std::vector<int32_t>& buf) {
+        buf.clear();
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const int32_t* el = conn + (int64_t)adj[k] * npe;
+            for (int a = 0; a < npe; ++a) buf.push_back(el[a]);
+        }
+        std::sort(buf.begin(), buf.end());
+        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+    };
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        std::vector<int32_t> buf;
+        for (int64_t i = lo; i < hi; ++i) {
+            row_cols(i, buf);
+            if (buf.empty()) buf.push_back((int32_t)i);  // isolated node: keep a diagonal
+            len[i + 1] = (int64_t)buf.size();
+        }
+    });
+    for (int64_t i = 0; i < n; ++i) len[i + 1] += len[i];
+    if (len[n] > INT32_MAX) throw Error{RAFEM_E_MESH, "nnz exceeds INT32_MAX"};
+    HostStructure S;
+    S.row_ptr.resize(n + 1);
+    for (int64_t i = 0; i <= n; ++i) S.row_ptr[i] = (int32_t)len[i];
+    S.col_idx.resize(len[n]);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        std::vector<int32_t> buf;
+        for (int64_t i = lo; i < hi; ++i) {
+            row_cols(i, buf);
+            if (buf.empty()) buf.push_back((int32_t)i);
+            std::memcpy(S.col_idx.data() + len[i], buf.data(), buf.size() * sizeof(int32_t));
+        }
+    });
+    return S;
+}
+
+int colour_elements(int64_t n, int64_t E, int npe, const int32_t* conn, int32_t* colour) {
+    // Greedy first fit in element order.  mask[node] holds the colours of the already
+    // coloured elements that touch the node; an element takes the lowest colour absent
+    // from the union of its nodes' masks, so no two elements of one colour share a node.
+    std::vector<uint64_t> mask(n, 0);
+    int used = 0;
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t* el = conn + e * npe;
+        uint64_t taken = 0;
+        for (int a = 0; a < npe; ++a) taken |= mask[el[a]];
+        if (taken == ~0ull) throw Error{RAFEM_E_MESH, "element colouring needs more than 64 colours"};
+        int c = __builtin_ctzll(~taken);
+        colour[e] = c;
+        used = std::max(used, c + 1);
+        for (int a = 0; a < npe; ++a) mask[el[a]] |= (1ull << c);
+    }
+    return used;
+}
+
+void check_geometry(int64_t E, int npe, const int32_t* conn, const double* xyz) {
+    // Reference-cube corner signs of the 8 hex nodes (local order of the ABI).
+    static const double sx[8] = {-1, 1, 1, -1, -1, 1, 1, -1};
+    static const double sy[8] = {-1, -1, 1, 1, -1, -1, 1, 1};
+    static const double sz[8] = {-1, -1, -1, -1, 1, 1, 1, 1};
+    const double g = 1.0 / std::sqrt(3.0);
+    std::atomic<int64_t> bad{-1};
+    parallel_for(E, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo; e < hi; ++e) {
+            const int32_t* el = conn + e * npe;
+            bool ok = true;
+            if (npe == 4) {
+                double J[3][3];
+                for (int c = 0; c < 3; ++c)
+                    for (int i = 0; i < 3; ++i) J[i][c] = xyz[el[c + 1] * 3 + i] - xyz[el[0] * 3 + i];
+                double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                             J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                             J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                ok = det > 0;
+            } else {
+                for (int q = 0; q < 8 && ok; ++q) {
+                    double xi = sx[q] * g, et = sy[q] * g, ze = sz[q] * g;
+                    double J[3][3] = {{0}};
+                    for (int a = 0; a < 8; ++a) {
+                        double d0 = 0.125 * sx[a] * (1 + sy[a] * et) * (1 + sz[a] * ze);
+                        double d1 = 0.125 * sy[a] * (1 + sx[a] * xi) * (1 + sz[a] * ze);
+                        double d2 = 0.125 * sz[a] * (1 + sx[a] * xi) * (1 + sy[a] * et);
+                        for (int i = 0; i < 3; ++i) {
+                            double x = xyz[el[a] * 3 + i];
+                            J[i][0] += x * d0;
+                            J[i][1] += x * d1;
+                            J[i][2] += x * d2;
+                        }
+                    }
+                    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                 J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                    ok = det > 0;
+                }
+            }
+            if (!ok) {
+                bad.store(e);  // any offending element will do for the message
+                return;
+            }
+        }
+    });
+    if (bad.load() >= 0)
+        throw Error{RAFEM_E_MESH, "element " + std::to_string(bad.load()) +
+                                      " has a non-positive Jacobian determinant"};
+}
+
+}  // namespace rafem

@@ -1,0 +1,58 @@
+"""Drive one radiofrequency-ablation problem on the device through the C ABI.
+
+A ``DeviceProblem`` uploads a mesh, its material fields and Dirichlet data once,
+keeps the state (T, V) in device memory, and advances it with ``rafem_step``.
+The bioheat matrix does not depend on temperature, so it is assembled on the
+first step and reused afterwards.
+"""
+from __future__ import annotations
+
+from typing import List, Optional
+
+import numpy as np
+
+from . import _lib as rafem
+
+
+class DeviceProblem:
+    def __init__(self, problem, device=None):
+        import torch
+        self.torch = torch
+        self.p = problem
+        self.dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.mesh = rafem.Mesh(problem.xyz, problem.conn, problem.dir_ids)
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        self.k_e = torch.as_tensor(problem.k_e, **f64).contiguous()
+        self.perf_e = torch.as_tensor(problem.perf_e, **f64).contiguous()
+        self.sigma0_e = torch.as_tensor(problem.sigma0_e, **f64).contiguous()
+        self.dir_V = torch.as_tensor(problem.dir_V, **f64).contiguous()
+        self.dir_T = torch.as_tensor(problem.dir_T, **f64).contiguous()
+        self.phys = rafem.Phys(problem.rho_c, problem.dt, problem.T_a, problem.alpha_sigma,
+                               problem.T_ref, 1 if problem.coupled else 0, 0)
+        self.reset()
+
+    def reset(self, T0: Optional[np.ndarray] = None, V0: Optional[np.ndarray] = None):
+        torch = self.torch
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        self.T = torch.as_tensor(self.p.initial_T() if T0 is None else T0, **f64).clone()
+        self.V = torch.as_tensor(self.p.initial_V() if V0 is None else V0, **f64).clone()
+        self.phys.reuse_bioheat = 0
+
+    def step(self, tol: float = 1e-12, precision: str = "fp64", **kw):
+        info = rafem.step(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e, self.dir_V,
+                          self.dir_T, self.T, self.V, tol=tol, precision=precision, **kw)
+        self.phys.reuse_bioheat = 1
+        return info
+
+    def simulate(self, steps: int, tol: float = 1e-12, precision: str = "fp64", keep: bool = False,
+                 **kw):
+        states: List = []
+        infos = []
+        for _ in range(steps):
+            infos.append(self.step(tol, precision, **kw))
+            if keep:
+                states.append((self.T.cpu().numpy().copy(), self.V.cpu().numpy().copy()))
+        return states, infos
+
+    def close(self):
+        self.mesh.close()
