@@ -26,7 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TOL = 1e-12
+TOL = 1e-13
 
 
 def spmv_bytes(n: int, nnz: int, fp32: bool) -> int:
