@@ -73,26 +73,66 @@ void check_device(rafem_mesh m) {
     if (d != m->device) throw Error{RAFEM_E_ARG, "the current HIP device is not the mesh's device"};
 }
 
-void assemble_into(rafem_mesh m, const double* mass, const double* stiff, double* vals,
-                   hipStream_t s) {
-    launch_fill(vals, m->nnz, 0.0, s);
+Layout csr_layout(rafem_mesh m) {
+    Layout L;
+    L.sell = 0;
+    L.rp = m->rp;
+    L.cols = m->ci;
+    return L;
+}
+
+Layout sell_layout(rafem_mesh m) {
+    Layout L;
+    L.sell = 1;
+    L.sptr = m->sptr;
+    L.rlen = m->rlen;
+    L.cols = m->scol;
+    return L;
+}
+
+// The step path keeps its matrices in the SELL layout.
+Mat step_matrix(rafem_mesh m, const double* v, const float* v32) {
+    Mat A;
+    A.n = (int32_t)m->n;
+    A.sell = 1;
+    A.nslabs = m->nslabs;
+    A.sptr = m->sptr;
+    A.scol = m->scol;
+    A.sdel = m->sdel;
+    A.v = v;
+    A.v32 = v32;
+    return A;
+}
+
+Mat csr_matrix(rafem_mesh m, const int32_t* rp, const int32_t* ci, const double* v,
+               const float* v32) {
+    Mat A;
+    A.n = (int32_t)m->n;
+    A.sell = 0;
+    A.rp = rp;
+    A.ci = ci;
+    A.v = v;
+    A.v32 = v32;
+    return A;
+}
+
+void assemble_into(rafem_mesh m, const Layout& L, int64_t count, const double* mass,
+                   const double* stiff, double* vals, hipStream_t s) {
+    launch_fill(vals, count, 0.0, s);
     for (int c = 0; c < m->n_colours; ++c) {
         const int off = m->colour_off[c], cnt = m->colour_off[c + 1] - off;
-        launch_assemble_colour(m->npe, m->colour_elems + off, cnt, m->conn, m->xyz, m->rp, m->ci,
-                               mass, stiff, vals, s);
+        launch_assemble_colour(m->npe, m->colour_elems + off, cnt, m->conn, m->xyz, L, mass, stiff,
+                               vals, s);
     }
 }
 
-void solve_any(rafem_mesh m, const SolveOpts& o, const double* vals, const float* vals32,
-               const double* dinv, const float* dinv32, const double* b, double* x,
-               rafem_solve_info* info, hipStream_t s, int hint, int* iters) {
-    Csr64 A{m->rp, m->ci, vals, (int32_t)m->n};
-    if (o.precision == RAFEM_MIXED) {
-        Csr32 A32{m->rp, m->ci, vals32, (int32_t)m->n};
-        pcg_mixed(m, A, A32, dinv, dinv32, b, x, o, info, s, hint, iters);
-    } else {
+void solve_any(rafem_mesh m, const SolveOpts& o, const Mat& A, const double* dinv,
+               const float* dinv32, const double* b, double* x, rafem_solve_info* info,
+               hipStream_t s, int hint, int* iters) {
+    if (o.precision == RAFEM_MIXED)
+        pcg_mixed(m, A, dinv, dinv32, b, x, o, info, s, hint, iters);
+    else
         pcg64(m, A, dinv, b, x, o, info, s, hint, iters);
-    }
 }
 
 }  // namespace
@@ -157,6 +197,7 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             if (!std::isfinite(xyz_h[i])) throw Error{RAFEM_E_MESH, "non-finite node coordinate"};
         check_geometry(n_elems, npe, conn_h, xyz_h);
         HostStructure S = build_structure(n_nodes, n_elems, npe, conn_h);
+        HostSell SL = build_sell(S, n_nodes);
         std::vector<int32_t> colour(n_elems);
         const int ncol = colour_elements(n_nodes, n_elems, npe, conn_h, colour.data());
 
@@ -167,6 +208,8 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             m->E = n_elems;
             m->npe = npe;
             m->nnz = (int64_t)S.col_idx.size();
+            m->nslabs = (int32_t)SL.nslabs;
+            m->sell_nnz = (int64_t)SL.scol.size();
             m->nD = n_dir;
             m->n_colours = ncol;
             m->spmv = choose_spmv_config(m->n, m->nnz);
@@ -181,8 +224,13 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             for (int64_t k = 0; k < n_dir; ++k) isD[dir_ids_h[k]] = 1;
 
             const size_t N = (size_t)n_nodes, E = (size_t)n_elems, NNZ = (size_t)m->nnz;
+            const size_t SNNZ = (size_t)m->sell_nnz;
             m->rp = dalloc<int32_t>(m, N + 1);
             m->ci = dalloc<int32_t>(m, NNZ);
+            m->sptr = dalloc<int32_t>(m, (size_t)m->nslabs + 1);
+            m->scol = dalloc<int32_t>(m, SNNZ);
+            m->rlen = dalloc<int32_t>(m, N);
+            if (!SL.sdel.empty()) m->sdel = dalloc<int16_t>(m, SNNZ);
             m->conn = dalloc<int32_t>(m, E * npe);
             m->xyz = dalloc<double>(m, 3 * N);
             m->colour_elems = dalloc<int32_t>(m, E);
@@ -193,10 +241,10 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             m->gtmp = dalloc<double>(m, N);
             m->sigma = dalloc<double>(m, E);
             m->coefT = dalloc<double>(m, E);
-            m->valsV = dalloc<double>(m, NNZ);
-            m->valsT = dalloc<double>(m, NNZ);
-            m->valsV32 = dalloc<float>(m, NNZ);
-            m->valsT32 = dalloc<float>(m, NNZ);
+            m->valsV = dalloc<double>(m, SNNZ);
+            m->valsT = dalloc<double>(m, SNNZ);
+            m->valsV32 = dalloc<float>(m, SNNZ);
+            m->valsT32 = dalloc<float>(m, SNNZ);
             m->liftV = dalloc<double>(m, N);
             m->liftT = dalloc<double>(m, N);
             m->dinvV = dalloc<double>(m, N);
@@ -216,6 +264,8 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             m->d32 = dalloc<float>(m, N);
             m->dinv32 = dalloc<float>(m, N);
             m->partials = dalloc<double>(m, 3 * (N / 64 + 64));
+            m->part_pq = dalloc<double>(m, N / 64 + 64);
+            m->part_rz = dalloc<double>(m, 2 * (N / 64 + 64));
             m->st = dalloc<PcgState>(m, 3);
             if (hipHostMalloc((void**)&m->st_host, 3 * sizeof(PcgState), hipHostMallocDefault) !=
                 hipSuccess) {
@@ -226,6 +276,11 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             std::memset(m->st_host, 0, 3 * sizeof(PcgState));
             RAFEM_HIP(hipMemcpy(m->rp, S.row_ptr.data(), (N + 1) * 4, hipMemcpyHostToDevice));
             RAFEM_HIP(hipMemcpy(m->ci, S.col_idx.data(), NNZ * 4, hipMemcpyHostToDevice));
+            RAFEM_HIP(hipMemcpy(m->sptr, SL.sptr.data(), SL.sptr.size() * 4, hipMemcpyHostToDevice));
+            RAFEM_HIP(hipMemcpy(m->scol, SL.scol.data(), SNNZ * 4, hipMemcpyHostToDevice));
+            RAFEM_HIP(hipMemcpy(m->rlen, SL.rlen.data(), N * 4, hipMemcpyHostToDevice));
+            if (m->sdel)
+                RAFEM_HIP(hipMemcpy(m->sdel, SL.sdel.data(), SNNZ * 2, hipMemcpyHostToDevice));
             RAFEM_HIP(hipMemcpy(m->conn, conn_h, E * npe * 4, hipMemcpyHostToDevice));
             RAFEM_HIP(hipMemcpy(m->xyz, xyz_h, 3 * N * 8, hipMemcpyHostToDevice));
             RAFEM_HIP(hipMemcpy(m->colour_elems, order.data(), E * 4, hipMemcpyHostToDevice));
@@ -278,11 +333,12 @@ rafem_status rafem_assemble_csr(rafem_mesh m, const double* mass_coef_d, const d
             RAFEM_HIP(hipMemcpyAsync(row_ptr_d, m->rp, (m->n + 1) * 4, hipMemcpyDeviceToDevice, s));
         if (col_idx_d)
             RAFEM_HIP(hipMemcpyAsync(col_idx_d, m->ci, m->nnz * 4, hipMemcpyDeviceToDevice, s));
-        assemble_into(m, mass_coef_d, stiff_coef_d, vals_d, s);
+        const Layout L = csr_layout(m);
+        assemble_into(m, L, m->nnz, mass_coef_d, stiff_coef_d, vals_d, s);
         const int do_lift = dir_vals_d != nullptr;
         if (do_lift) launch_scatter_dirichlet(m->dir_ids, dir_vals_d, m->nD, m->gtmp, s);
         if (do_lift || vals32_d)
-            launch_lift((int)m->n, m->rp, m->ci, vals_d, vals32_d, m->isD, m->gtmp,
+            launch_lift((int)m->n, L, vals_d, vals32_d, m->isD, m->gtmp,
                         do_lift ? rhs_lift_d : nullptr, nullptr, nullptr, do_lift, s);
         RAFEM_HIP(hipGetLastError());
         return RAFEM_OK;
@@ -300,13 +356,11 @@ rafem_status rafem_solve(rafem_mesh m, const int32_t* row_ptr_d, const int32_t* 
         SolveOpts o = resolve_opts(opts, 1e-10);
         require(o.precision != RAFEM_MIXED || vals32_d != nullptr, "MIXED precision needs vals32");
         hipStream_t s = (hipStream_t)stream;
-        Csr64 A{row_ptr_d, col_idx_d, vals_d, (int32_t)m->n};
-        if (o.precision == RAFEM_MIXED) {
-            Csr32 A32{row_ptr_d, col_idx_d, vals32_d, (int32_t)m->n};
-            st = pcg_mixed(m, A, A32, nullptr, nullptr, b_d, x_d, o, info, s, 0, nullptr);
-        } else {
+        const Mat A = csr_matrix(m, row_ptr_d, col_idx_d, vals_d, vals32_d);
+        if (o.precision == RAFEM_MIXED)
+            st = pcg_mixed(m, A, nullptr, nullptr, b_d, x_d, o, info, s, 0, nullptr);
+        else
             st = pcg64(m, A, nullptr, b_d, x_d, o, info, s, 0, nullptr);
-        }
         if (st != RAFEM_OK)
             set_error(st == RAFEM_E_NOCONV ? "iteration limit reached" : "PCG breakdown (p.Ap <= 0 or non-finite)");
         return st;
@@ -329,14 +383,12 @@ rafem_status rafem_solve_adjoint(rafem_mesh m, const int32_t* row_ptr_d, const i
         launch_fill(m->gtmp, m->n, 0.0, s);
         launch_set_dirichlet(m->dir_ids, m->gtmp, m->nD, m->bT, s);
         launch_set_dirichlet(m->dir_ids, m->gtmp, m->nD, lambda_d, s);
-        Csr64 A{row_ptr_d, col_idx_d, vals_d, (int32_t)m->n};
+        const Mat A = csr_matrix(m, row_ptr_d, col_idx_d, vals_d, vals32_d);
         rafem_status st;
-        if (o.precision == RAFEM_MIXED) {
-            Csr32 A32{row_ptr_d, col_idx_d, vals32_d, (int32_t)m->n};
-            st = pcg_mixed(m, A, A32, nullptr, nullptr, m->bT, lambda_d, o, info, s, 0, nullptr);
-        } else {
+        if (o.precision == RAFEM_MIXED)
+            st = pcg_mixed(m, A, nullptr, nullptr, m->bT, lambda_d, o, info, s, 0, nullptr);
+        else
             st = pcg64(m, A, nullptr, m->bT, lambda_d, o, info, s, 0, nullptr);
-        }
         if (st != RAFEM_OK)
             set_error(st == RAFEM_E_NOCONV ? "iteration limit reached" : "PCG breakdown (p.Ap <= 0 or non-finite)");
         return st;
@@ -352,10 +404,11 @@ rafem_status rafem_spmv(rafem_mesh m, const int32_t* row_ptr_d, const int32_t* c
         hipStream_t s = (hipStream_t)stream;
         if (vals_d) {
             require(x_d && y_d, "NULL x or y");
-            launch_spmv64(Csr64{row_ptr_d, col_idx_d, vals_d, (int32_t)m->n}, m->spmv, x_d, y_d, s);
+            launch_spmv64(csr_matrix(m, row_ptr_d, col_idx_d, vals_d, nullptr), m->spmv, x_d, y_d, s);
         } else {
             require(vals32_d && x32_d && y32_d, "NULL FP32 arguments");
-            launch_spmv32(Csr32{row_ptr_d, col_idx_d, vals32_d, (int32_t)m->n}, m->spmv, x32_d, y32_d, s);
+            launch_spmv32(csr_matrix(m, row_ptr_d, col_idx_d, nullptr, vals32_d), m->spmv, x32_d, y32_d,
+                          s);
         }
         RAFEM_HIP(hipGetLastError());
         return RAFEM_OK;
@@ -424,26 +477,27 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
         rafem_step_info& inf = info ? *info : local;
         std::memset(&inf, 0, sizeof(inf));
 
+        const Layout SL = sell_layout(m);
         launch_scatter_dirichlet(m->dir_ids, dir_T_d, m->nD, m->gT, s);
         if (!phys->reuse_bioheat) {
             launch_coef(perf_e_d, phys->rho_c / phys->dt, m->coefT, m->E, s);
-            assemble_into(m, m->coefT, k_e_d, m->valsT, s);
-            launch_lift((int)m->n, m->rp, m->ci, m->valsT, m->valsT32, m->isD, m->gT, m->liftT,
-                        m->dinvT, m->dinvT32, m->nD > 0, s);
+            assemble_into(m, SL, m->sell_nnz, m->coefT, k_e_d, m->valsT, s);
+            launch_lift((int)m->n, SL, m->valsT, m->valsT32, m->isD, m->gT, m->liftT, m->dinvT,
+                        m->dinvT32, m->nD > 0, s);
             m->bioheat_ready = true;
         }
         if (phys->coupled) {
             launch_scatter_dirichlet(m->dir_ids, dir_V_d, m->nD, m->gV, s);
             launch_sigma(m->npe, m->E, m->conn, T_d, sigma0_e_d, phys->alpha_sigma, phys->T_ref,
                          m->sigma, s);
-            assemble_into(m, nullptr, m->sigma, m->valsV, s);
-            launch_lift((int)m->n, m->rp, m->ci, m->valsV, m->valsV32, m->isD, m->gV, m->liftV,
-                        m->dinvV, m->dinvV32, m->nD > 0, s);
+            assemble_into(m, SL, m->sell_nnz, nullptr, m->sigma, m->valsV, s);
+            launch_lift((int)m->n, SL, m->valsV, m->valsV32, m->isD, m->gV, m->liftV, m->dinvV,
+                        m->dinvV32, m->nD > 0, s);
             launch_set_dirichlet(m->dir_ids, m->gV, m->nD, V_d, s);
             RAFEM_HIP(hipGetLastError());
             int it = 0;
-            solve_any(m, o, m->valsV, m->valsV32, m->dinvV, m->dinvV32, m->liftV, V_d, &inf.V, s,
-                      mixed ? 0 : m->hint_V, &it);
+            solve_any(m, o, step_matrix(m, m->valsV, m->valsV32), m->dinvV, m->dinvV32, m->liftV,
+                      V_d, &inf.V, s, mixed ? 0 : m->hint_V, &it);
             if (!mixed) m->hint_V = it;
             if (inf.V.status != RAFEM_OK) {
                 set_error("potential solve failed");
@@ -462,8 +516,8 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
         launch_set_dirichlet(m->dir_ids, m->gT, m->nD, T_d, s);
         RAFEM_HIP(hipGetLastError());
         int it = 0;
-        solve_any(m, o, m->valsT, m->valsT32, m->dinvT, m->dinvT32, m->bT, T_d, &inf.T, s,
-                  mixed ? 0 : m->hint_T, &it);
+        solve_any(m, o, step_matrix(m, m->valsT, m->valsT32), m->dinvT, m->dinvT32, m->bT, T_d,
+                  &inf.T, s, mixed ? 0 : m->hint_T, &it);
         if (!mixed) m->hint_T = it;
         if (inf.T.status != RAFEM_OK) {
             set_error("bioheat solve failed");

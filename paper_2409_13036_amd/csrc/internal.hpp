@@ -37,6 +37,16 @@ struct HostStructure {
     std::vector<int32_t> col_idx;
 };
 
+// SELL layout with slabs of 64 rows (one wavefront, one row per lane).
+struct HostSell {
+    int64_t nslabs = 0;
+    std::vector<int32_t> sptr;  // [nslabs + 1] element offset of each slab
+    std::vector<int32_t> scol;  // [sptr[nslabs]] column ids, slab-major, entry-major within slab
+    std::vector<int32_t> rlen;  // [n] entries of each row (without padding)
+    std::vector<int16_t> sdel;  // column - row offsets, empty if some offset exceeds int16
+};
+HostSell build_sell(const HostStructure& S, int64_t n);
+
 // Throws Error on bad input.
 void check_conn(int64_t n_nodes, int64_t n_elems, int npe, const int32_t* conn);
 HostStructure build_structure(int64_t n_nodes, int64_t n_elems, int npe, const int32_t* conn);
@@ -51,9 +61,8 @@ void check_geometry(int64_t n_elems, int npe, const int32_t* conn, const double*
 // Written only by the "last block" of a kernel or by k_state_init.
 // ---------------------------------------------------------------------------
 struct PcgState {
-    double rz;       // (r, D^-1 r) of the current residual
-    double pq;       // (p, A p)
-    double alpha;
+    double rzs[2];   // (r, D^-1 r) of the current residual, slot = iteration parity
+    double pq;       // (p, A p) of the last iteration (diagnostics)
     double beta;
     double rr;       // ||r||^2 of the current residual
     double bb;       // ||b||^2
@@ -66,63 +75,86 @@ struct PcgState {
     int32_t done;
     int32_t status;
     int32_t bad_diag;
-    uint32_t ticket;  // arrival counter of the last-block reductions; 0 between kernels
+    uint32_t ticket;  // arrival counter of the once-per-solve reductions; 0 between kernels
 };
 static_assert(sizeof(PcgState) % 8 == 0, "PcgState layout");
 
 // Launch geometry of the row kernels.
 struct SpmvConfig {
-    int lanes;           // lanes per row: 2, 4 or 8
-    int rows_per_block;  // multiple of 256 / lanes
+    int lanes;            // CSR kernels: lanes per row (2, 4, 8 or 16)
+    int rows_per_block;   // CSR kernels: multiple of 256 / lanes
+    int slabs_per_block;  // SELL kernels: 64-row slabs per 256-thread workgroup (multiple of 4)
 };
 
 SpmvConfig choose_spmv_config(int64_t n, int64_t nnz);
 int blocks_for(int64_t n, int rows_per_block);
 constexpr int kVecRowsPerBlock = 1024;  // vector kernels: 256 threads x 4 rows
 
+// A sparse matrix as the solver kernels see it: CSR, or SELL with 64-row slabs.
+struct Mat {
+    int32_t n = 0;
+    int sell = 0;
+    const int32_t* rp = nullptr;    // CSR row pointers [n + 1]
+    const int32_t* ci = nullptr;    // CSR column ids [nnz]
+    int32_t nslabs = 0;
+    const int32_t* sptr = nullptr;  // SELL slab offsets [nslabs + 1]
+    const int32_t* scol = nullptr;  // SELL column ids [sptr[nslabs]]
+    const int16_t* sdel = nullptr;  // SELL column - row offsets, or NULL if they do not fit
+    const double* v = nullptr;      // values in the layout's order
+    const float* v32 = nullptr;     // FP32 values in the layout's order (mixed precision)
+};
+
+// Where the entries of a row live, for the element-wise kernels (assembly, lifting).
+struct Layout {
+    int sell = 0;
+    const int32_t* rp = nullptr;    // CSR
+    const int32_t* sptr = nullptr;  // SELL
+    const int32_t* rlen = nullptr;  // SELL
+    const int32_t* cols = nullptr;  // column ids in the layout's order
+};
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).  All asynchronous on `s`.
 // ---------------------------------------------------------------------------
-struct Csr64 {
-    const int32_t* rp;
-    const int32_t* ci;
-    const double* v;
-    int32_t n;
-};
-struct Csr32 {
-    const int32_t* rp;
-    const int32_t* ci;
-    const float* v;
-    int32_t n;
-};
-
 void launch_state_init(PcgState* st, double tol, int maxit, hipStream_t s);
-void launch_diag_inv(const Csr64& A, double* dinv, float* dinv32, PcgState* st, hipStream_t s);
+// dinv = 1 / diag(A) (CSR matrices); a missing or non-positive diagonal marks st->bad_diag.
+void launch_diag_inv(const Mat& A, double* dinv, float* dinv32, PcgState* st, hipStream_t s);
 // r = b - A x; p = D^-1 r; reduction of rz, rr, bb into st (FP64 PCG start).
-void launch_pcg_start(const Csr64& A, const SpmvConfig& c, const double* b, const double* x,
+void launch_pcg_start(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
                       const double* dinv, double* r, double* p, double* partials,
                       PcgState* st, hipStream_t s);
-// q = A p; reduction of p.q into st, alpha = rz / pq.  Early exit when st->done.
-void launch_spmv_dot64(const Csr64& A, const SpmvConfig& c, const double* p, double* q,
-                       double* partials, PcgState* st, hipStream_t s);
-void launch_spmv_dot32(const Csr32& A, const SpmvConfig& c, const float* p, float* q,
-                       double* partials, PcgState* st, hipStream_t s);
-// x += alpha p; r -= alpha q; rz, rr reductions; convergence test; beta.
-void launch_update64(int n, double* x, double* r, const double* p, const double* q,
-                     const double* dinv, double* partials, PcgState* st, hipStream_t s);
-void launch_update32(int n, float* x, float* r, const float* p, const float* q,
-                     const float* dinv, double* partials, PcgState* st, hipStream_t s);
-// p = D^-1 r + beta p
-void launch_pupdate64(int n, double* p, const double* r, const double* dinv, PcgState* st,
-                      hipStream_t s);
-void launch_pupdate32(int n, float* p, const float* r, const float* dinv, PcgState* st,
-                      hipStream_t s);
+// One PCG iteration is three kernels.  None of them finalises a reduction itself: each
+// writes per-block partial sums, and every block of the next kernel adds the previous
+// kernel's partials in the same fixed order (kernel boundaries make them visible), so
+// no fences or atomics are needed and all blocks see bit-identical scalars.  `it` is the
+// iteration index (the host counts launches); scalars carried between iterations live
+// in slots chosen by its parity, so no kernel reads a slot it also writes.
+//   spmv_dot:  q = A p; partial p.q per block into pq_part.  Returns the grid size.
+//   update:    pq = sum(pq_part); alpha = rz[it&1] / pq (breakdown if pq <= 0);
+//              x += alpha p; r -= alpha q; partials of r.D^-1r and r.r into rz_part.
+//   pupdate:   rz', rr = sum(rz_part); stop on convergence / limit / breakdown, else
+//              beta = rz' / rz[it&1]; p = D^-1 r + beta p; rz[(it+1)&1] = rz'.
+// All three exit at once when st->done is set.
+int launch_spmv_dot64(const Mat& A, const SpmvConfig& c, const double* p, double* q,
+                      double* pq_part, PcgState* st, hipStream_t s);
+int launch_spmv_dot32(const Mat& A, const SpmvConfig& c, const float* p, float* q,
+                      double* pq_part, PcgState* st, hipStream_t s);
+int launch_update64(int n, double* x, double* r, const double* p, const double* q,
+                    const double* dinv, const double* pq_part, int nb_pq, double* rz_part,
+                    int it, PcgState* st, hipStream_t s);
+int launch_update32(int n, float* x, float* r, const float* p, const float* q,
+                    const float* dinv, const double* pq_part, int nb_pq, double* rz_part,
+                    int it, PcgState* st, hipStream_t s);
+void launch_pupdate64(int n, double* p, const double* r, const double* dinv,
+                      const double* rz_part, int nb_rz, int it, PcgState* st, hipStream_t s);
+void launch_pupdate32(int n, float* p, const float* r, const float* dinv, const double* rz_part,
+                      int nb_rz, int it, PcgState* st, hipStream_t s);
 // Plain y = A x (no state).
-void launch_spmv64(const Csr64& A, const SpmvConfig& c, const double* x, double* y, hipStream_t s);
-void launch_spmv32(const Csr32& A, const SpmvConfig& c, const float* x, float* y, hipStream_t s);
+void launch_spmv64(const Mat& A, const SpmvConfig& c, const double* x, double* y, hipStream_t s);
+void launch_spmv32(const Mat& A, const SpmvConfig& c, const float* x, float* y, hipStream_t s);
 // Residual r = b - A x with ||r||^2 and ||b||^2 into st->rr, st->bb (no early exit).
 // Mixed outer test: done when rr <= tol2 (tol2 = tol^2 bb set here), scale = 1/||r||.
-void launch_residual64(const Csr64& A, const SpmvConfig& c, const double* b, const double* x,
+void launch_residual64(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
                        double* r, double* partials, PcgState* st, int outer_mode, hipStream_t s);
 // Mixed inner start: r32 = scale * r64; d32 = 0; p32 = D^-1 r32; rz, rr into inner state.
 void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,
@@ -139,13 +171,12 @@ void launch_scatter_dirichlet(const int32_t* dir_ids, const double* dir_vals, in
 void launch_set_dirichlet(const int32_t* dir_ids, const double* gnode, int64_t nD, double* x,
                           hipStream_t s);
 void launch_assemble_colour(int npe, const int32_t* elems, int count, const int32_t* conn,
-                            const double* xyz, const int32_t* rp, const int32_t* ci,
-                            const double* mass, const double* stiff, double* vals,
-                            hipStream_t s);
+                            const double* xyz, const Layout& L, const double* mass,
+                            const double* stiff, double* vals, hipStream_t s);
 // Lifting with per-node Dirichlet mask/values; writes lifted vals, vals32, lift, dinv, dinv32.
-void launch_lift(int n, const int32_t* rp, const int32_t* ci, double* vals, float* vals32,
-                 const uint8_t* isD, const double* gnode, double* lift, double* dinv,
-                 float* dinv32, int do_lift, hipStream_t s);
+void launch_lift(int n, const Layout& L, double* vals, float* vals32, const uint8_t* isD,
+                 const double* gnode, double* lift, double* dinv, float* dinv32, int do_lift,
+                 hipStream_t s);
 void launch_cast32(const double* v, float* v32, int64_t n, hipStream_t s);
 // coef[e] = c0 + perf[e]
 void launch_coef(const double* perf, double c0, double* coef, int64_t E, hipStream_t s);
@@ -174,6 +205,12 @@ struct rafem_mesh_s {
     // structure and geometry
     int32_t* rp = nullptr;
     int32_t* ci = nullptr;
+    int64_t sell_nnz = 0;     // padded SELL storage (values per matrix of the step path)
+    int32_t nslabs = 0;
+    int32_t* sptr = nullptr;  // SELL slab offsets
+    int32_t* scol = nullptr;  // SELL column ids
+    int32_t* rlen = nullptr;  // SELL row lengths
+    int16_t* sdel = nullptr;  // SELL column - row offsets (NULL when the bandwidth exceeds int16)
     int32_t* conn = nullptr;
     double* xyz = nullptr;
     int32_t* colour_elems = nullptr;
@@ -192,7 +229,9 @@ struct rafem_mesh_s {
     // solver workspace
     double *r = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr, *r64 = nullptr;
     float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr, *dinv32 = nullptr;
-    double* partials = nullptr;
+    double* partials = nullptr;   // once-per-solve reductions
+    double* part_pq = nullptr;    // per-iteration partials of p.Ap
+    double* part_rz = nullptr;    // per-iteration partials of r.z and r.r
     rafem::PcgState* st = nullptr;      // device [3]: main/inner, outer, check
     rafem::PcgState* st_host = nullptr; // pinned host [3]
 

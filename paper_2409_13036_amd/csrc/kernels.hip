@@ -74,13 +74,17 @@ __device__ bool reduce_grid(double (&v)[K], double* partials, int slot, int nb, 
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) partials[k * nb + slot] = v[k];
-        __threadfence();
-        const unsigned t = atomicAdd(&st->ticket, 1u);
+        // Release only: publish the partials before the ticket.  A full fence here would
+        // also invalidate this XCD's L2 in every block, discarding the cached x-vector.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned t = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
         is_last = (t == (unsigned)(nb - 1));
     }
     __syncthreads();
     if (!is_last) return false;
-    __threadfence();
+    // Acquire, once per kernel: the other blocks' partials are visible from here on.
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         double s = 0.0;
@@ -94,12 +98,45 @@ __device__ bool reduce_grid(double (&v)[K], double* partials, int slot, int nb, 
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
 
+// Store this block's K sums as partials (no synchronisation with other blocks).
+template <int K>
+__device__ __forceinline__ void store_partials(double (&v)[K], double* partials, int slot,
+                                               int nb) {
+    block_sum<K>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) partials[k * nb + slot] = v[k];
+    }
+}
+
+// Totals of the K partial arrays written by the previous kernel, in a fixed order that
+// does not depend on the calling block; the result is returned to every thread.
+template <int K>
+__device__ __forceinline__ void grid_totals(const double* __restrict__ partials, int nb,
+                                            double (&tot)[K]) {
+    __shared__ double bcast[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nb; i += WG) s += partials[k * nb + i];
+        tot[k] = s;
+    }
+    block_sum<K>(tot);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) bcast[k] = tot[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) tot[k] = bcast[k];
+}
+
 // ---------------------------------------------------------------------------
 // Solver state
 // ---------------------------------------------------------------------------
 __global__ void k_state_init(PcgState* st, double tol, int maxit) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->rz = st->pq = st->alpha = st->beta = st->rr = st->bb = 0.0;
+        st->rzs[0] = st->rzs[1] = st->pq = st->beta = st->rr = st->bb = 0.0;
         st->tol = tol;
         st->tol2 = 0.0;
         st->scale = 1.0;
@@ -157,6 +194,50 @@ struct RowArgs {
     int outer_mode;
 };
 
+// Thread 0 of the last block: turn the grid totals of a row kernel into solver scalars.
+template <int MODE>
+__device__ void finish_rows(PcgState* st, const double (&tot)[3], int outer_mode) {
+    if constexpr (MODE == ROW_START) {
+        st->rzs[0] = tot[0];
+        st->rzs[1] = 0.0;
+        st->rr = tot[1];
+        st->bb = tot[2];
+        st->rr_first = tot[1];
+        st->tol2 = st->tol * st->tol * tot[2];
+        st->iters = 0;
+        if (st->bad_diag || !finite(tot[0]) || !finite(tot[1]) || !finite(tot[2])) {
+            st->status = RAFEM_E_BREAKDOWN;
+            st->done = 1;
+        } else if (tot[1] <= st->tol2) {
+            st->status = RAFEM_OK;
+            st->done = 1;
+        } else {
+            st->status = RAFEM_E_NOCONV;
+            st->done = 0;
+        }
+    } else {  // ROW_RESID
+        st->rr = tot[1];
+        st->bb = tot[2];
+        if (outer_mode) {
+            st->tol2 = st->tol * st->tol * tot[2];
+            if (st->iters == 0) st->rr_first = tot[1];
+            if (st->bad_diag || !finite(tot[1]) || !finite(tot[2])) {
+                st->status = RAFEM_E_BREAKDOWN;
+                st->done = 1;
+            } else if (tot[1] <= st->tol2) {
+                st->status = RAFEM_OK;
+                st->done = 1;
+            } else if (st->iters >= st->maxit) {
+                st->status = RAFEM_E_NOCONV;
+                st->done = 1;
+            } else {
+                st->scale = 1.0 / sqrt(tot[1]);
+                st->iters += 1;
+            }
+        }
+    }
+}
+
 template <typename T, int LANES, int MODE>
 __global__ __launch_bounds__(WG) void k_rows(RowArgs<T> a) {
     if constexpr (MODE == ROW_DOT) {
@@ -195,57 +276,121 @@ __global__ __launch_bounds__(WG) void k_rows(RowArgs<T> a) {
             }
         }
     }
-    if constexpr (MODE == ROW_PLAIN) return;
-    double tot[3];
-    if (!reduce_grid<3>(acc, a.partials, blk, nb, a.st, tot)) return;
-    if (threadIdx.x != 0) return;
-    PcgState* st = a.st;
+    if constexpr (MODE == ROW_PLAIN) {
+        return;
+    } else if constexpr (MODE == ROW_DOT) {
+        double v1[1] = {acc[0]};
+        store_partials<1>(v1, a.partials, blk, nb);
+    } else {
+        double tot[3];
+        if (!reduce_grid<3>(acc, a.partials, blk, nb, a.st, tot)) return;
+        if (threadIdx.x != 0) return;
+        finish_rows<MODE>(a.st, tot, a.outer_mode);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SELL kernels: 64-row slabs, one row per lane.  Entry j of the 64 rows of a slab is
+// one contiguous 64-word load for values and for column ids; for the banded meshes
+// here the x-gathers of a slab are contiguous too.  Rows are summed in entry order.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SellArgs {
+    const int* __restrict__ sptr;
+    const int* __restrict__ scol;     // absolute column ids (used when sdel is NULL)
+    const int16_t* __restrict__ sdel; // column - row offsets
+    const T* __restrict__ val;
+    const T* __restrict__ x;
+    T* __restrict__ y;
+    const double* __restrict__ b;
+    const double* __restrict__ dinv;
+    double* __restrict__ pout;
+    double* partials;
+    PcgState* st;
+    int n;
+    int nslabs;
+    int slabs_per_block;
+    int outer_mode;
+};
+
+constexpr int kSellUnroll = 9;
+
+// Sum over the entries of one row in entry order.  COL is int (absolute columns, xr = x)
+// or int16_t (offsets to the row, xr = x + row).
+template <typename T, typename COL>
+__device__ __forceinline__ T sell_row(const COL* __restrict__ cp, const T* __restrict__ vp,
+                                      const T* __restrict__ xr, int width) {
+    T sum = T(0);
+    int j = 0;
+    for (; j + kSellUnroll <= width; j += kSellUnroll) {
+        int c[kSellUnroll];
+        T v[kSellUnroll];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) {
+            c[u] = cp[(j + u) * WAVE];
+            v[u] = vp[(j + u) * WAVE];
+        }
+        T g[kSellUnroll];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) g[u] = xr[c[u]];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) sum += v[u] * g[u];
+    }
+    for (; j < width; ++j) sum += vp[j * WAVE] * xr[cp[j * WAVE]];
+    return sum;
+}
+
+template <typename T, int MODE, bool DELTA>
+__global__ __launch_bounds__(WG) void k_sell(SellArgs<T> a) {
     if constexpr (MODE == ROW_DOT) {
-        const double pq = tot[0];
-        st->pq = pq;
-        if (!(pq > 0.0) || !finite(pq)) {
-            st->status = RAFEM_E_BREAKDOWN;
-            st->done = 1;
-        } else {
-            st->alpha = st->rz / pq;
-        }
-    } else if constexpr (MODE == ROW_START) {
-        st->rz = tot[0];
-        st->rr = tot[1];
-        st->bb = tot[2];
-        st->rr_first = tot[1];
-        st->tol2 = st->tol * st->tol * tot[2];
-        st->iters = 0;
-        if (st->bad_diag || !finite(tot[0]) || !finite(tot[1]) || !finite(tot[2])) {
-            st->status = RAFEM_E_BREAKDOWN;
-            st->done = 1;
-        } else if (tot[1] <= st->tol2) {
-            st->status = RAFEM_OK;
-            st->done = 1;
-        } else {
-            st->status = RAFEM_E_NOCONV;
-            st->done = 0;
-        }
-    } else {  // ROW_RESID
-        st->rr = tot[1];
-        st->bb = tot[2];
-        if (a.outer_mode) {
-            st->tol2 = st->tol * st->tol * tot[2];
-            if (st->iters == 0) st->rr_first = tot[1];
-            if (st->bad_diag || !finite(tot[1]) || !finite(tot[2])) {
-                st->status = RAFEM_E_BREAKDOWN;
-                st->done = 1;
-            } else if (tot[1] <= st->tol2) {
-                st->status = RAFEM_OK;
-                st->done = 1;
-            } else if (st->iters >= st->maxit) {
-                st->status = RAFEM_E_NOCONV;
-                st->done = 1;
+        if (a.st->done) return;
+    }
+    const int nb = gridDim.x;
+    const int blk = xcd_block(blockIdx.x, nb);
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    const int s0 = blk * a.slabs_per_block;
+    const int s1 = min(s0 + a.slabs_per_block, a.nslabs);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int sl = s0 + w; sl < s1; sl += NWAVES) {
+        const int base = a.sptr[sl];
+        const int width = (a.sptr[sl + 1] - base) / WAVE;
+        const int r = sl * WAVE + lane;
+        T sum;
+        if constexpr (DELTA)
+            sum = sell_row<T, int16_t>(a.sdel + base + lane, a.val + base + lane,
+                                       a.x + min(r, a.n - 1), width);
+        else
+            sum = sell_row<T, int>(a.scol + base + lane, a.val + base + lane, a.x, width);
+        if (r < a.n) {
+            if constexpr (MODE == ROW_PLAIN) {
+                a.y[r] = sum;
+            } else if constexpr (MODE == ROW_DOT) {
+                a.y[r] = sum;
+                acc[0] += (double)a.x[r] * (double)sum;
             } else {
-                st->scale = 1.0 / sqrt(tot[1]);
-                st->iters += 1;
+                const double bi = a.b[r];
+                const double ri = bi - (double)sum;
+                a.y[r] = (T)ri;
+                acc[1] += ri * ri;
+                acc[2] += bi * bi;
+                if constexpr (MODE == ROW_START) {
+                    const double zi = a.dinv[r] * ri;
+                    a.pout[r] = zi;
+                    acc[0] += ri * zi;
+                }
             }
         }
+    }
+    if constexpr (MODE == ROW_PLAIN) {
+        return;
+    } else if constexpr (MODE == ROW_DOT) {
+        double v1[1] = {acc[0]};
+        store_partials<1>(v1, a.partials, blk, nb);
+    } else {
+        double tot[3];
+        if (!reduce_grid<3>(acc, a.partials, blk, nb, a.st, tot)) return;
+        if (threadIdx.x != 0) return;
+        finish_rows<MODE>(a.st, tot, a.outer_mode);
     }
 }
 
@@ -254,65 +399,112 @@ __global__ __launch_bounds__(WG) void k_rows(RowArgs<T> a) {
 // ---------------------------------------------------------------------------
 constexpr int VPT = kVecRowsPerBlock / WG;
 
-// x += alpha p; r -= alpha q; z = D^-1 r; sums r.z, r.r; convergence and beta.
+// x += alpha p; r -= alpha q with alpha = rz / sum(p.Ap partials); partials of r.z, r.r.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_update(int n, T* __restrict__ x, T* __restrict__ r,
                                                const T* __restrict__ p,
                                                const T* __restrict__ q,
-                                               const T* __restrict__ dinv, double* partials,
+                                               const T* __restrict__ dinv,
+                                               const double* __restrict__ pq_part, int nb_pq,
+                                               double* __restrict__ rz_part, int it,
                                                PcgState* st) {
     if (st->done) return;
-    const T alpha = (T)st->alpha;
     const int nb = gridDim.x;
     const int blk = xcd_block(blockIdx.x, nb);
     const int i0 = blk * kVecRowsPerBlock + threadIdx.x;
+    // issue this thread's loads before the partial sums so their latency overlaps
+    T xv[VPT], rv[VPT], pv[VPT], qv[VPT], dv[VPT];
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+        const int i = i0 + j * WG;
+        if (i < n) {
+            xv[j] = x[i];
+            rv[j] = r[i];
+            pv[j] = p[i];
+            qv[j] = q[i];
+            dv[j] = dinv[i];
+        }
+    }
+    double pq[1];
+    grid_totals<1>(pq_part, nb_pq, pq);
+    if (!(pq[0] > 0.0) || !finite(pq[0])) {
+        if (blk == 0 && threadIdx.x == 0) {
+            st->pq = pq[0];
+            st->iters = it;
+            st->status = RAFEM_E_BREAKDOWN;
+            st->done = 1;
+        }
+        return;
+    }
+    const T alpha = (T)(st->rzs[it & 1] / pq[0]);
     double acc[2] = {0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
         const int i = i0 + j * WG;
         if (i < n) {
-            const T xi = x[i] + alpha * p[i];
-            const T ri = r[i] - alpha * q[i];
+            const T xi = xv[j] + alpha * pv[j];
+            const T ri = rv[j] - alpha * qv[j];
             x[i] = xi;
             r[i] = ri;
-            const T zi = dinv[i] * ri;
+            const T zi = dv[j] * ri;
             acc[0] += (double)ri * (double)zi;
             acc[1] += (double)ri * (double)ri;
         }
     }
-    double tot[2];
-    if (!reduce_grid<2>(acc, partials, blk, nb, st, tot)) return;
-    if (threadIdx.x != 0) return;
-    st->iters += 1;
-    st->rr = tot[1];
-    if (!finite(tot[0]) || !finite(tot[1]) || tot[0] < 0.0) {
-        st->status = RAFEM_E_BREAKDOWN;
-        st->done = 1;
-    } else if (tot[1] <= st->tol2) {
-        st->status = RAFEM_OK;
-        st->done = 1;
-    } else if (st->iters >= st->maxit) {
-        st->status = RAFEM_E_NOCONV;
-        st->done = 1;
-    } else {
-        st->beta = tot[0] / st->rz;
-        st->rz = tot[0];
-    }
+    store_partials<2>(acc, rz_part, blk, nb);
+    if (blk == 0 && threadIdx.x == 0) st->pq = pq[0];
 }
 
-// p = D^-1 r + beta p
+// Convergence test on the totals of r.z and r.r, then p = D^-1 r + beta p.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
                                                 const T* __restrict__ r,
-                                                const T* __restrict__ dinv, PcgState* st) {
+                                                const T* __restrict__ dinv,
+                                                const double* __restrict__ rz_part, int nb_rz,
+                                                int it, PcgState* st) {
     if (st->done) return;
-    const T beta = (T)st->beta;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int i0 = blk * kVecRowsPerBlock + threadIdx.x;
+    T rv[VPT], pv[VPT], dv[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
         const int i = i0 + j * WG;
-        if (i < n) p[i] = dinv[i] * r[i] + beta * p[i];
+        if (i < n) {
+            rv[j] = r[i];
+            pv[j] = p[i];
+            dv[j] = dinv[i];
+        }
+    }
+    double tot[2];
+    grid_totals<2>(rz_part, nb_rz, tot);
+    const double rz = tot[0], rr = tot[1];
+    const int iters = it + 1;
+    int status = -1;
+    if (!finite(rz) || !finite(rr) || rz < 0.0) status = RAFEM_E_BREAKDOWN;
+    else if (rr <= st->tol2) status = RAFEM_OK;
+    else if (iters >= st->maxit) status = RAFEM_E_NOCONV;
+    const bool writer = blk == 0 && threadIdx.x == 0;
+    if (status >= 0) {
+        if (writer) {
+            st->rr = rr;
+            st->iters = iters;
+            st->status = status;
+            st->done = 1;
+        }
+        return;
+    }
+    const double beta = rz / st->rzs[it & 1];
+    const T bt = (T)beta;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+        const int i = i0 + j * WG;
+        if (i < n) p[i] = dv[j] * rv[j] + bt * pv[j];
+    }
+    if (writer) {
+        st->rzs[(it + 1) & 1] = rz;
+        st->rr = rr;
+        st->beta = beta;
+        st->iters = iters;
     }
 }
 
@@ -349,7 +541,8 @@ __global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restr
     double tot[2];
     if (!reduce_grid<2>(acc, partials, blk, nb, inner, tot)) return;
     if (threadIdx.x != 0) return;
-    inner->rz = tot[0];
+    inner->rzs[0] = tot[0];
+    inner->rzs[1] = 0.0;
     inner->rr = tot[1];
     inner->bb = tot[1];
     inner->rr_first = tot[1];
@@ -415,14 +608,30 @@ __global__ void k_set_dirichlet(const int* __restrict__ ids, const double* __res
     if (k < nD) x[ids[k]] = gnode[ids[k]];
 }
 
-// Position of column `col` in the sorted column list [s, e) of a row.
-__device__ __forceinline__ int find_slot(const int* __restrict__ ci, int s, int e, int col) {
-    while (s < e) {
-        const int m = (s + e) >> 1;
-        if (ci[m] < col) s = m + 1;
-        else e = m;
+// Entries of row r: positions start + j * stride, j < len (CSR: stride 1; SELL: 64).
+__device__ __forceinline__ void row_span(const Layout& L, int r, int& start, int& len,
+                                         int& stride) {
+    if (L.sell) {
+        start = L.sptr[r / WAVE] + (r % WAVE);
+        len = L.rlen[r];
+        stride = WAVE;
+    } else {
+        start = L.rp[r];
+        len = L.rp[r + 1] - start;
+        stride = 1;
     }
-    return s;
+}
+
+// Position of column `col` in a row's ascending column list.
+__device__ __forceinline__ int find_slot(const int* __restrict__ cols, int start, int len,
+                                         int stride, int col) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if (cols[start + m * stride] < col) lo = m + 1;
+        else hi = m;
+    }
+    return start + lo * stride;
 }
 
 // Reference-cube corner signs of hex local node a in the ABI order
@@ -546,8 +755,7 @@ template <int NPE>
 __global__ __launch_bounds__(WG) void k_assemble(const int* __restrict__ elems, int count,
                                                  const int* __restrict__ conn,
                                                  const double* __restrict__ xyz,
-                                                 const int* __restrict__ rp,
-                                                 const int* __restrict__ ci,
+                                                 const Layout L,
                                                  const double* __restrict__ mass,
                                                  const double* __restrict__ stiff,
                                                  double* __restrict__ vals) {
@@ -577,19 +785,17 @@ __global__ __launch_bounds__(WG) void k_assemble(const int* __restrict__ elems, 
             Mr[b] = (a == b ? 2.0 : 1.0) * V / 20.0;
         }
     }
-    const int row = nodes[a];
-    const int s = rp[row], en = rp[row + 1];
+    int start, len, stride;
+    row_span(L, nodes[a], start, len, stride);
 #pragma unroll
     for (int b = 0; b < NPE; ++b) {
-        const int k = find_slot(ci, s, en, nodes[b]);
+        const int k = find_slot(L.cols, start, len, stride, nodes[b]);
         vals[k] += m * Mr[b] + c * Kr[b];
     }
 }
 
 // Symmetric lifting of Dirichlet rows/columns, Jacobi inverse and FP32 copy.
-__global__ __launch_bounds__(WG) void k_lift(int n, const int* __restrict__ rp,
-                                             const int* __restrict__ ci,
-                                             double* __restrict__ vals,
+__global__ __launch_bounds__(WG) void k_lift(int n, const Layout L, double* __restrict__ vals,
                                              float* __restrict__ vals32,
                                              const uint8_t* __restrict__ isD,
                                              const double* __restrict__ gnode,
@@ -597,11 +803,13 @@ __global__ __launch_bounds__(WG) void k_lift(int n, const int* __restrict__ rp,
                                              float* __restrict__ dinv32, int do_lift) {
     const int i = blockIdx.x * WG + threadIdx.x;
     if (i >= n) return;
-    const int s = rp[i], e = rp[i + 1];
+    int start, len, stride;
+    row_span(L, i, start, len, stride);
     double diag = 0.0;
     if (do_lift && isD[i]) {
-        for (int k = s; k < e; ++k) {
-            const double v = (ci[k] == i) ? 1.0 : 0.0;
+        for (int j = 0; j < len; ++j) {
+            const int k = start + j * stride;
+            const double v = (L.cols[k] == i) ? 1.0 : 0.0;
             vals[k] = v;
             if (vals32) vals32[k] = (float)v;
         }
@@ -609,8 +817,9 @@ __global__ __launch_bounds__(WG) void k_lift(int n, const int* __restrict__ rp,
         if (lift) lift[i] = gnode[i];
     } else {
         double acc = 0.0;
-        for (int k = s; k < e; ++k) {
-            const int c = ci[k];
+        for (int j = 0; j < len; ++j) {
+            const int k = start + j * stride;
+            const int c = L.cols[k];
             double v = vals[k];
             if (do_lift && isD[c]) {
                 acc += v * gnode[c];
@@ -716,7 +925,7 @@ __global__ void k_finish_rhs(int n, const double* __restrict__ rhs,
 inline int grid1(int64_t n) { return (int)((n + WG - 1) / WG); }
 
 template <typename T, int MODE>
-void launch_rows(const SpmvConfig& c, const RowArgs<T>& a, hipStream_t s) {
+void launch_csr(const SpmvConfig& c, const RowArgs<T>& a, hipStream_t s) {
     const int nb = blocks_for(a.n, c.rows_per_block);
     if (nb == 0) return;
     switch (c.lanes) {
@@ -725,6 +934,29 @@ void launch_rows(const SpmvConfig& c, const RowArgs<T>& a, hipStream_t s) {
         case 16: hipLaunchKernelGGL((k_rows<T, 16, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
         default: hipLaunchKernelGGL((k_rows<T, 4, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
     }
+}
+
+// One launcher for both layouts: CSR row groups or SELL slabs.  Returns the grid size.
+template <typename T, int MODE>
+int launch_rows(const Mat& A, const T* vals, const SpmvConfig& c, const T* x, T* y,
+                const double* b, const double* dinv, double* pout, double* partials,
+                PcgState* st, int outer_mode, hipStream_t s) {
+    if (A.sell) {
+        SellArgs<T> a{A.sptr, A.scol, A.sdel, vals, x, y, b, dinv, pout, partials, st, A.n,
+                      A.nslabs, c.slabs_per_block, outer_mode};
+        const int nb = blocks_for(A.nslabs, c.slabs_per_block);
+        if (nb > 0) {
+            if (A.sdel)
+                hipLaunchKernelGGL((k_sell<T, MODE, true>), dim3(nb), dim3(WG), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_sell<T, MODE, false>), dim3(nb), dim3(WG), 0, s, a);
+        }
+        return nb;
+    }
+    RowArgs<T> a{A.rp, A.ci, vals, x, y, b, dinv, pout, partials, st, A.n, c.rows_per_block,
+                 outer_mode};
+    launch_csr<T, MODE>(c, a, s);
+    return blocks_for(A.n, c.rows_per_block);
 }
 
 inline int vec_blocks(int n) { return (n + kVecRowsPerBlock - 1) / kVecRowsPerBlock; }
@@ -741,12 +973,16 @@ int blocks_for(int64_t n, int rows_per_block) {
 SpmvConfig choose_spmv_config(int64_t n, int64_t nnz) {
     const double avg = n > 0 ? (double)nnz / (double)n : 1.0;
     SpmvConfig c;
-    c.lanes = avg > 20.0 ? 4 : (avg > 6.0 ? 4 : 2);
+    c.lanes = avg > 6.0 ? 4 : 2;
     const int rows_per_pass = WG / c.lanes;
     int passes = 8;
     // keep at least ~4 blocks per CU when the matrix is small
     while (passes > 1 && blocks_for(n, rows_per_pass * passes) < 1024) passes /= 2;
     c.rows_per_block = rows_per_pass * passes;
+    const int64_t nslabs = (n + WAVE - 1) / WAVE;
+    int spw = 2;  // slabs per wavefront
+    while (spw > 1 && blocks_for(nslabs, NWAVES * spw) < 1024) spw /= 2;
+    c.slabs_per_block = NWAVES * spw;
     return c;
 }
 
@@ -754,74 +990,75 @@ void launch_state_init(PcgState* st, double tol, int maxit, hipStream_t s) {
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, tol, maxit);
 }
 
-void launch_diag_inv(const Csr64& A, double* dinv, float* dinv32, PcgState* st, hipStream_t s) {
+void launch_diag_inv(const Mat& A, double* dinv, float* dinv32, PcgState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_diag_inv, dim3(grid1(A.n)), dim3(WG), 0, s, A.rp, A.ci, A.v, A.n, dinv,
                        dinv32, st);
 }
 
-void launch_pcg_start(const Csr64& A, const SpmvConfig& c, const double* b, const double* x,
+void launch_pcg_start(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
                       const double* dinv, double* r, double* p, double* partials, PcgState* st,
                       hipStream_t s) {
-    RowArgs<double> a{A.rp, A.ci, A.v, x, r, b, dinv, p, partials, st, A.n, c.rows_per_block, 0};
-    launch_rows<double, ROW_START>(c, a, s);
+    launch_rows<double, ROW_START>(A, A.v, c, x, r, b, dinv, p, partials, st, 0, s);
 }
 
-void launch_spmv_dot64(const Csr64& A, const SpmvConfig& c, const double* p, double* q,
-                       double* partials, PcgState* st, hipStream_t s) {
-    RowArgs<double> a{A.rp, A.ci, A.v, p, q, nullptr, nullptr, nullptr, partials, st, A.n,
-                      c.rows_per_block, 0};
-    launch_rows<double, ROW_DOT>(c, a, s);
+int launch_spmv_dot64(const Mat& A, const SpmvConfig& c, const double* p, double* q,
+                      double* pq_part, PcgState* st, hipStream_t s) {
+    return launch_rows<double, ROW_DOT>(A, A.v, c, p, q, nullptr, nullptr, nullptr, pq_part, st, 0,
+                                        s);
 }
 
-void launch_spmv_dot32(const Csr32& A, const SpmvConfig& c, const float* p, float* q,
-                       double* partials, PcgState* st, hipStream_t s) {
-    RowArgs<float> a{A.rp, A.ci, A.v, p, q, nullptr, nullptr, nullptr, partials, st, A.n,
-                     c.rows_per_block, 0};
-    launch_rows<float, ROW_DOT>(c, a, s);
+int launch_spmv_dot32(const Mat& A, const SpmvConfig& c, const float* p, float* q,
+                      double* pq_part, PcgState* st, hipStream_t s) {
+    return launch_rows<float, ROW_DOT>(A, A.v32, c, p, q, nullptr, nullptr, nullptr, pq_part, st, 0,
+                                       s);
 }
 
-void launch_spmv64(const Csr64& A, const SpmvConfig& c, const double* x, double* y,
+void launch_spmv64(const Mat& A, const SpmvConfig& c, const double* x, double* y,
                    hipStream_t s) {
-    RowArgs<double> a{A.rp, A.ci, A.v, x, y, nullptr, nullptr, nullptr, nullptr, nullptr, A.n,
-                      c.rows_per_block, 0};
-    launch_rows<double, ROW_PLAIN>(c, a, s);
+    launch_rows<double, ROW_PLAIN>(A, A.v, c, x, y, nullptr, nullptr, nullptr, nullptr, nullptr, 0,
+                                   s);
 }
 
-void launch_spmv32(const Csr32& A, const SpmvConfig& c, const float* x, float* y,
+void launch_spmv32(const Mat& A, const SpmvConfig& c, const float* x, float* y,
                    hipStream_t s) {
-    RowArgs<float> a{A.rp, A.ci, A.v, x, y, nullptr, nullptr, nullptr, nullptr, nullptr, A.n,
-                     c.rows_per_block, 0};
-    launch_rows<float, ROW_PLAIN>(c, a, s);
+    launch_rows<float, ROW_PLAIN>(A, A.v32, c, x, y, nullptr, nullptr, nullptr, nullptr, nullptr, 0,
+                                  s);
 }
 
-void launch_residual64(const Csr64& A, const SpmvConfig& c, const double* b, const double* x,
+void launch_residual64(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
                        double* r, double* partials, PcgState* st, int outer_mode, hipStream_t s) {
-    RowArgs<double> a{A.rp, A.ci, A.v, x, r, b, nullptr, nullptr, partials, st, A.n,
-                      c.rows_per_block, outer_mode};
-    launch_rows<double, ROW_RESID>(c, a, s);
+    launch_rows<double, ROW_RESID>(A, A.v, c, x, r, b, nullptr, nullptr, partials, st, outer_mode,
+                                   s);
 }
 
-void launch_update64(int n, double* x, double* r, const double* p, const double* q,
-                     const double* dinv, double* partials, PcgState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_update<double>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, x, r, p, q,
-                       dinv, partials, st);
+int launch_update64(int n, double* x, double* r, const double* p, const double* q,
+                    const double* dinv, const double* pq_part, int nb_pq, double* rz_part, int it,
+                    PcgState* st, hipStream_t s) {
+    const int nb = vec_blocks(n);
+    hipLaunchKernelGGL(k_update<double>, dim3(nb), dim3(WG), 0, s, n, x, r, p, q, dinv, pq_part,
+                       nb_pq, rz_part, it, st);
+    return nb;
 }
 
-void launch_update32(int n, float* x, float* r, const float* p, const float* q,
-                     const float* dinv, double* partials, PcgState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_update<float>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, x, r, p, q, dinv,
-                       partials, st);
+int launch_update32(int n, float* x, float* r, const float* p, const float* q,
+                    const float* dinv, const double* pq_part, int nb_pq, double* rz_part, int it,
+                    PcgState* st, hipStream_t s) {
+    const int nb = vec_blocks(n);
+    hipLaunchKernelGGL(k_update<float>, dim3(nb), dim3(WG), 0, s, n, x, r, p, q, dinv, pq_part,
+                       nb_pq, rz_part, it, st);
+    return nb;
 }
 
-void launch_pupdate64(int n, double* p, const double* r, const double* dinv, PcgState* st,
-                      hipStream_t s) {
+void launch_pupdate64(int n, double* p, const double* r, const double* dinv,
+                      const double* rz_part, int nb_rz, int it, PcgState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_pupdate<double>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv,
-                       st);
+                       rz_part, nb_rz, it, st);
 }
 
-void launch_pupdate32(int n, float* p, const float* r, const float* dinv, PcgState* st,
-                      hipStream_t s) {
-    hipLaunchKernelGGL(k_pupdate<float>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv, st);
+void launch_pupdate32(int n, float* p, const float* r, const float* dinv, const double* rz_part,
+                      int nb_rz, int it, PcgState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_pupdate<float>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv,
+                       rz_part, nb_rz, it, st);
 }
 
 void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,
@@ -862,23 +1099,22 @@ void launch_set_dirichlet(const int32_t* ids, const double* gnode, int64_t nD, d
 }
 
 void launch_assemble_colour(int npe, const int32_t* elems, int count, const int32_t* conn,
-                            const double* xyz, const int32_t* rp, const int32_t* ci,
-                            const double* mass, const double* stiff, double* vals,
-                            hipStream_t s) {
+                            const double* xyz, const Layout& L, const double* mass,
+                            const double* stiff, double* vals, hipStream_t s) {
     if (count <= 0) return;
     const int grid = grid1((int64_t)count * npe);
     if (npe == 8)
-        hipLaunchKernelGGL(k_assemble<8>, dim3(grid), dim3(WG), 0, s, elems, count, conn, xyz, rp,
-                           ci, mass, stiff, vals);
+        hipLaunchKernelGGL(k_assemble<8>, dim3(grid), dim3(WG), 0, s, elems, count, conn, xyz, L,
+                           mass, stiff, vals);
     else
-        hipLaunchKernelGGL(k_assemble<4>, dim3(grid), dim3(WG), 0, s, elems, count, conn, xyz, rp,
-                           ci, mass, stiff, vals);
+        hipLaunchKernelGGL(k_assemble<4>, dim3(grid), dim3(WG), 0, s, elems, count, conn, xyz, L,
+                           mass, stiff, vals);
 }
 
-void launch_lift(int n, const int32_t* rp, const int32_t* ci, double* vals, float* vals32,
-                 const uint8_t* isD, const double* gnode, double* lift, double* dinv,
-                 float* dinv32, int do_lift, hipStream_t s) {
-    hipLaunchKernelGGL(k_lift, dim3(grid1(n)), dim3(WG), 0, s, n, rp, ci, vals, vals32, isD, gnode,
+void launch_lift(int n, const Layout& L, double* vals, float* vals32, const uint8_t* isD,
+                 const double* gnode, double* lift, double* dinv, float* dinv32, int do_lift,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_lift, dim3(grid1(n)), dim3(WG), 0, s, n, L, vals, vals32, isD, gnode,
                        lift, dinv, dinv32, do_lift);
 }
 

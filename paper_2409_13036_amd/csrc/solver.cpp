@@ -83,7 +83,7 @@ SolveOpts resolve_opts(const rafem_solve_opts* o, double default_tol) {
     return r;
 }
 
-rafem_status pcg64(rafem_mesh m, const Csr64& A, const double* dinv_in, const double* b, double* x,
+rafem_status pcg64(rafem_mesh m, const Mat& A, const double* dinv_in, const double* b, double* x,
                    const SolveOpts& o, rafem_solve_info* info, hipStream_t s, int hint,
                    int* iters_out) {
     PcgState* st = m->st;
@@ -93,6 +93,7 @@ rafem_status pcg64(rafem_mesh m, const Csr64& A, const double* dinv_in, const do
     launch_state_init(st, o.tol, o.maxit, s);
     const double* dinv = dinv_in;
     if (!dinv) {
+        if (A.sell) throw Error{RAFEM_E_STATE, "slab-layout solve without a Jacobi inverse"};
         launch_diag_inv(A, m->dinv, nullptr, st, s);
         dinv = m->dinv;
     }
@@ -109,11 +110,13 @@ rafem_status pcg64(rafem_mesh m, const Csr64& A, const double* dinv_in, const do
         const int k = std::min(chunk, o.maxit - launched);
         ChunkTimer timer(m, k, 0);
         for (int j = 0; j < k; ++j) {
+            const int it = launched + j;
             timer.before(j, s);
-            launch_spmv_dot64(A, cfg, m->p, m->q, m->partials, st, s);
+            const int nb1 = launch_spmv_dot64(A, cfg, m->p, m->q, m->part_pq, st, s);
             timer.after(j, s);
-            launch_update64(n, x, m->r, m->p, m->q, dinv, m->partials, st, s);
-            launch_pupdate64(n, m->p, m->r, dinv, st, s);
+            const int nb2 = launch_update64(n, x, m->r, m->p, m->q, dinv, m->part_pq, nb1,
+                                            m->part_rz, it, st, s);
+            launch_pupdate64(n, m->p, m->r, dinv, m->part_rz, nb2, it, st, s);
         }
         check_launch();
         launched += k;
@@ -153,7 +156,7 @@ rafem_status pcg64(rafem_mesh m, const Csr64& A, const double* dinv_in, const do
     return status;
 }
 
-rafem_status pcg_mixed(rafem_mesh m, const Csr64& A, const Csr32& A32, const double* dinv_in,
+rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const double* dinv_in,
                        const float* dinv32_in, const double* b, double* x, const SolveOpts& o,
                        rafem_solve_info* info, hipStream_t s, int hint, int* iters_out) {
     PcgState* inner = m->st;
@@ -164,11 +167,11 @@ rafem_status pcg_mixed(rafem_mesh m, const Csr64& A, const Csr32& A32, const dou
     const double* dinv = dinv_in;
     const float* dinv32 = dinv32_in;
     if (!dinv || !dinv32) {
+        if (A.sell) throw Error{RAFEM_E_STATE, "slab-layout solve without a Jacobi inverse"};
         launch_diag_inv(A, m->dinv, m->dinv32, outer, s);
         dinv = m->dinv;
         dinv32 = m->dinv32;
     }
-    (void)dinv;
     int total_inner = 0, launched_total = 0, outer_steps = 0;
     int chunk0 = first_chunk(o, hint);
     double prev_outer_rr = -1.0;
@@ -192,11 +195,13 @@ rafem_status pcg_mixed(rafem_mesh m, const Csr64& A, const Csr32& A32, const dou
             const int k = std::min(chunk, o.maxit - launched);
             ChunkTimer timer(m, k, 1);
             for (int j = 0; j < k; ++j) {
+                const int it = launched + j;
                 timer.before(j, s);
-                launch_spmv_dot32(A32, cfg, m->p32, m->q32, m->partials, inner, s);
+                const int nb1 = launch_spmv_dot32(A, cfg, m->p32, m->q32, m->part_pq, inner, s);
                 timer.after(j, s);
-                launch_update32(n, m->d32, m->r32, m->p32, m->q32, dinv32, m->partials, inner, s);
-                launch_pupdate32(n, m->p32, m->r32, dinv32, inner, s);
+                const int nb2 = launch_update32(n, m->d32, m->r32, m->p32, m->q32, dinv32,
+                                                m->part_pq, nb1, m->part_rz, it, inner, s);
+                launch_pupdate32(n, m->p32, m->r32, dinv32, m->part_rz, nb2, it, inner, s);
             }
             check_launch();
             launched += k;
@@ -235,7 +240,7 @@ rafem_status pcg_mixed(rafem_mesh m, const Csr64& A, const Csr32& A32, const dou
         SolveOpts o64 = o;
         o64.precision = RAFEM_FP64;
         int it64 = 0;
-        rafem_status st = pcg64(m, A, dinv_in, b, x, o64, &sub, s, 0, &it64);
+        rafem_status st = pcg64(m, A, dinv, b, x, o64, &sub, s, 0, &it64);
         if (info) {
             *info = sub;
             info->iters = total_inner + sub.iters;

@@ -16,14 +16,16 @@ struct SolveOpts {
 
 SolveOpts resolve_opts(const rafem_solve_opts* o, double default_tol);
 
-// FP64 Jacobi-PCG on A from x (in/out).  dinv may be NULL (computed from A's diagonal).
+// FP64 Jacobi-PCG on A from x (in/out).  dinv may be NULL for a CSR matrix (then it is
+// computed from A's diagonal).
 // hint: expected iteration count (0 = unknown).  Fills info, returns its status.
-rafem_status pcg64(rafem_mesh m, const Csr64& A, const double* dinv, const double* b, double* x,
+rafem_status pcg64(rafem_mesh m, const Mat& A, const double* dinv, const double* b, double* x,
                    const SolveOpts& o, rafem_solve_info* info, hipStream_t s, int hint,
                    int* iters_out);
 
-// FP32 inner PCG inside FP64 iterative refinement.  dinv/dinv32 may be NULL.
-rafem_status pcg_mixed(rafem_mesh m, const Csr64& A, const Csr32& A32, const double* dinv,
+// FP32 inner PCG (on A.v32) inside FP64 iterative refinement (on A.v).  dinv/dinv32 may be
+// NULL for a CSR matrix.
+rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const double* dinv,
                        const float* dinv32, const double* b, double* x, const SolveOpts& o,
                        rafem_solve_info* info, hipStream_t s, int hint, int* iters_out);
 

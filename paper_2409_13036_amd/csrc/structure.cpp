@@ -104,6 +104,63 @@ HostStructure build_structure(int64_t n, int64_t E, int npe, const int32_t* conn
     return S;
 }
 
+HostSell build_sell(const HostStructure& S, int64_t n) {
+    // Slabs of 64 consecutive rows, one row per lane of a wavefront.  Entry j of row r
+    // lives at sptr[r / 64] + (r % 64) + 64 j, so a wavefront reading entry j of its 64
+    // rows touches 64 consecutive words.  A slab is as wide as its longest row; shorter
+    // rows are padded with value 0 and their own row index as column (a valid x index).
+    HostSell L;
+    L.nslabs = (n + 63) / 64;
+    L.sptr.assign(L.nslabs + 1, 0);
+    L.rlen.assign(n, 0);
+    int64_t total = 0;
+    for (int64_t s = 0; s < L.nslabs; ++s) {
+        int32_t w = 0;
+        for (int64_t r = s * 64; r < std::min<int64_t>(n, s * 64 + 64); ++r)
+            w = std::max(w, S.row_ptr[r + 1] - S.row_ptr[r]);
+        total += 64 * (int64_t)w;
+        if (total > INT32_MAX) throw Error{RAFEM_E_MESH, "padded slab storage exceeds INT32_MAX"};
+        L.sptr[s + 1] = (int32_t)total;
+    }
+    L.scol.assign(total, 0);
+    for (int64_t s = 0; s < L.nslabs; ++s) {
+        const int32_t base = L.sptr[s];
+        const int32_t w = (L.sptr[s + 1] - base) / 64;
+        for (int64_t lane = 0; lane < 64; ++lane) {
+            const int64_t r = s * 64 + lane;
+            const int32_t pad = (int32_t)std::min<int64_t>(r, n - 1);
+            int32_t len = 0;
+            if (r < n) {
+                len = S.row_ptr[r + 1] - S.row_ptr[r];
+                L.rlen[r] = len;
+                for (int32_t j = 0; j < len; ++j)
+                    L.scol[base + lane + 64 * (int64_t)j] = S.col_idx[S.row_ptr[r] + j];
+            }
+            for (int32_t j = len; j < w; ++j) L.scol[base + lane + 64 * (int64_t)j] = pad;
+        }
+    }
+    // 16-bit offsets to the row (padding: offset 0) when every column is within reach
+    bool fits = true;
+    for (int64_t s = 0; s < L.nslabs && fits; ++s)
+        for (int64_t k = L.sptr[s]; k < L.sptr[s + 1]; ++k) {
+            const int64_t r = std::min<int64_t>(s * 64 + (k - L.sptr[s]) % 64, n - 1);
+            const int64_t d = (int64_t)L.scol[k] - r;
+            if (d < INT16_MIN || d > INT16_MAX) {
+                fits = false;
+                break;
+            }
+        }
+    if (fits) {
+        L.sdel.resize(total);
+        for (int64_t s = 0; s < L.nslabs; ++s)
+            for (int64_t k = L.sptr[s]; k < L.sptr[s + 1]; ++k) {
+                const int64_t r = std::min<int64_t>(s * 64 + (k - L.sptr[s]) % 64, n - 1);
+                L.sdel[k] = (int16_t)((int64_t)L.scol[k] - r);
+            }
+    }
+    return L;
+}
+
 int colour_elements(int64_t n, int64_t E, int npe, const int32_t* conn, int32_t* colour) {
     // Greedy first fit in element order.  mask[node] holds the colours of the already
     // coloured elements that touch the node; an element takes the lowest colour absent
