@@ -119,10 +119,11 @@ Mat csr_matrix(rafem_mesh m, const int32_t* rp, const int32_t* ci, const double*
 void assemble_into(rafem_mesh m, const Layout& L, int64_t count, const double* mass,
                    const double* stiff, double* vals, hipStream_t s) {
     launch_fill(vals, count, 0.0, s);
+    const int32_t* e2s = L.sell ? m->e2s : nullptr;
     for (int c = 0; c < m->n_colours; ++c) {
         const int off = m->colour_off[c], cnt = m->colour_off[c + 1] - off;
-        launch_assemble_colour(m->npe, m->colour_elems + off, cnt, m->conn, m->xyz, L, mass, stiff,
-                               vals, s);
+        launch_assemble_colour(m->npe, m->affine, m->colour_elems + off, cnt, m->conn, m->xyz, L,
+                               e2s, mass, stiff, vals, s);
     }
 }
 
@@ -195,7 +196,7 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
         }
         for (int64_t i = 0; i < 3 * n_nodes; ++i)
             if (!std::isfinite(xyz_h[i])) throw Error{RAFEM_E_MESH, "non-finite node coordinate"};
-        check_geometry(n_elems, npe, conn_h, xyz_h);
+        const bool affine = check_geometry(n_elems, npe, conn_h, xyz_h);
         HostStructure S = build_structure(n_nodes, n_elems, npe, conn_h);
         HostSell SL = build_sell(S, n_nodes);
         std::vector<int32_t> colour(n_elems);
@@ -212,6 +213,7 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             m->sell_nnz = (int64_t)SL.scol.size();
             m->nD = n_dir;
             m->n_colours = ncol;
+            m->affine = (npe == 8 && affine) ? 1 : 0;
             m->spmv = choose_spmv_config(m->n, m->nnz);
             // elements grouped by colour, ascending id within a colour
             m->colour_off.assign(ncol + 1, 0);
@@ -230,6 +232,7 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             m->sptr = dalloc<int32_t>(m, (size_t)m->nslabs + 1);
             m->scol = dalloc<int32_t>(m, SNNZ);
             m->rlen = dalloc<int32_t>(m, N);
+            m->e2s = dalloc<int32_t>(m, E * (size_t)npe * npe);
             if (!SL.sdel.empty()) m->sdel = dalloc<int16_t>(m, SNNZ);
             m->conn = dalloc<int32_t>(m, E * npe);
             m->xyz = dalloc<double>(m, 3 * N);
@@ -288,7 +291,8 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
                 RAFEM_HIP(hipMemcpy(m->dir_ids, dir_ids_h, (size_t)n_dir * 4, hipMemcpyHostToDevice));
             RAFEM_HIP(hipMemcpy(m->isD, isD.data(), N, hipMemcpyHostToDevice));
             RAFEM_HIP(hipMemcpy(m->st, m->st_host, 3 * sizeof(PcgState), hipMemcpyHostToDevice));
-            // ticket counters must start at zero; later kernels keep them at zero between launches
+            launch_slot_map(m->E, m->npe, m->conn, sell_layout(m), m->e2s, nullptr);
+            RAFEM_HIP(hipGetLastError());
             RAFEM_HIP(hipDeviceSynchronize());
         } catch (...) {
             free_mesh(m);
@@ -507,7 +511,7 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
         launch_fill(m->rhs, m->n, 0.0, s);
         for (int c = 0; c < m->n_colours; ++c) {
             const int off = m->colour_off[c], cnt = m->colour_off[c + 1] - off;
-            launch_bioheat_rhs_colour(m->npe, m->colour_elems + off, cnt, m->conn, m->xyz, T_d,
+            launch_bioheat_rhs_colour(m->npe, m->affine, m->colour_elems + off, cnt, m->conn, m->xyz, T_d,
                                       phys->coupled ? V_d : nullptr, m->sigma, perf_e_d,
                                       phys->rho_c / phys->dt, phys->T_a, phys->coupled ? 1 : 0,
                                       m->rhs, s);

@@ -54,7 +54,8 @@ int colour_elements(int64_t n_nodes, int64_t n_elems, int npe, const int32_t* co
                     int32_t* colour);
 // Minimum Jacobian determinant over the quadrature points of every element (hex: 2x2x2
 // Gauss points; tet: the constant determinant).  Throws E_MESH if any is <= 0.
-void check_geometry(int64_t n_elems, int npe, const int32_t* conn, const double* xyz);
+// Returns true when every element is affine (hex: a parallelepiped; tets always are).
+bool check_geometry(int64_t n_elems, int npe, const int32_t* conn, const double* xyz);
 
 // ---------------------------------------------------------------------------
 // Device-side solver state.  One instance per concurrent reduction chain.
@@ -75,7 +76,7 @@ struct PcgState {
     int32_t done;
     int32_t status;
     int32_t bad_diag;
-    uint32_t ticket;  // arrival counter of the once-per-solve reductions; 0 between kernels
+    int32_t pad;
 };
 static_assert(sizeof(PcgState) % 8 == 0, "PcgState layout");
 
@@ -170,9 +171,14 @@ void launch_scatter_dirichlet(const int32_t* dir_ids, const double* dir_vals, in
                               double* gnode, hipStream_t s);
 void launch_set_dirichlet(const int32_t* dir_ids, const double* gnode, int64_t nD, double* x,
                           hipStream_t s);
-void launch_assemble_colour(int npe, const int32_t* elems, int count, const int32_t* conn,
-                            const double* xyz, const Layout& L, const double* mass,
-                            const double* stiff, double* vals, hipStream_t s);
+// affine: every hex is a parallelepiped (closed-form element integrals); e2s: optional
+// value position of every (element, a, b) in L (else searched).
+void launch_assemble_colour(int npe, int affine, const int32_t* elems, int count,
+                            const int32_t* conn, const double* xyz, const Layout& L,
+                            const int32_t* e2s, const double* mass, const double* stiff,
+                            double* vals, hipStream_t s);
+void launch_slot_map(int64_t E, int npe, const int32_t* conn, const Layout& L, int32_t* e2s,
+                     hipStream_t s);
 // Lifting with per-node Dirichlet mask/values; writes lifted vals, vals32, lift, dinv, dinv32.
 void launch_lift(int n, const Layout& L, double* vals, float* vals32, const uint8_t* isD,
                  const double* gnode, double* lift, double* dinv, float* dinv32, int do_lift,
@@ -182,10 +188,11 @@ void launch_cast32(const double* v, float* v32, int64_t n, hipStream_t s);
 void launch_coef(const double* perf, double c0, double* coef, int64_t E, hipStream_t s);
 void launch_sigma(int npe, int64_t E, const int32_t* conn, const double* T, const double* sigma0,
                   double alpha, double T_ref, double* sigma, hipStream_t s);
-void launch_bioheat_rhs_colour(int npe, const int32_t* elems, int count, const int32_t* conn,
-                               const double* xyz, const double* T, const double* V,
-                               const double* sigma, const double* perf, double rho_c_dt,
-                               double T_a, int with_joule, double* rhs, hipStream_t s);
+void launch_bioheat_rhs_colour(int npe, int affine, const int32_t* elems, int count,
+                               const int32_t* conn, const double* xyz, const double* T,
+                               const double* V, const double* sigma, const double* perf,
+                               double rho_c_dt, double T_a, int with_joule, double* rhs,
+                               hipStream_t s);
 // b = isD ? lift : rhs + lift
 void launch_finish_rhs(int n, const double* rhs, const double* lift, const uint8_t* isD,
                        double* b, hipStream_t s);
@@ -210,6 +217,8 @@ struct rafem_mesh_s {
     int32_t* sptr = nullptr;  // SELL slab offsets
     int32_t* scol = nullptr;  // SELL column ids
     int32_t* rlen = nullptr;  // SELL row lengths
+    int32_t* e2s = nullptr;   // value position in the SELL layout of every (element, a, b)
+    int affine = 0;           // every hex is a parallelepiped
     int16_t* sdel = nullptr;  // SELL column - row offsets (NULL when the bandwidth exceeds int16)
     int32_t* conn = nullptr;
     double* xyz = nullptr;

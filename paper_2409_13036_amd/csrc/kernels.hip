@@ -10,10 +10,11 @@
 //   * workgroups own contiguous row ranges and are remapped so each of the 8
 //     XCDs (own L2) walks one contiguous eighth of the rows, which keeps the
 //     x-gathers of neighbouring rows in that XCD's L2;
-//   * reductions are deterministic: per-block partial sums in a fixed slot,
-//     then the last block to arrive (integer ticket) adds the partials in
-//     index order and updates the solver scalars in device memory, so no
-//     floating-point atomics and no host round trip per iteration.
+//   * reductions are deterministic and need no atomics or fences: each block
+//     stores its partial sums in a fixed slot, and the consumer (every block of
+//     the next kernel, or a one-block finalize kernel) adds them in index order
+//     after the kernel boundary; solver scalars stay in device memory, so there
+//     is no host round trip per iteration.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -61,39 +62,6 @@ __device__ __forceinline__ void block_sum(double (&v)[K]) {
             v[k] = s;
         }
     }
-}
-
-// Store this block's K partial sums (thread 0), then take a ticket.  Returns true in
-// every thread of the last block to arrive; tot[] then holds the fixed-order totals in
-// thread 0 of that block, and the ticket has been reset to 0.
-template <int K>
-__device__ bool reduce_grid(double (&v)[K], double* partials, int slot, int nb, PcgState* st,
-                            double (&tot)[K]) {
-    block_sum<K>(v);
-    __shared__ int is_last;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) partials[k * nb + slot] = v[k];
-        // Release only: publish the partials before the ticket.  A full fence here would
-        // also invalidate this XCD's L2 in every block, discarding the cached x-vector.
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned t = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (t == (unsigned)(nb - 1));
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    // Acquire, once per kernel: the other blocks' partials are visible from here on.
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nb; i += WG) s += partials[k * nb + i];
-        tot[k] = s;
-    }
-    block_sum<K>(tot);
-    if (threadIdx.x == 0) st->ticket = 0u;
-    return true;
 }
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
@@ -146,7 +114,6 @@ __global__ void k_state_init(PcgState* st, double tol, int maxit) {
         st->done = 0;
         st->status = RAFEM_E_NOCONV;
         st->bad_diag = 0;
-        st->ticket = 0u;
     }
 }
 
@@ -282,10 +249,7 @@ __global__ __launch_bounds__(WG) void k_rows(RowArgs<T> a) {
         double v1[1] = {acc[0]};
         store_partials<1>(v1, a.partials, blk, nb);
     } else {
-        double tot[3];
-        if (!reduce_grid<3>(acc, a.partials, blk, nb, a.st, tot)) return;
-        if (threadIdx.x != 0) return;
-        finish_rows<MODE>(a.st, tot, a.outer_mode);
+        store_partials<3>(acc, a.partials, blk, nb);
     }
 }
 
@@ -387,11 +351,17 @@ __global__ __launch_bounds__(WG) void k_sell(SellArgs<T> a) {
         double v1[1] = {acc[0]};
         store_partials<1>(v1, a.partials, blk, nb);
     } else {
-        double tot[3];
-        if (!reduce_grid<3>(acc, a.partials, blk, nb, a.st, tot)) return;
-        if (threadIdx.x != 0) return;
-        finish_rows<MODE>(a.st, tot, a.outer_mode);
+        store_partials<3>(acc, a.partials, blk, nb);
     }
+}
+
+// One block: totals of a START / RESID row kernel's partials -> solver scalars.
+template <int MODE>
+__global__ __launch_bounds__(WG) void k_finalize_rows(const double* __restrict__ partials, int nb,
+                                                      PcgState* st, int outer_mode) {
+    double tot[3];
+    grid_totals<3>(partials, nb, tot);
+    if (threadIdx.x == 0) finish_rows<MODE>(st, tot, outer_mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -515,8 +485,7 @@ __global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restr
                                                     float* __restrict__ d32,
                                                     float* __restrict__ p32,
                                                     const float* __restrict__ dinv32,
-                                                    double inner_tol, int maxit,
-                                                    double* partials, PcgState* inner) {
+                                                    double* partials) {
     const bool skip = outer->done != 0;
     const double scale = outer->scale;
     const int nb = gridDim.x;
@@ -538,9 +507,17 @@ __global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restr
             }
         }
     }
+    store_partials<2>(acc, partials, blk, nb);
+}
+
+// One block: totals of k_inner_start's partials -> inner solver state.
+__global__ __launch_bounds__(WG) void k_finalize_inner(const double* __restrict__ partials, int nb,
+                                                       const PcgState* outer, double inner_tol,
+                                                       int maxit, PcgState* inner) {
     double tot[2];
-    if (!reduce_grid<2>(acc, partials, blk, nb, inner, tot)) return;
+    grid_totals<2>(partials, nb, tot);
     if (threadIdx.x != 0) return;
+    const bool skip = outer->done != 0;
     inner->rzs[0] = tot[0];
     inner->rzs[1] = 0.0;
     inner->rr = tot[1];
@@ -721,6 +698,75 @@ __device__ void hex_rows(const double (&X)[8][3], int a, double (&Kr)[8], double
     }
 }
 
+// Parallelepiped (affine) hex: constant Jacobian J = [x1-x0, x3-x0, x4-x0] / 2.  With
+// C = detJ J^-1 J^-T the stiffness is K_ab = sum_de C_de I_ab^de, where the reference
+// integrals of products of trilinear shape-function derivatives factor per axis:
+//   I_ab^dd = (s_ad s_bd / 64) 2 p_e p_f,   I_ab^de = (s_ad s_be / 64) 4 p_f  (d != e),
+// p_k = 2 + (2/3) s_ak s_bk, s = corner signs; and M_ab = detJ p_0 p_1 p_2 / 64.  These
+// are the exact integrals, which the 2x2x2 Gauss rule reproduces on affine elements.
+__device__ __forceinline__ double hex_affine_jacobian(const double (&X)[8][3],
+                                                      double (&Ji)[3][3]) {
+    double J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        J[i][0] = 0.5 * (X[1][i] - X[0][i]);
+        J[i][1] = 0.5 * (X[3][i] - X[0][i]);
+        J[i][2] = 0.5 * (X[4][i] - X[0][i]);
+    }
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double id = 1.0 / det;
+    Ji[0][0] = c00 * id;
+    Ji[1][0] = c01 * id;
+    Ji[2][0] = c02 * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    return det;
+}
+
+__device__ void hex_rows_affine(const double (&X)[8][3], int a, double (&Kr)[8],
+                                double (&Mr)[8]) {
+    double Ji[3][3];
+    const double det = hex_affine_jacobian(X, Ji);
+    double C[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+            C[d][e] = det * (Ji[d][0] * Ji[e][0] + Ji[d][1] * Ji[e][1] + Ji[d][2] * Ji[e][2]);
+    const double sa[3] = {hsx(a), hsy(a), hsz(a)};
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const double sb[3] = {hsx(b), hsy(b), hsz(b)};
+        double pk[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pk[k] = 2.0 + (2.0 / 3.0) * sa[k] * sb[k];
+        double k_ab = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                double I;
+                if (d == e) {
+                    I = sa[d] * sb[d] * (1.0 / 32.0) * pk[(d + 1) % 3] * pk[(d + 2) % 3];
+                } else {
+                    const int f = 3 - d - e;
+                    I = sa[d] * sb[e] * (1.0 / 16.0) * pk[f];
+                }
+                k_ab += C[d][e] * I;
+            }
+        }
+        Kr[b] = k_ab;
+        Mr[b] = det * pk[0] * pk[1] * pk[2] * (1.0 / 64.0);
+    }
+}
+
 // Tet: volume and constant gradients of the barycentric coordinates.
 __device__ __forceinline__ double tet_geometry(const double (&X)[4][3], double (&G)[4][3]) {
     double J[3][3];
@@ -749,13 +795,14 @@ __device__ __forceinline__ double tet_geometry(const double (&X)[4][3], double (
 }
 
 // One thread per (element of this colour, local row a): add row a of
-// mass[e] M_e + stiff[e] K_e into the CSR values.  Elements of one colour share no
-// node, so no two threads of a launch touch the same row.
-template <int NPE>
+// mass[e] M_e + stiff[e] K_e into the matrix values.  Elements of one colour share no
+// node, so no two threads of a launch touch the same row.  e2s, when given, holds the
+// value position of every (element, a, b) pair; otherwise it is searched in the row.
+template <int NPE, bool AFFINE>
 __global__ __launch_bounds__(WG) void k_assemble(const int* __restrict__ elems, int count,
                                                  const int* __restrict__ conn,
                                                  const double* __restrict__ xyz,
-                                                 const Layout L,
+                                                 const Layout L, const int* __restrict__ e2s,
                                                  const double* __restrict__ mass,
                                                  const double* __restrict__ stiff,
                                                  double* __restrict__ vals) {
@@ -775,7 +822,8 @@ __global__ __launch_bounds__(WG) void k_assemble(const int* __restrict__ elems, 
     const double c = stiff ? stiff[e] : 0.0;
     double Kr[NPE], Mr[NPE];
     if constexpr (NPE == 8) {
-        hex_rows(X, a, Kr, Mr);
+        if constexpr (AFFINE) hex_rows_affine(X, a, Kr, Mr);
+        else hex_rows(X, a, Kr, Mr);
     } else {
         double G[4][3];
         const double V = tet_geometry(X, G);
@@ -785,13 +833,31 @@ __global__ __launch_bounds__(WG) void k_assemble(const int* __restrict__ elems, 
             Mr[b] = (a == b ? 2.0 : 1.0) * V / 20.0;
         }
     }
-    int start, len, stride;
-    row_span(L, nodes[a], start, len, stride);
+    if (e2s) {
+        const int* sl = e2s + ((int64_t)e * NPE + a) * NPE;
 #pragma unroll
-    for (int b = 0; b < NPE; ++b) {
-        const int k = find_slot(L.cols, start, len, stride, nodes[b]);
-        vals[k] += m * Mr[b] + c * Kr[b];
+        for (int b = 0; b < NPE; ++b) vals[sl[b]] += m * Mr[b] + c * Kr[b];
+    } else {
+        int start, len, stride;
+        row_span(L, nodes[a], start, len, stride);
+#pragma unroll
+        for (int b = 0; b < NPE; ++b) {
+            const int k = find_slot(L.cols, start, len, stride, nodes[b]);
+            vals[k] += m * Mr[b] + c * Kr[b];
+        }
     }
+}
+
+// Value position of every (element, local row a, local column b) in a layout.
+__global__ __launch_bounds__(WG) void k_slot_map(int64_t E, int npe, const int* __restrict__ conn,
+                                                 const Layout L, int* __restrict__ e2s) {
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= E * npe) return;
+    const int64_t e = t / npe;
+    int start, len, stride;
+    row_span(L, conn[t], start, len, stride);
+    for (int b = 0; b < npe; ++b)
+        e2s[t * npe + b] = find_slot(L.cols, start, len, stride, conn[e * npe + b]);
 }
 
 // Symmetric lifting of Dirichlet rows/columns, Jacobi inverse and FP32 copy.
@@ -851,7 +917,7 @@ __global__ __launch_bounds__(WG) void k_sigma(int npe, int64_t E, const int* __r
 
 // Bioheat right-hand side, one thread per (element of this colour, local node a):
 // rhs[node a] += sum_b M_ab (rho_c_dt T_b + perf_e T_a) + int N_a sigma_e |grad V|^2.
-template <int NPE>
+template <int NPE, bool AFFINE>
 __global__ __launch_bounds__(WG) void k_bioheat_rhs(const int* __restrict__ elems, int count,
                                                     const int* __restrict__ conn,
                                                     const double* __restrict__ xyz,
@@ -879,11 +945,13 @@ __global__ __launch_bounds__(WG) void k_bioheat_rhs(const int* __restrict__ elem
     const double sg = with_joule ? sigma[e] : 0.0;
     double f = 0.0;
     if constexpr (NPE == 8) {
+        double Ji[3][3];
+        double det = 0.0;
+        if constexpr (AFFINE) det = hex_affine_jacobian(X, Ji);
         for (int q = 0; q < 8; ++q) {
             double xi, et, ze;
             gauss_point(q, xi, et, ze);
-            double Ji[3][3];
-            const double det = hex_jacobian(X, xi, et, ze, Ji);
+            if constexpr (!AFFINE) det = hex_jacobian(X, xi, et, ze, Ji);
             double Nw = 0.0, gv0 = 0.0, gv1 = 0.0, gv2 = 0.0, Na = 0.0;
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
@@ -998,7 +1066,8 @@ void launch_diag_inv(const Mat& A, double* dinv, float* dinv32, PcgState* st, hi
 void launch_pcg_start(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
                       const double* dinv, double* r, double* p, double* partials, PcgState* st,
                       hipStream_t s) {
-    launch_rows<double, ROW_START>(A, A.v, c, x, r, b, dinv, p, partials, st, 0, s);
+    const int nb = launch_rows<double, ROW_START>(A, A.v, c, x, r, b, dinv, p, partials, st, 0, s);
+    hipLaunchKernelGGL(k_finalize_rows<ROW_START>, dim3(1), dim3(WG), 0, s, partials, nb, st, 0);
 }
 
 int launch_spmv_dot64(const Mat& A, const SpmvConfig& c, const double* p, double* q,
@@ -1027,8 +1096,10 @@ void launch_spmv32(const Mat& A, const SpmvConfig& c, const float* x, float* y,
 
 void launch_residual64(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
                        double* r, double* partials, PcgState* st, int outer_mode, hipStream_t s) {
-    launch_rows<double, ROW_RESID>(A, A.v, c, x, r, b, nullptr, nullptr, partials, st, outer_mode,
-                                   s);
+    const int nb = launch_rows<double, ROW_RESID>(A, A.v, c, x, r, b, nullptr, nullptr, partials, st,
+                                                  outer_mode, s);
+    hipLaunchKernelGGL(k_finalize_rows<ROW_RESID>, dim3(1), dim3(WG), 0, s, partials, nb, st,
+                       outer_mode);
 }
 
 int launch_update64(int n, double* x, double* r, const double* p, const double* q,
@@ -1064,8 +1135,11 @@ void launch_pupdate32(int n, float* p, const float* r, const float* dinv, const 
 void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,
                         float* p32, const float* dinv32, double inner_tol, int maxit,
                         double* partials, PcgState* inner, hipStream_t s) {
-    hipLaunchKernelGGL(k_inner_start, dim3(vec_blocks(n)), dim3(WG), 0, s, n, r64, outer, r32,
-                       d32, p32, dinv32, inner_tol, maxit, partials, inner);
+    const int nb = vec_blocks(n);
+    hipLaunchKernelGGL(k_inner_start, dim3(nb), dim3(WG), 0, s, n, r64, outer, r32, d32, p32,
+                       dinv32, partials);
+    hipLaunchKernelGGL(k_finalize_inner, dim3(1), dim3(WG), 0, s, partials, nb, outer, inner_tol,
+                       maxit, inner);
 }
 
 void launch_refine_update(int n, double* x, const float* d32, const PcgState* outer,
@@ -1098,17 +1172,26 @@ void launch_set_dirichlet(const int32_t* ids, const double* gnode, int64_t nD, d
         hipLaunchKernelGGL(k_set_dirichlet, dim3(grid1(nD)), dim3(WG), 0, s, ids, gnode, nD, x);
 }
 
-void launch_assemble_colour(int npe, const int32_t* elems, int count, const int32_t* conn,
-                            const double* xyz, const Layout& L, const double* mass,
-                            const double* stiff, double* vals, hipStream_t s) {
+void launch_assemble_colour(int npe, int affine, const int32_t* elems, int count,
+                            const int32_t* conn, const double* xyz, const Layout& L,
+                            const int32_t* e2s, const double* mass, const double* stiff,
+                            double* vals, hipStream_t s) {
     if (count <= 0) return;
     const int grid = grid1((int64_t)count * npe);
-    if (npe == 8)
-        hipLaunchKernelGGL(k_assemble<8>, dim3(grid), dim3(WG), 0, s, elems, count, conn, xyz, L,
-                           mass, stiff, vals);
+    if (npe == 8 && affine)
+        hipLaunchKernelGGL((k_assemble<8, true>), dim3(grid), dim3(WG), 0, s, elems, count, conn,
+                           xyz, L, e2s, mass, stiff, vals);
+    else if (npe == 8)
+        hipLaunchKernelGGL((k_assemble<8, false>), dim3(grid), dim3(WG), 0, s, elems, count, conn,
+                           xyz, L, e2s, mass, stiff, vals);
     else
-        hipLaunchKernelGGL(k_assemble<4>, dim3(grid), dim3(WG), 0, s, elems, count, conn, xyz, L,
-                           mass, stiff, vals);
+        hipLaunchKernelGGL((k_assemble<4, false>), dim3(grid), dim3(WG), 0, s, elems, count, conn,
+                           xyz, L, e2s, mass, stiff, vals);
+}
+
+void launch_slot_map(int64_t E, int npe, const int32_t* conn, const Layout& L, int32_t* e2s,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_slot_map, dim3(grid1(E * npe)), dim3(WG), 0, s, E, npe, conn, L, e2s);
 }
 
 void launch_lift(int n, const Layout& L, double* vals, float* vals32, const uint8_t* isD,
@@ -1124,18 +1207,22 @@ void launch_sigma(int npe, int64_t E, const int32_t* conn, const double* T, cons
                        T_ref, sigma);
 }
 
-void launch_bioheat_rhs_colour(int npe, const int32_t* elems, int count, const int32_t* conn,
-                               const double* xyz, const double* T, const double* V,
-                               const double* sigma, const double* perf, double rho_c_dt,
-                               double T_a, int with_joule, double* rhs, hipStream_t s) {
+void launch_bioheat_rhs_colour(int npe, int affine, const int32_t* elems, int count,
+                               const int32_t* conn, const double* xyz, const double* T,
+                               const double* V, const double* sigma, const double* perf,
+                               double rho_c_dt, double T_a, int with_joule, double* rhs,
+                               hipStream_t s) {
     if (count <= 0) return;
     const int grid = grid1((int64_t)count * npe);
-    if (npe == 8)
-        hipLaunchKernelGGL(k_bioheat_rhs<8>, dim3(grid), dim3(WG), 0, s, elems, count, conn, xyz, T,
-                           V, sigma, perf, rho_c_dt, T_a, with_joule, rhs);
+    if (npe == 8 && affine)
+        hipLaunchKernelGGL((k_bioheat_rhs<8, true>), dim3(grid), dim3(WG), 0, s, elems, count, conn,
+                           xyz, T, V, sigma, perf, rho_c_dt, T_a, with_joule, rhs);
+    else if (npe == 8)
+        hipLaunchKernelGGL((k_bioheat_rhs<8, false>), dim3(grid), dim3(WG), 0, s, elems, count,
+                           conn, xyz, T, V, sigma, perf, rho_c_dt, T_a, with_joule, rhs);
     else
-        hipLaunchKernelGGL(k_bioheat_rhs<4>, dim3(grid), dim3(WG), 0, s, elems, count, conn, xyz, T,
-                           V, sigma, perf, rho_c_dt, T_a, with_joule, rhs);
+        hipLaunchKernelGGL((k_bioheat_rhs<4, false>), dim3(grid), dim3(WG), 0, s, elems, count,
+                           conn, xyz, T, V, sigma, perf, rho_c_dt, T_a, with_joule, rhs);
 }
 
 void launch_finish_rhs(int n, const double* rhs, const double* lift, const uint8_t* isD,

@@ -180,17 +180,38 @@ int colour_elements(int64_t n, int64_t E, int npe, const int32_t* conn, int32_t*
     return used;
 }
 
-void check_geometry(int64_t E, int npe, const int32_t* conn, const double* xyz) {
+bool check_geometry(int64_t E, int npe, const int32_t* conn, const double* xyz) {
     // Reference-cube corner signs of the 8 hex nodes (local order of the ABI).
     static const double sx[8] = {-1, 1, 1, -1, -1, 1, 1, -1};
     static const double sy[8] = {-1, -1, 1, 1, -1, -1, 1, 1};
     static const double sz[8] = {-1, -1, -1, -1, 1, 1, 1, 1};
     const double g = 1.0 / std::sqrt(3.0);
     std::atomic<int64_t> bad{-1};
+    std::atomic<bool> affine{true};
     parallel_for(E, [&](int64_t lo, int64_t hi) {
+        bool aff = true;
         for (int64_t e = lo; e < hi; ++e) {
             const int32_t* el = conn + e * npe;
             bool ok = true;
+            if (npe == 8 && aff) {
+                // parallelepiped: every corner is x0 + o1 (x1-x0) + o2 (x3-x0) + o3 (x4-x0)
+                double scale = 0.0;
+                for (int i = 0; i < 3; ++i) {
+                    scale = std::max(scale, std::fabs(xyz[el[1] * 3 + i] - xyz[el[0] * 3 + i]));
+                    scale = std::max(scale, std::fabs(xyz[el[3] * 3 + i] - xyz[el[0] * 3 + i]));
+                    scale = std::max(scale, std::fabs(xyz[el[4] * 3 + i] - xyz[el[0] * 3 + i]));
+                }
+                for (int a = 0; a < 8 && aff; ++a) {
+                    const double o1 = sx[a] > 0, o2 = sy[a] > 0, o3 = sz[a] > 0;
+                    for (int i = 0; i < 3; ++i) {
+                        const double x0 = xyz[el[0] * 3 + i];
+                        const double pred = x0 + o1 * (xyz[el[1] * 3 + i] - x0) +
+                                            o2 * (xyz[el[3] * 3 + i] - x0) +
+                                            o3 * (xyz[el[4] * 3 + i] - x0);
+                        if (std::fabs(xyz[el[a] * 3 + i] - pred) > 1e-12 * scale) aff = false;
+                    }
+                }
+            }
             if (npe == 4) {
                 double J[3][3];
                 for (int c = 0; c < 3; ++c)
@@ -225,10 +246,12 @@ void check_geometry(int64_t E, int npe, const int32_t* conn, const double* xyz) 
                 return;
             }
         }
+        if (!aff) affine.store(false);
     });
     if (bad.load() >= 0)
         throw Error{RAFEM_E_MESH, "element " + std::to_string(bad.load()) +
                                       " has a non-positive Jacobian determinant"};
+    return affine.load();
 }
 
 }  // namespace rafem

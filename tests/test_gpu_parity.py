@@ -34,13 +34,20 @@ def _mesh(R, p):
     return R.Mesh(p.xyz, p.conn, p.dir_ids)
 
 
-CASES = [("hex", 5), ("hex", 21), ("hex", 26), ("tet", 6), ("tet", 17)]
+# "hexj": hexes with jittered interior nodes, i.e. general trilinear (non-affine) elements
+CASES = [("hex", 5), ("hex", 21), ("hex", 26), ("hexj", 11), ("tet", 6), ("tet", 17)]
+
+
+def _problem(kind, n, seed, **kw):
+    if kind == "hexj":
+        return ri.make_problem("hex", n, seed, jitter=True, name=f"hexj{n}", **kw)
+    return ri.make_problem(kind, n, seed, **kw)
 
 
 @pytest.mark.parametrize("kind,n", CASES)
 def test_structure_and_assembly_match_oracle(R, kind, n):
     import torch
-    p = ri.make_problem(kind, n, 1)
+    p = _problem(kind, n, 1)
     m = Model(p)
     mesh = _mesh(R, p)
     # bioheat-type coefficients: mass and stiffness, no lifting
@@ -80,7 +87,7 @@ def test_structure_and_assembly_match_oracle(R, kind, n):
 @pytest.mark.parametrize("kind,n", CASES)
 def test_spmv_matches_oracle(R, kind, n):
     import torch
-    p = ri.make_problem(kind, n, 2)
+    p = _problem(kind, n, 2)
     m = Model(p)
     mesh = _mesh(R, p)
     vals = m.S.assemble(m.Ke, m.Me, p.rho_c / p.dt + p.perf_e, p.k_e)
@@ -139,11 +146,12 @@ def test_solve_matches_oracle(R, kind, n, precision):
     mesh.close()
 
 
-@pytest.mark.parametrize("kind,n,steps", [("hex", 21, 3), ("tet", 13, 2), ("hex", 9, 2)])
+@pytest.mark.parametrize("kind,n,steps", [("hex", 21, 3), ("tet", 13, 2), ("hex", 9, 2),
+                                          ("hexj", 11, 2)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_coupled_steps_match_oracle(R, kind, n, steps, precision):
     from paper_2409_13036_amd.sim import DeviceProblem
-    p = ri.make_problem(kind, n, 5, steps=steps)
+    p = _problem(kind, n, 5, steps=steps)
     m = Model(p)
     ref_states, _ = m.simulate(steps, 1e-15)
     dp = DeviceProblem(p)
