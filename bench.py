@@ -89,17 +89,17 @@ def cpu_baseline(n: int) -> dict:
             "host_cpus": len(os.sched_getaffinity(0))}
 
 
-def run_path(dp, precision: str, steps: int, warmup: int, profile_steps: int):
+def run_path(dp, precision: str, steps: int, warmup: int, profile_steps: int, **kw):
     import torch
     from paper_2409_13036_amd import _lib as R
     dp.reset()
     for _ in range(warmup):
-        dp.step(TOL, precision)
+        dp.step(TOL, precision, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
     for _ in range(steps):
-        infos.append(dp.step(TOL, precision))
+        infos.append(dp.step(TOL, precision, **kw))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     T_end, V_end = dp.T.clone(), dp.V.clone()
@@ -107,11 +107,89 @@ def run_path(dp, precision: str, steps: int, warmup: int, profile_steps: int):
     R.profile_enable(dp.mesh, True)
     R.profile_read(dp.mesh, precision, reset=True)
     for _ in range(profile_steps):
-        dp.step(TOL, precision)
+        dp.step(TOL, precision, **kw)
     torch.cuda.synchronize()
     mean_us, count = R.profile_read(dp.mesh, precision, reset=True)
     R.profile_enable(dp.mesh, False)
     return elapsed, infos, (T_end, V_end), (mean_us, count)
+
+
+def adjoint_leg(args) -> dict:
+    """Differentiation workload: 101^3 hex, 60 coupled steps, lesion loss, gradients with respect
+    to k_e and w_e by the reverse sweep (checkpoints every 10 steps), timed; then central
+    finite differences (relative step 1e-6) on 32 single parameters drawn from the 1% of
+    elements with the largest adjoint gradients (16 k_e, 16 w_e) and along the two directions
+    k and w (all entries scaled), forward solves at tol 1e-14."""
+    import numpy as np
+    import torch
+    import rafem_inputs as ri
+    from paper_2409_13036_amd.adjoint import lesion_loss
+    from paper_2409_13036_amd.sim import DeviceProblem
+
+    tol = 1e-14
+    p = ri.config3(n=args.n, steps=args.adj_steps)
+    dp = DeviceProblem(p)
+    dev = dp.dev
+    k = torch.tensor(p.k_e, dtype=torch.float64, device=dev, requires_grad=True)
+    w = torch.tensor(p.perf_e, dtype=torch.float64, device=dev, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = lesion_loss(dp, k, w, p.steps, checkpoint_every=10, tol=tol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    gk, gw = k.grad.cpu().numpy(), w.grad.cpu().numpy()
+    rng = np.random.default_rng(0)
+    # single parameters where the sensitivity is large: the 1% largest |dL/dk_e| and |dL/dw_e|
+    top_k = np.argsort(-np.abs(gk))[: p.n_elems // 100]
+    top_w = np.argsort(-np.abs(gw))[: p.n_elems // 100]
+    picks = [("k", int(e)) for e in rng.choice(top_k, args.fd_params // 2, replace=False)]
+    picks += [("w", int(e)) for e in rng.choice(top_w, args.fd_params - args.fd_params // 2,
+                                                 replace=False)]
+
+    def final_T(kk, ww):
+        dp.set_params(torch.as_tensor(kk, device=dev), torch.as_tensor(ww, device=dev))
+        dp.reset()
+        for _ in range(p.steps):
+            dp.step(tol)
+        return dp.T.cpu().numpy()
+
+    ids, tgt = p.loss_ids, p.T_target
+
+    def fd_along(dk, dw, h=1e-6):
+        Tp = final_T(p.k_e + h * dk, p.perf_e + h * dw)
+        Tm = final_T(p.k_e - h * dk, p.perf_e - h * dw)
+        a, b = Tp[ids], Tm[ids]
+        return float(np.sum((a - b) * (a + b - 2 * tgt))) / (2 * h)
+
+    rows = []
+    cases = []
+    for which, e in picks:
+        d = np.zeros(p.n_elems)
+        d[e] = abs((p.k_e if which == "k" else p.perf_e)[e])
+        cases.append((f"{which}[{e}]", d if which == "k" else 0 * d, d if which == "w" else 0 * d,
+                      1e-6))
+    cases.append(("direction k", p.k_e.copy(), 0 * p.k_e, 1e-6))
+    # perfusion moves T by ~1e-9 K at a 1e-6 step (FP64 round-off floor): 1e-3 in its direction
+    cases.append(("direction w", 0 * p.perf_e, p.perf_e.copy(), 1e-3))
+    for name, dk, dw, h in cases:
+        fd = fd_along(dk, dw, h)
+        ad = float(gk @ dk + gw @ dw)
+        rows.append({"param": name, "h": h, "adjoint": ad, "fd": fd,
+                     "rel_err": abs(ad - fd) / abs(fd)})
+        print(f"[adjoint] {name} adjoint {ad:.10e} fd {fd:.10e} rel {rows[-1]['rel_err']:.2e}",
+              file=sys.stderr, flush=True)
+    dp.close()
+    return {"workload": f"C3 adjoint, {args.n}^3 hex, {p.steps} steps, checkpoints every 10",
+            "loss": float(L), "forward_s": t1 - t0, "backward_s": t2 - t1,
+            "fd_checks": len(rows),
+            "fd_max_rel_err_k": max(r["rel_err"] for r in rows if r["param"].startswith("k")),
+            "fd_max_rel_err_directional": max(r["rel_err"] for r in rows
+                                              if r["param"].startswith("direction")),
+            "fd_max_rel_err_w_single": max(r["rel_err"] for r in rows if r["param"].startswith("w")),
+            "fd": rows}
 
 
 def main():
@@ -121,8 +199,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=101)
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="relative tolerance of each FP32 inner solve (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-child", action="store_true")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="run only the differentiation workload (timing + finite-difference check)")
+    ap.add_argument("--adj-steps", type=int, default=60)
+    ap.add_argument("--fd-params", type=int, default=32)
     args = ap.parse_args()
     if args.cpu_baseline_child:
         cpu_baseline_child(args.n)
@@ -131,6 +215,10 @@ def main():
         print(f"bench.py measures one GPU only (the solve is not sharded across GPUs); "
               f"got --gpus {args.gpus}", file=sys.stderr)
         sys.exit(2)
+
+    if args.adjoint:
+        print(json.dumps(adjoint_leg(args)), flush=True)
+        return
 
     # CPU oracle first, before this process touches the GPU
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.n)
@@ -146,8 +234,9 @@ def main():
     N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
     res = {}
     for precision in ("fp64", "mixed"):
+        kw = {"inner_tol": args.inner_tol} if precision == "mixed" else {}
         el, infos, state, (mean_us, count) = run_path(dp, precision, args.steps, args.warmup,
-                                                      args.profile_steps)
+                                                      args.profile_steps, **kw)
         it_v = float(np.mean([i["V"]["iters"] for i in infos]))
         it_t = float(np.mean([i["T"]["iters"] for i in infos]))
         res[precision] = {"elapsed": el, "state": state, "spmv_us": mean_us, "spmv_count": count,

@@ -255,6 +255,39 @@ rafem_status rafem_step(rafem_mesh mesh, const rafem_phys* phys, const double* k
                         const double* dir_V_d, const double* dir_T_d, double* T_d, double* V_d,
                         const rafem_solve_opts* opts, rafem_step_info* info, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Reverse mode: gradients of a loss on the final temperature with respect to the
+ * per-element conductivity k_e and perfusion w_e, by the discrete adjoint of the
+ * steps above run backwards in time (the time loop of Sec. II-A, reversed).
+ * ------------------------------------------------------------------------- */
+
+/* Reverse of one rafem_step.  Given the adjoint load lambda on T^n (dL/dT^n), computes
+ *   A_T mu = lambda (Dirichlet rows zeroed), K_sigma(T^{n-1}) nu = (dF/dV)^T mu,
+ *   grad_k[e] += -mu_e^T K_e T^n_e,  grad_perf[e] += -mu_e^T M_e (T^n_e - T_a),
+ * and overwrites lambda with the adjoint load on T^{n-1}:
+ *   (rho_c/dt) M mu + sum_e (mu_e^T J_e(V^n) - nu_e^T K_e V^n_e) sigma0_e alpha / npe
+ * on the nodes of e (J_e = Joule load at unit conductivity).  Both matrices are
+ * symmetric, so the adjoint solves are PCG solves on the same matrices.
+ *   T_prev_d, V_d, T_d  [n_nodes] device: T^{n-1}, V^n, T^n of the forward step
+ *   lambda_d            [n_nodes] device, in: dL/dT^n; out: dL/dT^{n-1}
+ *   grad_k_d, grad_perf_d [n_elems] device, accumulated (+=)
+ *   other arguments as rafem_step; phys->reuse_bioheat as there; info->T describes the
+ *   mu solve and info->V the nu solve (zero when not coupled). */
+rafem_status rafem_step_vjp(rafem_mesh mesh, const rafem_phys* phys, const double* k_e_d,
+                            const double* perf_e_d, const double* sigma0_e_d,
+                            const double* dir_V_d, const double* dir_T_d, const double* T_prev_d,
+                            const double* V_d, const double* T_d, double* lambda_d,
+                            double* grad_k_d, double* grad_perf_d, const rafem_solve_opts* opts,
+                            rafem_step_info* info, void* stream);
+
+/* Lesion-temperature loss L = scale * sum_k (T[ids[k]] - target[k])^2 and its gradient
+ * grad = dL/dT (2 scale (T - target) on ids, 0 elsewhere), deterministically summed.
+ *   ids_d [n_loss] device node ids (distinct), target_d [n_loss] device
+ *   T_d [n_nodes] device; loss_d [1] device output; grad_d [n_nodes] device output or NULL */
+rafem_status rafem_lesion_loss(rafem_mesh mesh, int64_t n_loss, const int32_t* ids_d,
+                               const double* target_d, const double* T_d, double scale,
+                               double* loss_d, double* grad_d, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

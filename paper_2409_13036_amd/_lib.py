@@ -29,7 +29,7 @@ STATUS_NAMES = {OK: "OK", E_ARG: "E_ARG", E_MESH: "E_MESH", E_NOCONV: "E_NOCONV"
 EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafem_colour_elements",
            "rafem_mesh_create", "rafem_mesh_destroy", "rafem_mesh_get_stats", "rafem_assemble_csr",
            "rafem_solve", "rafem_solve_adjoint", "rafem_spmv", "rafem_profile_enable",
-           "rafem_profile_read", "rafem_step")
+           "rafem_profile_read", "rafem_step", "rafem_step_vjp", "rafem_lesion_loss")
 
 
 class RafemError(RuntimeError):
@@ -84,6 +84,9 @@ _lib.rafem_profile_enable.argtypes = [_p, _i32]
 _lib.rafem_profile_read.argtypes = [_p, _i32, C.POINTER(C.c_double), C.POINTER(C.c_int64), _i32]
 _lib.rafem_step.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts),
                             C.POINTER(StepInfo), _p]
+_lib.rafem_step_vjp.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
+                                C.POINTER(SolveOpts), C.POINTER(StepInfo), _p]
+_lib.rafem_lesion_loss.argtypes = [_p, _i64, _p, _p, _p, C.c_double, _p, _p, _p]
 for _name in EXPORTS:
     if _name not in ("rafem_last_error", "rafem_abi_version"):
         getattr(_lib, _name).restype = C.c_int32
@@ -336,3 +339,44 @@ def step(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T, V, *, t
     if check:
         _check(st)
     return {"status": st, "V": info.V.as_dict(), "T": info.T.as_dict()}
+
+
+def step_vjp(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T_prev, V, T, lam, grad_k,
+             grad_perf, *, tol=1e-12, precision="fp64", maxit=0, inner_tol=0.0, max_outer=0,
+             poll_every=0, stream=None, check=True):
+    """rafem_step_vjp: reverse of one step.  lam in: dL/dT^n, out: dL/dT^{n-1}; grads accumulate."""
+    torch = _torch()
+    E, n = mesh.n_elems, mesh.n_nodes
+    k_e = _dev(k_e, torch.float64, E, "k_e")
+    perf_e = _dev(perf_e, torch.float64, E, "perf_e")
+    sigma0_e = _dev(sigma0_e, torch.float64, E, "sigma0_e", allow_none=not phys.coupled)
+    dir_V = _dev(dir_V, torch.float64, mesh.n_dir, "dir_V", allow_none=not phys.coupled)
+    dir_T = _dev(dir_T, torch.float64, mesh.n_dir, "dir_T")
+    T_prev = _dev(T_prev, torch.float64, n, "T_prev", allow_none=not phys.coupled)
+    V = _dev(V, torch.float64, n, "V", allow_none=not phys.coupled)
+    T = _dev(T, torch.float64, n, "T")
+    lam = _dev(lam, torch.float64, n, "lambda")
+    grad_k = _dev(grad_k, torch.float64, E, "grad_k")
+    grad_perf = _dev(grad_perf, torch.float64, E, "grad_perf")
+    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every)
+    info = StepInfo()
+    st = _lib.rafem_step_vjp(mesh.handle, C.byref(phys), _ptr(k_e), _ptr(perf_e), _ptr(sigma0_e),
+                             _ptr(dir_V), _ptr(dir_T), _ptr(T_prev), _ptr(V), _ptr(T), _ptr(lam),
+                             _ptr(grad_k), _ptr(grad_perf), C.byref(opts), C.byref(info),
+                             _stream(stream))
+    if check:
+        _check(st)
+    return {"status": st, "V": info.V.as_dict(), "T": info.T.as_dict()}
+
+
+def lesion_loss(mesh: Mesh, ids, target, T, *, scale=1.0, grad=None, stream=None):
+    """rafem_lesion_loss -> loss as a 1-element device tensor; grad (if given) = dL/dT."""
+    torch = _torch()
+    ids = _dev(ids, torch.int32, None, "ids")
+    target = _dev(target, torch.float64, ids.numel(), "target")
+    T = _dev(T, torch.float64, mesh.n_nodes, "T")
+    grad = _dev(grad, torch.float64, mesh.n_nodes, "grad", allow_none=True)
+    out = torch.empty(1, dtype=torch.float64, device=T.device)
+    _check(_lib.rafem_lesion_loss(mesh.handle, ids.numel(), _ptr(ids), _ptr(target), _ptr(T),
+                                  float(scale), _ptr(out), _ptr(grad), _stream(stream)))
+    return out

@@ -127,6 +127,27 @@ void assemble_into(rafem_mesh m, const Layout& L, int64_t count, const double* m
     }
 }
 
+// Bioheat matrix sum_e (rho_c/dt + w_e) M_e + k_e K_e, lifted with the values in m->gT.
+void assemble_bioheat(rafem_mesh m, const rafem_phys* phys, const double* k_e,
+                      const double* perf_e, hipStream_t s) {
+    const Layout SL = sell_layout(m);
+    launch_coef(perf_e, phys->rho_c / phys->dt, m->coefT, m->E, s);
+    assemble_into(m, SL, m->sell_nnz, m->coefT, k_e, m->valsT, s);
+    launch_lift((int)m->n, SL, m->valsT, m->valsT32, m->isD, m->gT, m->liftT, m->dinvT,
+                m->dinvT32, m->nD > 0, s);
+    m->bioheat_ready = true;
+}
+
+// Potential matrix K_sigma(T) with sigma from the element means of T, lifted with m->gV.
+void assemble_potential(rafem_mesh m, const rafem_phys* phys, const double* sigma0_e,
+                        const double* T, hipStream_t s) {
+    const Layout SL = sell_layout(m);
+    launch_sigma(m->npe, m->E, m->conn, T, sigma0_e, phys->alpha_sigma, phys->T_ref, m->sigma, s);
+    assemble_into(m, SL, m->sell_nnz, nullptr, m->sigma, m->valsV, s);
+    launch_lift((int)m->n, SL, m->valsV, m->valsV32, m->isD, m->gV, m->liftV, m->dinvV,
+                m->dinvV32, m->nD > 0, s);
+}
+
 void solve_any(rafem_mesh m, const SolveOpts& o, const Mat& A, const double* dinv,
                const float* dinv32, const double* b, double* x, rafem_solve_info* info,
                hipStream_t s, int hint, int* iters) {
@@ -243,6 +264,10 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             m->gT = dalloc<double>(m, N);
             m->gtmp = dalloc<double>(m, N);
             m->sigma = dalloc<double>(m, E);
+            m->adj_mu = dalloc<double>(m, N);
+            m->adj_nu = dalloc<double>(m, N);
+            m->adj_sbar = dalloc<double>(m, E);
+            m->adj_dsig = dalloc<double>(m, E);
             m->coefT = dalloc<double>(m, E);
             m->valsV = dalloc<double>(m, SNNZ);
             m->valsT = dalloc<double>(m, SNNZ);
@@ -269,6 +294,9 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             m->partials = dalloc<double>(m, 3 * (N / 64 + 64));
             m->part_pq = dalloc<double>(m, N / 64 + 64);
             m->part_rz = dalloc<double>(m, 2 * (N / 64 + 64));
+            m->part_rz2 = dalloc<double>(m, 2 * (N / 64 + 64));
+            m->s32 = dalloc<float>(m, N);
+            m->z32 = dalloc<float>(m, N);
             m->st = dalloc<PcgState>(m, 3);
             if (hipHostMalloc((void**)&m->st_host, 3 * sizeof(PcgState), hipHostMallocDefault) !=
                 hipSuccess) {
@@ -481,22 +509,11 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
         rafem_step_info& inf = info ? *info : local;
         std::memset(&inf, 0, sizeof(inf));
 
-        const Layout SL = sell_layout(m);
         launch_scatter_dirichlet(m->dir_ids, dir_T_d, m->nD, m->gT, s);
-        if (!phys->reuse_bioheat) {
-            launch_coef(perf_e_d, phys->rho_c / phys->dt, m->coefT, m->E, s);
-            assemble_into(m, SL, m->sell_nnz, m->coefT, k_e_d, m->valsT, s);
-            launch_lift((int)m->n, SL, m->valsT, m->valsT32, m->isD, m->gT, m->liftT, m->dinvT,
-                        m->dinvT32, m->nD > 0, s);
-            m->bioheat_ready = true;
-        }
+        if (!phys->reuse_bioheat) assemble_bioheat(m, phys, k_e_d, perf_e_d, s);
         if (phys->coupled) {
             launch_scatter_dirichlet(m->dir_ids, dir_V_d, m->nD, m->gV, s);
-            launch_sigma(m->npe, m->E, m->conn, T_d, sigma0_e_d, phys->alpha_sigma, phys->T_ref,
-                         m->sigma, s);
-            assemble_into(m, SL, m->sell_nnz, nullptr, m->sigma, m->valsV, s);
-            launch_lift((int)m->n, SL, m->valsV, m->valsV32, m->isD, m->gV, m->liftV, m->dinvV,
-                        m->dinvV32, m->nD > 0, s);
+            assemble_potential(m, phys, sigma0_e_d, T_d, s);
             launch_set_dirichlet(m->dir_ids, m->gV, m->nD, V_d, s);
             RAFEM_HIP(hipGetLastError());
             int it = 0;
@@ -527,6 +544,98 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
             set_error("bioheat solve failed");
             return inf.T.status;
         }
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_step_vjp(rafem_mesh m, const rafem_phys* phys, const double* k_e_d,
+                            const double* perf_e_d, const double* sigma0_e_d,
+                            const double* dir_V_d, const double* dir_T_d, const double* T_prev_d,
+                            const double* V_d, const double* T_d, double* lambda_d,
+                            double* grad_k_d, double* grad_perf_d, const rafem_solve_opts* opts,
+                            rafem_step_info* info, void* stream) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        require(phys != nullptr, "phys is NULL");
+        require(k_e_d && perf_e_d && T_d && lambda_d && grad_k_d && grad_perf_d,
+                "NULL k, perfusion, T, lambda or gradient");
+        require(m->nD == 0 || dir_T_d != nullptr, "dir_T is NULL");
+        require(phys->dt > 0.0 && std::isfinite(phys->dt), "dt must be > 0");
+        if (phys->coupled) {
+            require(sigma0_e_d && V_d && T_prev_d, "coupled reverse step needs sigma0, V and T_prev");
+            require(m->nD == 0 || dir_V_d != nullptr, "dir_V is NULL");
+        }
+        if (phys->reuse_bioheat && !m->bioheat_ready)
+            throw Error{RAFEM_E_STATE, "reuse_bioheat set but no bioheat matrix has been assembled"};
+        SolveOpts o = resolve_opts(opts, 1e-12);
+        hipStream_t s = (hipStream_t)stream;
+        rafem_step_info local{};
+        rafem_step_info& inf = info ? *info : local;
+        std::memset(&inf, 0, sizeof(inf));
+        const int npe = m->npe, aff = m->affine;
+
+        launch_scatter_dirichlet(m->dir_ids, dir_T_d, m->nD, m->gT, s);
+        if (!phys->reuse_bioheat) assemble_bioheat(m, phys, k_e_d, perf_e_d, s);
+        // mu: A_T mu = lambda with the Dirichlet rows of the load zeroed
+        launch_fill(m->gtmp, m->n, 0.0, s);
+        RAFEM_HIP(hipMemcpyAsync(m->bT, lambda_d, m->n * 8, hipMemcpyDeviceToDevice, s));
+        launch_set_dirichlet(m->dir_ids, m->gtmp, m->nD, m->bT, s);
+        launch_fill(m->adj_mu, m->n, 0.0, s);
+        RAFEM_HIP(hipGetLastError());
+        solve_any(m, o, step_matrix(m, m->valsT, m->valsT32), m->dinvT, m->dinvT32, m->bT,
+                  m->adj_mu, &inf.T, s, 0, nullptr);
+        if (inf.T.status != RAFEM_OK) {
+            set_error("adjoint bioheat solve failed");
+            return inf.T.status;
+        }
+        launch_vjp_params(npe, aff, m->E, m->conn, m->xyz, m->adj_mu, T_d, phys->T_a, grad_k_d,
+                          grad_perf_d, s);
+        const double* dsig = nullptr;
+        if (phys->coupled) {
+            launch_scatter_dirichlet(m->dir_ids, dir_V_d, m->nD, m->gV, s);
+            assemble_potential(m, phys, sigma0_e_d, T_prev_d, s);
+            launch_fill(m->rhs, m->n, 0.0, s);
+            for (int c = 0; c < m->n_colours; ++c) {
+                const int off = m->colour_off[c], cnt = m->colour_off[c + 1] - off;
+                launch_vjp_joule_colour(npe, aff, m->colour_elems + off, cnt, m->conn, m->xyz, V_d,
+                                        m->adj_mu, m->sigma, m->rhs, m->adj_sbar, s);
+            }
+            launch_set_dirichlet(m->dir_ids, m->gtmp, m->nD, m->rhs, s);
+            launch_fill(m->adj_nu, m->n, 0.0, s);
+            RAFEM_HIP(hipGetLastError());
+            solve_any(m, o, step_matrix(m, m->valsV, m->valsV32), m->dinvV, m->dinvV32, m->rhs,
+                      m->adj_nu, &inf.V, s, 0, nullptr);
+            if (inf.V.status != RAFEM_OK) {
+                set_error("adjoint potential solve failed");
+                return inf.V.status;
+            }
+            launch_vjp_sigma(npe, aff, m->E, m->conn, m->xyz, m->adj_nu, V_d, m->adj_sbar,
+                             sigma0_e_d, phys->alpha_sigma, m->adj_dsig, s);
+            dsig = m->adj_dsig;
+        }
+        launch_fill(lambda_d, m->n, 0.0, s);
+        for (int c = 0; c < m->n_colours; ++c) {
+            const int off = m->colour_off[c], cnt = m->colour_off[c + 1] - off;
+            launch_vjp_lambda_colour(npe, aff, m->colour_elems + off, cnt, m->conn, m->xyz,
+                                     m->adj_mu, dsig, phys->rho_c / phys->dt, lambda_d, s);
+        }
+        RAFEM_HIP(hipGetLastError());
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_lesion_loss(rafem_mesh m, int64_t n_loss, const int32_t* ids_d,
+                               const double* target_d, const double* T_d, double scale,
+                               double* loss_d, double* grad_d, void* stream) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        require(n_loss >= 0 && n_loss <= m->n, "n_loss out of range");
+        require(T_d && loss_d && (n_loss == 0 || (ids_d && target_d)), "NULL argument");
+        hipStream_t s = (hipStream_t)stream;
+        double* grad = grad_d ? grad_d : m->gtmp;
+        launch_fill(grad, m->n, 0.0, s);
+        launch_loss(n_loss, ids_d, target_d, T_d, scale, grad, m->partials, loss_d, s);
+        RAFEM_HIP(hipGetLastError());
         return RAFEM_OK;
     });
 }

@@ -71,6 +71,7 @@ struct PcgState {
     double tol2;     // tol^2 * bb: stop when rr <= tol2
     double scale;    // mixed refinement: 1 / ||r_outer||
     double rr_first; // ||r||^2 at the start of this solve
+    double alpha_slots[2];  // single-reduction inner solve: alpha of iteration i in slot i&1
     int32_t iters;
     int32_t maxit;
     int32_t done;
@@ -157,6 +158,14 @@ void launch_spmv32(const Mat& A, const SpmvConfig& c, const float* x, float* y, 
 // Mixed outer test: done when rr <= tol2 (tol2 = tol^2 bb set here), scale = 1/||r||.
 void launch_residual64(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
                        double* r, double* partials, PcgState* st, int outer_mode, hipStream_t s);
+// Inner FP32 iteration in the single-reduction (Chronopoulos-Gear) form: after
+// launch_spmv_dot32(z -> w) this kernel updates p, s, x, r, z.  gam_in holds the partials
+// of r.z and r.r of the current residual (buffer it&1, from k_inner_start at it = 0);
+// gam_out receives the next ones.  Returns its grid size.
+int launch_cg_update32(int n, float* x, float* r, float* z, const float* w, float* p, float* sv,
+                       const float* dinv, const double* delta_part, int nb_delta,
+                       const double* gam_in, double* gam_out, int it, PcgState* st,
+                       hipStream_t s);
 // Mixed inner start: r32 = scale * r64; d32 = 0; p32 = D^-1 r32; rz, rr into inner state.
 void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,
                         float* p32, const float* dinv32, double inner_tol, int maxit,
@@ -193,6 +202,22 @@ void launch_bioheat_rhs_colour(int npe, int affine, const int32_t* elems, int co
                                const double* V, const double* sigma, const double* perf,
                                double rho_c_dt, double T_a, int with_joule, double* rhs,
                                hipStream_t s);
+// Reverse step of the coupled time step (adjoint.hip).
+void launch_vjp_params(int npe, int affine, int64_t E, const int32_t* conn, const double* xyz,
+                       const double* mu, const double* Tn, double T_a, double* grad_k,
+                       double* grad_w, hipStream_t s);
+void launch_vjp_joule_colour(int npe, int affine, const int32_t* elems, int count,
+                             const int32_t* conn, const double* xyz, const double* V,
+                             const double* mu, const double* sigma, double* nubar, double* sbar1,
+                             hipStream_t s);
+void launch_vjp_sigma(int npe, int affine, int64_t E, const int32_t* conn, const double* xyz,
+                      const double* nu, const double* V, const double* sbar1,
+                      const double* sigma0, double alpha, double* dsig, hipStream_t s);
+void launch_vjp_lambda_colour(int npe, int affine, const int32_t* elems, int count,
+                              const int32_t* conn, const double* xyz, const double* mu,
+                              const double* dsig, double rho_c_dt, double* lam, hipStream_t s);
+void launch_loss(int64_t n, const int32_t* ids, const double* target, const double* T,
+                 double scale, double* grad, double* partials, double* loss, hipStream_t s);
 // b = isD ? lift : rhs + lift
 void launch_finish_rhs(int n, const double* rhs, const double* lift, const uint8_t* isD,
                        double* b, hipStream_t s);
@@ -233,6 +258,7 @@ struct rafem_mesh_s {
     float *valsV32 = nullptr, *valsT32 = nullptr, *dinvV32 = nullptr, *dinvT32 = nullptr;
     double *rhs = nullptr, *bT = nullptr, *gtmp = nullptr, *coefT = nullptr;
     bool bioheat_ready = false;
+    double *adj_mu = nullptr, *adj_nu = nullptr, *adj_sbar = nullptr, *adj_dsig = nullptr;
     int hint_V = 0, hint_T = 0;  // iterations of the previous FP64 solves, first-chunk guess
 
     // solver workspace
@@ -241,6 +267,8 @@ struct rafem_mesh_s {
     double* partials = nullptr;   // once-per-solve reductions
     double* part_pq = nullptr;    // per-iteration partials of p.Ap
     double* part_rz = nullptr;    // per-iteration partials of r.z and r.r
+    double* part_rz2 = nullptr;   // second parity buffer of the single-reduction inner solve
+    float *s32 = nullptr, *z32 = nullptr;
     rafem::PcgState* st = nullptr;      // device [3]: main/inner, outer, check
     rafem::PcgState* st_host = nullptr; // pinned host [3]
 

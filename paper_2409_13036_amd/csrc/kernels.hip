@@ -19,85 +19,14 @@
 
 #include <cmath>
 
+#include "fem_device.hpp"
 #include "internal.hpp"
 
 namespace rafem {
 namespace {
 
-constexpr int WG = 256;
-constexpr int WAVE = 64;
-constexpr int NWAVES = WG / WAVE;
-constexpr int NXCD = 8;
+using namespace dev;
 
-// Workgroups are dispatched round-robin over the XCDs; give XCD x the x-th contiguous
-// share of the logical block indices.
-__device__ __forceinline__ int xcd_block(int bid, int nb) {
-    const int xcd = bid % NXCD, idx = bid / NXCD;
-    const int q = nb / NXCD, r = nb % NXCD;
-    return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return v;
-}
-
-// Sum K values over the block in a fixed order; result in thread 0.
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K]) {
-    __shared__ double lds[K][NWAVES];
-    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        v[k] = wave_sum(v[k]);
-        if (lane == 0) lds[k][w] = v[k];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double s = 0.0;
-            for (int j = 0; j < NWAVES; ++j) s += lds[k][j];
-            v[k] = s;
-        }
-    }
-}
-
-__device__ __forceinline__ bool finite(double x) { return isfinite(x); }
-
-// Store this block's K sums as partials (no synchronisation with other blocks).
-template <int K>
-__device__ __forceinline__ void store_partials(double (&v)[K], double* partials, int slot,
-                                               int nb) {
-    block_sum<K>(v);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) partials[k * nb + slot] = v[k];
-    }
-}
-
-// Totals of the K partial arrays written by the previous kernel, in a fixed order that
-// does not depend on the calling block; the result is returned to every thread.
-template <int K>
-__device__ __forceinline__ void grid_totals(const double* __restrict__ partials, int nb,
-                                            double (&tot)[K]) {
-    __shared__ double bcast[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nb; i += WG) s += partials[k * nb + i];
-        tot[k] = s;
-    }
-    block_sum<K>(tot);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) bcast[k] = tot[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) tot[k] = bcast[k];
-}
 
 // ---------------------------------------------------------------------------
 // Solver state
@@ -109,6 +38,7 @@ __global__ void k_state_init(PcgState* st, double tol, int maxit) {
         st->tol2 = 0.0;
         st->scale = 1.0;
         st->rr_first = 0.0;
+        st->alpha_slots[0] = st->alpha_slots[1] = 0.0;
         st->iters = 0;
         st->maxit = maxit;
         st->done = 0;
@@ -478,6 +408,104 @@ __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
     }
 }
 
+// Inner FP32 solve in the Chronopoulos-Gear form of Jacobi-PCG: one SpMV (w = A z, with
+// partials of delta = z.w) and this one fused vector kernel per iteration, with s = A p
+// carried by recurrence.  Iteration i holds z_i = D^-1 r_i, w_i = A z_i, and reads
+//   gamma_i = r_i.z_i, rr_i = r_i.r_i  (partials of the previous kernel, buffer i&1),
+//   delta_i = z_i.w_i                  (partials of this iteration's SpMV);
+// stops when rr_i <= tol2, else
+//   beta_i = gamma_i / gamma_{i-1} (0 at i = 0),  alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
+//   p = z + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,  z = D^-1 r,
+// and writes the partials of gamma_{i+1}, rr_{i+1} into buffer (i+1)&1.  gamma and alpha
+// of iteration i are kept in state slots i&1 (read back at i+1 from slot (i-1)&1).
+template <typename T>
+__global__ __launch_bounds__(WG) void k_cg_update(int n, T* __restrict__ x, T* __restrict__ r,
+                                                  T* __restrict__ z, const T* __restrict__ w,
+                                                  T* __restrict__ p, T* __restrict__ sv,
+                                                  const T* __restrict__ dinv,
+                                                  const double* __restrict__ delta_part,
+                                                  int nb_delta,
+                                                  const double* __restrict__ gam_in,
+                                                  double* __restrict__ gam_out, int it,
+                                                  PcgState* st) {
+    if (st->done) return;
+    const int nb = gridDim.x;
+    const int blk = xcd_block(blockIdx.x, nb);
+    const int i0 = blk * kVecRowsPerBlock + threadIdx.x;
+    T xv[VPT], rv[VPT], zv[VPT], wv[VPT], pv[VPT], sv_[VPT], dv[VPT];
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+        const int i = i0 + j * WG;
+        if (i < n) {
+            xv[j] = x[i];
+            rv[j] = r[i];
+            zv[j] = z[i];
+            wv[j] = w[i];
+            dv[j] = dinv[i];
+            if (it > 0) {
+                pv[j] = p[i];
+                sv_[j] = sv[i];
+            }
+        }
+    }
+    double dl[1], gr[2];
+    grid_totals<1>(delta_part, nb_delta, dl);
+    grid_totals<2>(gam_in, nb, gr);
+    const double gamma = gr[0], rr = gr[1], delta = dl[0];
+    const bool writer = blk == 0 && threadIdx.x == 0;
+    int status = -1;
+    if (!finite(gamma) || !finite(rr) || gamma < 0.0) status = RAFEM_E_BREAKDOWN;
+    else if (rr <= st->tol2) status = RAFEM_OK;
+    else if (it >= st->maxit) status = RAFEM_E_NOCONV;
+    double beta = 0.0, alpha = 0.0;
+    if (status < 0) {
+        double denom = delta;
+        if (it > 0) {
+            beta = gamma / st->rzs[(it - 1) & 1];
+            denom = delta - beta * gamma / st->alpha_slots[(it - 1) & 1];
+        }
+        if (!(denom > 0.0) || !finite(denom)) status = RAFEM_E_BREAKDOWN;
+        else alpha = gamma / denom;
+    }
+    if (status >= 0) {
+        if (writer) {
+            st->rr = rr;
+            st->iters = it;
+            st->status = status;
+            st->done = 1;
+        }
+        return;
+    }
+    const T a = (T)alpha, b = (T)beta;
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+        const int i = i0 + j * WG;
+        if (i < n) {
+            const T pn = it > 0 ? zv[j] + b * pv[j] : zv[j];
+            const T sn = it > 0 ? wv[j] + b * sv_[j] : wv[j];
+            const T xn = xv[j] + a * pn;
+            const T rn = rv[j] - a * sn;
+            const T zn = dv[j] * rn;
+            p[i] = pn;
+            sv[i] = sn;
+            x[i] = xn;
+            r[i] = rn;
+            z[i] = zn;
+            acc[0] += (double)rn * (double)zn;
+            acc[1] += (double)rn * (double)rn;
+        }
+    }
+    store_partials<2>(acc, gam_out, blk, nb);
+    if (writer) {
+        st->rzs[it & 1] = gamma;
+        st->alpha_slots[it & 1] = alpha;
+        st->rr = rr;
+        st->beta = beta;
+        st->iters = it;
+    }
+}
+
 // Mixed refinement: inner right-hand side r32 = r64 / ||r64||, d32 = 0, p32 = D^-1 r32.
 __global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restrict__ r64,
                                                     const PcgState* outer,
@@ -486,6 +514,8 @@ __global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restr
                                                     float* __restrict__ p32,
                                                     const float* __restrict__ dinv32,
                                                     double* partials) {
+    // p32 receives z_0 = D^-1 r_0 (the first search direction, and the z of the
+    // single-reduction form)
     const bool skip = outer->done != 0;
     const double scale = outer->scale;
     const int nb = gridDim.x;
@@ -583,215 +613,6 @@ __global__ void k_set_dirichlet(const int* __restrict__ ids, const double* __res
                                 int64_t nD, double* __restrict__ x) {
     const int64_t k = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (k < nD) x[ids[k]] = gnode[ids[k]];
-}
-
-// Entries of row r: positions start + j * stride, j < len (CSR: stride 1; SELL: 64).
-__device__ __forceinline__ void row_span(const Layout& L, int r, int& start, int& len,
-                                         int& stride) {
-    if (L.sell) {
-        start = L.sptr[r / WAVE] + (r % WAVE);
-        len = L.rlen[r];
-        stride = WAVE;
-    } else {
-        start = L.rp[r];
-        len = L.rp[r + 1] - start;
-        stride = 1;
-    }
-}
-
-// Position of column `col` in a row's ascending column list.
-__device__ __forceinline__ int find_slot(const int* __restrict__ cols, int start, int len,
-                                         int stride, int col) {
-    int lo = 0, hi = len;
-    while (lo < hi) {
-        const int m = (lo + hi) >> 1;
-        if (cols[start + m * stride] < col) lo = m + 1;
-        else hi = m;
-    }
-    return start + lo * stride;
-}
-
-// Reference-cube corner signs of hex local node a in the ABI order
-// (0,0,0),(1,0,0),(1,1,0),(0,1,0),(0,0,1),(1,0,1),(1,1,1),(0,1,1).
-__device__ __forceinline__ double hsx(int a) { return ((a + 1) & 2) ? 1.0 : -1.0; }
-__device__ __forceinline__ double hsy(int a) { return (a & 2) ? 1.0 : -1.0; }
-__device__ __forceinline__ double hsz(int a) { return (a & 4) ? 1.0 : -1.0; }
-
-// Trilinear shape function b and its reference gradient at (xi, et, ze).
-__device__ __forceinline__ void hex_shape(int b, double xi, double et, double ze, double& N,
-                                          double& d0, double& d1, double& d2) {
-    const double sx = hsx(b), sy = hsy(b), sz = hsz(b);
-    const double f0 = 1.0 + sx * xi, f1 = 1.0 + sy * et, f2 = 1.0 + sz * ze;
-    N = 0.125 * f0 * f1 * f2;
-    d0 = 0.125 * sx * f1 * f2;
-    d1 = 0.125 * sy * f0 * f2;
-    d2 = 0.125 * sz * f0 * f1;
-}
-
-// J[i][d] = dx_i/dxi_d at a Gauss point; returns det and Jinv[d][i] = dxi_d/dx_i.
-__device__ __forceinline__ double hex_jacobian(const double (&X)[8][3], double xi, double et,
-                                               double ze, double (&Ji)[3][3]) {
-    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        double N, d0, d1, d2;
-        hex_shape(b, xi, et, ze, N, d0, d1, d2);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            J[i][0] += X[b][i] * d0;
-            J[i][1] += X[b][i] * d1;
-            J[i][2] += X[b][i] * d2;
-        }
-    }
-    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-    const double id = 1.0 / det;
-    // inverse of J: (J^-1)[d][i]
-    Ji[0][0] = c00 * id;
-    Ji[1][0] = c01 * id;
-    Ji[2][0] = c02 * id;
-    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
-    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
-    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
-    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
-    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
-    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
-    return det;
-}
-
-__device__ __forceinline__ void grad_x(const double (&Ji)[3][3], double d0, double d1, double d2,
-                                       double (&g)[3]) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) g[i] = Ji[0][i] * d0 + Ji[1][i] * d1 + Ji[2][i] * d2;
-}
-
-constexpr double kGauss = 0.57735026918962576451;  // 1/sqrt(3)
-
-__device__ __forceinline__ void gauss_point(int q, double& xi, double& et, double& ze) {
-    xi = (q & 1) ? kGauss : -kGauss;
-    et = (q & 2) ? kGauss : -kGauss;
-    ze = (q & 4) ? kGauss : -kGauss;
-}
-
-// Row a of the stiffness and mass of hex element with corner coordinates X.
-__device__ void hex_rows(const double (&X)[8][3], int a, double (&Kr)[8], double (&Mr)[8]) {
-#pragma unroll
-    for (int b = 0; b < 8; ++b) Kr[b] = Mr[b] = 0.0;
-    for (int q = 0; q < 8; ++q) {
-        double xi, et, ze;
-        gauss_point(q, xi, et, ze);
-        double Ji[3][3];
-        const double det = hex_jacobian(X, xi, et, ze, Ji);
-        double Na, a0, a1, a2, ga[3];
-        hex_shape(a, xi, et, ze, Na, a0, a1, a2);
-        grad_x(Ji, a0, a1, a2, ga);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            double Nb, b0, b1, b2, gb[3];
-            hex_shape(b, xi, et, ze, Nb, b0, b1, b2);
-            grad_x(Ji, b0, b1, b2, gb);
-            Kr[b] += det * (ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2]);
-            Mr[b] += det * Na * Nb;
-        }
-    }
-}
-
-// Parallelepiped (affine) hex: constant Jacobian J = [x1-x0, x3-x0, x4-x0] / 2.  With
-// C = detJ J^-1 J^-T the stiffness is K_ab = sum_de C_de I_ab^de, where the reference
-// integrals of products of trilinear shape-function derivatives factor per axis:
-//   I_ab^dd = (s_ad s_bd / 64) 2 p_e p_f,   I_ab^de = (s_ad s_be / 64) 4 p_f  (d != e),
-// p_k = 2 + (2/3) s_ak s_bk, s = corner signs; and M_ab = detJ p_0 p_1 p_2 / 64.  These
-// are the exact integrals, which the 2x2x2 Gauss rule reproduces on affine elements.
-__device__ __forceinline__ double hex_affine_jacobian(const double (&X)[8][3],
-                                                      double (&Ji)[3][3]) {
-    double J[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        J[i][0] = 0.5 * (X[1][i] - X[0][i]);
-        J[i][1] = 0.5 * (X[3][i] - X[0][i]);
-        J[i][2] = 0.5 * (X[4][i] - X[0][i]);
-    }
-    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-    const double id = 1.0 / det;
-    Ji[0][0] = c00 * id;
-    Ji[1][0] = c01 * id;
-    Ji[2][0] = c02 * id;
-    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
-    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
-    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
-    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
-    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
-    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
-    return det;
-}
-
-__device__ void hex_rows_affine(const double (&X)[8][3], int a, double (&Kr)[8],
-                                double (&Mr)[8]) {
-    double Ji[3][3];
-    const double det = hex_affine_jacobian(X, Ji);
-    double C[3][3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int e = 0; e < 3; ++e)
-            C[d][e] = det * (Ji[d][0] * Ji[e][0] + Ji[d][1] * Ji[e][1] + Ji[d][2] * Ji[e][2]);
-    const double sa[3] = {hsx(a), hsy(a), hsz(a)};
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const double sb[3] = {hsx(b), hsy(b), hsz(b)};
-        double pk[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) pk[k] = 2.0 + (2.0 / 3.0) * sa[k] * sb[k];
-        double k_ab = 0.0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-#pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                double I;
-                if (d == e) {
-                    I = sa[d] * sb[d] * (1.0 / 32.0) * pk[(d + 1) % 3] * pk[(d + 2) % 3];
-                } else {
-                    const int f = 3 - d - e;
-                    I = sa[d] * sb[e] * (1.0 / 16.0) * pk[f];
-                }
-                k_ab += C[d][e] * I;
-            }
-        }
-        Kr[b] = k_ab;
-        Mr[b] = det * pk[0] * pk[1] * pk[2] * (1.0 / 64.0);
-    }
-}
-
-// Tet: volume and constant gradients of the barycentric coordinates.
-__device__ __forceinline__ double tet_geometry(const double (&X)[4][3], double (&G)[4][3]) {
-    double J[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) J[i][c] = X[c + 1][i] - X[0][i];
-    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-    const double id = 1.0 / det;
-    // rows of J^-1 are the gradients of barycentric coordinates 1..3
-    G[1][0] = c00 * id;
-    G[1][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
-    G[1][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
-    G[2][0] = c01 * id;
-    G[2][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
-    G[2][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
-    G[3][0] = c02 * id;
-    G[3][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
-    G[3][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) G[0][i] = -(G[1][i] + G[2][i] + G[3][i]);
-    return det / 6.0;
 }
 
 // One thread per (element of this colour, local row a): add row a of
@@ -1130,6 +951,16 @@ void launch_pupdate32(int n, float* p, const float* r, const float* dinv, const 
                       int nb_rz, int it, PcgState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_pupdate<float>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv,
                        rz_part, nb_rz, it, st);
+}
+
+int launch_cg_update32(int n, float* x, float* r, float* z, const float* w, float* p, float* sv,
+                       const float* dinv, const double* delta_part, int nb_delta,
+                       const double* gam_in, double* gam_out, int it, PcgState* st,
+                       hipStream_t s) {
+    const int nb = vec_blocks(n);
+    hipLaunchKernelGGL(k_cg_update<float>, dim3(nb), dim3(WG), 0, s, n, x, r, z, w, p, sv, dinv,
+                       delta_part, nb_delta, gam_in, gam_out, it, st);
+    return nb;
 }
 
 void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,

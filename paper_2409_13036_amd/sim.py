@@ -29,16 +29,31 @@ class DeviceProblem:
         self.dir_T = torch.as_tensor(problem.dir_T, **f64).contiguous()
         self.phys = rafem.Phys(problem.rho_c, problem.dt, problem.T_a, problem.alpha_sigma,
                                problem.T_ref, 1 if problem.coupled else 0, 0)
+        self.loss_ids = self.T_target = None
+        if problem.loss_ids is not None:
+            self.loss_ids = torch.as_tensor(problem.loss_ids, dtype=torch.int32, device=self.dev)
+            self.T_target = torch.as_tensor(problem.T_target, **f64).contiguous()
         self.reset()
+
+    def set_params(self, k_e, perf_e):
+        """New conductivity / perfusion fields (device tensors); the bioheat matrix is rebuilt."""
+        self.k_e = k_e.to(self.dev, self.torch.float64).contiguous().clone()
+        self.perf_e = perf_e.to(self.dev, self.torch.float64).contiguous().clone()
+        self.phys.reuse_bioheat = 0
+
+    def restore(self, T, V):
+        """Continue from a saved state (the bioheat matrix is kept)."""
+        self.T.copy_(T)
+        self.V.copy_(V)
 
     def reset(self, T0: Optional[np.ndarray] = None, V0: Optional[np.ndarray] = None):
         torch = self.torch
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.T = torch.as_tensor(self.p.initial_T() if T0 is None else T0, **f64).clone()
         self.V = torch.as_tensor(self.p.initial_V() if V0 is None else V0, **f64).clone()
-        self.phys.reuse_bioheat = 0
 
     def step(self, tol: float = 1e-12, precision: str = "fp64", **kw):
+        """One coupled step (the bioheat matrix is assembled on the first call only)."""
         info = rafem.step(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e, self.dir_V,
                           self.dir_T, self.T, self.V, tol=tol, precision=precision, **kw)
         self.phys.reuse_bioheat = 1
