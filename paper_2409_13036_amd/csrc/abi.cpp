@@ -294,9 +294,6 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             m->partials = dalloc<double>(m, 3 * (N / 64 + 64));
             m->part_pq = dalloc<double>(m, N / 64 + 64);
             m->part_rz = dalloc<double>(m, 2 * (N / 64 + 64));
-            m->part_rz2 = dalloc<double>(m, 2 * (N / 64 + 64));
-            m->s32 = dalloc<float>(m, N);
-            m->z32 = dalloc<float>(m, N);
             m->st = dalloc<PcgState>(m, 3);
             if (hipHostMalloc((void**)&m->st_host, 3 * sizeof(PcgState), hipHostMallocDefault) !=
                 hipSuccess) {

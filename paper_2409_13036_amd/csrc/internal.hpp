@@ -71,7 +71,6 @@ struct PcgState {
     double tol2;     // tol^2 * bb: stop when rr <= tol2
     double scale;    // mixed refinement: 1 / ||r_outer||
     double rr_first; // ||r||^2 at the start of this solve
-    double alpha_slots[2];  // single-reduction inner solve: alpha of iteration i in slot i&1
     int32_t iters;
     int32_t maxit;
     int32_t done;
@@ -158,14 +157,6 @@ void launch_spmv32(const Mat& A, const SpmvConfig& c, const float* x, float* y, 
 // Mixed outer test: done when rr <= tol2 (tol2 = tol^2 bb set here), scale = 1/||r||.
 void launch_residual64(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
                        double* r, double* partials, PcgState* st, int outer_mode, hipStream_t s);
-// Inner FP32 iteration in the single-reduction (Chronopoulos-Gear) form: after
-// launch_spmv_dot32(z -> w) this kernel updates p, s, x, r, z.  gam_in holds the partials
-// of r.z and r.r of the current residual (buffer it&1, from k_inner_start at it = 0);
-// gam_out receives the next ones.  Returns its grid size.
-int launch_cg_update32(int n, float* x, float* r, float* z, const float* w, float* p, float* sv,
-                       const float* dinv, const double* delta_part, int nb_delta,
-                       const double* gam_in, double* gam_out, int it, PcgState* st,
-                       hipStream_t s);
 // Mixed inner start: r32 = scale * r64; d32 = 0; p32 = D^-1 r32; rz, rr into inner state.
 void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,
                         float* p32, const float* dinv32, double inner_tol, int maxit,
@@ -267,8 +258,6 @@ struct rafem_mesh_s {
     double* partials = nullptr;   // once-per-solve reductions
     double* part_pq = nullptr;    // per-iteration partials of p.Ap
     double* part_rz = nullptr;    // per-iteration partials of r.z and r.r
-    double* part_rz2 = nullptr;   // second parity buffer of the single-reduction inner solve
-    float *s32 = nullptr, *z32 = nullptr;
     rafem::PcgState* st = nullptr;      // device [3]: main/inner, outer, check
     rafem::PcgState* st_host = nullptr; // pinned host [3]
 

@@ -38,7 +38,6 @@ __global__ void k_state_init(PcgState* st, double tol, int maxit) {
         st->tol2 = 0.0;
         st->scale = 1.0;
         st->rr_first = 0.0;
-        st->alpha_slots[0] = st->alpha_slots[1] = 0.0;
         st->iters = 0;
         st->maxit = maxit;
         st->done = 0;
@@ -408,104 +407,6 @@ __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
     }
 }
 
-// Inner FP32 solve in the Chronopoulos-Gear form of Jacobi-PCG: one SpMV (w = A z, with
-// partials of delta = z.w) and this one fused vector kernel per iteration, with s = A p
-// carried by recurrence.  Iteration i holds z_i = D^-1 r_i, w_i = A z_i, and reads
-//   gamma_i = r_i.z_i, rr_i = r_i.r_i  (partials of the previous kernel, buffer i&1),
-//   delta_i = z_i.w_i                  (partials of this iteration's SpMV);
-// stops when rr_i <= tol2, else
-//   beta_i = gamma_i / gamma_{i-1} (0 at i = 0),  alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
-//   p = z + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,  z = D^-1 r,
-// and writes the partials of gamma_{i+1}, rr_{i+1} into buffer (i+1)&1.  gamma and alpha
-// of iteration i are kept in state slots i&1 (read back at i+1 from slot (i-1)&1).
-template <typename T>
-__global__ __launch_bounds__(WG) void k_cg_update(int n, T* __restrict__ x, T* __restrict__ r,
-                                                  T* __restrict__ z, const T* __restrict__ w,
-                                                  T* __restrict__ p, T* __restrict__ sv,
-                                                  const T* __restrict__ dinv,
-                                                  const double* __restrict__ delta_part,
-                                                  int nb_delta,
-                                                  const double* __restrict__ gam_in,
-                                                  double* __restrict__ gam_out, int it,
-                                                  PcgState* st) {
-    if (st->done) return;
-    const int nb = gridDim.x;
-    const int blk = xcd_block(blockIdx.x, nb);
-    const int i0 = blk * kVecRowsPerBlock + threadIdx.x;
-    T xv[VPT], rv[VPT], zv[VPT], wv[VPT], pv[VPT], sv_[VPT], dv[VPT];
-#pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-        const int i = i0 + j * WG;
-        if (i < n) {
-            xv[j] = x[i];
-            rv[j] = r[i];
-            zv[j] = z[i];
-            wv[j] = w[i];
-            dv[j] = dinv[i];
-            if (it > 0) {
-                pv[j] = p[i];
-                sv_[j] = sv[i];
-            }
-        }
-    }
-    double dl[1], gr[2];
-    grid_totals<1>(delta_part, nb_delta, dl);
-    grid_totals<2>(gam_in, nb, gr);
-    const double gamma = gr[0], rr = gr[1], delta = dl[0];
-    const bool writer = blk == 0 && threadIdx.x == 0;
-    int status = -1;
-    if (!finite(gamma) || !finite(rr) || gamma < 0.0) status = RAFEM_E_BREAKDOWN;
-    else if (rr <= st->tol2) status = RAFEM_OK;
-    else if (it >= st->maxit) status = RAFEM_E_NOCONV;
-    double beta = 0.0, alpha = 0.0;
-    if (status < 0) {
-        double denom = delta;
-        if (it > 0) {
-            beta = gamma / st->rzs[(it - 1) & 1];
-            denom = delta - beta * gamma / st->alpha_slots[(it - 1) & 1];
-        }
-        if (!(denom > 0.0) || !finite(denom)) status = RAFEM_E_BREAKDOWN;
-        else alpha = gamma / denom;
-    }
-    if (status >= 0) {
-        if (writer) {
-            st->rr = rr;
-            st->iters = it;
-            st->status = status;
-            st->done = 1;
-        }
-        return;
-    }
-    const T a = (T)alpha, b = (T)beta;
-    double acc[2] = {0.0, 0.0};
-#pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-        const int i = i0 + j * WG;
-        if (i < n) {
-            const T pn = it > 0 ? zv[j] + b * pv[j] : zv[j];
-            const T sn = it > 0 ? wv[j] + b * sv_[j] : wv[j];
-            const T xn = xv[j] + a * pn;
-            const T rn = rv[j] - a * sn;
-            const T zn = dv[j] * rn;
-            p[i] = pn;
-            sv[i] = sn;
-            x[i] = xn;
-            r[i] = rn;
-            z[i] = zn;
-            acc[0] += (double)rn * (double)zn;
-            acc[1] += (double)rn * (double)rn;
-        }
-    }
-    store_partials<2>(acc, gam_out, blk, nb);
-    if (writer) {
-        st->rzs[it & 1] = gamma;
-        st->alpha_slots[it & 1] = alpha;
-        st->rr = rr;
-        st->beta = beta;
-        st->iters = it;
-    }
-}
-
 // Mixed refinement: inner right-hand side r32 = r64 / ||r64||, d32 = 0, p32 = D^-1 r32.
 __global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restrict__ r64,
                                                     const PcgState* outer,
@@ -514,8 +415,6 @@ __global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restr
                                                     float* __restrict__ p32,
                                                     const float* __restrict__ dinv32,
                                                     double* partials) {
-    // p32 receives z_0 = D^-1 r_0 (the first search direction, and the z of the
-    // single-reduction form)
     const bool skip = outer->done != 0;
     const double scale = outer->scale;
     const int nb = gridDim.x;
@@ -951,16 +850,6 @@ void launch_pupdate32(int n, float* p, const float* r, const float* dinv, const 
                       int nb_rz, int it, PcgState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_pupdate<float>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv,
                        rz_part, nb_rz, it, st);
-}
-
-int launch_cg_update32(int n, float* x, float* r, float* z, const float* w, float* p, float* sv,
-                       const float* dinv, const double* delta_part, int nb_delta,
-                       const double* gam_in, double* gam_out, int it, PcgState* st,
-                       hipStream_t s) {
-    const int nb = vec_blocks(n);
-    hipLaunchKernelGGL(k_cg_update<float>, dim3(nb), dim3(WG), 0, s, n, x, r, z, w, p, sv, dinv,
-                       delta_part, nb_delta, gam_in, gam_out, it, st);
-    return nb;
 }
 
 void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,

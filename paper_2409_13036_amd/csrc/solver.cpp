@@ -181,9 +181,8 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const double* dinv_in,
     PcgState& ho = m->st_host[1];
     while (true) {
         launch_residual64(A, cfg, b, x, m->r64, m->partials, outer, 1, s);
-        // z_0 goes to z32; the partials of r.z, r.r to the parity-0 buffer of the iterations
-        launch_inner_start(n, m->r64, outer, m->r32, m->d32, m->z32, dinv32, o.inner_tol,
-                           o.maxit, m->part_rz, inner, s);
+        launch_inner_start(n, m->r64, outer, m->r32, m->d32, m->p32, dinv32, o.inner_tol,
+                           o.maxit, m->partials, inner, s);
         check_launch();
         poll(m, s);  // outer convergence is decided by the residual just computed
         if (ho.done) break;
@@ -197,13 +196,12 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const double* dinv_in,
             ChunkTimer timer(m, k, 1);
             for (int j = 0; j < k; ++j) {
                 const int it = launched + j;
-                double* g_in = (it & 1) ? m->part_rz2 : m->part_rz;
-                double* g_out = (it & 1) ? m->part_rz : m->part_rz2;
                 timer.before(j, s);
-                const int nb1 = launch_spmv_dot32(A, cfg, m->z32, m->q32, m->part_pq, inner, s);
+                const int nb1 = launch_spmv_dot32(A, cfg, m->p32, m->q32, m->part_pq, inner, s);
                 timer.after(j, s);
-                launch_cg_update32(n, m->d32, m->r32, m->z32, m->q32, m->p32, m->s32, dinv32,
-                                   m->part_pq, nb1, g_in, g_out, it, inner, s);
+                const int nb2 = launch_update32(n, m->d32, m->r32, m->p32, m->q32, dinv32,
+                                                m->part_pq, nb1, m->part_rz, it, inner, s);
+                launch_pupdate32(n, m->p32, m->r32, dinv32, m->part_rz, nb2, it, inner, s);
             }
             check_launch();
             launched += k;
