@@ -37,8 +37,30 @@ def spmv_bytes(n: int, nnz: int, fp32: bool) -> int:
 
 
 def kernel_hash() -> str:
-    with open(os.path.join(ROOT, "paper_2409_13036_amd", "csrc", "kernels.hip"), "rb") as f:
+    """Hash of the source of the PCG kernels (the SpMV whose traffic is quoted)."""
+    with open(os.path.join(ROOT, "paper_2409_13036_amd", "csrc", "pcg.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def spmv_kernel_name(mesh, fp32: bool) -> str:
+    """rocprofv3's name of the PCG SpMV (fused with p.Ap) that this mesh launches."""
+    t = "float" if fp32 else "double"
+    return f"k_sell<{t}, 1, {'true' if mesh.stats().int16_columns else 'false'}>"
+
+
+def copy_probe(mib: int) -> None:
+    """A plain device-to-device copy of known size, launched a few times: the reference the
+    HBM byte counters are scaled by (it reads and writes mib MiB per launch)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[bench] copy probe: {mib} MiB read + {mib} MiB written per launch, 3 launches",
+          file=sys.stderr, flush=True)
+    del a, b
 
 
 def measured_traffic(kernel: str):
@@ -192,6 +214,67 @@ def adjoint_leg(args) -> dict:
             "fd": rows}
 
 
+def batch_leg(args) -> dict:
+    """Ensemble workload: 64 hex samples of side n ~ U{41..81} nodes with per-sample lognormal
+    k, sigma0 and w, advanced together through one batch handle (graph-captured iteration
+    chunks, autotuned SpMV slab shape) for 30 coupled steps, FP64 and mixed.  Reports
+    sample-steps/s and, per sample, the relative error of the mixed state against the FP64
+    state after the last step."""
+    import numpy as np
+    import torch
+    import rafem_inputs as ri
+    from paper_2409_13036_amd import _lib as R
+    from paper_2409_13036_amd.sim import BatchProblem
+
+    probs = ri.config4(samples=args.batch_samples, steps=args.batch_steps)
+    t0 = time.perf_counter()
+    bp = BatchProblem(probs)
+    setup = time.perf_counter() - t0
+    S = len(probs)
+    nnz = sum((3 * p.n - 2) ** 3 for p in probs)
+    out = {"workload": f"C4 ensemble, {S} hex samples n~U{{41..81}}, {args.batch_steps} coupled "
+                       f"steps, one batch handle",
+           "samples": S, "n_nodes_total": int(sum(p.n_nodes for p in probs)), "nnz_total": nnz,
+           "setup_s": setup}
+    finals = {}
+    for precision in ("fp64", "mixed"):
+        bp.reset()
+        bp.step(TOL, precision)  # warm-up: bioheat assembly, autotuning, graph capture
+        bp.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            bp.step(TOL, precision)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        finals[precision] = [bp.sample(q) for q in range(S)]
+        its = [bp.mesh.sample_info(q) for q in range(S)]
+        R.profile_enable(bp.mesh, True)
+        R.profile_read(bp.mesh, precision, reset=True)
+        bp.step(TOL, precision)
+        torch.cuda.synchronize()
+        mean_us, count = R.profile_read(bp.mesh, precision, reset=True)
+        R.profile_enable(bp.mesh, False)
+        out[precision] = {
+            "sample_steps_per_s": S * args.batch_steps / el, "elapsed_s": el,
+            "V_iters_last_step": [min(i["V"]["iters"] for i in its),
+                                  max(i["V"]["iters"] for i in its)],
+            "T_iters_last_step": [min(i["T"]["iters"] for i in its),
+                                  max(i["T"]["iters"] for i in its)],
+            "spmv_us_mean": mean_us, "spmv_launches": count}
+        print(f"[bench] batch {precision}: {S * args.batch_steps / el:.1f} sample-steps/s "
+              f"({el:.2f} s), spmv {mean_us:.1f} us x {count}", file=sys.stderr, flush=True)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    eT = [rel(m[0], f[0]) for m, f in zip(finals["mixed"], finals["fp64"])]
+    eV = [rel(m[1], f[1]) for m, f in zip(finals["mixed"], finals["fp64"])]
+    out["mixed_rel_err_vs_fp64_max"] = {"T": max(eT), "V": max(eV)}
+    mixed_ok = max(eT) <= 1e-8 and max(eV) <= 1e-8
+    out["path"] = "mixed" if mixed_ok else "fp64"
+    out["sample_steps_per_s"] = out[out["path"]]["sample_steps_per_s"]
+    bp.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +290,14 @@ def main():
                     help="run only the differentiation workload (timing + finite-difference check)")
     ap.add_argument("--adj-steps", type=int, default=60)
     ap.add_argument("--fd-params", type=int, default=32)
+    ap.add_argument("--workload", choices=["c1", "c2"], default="c1",
+                    help="c1: 101^3 hex (default); c2: 161^3-node jittered Kuhn tets")
+    ap.add_argument("--no-batch", action="store_true", help="skip the ensemble leg")
+    ap.add_argument("--batch-only", action="store_true", help="run only the ensemble leg")
+    ap.add_argument("--batch-samples", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=30)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first launch a plain copy of this many MiB (byte-counter reference)")
     args = ap.parse_args()
     if args.cpu_baseline_child:
         cpu_baseline_child(args.n)
@@ -219,9 +310,12 @@ def main():
     if args.adjoint:
         print(json.dumps(adjoint_leg(args)), flush=True)
         return
+    if args.batch_only:
+        print(json.dumps(batch_leg(args)), flush=True)
+        return
 
     # CPU oracle first, before this process touches the GPU
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.n)
+    cpu = None if (args.no_cpu_baseline or args.workload != "c1") else cpu_baseline(args.n)
     print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
 
     import numpy as np
@@ -229,7 +323,16 @@ def main():
     import rafem_inputs as ri
     from paper_2409_13036_amd.sim import DeviceProblem
 
-    p = ri.config1(n=args.n, steps=args.steps)
+    if args.copy_probe_mib > 0:
+        copy_probe(args.copy_probe_mib)
+    if args.workload == "c2":
+        n = 161 if args.n == 101 else args.n
+        p = ri.config2(n=n, steps=args.steps)
+        workload = f"C2 coupled RFA step, {n}^3-node jittered Kuhn-tet mesh"
+    else:
+        n = args.n
+        p = ri.config1(n=n, steps=args.steps)
+        workload = f"C1 coupled RFA step, {n}^3-node hex cube"
     dp = DeviceProblem(p)
     N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
     res = {}
@@ -255,7 +358,7 @@ def main():
     r = res[head]
     sps = args.steps / r["elapsed"]
     fp32 = head == "mixed"
-    kernel = "k_rows<float,4,ROW_DOT>" if fp32 else "k_rows<double,4,ROW_DOT>"
+    kernel = spmv_kernel_name(dp.mesh, fp32)
     per_launch = spmv_bytes(N, nnz, fp32)
     achieved = per_launch / (r["spmv_us"] * 1e-6) / 1e9 if r["spmv_us"] > 0 else 0.0
     line = {
@@ -264,7 +367,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": 1000.0 / sps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-inner/f64-refined" if fp32 else "f64", "data": "synthetic",
-        "config": {"workload": f"C1 coupled RFA step, {args.n}^3-node hex cube", "n_nodes": N,
+        "config": {"workload": workload, "n_nodes": N,
                    "nnz": nnz, "dt_s": p.dt, "tol": TOL, "path": head},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel),
@@ -288,6 +391,9 @@ def main():
     if cpu:
         line["speedup_vs_cpu_oracle"] = sps / cpu["value"]
     dp.close()
+    del dp
+    if not args.no_batch and args.workload == "c1":
+        line["batch"] = batch_leg(args)
     print(json.dumps(line), flush=True)
 
 

@@ -102,6 +102,10 @@ typedef struct {
     int64_t n_dirichlet;
     int32_t nodes_per_elem;
     int32_t n_colours;
+    int32_t n_samples;
+    int32_t slabs_per_block;     /* SELL shape of the FP64 SpMV (autotuned at the first step) */
+    int32_t slabs_per_block32;   /* SELL shape of the FP32 SpMV */
+    int32_t int16_columns;       /* 1 if the SpMV reads 16-bit column offsets */
 } rafem_mesh_stats;
 
 /* Build a mesh on the current device.
@@ -115,6 +119,33 @@ typedef struct {
 rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe,
                                const double* xyz_h, const int32_t* conn_h,
                                const int32_t* dir_ids_h, int64_t n_dir, rafem_mesh* out);
+
+/* A batch of independent problems (the ensemble workload: many tissue-parameter samples
+ * on meshes of different sizes) as one handle.  Sample q's arrays are as for
+ * rafem_mesh_create; the handle holds their disjoint union: sample q's nodes occupy
+ * [node_off[q], node_off[q] + n_nodes[q]) of every node vector, followed by padding nodes
+ * up to node_off[q+1] (a multiple of 1024, so no GPU workgroup spans two samples); its
+ * elements occupy [elem_off[q], elem_off[q+1]) of every element vector; its Dirichlet
+ * values occupy [dir_off[q], dir_off[q] + n_dir[q]) of dir_V / dir_T, followed by the
+ * values of its padding nodes (isolated Dirichlet nodes; any value, e.g. 0).  Every
+ * solve of rafem_step / rafem_step_vjp on a batch handle runs all samples together with
+ * per-sample scalars and convergence (each sample's iterates are those of its own solve)
+ * and its iteration chunks are replayed as HIP graphs.  Query the layout with
+ * rafem_mesh_sample_layout and per-sample results with rafem_sample_info. */
+rafem_status rafem_mesh_create_batch(int32_t n_samples, const int64_t* n_nodes,
+                                     const int64_t* n_elems, int32_t npe,
+                                     const double* const* xyz_h, const int32_t* const* conn_h,
+                                     const int32_t* const* dir_ids_h, const int64_t* n_dir,
+                                     rafem_mesh* out);
+
+/* node_off, elem_off, dir_off: [n_samples + 1] host outputs (any may be NULL).  A mesh made
+ * by rafem_mesh_create is one sample: {0, n_nodes}, {0, n_elems}, {0, n_dir}. */
+rafem_status rafem_mesh_sample_layout(rafem_mesh mesh, int64_t* node_off, int64_t* elem_off,
+                                      int64_t* dir_off);
+
+/* Use (nonzero) or not HIP graphs for the PCG iteration chunks of this mesh's steps.  On by
+ * default for batch handles.  Graphs are not used while SpMV profiling is enabled. */
+rafem_status rafem_mesh_set_graphs(rafem_mesh mesh, int32_t enable);
 
 /* Free a mesh and its device memory (synchronises the device first).  NULL is a no-op. */
 rafem_status rafem_mesh_destroy(rafem_mesh mesh);
@@ -287,6 +318,10 @@ rafem_status rafem_step_vjp(rafem_mesh mesh, const rafem_phys* phys, const doubl
 rafem_status rafem_lesion_loss(rafem_mesh mesh, int64_t n_loss, const int32_t* ids_d,
                                const double* target_d, const double* T_d, double scale,
                                double* loss_d, double* grad_d, void* stream);
+
+/* Per-sample solve information of the last rafem_step on this mesh (sample in
+ * [0, n_samples)); for a single mesh, sample 0 repeats the step's own info. */
+rafem_status rafem_sample_info(rafem_mesh mesh, int32_t sample, rafem_step_info* out);
 
 #ifdef __cplusplus
 }

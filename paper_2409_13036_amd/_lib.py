@@ -29,7 +29,9 @@ STATUS_NAMES = {OK: "OK", E_ARG: "E_ARG", E_MESH: "E_MESH", E_NOCONV: "E_NOCONV"
 EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafem_colour_elements",
            "rafem_mesh_create", "rafem_mesh_destroy", "rafem_mesh_get_stats", "rafem_assemble_csr",
            "rafem_solve", "rafem_solve_adjoint", "rafem_spmv", "rafem_profile_enable",
-           "rafem_profile_read", "rafem_step", "rafem_step_vjp", "rafem_lesion_loss")
+           "rafem_profile_read", "rafem_step", "rafem_step_vjp", "rafem_lesion_loss",
+           "rafem_mesh_create_batch", "rafem_mesh_sample_layout", "rafem_mesh_set_graphs",
+           "rafem_sample_info")
 
 
 class RafemError(RuntimeError):
@@ -40,7 +42,9 @@ class RafemError(RuntimeError):
 
 class MeshStats(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_elems", C.c_int64), ("nnz", C.c_int64),
-                ("n_dirichlet", C.c_int64), ("nodes_per_elem", C.c_int32), ("n_colours", C.c_int32)]
+                ("n_dirichlet", C.c_int64), ("nodes_per_elem", C.c_int32), ("n_colours", C.c_int32),
+                ("n_samples", C.c_int32), ("slabs_per_block", C.c_int32),
+                ("slabs_per_block32", C.c_int32), ("int16_columns", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -87,6 +91,10 @@ _lib.rafem_step.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, C.P
 _lib.rafem_step_vjp.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
                                 C.POINTER(SolveOpts), C.POINTER(StepInfo), _p]
 _lib.rafem_lesion_loss.argtypes = [_p, _i64, _p, _p, _p, C.c_double, _p, _p, _p]
+_lib.rafem_mesh_create_batch.argtypes = [_i32, _p, _p, _i32, _p, _p, _p, _p, C.POINTER(_p)]
+_lib.rafem_mesh_sample_layout.argtypes = [_p, _p, _p, _p]
+_lib.rafem_mesh_set_graphs.argtypes = [_p, _i32]
+_lib.rafem_sample_info.argtypes = [_p, _i32, C.POINTER(StepInfo)]
 for _name in EXPORTS:
     if _name not in ("rafem_last_error", "rafem_abi_version"):
         getattr(_lib, _name).restype = C.c_int32
@@ -193,18 +201,73 @@ class Mesh:
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         conn = _host_i32(conn)
         dir_ids = _host_i32(dir_ids)
-        self.n_nodes = int(xyz.shape[0])
-        self.n_elems, self.npe = (int(v) for v in conn.shape)
-        self.n_dir = int(dir_ids.size)
         h = C.c_void_p()
-        _check(_lib.rafem_mesh_create(self.n_nodes, self.n_elems, self.npe, xyz.ctypes.data,
+        _check(_lib.rafem_mesh_create(int(xyz.shape[0]), conn.shape[0], conn.shape[1], xyz.ctypes.data,
                                       conn.ctypes.data, dir_ids.ctypes.data if dir_ids.size else None,
-                                      self.n_dir, C.byref(h)))
+                                      int(dir_ids.size), C.byref(h)))
+        self._adopt(h)
+
+    @classmethod
+    def batch(cls, meshes):
+        """rafem_mesh_create_batch from a list of (xyz, conn, dir_ids) of one element type."""
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("rafem needs a HIP device")
+        torch.cuda.init()
+        S = len(meshes)
+        keep = []
+        nn = np.empty(S, dtype=np.int64)
+        ne = np.empty(S, dtype=np.int64)
+        nd = np.empty(S, dtype=np.int64)
+        xp = (C.c_void_p * S)()
+        cp = (C.c_void_p * S)()
+        dp = (C.c_void_p * S)()
+        npe = None
+        for q, (xyz, conn, dirs) in enumerate(meshes):
+            xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+            conn = _host_i32(conn)
+            dirs = _host_i32(dirs)
+            npe = conn.shape[1] if npe is None else npe
+            keep += [xyz, conn, dirs]
+            nn[q], ne[q], nd[q] = xyz.shape[0], conn.shape[0], dirs.size
+            xp[q], cp[q] = xyz.ctypes.data, conn.ctypes.data
+            dp[q] = dirs.ctypes.data if dirs.size else None
+        h = C.c_void_p()
+        _check(_lib.rafem_mesh_create_batch(S, nn.ctypes.data, ne.ctypes.data, int(npe), xp, cp, dp,
+                                            nd.ctypes.data, C.byref(h)))
+        self = cls.__new__(cls)
+        self._adopt(h)
+        return self
+
+    def _adopt(self, h):
         self.handle = h
-        st = MeshStats()
-        _check(_lib.rafem_mesh_get_stats(self.handle, C.byref(st)))
+        st = self.stats()
+        self.n_nodes = int(st.n_nodes)
+        self.n_elems = int(st.n_elems)
+        self.npe = int(st.nodes_per_elem)
+        self.n_dir = int(st.n_dirichlet)
         self.nnz = int(st.nnz)
         self.n_colours = int(st.n_colours)
+        self.n_samples = int(st.n_samples)
+        S = self.n_samples
+        self.node_off = np.empty(S + 1, dtype=np.int64)
+        self.elem_off = np.empty(S + 1, dtype=np.int64)
+        self.dir_off = np.empty(S + 1, dtype=np.int64)
+        _check(_lib.rafem_mesh_sample_layout(self.handle, self.node_off.ctypes.data,
+                                             self.elem_off.ctypes.data, self.dir_off.ctypes.data))
+
+    def stats(self) -> MeshStats:
+        st = MeshStats()
+        _check(_lib.rafem_mesh_get_stats(self.handle, C.byref(st)))
+        return st
+
+    def set_graphs(self, enable: bool):
+        _check(_lib.rafem_mesh_set_graphs(self.handle, 1 if enable else 0))
+
+    def sample_info(self, q: int):
+        info = StepInfo()
+        _check(_lib.rafem_sample_info(self.handle, int(q), C.byref(info)))
+        return {"V": info.V.as_dict(), "T": info.T.as_dict()}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librafem.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "solver.cpp", "abi.cpp", "structure.cpp"]
+SOURCES = ["pcg.hip", "kernels.hip", "adjoint.hip", "solver.cpp", "abi.cpp", "structure.cpp"]
 ARCH = "gfx950"
 
 

@@ -61,6 +61,9 @@ void free_mesh(rafem_mesh m) {
     if (!m) return;
     (void)hipDeviceSynchronize();
     profile_off(m);
+    for (auto& g : m->graphs) (void)hipGraphExecDestroy(g.exec);
+    m->graphs.clear();
+    if (m->gstream) (void)hipStreamDestroy(m->gstream);
     for (void* p : m->allocations) (void)hipFree(p);
     if (m->st_host) (void)hipHostFree(m->st_host);
     delete m;
@@ -148,66 +151,45 @@ void assemble_potential(rafem_mesh m, const rafem_phys* phys, const double* sigm
                 m->dinvV32, m->nD > 0, s);
 }
 
-void solve_any(rafem_mesh m, const SolveOpts& o, const Mat& A, const double* dinv,
-               const float* dinv32, const double* b, double* x, rafem_solve_info* info,
-               hipStream_t s, int hint, int* iters) {
+Samples step_samples(rafem_mesh m) { return Samples{m->S, m->row_off}; }
+Samples whole_mesh(rafem_mesh m) { return Samples{1, m->row_off_one}; }
+
+void solve_any(rafem_mesh m, const SolveOpts& o, const Mat& A, const Samples& smp,
+               const double* dinv, const float* dinv32, const double* b, double* x,
+               rafem_solve_info* info, hipStream_t s, int hint, int* iters) {
     if (o.precision == RAFEM_MIXED)
-        pcg_mixed(m, A, dinv, dinv32, b, x, o, info, s, hint, iters);
+        pcg_mixed(m, A, smp, dinv, dinv32, b, x, o, info, s, hint, iters);
     else
-        pcg64(m, A, dinv, b, x, o, info, s, hint, iters);
+        pcg64(m, A, smp, dinv, b, x, o, info, s, hint, iters);
 }
 
-}  // namespace
-
-void set_error(const std::string& msg) { g_error = msg; }
-void clear_error() { g_error.clear(); }
-
-}  // namespace rafem
-
-using namespace rafem;
-
-extern "C" {
-
-const char* rafem_last_error(void) { return g_error.c_str(); }
-
-int32_t rafem_abi_version(void) { return RAFEM_ABI_VERSION; }
-
-rafem_status rafem_csr_structure(int64_t n_nodes, int64_t n_elems, int32_t npe,
-                                 const int32_t* conn_h, int64_t* nnz_out, int32_t* row_ptr_h,
-                                 int32_t* col_idx_h) {
-    return guard([&]() -> rafem_status {
-        require(nnz_out != nullptr, "nnz_out is NULL");
-        check_conn(n_nodes, n_elems, npe, conn_h);
-        HostStructure S = build_structure(n_nodes, n_elems, npe, conn_h);
-        *nnz_out = (int64_t)S.col_idx.size();
-        if (row_ptr_h && col_idx_h) {
-            std::memcpy(row_ptr_h, S.row_ptr.data(), S.row_ptr.size() * sizeof(int32_t));
-            std::memcpy(col_idx_h, S.col_idx.data(), S.col_idx.size() * sizeof(int32_t));
+// Per-sample results of the solve that just finished (its last poll is in st_host).
+void record_samples(rafem_mesh m, bool potential, bool mixed) {
+    const int S = m->S;
+    const PcgState* h = m->st_host;
+    for (int q = 0; q < S; ++q) {
+        const PcgState& main = mixed ? h[S + q] : h[q];
+        rafem_solve_info& o = potential ? m->sample_info[q].V : m->sample_info[q].T;
+        o.status = main.status;
+        o.iters = main.iters;
+        o.outer = mixed ? main.iters : 0;
+        o.launched = 0;
+        o.relres = main.bb > 0.0 ? std::sqrt(main.rr / main.bb) : std::sqrt(main.rr);
+        if (mixed) {
+            o.relres_true = o.relres;
+        } else {
+            const PcgState& c = h[2 * S + q];
+            o.relres_true = c.bb > 0.0 ? std::sqrt(c.rr / c.bb) : std::sqrt(c.rr);
         }
-        return RAFEM_OK;
-    });
+    }
 }
 
-rafem_status rafem_colour_elements(int64_t n_nodes, int64_t n_elems, int32_t npe,
-                                   const int32_t* conn_h, int32_t* colour_h,
-                                   int32_t* n_colours_out) {
-    return guard([&]() -> rafem_status {
-        require(colour_h != nullptr && n_colours_out != nullptr, "output is NULL");
-        check_conn(n_nodes, n_elems, npe, conn_h);
-        *n_colours_out = colour_elements(n_nodes, n_elems, npe, conn_h, colour_h);
-        return RAFEM_OK;
-    });
-}
-
-rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, const double* xyz_h,
-                               const int32_t* conn_h, const int32_t* dir_ids_h, int64_t n_dir,
-                               rafem_mesh* out) {
-    return guard([&]() -> rafem_status {
-        require(out != nullptr, "out is NULL");
-        require(xyz_h != nullptr, "xyz is NULL");
-        require(n_dir >= 0 && n_dir <= n_nodes, "n_dir out of range");
-        require(n_dir == 0 || dir_ids_h != nullptr, "dir_ids is NULL");
-        *out = nullptr;
+// Everything rafem_mesh_create needs, for one mesh or the union of a batch (S samples,
+// sample q owning nodes [node_off[q], node_off[q+1])).
+rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const double* xyz_h,
+                      const int32_t* conn_h, const int32_t* dir_ids_h, int64_t n_dir, int S_,
+                      const std::vector<int64_t>& node_off, const std::vector<int64_t>& elem_off,
+                      const std::vector<int64_t>& dir_off) {
         check_conn(n_nodes, n_elems, npe, conn_h);
         for (int64_t k = 0; k < n_dir; ++k) {
             if (dir_ids_h[k] < 0 || dir_ids_h[k] >= n_nodes)
@@ -236,6 +218,7 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             m->n_colours = ncol;
             m->affine = (npe == 8 && affine) ? 1 : 0;
             m->spmv = choose_spmv_config(m->n, m->nnz);
+            m->spmv32 = m->spmv;
             // elements grouped by colour, ascending id within a colour
             m->colour_off.assign(ncol + 1, 0);
             for (int64_t e = 0; e < n_elems; ++e) m->colour_off[colour[e] + 1]++;
@@ -294,14 +277,18 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             m->partials = dalloc<double>(m, 3 * (N / 64 + 64));
             m->part_pq = dalloc<double>(m, N / 64 + 64);
             m->part_rz = dalloc<double>(m, 2 * (N / 64 + 64));
-            m->st = dalloc<PcgState>(m, 3);
-            if (hipHostMalloc((void**)&m->st_host, 3 * sizeof(PcgState), hipHostMallocDefault) !=
+            m->st = dalloc<PcgState>(m, 3 * (size_t)S_);
+            m->itb = dalloc<int32_t>(m, 2);
+            m->row_off = dalloc<int32_t>(m, (size_t)S_ + 1);
+            m->row_off_one = dalloc<int32_t>(m, 2);
+            if (hipHostMalloc((void**)&m->st_host, 3 * (size_t)S_ * sizeof(PcgState),
+                              hipHostMallocDefault) !=
                 hipSuccess) {
                 (void)hipGetLastError();
                 m->st_host = nullptr;
                 throw Error{RAFEM_E_NOMEM, "pinned host allocation failed"};
             }
-            std::memset(m->st_host, 0, 3 * sizeof(PcgState));
+            std::memset(m->st_host, 0, 3 * (size_t)S_ * sizeof(PcgState));
             RAFEM_HIP(hipMemcpy(m->rp, S.row_ptr.data(), (N + 1) * 4, hipMemcpyHostToDevice));
             RAFEM_HIP(hipMemcpy(m->ci, S.col_idx.data(), NNZ * 4, hipMemcpyHostToDevice));
             RAFEM_HIP(hipMemcpy(m->sptr, SL.sptr.data(), SL.sptr.size() * 4, hipMemcpyHostToDevice));
@@ -315,15 +302,170 @@ rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, co
             if (n_dir > 0)
                 RAFEM_HIP(hipMemcpy(m->dir_ids, dir_ids_h, (size_t)n_dir * 4, hipMemcpyHostToDevice));
             RAFEM_HIP(hipMemcpy(m->isD, isD.data(), N, hipMemcpyHostToDevice));
-            RAFEM_HIP(hipMemcpy(m->st, m->st_host, 3 * sizeof(PcgState), hipMemcpyHostToDevice));
+            RAFEM_HIP(hipMemcpy(m->st, m->st_host, 3 * (size_t)S_ * sizeof(PcgState),
+                                hipMemcpyHostToDevice));
+            std::vector<int32_t> roff(S_ + 1);
+            for (int q = 0; q <= S_; ++q) roff[q] = (int32_t)node_off[q];
+            const int32_t one[2] = {0, (int32_t)n_nodes};
+            RAFEM_HIP(hipMemcpy(m->row_off, roff.data(), roff.size() * 4, hipMemcpyHostToDevice));
+            RAFEM_HIP(hipMemcpy(m->row_off_one, one, 8, hipMemcpyHostToDevice));
+            m->S = S_;
+            m->node_off = node_off;
+            m->elem_off = elem_off;
+            m->dir_off = dir_off;
+            m->sample_info.assign(S_, rafem_step_info{});
+            m->use_graphs = S_ > 1;
             launch_slot_map(m->E, m->npe, m->conn, sell_layout(m), m->e2s, nullptr);
+            // The slab padding of the FP32 values is read by the FP32 SpMV (column = own
+            // row) but never written by assembly or lifting: it must hold zeros.  (The FP64
+            // values are cleared in full before every assembly.)
+            launch_fill32(m->valsV32, SNNZ, 0.0f, nullptr);
+            launch_fill32(m->valsT32, SNNZ, 0.0f, nullptr);
             RAFEM_HIP(hipGetLastError());
             RAFEM_HIP(hipDeviceSynchronize());
         } catch (...) {
             free_mesh(m);
             throw;
         }
-        *out = m;
+    return m;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+void clear_error() { g_error.clear(); }
+
+}  // namespace rafem
+
+using namespace rafem;
+
+extern "C" {
+
+const char* rafem_last_error(void) { return g_error.c_str(); }
+
+int32_t rafem_abi_version(void) { return RAFEM_ABI_VERSION; }
+
+rafem_status rafem_csr_structure(int64_t n_nodes, int64_t n_elems, int32_t npe,
+                                 const int32_t* conn_h, int64_t* nnz_out, int32_t* row_ptr_h,
+                                 int32_t* col_idx_h) {
+    return guard([&]() -> rafem_status {
+        require(nnz_out != nullptr, "nnz_out is NULL");
+        check_conn(n_nodes, n_elems, npe, conn_h);
+        HostStructure S = build_structure(n_nodes, n_elems, npe, conn_h);
+        *nnz_out = (int64_t)S.col_idx.size();
+        if (row_ptr_h && col_idx_h) {
+            std::memcpy(row_ptr_h, S.row_ptr.data(), S.row_ptr.size() * sizeof(int32_t));
+            std::memcpy(col_idx_h, S.col_idx.data(), S.col_idx.size() * sizeof(int32_t));
+        }
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_colour_elements(int64_t n_nodes, int64_t n_elems, int32_t npe,
+                                   const int32_t* conn_h, int32_t* colour_h,
+                                   int32_t* n_colours_out) {
+    return guard([&]() -> rafem_status {
+        require(colour_h != nullptr && n_colours_out != nullptr, "output is NULL");
+        check_conn(n_nodes, n_elems, npe, conn_h);
+        *n_colours_out = colour_elements(n_nodes, n_elems, npe, conn_h, colour_h);
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, const double* xyz_h,
+                               const int32_t* conn_h, const int32_t* dir_ids_h, int64_t n_dir,
+                               rafem_mesh* out) {
+    return guard([&]() -> rafem_status {
+        require(out != nullptr, "out is NULL");
+        require(xyz_h != nullptr, "xyz is NULL");
+        require(n_dir >= 0 && n_dir <= n_nodes, "n_dir out of range");
+        require(n_dir == 0 || dir_ids_h != nullptr, "dir_ids is NULL");
+        *out = nullptr;
+        *out = build_mesh(n_nodes, n_elems, npe, xyz_h, conn_h, dir_ids_h, n_dir, 1, {0, n_nodes},
+                          {0, n_elems}, {0, n_dir});
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_mesh_create_batch(int32_t n_samples, const int64_t* n_nodes,
+                                     const int64_t* n_elems, int32_t npe,
+                                     const double* const* xyz_h, const int32_t* const* conn_h,
+                                     const int32_t* const* dir_ids_h, const int64_t* n_dir,
+                                     rafem_mesh* out) {
+    return guard([&]() -> rafem_status {
+        require(out != nullptr, "out is NULL");
+        require(n_samples >= 1 && n_samples <= 4096, "n_samples out of range");
+        require(n_nodes && n_elems && xyz_h && conn_h && n_dir, "NULL argument");
+        require(npe == 8 || npe == 4, "nodes_per_elem must be 8 (hex) or 4 (tet)");
+        *out = nullptr;
+        const int S_ = n_samples;
+        // sample q: its nodes, then padding up to a multiple of kRowAlign; padding nodes have
+        // no element and are Dirichlet nodes (their rows lift to the identity)
+        std::vector<int64_t> node_off(S_ + 1, 0), elem_off(S_ + 1, 0), dir_off(S_ + 1, 0);
+        for (int q = 0; q < S_; ++q) {
+            require(n_nodes[q] > 0 && n_elems[q] > 0 && n_dir[q] >= 0 && n_dir[q] <= n_nodes[q],
+                    "sample size out of range");
+            require(xyz_h[q] && conn_h[q] && (n_dir[q] == 0 || dir_ids_h[q]), "NULL sample array");
+            const int64_t padded = (n_nodes[q] + kRowAlign - 1) / kRowAlign * kRowAlign;
+            node_off[q + 1] = node_off[q] + padded;
+            elem_off[q + 1] = elem_off[q] + n_elems[q];
+            dir_off[q + 1] = dir_off[q] + n_dir[q] + (padded - n_nodes[q]);
+        }
+        require(node_off[S_] < INT32_MAX && elem_off[S_] * npe < INT32_MAX, "batch too large");
+        const int64_t N = node_off[S_], E = elem_off[S_], ND = dir_off[S_];
+        std::vector<double> xyz(3 * N, 0.0);
+        std::vector<int32_t> conn(E * npe), dirs(ND);
+        for (int q = 0; q < S_; ++q) {
+            const int64_t no = node_off[q], nq = n_nodes[q];
+            std::memcpy(xyz.data() + 3 * no, xyz_h[q], 3 * nq * sizeof(double));
+            for (int64_t i = nq; i < node_off[q + 1] - no; ++i)
+                for (int c = 0; c < 3; ++c) xyz[3 * (no + i) + c] = xyz_h[q][c];
+            for (int64_t k = 0; k < n_elems[q] * npe; ++k) {
+                const int32_t v = conn_h[q][k];
+                if (v < 0 || v >= nq) throw Error{RAFEM_E_MESH, "sample element refers to a node out of range"};
+                conn[elem_off[q] * npe + k] = (int32_t)(v + no);
+            }
+            int64_t d = dir_off[q];
+            for (int64_t k = 0; k < n_dir[q]; ++k) {
+                if (dir_ids_h[q][k] < 0 || dir_ids_h[q][k] >= nq ||
+                    (k > 0 && dir_ids_h[q][k] <= dir_ids_h[q][k - 1]))
+                    throw Error{RAFEM_E_ARG, "sample Dirichlet ids must be increasing and in range"};
+                dirs[d++] = (int32_t)(dir_ids_h[q][k] + no);
+            }
+            for (int64_t i = no + nq; i < node_off[q + 1]; ++i) dirs[d++] = (int32_t)i;
+        }
+        *out = build_mesh(N, E, npe, xyz.data(), conn.data(), dirs.data(), ND, S_, node_off,
+                          elem_off, dir_off);
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_mesh_sample_layout(rafem_mesh m, int64_t* node_off, int64_t* elem_off,
+                                      int64_t* dir_off) {
+    return guard([&]() -> rafem_status {
+        require(m != nullptr, "mesh is NULL");
+        for (int q = 0; q <= m->S; ++q) {
+            if (node_off) node_off[q] = m->node_off[q];
+            if (elem_off) elem_off[q] = m->elem_off[q];
+            if (dir_off) dir_off[q] = m->dir_off[q];
+        }
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_sample_info(rafem_mesh m, int32_t sample, rafem_step_info* out) {
+    return guard([&]() -> rafem_status {
+        require(m != nullptr && out != nullptr, "NULL argument");
+        require(sample >= 0 && sample < m->S, "sample out of range");
+        *out = m->sample_info[sample];
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_mesh_set_graphs(rafem_mesh m, int32_t enable) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        m->use_graphs = enable != 0;
         return RAFEM_OK;
     });
 }
@@ -344,6 +486,10 @@ rafem_status rafem_mesh_get_stats(rafem_mesh m, rafem_mesh_stats* out) {
         out->n_dirichlet = m->nD;
         out->nodes_per_elem = m->npe;
         out->n_colours = m->n_colours;
+        out->n_samples = m->S;
+        out->slabs_per_block = m->spmv.slabs_per_block;
+        out->slabs_per_block32 = m->spmv32.slabs_per_block;
+        out->int16_columns = m->sdel ? 1 : 0;
         return RAFEM_OK;
     });
 }
@@ -387,9 +533,9 @@ rafem_status rafem_solve(rafem_mesh m, const int32_t* row_ptr_d, const int32_t* 
         hipStream_t s = (hipStream_t)stream;
         const Mat A = csr_matrix(m, row_ptr_d, col_idx_d, vals_d, vals32_d);
         if (o.precision == RAFEM_MIXED)
-            st = pcg_mixed(m, A, nullptr, nullptr, b_d, x_d, o, info, s, 0, nullptr);
+            st = pcg_mixed(m, A, whole_mesh(m), nullptr, nullptr, b_d, x_d, o, info, s, 0, nullptr);
         else
-            st = pcg64(m, A, nullptr, b_d, x_d, o, info, s, 0, nullptr);
+            st = pcg64(m, A, whole_mesh(m), nullptr, b_d, x_d, o, info, s, 0, nullptr);
         if (st != RAFEM_OK)
             set_error(st == RAFEM_E_NOCONV ? "iteration limit reached" : "PCG breakdown (p.Ap <= 0 or non-finite)");
         return st;
@@ -415,9 +561,10 @@ rafem_status rafem_solve_adjoint(rafem_mesh m, const int32_t* row_ptr_d, const i
         const Mat A = csr_matrix(m, row_ptr_d, col_idx_d, vals_d, vals32_d);
         rafem_status st;
         if (o.precision == RAFEM_MIXED)
-            st = pcg_mixed(m, A, nullptr, nullptr, m->bT, lambda_d, o, info, s, 0, nullptr);
+            st = pcg_mixed(m, A, whole_mesh(m), nullptr, nullptr, m->bT, lambda_d, o, info, s, 0,
+                           nullptr);
         else
-            st = pcg64(m, A, nullptr, m->bT, lambda_d, o, info, s, 0, nullptr);
+            st = pcg64(m, A, whole_mesh(m), nullptr, m->bT, lambda_d, o, info, s, 0, nullptr);
         if (st != RAFEM_OK)
             set_error(st == RAFEM_E_NOCONV ? "iteration limit reached" : "PCG breakdown (p.Ap <= 0 or non-finite)");
         return st;
@@ -514,8 +661,11 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
             launch_set_dirichlet(m->dir_ids, m->gV, m->nD, V_d, s);
             RAFEM_HIP(hipGetLastError());
             int it = 0;
-            solve_any(m, o, step_matrix(m, m->valsV, m->valsV32), m->dinvV, m->dinvV32, m->liftV,
-                      V_d, &inf.V, s, mixed ? 0 : m->hint_V, &it);
+            const Mat AV = step_matrix(m, m->valsV, m->valsV32);
+            if (!m->tuned) autotune_spmv(m, AV, s);
+            solve_any(m, o, AV, step_samples(m), m->dinvV, m->dinvV32, m->liftV, V_d, &inf.V, s,
+                      mixed ? 0 : m->hint_V, &it);
+            record_samples(m, true, mixed);
             if (!mixed) m->hint_V = it;
             if (inf.V.status != RAFEM_OK) {
                 set_error("potential solve failed");
@@ -534,8 +684,11 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
         launch_set_dirichlet(m->dir_ids, m->gT, m->nD, T_d, s);
         RAFEM_HIP(hipGetLastError());
         int it = 0;
-        solve_any(m, o, step_matrix(m, m->valsT, m->valsT32), m->dinvT, m->dinvT32, m->bT, T_d,
-                  &inf.T, s, mixed ? 0 : m->hint_T, &it);
+        const Mat AT = step_matrix(m, m->valsT, m->valsT32);
+        if (!m->tuned) autotune_spmv(m, AT, s);
+        solve_any(m, o, AT, step_samples(m), m->dinvT, m->dinvT32, m->bT, T_d, &inf.T, s,
+                  mixed ? 0 : m->hint_T, &it);
+        record_samples(m, false, mixed);
         if (!mixed) m->hint_T = it;
         if (inf.T.status != RAFEM_OK) {
             set_error("bioheat solve failed");
@@ -579,8 +732,8 @@ rafem_status rafem_step_vjp(rafem_mesh m, const rafem_phys* phys, const double* 
         launch_set_dirichlet(m->dir_ids, m->gtmp, m->nD, m->bT, s);
         launch_fill(m->adj_mu, m->n, 0.0, s);
         RAFEM_HIP(hipGetLastError());
-        solve_any(m, o, step_matrix(m, m->valsT, m->valsT32), m->dinvT, m->dinvT32, m->bT,
-                  m->adj_mu, &inf.T, s, 0, nullptr);
+        solve_any(m, o, step_matrix(m, m->valsT, m->valsT32), step_samples(m), m->dinvT,
+                  m->dinvT32, m->bT, m->adj_mu, &inf.T, s, 0, nullptr);
         if (inf.T.status != RAFEM_OK) {
             set_error("adjoint bioheat solve failed");
             return inf.T.status;
@@ -600,8 +753,8 @@ rafem_status rafem_step_vjp(rafem_mesh m, const rafem_phys* phys, const double* 
             launch_set_dirichlet(m->dir_ids, m->gtmp, m->nD, m->rhs, s);
             launch_fill(m->adj_nu, m->n, 0.0, s);
             RAFEM_HIP(hipGetLastError());
-            solve_any(m, o, step_matrix(m, m->valsV, m->valsV32), m->dinvV, m->dinvV32, m->rhs,
-                      m->adj_nu, &inf.V, s, 0, nullptr);
+            solve_any(m, o, step_matrix(m, m->valsV, m->valsV32), step_samples(m), m->dinvV,
+                      m->dinvV32, m->rhs, m->adj_nu, &inf.V, s, 0, nullptr);
             if (inf.V.status != RAFEM_OK) {
                 set_error("adjoint potential solve failed");
                 return inf.V.status;

@@ -117,56 +117,80 @@ struct Layout {
 // ---------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).  All asynchronous on `s`.
 // ---------------------------------------------------------------------------
-void launch_state_init(PcgState* st, double tol, int maxit, hipStream_t s);
-// dinv = 1 / diag(A) (CSR matrices); a missing or non-positive diagonal marks st->bad_diag.
+// A batch of independent systems: sample s owns rows [row_off[s], row_off[s+1]) (device
+// array); interior offsets are multiples of kRowAlign so no workgroup spans two samples.
+constexpr int kRowAlign = 1024;
+struct Samples {
+    int S;
+    const int32_t* row_off;
+};
+
+// Grid of a row kernel: blocks and rows per block (to locate a sample's partial slots).
+struct GridInfo {
+    int nb = 0;
+    int rpb = 1;
+};
+
+// Solver states are arrays of S (one per sample).  itb points at the device iteration
+// counter of the running loop (set to 0 by launch_state_init when given).
+void launch_state_init(PcgState* st, int S, double tol, int maxit, int* itb, hipStream_t s);
+void launch_advance(int* itb, int k, hipStream_t s);
+// dinv = 1 / diag(A) (CSR matrices, one system); a missing or non-positive diagonal marks
+// st->bad_diag.
 void launch_diag_inv(const Mat& A, double* dinv, float* dinv32, PcgState* st, hipStream_t s);
-// r = b - A x; p = D^-1 r; reduction of rz, rr, bb into st (FP64 PCG start).
+// r = b - A x; p = D^-1 r; per-sample r.z, r.r, b.b into st (FP64 PCG start).
 void launch_pcg_start(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
                       const double* dinv, double* r, double* p, double* partials,
-                      PcgState* st, hipStream_t s);
+                      PcgState* st, const Samples& smp, hipStream_t s);
 // One PCG iteration is three kernels.  None of them finalises a reduction itself: each
-// writes per-block partial sums, and every block of the next kernel adds the previous
-// kernel's partials in the same fixed order (kernel boundaries make them visible), so
-// no fences or atomics are needed and all blocks see bit-identical scalars.  `it` is the
-// iteration index (the host counts launches); scalars carried between iterations live
-// in slots chosen by its parity, so no kernel reads a slot it also writes.
-//   spmv_dot:  q = A p; partial p.q per block into pq_part.  Returns the grid size.
+// writes per-block partial sums, and every block of the next kernel adds its sample's
+// partials in a fixed order (kernel boundaries make them visible), so no fences or
+// atomics are needed and all blocks of a sample see bit-identical scalars.  The
+// iteration index is *itb + j; scalars carried between iterations live in slots chosen
+// by its parity, so no kernel reads a slot it also writes.
+//   spmv_dot:  q = A p; partial p.q per block into pq_part.
 //   update:    pq = sum(pq_part); alpha = rz[it&1] / pq (breakdown if pq <= 0);
 //              x += alpha p; r -= alpha q; partials of r.D^-1r and r.r into rz_part.
 //   pupdate:   rz', rr = sum(rz_part); stop on convergence / limit / breakdown, else
 //              beta = rz' / rz[it&1]; p = D^-1 r + beta p; rz[(it+1)&1] = rz'.
-// All three exit at once when st->done is set.
-int launch_spmv_dot64(const Mat& A, const SpmvConfig& c, const double* p, double* q,
-                      double* pq_part, PcgState* st, hipStream_t s);
-int launch_spmv_dot32(const Mat& A, const SpmvConfig& c, const float* p, float* q,
-                      double* pq_part, PcgState* st, hipStream_t s);
+// All three skip the samples whose st->done is set.
+GridInfo launch_spmv_dot64(const Mat& A, const SpmvConfig& c, const double* p, double* q,
+                           double* pq_part, PcgState* st, const Samples& smp, hipStream_t s);
+GridInfo launch_spmv_dot32(const Mat& A, const SpmvConfig& c, const float* p, float* q,
+                           double* pq_part, PcgState* st, const Samples& smp, hipStream_t s);
 int launch_update64(int n, double* x, double* r, const double* p, const double* q,
-                    const double* dinv, const double* pq_part, int nb_pq, double* rz_part,
-                    int it, PcgState* st, hipStream_t s);
-int launch_update32(int n, float* x, float* r, const float* p, const float* q,
-                    const float* dinv, const double* pq_part, int nb_pq, double* rz_part,
-                    int it, PcgState* st, hipStream_t s);
+                    const double* dinv, const double* pq_part, const GridInfo& gpq,
+                    double* rz_part, const int* itb, int j, PcgState* st, const Samples& smp,
+                    hipStream_t s);
+int launch_update32(int n, float* x, float* r, const float* p, const float* q, const float* dinv,
+                    const double* pq_part, const GridInfo& gpq, double* rz_part, const int* itb,
+                    int j, PcgState* st, const Samples& smp, hipStream_t s);
 void launch_pupdate64(int n, double* p, const double* r, const double* dinv,
-                      const double* rz_part, int nb_rz, int it, PcgState* st, hipStream_t s);
+                      const double* rz_part, int nb_rz, const int* itb, int j, PcgState* st,
+                      const Samples& smp, hipStream_t s);
 void launch_pupdate32(int n, float* p, const float* r, const float* dinv, const double* rz_part,
-                      int nb_rz, int it, PcgState* st, hipStream_t s);
+                      int nb_rz, const int* itb, int j, PcgState* st, const Samples& smp,
+                      hipStream_t s);
 // Plain y = A x (no state).
 void launch_spmv64(const Mat& A, const SpmvConfig& c, const double* x, double* y, hipStream_t s);
 void launch_spmv32(const Mat& A, const SpmvConfig& c, const float* x, float* y, hipStream_t s);
-// Residual r = b - A x with ||r||^2 and ||b||^2 into st->rr, st->bb (no early exit).
-// Mixed outer test: done when rr <= tol2 (tol2 = tol^2 bb set here), scale = 1/||r||.
+// Residual r = b - A x with ||r||^2 and ||b||^2 into st[s].rr, st[s].bb.  outer_mode (mixed
+// refinement): skips finished samples, tol2 = tol^2 bb, done when rr <= tol2, else
+// scale = 1/||r|| and one more refinement is counted.
 void launch_residual64(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
-                       double* r, double* partials, PcgState* st, int outer_mode, hipStream_t s);
+                       double* r, double* partials, PcgState* st, const Samples& smp,
+                       int outer_mode, hipStream_t s);
 // Mixed inner start: r32 = scale * r64; d32 = 0; p32 = D^-1 r32; rz, rr into inner state.
 void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,
                         float* p32, const float* dinv32, double inner_tol, int maxit,
-                        double* partials, PcgState* inner, hipStream_t s);
-// x64 += d32 / scale (unless the outer state is done).
+                        double* partials, PcgState* inner, const Samples& smp, hipStream_t s);
+// x64 += d32 / scale (samples whose refinement is not finished).
 void launch_refine_update(int n, double* x, const float* d32, const PcgState* outer,
-                          hipStream_t s);
+                          const Samples& smp, hipStream_t s);
 
 // Assembly.
 void launch_fill(double* v, int64_t n, double value, hipStream_t s);
+void launch_fill32(float* v, int64_t n, float value, hipStream_t s);
 void launch_scatter_dirichlet(const int32_t* dir_ids, const double* dir_vals, int64_t nD,
                               double* gnode, hipStream_t s);
 void launch_set_dirichlet(const int32_t* dir_ids, const double* gnode, int64_t nD, double* x,
@@ -223,7 +247,18 @@ struct rafem_mesh_s {
     int npe = 0, n_colours = 0;
     int device = 0;
     std::vector<int32_t> colour_off;  // host [n_colours + 1]
-    rafem::SpmvConfig spmv{4, 512};
+    rafem::SpmvConfig spmv{4, 512, 8};    // FP64 kernels
+    rafem::SpmvConfig spmv32{4, 512, 8};  // FP32 kernels
+    bool tuned = false;                   // slab shapes picked by the autotuner
+    bool use_graphs = false;              // iteration chunks captured as HIP graphs
+    hipStream_t gstream = nullptr;        // capture stream
+    struct GraphEntry {
+        int kind;
+        const void* key[4];
+        int len;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
 
     // structure and geometry
     int32_t* rp = nullptr;
@@ -258,8 +293,16 @@ struct rafem_mesh_s {
     double* partials = nullptr;   // once-per-solve reductions
     double* part_pq = nullptr;    // per-iteration partials of p.Ap
     double* part_rz = nullptr;    // per-iteration partials of r.z and r.r
-    rafem::PcgState* st = nullptr;      // device [3]: main/inner, outer, check
-    rafem::PcgState* st_host = nullptr; // pinned host [3]
+    rafem::PcgState* st = nullptr;      // device [3 S]: main/inner, outer, check per sample
+    rafem::PcgState* st_host = nullptr; // pinned host [3 S]
+    int32_t* itb = nullptr;             // device iteration counters [2]: FP64 loop, inner loop
+    int S = 1;                          // samples in the batch
+    std::vector<int64_t> node_off;      // host [S + 1] first node of each sample (padded layout)
+    std::vector<int64_t> elem_off;      // host [S + 1]
+    std::vector<int64_t> dir_off;       // host [S + 1]
+    int32_t* row_off = nullptr;         // device [S + 1]
+    int32_t* row_off_one = nullptr;     // device {0, n}: the whole mesh as one system
+    std::vector<rafem_step_info> sample_info;  // per-sample info of the last step
 
     // measurement of the SpMV kernels (rafem_profile_*)
     bool prof_on = false;

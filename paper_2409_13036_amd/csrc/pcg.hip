@@ -1,0 +1,751 @@
+// Jacobi-PCG kernels for gfx950 (CDNA4, wave64), for one system or a batch of
+// independent systems solved together.
+//
+// A batch is the union of S systems with disjoint rows: sample s owns rows
+// [row_off[s], row_off[s+1]), and every interior offset is a multiple of kRowAlign, so
+// no workgroup of any kernel spans two samples.  Each sample has its own solver state
+// (scalars, tolerance, iteration count, done flag); kernels look up the sample of their
+// first row, skip work once that sample is done, and reduce dot products per sample.
+//
+// Reductions are deterministic and need no atomics or fences: every block stores its
+// partial sums in a fixed slot, and the consumer (every block of the next kernel, or a
+// one-block-per-sample finalize kernel) adds the slots of its sample in index order
+// after the kernel boundary, so all consumers of a sample hold bit-identical scalars.
+// The iteration index lives in device memory (`itb` plus the iteration's offset j in
+// its chunk, advanced by k_advance after a chunk), so a chunk of iterations can be
+// captured once in a graph and replayed.  Scalars carried between iterations are kept
+// in slots chosen by the iteration's parity, so no kernel reads a slot it writes.
+//
+// The SpMV kernels stream the matrix in one of two layouts:
+//   * CSR, LANES consecutive lanes per row (general matrices handed over the ABI);
+//   * SELL with 64-row slabs, one row per lane (the step path): entry j of a slab's 64
+//     rows is one contiguous wavefront load for values and for column offsets, stored
+//     as int16 distances to the row when they fit; the x-gathers of neighbouring rows
+//     are contiguous too for the banded meshes here.
+// Workgroups walk contiguous row ranges, remapped so each XCD (own L2) takes one
+// contiguous share of the rows.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fem_device.hpp"
+#include "internal.hpp"
+
+namespace rafem {
+namespace {
+
+using namespace dev;
+
+// Sample owning `row` (largest s with row_off[s] <= row).
+__device__ __forceinline__ int sample_of(const Samples& B, int row) {
+    if (B.S == 1) return 0;
+    int lo = 0, hi = B.S - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (B.row_off[mid] <= row) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Partial slots [b0, b1) that a producer with `rpb` rows per block wrote for sample s.
+__device__ __forceinline__ void sample_blocks(const Samples& B, int s, int rpb, int& b0,
+                                              int& b1) {
+    b0 = B.row_off[s] / rpb;
+    b1 = (B.row_off[s + 1] + rpb - 1) / rpb;
+}
+
+// Fixed-order totals of partial slots [b0, b1) of K arrays; returned to every thread.
+template <int K>
+__device__ __forceinline__ void range_totals(const double* __restrict__ partials, int nb, int b0,
+                                             int b1, double (&tot)[K]) {
+    __shared__ double bcast[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int i = b0 + threadIdx.x; i < b1; i += WG) s += partials[k * nb + i];
+        tot[k] = s;
+    }
+    block_sum<K>(tot);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) bcast[k] = tot[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) tot[k] = bcast[k];
+}
+
+// ---------------------------------------------------------------------------
+// Solver state
+// ---------------------------------------------------------------------------
+__global__ void k_state_init(PcgState* st, int S, double tol, int maxit, int* itb) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s == 0 && itb) *itb = 0;
+    if (s >= S) return;
+    PcgState& t = st[s];
+    t.rzs[0] = t.rzs[1] = t.pq = t.beta = t.rr = t.bb = 0.0;
+    t.tol = tol;
+    t.tol2 = 0.0;
+    t.scale = 1.0;
+    t.rr_first = 0.0;
+    t.iters = 0;
+    t.maxit = maxit;
+    t.done = 0;
+    t.status = RAFEM_E_NOCONV;
+    t.bad_diag = 0;
+}
+
+__global__ void k_advance(int* itb, int k) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *itb += k;
+}
+
+// dinv = 1 / diag(A) (also as FP32), CSR, one system.  A missing or non-positive
+// diagonal marks the state.
+__global__ __launch_bounds__(WG) void k_diag_inv(const int* __restrict__ rp,
+                                                 const int* __restrict__ ci,
+                                                 const double* __restrict__ v, int n,
+                                                 double* __restrict__ dinv,
+                                                 float* __restrict__ dinv32, PcgState* st) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= n) return;
+    double d = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (ci[k] == i) d += v[k];
+    const double inv = (d > 0.0 && finite(d)) ? 1.0 / d : 0.0;
+    if (!(d > 0.0) || !finite(d)) st->bad_diag = 1;
+    dinv[i] = inv;
+    if (dinv32) dinv32[i] = (float)inv;
+}
+
+// ---------------------------------------------------------------------------
+// Row kernels
+// ---------------------------------------------------------------------------
+enum RowMode : int {
+    ROW_PLAIN = 0,  // y = A x
+    ROW_DOT = 1,    // y = A x, partials of x.y (PCG step; skipped once the sample is done)
+    ROW_START = 2,  // y = b - A x, p = D^-1 y, partials of y.p, y.y, b.b (PCG start)
+    ROW_RESID = 3,  // y = b - A x, partials of y.y, b.b (refinement / true residual)
+};
+
+template <typename T>
+struct RowArgs {
+    const int* __restrict__ rp;       // CSR
+    const int* __restrict__ ci;
+    const int* __restrict__ sptr;     // SELL
+    const int* __restrict__ scol;
+    const int16_t* __restrict__ sdel;
+    const T* __restrict__ val;
+    const T* __restrict__ x;
+    T* __restrict__ y;
+    const double* __restrict__ b;
+    const double* __restrict__ dinv;
+    double* __restrict__ pout;
+    double* partials;
+    PcgState* st;
+    Samples smp;
+    int n;
+    int nslabs;
+    int rows_per_block;   // CSR: rows per workgroup
+    int slabs_per_block;  // SELL: slabs per workgroup
+    int outer_mode;
+};
+
+// Per-row epilogue of every row mode; acc receives this lane's dot-product terms.
+template <typename T, int MODE>
+__device__ __forceinline__ void row_epilogue(const RowArgs<T>& a, int r, T sum, double (&acc)[3]) {
+    if constexpr (MODE == ROW_PLAIN) {
+        a.y[r] = sum;
+    } else if constexpr (MODE == ROW_DOT) {
+        a.y[r] = sum;
+        acc[0] += (double)a.x[r] * (double)sum;
+    } else {
+        const double bi = a.b[r];
+        const double ri = bi - (double)sum;
+        a.y[r] = (T)ri;
+        acc[1] += ri * ri;
+        acc[2] += bi * bi;
+        if constexpr (MODE == ROW_START) {
+            const double zi = a.dinv[r] * ri;
+            a.pout[r] = zi;
+            acc[0] += ri * zi;
+        }
+    }
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ bool skip_sample(const RowArgs<T>& a, int row0) {
+    if constexpr (MODE == ROW_DOT) return a.st[sample_of(a.smp, row0)].done != 0;
+    if constexpr (MODE == ROW_RESID) return a.outer_mode && a.st[sample_of(a.smp, row0)].done;
+    return false;
+}
+
+template <int MODE>
+__device__ __forceinline__ void row_partials(double (&acc)[3], double* partials, int blk, int nb) {
+    if constexpr (MODE == ROW_DOT) {
+        double v[1] = {acc[0]};
+        store_partials<1>(v, partials, blk, nb);
+    } else if constexpr (MODE != ROW_PLAIN) {
+        store_partials<3>(acc, partials, blk, nb);
+    }
+}
+
+template <typename T, int LANES, int MODE>
+__global__ __launch_bounds__(WG) void k_csr(RowArgs<T> a) {
+    const int nb = gridDim.x;
+    const int blk = xcd_block(blockIdx.x, nb);
+    const int row0 = blk * a.rows_per_block;
+    if (skip_sample<T, MODE>(a, row0)) return;
+    const int row1 = min(row0 + a.rows_per_block, a.n);
+    const int g = threadIdx.x / LANES, sub = threadIdx.x % LANES;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int r = row0 + g; r < row1; r += WG / LANES) {
+        const int s = a.rp[r], e = a.rp[r + 1];
+        T sum = T(0);
+#pragma unroll 4
+        for (int k = s + sub; k < e; k += LANES) sum += a.val[k] * a.x[a.ci[k]];
+#pragma unroll
+        for (int off = LANES / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, LANES);
+        if (sub == 0) row_epilogue<T, MODE>(a, r, sum, acc);
+    }
+    row_partials<MODE>(acc, a.partials, blk, nb);
+}
+
+constexpr int kSellUnroll = 9;
+
+// Sum over the entries of one row in entry order.  COL is int (absolute columns, xr = x)
+// or int16_t (offsets to the row, xr = x + row).
+template <typename T, typename COL>
+__device__ __forceinline__ T sell_row(const COL* __restrict__ cp, const T* __restrict__ vp,
+                                      const T* __restrict__ xr, int width) {
+    T sum = T(0);
+    int j = 0;
+    for (; j + kSellUnroll <= width; j += kSellUnroll) {
+        int c[kSellUnroll];
+        T v[kSellUnroll];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) {
+            c[u] = cp[(j + u) * WAVE];
+            v[u] = vp[(j + u) * WAVE];
+        }
+        T g[kSellUnroll];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) g[u] = xr[c[u]];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) sum += v[u] * g[u];
+    }
+    for (; j < width; ++j) sum += vp[j * WAVE] * xr[cp[j * WAVE]];
+    return sum;
+}
+
+// Partial sums of the SELL kernels cover fixed groups of kSlabGroup slabs, whatever the
+// workgroup shape, and are formed in a fixed order (per slab: wavefront butterfly; within
+// a group: wavefront w adds its slabs w, w + 4 in that order; then the four wavefronts in
+// order).  So the tuned shape (1 or 2 groups per workgroup) never changes a result.
+constexpr int kSlabGroup = 2 * NWAVES;
+constexpr int kMaxGroups = 2;
+
+template <int K>
+__device__ __forceinline__ void store_group_partials(double (&v)[kMaxGroups][K], int ngroups,
+                                                     double* partials, int g0, int nb) {
+    __shared__ double lds[kMaxGroups][K][NWAVES];
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    for (int g = 0; g < ngroups; ++g) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double t = wave_sum(v[g][k]);
+            if (lane == 0) lds[g][k][w] = t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int g = 0; g < ngroups; ++g) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                double t = 0.0;
+                for (int j = 0; j < NWAVES; ++j) t += lds[g][k][j];
+                partials[k * nb + g0 + g] = t;
+            }
+        }
+    }
+}
+
+template <typename T, int MODE, bool DELTA>
+__global__ __launch_bounds__(WG) void k_sell(RowArgs<T> a) {
+    const int nblk = gridDim.x;
+    const int blk = xcd_block(blockIdx.x, nblk);
+    const int s0 = blk * a.slabs_per_block;
+    if (skip_sample<T, MODE>(a, s0 * WAVE)) return;
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    const int s1 = min(s0 + a.slabs_per_block, a.nslabs);
+    double acc[kMaxGroups][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int i = 0; s0 + w + NWAVES * i < s1; ++i) {
+        const int sl = s0 + w + NWAVES * i;
+        const int base = a.sptr[sl];
+        const int width = (a.sptr[sl + 1] - base) / WAVE;
+        const int r = sl * WAVE + lane;
+        T sum;
+        if constexpr (DELTA)
+            sum = sell_row<T, int16_t>(a.sdel + base + lane, a.val + base + lane,
+                                       a.x + min(r, a.n - 1), width);
+        else
+            sum = sell_row<T, int>(a.scol + base + lane, a.val + base + lane, a.x, width);
+        if (r < a.n) row_epilogue<T, MODE>(a, r, sum, acc[i / 2]);
+    }
+    if constexpr (MODE != ROW_PLAIN) {
+        const int ngroups = a.slabs_per_block / kSlabGroup;
+        const int nb = (a.nslabs + kSlabGroup - 1) / kSlabGroup;
+        const int g0 = s0 / kSlabGroup;
+        const int ng = min(ngroups, nb - g0);
+        if constexpr (MODE == ROW_DOT) {
+            double v[kMaxGroups][1] = {{acc[0][0]}, {acc[1][0]}};
+            store_group_partials<1>(v, ng, a.partials, g0, nb);
+        } else {
+            store_group_partials<3>(acc, ng, a.partials, g0, nb);
+        }
+    }
+}
+
+// Totals of a START / RESID row kernel -> solver scalars (thread 0 of sample s's block).
+template <int MODE>
+__device__ void finish_rows(PcgState* st, const double (&tot)[3], int outer_mode) {
+    if constexpr (MODE == ROW_START) {
+        st->rzs[0] = tot[0];
+        st->rzs[1] = 0.0;
+        st->rr = tot[1];
+        st->bb = tot[2];
+        st->rr_first = tot[1];
+        st->tol2 = st->tol * st->tol * tot[2];
+        st->iters = 0;
+        if (st->bad_diag || !finite(tot[0]) || !finite(tot[1]) || !finite(tot[2])) {
+            st->status = RAFEM_E_BREAKDOWN;
+            st->done = 1;
+        } else if (tot[1] <= st->tol2) {
+            st->status = RAFEM_OK;
+            st->done = 1;
+        } else {
+            st->status = RAFEM_E_NOCONV;
+            st->done = 0;
+        }
+    } else {  // ROW_RESID
+        st->rr = tot[1];
+        st->bb = tot[2];
+        if (outer_mode) {
+            st->tol2 = st->tol * st->tol * tot[2];
+            if (st->iters == 0) st->rr_first = tot[1];
+            if (st->bad_diag || !finite(tot[1]) || !finite(tot[2])) {
+                st->status = RAFEM_E_BREAKDOWN;
+                st->done = 1;
+            } else if (tot[1] <= st->tol2) {
+                st->status = RAFEM_OK;
+                st->done = 1;
+            } else if (st->iters >= st->maxit) {
+                st->status = RAFEM_E_NOCONV;
+                st->done = 1;
+            } else {
+                st->scale = 1.0 / sqrt(tot[1]);
+                st->iters += 1;
+            }
+        }
+    }
+}
+
+// One block per sample.
+template <int MODE>
+__global__ __launch_bounds__(WG) void k_finalize_rows(const double* __restrict__ partials, int nb,
+                                                      int rpb, PcgState* st, int outer_mode,
+                                                      Samples smp) {
+    const int s = blockIdx.x;
+    if (MODE == ROW_RESID && outer_mode && st[s].done) return;
+    int b0, b1;
+    sample_blocks(smp, s, rpb, b0, b1);
+    double tot[3];
+    range_totals<3>(partials, nb, b0, b1, tot);
+    if (threadIdx.x == 0) finish_rows<MODE>(st + s, tot, outer_mode);
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels (kVecRowsPerBlock rows per workgroup, VPT per thread)
+// ---------------------------------------------------------------------------
+constexpr int VPT = kVecRowsPerBlock / WG;
+
+// x += alpha p; r -= alpha q, alpha = rz / (sample's total of p.Ap); partials of r.z, r.r.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_update(int n, T* __restrict__ x, T* __restrict__ r,
+                                               const T* __restrict__ p,
+                                               const T* __restrict__ q,
+                                               const T* __restrict__ dinv,
+                                               const double* __restrict__ pq_part, int nb_pq,
+                                               int rpb_pq, double* __restrict__ rz_part,
+                                               const int* __restrict__ itb, int j,
+                                               PcgState* st, Samples smp) {
+    const int nb = gridDim.x;
+    const int blk = xcd_block(blockIdx.x, nb);
+    const int row0 = blk * kVecRowsPerBlock;
+    const int s = sample_of(smp, row0);
+    PcgState& S = st[s];
+    if (S.done) return;
+    const int it = *itb + j;
+    const int i0 = row0 + threadIdx.x;
+    // issue this thread's loads before the partial sums so their latency overlaps
+    T xv[VPT], rv[VPT], pv[VPT], qv[VPT], dv[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int i = i0 + u * WG;
+        if (i < n) {
+            xv[u] = x[i];
+            rv[u] = r[i];
+            pv[u] = p[i];
+            qv[u] = q[i];
+            dv[u] = dinv[i];
+        }
+    }
+    int b0, b1;
+    sample_blocks(smp, s, rpb_pq, b0, b1);
+    double pq[1];
+    range_totals<1>(pq_part, nb_pq, b0, b1, pq);
+    const bool writer = threadIdx.x == 0 && blk == smp.row_off[s] / kVecRowsPerBlock;
+    if (!(pq[0] > 0.0) || !finite(pq[0])) {
+        if (writer) {
+            S.pq = pq[0];
+            S.iters = it;
+            S.status = RAFEM_E_BREAKDOWN;
+            S.done = 1;
+        }
+        return;
+    }
+    const T alpha = (T)(S.rzs[it & 1] / pq[0]);
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int i = i0 + u * WG;
+        if (i < n) {
+            const T xi = xv[u] + alpha * pv[u];
+            const T ri = rv[u] - alpha * qv[u];
+            x[i] = xi;
+            r[i] = ri;
+            const T zi = dv[u] * ri;
+            acc[0] += (double)ri * (double)zi;
+            acc[1] += (double)ri * (double)ri;
+        }
+    }
+    store_partials<2>(acc, rz_part, blk, nb);
+    if (writer) S.pq = pq[0];
+}
+
+// Convergence test on the sample's totals of r.z and r.r, then p = D^-1 r + beta p.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
+                                                const T* __restrict__ r,
+                                                const T* __restrict__ dinv,
+                                                const double* __restrict__ rz_part, int nb_rz,
+                                                const int* __restrict__ itb, int j, PcgState* st,
+                                                Samples smp) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int row0 = blk * kVecRowsPerBlock;
+    const int s = sample_of(smp, row0);
+    PcgState& S = st[s];
+    if (S.done) return;
+    const int it = *itb + j;
+    const int i0 = row0 + threadIdx.x;
+    T rv[VPT], pv[VPT], dv[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int i = i0 + u * WG;
+        if (i < n) {
+            rv[u] = r[i];
+            pv[u] = p[i];
+            dv[u] = dinv[i];
+        }
+    }
+    int b0, b1;
+    sample_blocks(smp, s, kVecRowsPerBlock, b0, b1);
+    double tot[2];
+    range_totals<2>(rz_part, nb_rz, b0, b1, tot);
+    const double rz = tot[0], rr = tot[1];
+    const int iters = it + 1;
+    int status = -1;
+    if (!finite(rz) || !finite(rr) || rz < 0.0) status = RAFEM_E_BREAKDOWN;
+    else if (rr <= S.tol2) status = RAFEM_OK;
+    else if (iters >= S.maxit) status = RAFEM_E_NOCONV;
+    const bool writer = threadIdx.x == 0 && blk == b0;
+    if (status >= 0) {
+        if (writer) {
+            S.rr = rr;
+            S.iters = iters;
+            S.status = status;
+            S.done = 1;
+        }
+        return;
+    }
+    const double beta = rz / S.rzs[it & 1];
+    const T bt = (T)beta;
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int i = i0 + u * WG;
+        if (i < n) p[i] = dv[u] * rv[u] + bt * pv[u];
+    }
+    if (writer) {
+        S.rzs[(it + 1) & 1] = rz;
+        S.rr = rr;
+        S.beta = beta;
+        S.iters = iters;
+    }
+}
+
+// Mixed refinement: inner right-hand side r32 = r64 / ||r64||, d32 = 0, p32 = D^-1 r32,
+// for the samples whose refinement is not finished.
+__global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restrict__ r64,
+                                                    const PcgState* outer,
+                                                    float* __restrict__ r32,
+                                                    float* __restrict__ d32,
+                                                    float* __restrict__ p32,
+                                                    const float* __restrict__ dinv32,
+                                                    double* partials, Samples smp) {
+    const int nb = gridDim.x;
+    const int blk = xcd_block(blockIdx.x, nb);
+    const int row0 = blk * kVecRowsPerBlock;
+    const int s = sample_of(smp, row0);
+    const bool skip = outer[s].done != 0;
+    const double scale = outer[s].scale;
+    const int i0 = row0 + threadIdx.x;
+    double acc[2] = {0.0, 0.0};
+    if (!skip) {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int i = i0 + u * WG;
+            if (i < n) {
+                const float ri = (float)(r64[i] * scale);
+                const float zi = dinv32[i] * ri;
+                r32[i] = ri;
+                d32[i] = 0.0f;
+                p32[i] = zi;
+                acc[0] += (double)ri * (double)zi;
+                acc[1] += (double)ri * (double)ri;
+            }
+        }
+    }
+    store_partials<2>(acc, partials, blk, nb);
+}
+
+// One block per sample: totals of k_inner_start's partials -> inner solver state.
+__global__ __launch_bounds__(WG) void k_finalize_inner(const double* __restrict__ partials, int nb,
+                                                       const PcgState* outer, double inner_tol,
+                                                       int maxit, PcgState* inner, Samples smp) {
+    const int s = blockIdx.x;
+    int b0, b1;
+    sample_blocks(smp, s, kVecRowsPerBlock, b0, b1);
+    double tot[2];
+    range_totals<2>(partials, nb, b0, b1, tot);
+    if (threadIdx.x != 0) return;
+    PcgState& S = inner[s];
+    const bool skip = outer[s].done != 0;
+    S.rzs[0] = tot[0];
+    S.rzs[1] = 0.0;
+    S.rr = tot[1];
+    S.bb = tot[1];
+    S.rr_first = tot[1];
+    S.tol = inner_tol;
+    S.tol2 = inner_tol * inner_tol * tot[1];
+    S.iters = 0;
+    S.maxit = maxit;
+    S.bad_diag = 0;
+    if (skip || !(tot[1] > 0.0)) {
+        S.status = RAFEM_OK;
+        S.done = 1;
+    } else if (!finite(tot[0]) || !finite(tot[1])) {
+        S.status = RAFEM_E_BREAKDOWN;
+        S.done = 1;
+    } else {
+        S.status = RAFEM_E_NOCONV;
+        S.done = 0;
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_refine_update(int n, double* __restrict__ x,
+                                                      const float* __restrict__ d32,
+                                                      const PcgState* outer, Samples smp) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int row0 = blk * kVecRowsPerBlock;
+    const int s = sample_of(smp, row0);
+    if (outer[s].done) return;
+    const double norm = 1.0 / outer[s].scale;
+    const int i0 = row0 + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int i = i0 + u * WG;
+        if (i < n) x[i] += (double)d32[i] * norm;
+    }
+}
+
+inline int grid1(int64_t n) { return (int)((n + WG - 1) / WG); }
+inline int vec_blocks(int n) { return (n + kVecRowsPerBlock - 1) / kVecRowsPerBlock; }
+
+template <typename T, int MODE>
+void launch_csr_kernel(int lanes, int nb, const RowArgs<T>& a, hipStream_t s) {
+    switch (lanes) {
+        case 2: hipLaunchKernelGGL((k_csr<T, 2, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_csr<T, 8, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_csr<T, 16, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_csr<T, 4, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
+    }
+}
+
+// One launcher for both layouts.  Returns {grid size, rows per block}.
+template <typename T, int MODE>
+GridInfo launch_rows(const Mat& A, const T* vals, const SpmvConfig& c, const T* x, T* y,
+                     const double* b, const double* dinv, double* pout, double* partials,
+                     PcgState* st, const Samples& smp, int outer_mode, hipStream_t s) {
+    RowArgs<T> a{A.rp, A.ci, A.sptr, A.scol, A.sdel, vals, x, y, b, dinv, pout, partials, st, smp,
+                 A.n, A.nslabs, c.rows_per_block, c.slabs_per_block, outer_mode};
+    GridInfo g;
+    if (A.sell) {
+        const int nblk = blocks_for(A.nslabs, c.slabs_per_block);
+        g.nb = blocks_for(A.nslabs, kSlabGroup);  // partial slots: one per group of slabs
+        g.rpb = kSlabGroup * WAVE;
+        if (nblk > 0) {
+            if (A.sdel)
+                hipLaunchKernelGGL((k_sell<T, MODE, true>), dim3(nblk), dim3(WG), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_sell<T, MODE, false>), dim3(nblk), dim3(WG), 0, s, a);
+        }
+    } else {
+        g.nb = blocks_for(A.n, c.rows_per_block);
+        g.rpb = c.rows_per_block;
+        if (g.nb > 0) launch_csr_kernel<T, MODE>(c.lanes, g.nb, a, s);
+    }
+    return g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+int blocks_for(int64_t n, int rows_per_block) {
+    return (int)((n + rows_per_block - 1) / rows_per_block);
+}
+
+SpmvConfig choose_spmv_config(int64_t n, int64_t nnz) {
+    const double avg = n > 0 ? (double)nnz / (double)n : 1.0;
+    SpmvConfig c;
+    c.lanes = avg > 6.0 ? 4 : 2;
+    const int rows_per_pass = WG / c.lanes;
+    int passes = 8;
+    // keep at least ~4 blocks per CU when the matrix is small
+    while (passes > 1 && blocks_for(n, rows_per_pass * passes) < 1024) passes /= 2;
+    c.rows_per_block = rows_per_pass * passes;
+    // two slabs per wavefront: one group of partial sums per workgroup (the autotuner may
+    // move to two groups)
+    c.slabs_per_block = kSlabGroup;
+    return c;
+}
+
+void launch_state_init(PcgState* st, int S, double tol, int maxit, int* itb, hipStream_t s) {
+    const int grid = S > 0 ? (S + 63) / 64 : 1;
+    hipLaunchKernelGGL(k_state_init, dim3(grid), dim3(64), 0, s, st, S, tol, maxit, itb);
+}
+
+void launch_advance(int* itb, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, itb, k);
+}
+
+void launch_diag_inv(const Mat& A, double* dinv, float* dinv32, PcgState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_diag_inv, dim3(grid1(A.n)), dim3(WG), 0, s, A.rp, A.ci, A.v, A.n, dinv,
+                       dinv32, st);
+}
+
+void launch_pcg_start(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
+                      const double* dinv, double* r, double* p, double* partials, PcgState* st,
+                      const Samples& smp, hipStream_t s) {
+    const GridInfo g = launch_rows<double, ROW_START>(A, A.v, c, x, r, b, dinv, p, partials, st,
+                                                      smp, 0, s);
+    hipLaunchKernelGGL(k_finalize_rows<ROW_START>, dim3(smp.S), dim3(WG), 0, s, partials, g.nb,
+                       g.rpb, st, 0, smp);
+}
+
+GridInfo launch_spmv_dot64(const Mat& A, const SpmvConfig& c, const double* p, double* q,
+                           double* pq_part, PcgState* st, const Samples& smp, hipStream_t s) {
+    return launch_rows<double, ROW_DOT>(A, A.v, c, p, q, nullptr, nullptr, nullptr, pq_part, st,
+                                        smp, 0, s);
+}
+
+GridInfo launch_spmv_dot32(const Mat& A, const SpmvConfig& c, const float* p, float* q,
+                           double* pq_part, PcgState* st, const Samples& smp, hipStream_t s) {
+    return launch_rows<float, ROW_DOT>(A, A.v32, c, p, q, nullptr, nullptr, nullptr, pq_part, st,
+                                       smp, 0, s);
+}
+
+void launch_spmv64(const Mat& A, const SpmvConfig& c, const double* x, double* y,
+                   hipStream_t s) {
+    Samples one{1, nullptr};
+    launch_rows<double, ROW_PLAIN>(A, A.v, c, x, y, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   one, 0, s);
+}
+
+void launch_spmv32(const Mat& A, const SpmvConfig& c, const float* x, float* y,
+                   hipStream_t s) {
+    Samples one{1, nullptr};
+    launch_rows<float, ROW_PLAIN>(A, A.v32, c, x, y, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                  one, 0, s);
+}
+
+void launch_residual64(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
+                       double* r, double* partials, PcgState* st, const Samples& smp,
+                       int outer_mode, hipStream_t s) {
+    const GridInfo g = launch_rows<double, ROW_RESID>(A, A.v, c, x, r, b, nullptr, nullptr,
+                                                      partials, st, smp, outer_mode, s);
+    hipLaunchKernelGGL(k_finalize_rows<ROW_RESID>, dim3(smp.S), dim3(WG), 0, s, partials, g.nb,
+                       g.rpb, st, outer_mode, smp);
+}
+
+int launch_update64(int n, double* x, double* r, const double* p, const double* q,
+                    const double* dinv, const double* pq_part, const GridInfo& gpq,
+                    double* rz_part, const int* itb, int j, PcgState* st, const Samples& smp,
+                    hipStream_t s) {
+    const int nb = vec_blocks(n);
+    hipLaunchKernelGGL(k_update<double>, dim3(nb), dim3(WG), 0, s, n, x, r, p, q, dinv, pq_part,
+                       gpq.nb, gpq.rpb, rz_part, itb, j, st, smp);
+    return nb;
+}
+
+int launch_update32(int n, float* x, float* r, const float* p, const float* q, const float* dinv,
+                    const double* pq_part, const GridInfo& gpq, double* rz_part, const int* itb,
+                    int j, PcgState* st, const Samples& smp, hipStream_t s) {
+    const int nb = vec_blocks(n);
+    hipLaunchKernelGGL(k_update<float>, dim3(nb), dim3(WG), 0, s, n, x, r, p, q, dinv, pq_part,
+                       gpq.nb, gpq.rpb, rz_part, itb, j, st, smp);
+    return nb;
+}
+
+void launch_pupdate64(int n, double* p, const double* r, const double* dinv,
+                      const double* rz_part, int nb_rz, const int* itb, int j, PcgState* st,
+                      const Samples& smp, hipStream_t s) {
+    hipLaunchKernelGGL(k_pupdate<double>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv,
+                       rz_part, nb_rz, itb, j, st, smp);
+}
+
+void launch_pupdate32(int n, float* p, const float* r, const float* dinv, const double* rz_part,
+                      int nb_rz, const int* itb, int j, PcgState* st, const Samples& smp,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_pupdate<float>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv,
+                       rz_part, nb_rz, itb, j, st, smp);
+}
+
+void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,
+                        float* p32, const float* dinv32, double inner_tol, int maxit,
+                        double* partials, PcgState* inner, const Samples& smp, hipStream_t s) {
+    const int nb = vec_blocks(n);
+    hipLaunchKernelGGL(k_inner_start, dim3(nb), dim3(WG), 0, s, n, r64, outer, r32, d32, p32,
+                       dinv32, partials, smp);
+    hipLaunchKernelGGL(k_finalize_inner, dim3(smp.S), dim3(WG), 0, s, partials, nb, outer,
+                       inner_tol, maxit, inner, smp);
+}
+
+void launch_refine_update(int n, double* x, const float* d32, const PcgState* outer,
+                          const Samples& smp, hipStream_t s) {
+    hipLaunchKernelGGL(k_refine_update, dim3(vec_blocks(n)), dim3(WG), 0, s, n, x, d32, outer,
+                       smp);
+}
+
+}  // namespace rafem

@@ -1,12 +1,15 @@
-// Host drivers of the Jacobi-PCG solves: FP64 PCG and FP32-inner / FP64-refined PCG.
+// Host drivers of the Jacobi-PCG solves: FP64 PCG and FP32-inner / FP64-refined PCG,
+// for one system or a batch of independent systems (one state per sample).
 //
-// All arithmetic runs in the kernels; the host only enqueues chunks of
-// iterations and polls the device-resident solver state between chunks.  The
-// chunk length is predicted from the observed convergence rate so that few
-// iterations are enqueued past convergence (those exit at once on the device
-// flag) and the host synchronises only a handful of times per solve.
+// All arithmetic runs in the kernels; the host only enqueues chunks of iterations and
+// polls the device-resident solver states between chunks.  The chunk length is
+// predicted from the observed convergence rate of the slowest sample, so few iterations
+// are enqueued past convergence (those exit at once on the device flag) and the host
+// synchronises only a handful of times per solve.  Optionally a chunk is captured once
+// as a HIP graph (its iteration index comes from device memory) and replayed.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "solver.hpp"
 
@@ -14,13 +17,16 @@ namespace rafem {
 
 namespace {
 
+void check_launch() { RAFEM_HIP(hipGetLastError()); }
+
 void poll(rafem_mesh m, hipStream_t s) {
-    RAFEM_HIP(hipMemcpyAsync(m->st_host, m->st, 3 * sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    RAFEM_HIP(hipMemcpyAsync(m->st_host, m->st, 3 * m->S * sizeof(PcgState), hipMemcpyDeviceToHost,
+                             s));
     RAFEM_HIP(hipStreamSynchronize(s));
 }
 
 // Iterations still needed to take rr down to tol2, from the rate seen between two polls.
-int predict_chunk(double rr_prev, int it_prev, double rr, int it, double tol2, int fallback) {
+int predict_one(double rr_prev, int it_prev, double rr, int it, double tol2, int fallback) {
     if (it > it_prev && rr_prev > 0.0 && rr > 0.0 && rr < rr_prev && tol2 > 0.0) {
         const double rate = std::log(rr / rr_prev) / double(it - it_prev);  // < 0
         const double need = std::log(tol2 / rr) / rate;
@@ -35,9 +41,50 @@ int first_chunk(const SolveOpts& o, int hint) {
     return 16;
 }
 
-void check_launch() { RAFEM_HIP(hipGetLastError()); }
+// Tracks the convergence of every unfinished sample between polls.
+struct Predictor {
+    std::vector<double> rr_prev;
+    std::vector<int> it_prev;
+    explicit Predictor(int S) : rr_prev(S, -1.0), it_prev(S, 0) {}
+    int next(const PcgState* h, int S, int fallback) {
+        int need = 0;
+        bool any = false;
+        for (int s = 0; s < S; ++s) {
+            if (h[s].done) continue;
+            any = true;
+            if (rr_prev[s] < 0.0) {
+                rr_prev[s] = h[s].rr_first;
+                it_prev[s] = 0;
+            }
+            need = std::max(need, predict_one(rr_prev[s], it_prev[s], h[s].rr, h[s].iters,
+                                              h[s].tol2, fallback));
+            rr_prev[s] = h[s].rr;
+            it_prev[s] = h[s].iters;
+        }
+        return any ? std::max(1, need) : fallback;
+    }
+};
 
-// Event pairs around the first launches of a chunk (measurement mode only).
+bool all_done(const PcgState* h, int S) {
+    for (int s = 0; s < S; ++s)
+        if (!h[s].done) return false;
+    return true;
+}
+
+int max_iters(const PcgState* h, int S) {
+    int it = 0;
+    for (int s = 0; s < S; ++s) it = std::max(it, h[s].iters);
+    return it;
+}
+
+int worst_status(const PcgState* h, int S) {
+    int status = RAFEM_OK;
+    for (int s = 0; s < S; ++s)
+        if (h[s].status != RAFEM_OK) status = std::max(status, h[s].status);
+    return status;
+}
+
+// Event pairs around the SpMV launches of a chunk (measurement mode, no graphs).
 struct ChunkTimer {
     rafem_mesh m;
     int rec = 0;
@@ -51,7 +98,7 @@ struct ChunkTimer {
     void after(int j, hipStream_t s) {
         if (j < rec) RAFEM_HIP(hipEventRecord(m->prof_ev[2 * j + 1], s));
     }
-    // after the stream has been synchronised: launches j with it_before + j < iters ran
+    // after the stream has been synchronised: launch j ran iff it_before + j < iters
     void collect(int it_before, int iters) {
         for (int j = 0; j < rec; ++j) {
             if (it_before + j >= iters) break;
@@ -63,16 +110,120 @@ struct ChunkTimer {
     }
 };
 
+// One FP64 PCG iteration (three kernels) at offset j of a chunk.
+struct Iter64 {
+    rafem_mesh m;
+    const Mat* A;
+    const SpmvConfig* cfg;
+    const double* dinv;
+    double* x;
+    PcgState* st;
+    Samples smp;
+    int* itb;
+    void operator()(int j, hipStream_t s, ChunkTimer* t) const {
+        const int n = A->n;
+        if (t) t->before(j, s);
+        const GridInfo g1 = launch_spmv_dot64(*A, *cfg, m->p, m->q, m->part_pq, st, smp, s);
+        if (t) t->after(j, s);
+        const int nb2 = launch_update64(n, x, m->r, m->p, m->q, dinv, m->part_pq, g1, m->part_rz,
+                                        itb, j, st, smp, s);
+        launch_pupdate64(n, m->p, m->r, dinv, m->part_rz, nb2, itb, j, st, smp, s);
+    }
+};
+
+// One FP32 inner iteration.
+struct Iter32 {
+    rafem_mesh m;
+    const Mat* A;
+    const SpmvConfig* cfg;
+    const float* dinv32;
+    PcgState* st;
+    Samples smp;
+    int* itb;
+    void operator()(int j, hipStream_t s, ChunkTimer* t) const {
+        const int n = A->n;
+        if (t) t->before(j, s);
+        const GridInfo g1 = launch_spmv_dot32(*A, *cfg, m->p32, m->q32, m->part_pq, st, smp, s);
+        if (t) t->after(j, s);
+        const int nb2 = launch_update32(n, m->d32, m->r32, m->p32, m->q32, dinv32, m->part_pq, g1,
+                                        m->part_rz, itb, j, st, smp, s);
+        launch_pupdate32(n, m->p32, m->r32, dinv32, m->part_rz, nb2, itb, j, st, smp, s);
+    }
+};
+
+constexpr int kGraphLen = 8;  // iterations per captured chunk
+
+// The graph of kGraphLen iterations for this set of buffers, captured on first use.
+template <typename IT>
+hipGraphExec_t chunk_graph(rafem_mesh m, int kind, const void* k0, const void* k1,
+                           const void* k2, const void* k3, const IT& iter, int* itb) {
+    for (auto& g : m->graphs)
+        if (g.kind == kind && g.key[0] == k0 && g.key[1] == k1 && g.key[2] == k2 &&
+            g.key[3] == k3 && g.len == kGraphLen)
+            return g.exec;
+    if (!m->gstream) RAFEM_HIP(hipStreamCreateWithFlags(&m->gstream, hipStreamNonBlocking));
+    RAFEM_HIP(hipStreamBeginCapture(m->gstream, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < kGraphLen; ++j) iter(j, m->gstream, nullptr);
+    launch_advance(itb, kGraphLen, m->gstream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(m->gstream, &graph);
+    if (e != hipSuccess)
+        throw Error{RAFEM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e)};
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess)
+        throw Error{RAFEM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e2)};
+    m->graphs.push_back({kind, {k0, k1, k2, k3}, kGraphLen, exec});
+    return exec;
+}
+
+// Enqueue at least k iterations; returns how many (graphs round up to whole chunks).
+template <typename IT>
+int enqueue(int k, const IT& iter, hipGraphExec_t graph, int* itb, ChunkTimer* t, hipStream_t s) {
+    if (graph) {
+        const int reps = (k + kGraphLen - 1) / kGraphLen;
+        for (int r = 0; r < reps; ++r) RAFEM_HIP(hipGraphLaunch(graph, s));
+        return reps * kGraphLen;
+    }
+    for (int j = 0; j < k; ++j) iter(j, s, t);
+    launch_advance(itb, k, s);
+    return k;
+}
+
+void fill_info(rafem_solve_info* info, const PcgState* h, const PcgState* chk, int S, int launched,
+               int outer) {
+    if (!info) return;
+    double relres = 0.0, relres_true = 0.0;
+    for (int s = 0; s < S; ++s) {
+        const double bb = h[s].bb;
+        relres = std::max(relres, bb > 0.0 ? std::sqrt(h[s].rr / bb) : std::sqrt(h[s].rr));
+        if (chk) {
+            const double cb = chk[s].bb;
+            relres_true = std::max(relres_true,
+                                   cb > 0.0 ? std::sqrt(chk[s].rr / cb) : std::sqrt(chk[s].rr));
+        }
+    }
+    info->status = worst_status(h, S);
+    info->iters = max_iters(h, S);
+    info->outer = outer;
+    info->launched = launched;
+    info->relres = relres;
+    info->relres_true = chk ? relres_true : relres;
+}
+
 }  // namespace
 
 SolveOpts resolve_opts(const rafem_solve_opts* o, double default_tol) {
     SolveOpts r;
     r.tol = default_tol;
     if (o) {
-        if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) throw Error{RAFEM_E_ARG, "opts.tol must be finite and >= 0"};
+        if (!(o->tol >= 0.0) || !std::isfinite(o->tol))
+            throw Error{RAFEM_E_ARG, "opts.tol must be finite and >= 0"};
         if (o->precision != RAFEM_FP64 && o->precision != RAFEM_MIXED)
             throw Error{RAFEM_E_ARG, "opts.precision must be RAFEM_FP64 or RAFEM_MIXED"};
-        if (o->inner_tol < 0.0 || o->inner_tol >= 1.0) throw Error{RAFEM_E_ARG, "opts.inner_tol must be in [0, 1)"};
+        if (o->inner_tol < 0.0 || o->inner_tol >= 1.0)
+            throw Error{RAFEM_E_ARG, "opts.inner_tol must be in [0, 1)"};
         r.tol = o->tol;
         r.maxit = o->maxit > 0 ? o->maxit : 20000;
         r.precision = o->precision;
@@ -83,164 +234,145 @@ SolveOpts resolve_opts(const rafem_solve_opts* o, double default_tol) {
     return r;
 }
 
-rafem_status pcg64(rafem_mesh m, const Mat& A, const double* dinv_in, const double* b, double* x,
-                   const SolveOpts& o, rafem_solve_info* info, hipStream_t s, int hint,
-                   int* iters_out) {
+rafem_status pcg64(rafem_mesh m, const Mat& A, const Samples& smp, const double* dinv_in,
+                   const double* b, double* x, const SolveOpts& o, rafem_solve_info* info,
+                   hipStream_t s, int hint, int* iters_out) {
+    const int S = smp.S;
     PcgState* st = m->st;
-    PcgState* chk = m->st + 2;
+    PcgState* chk = m->st + 2 * S;
     const SpmvConfig& cfg = m->spmv;
-    const int n = A.n;
-    launch_state_init(st, o.tol, o.maxit, s);
+    int* itb = m->itb;
+    launch_state_init(st, S, o.tol, o.maxit, itb, s);
     const double* dinv = dinv_in;
     if (!dinv) {
-        if (A.sell) throw Error{RAFEM_E_STATE, "slab-layout solve without a Jacobi inverse"};
+        if (A.sell || S != 1) throw Error{RAFEM_E_STATE, "slab-layout solve without a Jacobi inverse"};
         launch_diag_inv(A, m->dinv, nullptr, st, s);
         dinv = m->dinv;
     }
-    launch_pcg_start(A, cfg, b, x, dinv, m->r, m->p, m->partials, st, s);
+    launch_pcg_start(A, cfg, b, x, dinv, m->r, m->p, m->partials, st, smp, s);
     check_launch();
 
+    const Iter64 iter{m, &A, &cfg, dinv, x, st, smp, itb};
+    hipGraphExec_t graph = nullptr;
+    if (m->use_graphs && !m->prof_on)
+        graph = chunk_graph(m, 0, A.v, x, dinv, A.sell ? (const void*)A.sptr : (const void*)A.rp,
+                            iter, itb);
     int launched = 0;
     int chunk = first_chunk(o, hint);
-    double rr_prev = -1.0;
-    int it_prev = 0;
-    PcgState& h = m->st_host[0];
-    int it_before = 0;
+    Predictor pred(S);
+    const PcgState* h = m->st_host;
     while (true) {
         const int k = std::min(chunk, o.maxit - launched);
-        ChunkTimer timer(m, k, 0);
-        for (int j = 0; j < k; ++j) {
-            const int it = launched + j;
-            timer.before(j, s);
-            const int nb1 = launch_spmv_dot64(A, cfg, m->p, m->q, m->part_pq, st, s);
-            timer.after(j, s);
-            const int nb2 = launch_update64(n, x, m->r, m->p, m->q, dinv, m->part_pq, nb1,
-                                            m->part_rz, it, st, s);
-            launch_pupdate64(n, m->p, m->r, dinv, m->part_rz, nb2, it, st, s);
-        }
+        ChunkTimer timer(m, graph ? 0 : k, 0);
+        const int it_before = launched;
+        launched += enqueue(k, iter, graph, itb, &timer, s);
         check_launch();
-        launched += k;
         poll(m, s);
-        timer.collect(it_before, h.iters);
-        it_before = h.iters;
-        if (h.done || launched >= o.maxit) break;
-        if (rr_prev < 0.0) {
-            rr_prev = h.rr_first;
-            it_prev = 0;
-        }
+        timer.collect(it_before, max_iters(h, S));
+        if (all_done(h, S) || launched >= o.maxit) break;
         const int fallback = o.poll_every > 0 ? o.poll_every : std::max(8, chunk);
-        chunk = o.poll_every > 0 ? o.poll_every
-                                 : predict_chunk(rr_prev, it_prev, h.rr, h.iters, h.tol2, fallback);
-        rr_prev = h.rr;
-        it_prev = h.iters;
+        chunk = o.poll_every > 0 ? o.poll_every : pred.next(h, S, fallback);
     }
-    const int status = h.status;
-    const int iters = h.iters;
-    const double bb = h.bb;
-    const double relres = bb > 0.0 ? std::sqrt(h.rr / bb) : std::sqrt(h.rr);
-    // True residual of the returned iterate.
-    launch_state_init(chk, 0.0, 0, s);
-    launch_residual64(A, cfg, b, x, m->r, m->partials, chk, 0, s);
+    const int iters = max_iters(h, S);
+    // true residual of the returned iterates
+    launch_state_init(chk, S, 0.0, 0, nullptr, s);
+    launch_residual64(A, cfg, b, x, m->r, m->partials, chk, smp, 0, s);
     check_launch();
     poll(m, s);
-    const PcgState& c = m->st_host[2];
-    if (info) {
-        info->status = status;
-        info->iters = iters;
-        info->outer = 0;
-        info->launched = launched;
-        info->relres = relres;
-        info->relres_true = c.bb > 0.0 ? std::sqrt(c.rr / c.bb) : std::sqrt(c.rr);
-    }
+    fill_info(info, h, h + 2 * S, S, launched, 0);
     if (iters_out) *iters_out = iters;
-    return status;
+    return worst_status(h, S);
 }
 
-rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const double* dinv_in,
+rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const double* dinv_in,
                        const float* dinv32_in, const double* b, double* x, const SolveOpts& o,
                        rafem_solve_info* info, hipStream_t s, int hint, int* iters_out) {
+    const int S = smp.S;
     PcgState* inner = m->st;
-    PcgState* outer = m->st + 1;
-    const SpmvConfig& cfg = m->spmv;
+    PcgState* outer = m->st + S;
     const int n = A.n;
-    launch_state_init(outer, o.tol, o.max_outer, s);
+    int* itb = m->itb + 1;
+    launch_state_init(outer, S, o.tol, o.max_outer, nullptr, s);
     const double* dinv = dinv_in;
     const float* dinv32 = dinv32_in;
     if (!dinv || !dinv32) {
-        if (A.sell) throw Error{RAFEM_E_STATE, "slab-layout solve without a Jacobi inverse"};
+        if (A.sell || S != 1) throw Error{RAFEM_E_STATE, "slab-layout solve without a Jacobi inverse"};
         launch_diag_inv(A, m->dinv, m->dinv32, outer, s);
         dinv = m->dinv;
         dinv32 = m->dinv32;
     }
+    const Iter32 iter{m, &A, &m->spmv32, dinv32, inner, smp, itb};
+    hipGraphExec_t graph = nullptr;
+    if (m->use_graphs && !m->prof_on)
+        graph = chunk_graph(m, 1, A.v32, dinv32, A.sell ? (const void*)A.sptr : (const void*)A.rp,
+                            nullptr, iter, itb);
     int total_inner = 0, launched_total = 0, outer_steps = 0;
     int chunk0 = first_chunk(o, hint);
-    double prev_outer_rr = -1.0;
-    int stagnant = 0;
+    std::vector<double> prev_rr(S, -1.0);
+    std::vector<int> stagnant(S, 0);
     bool fell_back = false;
-    PcgState& hi = m->st_host[0];
-    PcgState& ho = m->st_host[1];
+    const PcgState* hi = m->st_host;
+    PcgState* ho = m->st_host + S;
     while (true) {
-        launch_residual64(A, cfg, b, x, m->r64, m->partials, outer, 1, s);
-        launch_inner_start(n, m->r64, outer, m->r32, m->d32, m->p32, dinv32, o.inner_tol,
-                           o.maxit, m->partials, inner, s);
+        launch_residual64(A, m->spmv, b, x, m->r64, m->partials, outer, smp, 1, s);
+        launch_inner_start(n, m->r64, outer, m->r32, m->d32, m->p32, dinv32, o.inner_tol, o.maxit,
+                           m->partials, inner, smp, s);
+        launch_state_init(nullptr, 0, 0.0, 0, itb, s);  // inner iteration counter = 0
         check_launch();
-        poll(m, s);  // outer convergence is decided by the residual just computed
-        if (ho.done) break;
+        poll(m, s);  // outer convergence is decided by the residuals just computed
+        if (all_done(ho, S)) break;
         int launched = 0;
         int chunk = chunk0;
-        double rr_prev = -1.0;
-        int it_prev = 0;
-        int it_before = 0;
+        Predictor pred(S);
         while (true) {
             const int k = std::min(chunk, o.maxit - launched);
-            ChunkTimer timer(m, k, 1);
-            for (int j = 0; j < k; ++j) {
-                const int it = launched + j;
-                timer.before(j, s);
-                const int nb1 = launch_spmv_dot32(A, cfg, m->p32, m->q32, m->part_pq, inner, s);
-                timer.after(j, s);
-                const int nb2 = launch_update32(n, m->d32, m->r32, m->p32, m->q32, dinv32,
-                                                m->part_pq, nb1, m->part_rz, it, inner, s);
-                launch_pupdate32(n, m->p32, m->r32, dinv32, m->part_rz, nb2, it, inner, s);
-            }
+            ChunkTimer timer(m, graph ? 0 : k, 1);
+            const int it_before = launched;
+            launched += enqueue(k, iter, graph, itb, &timer, s);
             check_launch();
-            launched += k;
             poll(m, s);
-            timer.collect(it_before, hi.iters);
-            it_before = hi.iters;
-            if (hi.done || launched >= o.maxit) break;
-            if (rr_prev < 0.0) {
-                rr_prev = hi.rr_first;
-                it_prev = 0;
-            }
-            chunk = o.poll_every > 0 ? o.poll_every
-                                     : predict_chunk(rr_prev, it_prev, hi.rr, hi.iters, hi.tol2,
-                                                     std::max(8, chunk));
-            rr_prev = hi.rr;
-            it_prev = hi.iters;
+            timer.collect(it_before, max_iters(hi, S));
+            if (all_done(hi, S) || launched >= o.maxit) break;
+            chunk = o.poll_every > 0 ? o.poll_every : pred.next(hi, S, std::max(8, chunk));
         }
-        total_inner += hi.iters;
+        const int it_in = max_iters(hi, S);
+        total_inner += it_in;
         launched_total += launched;
         outer_steps += 1;
         // next inner solve: the same number of iterations is a good first guess
-        if (o.poll_every <= 0 && hi.iters > 0) chunk0 = std::max(1, (int)(hi.iters * 0.95));
-        launch_refine_update(n, x, m->d32, outer, s);
+        if (o.poll_every <= 0 && it_in > 0) chunk0 = std::max(1, (int)(it_in * 0.95));
+        launch_refine_update(n, x, m->d32, outer, smp, s);
         check_launch();
-        // stagnation: the FP64 residual must at least halve per refinement
-        if (prev_outer_rr > 0.0 && ho.rr > 0.25 * prev_outer_rr) stagnant += 1;
-        else stagnant = 0;
-        prev_outer_rr = ho.rr;
-        if (stagnant >= 2) {
+        // Stagnation: each unfinished sample's FP64 residual must fall 4x per refinement.  A
+        // sample that fails twice is frozen (its refinement state is marked done, after the
+        // update just enqueued) and FP64 PCG finishes it once every other sample is through,
+        // so a sample's iterates never depend on the other samples of a batch.
+        bool frozen = false;
+        for (int q = 0; q < S; ++q) {
+            if (ho[q].done) continue;
+            if (prev_rr[q] > 0.0 && ho[q].rr > 0.25 * prev_rr[q]) stagnant[q] += 1;
+            else stagnant[q] = 0;
+            prev_rr[q] = ho[q].rr;
+            if (stagnant[q] >= 2) {
+                ho[q].done = 1;
+                frozen = true;
+            }
+        }
+        if (frozen) {
+            // the host copy of the refinement states is current: only the inner states have
+            // changed on the device since the last poll
+            RAFEM_HIP(hipMemcpyAsync(outer, ho, S * sizeof(PcgState), hipMemcpyHostToDevice, s));
             fell_back = true;
-            break;
         }
     }
     if (fell_back) {
+        // samples that converged under refinement exit FP64 PCG at once (its start computes
+        // the same residual), so only the frozen ones move
         rafem_solve_info sub{};
         SolveOpts o64 = o;
         o64.precision = RAFEM_FP64;
         int it64 = 0;
-        rafem_status st = pcg64(m, A, dinv, b, x, o64, &sub, s, 0, &it64);
+        const rafem_status st = pcg64(m, A, smp, dinv, b, x, o64, &sub, s, 0, &it64);
         if (info) {
             *info = sub;
             info->iters = total_inner + sub.iters;
@@ -250,17 +382,57 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const double* dinv_in,
         if (iters_out) *iters_out = total_inner + it64;
         return st;
     }
-    const int status = ho.status;
-    if (info) {
-        info->status = status;
-        info->iters = total_inner;
-        info->outer = outer_steps;
-        info->launched = launched_total;
-        info->relres = ho.bb > 0.0 ? std::sqrt(ho.rr / ho.bb) : std::sqrt(ho.rr);
-        info->relres_true = info->relres;  // the refinement residual is the true FP64 residual
-    }
+    // the refinement residual is the true FP64 residual of the returned iterate
+    fill_info(info, ho, nullptr, S, launched_total, outer_steps);
+    if (info) info->iters = total_inner;
     if (iters_out) *iters_out = total_inner;
-    return status;
+    return worst_status(ho, S);
+}
+
+void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
+    // Slab shapes of the SELL kernels: 2 or 4 slabs per wavefront (one or two groups of
+    // partial sums per workgroup, so results do not depend on the choice), chosen by timing
+    // the PCG SpMV (with its fused dot product) on this mesh's matrix, for FP64 and FP32
+    // values.  Both candidates keep workgroups inside one sample (kRowAlign is 16 slabs).
+    if (!A.sell) return;
+    const int S = m->S;
+    Samples smp{S, m->row_off};
+    PcgState* chk = m->st + 2 * S;
+    hipEvent_t e0, e1;
+    RAFEM_HIP(hipEventCreate(&e0));
+    RAFEM_HIP(hipEventCreate(&e1));
+    launch_fill(m->p, m->n, 0.0, s);
+    launch_fill32(m->p32, m->n, 0.0f, s);
+    launch_state_init(chk, S, 0.0, 0, nullptr, s);
+    for (int prec = 0; prec < 2; ++prec) {
+        SpmvConfig& target = prec ? m->spmv32 : m->spmv;
+        double best = 1e30;
+        int best_spb = target.slabs_per_block;
+        for (int spw : {2, 4}) {
+            SpmvConfig c = target;
+            c.slabs_per_block = 4 * spw;
+            auto run = [&]() {
+                if (prec) launch_spmv_dot32(A, c, m->p32, m->q32, m->part_pq, chk, smp, s);
+                else launch_spmv_dot64(A, c, m->p, m->q, m->part_pq, chk, smp, s);
+            };
+            for (int w = 0; w < 2; ++w) run();
+            RAFEM_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < 5; ++r) run();
+            RAFEM_HIP(hipEventRecord(e1, s));
+            RAFEM_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            RAFEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_spb = c.slabs_per_block;
+            }
+        }
+        target.slabs_per_block = best_spb;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    RAFEM_HIP(hipGetLastError());
+    m->tuned = true;
 }
 
 }  // namespace rafem

@@ -19,14 +19,17 @@ SolveOpts resolve_opts(const rafem_solve_opts* o, double default_tol);
 // FP64 Jacobi-PCG on A from x (in/out).  dinv may be NULL for a CSR matrix (then it is
 // computed from A's diagonal).
 // hint: expected iteration count (0 = unknown).  Fills info, returns its status.
-rafem_status pcg64(rafem_mesh m, const Mat& A, const double* dinv, const double* b, double* x,
+rafem_status pcg64(rafem_mesh m, const Mat& A, const Samples& smp, const double* dinv, const double* b, double* x,
                    const SolveOpts& o, rafem_solve_info* info, hipStream_t s, int hint,
                    int* iters_out);
 
 // FP32 inner PCG (on A.v32) inside FP64 iterative refinement (on A.v).  dinv/dinv32 may be
 // NULL for a CSR matrix.
-rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const double* dinv,
+rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const double* dinv,
                        const float* dinv32, const double* b, double* x, const SolveOpts& o,
                        rafem_solve_info* info, hipStream_t s, int hint, int* iters_out);
+
+// Pick the SELL slab shape of the FP64 and FP32 SpMV by timing them on A (sets m->tuned).
+void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s);
 
 }  // namespace rafem

@@ -71,3 +71,64 @@ class DeviceProblem:
 
     def close(self):
         self.mesh.close()
+
+
+class BatchProblem:
+    """An ensemble of problems (same element type, any sizes) advanced together.
+
+    The device vectors use the batch layout of the native handle: sample q's nodes start
+    at node_off[q] and are followed by padding nodes (isolated Dirichlet nodes held at 0).
+    Physical constants (rho c, dt, T_a, alpha) are taken from the first problem.
+    """
+
+    def __init__(self, problems, device=None):
+        import torch
+        self.torch = torch
+        self.problems = list(problems)
+        p0 = self.problems[0]
+        self.dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.mesh = rafem.Mesh.batch([(p.xyz, p.conn, p.dir_ids) for p in self.problems])
+        m = self.mesh
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        cat = lambda arrs: torch.as_tensor(np.concatenate(arrs), **f64).contiguous()
+        self.k_e = cat([p.k_e for p in self.problems])
+        self.perf_e = cat([p.perf_e for p in self.problems])
+        self.sigma0_e = cat([p.sigma0_e for p in self.problems])
+        dV, dT = np.zeros(m.n_dir), np.zeros(m.n_dir)
+        for q, p in enumerate(self.problems):
+            a = int(m.dir_off[q])
+            dV[a:a + p.dir_ids.size] = p.dir_V
+            dT[a:a + p.dir_ids.size] = p.dir_T
+        self.dir_V = torch.as_tensor(dV, **f64)
+        self.dir_T = torch.as_tensor(dT, **f64)
+        self.phys = rafem.Phys(p0.rho_c, p0.dt, p0.T_a, p0.alpha_sigma, p0.T_ref,
+                               1 if p0.coupled else 0, 0)
+        self.reset()
+
+    def _gather(self, per_sample):
+        out = np.zeros(self.mesh.n_nodes)
+        for q, v in enumerate(per_sample):
+            a = int(self.mesh.node_off[q])
+            out[a:a + v.size] = v
+        return out
+
+    def reset(self):
+        torch = self.torch
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        self.T = torch.as_tensor(self._gather([p.initial_T() for p in self.problems]), **f64)
+        self.V = torch.as_tensor(self._gather([p.initial_V() for p in self.problems]), **f64)
+
+    def sample(self, q: int):
+        """(T, V) of sample q as host arrays."""
+        a = int(self.mesh.node_off[q])
+        n = self.problems[q].n_nodes
+        return self.T[a:a + n].cpu().numpy(), self.V[a:a + n].cpu().numpy()
+
+    def step(self, tol: float = 1e-12, precision: str = "fp64", **kw):
+        info = rafem.step(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e, self.dir_V,
+                          self.dir_T, self.T, self.V, tol=tol, precision=precision, **kw)
+        self.phys.reuse_bioheat = 1
+        return info
+
+    def close(self):
+        self.mesh.close()

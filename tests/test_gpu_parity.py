@@ -201,6 +201,32 @@ def test_steps_are_deterministic(R):
     dp.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_steps_do_not_depend_on_stale_device_memory(R, precision):
+    """Device memory handed to a new mesh may hold anything: a mesh built on memory that
+    held NaN must step exactly as one built on fresh memory (no kernel may read an entry
+    that nothing wrote, such as the slab padding of the FP32 matrix values)."""
+    import torch
+    from paper_2409_13036_amd.sim import DeviceProblem
+    p = ri.make_problem("hex", 13, 5, steps=2)
+
+    def run():
+        dp = DeviceProblem(p)
+        states, infos = dp.simulate(2, tol=1e-13, precision=precision, keep=True)
+        dp.close()
+        return states, infos
+
+    clean, _ = run()
+    junk = torch.full((64 << 20,), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+    dirty, infos = run()
+    assert all(i["V"]["status"] == 0 and i["T"]["status"] == 0 for i in infos)
+    for (T1, V1), (T2, V2) in zip(clean, dirty):
+        assert np.array_equal(T1, T2) and np.array_equal(V1, V2)
+
+
 def test_solve_adjoint_matches_oracle(R):
     import torch
     p = ri.make_problem("hex", 13, 7)
