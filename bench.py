@@ -72,7 +72,7 @@ def measured_traffic(kernel: str):
     with open(path) as f:
         data = json.load(f)
     entry = data.get(kernel)
-    if not entry or entry.get("kernels_sha") != kernel_hash():
+    if not isinstance(entry, dict) or entry.get("kernels_sha") != kernel_hash():
         return None
     return entry.get("bytes_per_launch")
 
@@ -139,9 +139,10 @@ def run_path(dp, precision: str, steps: int, warmup: int, profile_steps: int, **
 def adjoint_leg(args) -> dict:
     """Differentiation workload: 101^3 hex, 60 coupled steps, lesion loss, gradients with respect
     to k_e and w_e by the reverse sweep (checkpoints every 10 steps), timed; then central
-    finite differences (relative step 1e-6) on 32 single parameters drawn from the 1% of
-    elements with the largest adjoint gradients (16 k_e, 16 w_e) and along the two directions
-    k and w (all entries scaled), forward solves at tol 1e-14."""
+    finite differences on 32 single parameters drawn from the 1% of elements with the
+    largest adjoint gradients (16 k_e at relative step 1e-6; 16 w_e at 0.1 and 0.05,
+    Richardson-extrapolated) and along the two directions k and w (all entries scaled),
+    forward solves at tol 1e-14."""
     import numpy as np
     import torch
     import rafem_inputs as ri
@@ -188,20 +189,32 @@ def adjoint_leg(args) -> dict:
 
     rows = []
     cases = []
+    # One element's perfusion moves the loss by ~1e-14 of itself at a 1e-6 relative step,
+    # below the solves' round-off.  It enters the element's mass coefficient beside
+    # rho_c/dt ~ 3.8e6, so even a 10% step changes that coefficient by < 1e-6 and the
+    # response stays linear far below the check's tolerance: those singles take h = 0.1
+    # and h/2, combined by Richardson extrapolation; |fd(h) - fd(h/2)| is reported.
     for which, e in picks:
         d = np.zeros(p.n_elems)
         d[e] = abs((p.k_e if which == "k" else p.perf_e)[e])
         cases.append((f"{which}[{e}]", d if which == "k" else 0 * d, d if which == "w" else 0 * d,
-                      1e-6))
-    cases.append(("direction k", p.k_e.copy(), 0 * p.k_e, 1e-6))
-    # perfusion moves T by ~1e-9 K at a 1e-6 step (FP64 round-off floor): 1e-3 in its direction
-    cases.append(("direction w", 0 * p.perf_e, p.perf_e.copy(), 1e-3))
-    for name, dk, dw, h in cases:
+                      1e-6 if which == "k" else 1e-1, which == "w"))
+    cases.append(("direction k", p.k_e.copy(), 0 * p.k_e, 1e-6, False))
+    # along the whole perfusion field a 1e-6 step moves T by ~1e-9 K: 1e-3 there
+    cases.append(("direction w", 0 * p.perf_e, p.perf_e.copy(), 1e-3, False))
+    for name, dk, dw, h, richardson in cases:
         fd = fd_along(dk, dw, h)
+        row = {"param": name, "h": h}
+        if richardson:
+            fd2 = fd_along(dk, dw, h / 2)
+            row["fd_h"], row["fd_h2"] = fd, fd2
+            row["h_vs_h2"] = abs(fd - fd2) / abs(fd2)
+            fd = (4.0 * fd2 - fd) / 3.0
         ad = float(gk @ dk + gw @ dw)
-        rows.append({"param": name, "h": h, "adjoint": ad, "fd": fd,
-                     "rel_err": abs(ad - fd) / abs(fd)})
-        print(f"[adjoint] {name} adjoint {ad:.10e} fd {fd:.10e} rel {rows[-1]['rel_err']:.2e}",
+        row.update({"adjoint": ad, "fd": fd, "rel_err": abs(ad - fd) / abs(fd)})
+        rows.append(row)
+        print(f"[adjoint] {name} adjoint {ad:.10e} fd {fd:.10e} rel {row['rel_err']:.2e}"
+              + (f" (h vs h/2 {row['h_vs_h2']:.1e})" if richardson else ""),
               file=sys.stderr, flush=True)
     dp.close()
     return {"workload": f"C3 adjoint, {args.n}^3 hex, {p.steps} steps, checkpoints every 10",
@@ -210,8 +223,121 @@ def adjoint_leg(args) -> dict:
             "fd_max_rel_err_k": max(r["rel_err"] for r in rows if r["param"].startswith("k")),
             "fd_max_rel_err_directional": max(r["rel_err"] for r in rows
                                               if r["param"].startswith("direction")),
-            "fd_max_rel_err_w_single": max(r["rel_err"] for r in rows if r["param"].startswith("w")),
+            "fd_max_rel_err_w": max(r["rel_err"] for r in rows if r["param"].startswith("w")),
             "fd": rows}
+
+
+def _counter_rows(d: str, counter: str):
+    """Per-dispatch values of one counter from a rocprofv3 --pmc output folder:
+    [(dispatch id, kernel name, value in KiB)]."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    per = {}
+    for fn in files:
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (fn, r["Dispatch_Id"])
+                name = r["Kernel_Name"]
+                per[key] = (name, per.get(key, (name, 0.0))[1] + float(r["Counter_Value"]))
+    return [(k[1], v[0], v[1]) for k, v in per.items()]
+
+
+def _short_kernel(name: str) -> str:
+    n = name.replace("(anonymous namespace)::", "").replace("rafem::", "").replace("void ", "")
+    return n.split("(")[0][:48]
+
+
+def trace_summary(d: str) -> None:
+    """Summary of a rocprofv3 --kernel-trace --stats folder: the kernel statistics table,
+    the gaps between consecutive dispatches (pairs seen >= 50 times, host syncs > 200 us
+    left out) and per-kernel durations without launches under 5 us (iterations enqueued
+    past convergence, which exit at once)."""
+    import csv
+    import glob
+    import statistics
+    st = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    if st:
+        with open(st[0]) as f:
+            rows = list(csv.DictReader(f))
+        print(f"{'kernel':50s} {'calls':>6s} {'avg_us':>9s} {'min_us':>8s} {'total_ms':>9s} "
+              f"{'pct':>6s}")
+        for r in rows[:24]:
+            print(f"{_short_kernel(r['Name']):50s} {int(r['Calls']):6d} "
+                  f"{float(r['AverageNs']) / 1e3:9.2f} {float(r['MinNs']) / 1e3:8.2f} "
+                  f"{float(r['TotalDurationNs']) / 1e6:9.2f} {float(r['Percentage']):6.2f}")
+    tr = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
+    if not tr:
+        return
+    with open(tr[0]) as f:
+        ks = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]),
+                     _short_kernel(r["Kernel_Name"])) for r in csv.DictReader(f))
+    gaps, per = {}, {}
+    for (s0, e0, n0), (s1, e1, n1) in zip(ks, ks[1:]):
+        g = (s1 - e0) / 1e3
+        if g < 200:
+            gaps.setdefault((n0, n1), []).append(g)
+    for s0, e0, n0 in ks:
+        per.setdefault(n0, []).append((e0 - s0) / 1e3)
+    print("\ngaps between consecutive kernels (us), pairs with >= 50 occurrences:")
+    for (a, b), v in sorted(gaps.items(), key=lambda kv: -len(kv[1])):
+        if len(v) >= 50:
+            print(f"  {a[:36]:36s} -> {b[:36]:36s} n={len(v):5d} "
+                  f"median={statistics.median(v):6.2f} mean={statistics.mean(v):6.2f}")
+    print("\nper-kernel durations excluding launches under 5 us (early exits):")
+    for n0, v in per.items():
+        w = [x for x in v if x >= 5.0]
+        if len(w) >= 20:
+            print(f"  {n0:48s} n={len(w):5d} (of {len(v)}) median={statistics.median(w):8.2f} "
+                  f"mean={statistics.mean(w):8.2f}")
+
+
+def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int) -> None:
+    """HBM bytes per launch of the PCG SpMV kernels from two rocprofv3 --pmc runs of
+    `bench.py --copy-probe-mib M ...` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).
+    Each counter is scaled by what it reads for the probe's plain copy of M MiB (the
+    copy dispatches with the largest values), and a kernel's figure is the mean over
+    its launches that did work (value >= 10% of its largest; launches enqueued past
+    convergence exit at once).  Writes profiles/traffic.json and prints a summary."""
+    import statistics
+    out = {"kernels_sha": kernel_hash(), "probe_mib": probe_mib}
+    lines = []
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _counter_rows(d, counter)
+        copies = [v for _, n, v in rows if "copy" in n.lower()]
+        if not copies:
+            raise SystemExit(f"{counter}: no copy dispatch found")
+        top = max(copies)
+        probe = [v for v in copies if v >= 0.5 * top]
+        factor = statistics.mean(probe) / (probe_mib * 1024.0)
+        out[f"{counter}_copy_factor"] = factor
+        lines.append(f"{counter}: copy probe {len(probe)} dispatches, mean "
+                     f"{statistics.mean(probe):.0f} KiB for {probe_mib * 1024} KiB moved "
+                     f"-> factor {factor:.4f}")
+        by = {}
+        for _, n, v in rows:
+            short = _short_kernel(n)
+            if short.startswith("k_sell") or short.startswith("k_csr"):
+                by.setdefault(short, []).append(v)
+        for name, vals in sorted(by.items()):
+            busy = [v for v in vals if v >= 0.1 * max(vals)]
+            kib = statistics.mean(busy)
+            e = out.setdefault(name, {"kernels_sha": kernel_hash()})
+            e[counter.lower() + "_bytes"] = kib * 1024.0 / factor
+            e[counter.lower() + "_launches"] = len(busy)
+            lines.append(f"  {name:34s} {len(busy):5d} of {len(vals):5d} launches, mean "
+                         f"{kib:10.0f} KiB -> {kib * 1024.0 / factor / 1e6:8.1f} MB scaled")
+    for name, e in out.items():
+        if isinstance(e, dict) and "fetch_size_bytes" in e and "write_size_bytes" in e:
+            e["bytes_per_launch"] = e["fetch_size_bytes"] + e["write_size_bytes"]
+            lines.append(f"{name}: HBM bytes per launch {e['bytes_per_launch'] / 1e6:.1f} MB")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("\n".join(lines))
 
 
 def batch_leg(args) -> dict:
@@ -257,10 +383,10 @@ def batch_leg(args) -> dict:
         R.profile_enable(bp.mesh, False)
         out[precision] = {
             "sample_steps_per_s": S * args.batch_steps / el, "elapsed_s": el,
-            "V_iters_last_step": [min(i["V"]["iters"] for i in its),
-                                  max(i["V"]["iters"] for i in its)],
-            "T_iters_last_step": [min(i["T"]["iters"] for i in its),
-                                  max(i["T"]["iters"] for i in its)],
+            "V_iters_last_step_min_max": [min(i["V"]["iters"] for i in its),
+                                          max(i["V"]["iters"] for i in its)],
+            "T_iters_last_step_min_max": [min(i["T"]["iters"] for i in its),
+                                          max(i["T"]["iters"] for i in its)],
             "spmv_us_mean": mean_us, "spmv_launches": count}
         print(f"[bench] batch {precision}: {S * args.batch_steps / el:.1f} sample-steps/s "
               f"({el:.2f} s), spmv {mean_us:.1f} us x {count}", file=sys.stderr, flush=True)
@@ -298,7 +424,18 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=30)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first launch a plain copy of this many MiB (byte-counter reference)")
+    ap.add_argument("--counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of a "
+                         "bench run with --copy-probe-mib into profiles/traffic.json")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="summarise a rocprofv3 --kernel-trace --stats output folder")
     args = ap.parse_args()
+    if args.summarize_trace:
+        trace_summary(args.summarize_trace)
+        return
+    if args.counters:
+        counters_summary(args.counters[0], args.counters[1], args.copy_probe_mib or 1024)
+        return
     if args.cpu_baseline_child:
         cpu_baseline_child(args.n)
         return

@@ -237,11 +237,12 @@ rafem_status rafem_spmv(rafem_mesh mesh, const int32_t* row_ptr_d, const int32_t
                         const float* vals32_d, const float* x32_d, float* y32_d, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Measurement.  While enabled, the SpMV of every PCG iteration that the solves on
- * this mesh enqueue is bracketed by a pair of HIP events on the solve's stream
- * (at most 2048 per chunk of iterations); after each chunk the durations of the
- * launches that performed an iteration are accumulated, launches skipped after
- * convergence are not.  Enabling creates the events, disabling destroys them.
+ * Measurement.  While enabled, the SpMV kernel of every PCG iteration that the solves
+ * on this mesh enqueue carries a pair of HIP events stamped when the kernel itself
+ * starts and ends (at most 2048 per chunk of iterations; the gap before a launch is not
+ * counted); after each chunk the durations of the launches that performed an iteration
+ * are accumulated, launches skipped after convergence are not.  Iteration chunks are not
+ * replayed as graphs meanwhile.  Enabling creates the events, disabling destroys them.
  * ------------------------------------------------------------------------- */
 rafem_status rafem_profile_enable(rafem_mesh mesh, int32_t enable);
 
@@ -320,7 +321,10 @@ rafem_status rafem_lesion_loss(rafem_mesh mesh, int64_t n_loss, const int32_t* i
                                double* loss_d, double* grad_d, void* stream);
 
 /* Per-sample solve information of the last rafem_step on this mesh (sample in
- * [0, n_samples)); for a single mesh, sample 0 repeats the step's own info. */
+ * [0, n_samples)); for a single mesh, sample 0 repeats the step's own info.  For a
+ * mixed-precision solve, iters counts that sample's FP32 inner iterations (plus FP64
+ * iterations if it fell back) and outer its refinements (negative: the refinement
+ * stagnated and FP64 PCG finished the sample). */
 rafem_status rafem_sample_info(rafem_mesh mesh, int32_t sample, rafem_step_info* out);
 
 #ifdef __cplusplus

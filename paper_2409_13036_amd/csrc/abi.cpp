@@ -168,14 +168,16 @@ void record_samples(rafem_mesh m, bool potential, bool mixed) {
     const int S = m->S;
     const PcgState* h = m->st_host;
     for (int q = 0; q < S; ++q) {
-        const PcgState& main = mixed ? h[S + q] : h[q];
+        // a mixed solve's sample that fell back to FP64 PCG ends with that solve's state
+        const bool fell = mixed && m->mixed_fell[q];
+        const PcgState& main = (mixed && !fell) ? h[S + q] : h[q];
         rafem_solve_info& o = potential ? m->sample_info[q].V : m->sample_info[q].T;
         o.status = main.status;
-        o.iters = main.iters;
-        o.outer = mixed ? main.iters : 0;
+        o.iters = mixed ? m->mixed_iters[q] : main.iters;
+        o.outer = mixed ? (fell ? -h[S + q].iters : main.iters) : 0;
         o.launched = 0;
         o.relres = main.bb > 0.0 ? std::sqrt(main.rr / main.bb) : std::sqrt(main.rr);
-        if (mixed) {
+        if (mixed && !fell) {
             o.relres_true = o.relres;
         } else {
             const PcgState& c = h[2 * S + q];

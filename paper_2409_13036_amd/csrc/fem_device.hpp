@@ -24,10 +24,29 @@ __device__ __forceinline__ int xcd_block(int bid, int nb) {
     return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// A double moved between lanes by one DPP pattern (both 32-bit halves; lanes without a
+// source read 0).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes in a fixed order, returned to every lane: pairs and quads by quad
+// permutations, rows of 16 by row shifts of 4 and 8 (lane 15 of a row holds its sum), then
+// the rows by the row broadcasts of lanes 15 and 31 (lane 63 ends with the total).  All
+// register-to-register: no LDS round trips.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return v;
+    v += dpp_move<0xb1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4e>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x114>(v);  // row_shr:4
+    v += dpp_move<0x118>(v);  // row_shr:8
+    v += dpp_move<0x142>(v);  // row_bcast:15
+    v += dpp_move<0x143>(v);  // row_bcast:31
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), WAVE - 1);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), WAVE - 1);
+    return __hiloint2double(hi, lo);
 }
 
 // Sum K values over the block in a fixed order; result in thread 0.

@@ -154,10 +154,13 @@ void launch_pcg_start(const Mat& A, const SpmvConfig& c, const double* b, const 
 //   pupdate:   rz', rr = sum(rz_part); stop on convergence / limit / breakdown, else
 //              beta = rz' / rz[it&1]; p = D^-1 r + beta p; rz[(it+1)&1] = rz'.
 // All three skip the samples whose st->done is set.
+// ev0 / ev1 (optional): events stamped at the kernel's own start and end
 GridInfo launch_spmv_dot64(const Mat& A, const SpmvConfig& c, const double* p, double* q,
-                           double* pq_part, PcgState* st, const Samples& smp, hipStream_t s);
+                           double* pq_part, PcgState* st, const Samples& smp, hipStream_t s,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 GridInfo launch_spmv_dot32(const Mat& A, const SpmvConfig& c, const float* p, float* q,
-                           double* pq_part, PcgState* st, const Samples& smp, hipStream_t s);
+                           double* pq_part, PcgState* st, const Samples& smp, hipStream_t s,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int launch_update64(int n, double* x, double* r, const double* p, const double* q,
                     const double* dinv, const double* pq_part, const GridInfo& gpq,
                     double* rz_part, const int* itb, int j, PcgState* st, const Samples& smp,
@@ -303,6 +306,8 @@ struct rafem_mesh_s {
     int32_t* row_off = nullptr;         // device [S + 1]
     int32_t* row_off_one = nullptr;     // device {0, n}: the whole mesh as one system
     std::vector<rafem_step_info> sample_info;  // per-sample info of the last step
+    std::vector<int> mixed_iters;   // per sample: inner (+ FP64 fallback) iterations of the last mixed solve
+    std::vector<char> mixed_fell;   // per sample: 1 if that solve was finished by FP64 PCG
 
     // measurement of the SpMV kernels (rafem_profile_*)
     bool prof_on = false;

@@ -24,6 +24,7 @@
 //     are contiguous too for the banded meshes here.
 // Workgroups walk contiguous row ranges, remapped so each XCD (own L2) takes one
 // contiguous share of the rows.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -56,15 +57,31 @@ __device__ __forceinline__ void sample_blocks(const Samples& B, int s, int rpb, 
 }
 
 // Fixed-order totals of partial slots [b0, b1) of K arrays; returned to every thread.
+// Thread t adds slots b0 + t + WG u in increasing u (the order depends only on the offset
+// from b0, so a sample sums alike in any batch), then the block adds the threads.  The
+// slots come from the previous kernel (other XCDs' L2s): kRangeUnroll of them are loaded
+// at once so their latencies overlap.
+constexpr int kRangeUnroll = 8;
+
 template <int K>
 __device__ __forceinline__ void range_totals(const double* __restrict__ partials, int nb, int b0,
                                              int b1, double (&tot)[K]) {
     __shared__ double bcast[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int i = b0 + threadIdx.x; i < b1; i += WG) s += partials[k * nb + i];
-        tot[k] = s;
+    for (int k = 0; k < K; ++k) tot[k] = 0.0;
+    for (int base = b0 + (int)threadIdx.x; base < b1; base += kRangeUnroll * WG) {
+        double v[K][kRangeUnroll];
+#pragma unroll
+        for (int u = 0; u < kRangeUnroll; ++u) {
+            const int i = base + u * WG;
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k][u] = i < b1 ? partials[k * nb + i] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int u = 0; u < kRangeUnroll; ++u) tot[k] += v[k][u];
+        }
     }
     block_sum<K>(tot);
     if (threadIdx.x == 0) {
@@ -275,14 +292,18 @@ __global__ __launch_bounds__(WG) void k_sell(RowArgs<T> a) {
     const int nblk = gridDim.x;
     const int blk = xcd_block(blockIdx.x, nblk);
     const int s0 = blk * a.slabs_per_block;
-    if (skip_sample<T, MODE>(a, s0 * WAVE)) return;
     const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    // the wavefront's first slab pointers are read together with the sample state, so
+    // the two latencies overlap (sptr has nslabs + 1 entries)
+    const int sl0 = min(s0 + w, a.nslabs - 1);
+    const int base0 = a.sptr[sl0], end0 = a.sptr[sl0 + 1];
+    if (skip_sample<T, MODE>(a, s0 * WAVE)) return;
     const int s1 = min(s0 + a.slabs_per_block, a.nslabs);
     double acc[kMaxGroups][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     for (int i = 0; s0 + w + NWAVES * i < s1; ++i) {
         const int sl = s0 + w + NWAVES * i;
-        const int base = a.sptr[sl];
-        const int width = (a.sptr[sl + 1] - base) / WAVE;
+        const int base = i == 0 ? base0 : a.sptr[sl];
+        const int width = ((i == 0 ? end0 : a.sptr[sl + 1]) - base) / WAVE;
         const int r = sl * WAVE + lane;
         T sum;
         if constexpr (DELTA)
@@ -384,10 +405,12 @@ __global__ __launch_bounds__(WG) void k_update(int n, T* __restrict__ x, T* __re
     const int row0 = blk * kVecRowsPerBlock;
     const int s = sample_of(smp, row0);
     PcgState& S = st[s];
-    if (S.done) return;
+    // In a batch, finished samples skip their rows before loading them.  A single solve
+    // issues its loads first so that they overlap the read of the state (only launches
+    // enqueued past convergence waste them).
+    if (smp.S > 1 && S.done) return;
     const int it = *itb + j;
     const int i0 = row0 + threadIdx.x;
-    // issue this thread's loads before the partial sums so their latency overlaps
     T xv[VPT], rv[VPT], pv[VPT], qv[VPT], dv[VPT];
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
@@ -400,6 +423,7 @@ __global__ __launch_bounds__(WG) void k_update(int n, T* __restrict__ x, T* __re
             dv[u] = dinv[i];
         }
     }
+    if (S.done) return;
     int b0, b1;
     sample_blocks(smp, s, rpb_pq, b0, b1);
     double pq[1];
@@ -445,7 +469,7 @@ __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
     const int row0 = blk * kVecRowsPerBlock;
     const int s = sample_of(smp, row0);
     PcgState& S = st[s];
-    if (S.done) return;
+    if (smp.S > 1 && S.done) return;  // as in k_update
     const int it = *itb + j;
     const int i0 = row0 + threadIdx.x;
     T rv[VPT], pv[VPT], dv[VPT];
@@ -458,6 +482,7 @@ __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
             dv[u] = dinv[i];
         }
     }
+    if (S.done) return;
     int b0, b1;
     sample_blocks(smp, s, kVecRowsPerBlock, b0, b1);
     double tot[2];
@@ -581,13 +606,24 @@ __global__ __launch_bounds__(WG) void k_refine_update(int n, double* __restrict_
 inline int grid1(int64_t n) { return (int)((n + WG - 1) / WG); }
 inline int vec_blocks(int n) { return (n + kVecRowsPerBlock - 1) / kVecRowsPerBlock; }
 
+// A launch, optionally with events stamped when the kernel itself starts and ends (the
+// measurement mode: the events then time the kernel alone, not the gap before it).
+template <typename K, typename A>
+void launch_timed(K kernel, int nb, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, const A& a) {
+    if (ev0)
+        hipExtLaunchKernelGGL(kernel, dim3(nb), dim3(WG), 0, s, ev0, ev1, 0, a);
+    else
+        hipLaunchKernelGGL(kernel, dim3(nb), dim3(WG), 0, s, a);
+}
+
 template <typename T, int MODE>
-void launch_csr_kernel(int lanes, int nb, const RowArgs<T>& a, hipStream_t s) {
+void launch_csr_kernel(int lanes, int nb, const RowArgs<T>& a, hipStream_t s, hipEvent_t ev0,
+                       hipEvent_t ev1) {
     switch (lanes) {
-        case 2: hipLaunchKernelGGL((k_csr<T, 2, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((k_csr<T, 8, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
-        case 16: hipLaunchKernelGGL((k_csr<T, 16, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_csr<T, 4, MODE>), dim3(nb), dim3(WG), 0, s, a); break;
+        case 2: launch_timed(k_csr<T, 2, MODE>, nb, s, ev0, ev1, a); break;
+        case 8: launch_timed(k_csr<T, 8, MODE>, nb, s, ev0, ev1, a); break;
+        case 16: launch_timed(k_csr<T, 16, MODE>, nb, s, ev0, ev1, a); break;
+        default: launch_timed(k_csr<T, 4, MODE>, nb, s, ev0, ev1, a); break;
     }
 }
 
@@ -595,7 +631,8 @@ void launch_csr_kernel(int lanes, int nb, const RowArgs<T>& a, hipStream_t s) {
 template <typename T, int MODE>
 GridInfo launch_rows(const Mat& A, const T* vals, const SpmvConfig& c, const T* x, T* y,
                      const double* b, const double* dinv, double* pout, double* partials,
-                     PcgState* st, const Samples& smp, int outer_mode, hipStream_t s) {
+                     PcgState* st, const Samples& smp, int outer_mode, hipStream_t s,
+                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     RowArgs<T> a{A.rp, A.ci, A.sptr, A.scol, A.sdel, vals, x, y, b, dinv, pout, partials, st, smp,
                  A.n, A.nslabs, c.rows_per_block, c.slabs_per_block, outer_mode};
     GridInfo g;
@@ -605,14 +642,14 @@ GridInfo launch_rows(const Mat& A, const T* vals, const SpmvConfig& c, const T* 
         g.rpb = kSlabGroup * WAVE;
         if (nblk > 0) {
             if (A.sdel)
-                hipLaunchKernelGGL((k_sell<T, MODE, true>), dim3(nblk), dim3(WG), 0, s, a);
+                launch_timed(k_sell<T, MODE, true>, nblk, s, ev0, ev1, a);
             else
-                hipLaunchKernelGGL((k_sell<T, MODE, false>), dim3(nblk), dim3(WG), 0, s, a);
+                launch_timed(k_sell<T, MODE, false>, nblk, s, ev0, ev1, a);
         }
     } else {
         g.nb = blocks_for(A.n, c.rows_per_block);
         g.rpb = c.rows_per_block;
-        if (g.nb > 0) launch_csr_kernel<T, MODE>(c.lanes, g.nb, a, s);
+        if (g.nb > 0) launch_csr_kernel<T, MODE>(c.lanes, g.nb, a, s, ev0, ev1);
     }
     return g;
 }
@@ -665,15 +702,17 @@ void launch_pcg_start(const Mat& A, const SpmvConfig& c, const double* b, const 
 }
 
 GridInfo launch_spmv_dot64(const Mat& A, const SpmvConfig& c, const double* p, double* q,
-                           double* pq_part, PcgState* st, const Samples& smp, hipStream_t s) {
+                           double* pq_part, PcgState* st, const Samples& smp, hipStream_t s,
+                           hipEvent_t ev0, hipEvent_t ev1) {
     return launch_rows<double, ROW_DOT>(A, A.v, c, p, q, nullptr, nullptr, nullptr, pq_part, st,
-                                        smp, 0, s);
+                                        smp, 0, s, ev0, ev1);
 }
 
 GridInfo launch_spmv_dot32(const Mat& A, const SpmvConfig& c, const float* p, float* q,
-                           double* pq_part, PcgState* st, const Samples& smp, hipStream_t s) {
+                           double* pq_part, PcgState* st, const Samples& smp, hipStream_t s,
+                           hipEvent_t ev0, hipEvent_t ev1) {
     return launch_rows<float, ROW_DOT>(A, A.v32, c, p, q, nullptr, nullptr, nullptr, pq_part, st,
-                                       smp, 0, s);
+                                       smp, 0, s, ev0, ev1);
 }
 
 void launch_spmv64(const Mat& A, const SpmvConfig& c, const double* x, double* y,

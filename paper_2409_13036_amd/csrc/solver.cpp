@@ -84,7 +84,8 @@ int worst_status(const PcgState* h, int S) {
     return status;
 }
 
-// Event pairs around the SpMV launches of a chunk (measurement mode, no graphs).
+// Event pairs stamped at the start and end of the SpMV kernels of a chunk (measurement
+// mode, no graphs).
 struct ChunkTimer {
     rafem_mesh m;
     int rec = 0;
@@ -92,12 +93,8 @@ struct ChunkTimer {
     ChunkTimer(rafem_mesh mm, int k, int which) : m(mm), kind(which) {
         rec = m->prof_on ? std::min(k, kProfCap) : 0;
     }
-    void before(int j, hipStream_t s) {
-        if (j < rec) RAFEM_HIP(hipEventRecord(m->prof_ev[2 * j], s));
-    }
-    void after(int j, hipStream_t s) {
-        if (j < rec) RAFEM_HIP(hipEventRecord(m->prof_ev[2 * j + 1], s));
-    }
+    hipEvent_t start(int j) const { return j < rec ? m->prof_ev[2 * j] : nullptr; }
+    hipEvent_t stop(int j) const { return j < rec ? m->prof_ev[2 * j + 1] : nullptr; }
     // after the stream has been synchronised: launch j ran iff it_before + j < iters
     void collect(int it_before, int iters) {
         for (int j = 0; j < rec; ++j) {
@@ -122,9 +119,8 @@ struct Iter64 {
     int* itb;
     void operator()(int j, hipStream_t s, ChunkTimer* t) const {
         const int n = A->n;
-        if (t) t->before(j, s);
-        const GridInfo g1 = launch_spmv_dot64(*A, *cfg, m->p, m->q, m->part_pq, st, smp, s);
-        if (t) t->after(j, s);
+        const GridInfo g1 = launch_spmv_dot64(*A, *cfg, m->p, m->q, m->part_pq, st, smp, s,
+                                              t ? t->start(j) : nullptr, t ? t->stop(j) : nullptr);
         const int nb2 = launch_update64(n, x, m->r, m->p, m->q, dinv, m->part_pq, g1, m->part_rz,
                                         itb, j, st, smp, s);
         launch_pupdate64(n, m->p, m->r, dinv, m->part_rz, nb2, itb, j, st, smp, s);
@@ -142,9 +138,8 @@ struct Iter32 {
     int* itb;
     void operator()(int j, hipStream_t s, ChunkTimer* t) const {
         const int n = A->n;
-        if (t) t->before(j, s);
-        const GridInfo g1 = launch_spmv_dot32(*A, *cfg, m->p32, m->q32, m->part_pq, st, smp, s);
-        if (t) t->after(j, s);
+        const GridInfo g1 = launch_spmv_dot32(*A, *cfg, m->p32, m->q32, m->part_pq, st, smp, s,
+                                              t ? t->start(j) : nullptr, t ? t->stop(j) : nullptr);
         const int nb2 = launch_update32(n, m->d32, m->r32, m->p32, m->q32, dinv32, m->part_pq, g1,
                                         m->part_rz, itb, j, st, smp, s);
         launch_pupdate32(n, m->p32, m->r32, dinv32, m->part_rz, nb2, itb, j, st, smp, s);
@@ -307,6 +302,8 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
         graph = chunk_graph(m, 1, A.v32, dinv32, A.sell ? (const void*)A.sptr : (const void*)A.rp,
                             nullptr, iter, itb);
     int total_inner = 0, launched_total = 0, outer_steps = 0;
+    m->mixed_iters.assign(S, 0);
+    m->mixed_fell.assign(S, 0);
     int chunk0 = first_chunk(o, hint);
     std::vector<double> prev_rr(S, -1.0);
     std::vector<int> stagnant(S, 0);
@@ -337,6 +334,7 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
         }
         const int it_in = max_iters(hi, S);
         total_inner += it_in;
+        for (int q = 0; q < S; ++q) m->mixed_iters[q] += hi[q].iters;
         launched_total += launched;
         outer_steps += 1;
         // next inner solve: the same number of iterations is a good first guess
@@ -355,6 +353,7 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
             prev_rr[q] = ho[q].rr;
             if (stagnant[q] >= 2) {
                 ho[q].done = 1;
+                m->mixed_fell[q] = 1;
                 frozen = true;
             }
         }
@@ -373,6 +372,7 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
         o64.precision = RAFEM_FP64;
         int it64 = 0;
         const rafem_status st = pcg64(m, A, smp, dinv, b, x, o64, &sub, s, 0, &it64);
+        for (int q = 0; q < S; ++q) m->mixed_iters[q] += m->st_host[q].iters;
         if (info) {
             *info = sub;
             info->iters = total_inner + sub.iters;

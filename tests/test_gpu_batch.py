@@ -87,4 +87,17 @@ def test_batch_samples_converge_independently(torch_cuda):
     it_small = bp.mesh.sample_info(0)["V"]["iters"]
     it_big = bp.mesh.sample_info(1)["V"]["iters"]
     assert 0 < it_small < it_big
+    # mixed: per-sample inner iteration totals and refinement counts, as for single solves
+    bp.reset()
+    bp.step(1e-13, "mixed")
+    for q, p in enumerate(probs):
+        from paper_2409_13036_amd.sim import DeviceProblem
+        dp = DeviceProblem(p)
+        single = dp.step(1e-13, "mixed")
+        got = bp.mesh.sample_info(q)
+        for f in ("V", "T"):
+            assert got[f]["status"] == 0
+            assert got[f]["iters"] == single[f]["iters"] and got[f]["outer"] == single[f]["outer"]
+            assert got[f]["iters"] > got[f]["outer"] > 0
+        dp.close()
     bp.close()
