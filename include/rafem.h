@@ -106,6 +106,8 @@ typedef struct {
     int32_t slabs_per_block;     /* SELL shape of the FP64 SpMV (autotuned at the first step) */
     int32_t slabs_per_block32;   /* SELL shape of the FP32 SpMV */
     int32_t int16_columns;       /* 1 if the SpMV reads 16-bit column offsets */
+    int64_t slabs;               /* 64-row slabs of the SpMV layout */
+    int64_t shared_offset_slabs; /* slabs whose rows share one column-offset list */
 } rafem_mesh_stats;
 
 /* Build a mesh on the current device.
@@ -245,6 +247,16 @@ rafem_status rafem_spmv(rafem_mesh mesh, const int32_t* row_ptr_d, const int32_t
  * replayed as graphs meanwhile.  Enabling creates the events, disabling destroys them.
  * ------------------------------------------------------------------------- */
 rafem_status rafem_profile_enable(rafem_mesh mesh, int32_t enable);
+
+/* Timing of the PCG SpMV kernel (with its fused p.Ap) on this mesh's potential matrix as
+ * the last rafem_step assembled it (E_STATE before any step).  n_copies >= 1 copies of
+ * its values (FP64, or FP32 for RAFEM_MIXED) are made and reps launches rotate through
+ * them, so that with enough copies no launch finds its values in the 256 MB Infinity
+ * Cache; each launch is timed by events stamped at the kernel's own start and end.
+ * mean_us receives the mean duration.  Allocates and frees the copies (E_NOMEM if they do
+ * not fit) and synchronises; a measurement call, not part of a step. */
+rafem_status rafem_spmv_timing(rafem_mesh mesh, int32_t precision, int32_t n_copies,
+                               int32_t reps, double* mean_us);
 
 /* Mean duration in microseconds and number of the SpMV launches measured since the
  * last reset, for the FP64 kernel (precision RAFEM_FP64) or the FP32 kernel of the

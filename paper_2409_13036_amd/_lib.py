@@ -31,7 +31,7 @@ EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafe
            "rafem_solve", "rafem_solve_adjoint", "rafem_spmv", "rafem_profile_enable",
            "rafem_profile_read", "rafem_step", "rafem_step_vjp", "rafem_lesion_loss",
            "rafem_mesh_create_batch", "rafem_mesh_sample_layout", "rafem_mesh_set_graphs",
-           "rafem_sample_info")
+           "rafem_sample_info", "rafem_spmv_timing")
 
 
 class RafemError(RuntimeError):
@@ -44,7 +44,8 @@ class MeshStats(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_elems", C.c_int64), ("nnz", C.c_int64),
                 ("n_dirichlet", C.c_int64), ("nodes_per_elem", C.c_int32), ("n_colours", C.c_int32),
                 ("n_samples", C.c_int32), ("slabs_per_block", C.c_int32),
-                ("slabs_per_block32", C.c_int32), ("int16_columns", C.c_int32)]
+                ("slabs_per_block32", C.c_int32), ("int16_columns", C.c_int32),
+                ("slabs", C.c_int64), ("shared_offset_slabs", C.c_int64)]
 
 
 class SolveOpts(C.Structure):
@@ -86,6 +87,7 @@ _lib.rafem_solve_adjoint.argtypes = [_p, _p, _p, _p, _p, _p, _p, C.POINTER(Solve
 _lib.rafem_spmv.argtypes = [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
 _lib.rafem_profile_enable.argtypes = [_p, _i32]
 _lib.rafem_profile_read.argtypes = [_p, _i32, C.POINTER(C.c_double), C.POINTER(C.c_int64), _i32]
+_lib.rafem_spmv_timing.argtypes = [_p, _i32, _i32, _i32, C.POINTER(C.c_double)]
 _lib.rafem_step.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts),
                             C.POINTER(StepInfo), _p]
 _lib.rafem_step_vjp.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
@@ -299,6 +301,15 @@ def profile_read(mesh: Mesh, precision: str = "fp64", reset: bool = True):
     prec = {"fp64": FP64, "mixed": MIXED}.get(precision, precision)
     _check(_lib.rafem_profile_read(mesh.handle, prec, C.byref(mean), C.byref(cnt), 1 if reset else 0))
     return float(mean.value), int(cnt.value)
+
+
+def spmv_timing(mesh: Mesh, precision: str = "fp64", copies: int = 1, reps: int = 20) -> float:
+    """rafem_spmv_timing -> mean duration (us) of the PCG SpMV on the mesh's potential matrix,
+    rotating through `copies` copies of its values (enough copies defeat the Infinity Cache)."""
+    mean = C.c_double(0.0)
+    prec = {"fp64": FP64, "mixed": MIXED}.get(precision, precision)
+    _check(_lib.rafem_spmv_timing(mesh.handle, prec, int(copies), int(reps), C.byref(mean)))
+    return float(mean.value)
 
 
 def assemble_csr(mesh: Mesh, stiff_coef=None, mass_coef=None, dir_vals=None, *, want_structure=True,

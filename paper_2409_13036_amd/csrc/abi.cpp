@@ -102,6 +102,8 @@ Mat step_matrix(rafem_mesh m, const double* v, const float* v32) {
     A.sptr = m->sptr;
     A.scol = m->scol;
     A.sdel = m->sdel;
+    A.sofs = m->sofs;
+    A.soff = m->soff;
     A.v = v;
     A.v32 = v32;
     return A;
@@ -149,6 +151,7 @@ void assemble_potential(rafem_mesh m, const rafem_phys* phys, const double* sigm
     assemble_into(m, SL, m->sell_nnz, nullptr, m->sigma, m->valsV, s);
     launch_lift((int)m->n, SL, m->valsV, m->valsV32, m->isD, m->gV, m->liftV, m->dinvV,
                 m->dinvV32, m->nD > 0, s);
+    m->potential_ready = true;
 }
 
 Samples step_samples(rafem_mesh m) { return Samples{m->S, m->row_off}; }
@@ -203,7 +206,7 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             if (!std::isfinite(xyz_h[i])) throw Error{RAFEM_E_MESH, "non-finite node coordinate"};
         const bool affine = check_geometry(n_elems, npe, conn_h, xyz_h);
         HostStructure S = build_structure(n_nodes, n_elems, npe, conn_h);
-        HostSell SL = build_sell(S, n_nodes);
+        HostSell SL = build_sell(S, n_nodes, node_off);
         std::vector<int32_t> colour(n_elems);
         const int ncol = colour_elements(n_nodes, n_elems, npe, conn_h, colour.data());
 
@@ -240,6 +243,9 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             m->rlen = dalloc<int32_t>(m, N);
             m->e2s = dalloc<int32_t>(m, E * (size_t)npe * npe);
             if (!SL.sdel.empty()) m->sdel = dalloc<int16_t>(m, SNNZ);
+            m->sofs = dalloc<int32_t>(m, (size_t)m->nslabs);
+            m->soff = dalloc<int32_t>(m, std::max<size_t>(1, SL.soff.size()));
+            for (int32_t o : SL.sofs) m->shared_slabs += o >= 0 ? 1 : 0;
             m->conn = dalloc<int32_t>(m, E * npe);
             m->xyz = dalloc<double>(m, 3 * N);
             m->colour_elems = dalloc<int32_t>(m, E);
@@ -298,6 +304,10 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             RAFEM_HIP(hipMemcpy(m->rlen, SL.rlen.data(), N * 4, hipMemcpyHostToDevice));
             if (m->sdel)
                 RAFEM_HIP(hipMemcpy(m->sdel, SL.sdel.data(), SNNZ * 2, hipMemcpyHostToDevice));
+            RAFEM_HIP(hipMemcpy(m->sofs, SL.sofs.data(), SL.sofs.size() * 4, hipMemcpyHostToDevice));
+            if (!SL.soff.empty())
+                RAFEM_HIP(hipMemcpy(m->soff, SL.soff.data(), SL.soff.size() * 4,
+                                    hipMemcpyHostToDevice));
             RAFEM_HIP(hipMemcpy(m->conn, conn_h, E * npe * 4, hipMemcpyHostToDevice));
             RAFEM_HIP(hipMemcpy(m->xyz, xyz_h, 3 * N * 8, hipMemcpyHostToDevice));
             RAFEM_HIP(hipMemcpy(m->colour_elems, order.data(), E * 4, hipMemcpyHostToDevice));
@@ -492,6 +502,8 @@ rafem_status rafem_mesh_get_stats(rafem_mesh m, rafem_mesh_stats* out) {
         out->slabs_per_block = m->spmv.slabs_per_block;
         out->slabs_per_block32 = m->spmv32.slabs_per_block;
         out->int16_columns = m->sdel ? 1 : 0;
+        out->shared_offset_slabs = m->shared_slabs;
+        out->slabs = m->nslabs;
         return RAFEM_OK;
     });
 }
@@ -589,6 +601,70 @@ rafem_status rafem_spmv(rafem_mesh m, const int32_t* row_ptr_d, const int32_t* c
                           s);
         }
         RAFEM_HIP(hipGetLastError());
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_spmv_timing(rafem_mesh m, int32_t precision, int32_t n_copies, int32_t reps,
+                               double* mean_us) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        require(precision == RAFEM_FP64 || precision == RAFEM_MIXED, "precision");
+        require(n_copies >= 1 && n_copies <= 64 && reps >= 1 && reps <= 100000 && mean_us,
+                "n_copies in [1, 64], reps in [1, 100000], mean_us");
+        if (!m->potential_ready) throw Error{RAFEM_E_STATE, "no step has assembled the matrix yet"};
+        const bool fp32 = precision == RAFEM_MIXED;
+        const size_t bytes = (size_t)m->sell_nnz * (fp32 ? sizeof(float) : sizeof(double));
+        std::vector<void*> copies(n_copies, nullptr);
+        std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+        auto release = [&]() {
+            for (void* c : copies)
+                if (c) (void)hipFree(c);
+            for (hipEvent_t e : ev)
+                if (e) (void)hipEventDestroy(e);
+        };
+        try {
+            for (auto& c : copies) {
+                if (hipMalloc(&c, bytes) != hipSuccess) {
+                    (void)hipGetLastError();
+                    c = nullptr;
+                    throw Error{RAFEM_E_NOMEM, "value copies do not fit in device memory"};
+                }
+                RAFEM_HIP(hipMemcpy(c, fp32 ? (const void*)m->valsV32 : (const void*)m->valsV,
+                                    bytes, hipMemcpyDeviceToDevice));
+            }
+            for (auto& e : ev) RAFEM_HIP(hipEventCreate(&e));
+            hipStream_t s = nullptr;
+            const int S = m->S;
+            Samples smp{S, m->row_off};
+            PcgState* chk = m->st + 2 * S;
+            launch_state_init(chk, S, 0.0, 0, nullptr, s);
+            launch_fill(m->p, m->n, 1.0, s);
+            launch_fill32(m->p32, m->n, 1.0f, s);
+            for (int r = 0; r < reps; ++r) {
+                Mat A = step_matrix(m, fp32 ? nullptr : (const double*)copies[r % n_copies],
+                                    fp32 ? (const float*)copies[r % n_copies] : nullptr);
+                if (fp32)
+                    launch_spmv_dot32(A, m->spmv32, m->p32, m->q32, m->part_pq, chk, smp, s,
+                                      ev[2 * r], ev[2 * r + 1]);
+                else
+                    launch_spmv_dot64(A, m->spmv, m->p, m->q, m->part_pq, chk, smp, s, ev[2 * r],
+                                      ev[2 * r + 1]);
+            }
+            RAFEM_HIP(hipGetLastError());
+            RAFEM_HIP(hipStreamSynchronize(s));
+            double sum = 0.0;
+            for (int r = 0; r < reps; ++r) {
+                float ms = 0.f;
+                RAFEM_HIP(hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]));
+                sum += 1000.0 * ms;
+            }
+            *mean_us = sum / reps;
+        } catch (...) {
+            release();
+            throw;
+        }
+        release();
         return RAFEM_OK;
     });
 }

@@ -42,10 +42,13 @@ struct HostSell {
     int64_t nslabs = 0;
     std::vector<int32_t> sptr;  // [nslabs + 1] element offset of each slab
     std::vector<int32_t> scol;  // [sptr[nslabs]] column ids, slab-major, entry-major within slab
-    std::vector<int32_t> rlen;  // [n] entries of each row (without padding)
+    std::vector<int32_t> rlen;  // [n] entries of each row that may be nonzero (no padding)
     std::vector<int16_t> sdel;  // column - row offsets, empty if some offset exceeds int16
+    std::vector<int32_t> sofs;  // [nslabs] start of a shared-offset slab's list in soff, or -1
+    std::vector<int32_t> soff;  // offset lists of the shared-offset slabs, slab by slab
 };
-HostSell build_sell(const HostStructure& S, int64_t n);
+// row_off: sample boundaries ({0, n} for one mesh); no slab offset crosses them.
+HostSell build_sell(const HostStructure& S, int64_t n, const std::vector<int64_t>& row_off);
 
 // Throws Error on bad input.
 void check_conn(int64_t n_nodes, int64_t n_elems, int npe, const int32_t* conn);
@@ -101,6 +104,8 @@ struct Mat {
     const int32_t* sptr = nullptr;  // SELL slab offsets [nslabs + 1]
     const int32_t* scol = nullptr;  // SELL column ids [sptr[nslabs]]
     const int16_t* sdel = nullptr;  // SELL column - row offsets, or NULL if they do not fit
+    const int32_t* sofs = nullptr;  // SELL [nslabs]: start of a slab's shared offsets, or -1
+    const int32_t* soff = nullptr;  // SELL shared offset lists
     const double* v = nullptr;      // values in the layout's order
     const float* v32 = nullptr;     // FP32 values in the layout's order (mixed precision)
 };
@@ -274,6 +279,9 @@ struct rafem_mesh_s {
     int32_t* e2s = nullptr;   // value position in the SELL layout of every (element, a, b)
     int affine = 0;           // every hex is a parallelepiped
     int16_t* sdel = nullptr;  // SELL column - row offsets (NULL when the bandwidth exceeds int16)
+    int32_t* sofs = nullptr;  // [nslabs] start of a shared-offset slab's list in soff, or -1
+    int32_t* soff = nullptr;  // offset lists of the shared-offset slabs
+    int64_t shared_slabs = 0;
     int32_t* conn = nullptr;
     double* xyz = nullptr;
     int32_t* colour_elems = nullptr;
@@ -287,6 +295,7 @@ struct rafem_mesh_s {
     float *valsV32 = nullptr, *valsT32 = nullptr, *dinvV32 = nullptr, *dinvT32 = nullptr;
     double *rhs = nullptr, *bT = nullptr, *gtmp = nullptr, *coefT = nullptr;
     bool bioheat_ready = false;
+    bool potential_ready = false;  // a step has assembled the potential matrix
     double *adj_mu = nullptr, *adj_nu = nullptr, *adj_sbar = nullptr, *adj_dsig = nullptr;
     int hint_V = 0, hint_T = 0;  // iterations of the previous FP64 solves, first-chunk guess
 

@@ -152,6 +152,8 @@ struct RowArgs {
     const int* __restrict__ sptr;     // SELL
     const int* __restrict__ scol;
     const int16_t* __restrict__ sdel;
+    const int* __restrict__ sofs;     // shared-offset slabs
+    const int* __restrict__ soff;
     const T* __restrict__ val;
     const T* __restrict__ x;
     T* __restrict__ y;
@@ -255,6 +257,33 @@ __device__ __forceinline__ T sell_row(const COL* __restrict__ cp, const T* __res
     return sum;
 }
 
+// The same sum for a shared-offset slab: entry j of every row has column row + off[j],
+// off being one list for the whole wavefront (read through the scalar cache), so the x
+// reads of one entry are 64 consecutive words.  Same order of operations as sell_row; the
+// entries that are not in the matrix hold 0 and add exactly nothing.
+template <typename T>
+__device__ __forceinline__ T sell_row_shared(const int* __restrict__ off, const T* __restrict__ vp,
+                                             const T* __restrict__ xr, int width) {
+    T sum = T(0);
+    int j = 0;
+    for (; j + kSellUnroll <= width; j += kSellUnroll) {
+        int c[kSellUnroll];
+        T v[kSellUnroll];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) {
+            c[u] = off[j + u];
+            v[u] = vp[(j + u) * WAVE];
+        }
+        T g[kSellUnroll];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) g[u] = xr[c[u]];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) sum += v[u] * g[u];
+    }
+    for (; j < width; ++j) sum += vp[j * WAVE] * xr[off[j]];
+    return sum;
+}
+
 // Partial sums of the SELL kernels cover fixed groups of kSlabGroup slabs, whatever the
 // workgroup shape, and are formed in a fixed order (per slab: wavefront butterfly; within
 // a group: wavefront w adds its slabs w, w + 4 in that order; then the four wavefronts in
@@ -292,11 +321,12 @@ __global__ __launch_bounds__(WG) void k_sell(RowArgs<T> a) {
     const int nblk = gridDim.x;
     const int blk = xcd_block(blockIdx.x, nblk);
     const int s0 = blk * a.slabs_per_block;
-    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);  // wave-uniform
     // the wavefront's first slab pointers are read together with the sample state, so
     // the two latencies overlap (sptr has nslabs + 1 entries)
     const int sl0 = min(s0 + w, a.nslabs - 1);
-    const int base0 = a.sptr[sl0], end0 = a.sptr[sl0 + 1];
+    const int base0 = a.sptr[sl0], end0 = a.sptr[sl0 + 1], so0 = a.sofs[sl0];
     if (skip_sample<T, MODE>(a, s0 * WAVE)) return;
     const int s1 = min(s0 + a.slabs_per_block, a.nslabs);
     double acc[kMaxGroups][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
@@ -304,9 +334,12 @@ __global__ __launch_bounds__(WG) void k_sell(RowArgs<T> a) {
         const int sl = s0 + w + NWAVES * i;
         const int base = i == 0 ? base0 : a.sptr[sl];
         const int width = ((i == 0 ? end0 : a.sptr[sl + 1]) - base) / WAVE;
+        const int so = i == 0 ? so0 : a.sofs[sl];
         const int r = sl * WAVE + lane;
         T sum;
-        if constexpr (DELTA)
+        if (so >= 0)
+            sum = sell_row_shared<T>(a.soff + so, a.val + base + lane, a.x + r, width);
+        else if constexpr (DELTA)
             sum = sell_row<T, int16_t>(a.sdel + base + lane, a.val + base + lane,
                                        a.x + min(r, a.n - 1), width);
         else
@@ -633,8 +666,10 @@ GridInfo launch_rows(const Mat& A, const T* vals, const SpmvConfig& c, const T* 
                      const double* b, const double* dinv, double* pout, double* partials,
                      PcgState* st, const Samples& smp, int outer_mode, hipStream_t s,
                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
-    RowArgs<T> a{A.rp, A.ci, A.sptr, A.scol, A.sdel, vals, x, y, b, dinv, pout, partials, st, smp,
-                 A.n, A.nslabs, c.rows_per_block, c.slabs_per_block, outer_mode};
+    RowArgs<T> a{A.rp,   A.ci, A.sptr, A.scol,   A.sdel, A.sofs, A.soff,
+                 vals,   x,    y,      b,        dinv,   pout,   partials,
+                 st,     smp,  A.n,    A.nslabs, c.rows_per_block, c.slabs_per_block,
+                 outer_mode};
     GridInfo g;
     if (A.sell) {
         const int nblk = blocks_for(A.nslabs, c.slabs_per_block);

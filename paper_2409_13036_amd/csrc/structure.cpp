@@ -104,59 +104,117 @@ HostStructure build_structure(int64_t n, int64_t E, int npe, const int32_t* conn
     return S;
 }
 
-HostSell build_sell(const HostStructure& S, int64_t n) {
+HostSell build_sell(const HostStructure& S, int64_t n, const std::vector<int64_t>& row_off) {
     // Slabs of 64 consecutive rows, one row per lane of a wavefront.  Entry j of row r
     // lives at sptr[r / 64] + (r % 64) + 64 j, so a wavefront reading entry j of its 64
-    // rows touches 64 consecutive words.  A slab is as wide as its longest row; shorter
-    // rows are padded with value 0 and their own row index as column (a valid x index).
+    // rows touches 64 consecutive words.  A slab is as wide as its longest row.
+    //
+    // Shared-offset slabs: when the column offsets (column - row) of a full slab's rows
+    // together take no more distinct values than the slab is wide, entry j of every row
+    // of the slab is given the same offset U[j] (U sorted ascending), its value being 0
+    // where (r, r + U[j]) is not an entry of the matrix.  The SpMV then reads one offset
+    // list per slab instead of one offset per entry, and its x reads are contiguous.  This
+    // holds for every slab of the grid meshes away from the first and last planes (rows
+    // on a boundary have a subset of the interior stencil).  Every r + U[j] must lie in
+    // the rows of the slab's own sample (row_off), so a slab never reads another sample.
+    //
+    // Other slabs: shorter rows are padded with value 0 and their own row index as column
+    // (a valid x index).  In both kinds the columns of a row ascend along its entries.
     HostSell L;
     L.nslabs = (n + 63) / 64;
     L.sptr.assign(L.nslabs + 1, 0);
+    L.sofs.assign(L.nslabs, -1);
     L.rlen.assign(n, 0);
+    std::vector<std::vector<int32_t>> shared(L.nslabs);
+    std::vector<int32_t> width(L.nslabs, 0);
+    parallel_for(L.nslabs, [&](int64_t s_lo, int64_t s_hi) {
+        std::vector<int32_t> U;
+        for (int64_t s = s_lo; s < s_hi; ++s) {
+            const int64_t r0 = s * 64, r1 = std::min<int64_t>(n, r0 + 64);
+            int32_t w = 0;
+            for (int64_t r = r0; r < r1; ++r) w = std::max(w, S.row_ptr[r + 1] - S.row_ptr[r]);
+            width[s] = w;
+            // the sample holding row r0
+            const size_t q = (size_t)(std::upper_bound(row_off.begin(), row_off.end(), r0) -
+                                      row_off.begin()) - 1;
+            const int64_t lo = row_off[q], hi = row_off[q + 1];
+            if (r1 - r0 != 64 || r1 > hi) continue;
+            U.clear();
+            for (int64_t r = r0; r < r1; ++r)
+                for (int32_t k = S.row_ptr[r]; k < S.row_ptr[r + 1]; ++k)
+                    U.push_back((int32_t)(S.col_idx[k] - r));
+            std::sort(U.begin(), U.end());
+            U.erase(std::unique(U.begin(), U.end()), U.end());
+            bool ok = (int32_t)U.size() <= w;
+            for (size_t j = 0; ok && j < U.size(); ++j)
+                ok = r0 + U[j] >= lo && r1 - 1 + U[j] < hi;
+            if (ok) {
+                width[s] = (int32_t)U.size();
+                shared[s] = U;
+            }
+        }
+    });
     int64_t total = 0;
     for (int64_t s = 0; s < L.nslabs; ++s) {
-        int32_t w = 0;
-        for (int64_t r = s * 64; r < std::min<int64_t>(n, s * 64 + 64); ++r)
-            w = std::max(w, S.row_ptr[r + 1] - S.row_ptr[r]);
-        total += 64 * (int64_t)w;
+        total += 64 * (int64_t)width[s];
         if (total > INT32_MAX) throw Error{RAFEM_E_MESH, "padded slab storage exceeds INT32_MAX"};
         L.sptr[s + 1] = (int32_t)total;
+        if (!shared[s].empty()) {
+            L.sofs[s] = (int32_t)L.soff.size();
+            L.soff.insert(L.soff.end(), shared[s].begin(), shared[s].end());
+        }
     }
     L.scol.assign(total, 0);
-    for (int64_t s = 0; s < L.nslabs; ++s) {
-        const int32_t base = L.sptr[s];
-        const int32_t w = (L.sptr[s + 1] - base) / 64;
-        for (int64_t lane = 0; lane < 64; ++lane) {
-            const int64_t r = s * 64 + lane;
-            const int32_t pad = (int32_t)std::min<int64_t>(r, n - 1);
-            int32_t len = 0;
-            if (r < n) {
-                len = S.row_ptr[r + 1] - S.row_ptr[r];
-                L.rlen[r] = len;
-                for (int32_t j = 0; j < len; ++j)
-                    L.scol[base + lane + 64 * (int64_t)j] = S.col_idx[S.row_ptr[r] + j];
+    parallel_for(L.nslabs, [&](int64_t s_lo, int64_t s_hi) {
+        for (int64_t s = s_lo; s < s_hi; ++s) {
+            const int32_t base = L.sptr[s];
+            const int32_t w = (L.sptr[s + 1] - base) / 64;
+            if (!shared[s].empty()) {
+                const std::vector<int32_t>& U = shared[s];
+                for (int64_t lane = 0; lane < 64; ++lane) {
+                    const int64_t r = s * 64 + lane;
+                    L.rlen[r] = w;
+                    for (int32_t j = 0; j < w; ++j)
+                        L.scol[base + lane + 64 * (int64_t)j] = (int32_t)(r + U[j]);
+                }
+                continue;
             }
-            for (int32_t j = len; j < w; ++j) L.scol[base + lane + 64 * (int64_t)j] = pad;
+            for (int64_t lane = 0; lane < 64; ++lane) {
+                const int64_t r = s * 64 + lane;
+                const int32_t pad = (int32_t)std::min<int64_t>(r, n - 1);
+                int32_t len = 0;
+                if (r < n) {
+                    len = S.row_ptr[r + 1] - S.row_ptr[r];
+                    L.rlen[r] = len;
+                    for (int32_t j = 0; j < len; ++j)
+                        L.scol[base + lane + 64 * (int64_t)j] = S.col_idx[S.row_ptr[r] + j];
+                }
+                for (int32_t j = len; j < w; ++j) L.scol[base + lane + 64 * (int64_t)j] = pad;
+            }
         }
-    }
+    });
     // 16-bit offsets to the row (padding: offset 0) when every column is within reach
-    bool fits = true;
-    for (int64_t s = 0; s < L.nslabs && fits; ++s)
-        for (int64_t k = L.sptr[s]; k < L.sptr[s + 1]; ++k) {
-            const int64_t r = std::min<int64_t>(s * 64 + (k - L.sptr[s]) % 64, n - 1);
-            const int64_t d = (int64_t)L.scol[k] - r;
-            if (d < INT16_MIN || d > INT16_MAX) {
-                fits = false;
-                break;
-            }
-        }
-    if (fits) {
-        L.sdel.resize(total);
-        for (int64_t s = 0; s < L.nslabs; ++s)
+    std::atomic<bool> fits{true};
+    parallel_for(L.nslabs, [&](int64_t s_lo, int64_t s_hi) {
+        for (int64_t s = s_lo; s < s_hi && fits.load(std::memory_order_relaxed); ++s)
             for (int64_t k = L.sptr[s]; k < L.sptr[s + 1]; ++k) {
                 const int64_t r = std::min<int64_t>(s * 64 + (k - L.sptr[s]) % 64, n - 1);
-                L.sdel[k] = (int16_t)((int64_t)L.scol[k] - r);
+                const int64_t d = (int64_t)L.scol[k] - r;
+                if (d < INT16_MIN || d > INT16_MAX) {
+                    fits = false;
+                    break;
+                }
             }
+    });
+    if (fits) {
+        L.sdel.resize(total);
+        parallel_for(L.nslabs, [&](int64_t s_lo, int64_t s_hi) {
+            for (int64_t s = s_lo; s < s_hi; ++s)
+                for (int64_t k = L.sptr[s]; k < L.sptr[s + 1]; ++k) {
+                    const int64_t r = std::min<int64_t>(s * 64 + (k - L.sptr[s]) % 64, n - 1);
+                    L.sdel[k] = (int16_t)((int64_t)L.scol[k] - r);
+                }
+        });
     }
     return L;
 }

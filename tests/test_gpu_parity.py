@@ -201,6 +201,41 @@ def test_steps_are_deterministic(R):
     dp.close()
 
 
+@pytest.mark.parametrize("kind", ["hex", "tet"])
+def test_grid_meshes_use_shared_offset_slabs(R, kind):
+    """On the grid meshes every full slab away from the first and last planes shares one
+    column-offset list (boundary rows hold a subset of the interior stencil); the steps
+    and solves above run through those slabs."""
+    p = ri.make_problem(kind, 26, 1)
+    mesh = _mesh(R, p)
+    st = mesh.stats()
+    plane_slabs = 2 * (26 * 26 + 26 + 1) // 64 + 4
+    assert st.slabs == (p.n_nodes + 63) // 64
+    assert st.shared_offset_slabs >= st.slabs - plane_slabs
+    mesh.close()
+
+
+def test_spmv_timing_entry_point(R):
+    from paper_2409_13036_amd.sim import DeviceProblem
+    p = ri.make_problem("hex", 13, 2)
+    dp = DeviceProblem(p)
+    with pytest.raises(R.RafemError, match="E_STATE"):
+        R.spmv_timing(dp.mesh, "fp64")
+    with pytest.raises(R.RafemError, match="E_ARG"):
+        R.spmv_timing(dp.mesh, "fp64", copies=0)
+    dp.step(1e-12)
+    for precision in ("fp64", "mixed"):
+        for copies in (1, 3):
+            t = R.spmv_timing(dp.mesh, precision, copies=copies, reps=6)
+            assert 0.0 < t < 1e5
+    # the solver's own buffers are left usable: the next step still matches the oracle
+    T0, V0 = to_host(dp.T), to_host(dp.V)
+    dp.step(1e-13)
+    ref = Model(p).step(T0, V0, 1e-15)
+    assert rel_err(to_host(dp.T), ref[0]) <= SOL_TOL and rel_err(to_host(dp.V), ref[1]) <= SOL_TOL
+    dp.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_steps_do_not_depend_on_stale_device_memory(R, precision):
     """Device memory handed to a new mesh may hold anything: a mesh built on memory that
