@@ -26,7 +26,8 @@
  *     device scalars on that stream and return only when the solve has finished.
  *   - Opaque handles (rafem_mesh) and their workspaces belong to the library:
  *     they are allocated in rafem_mesh_create and freed by rafem_mesh_destroy.
- *     No other entry point allocates device memory.
+ *     No other entry point allocates device memory, except the measurement call
+ *     rafem_spmv_timing (its own temporary copies).
  *   - Argument and mesh errors are detected on the host before anything is
  *     enqueued; on such an error nothing is enqueued and the outputs are
  *     untouched.  Numerical failures (no convergence, breakdown) are reported in
