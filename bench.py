@@ -218,7 +218,7 @@ def adjoint_leg(args) -> dict:
               file=sys.stderr, flush=True)
     dp.close()
     return {"workload": f"C3 adjoint, {args.n}^3 hex, {p.steps} steps, checkpoints every 10",
-            "loss": float(L), "forward_s": t1 - t0, "backward_s": t2 - t1,
+            "loss": float(L.detach()), "forward_s": t1 - t0, "backward_s": t2 - t1,
             "fd_checks": len(rows),
             "fd_max_rel_err_k": max(r["rel_err"] for r in rows if r["param"].startswith("k")),
             "fd_max_rel_err_directional": max(r["rel_err"] for r in rows
@@ -473,6 +473,7 @@ def main():
         workload = f"C1 coupled RFA step, {n}^3-node hex cube"
     dp = DeviceProblem(p)
     N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
+    mesh_stats = dp.mesh.stats()
     res = {}
     for precision in ("fp64", "mixed"):
         kw = {"inner_tol": args.inner_tol} if precision == "mixed" else {}
@@ -517,7 +518,9 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-inner/f64-refined" if fp32 else "f64", "data": "synthetic",
         "config": {"workload": workload, "n_nodes": N,
-                   "nnz": nnz, "dt_s": p.dt, "tol": TOL, "path": head},
+                   "nnz": nnz, "dt_s": p.dt, "tol": TOL, "path": head,
+                   "slabs": int(mesh_stats.slabs),
+                   "shared_offset_slabs": int(mesh_stats.shared_offset_slabs)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "bytes_per_launch": per_launch,
