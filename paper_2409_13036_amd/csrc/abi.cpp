@@ -159,11 +159,14 @@ Samples whole_mesh(rafem_mesh m) { return Samples{1, m->row_off_one}; }
 
 void solve_any(rafem_mesh m, const SolveOpts& o, const Mat& A, const Samples& smp,
                const double* dinv, const float* dinv32, const double* b, double* x,
-               rafem_solve_info* info, hipStream_t s, int hint, int* iters) {
-    if (o.precision == RAFEM_MIXED)
-        pcg_mixed(m, A, smp, dinv, dinv32, b, x, o, info, s, hint, iters);
+               rafem_solve_info* info, hipStream_t s, int kind) {
+    // kind: which solve of a step (its own chunk hints per precision), or -1 for none
+    const bool mixed = o.precision == RAFEM_MIXED;
+    std::vector<int>* hints = kind >= 0 ? &m->hints[kind][mixed ? 1 : 0] : nullptr;
+    if (mixed)
+        pcg_mixed(m, A, smp, dinv, dinv32, b, x, o, info, s, hints);
     else
-        pcg64(m, A, smp, dinv, b, x, o, info, s, hint, iters);
+        pcg64(m, A, smp, dinv, b, x, o, info, s, hints);
 }
 
 // Per-sample results of the solve that just finished (its last poll is in st_host).
@@ -547,9 +550,9 @@ rafem_status rafem_solve(rafem_mesh m, const int32_t* row_ptr_d, const int32_t* 
         hipStream_t s = (hipStream_t)stream;
         const Mat A = csr_matrix(m, row_ptr_d, col_idx_d, vals_d, vals32_d);
         if (o.precision == RAFEM_MIXED)
-            st = pcg_mixed(m, A, whole_mesh(m), nullptr, nullptr, b_d, x_d, o, info, s, 0, nullptr);
+            st = pcg_mixed(m, A, whole_mesh(m), nullptr, nullptr, b_d, x_d, o, info, s, nullptr);
         else
-            st = pcg64(m, A, whole_mesh(m), nullptr, b_d, x_d, o, info, s, 0, nullptr);
+            st = pcg64(m, A, whole_mesh(m), nullptr, b_d, x_d, o, info, s, nullptr);
         if (st != RAFEM_OK)
             set_error(st == RAFEM_E_NOCONV ? "iteration limit reached" : "PCG breakdown (p.Ap <= 0 or non-finite)");
         return st;
@@ -575,10 +578,10 @@ rafem_status rafem_solve_adjoint(rafem_mesh m, const int32_t* row_ptr_d, const i
         const Mat A = csr_matrix(m, row_ptr_d, col_idx_d, vals_d, vals32_d);
         rafem_status st;
         if (o.precision == RAFEM_MIXED)
-            st = pcg_mixed(m, A, whole_mesh(m), nullptr, nullptr, m->bT, lambda_d, o, info, s, 0,
+            st = pcg_mixed(m, A, whole_mesh(m), nullptr, nullptr, m->bT, lambda_d, o, info, s,
                            nullptr);
         else
-            st = pcg64(m, A, whole_mesh(m), nullptr, m->bT, lambda_d, o, info, s, 0, nullptr);
+            st = pcg64(m, A, whole_mesh(m), nullptr, m->bT, lambda_d, o, info, s, nullptr);
         if (st != RAFEM_OK)
             set_error(st == RAFEM_E_NOCONV ? "iteration limit reached" : "PCG breakdown (p.Ap <= 0 or non-finite)");
         return st;
@@ -738,13 +741,11 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
             assemble_potential(m, phys, sigma0_e_d, T_d, s);
             launch_set_dirichlet(m->dir_ids, m->gV, m->nD, V_d, s);
             RAFEM_HIP(hipGetLastError());
-            int it = 0;
             const Mat AV = step_matrix(m, m->valsV, m->valsV32);
             if (!m->tuned) autotune_spmv(m, AV, s);
             solve_any(m, o, AV, step_samples(m), m->dinvV, m->dinvV32, m->liftV, V_d, &inf.V, s,
-                      mixed ? 0 : m->hint_V, &it);
+                      kSolvePotential);
             record_samples(m, true, mixed);
-            if (!mixed) m->hint_V = it;
             if (inf.V.status != RAFEM_OK) {
                 set_error("potential solve failed");
                 return inf.V.status;
@@ -761,13 +762,11 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
         launch_finish_rhs((int)m->n, m->rhs, m->liftT, m->isD, m->bT, s);
         launch_set_dirichlet(m->dir_ids, m->gT, m->nD, T_d, s);
         RAFEM_HIP(hipGetLastError());
-        int it = 0;
         const Mat AT = step_matrix(m, m->valsT, m->valsT32);
         if (!m->tuned) autotune_spmv(m, AT, s);
         solve_any(m, o, AT, step_samples(m), m->dinvT, m->dinvT32, m->bT, T_d, &inf.T, s,
-                  mixed ? 0 : m->hint_T, &it);
+                  kSolveBioheat);
         record_samples(m, false, mixed);
-        if (!mixed) m->hint_T = it;
         if (inf.T.status != RAFEM_OK) {
             set_error("bioheat solve failed");
             return inf.T.status;
@@ -811,7 +810,7 @@ rafem_status rafem_step_vjp(rafem_mesh m, const rafem_phys* phys, const double* 
         launch_fill(m->adj_mu, m->n, 0.0, s);
         RAFEM_HIP(hipGetLastError());
         solve_any(m, o, step_matrix(m, m->valsT, m->valsT32), step_samples(m), m->dinvT,
-                  m->dinvT32, m->bT, m->adj_mu, &inf.T, s, 0, nullptr);
+                  m->dinvT32, m->bT, m->adj_mu, &inf.T, s, kSolveAdjointBioheat);
         if (inf.T.status != RAFEM_OK) {
             set_error("adjoint bioheat solve failed");
             return inf.T.status;
@@ -832,7 +831,7 @@ rafem_status rafem_step_vjp(rafem_mesh m, const rafem_phys* phys, const double* 
             launch_fill(m->adj_nu, m->n, 0.0, s);
             RAFEM_HIP(hipGetLastError());
             solve_any(m, o, step_matrix(m, m->valsV, m->valsV32), step_samples(m), m->dinvV,
-                      m->dinvV32, m->rhs, m->adj_nu, &inf.V, s, 0, nullptr);
+                      m->dinvV32, m->rhs, m->adj_nu, &inf.V, s, kSolveAdjointPotential);
             if (inf.V.status != RAFEM_OK) {
                 set_error("adjoint potential solve failed");
                 return inf.V.status;

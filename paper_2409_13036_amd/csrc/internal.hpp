@@ -250,6 +250,10 @@ void launch_finish_rhs(int n, const double* rhs, const double* lift, const uint8
 // ---------------------------------------------------------------------------
 }  // namespace rafem
 
+// The solves of a step and of its reverse, each with its own chunk hints.
+constexpr int kSolvePotential = 0, kSolveBioheat = 1, kSolveAdjointBioheat = 2,
+              kSolveAdjointPotential = 3;
+
 struct rafem_mesh_s {
     int64_t n = 0, E = 0, nnz = 0, nD = 0;
     int npe = 0, n_colours = 0;
@@ -297,7 +301,8 @@ struct rafem_mesh_s {
     bool bioheat_ready = false;
     bool potential_ready = false;  // a step has assembled the potential matrix
     double *adj_mu = nullptr, *adj_nu = nullptr, *adj_sbar = nullptr, *adj_dsig = nullptr;
-    int hint_V = 0, hint_T = 0;  // iterations of the previous FP64 solves, first-chunk guess
+    // iteration counts of the previous solve of each kind and precision (first-chunk guesses)
+    std::vector<int> hints[4][2];
 
     // solver workspace
     double *r = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr, *r64 = nullptr;

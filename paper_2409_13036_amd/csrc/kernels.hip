@@ -203,27 +203,36 @@ __global__ __launch_bounds__(WG) void k_bioheat_rhs(const int* __restrict__ elem
     const double sg = with_joule ? sigma[e] : 0.0;
     double f = 0.0;
     if constexpr (NPE == 8) {
+        // The 8 threads of an element (8 consecutive lanes) split the quadrature: thread a
+        // evaluates the integrand at Gauss point a,
+        //   s_a = detJ (sum_b N_b T~_b + sigma |grad V|^2),
+        // and then forms rhs_a = sum_q N_a(q) s_q from the 8 values of its lane group.
+        double xi, et, ze;
+        gauss_point(a, xi, et, ze);
         double Ji[3][3];
-        double det = 0.0;
-        if constexpr (AFFINE) det = hex_affine_jacobian(X, Ji);
-        for (int q = 0; q < 8; ++q) {
-            double xi, et, ze;
-            gauss_point(q, xi, et, ze);
-            if constexpr (!AFFINE) det = hex_jacobian(X, xi, et, ze, Ji);
-            double Nw = 0.0, gv0 = 0.0, gv1 = 0.0, gv2 = 0.0, Na = 0.0;
+        const double det = AFFINE ? hex_affine_jacobian(X, Ji) : hex_jacobian(X, xi, et, ze, Ji);
+        double Nw = 0.0, gv0 = 0.0, gv1 = 0.0, gv2 = 0.0;
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                double Nb, d0, d1, d2;
-                hex_shape(b, xi, et, ze, Nb, d0, d1, d2);
-                if (b == a) Na = Nb;
-                Nw += Nb * Tw[b];
-                gv0 += Vb[b] * d0;
-                gv1 += Vb[b] * d1;
-                gv2 += Vb[b] * d2;
-            }
-            double gV[3];
-            grad_x(Ji, gv0, gv1, gv2, gV);
-            f += det * Na * (Nw + sg * (gV[0] * gV[0] + gV[1] * gV[1] + gV[2] * gV[2]));
+        for (int b = 0; b < 8; ++b) {
+            double Nb, d0, d1, d2;
+            hex_shape(b, xi, et, ze, Nb, d0, d1, d2);
+            Nw += Nb * Tw[b];
+            gv0 += Vb[b] * d0;
+            gv1 += Vb[b] * d1;
+            gv2 += Vb[b] * d2;
+        }
+        double gV[3];
+        grad_x(Ji, gv0, gv1, gv2, gV);
+        const double sq = det * (Nw + sg * (gV[0] * gV[0] + gV[1] * gV[1] + gV[2] * gV[2]));
+        const int lane0 = (int)(threadIdx.x % WAVE) & ~7;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double s_q = __shfl(sq, lane0 + q, WAVE);
+            double gx, gy, gz;
+            gauss_point(q, gx, gy, gz);
+            double Na, d0, d1, d2;
+            hex_shape(a, gx, gy, gz, Na, d0, d1, d2);
+            f += Na * s_q;
         }
     } else {
         double G[4][3];

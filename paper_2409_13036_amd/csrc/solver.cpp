@@ -30,15 +30,20 @@ int predict_one(double rr_prev, int it_prev, double rr, int it, double tol2, int
     if (it > it_prev && rr_prev > 0.0 && rr > 0.0 && rr < rr_prev && tol2 > 0.0) {
         const double rate = std::log(rr / rr_prev) / double(it - it_prev);  // < 0
         const double need = std::log(tol2 / rr) / rate;
-        if (std::isfinite(need)) return std::max(1, std::min(1024, (int)std::ceil(need * 1.02) + 1));
+        // a launch past convergence costs a few microseconds, a poll tens: overshoot a little
+        if (std::isfinite(need)) return std::max(1, std::min(1024, (int)std::ceil(need * 1.03) + 2));
     }
     return fallback;
 }
 
 int first_chunk(const SolveOpts& o, int hint) {
     if (o.poll_every > 0) return o.poll_every;
-    if (hint > 0) return std::max(1, (int)(hint * 0.95));
+    if (hint > 0) return hint;
     return 16;
+}
+
+int hint_at(const std::vector<int>* hints, size_t k) {
+    return hints && k < hints->size() ? (*hints)[k] : 0;
 }
 
 // Tracks the convergence of every unfinished sample between polls.
@@ -231,7 +236,7 @@ SolveOpts resolve_opts(const rafem_solve_opts* o, double default_tol) {
 
 rafem_status pcg64(rafem_mesh m, const Mat& A, const Samples& smp, const double* dinv_in,
                    const double* b, double* x, const SolveOpts& o, rafem_solve_info* info,
-                   hipStream_t s, int hint, int* iters_out) {
+                   hipStream_t s, std::vector<int>* hints) {
     const int S = smp.S;
     PcgState* st = m->st;
     PcgState* chk = m->st + 2 * S;
@@ -253,7 +258,7 @@ rafem_status pcg64(rafem_mesh m, const Mat& A, const Samples& smp, const double*
         graph = chunk_graph(m, 0, A.v, x, dinv, A.sell ? (const void*)A.sptr : (const void*)A.rp,
                             iter, itb);
     int launched = 0;
-    int chunk = first_chunk(o, hint);
+    int chunk = first_chunk(o, hint_at(hints, 0));
     Predictor pred(S);
     const PcgState* h = m->st_host;
     while (true) {
@@ -275,13 +280,13 @@ rafem_status pcg64(rafem_mesh m, const Mat& A, const Samples& smp, const double*
     check_launch();
     poll(m, s);
     fill_info(info, h, h + 2 * S, S, launched, 0);
-    if (iters_out) *iters_out = iters;
+    if (hints) hints->assign(1, iters);
     return worst_status(h, S);
 }
 
 rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const double* dinv_in,
                        const float* dinv32_in, const double* b, double* x, const SolveOpts& o,
-                       rafem_solve_info* info, hipStream_t s, int hint, int* iters_out) {
+                       rafem_solve_info* info, hipStream_t s, std::vector<int>* hints) {
     const int S = smp.S;
     PcgState* inner = m->st;
     PcgState* outer = m->st + S;
@@ -304,7 +309,7 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
     int total_inner = 0, launched_total = 0, outer_steps = 0;
     m->mixed_iters.assign(S, 0);
     m->mixed_fell.assign(S, 0);
-    int chunk0 = first_chunk(o, hint);
+    std::vector<int> counts;  // iterations of each inner solve
     std::vector<double> prev_rr(S, -1.0);
     std::vector<int> stagnant(S, 0);
     bool fell_back = false;
@@ -319,7 +324,10 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
         poll(m, s);  // outer convergence is decided by the residuals just computed
         if (all_done(ho, S)) break;
         int launched = 0;
-        int chunk = chunk0;
+        // first chunk: the same inner solve of the previous solve, else 90% of this one's last
+        int guess = hint_at(hints, counts.size());
+        if (guess <= 0 && !counts.empty()) guess = std::max(1, (int)(counts.back() * 0.9));
+        int chunk = first_chunk(o, guess);
         Predictor pred(S);
         while (true) {
             const int k = std::min(chunk, o.maxit - launched);
@@ -334,11 +342,10 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
         }
         const int it_in = max_iters(hi, S);
         total_inner += it_in;
+        counts.push_back(it_in);
         for (int q = 0; q < S; ++q) m->mixed_iters[q] += hi[q].iters;
         launched_total += launched;
         outer_steps += 1;
-        // next inner solve: the same number of iterations is a good first guess
-        if (o.poll_every <= 0 && it_in > 0) chunk0 = std::max(1, (int)(it_in * 0.95));
         launch_refine_update(n, x, m->d32, outer, smp, s);
         check_launch();
         // Stagnation: each unfinished sample's FP64 residual must fall 4x per refinement.  A
@@ -370,8 +377,7 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
         rafem_solve_info sub{};
         SolveOpts o64 = o;
         o64.precision = RAFEM_FP64;
-        int it64 = 0;
-        const rafem_status st = pcg64(m, A, smp, dinv, b, x, o64, &sub, s, 0, &it64);
+        const rafem_status st = pcg64(m, A, smp, dinv, b, x, o64, &sub, s, nullptr);
         for (int q = 0; q < S; ++q) m->mixed_iters[q] += m->st_host[q].iters;
         if (info) {
             *info = sub;
@@ -379,13 +385,13 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
             info->outer = -outer_steps;  // negative: refinement stagnated, FP64 PCG finished
             info->launched = launched_total + sub.launched;
         }
-        if (iters_out) *iters_out = total_inner + it64;
+        if (hints) *hints = counts;
         return st;
     }
     // the refinement residual is the true FP64 residual of the returned iterate
     fill_info(info, ho, nullptr, S, launched_total, outer_steps);
     if (info) info->iters = total_inner;
-    if (iters_out) *iters_out = total_inner;
+    if (hints) *hints = counts;
     return worst_status(ho, S);
 }
 
