@@ -234,26 +234,36 @@ constexpr int kSellUnroll = 9;
 
 // Sum over the entries of one row in entry order.  COL is int (absolute columns, xr = x)
 // or int16_t (offsets to the row, xr = x + row).
+// Entries go in batches of kSellUnroll whose loads are all issued before their x reads; a
+// last, shorter batch is masked (its missing entries add nothing), so a row of any width
+// keeps a whole batch of loads in flight (the 15-entry rows of the tet meshes: 9 + 6).
+// COL is int (absolute columns, xr = x) or int16_t (offsets to the row, xr = x + row).
+template <typename T, typename COL, bool MASKED>
+__device__ __forceinline__ void sell_batch(const COL* __restrict__ cp, const T* __restrict__ vp,
+                                           const T* __restrict__ xr, int j, int width, T& sum) {
+    int c[kSellUnroll];
+    T v[kSellUnroll];
+#pragma unroll
+    for (int u = 0; u < kSellUnroll; ++u) {
+        const bool in = !MASKED || j + u < width;
+        c[u] = in ? (int)cp[(j + u) * WAVE] : 0;
+        v[u] = in ? vp[(j + u) * WAVE] : T(0);
+    }
+    T g[kSellUnroll];
+#pragma unroll
+    for (int u = 0; u < kSellUnroll; ++u) g[u] = (!MASKED || j + u < width) ? xr[c[u]] : T(0);
+#pragma unroll
+    for (int u = 0; u < kSellUnroll; ++u)
+        if (!MASKED || j + u < width) sum += v[u] * g[u];
+}
+
 template <typename T, typename COL>
 __device__ __forceinline__ T sell_row(const COL* __restrict__ cp, const T* __restrict__ vp,
                                       const T* __restrict__ xr, int width) {
     T sum = T(0);
     int j = 0;
-    for (; j + kSellUnroll <= width; j += kSellUnroll) {
-        int c[kSellUnroll];
-        T v[kSellUnroll];
-#pragma unroll
-        for (int u = 0; u < kSellUnroll; ++u) {
-            c[u] = cp[(j + u) * WAVE];
-            v[u] = vp[(j + u) * WAVE];
-        }
-        T g[kSellUnroll];
-#pragma unroll
-        for (int u = 0; u < kSellUnroll; ++u) g[u] = xr[c[u]];
-#pragma unroll
-        for (int u = 0; u < kSellUnroll; ++u) sum += v[u] * g[u];
-    }
-    for (; j < width; ++j) sum += vp[j * WAVE] * xr[cp[j * WAVE]];
+    for (; j + kSellUnroll <= width; j += kSellUnroll) sell_batch<T, COL, false>(cp, vp, xr, j, width, sum);
+    if (j < width) sell_batch<T, COL, true>(cp, vp, xr, j, width, sum);
     return sum;
 }
 
@@ -261,26 +271,32 @@ __device__ __forceinline__ T sell_row(const COL* __restrict__ cp, const T* __res
 // off being one list for the whole wavefront (read through the scalar cache), so the x
 // reads of one entry are 64 consecutive words.  Same order of operations as sell_row; the
 // entries that are not in the matrix hold 0 and add exactly nothing.
+template <typename T, bool MASKED>
+__device__ __forceinline__ void shared_batch(const int* __restrict__ off, const T* __restrict__ vp,
+                                             const T* __restrict__ xr, int j, int width, T& sum) {
+    int c[kSellUnroll];
+    T v[kSellUnroll];
+#pragma unroll
+    for (int u = 0; u < kSellUnroll; ++u) {
+        const bool in = !MASKED || j + u < width;
+        c[u] = in ? off[j + u] : 0;
+        v[u] = in ? vp[(j + u) * WAVE] : T(0);
+    }
+    T g[kSellUnroll];
+#pragma unroll
+    for (int u = 0; u < kSellUnroll; ++u) g[u] = (!MASKED || j + u < width) ? xr[c[u]] : T(0);
+#pragma unroll
+    for (int u = 0; u < kSellUnroll; ++u)
+        if (!MASKED || j + u < width) sum += v[u] * g[u];
+}
+
 template <typename T>
 __device__ __forceinline__ T sell_row_shared(const int* __restrict__ off, const T* __restrict__ vp,
                                              const T* __restrict__ xr, int width) {
     T sum = T(0);
     int j = 0;
-    for (; j + kSellUnroll <= width; j += kSellUnroll) {
-        int c[kSellUnroll];
-        T v[kSellUnroll];
-#pragma unroll
-        for (int u = 0; u < kSellUnroll; ++u) {
-            c[u] = off[j + u];
-            v[u] = vp[(j + u) * WAVE];
-        }
-        T g[kSellUnroll];
-#pragma unroll
-        for (int u = 0; u < kSellUnroll; ++u) g[u] = xr[c[u]];
-#pragma unroll
-        for (int u = 0; u < kSellUnroll; ++u) sum += v[u] * g[u];
-    }
-    for (; j < width; ++j) sum += vp[j * WAVE] * xr[off[j]];
+    for (; j + kSellUnroll <= width; j += kSellUnroll) shared_batch<T, false>(off, vp, xr, j, width, sum);
+    if (j < width) shared_batch<T, true>(off, vp, xr, j, width, sum);
     return sum;
 }
 
