@@ -296,7 +296,7 @@ def trace_summary(d: str) -> None:
                   f"mean={statistics.mean(w):8.2f}")
 
 
-def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int) -> None:
+def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int, out_path: str = "") -> None:
     """HBM bytes per launch of the PCG SpMV kernels from two rocprofv3 --pmc runs of
     `bench.py --copy-probe-mib M ...` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).
     Each counter is scaled by what it reads for the probe's plain copy of M MiB (the
@@ -335,7 +335,7 @@ def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int) -> None:
         if isinstance(e, dict) and "fetch_size_bytes" in e and "write_size_bytes" in e:
             e["bytes_per_launch"] = e["fetch_size_bytes"] + e["write_size_bytes"]
             lines.append(f"{name}: HBM bytes per launch {e['bytes_per_launch'] / 1e6:.1f} MB")
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+    with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
         json.dump(out, f, indent=1)
     print("\n".join(lines))
 

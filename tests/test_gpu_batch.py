@@ -101,3 +101,49 @@ def test_batch_samples_converge_independently(torch_cuda):
             assert got[f]["iters"] > got[f]["outer"] > 0
         dp.close()
     bp.close()
+
+
+@pytest.mark.parametrize("kind", ["hex", "tet"])
+def test_batch_reverse_sweep_matches_single_adjoints(torch_cuda, kind):
+    """rafem_step_vjp on a batch handle: each sample's gradients with respect to its k_e
+    and w_e equal those of its own single-mesh reverse sweep."""
+    torch = torch_cuda
+    from paper_2409_13036_amd import _lib as R
+    from paper_2409_13036_amd.adjoint import lesion_loss
+    from paper_2409_13036_amd.sim import BatchProblem, DeviceProblem
+    steps, tol = 3, 1e-13
+    probs = [ri.make_problem(kind, n, 60 + q, steps=steps, with_loss=True, k_scale=ks,
+                             per_element_eps=False, name=f"a{q}")
+             for q, (n, ks) in enumerate([(9, 1.0), (12, 0.8), (7, 1.3)])]
+    bp = BatchProblem(probs)
+    m = bp.mesh
+    Ts, Vs = [bp.T.clone()], [bp.V.clone()]
+    for _ in range(steps):
+        bp.step(tol, "fp64")
+        Ts.append(bp.T.clone())
+        Vs.append(bp.V.clone())
+    # dL/dT^N of L = sum over samples of their lesion losses
+    ids = np.concatenate([p.loss_ids + int(m.node_off[q]) for q, p in enumerate(probs)])
+    tgt = np.concatenate([p.T_target for p in probs])
+    lam = torch.zeros(m.n_nodes, dtype=torch.float64, device="cuda")
+    R.lesion_loss(m, torch.as_tensor(ids, dtype=torch.int32, device="cuda"),
+                  torch.as_tensor(tgt, dtype=torch.float64, device="cuda"), Ts[-1], grad=lam)
+    gk = torch.zeros(m.n_elems, dtype=torch.float64, device="cuda")
+    gw = torch.zeros_like(gk)
+    bp.phys.reuse_bioheat = 1
+    for n in range(steps, 0, -1):
+        R.step_vjp(m, bp.phys, bp.k_e, bp.perf_e, bp.sigma0_e, bp.dir_V, bp.dir_T, Ts[n - 1],
+                   Vs[n], Ts[n], lam, gk, gw, tol=tol)
+    gk, gw = to_host(gk), to_host(gw)
+    bp.close()
+    for q, p in enumerate(probs):
+        dp = DeviceProblem(p)
+        k = torch.tensor(p.k_e, dtype=torch.float64, device="cuda", requires_grad=True)
+        w = torch.tensor(p.perf_e, dtype=torch.float64, device="cuda", requires_grad=True)
+        lesion_loss(dp, k, w, steps, checkpoint_every=steps, tol=tol).backward()
+        a, b = int(m.elem_off[q]), int(m.elem_off[q + 1])
+        ek = rel_err(gk[a:b], to_host(k.grad))
+        ew = rel_err(gw[a:b], to_host(w.grad))
+        print(f"[batch adjoint {kind} sample {q}] grad_k {ek:.2e} grad_w {ew:.2e}", flush=True)
+        assert ek <= 1e-12 and ew <= 1e-12
+        dp.close()
