@@ -19,9 +19,10 @@
 // The SpMV kernels stream the matrix in one of two layouts:
 //   * CSR, LANES consecutive lanes per row (general matrices handed over the ABI);
 //   * SELL with 64-row slabs, one row per lane (the step path): entry j of a slab's 64
-//     rows is one contiguous wavefront load for values and for column offsets, stored
-//     as int16 distances to the row when they fit; the x-gathers of neighbouring rows
-//     are contiguous too for the banded meshes here.
+//     rows is one contiguous wavefront load.  Most slabs of the grid meshes share one
+//     column-offset list for all their rows (read through the scalar cache; the x reads
+//     of an entry are then 64 consecutive words); the others keep per-lane column
+//     offsets, as int16 distances to the row when they fit.
 // Workgroups walk contiguous row ranges, remapped so each XCD (own L2) takes one
 // contiguous share of the rows.
 #include <hip/hip_ext.h>

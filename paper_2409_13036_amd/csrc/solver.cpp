@@ -151,7 +151,9 @@ struct Iter32 {
     }
 };
 
-constexpr int kGraphLen = 8;  // iterations per captured chunk
+constexpr int kGraphLen = 8;     // iterations per captured chunk
+constexpr size_t kMaxGraphs = 16;  // graphs kept per mesh (callers that keep changing their
+                                   // buffers would otherwise grow the cache without bound)
 
 // The graph of kGraphLen iterations for this set of buffers, captured on first use.
 template <typename IT>
@@ -161,6 +163,10 @@ hipGraphExec_t chunk_graph(rafem_mesh m, int kind, const void* k0, const void* k
         if (g.kind == kind && g.key[0] == k0 && g.key[1] == k1 && g.key[2] == k2 &&
             g.key[3] == k3 && g.len == kGraphLen)
             return g.exec;
+    if (m->graphs.size() >= kMaxGraphs) {  // drop the oldest
+        (void)hipGraphExecDestroy(m->graphs.front().exec);
+        m->graphs.erase(m->graphs.begin());
+    }
     if (!m->gstream) RAFEM_HIP(hipStreamCreateWithFlags(&m->gstream, hipStreamNonBlocking));
     RAFEM_HIP(hipStreamBeginCapture(m->gstream, hipStreamCaptureModeThreadLocal));
     for (int j = 0; j < kGraphLen; ++j) iter(j, m->gstream, nullptr);
