@@ -78,23 +78,27 @@ class Model:
         return out
 
     # --- bioheat ------------------------------------------------------------------------
-    def bioheat_values(self, k_e=None, perf_e=None) -> np.ndarray:
-        """Unlifted A_T values = sum_e [(rho c/dt + w_e) M_e + k_e K_e]."""
+    def bioheat_values(self, k_e=None, perf_e=None, dt=None) -> np.ndarray:
+        """Unlifted A_T values = sum_e [(rho c/dt + w_e) M_e + k_e K_e] (dt: the problem's
+        step unless given)."""
         p = self.p
         k_e = p.k_e if k_e is None else k_e
         perf_e = p.perf_e if perf_e is None else perf_e
-        return self.S.assemble(self.Ke, self.Me, p.rho_c / p.dt + perf_e, k_e)
+        dt = p.dt if dt is None else dt
+        return self.S.assemble(self.Ke, self.Me, p.rho_c / dt + perf_e, k_e)
 
-    def bioheat_system(self, k_e=None, perf_e=None):
+    def bioheat_system(self, k_e=None, perf_e=None, dt=None):
         p = self.p
-        lv, lift = self.S.lift(self.bioheat_values(k_e, perf_e), p.dir_ids, p.dir_T)
+        lv, lift = self.S.lift(self.bioheat_values(k_e, perf_e, dt), p.dir_ids, p.dir_T)
         return self.S.matrix(lv), lift
 
-    def bioheat_rhs(self, T: np.ndarray, F: np.ndarray, lift: np.ndarray, perf_e=None) -> np.ndarray:
+    def bioheat_rhs(self, T: np.ndarray, F: np.ndarray, lift: np.ndarray, perf_e=None,
+                    dt=None) -> np.ndarray:
         """(rho c/dt) M T^n + T_a M_w 1 + F, element by element, then lifted."""
         p = self.p
         perf_e = p.perf_e if perf_e is None else perf_e
-        w = (p.rho_c / p.dt) * T[p.conn] + (perf_e * p.T_a)[:, None]     # [E, npe]
+        dt = p.dt if dt is None else dt
+        w = (p.rho_c / dt) * T[p.conn] + (perf_e * p.T_a)[:, None]       # [E, npe]
         fe = np.einsum("eab,eb->ea", self.Me, w)
         b_phys = self.S.scatter_vector(fe) + F
         return lifted_rhs(b_phys, lift, p.dir_ids)
