@@ -276,7 +276,8 @@ typedef struct {
     double  T_ref;
     int32_t coupled;      /* 0: bioheat step only, with zero Joule source and V untouched */
     int32_t reuse_bioheat;/* nonzero: reuse the bioheat matrix assembled by the previous call
-                             (k, perfusion, rho_c, dt unchanged); E_STATE if there is none */
+                             (k, perfusion, rho_c unchanged); E_STATE if there is none; a
+                             matrix built for another dt is rebuilt regardless */
 } rafem_phys;
 
 typedef struct {
@@ -299,6 +300,47 @@ rafem_status rafem_step(rafem_mesh mesh, const rafem_phys* phys, const double* k
                         const double* perf_e_d, const double* sigma0_e_d,
                         const double* dir_V_d, const double* dir_T_d, double* T_d, double* V_d,
                         const rafem_solve_opts* opts, rafem_step_info* info, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Predictor-corrector step (the application's main loop, Sec. II-A and Fig. 1: each
+ * time step extrapolates the solution, then repeats the corrector -- element equations
+ * with updated values, assembly, solve -- until a convergence threshold is met; a step
+ * whose corrector has not converged after the allowed iterations is not accepted and is
+ * retried with half the step, Sec. IV).
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    double  tol;         /* corrector threshold on ||T^{k+1} - T^k||_2 / ||T^{k+1}||_2 (<= 0: 1e-10) */
+    int32_t max_iters;   /* corrector iterations before the step is rejected (<= 0: 50) */
+} rafem_corrector_opts;
+
+typedef struct {
+    int32_t accepted;     /* 1: T and V advanced to t + dt; 0: left at t (rejected or failed) */
+    int32_t iters;        /* corrector iterations performed */
+    double  change;       /* last relative change of T */
+    int32_t solver_iters; /* PCG iterations (inner iterations if MIXED) of all solves */
+    int32_t status;       /* RAFEM_OK unless a solve failed */
+} rafem_corrector_info;
+
+/* One predictor-corrector step of size phys->dt on a single mesh.
+ *   predictor  T* = T^n + (dt / dt_prev)(T^n - T^{n-1}), or T^n when T_prev_d is NULL;
+ *   corrector  k = 1, 2, ...: sigma from T^{n+1,k} (T^{n+1,0} = T*), potential solve (V
+ *              warm-started from its last value), Joule load, bioheat solve with T^n on the
+ *              right-hand side giving T^{n+1,k+1}; stop when the relative change of T is
+ *              <= copts->tol (accepted) or after copts->max_iters iterations (rejected).
+ * The first corrector iterate from T* = T^n is exactly rafem_step.  The bioheat matrix is
+ * reassembled when dt differs from the one it was built for (or reuse_bioheat is 0).
+ *   T_prev_d [n_nodes] device or NULL; dt_prev its step (> 0 when T_prev_d is given)
+ *   T_d, V_d [n_nodes] device, in: T^n, V^n; out: T^{n+1}, V^{n+1} if accepted, unchanged
+ *            otherwise
+ * Returns RAFEM_OK for accepted and rejected steps alike (see info->accepted), a solve's
+ * status if one failed (T_d, V_d then restored).  E_ARG on a batch handle. */
+rafem_status rafem_step_pc(rafem_mesh mesh, const rafem_phys* phys, const double* k_e_d,
+                           const double* perf_e_d, const double* sigma0_e_d,
+                           const double* dir_V_d, const double* dir_T_d, const double* T_prev_d,
+                           double dt_prev, double* T_d, double* V_d, const rafem_solve_opts* opts,
+                           const rafem_corrector_opts* copts, rafem_corrector_info* info,
+                           void* stream);
 
 /* ---------------------------------------------------------------------------
  * Reverse mode: gradients of a loss on the final temperature with respect to the

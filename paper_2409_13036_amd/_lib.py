@@ -31,7 +31,7 @@ EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafe
            "rafem_solve", "rafem_solve_adjoint", "rafem_spmv", "rafem_profile_enable",
            "rafem_profile_read", "rafem_step", "rafem_step_vjp", "rafem_lesion_loss",
            "rafem_mesh_create_batch", "rafem_mesh_sample_layout", "rafem_mesh_set_graphs",
-           "rafem_sample_info", "rafem_spmv_timing")
+           "rafem_sample_info", "rafem_spmv_timing", "rafem_step_pc")
 
 
 class RafemError(RuntimeError):
@@ -56,6 +56,18 @@ class SolveOpts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("outer", C.c_int32),
                 ("launched", C.c_int32), ("relres", C.c_double), ("relres_true", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class CorrectorOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iters", C.c_int32)]
+
+
+class CorrectorInfo(C.Structure):
+    _fields_ = [("accepted", C.c_int32), ("iters", C.c_int32), ("change", C.c_double),
+                ("solver_iters", C.c_int32), ("status", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -90,6 +102,9 @@ _lib.rafem_profile_read.argtypes = [_p, _i32, C.POINTER(C.c_double), C.POINTER(C
 _lib.rafem_spmv_timing.argtypes = [_p, _i32, _i32, _i32, C.POINTER(C.c_double)]
 _lib.rafem_step.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts),
                             C.POINTER(StepInfo), _p]
+_lib.rafem_step_pc.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, C.c_double, _p, _p,
+                               C.POINTER(SolveOpts), C.POINTER(CorrectorOpts),
+                               C.POINTER(CorrectorInfo), _p]
 _lib.rafem_step_vjp.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
                                 C.POINTER(SolveOpts), C.POINTER(StepInfo), _p]
 _lib.rafem_lesion_loss.argtypes = [_p, _i64, _p, _p, _p, C.c_double, _p, _p, _p]
@@ -413,6 +428,33 @@ def step(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T, V, *, t
     if check:
         _check(st)
     return {"status": st, "V": info.V.as_dict(), "T": info.T.as_dict()}
+
+
+def step_pc(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T_prev, dt_prev, T, V, *,
+            corr_tol=1e-10, max_iters=50, tol=1e-12, precision="fp64", maxit=0, inner_tol=0.0,
+            max_outer=0, poll_every=0, stream=None, check=True):
+    """rafem_step_pc: one predictor-corrector step of size phys.dt; T and V are advanced in
+    place when the step is accepted.  Returns the corrector info as a dict."""
+    torch = _torch()
+    E, n = mesh.n_elems, mesh.n_nodes
+    k_e = _dev(k_e, torch.float64, E, "k_e")
+    perf_e = _dev(perf_e, torch.float64, E, "perf_e")
+    sigma0_e = _dev(sigma0_e, torch.float64, E, "sigma0_e", allow_none=not phys.coupled)
+    dir_V = _dev(dir_V, torch.float64, mesh.n_dir, "dir_V", allow_none=not phys.coupled)
+    dir_T = _dev(dir_T, torch.float64, mesh.n_dir, "dir_T")
+    T_prev = _dev(T_prev, torch.float64, n, "T_prev", allow_none=True)
+    T = _dev(T, torch.float64, n, "T")
+    V = _dev(V, torch.float64, n, "V", allow_none=not phys.coupled)
+    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every)
+    copts = CorrectorOpts(float(corr_tol), int(max_iters))
+    info = CorrectorInfo()
+    st = _lib.rafem_step_pc(mesh.handle, C.byref(phys), _ptr(k_e), _ptr(perf_e), _ptr(sigma0_e),
+                            _ptr(dir_V), _ptr(dir_T), _ptr(T_prev),
+                            float(dt_prev) if dt_prev else 0.0, _ptr(T), _ptr(V), C.byref(opts),
+                            C.byref(copts), C.byref(info), _stream(stream))
+    if check:
+        _check(st)
+    return info.as_dict()
 
 
 def step_vjp(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T_prev, V, T, lam, grad_k,

@@ -141,6 +141,7 @@ void assemble_bioheat(rafem_mesh m, const rafem_phys* phys, const double* k_e,
     launch_lift((int)m->n, SL, m->valsT, m->valsT32, m->isD, m->gT, m->liftT, m->dinvT,
                 m->dinvT32, m->nD > 0, s);
     m->bioheat_ready = true;
+    m->bioheat_dt = phys->dt;
 }
 
 // Potential matrix K_sigma(T) with sigma from the element means of T, lifted with m->gV.
@@ -274,6 +275,10 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             m->dinvV32 = dalloc<float>(m, N);
             m->dinvT32 = dalloc<float>(m, N);
             m->rhs = dalloc<double>(m, N);
+            m->pc_Tn = dalloc<double>(m, N);
+            m->pc_Vn = dalloc<double>(m, N);
+            m->pc_Tk = dalloc<double>(m, N);
+            m->pc_norm = dalloc<double>(m, 2);
             m->bT = dalloc<double>(m, N);
             m->r = dalloc<double>(m, N);
             m->p = dalloc<double>(m, N);
@@ -710,68 +715,155 @@ rafem_status rafem_profile_read(rafem_mesh m, int32_t precision, double* mean_us
     });
 }
 
+namespace {
+
+void check_step_args(rafem_mesh m, const rafem_phys* phys, const double* k_e_d,
+                     const double* perf_e_d, const double* sigma0_e_d, const double* dir_V_d,
+                     const double* dir_T_d, const double* T_d, const double* V_d) {
+    check_device(m);
+    require(phys != nullptr, "phys is NULL");
+    require(k_e_d && perf_e_d && T_d, "NULL k, perfusion or T");
+    require(m->nD == 0 || dir_T_d != nullptr, "dir_T is NULL");
+    require(phys->dt > 0.0 && std::isfinite(phys->dt), "dt must be > 0");
+    require(std::isfinite(phys->rho_c) && std::isfinite(phys->T_a), "non-finite physics constant");
+    if (phys->coupled) {
+        require(sigma0_e_d && V_d, "coupled step needs sigma0 and V");
+        require(m->nD == 0 || dir_V_d != nullptr, "dir_V is NULL");
+    }
+}
+
+// The body of one coupled step: sigma from T_sig, the bioheat right-hand side from T_rhs
+// (T^n), T_out in: initial guess, out: T^{n+1} (may alias T_rhs and T_sig), V in/out.
+// reuse_bioheat: the bioheat matrix of this dt is already assembled.
+rafem_status step_core(rafem_mesh m, const rafem_phys* phys, bool reuse_bioheat,
+                       const double* k_e_d, const double* perf_e_d, const double* sigma0_e_d,
+                       const double* dir_V_d, const double* dir_T_d, const double* T_sig,
+                       const double* T_rhs, double* T_out, double* V_d, const SolveOpts& o,
+                       rafem_step_info& inf, hipStream_t s) {
+    const bool mixed = o.precision == RAFEM_MIXED;
+    launch_scatter_dirichlet(m->dir_ids, dir_T_d, m->nD, m->gT, s);
+    if (!reuse_bioheat) assemble_bioheat(m, phys, k_e_d, perf_e_d, s);
+    if (phys->coupled) {
+        launch_scatter_dirichlet(m->dir_ids, dir_V_d, m->nD, m->gV, s);
+        assemble_potential(m, phys, sigma0_e_d, T_sig, s);
+        launch_set_dirichlet(m->dir_ids, m->gV, m->nD, V_d, s);
+        RAFEM_HIP(hipGetLastError());
+        const Mat AV = step_matrix(m, m->valsV, m->valsV32);
+        if (!m->tuned) autotune_spmv(m, AV, s);
+        solve_any(m, o, AV, step_samples(m), m->dinvV, m->dinvV32, m->liftV, V_d, &inf.V, s,
+                  kSolvePotential);
+        record_samples(m, true, mixed);
+        if (inf.V.status != RAFEM_OK) {
+            set_error("potential solve failed");
+            return inf.V.status;
+        }
+    }
+    launch_fill(m->rhs, m->n, 0.0, s);
+    for (int c = 0; c < m->n_colours; ++c) {
+        const int off = m->colour_off[c], cnt = m->colour_off[c + 1] - off;
+        launch_bioheat_rhs_colour(m->npe, m->affine, m->colour_elems + off, cnt, m->conn, m->xyz, T_rhs,
+                                  phys->coupled ? V_d : nullptr, m->sigma, perf_e_d,
+                                  phys->rho_c / phys->dt, phys->T_a, phys->coupled ? 1 : 0,
+                                  m->rhs, s);
+    }
+    launch_finish_rhs((int)m->n, m->rhs, m->liftT, m->isD, m->bT, s);
+    launch_set_dirichlet(m->dir_ids, m->gT, m->nD, T_out, s);
+    RAFEM_HIP(hipGetLastError());
+    const Mat AT = step_matrix(m, m->valsT, m->valsT32);
+    if (!m->tuned) autotune_spmv(m, AT, s);
+    solve_any(m, o, AT, step_samples(m), m->dinvT, m->dinvT32, m->bT, T_out, &inf.T, s,
+              kSolveBioheat);
+    record_samples(m, false, mixed);
+    if (inf.T.status != RAFEM_OK) {
+        set_error("bioheat solve failed");
+        return inf.T.status;
+    }
+    return RAFEM_OK;
+}
+
+}  // namespace
+
 rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_d,
                         const double* perf_e_d, const double* sigma0_e_d, const double* dir_V_d,
                         const double* dir_T_d, double* T_d, double* V_d,
                         const rafem_solve_opts* opts, rafem_step_info* info, void* stream) {
     return guard([&]() -> rafem_status {
-        check_device(m);
-        require(phys != nullptr, "phys is NULL");
-        require(k_e_d && perf_e_d && T_d, "NULL k, perfusion or T");
-        require(m->nD == 0 || dir_T_d != nullptr, "dir_T is NULL");
-        require(phys->dt > 0.0 && std::isfinite(phys->dt), "dt must be > 0");
-        require(std::isfinite(phys->rho_c) && std::isfinite(phys->T_a), "non-finite physics constant");
-        if (phys->coupled) {
-            require(sigma0_e_d && V_d, "coupled step needs sigma0 and V");
-            require(m->nD == 0 || dir_V_d != nullptr, "dir_V is NULL");
-        }
+        check_step_args(m, phys, k_e_d, perf_e_d, sigma0_e_d, dir_V_d, dir_T_d, T_d, V_d);
         if (phys->reuse_bioheat && !m->bioheat_ready)
             throw Error{RAFEM_E_STATE, "reuse_bioheat set but no bioheat matrix has been assembled"};
-        SolveOpts o = resolve_opts(opts, 1e-12);
-        hipStream_t s = (hipStream_t)stream;
-        const bool mixed = o.precision == RAFEM_MIXED;
+        const SolveOpts o = resolve_opts(opts, 1e-12);
         rafem_step_info local{};
         rafem_step_info& inf = info ? *info : local;
         std::memset(&inf, 0, sizeof(inf));
+        // a bioheat matrix built for another time step is rebuilt
+        const bool reuse = phys->reuse_bioheat && m->bioheat_dt == phys->dt;
+        return step_core(m, phys, reuse, k_e_d, perf_e_d, sigma0_e_d, dir_V_d, dir_T_d, T_d, T_d,
+                         T_d, V_d, o, inf, (hipStream_t)stream);
+    });
+}
 
-        launch_scatter_dirichlet(m->dir_ids, dir_T_d, m->nD, m->gT, s);
-        if (!phys->reuse_bioheat) assemble_bioheat(m, phys, k_e_d, perf_e_d, s);
-        if (phys->coupled) {
-            launch_scatter_dirichlet(m->dir_ids, dir_V_d, m->nD, m->gV, s);
-            assemble_potential(m, phys, sigma0_e_d, T_d, s);
-            launch_set_dirichlet(m->dir_ids, m->gV, m->nD, V_d, s);
-            RAFEM_HIP(hipGetLastError());
-            const Mat AV = step_matrix(m, m->valsV, m->valsV32);
-            if (!m->tuned) autotune_spmv(m, AV, s);
-            solve_any(m, o, AV, step_samples(m), m->dinvV, m->dinvV32, m->liftV, V_d, &inf.V, s,
-                      kSolvePotential);
-            record_samples(m, true, mixed);
-            if (inf.V.status != RAFEM_OK) {
-                set_error("potential solve failed");
-                return inf.V.status;
+rafem_status rafem_step_pc(rafem_mesh m, const rafem_phys* phys, const double* k_e_d,
+                           const double* perf_e_d, const double* sigma0_e_d,
+                           const double* dir_V_d, const double* dir_T_d, const double* T_prev_d,
+                           double dt_prev, double* T_d, double* V_d, const rafem_solve_opts* opts,
+                           const rafem_corrector_opts* copts, rafem_corrector_info* info,
+                           void* stream) {
+    return guard([&]() -> rafem_status {
+        check_step_args(m, phys, k_e_d, perf_e_d, sigma0_e_d, dir_V_d, dir_T_d, T_d, V_d);
+        require(m->S == 1, "the predictor-corrector step runs on single meshes");
+        require(!T_prev_d || (dt_prev > 0.0 && std::isfinite(dt_prev)),
+                "dt_prev must be > 0 when T_prev is given");
+        const double eps = copts && copts->tol > 0.0 ? copts->tol : 1e-10;
+        const int max_iters = copts && copts->max_iters > 0 ? copts->max_iters : 50;
+        require(std::isfinite(eps) && eps < 1.0, "corrector tol must be in (0, 1)");
+        const SolveOpts o = resolve_opts(opts, 1e-12);
+        hipStream_t s = (hipStream_t)stream;
+        rafem_corrector_info local{};
+        rafem_corrector_info& ci = info ? *info : local;
+        std::memset(&ci, 0, sizeof(ci));
+        const size_t bytes = (size_t)m->n * sizeof(double);
+        // keep (T^n, V^n) to restore a rejected step; predictor into pc_Tk
+        RAFEM_HIP(hipMemcpyAsync(m->pc_Tn, T_d, bytes, hipMemcpyDeviceToDevice, s));
+        if (phys->coupled)
+            RAFEM_HIP(hipMemcpyAsync(m->pc_Vn, V_d, bytes, hipMemcpyDeviceToDevice, s));
+        launch_extrapolate((int)m->n, m->pc_Tn, T_prev_d, T_prev_d ? phys->dt / dt_prev : 0.0,
+                           m->pc_Tk, s);
+        bool reuse = phys->reuse_bioheat && m->bioheat_ready && m->bioheat_dt == phys->dt;
+        rafem_status st = RAFEM_OK;
+        for (int k = 1; k <= max_iters; ++k) {
+            RAFEM_HIP(hipMemcpyAsync(T_d, m->pc_Tk, bytes, hipMemcpyDeviceToDevice, s));
+            rafem_step_info inf{};
+            st = step_core(m, phys, reuse, k_e_d, perf_e_d, sigma0_e_d, dir_V_d, dir_T_d,
+                           m->pc_Tk, m->pc_Tn, T_d, V_d, o, inf, s);
+            reuse = true;
+            ci.iters = k;
+            ci.solver_iters += inf.V.iters + inf.T.iters;
+            if (st != RAFEM_OK) break;
+            // relative change of T over this corrector iteration
+            double h[2];
+            launch_change_norm((int)m->n, T_d, m->pc_Tk, m->partials, m->pc_norm, s);
+            RAFEM_HIP(hipMemcpyAsync(h, m->pc_norm, sizeof(h), hipMemcpyDeviceToHost, s));
+            RAFEM_HIP(hipStreamSynchronize(s));
+            ci.change = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+            RAFEM_HIP(hipMemcpyAsync(m->pc_Tk, T_d, bytes, hipMemcpyDeviceToDevice, s));
+            if (!std::isfinite(ci.change)) {
+                st = RAFEM_E_BREAKDOWN;
+                set_error("non-finite temperature change in the corrector");
+                break;
+            }
+            if (ci.change <= eps) {
+                ci.accepted = 1;
+                break;
             }
         }
-        launch_fill(m->rhs, m->n, 0.0, s);
-        for (int c = 0; c < m->n_colours; ++c) {
-            const int off = m->colour_off[c], cnt = m->colour_off[c + 1] - off;
-            launch_bioheat_rhs_colour(m->npe, m->affine, m->colour_elems + off, cnt, m->conn, m->xyz, T_d,
-                                      phys->coupled ? V_d : nullptr, m->sigma, perf_e_d,
-                                      phys->rho_c / phys->dt, phys->T_a, phys->coupled ? 1 : 0,
-                                      m->rhs, s);
+        ci.status = st;
+        if (!ci.accepted) {  // rejected (or failed): leave (T^n, V^n) as they were
+            RAFEM_HIP(hipMemcpyAsync(T_d, m->pc_Tn, bytes, hipMemcpyDeviceToDevice, s));
+            if (phys->coupled)
+                RAFEM_HIP(hipMemcpyAsync(V_d, m->pc_Vn, bytes, hipMemcpyDeviceToDevice, s));
+            RAFEM_HIP(hipStreamSynchronize(s));
         }
-        launch_finish_rhs((int)m->n, m->rhs, m->liftT, m->isD, m->bT, s);
-        launch_set_dirichlet(m->dir_ids, m->gT, m->nD, T_d, s);
-        RAFEM_HIP(hipGetLastError());
-        const Mat AT = step_matrix(m, m->valsT, m->valsT32);
-        if (!m->tuned) autotune_spmv(m, AT, s);
-        solve_any(m, o, AT, step_samples(m), m->dinvT, m->dinvT32, m->bT, T_d, &inf.T, s,
-                  kSolveBioheat);
-        record_samples(m, false, mixed);
-        if (inf.T.status != RAFEM_OK) {
-            set_error("bioheat solve failed");
-            return inf.T.status;
-        }
-        return RAFEM_OK;
+        return st;
     });
 }
 
@@ -802,7 +894,8 @@ rafem_status rafem_step_vjp(rafem_mesh m, const rafem_phys* phys, const double* 
         const int npe = m->npe, aff = m->affine;
 
         launch_scatter_dirichlet(m->dir_ids, dir_T_d, m->nD, m->gT, s);
-        if (!phys->reuse_bioheat) assemble_bioheat(m, phys, k_e_d, perf_e_d, s);
+        if (!phys->reuse_bioheat || m->bioheat_dt != phys->dt)
+            assemble_bioheat(m, phys, k_e_d, perf_e_d, s);
         // mu: A_T mu = lambda with the Dirichlet rows of the load zeroed
         launch_fill(m->gtmp, m->n, 0.0, s);
         RAFEM_HIP(hipMemcpyAsync(m->bT, lambda_d, m->n * 8, hipMemcpyDeviceToDevice, s));

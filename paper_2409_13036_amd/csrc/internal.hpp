@@ -242,6 +242,12 @@ void launch_vjp_lambda_colour(int npe, int affine, const int32_t* elems, int cou
 void launch_loss(int64_t n, const int32_t* ids, const double* target, const double* T,
                  double scale, double* grad, double* partials, double* loss, hipStream_t s);
 // b = isD ? lift : rhs + lift
+// out = a + c (a - b) (b may be NULL: out = a); the predictor's linear extrapolation.
+void launch_extrapolate(int n, const double* a, const double* b, double c, double* out,
+                        hipStream_t s);
+// norm2[0] = sum (x - y)^2, norm2[1] = sum x^2, deterministically (partials: >= n/256 + 1).
+void launch_change_norm(int n, const double* x, const double* y, double* partials,
+                        double* norm2, hipStream_t s);
 void launch_finish_rhs(int n, const double* rhs, const double* lift, const uint8_t* isD,
                        double* b, hipStream_t s);
 
@@ -299,6 +305,10 @@ struct rafem_mesh_s {
     float *valsV32 = nullptr, *valsT32 = nullptr, *dinvV32 = nullptr, *dinvT32 = nullptr;
     double *rhs = nullptr, *bT = nullptr, *gtmp = nullptr, *coefT = nullptr;
     bool bioheat_ready = false;
+    double bioheat_dt = 0.0;       // time step the bioheat matrix was assembled for
+    // predictor-corrector step: T^n and V^n (restored on rejection), the current iterate,
+    // and the two sums of the change norm
+    double *pc_Tn = nullptr, *pc_Vn = nullptr, *pc_Tk = nullptr, *pc_norm = nullptr;
     bool potential_ready = false;  // a step has assembled the potential matrix
     double *adj_mu = nullptr, *adj_nu = nullptr, *adj_sbar = nullptr, *adj_dsig = nullptr;
     // iteration counts of the previous solve of each kind and precision (first-chunk guesses)

@@ -259,6 +259,38 @@ __global__ void k_finish_rhs(int n, const double* __restrict__ rhs,
 
 inline int grid1(int64_t n) { return (int)((n + WG - 1) / WG); }
 
+// Predictor: out = a + c (a - b), or a when b is NULL.
+__global__ __launch_bounds__(WG) void k_extrapolate(int n, const double* __restrict__ a,
+                                                    const double* __restrict__ b, double c,
+                                                    double* __restrict__ out) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i < n) out[i] = b ? a[i] + c * (a[i] - b[i]) : a[i];
+}
+
+// Sums of (x - y)^2 and x^2: per-block partials, then one block adds them in order.
+__global__ __launch_bounds__(WG) void k_change_norm_part(int n, const double* __restrict__ x,
+                                                         const double* __restrict__ y,
+                                                         double* __restrict__ partials) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (i < n) {
+        const double d = x[i] - y[i];
+        v[0] = d * d;
+        v[1] = x[i] * x[i];
+    }
+    store_partials<2>(v, partials, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(WG) void k_change_norm_final(const double* __restrict__ partials,
+                                                          int nb, double* __restrict__ norm2) {
+    double tot[2];
+    grid_totals<2>(partials, nb, tot);
+    if (threadIdx.x == 0) {
+        norm2[0] = tot[0];
+        norm2[1] = tot[1];
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -344,6 +376,19 @@ void launch_bioheat_rhs_colour(int npe, int affine, const int32_t* elems, int co
     else
         hipLaunchKernelGGL((k_bioheat_rhs<4, false>), dim3(grid), dim3(WG), 0, s, elems, count,
                            conn, xyz, T, V, sigma, perf, rho_c_dt, T_a, with_joule, rhs);
+}
+
+void launch_extrapolate(int n, const double* a, const double* b, double c, double* out,
+                        hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_extrapolate, dim3(grid1(n)), dim3(WG), 0, s, n, a, b, c, out);
+}
+
+void launch_change_norm(int n, const double* x, const double* y, double* partials,
+                        double* norm2, hipStream_t s) {
+    const int nb = std::max(1, grid1(n));
+    hipLaunchKernelGGL(k_change_norm_part, dim3(nb), dim3(WG), 0, s, n, x, y, partials);
+    hipLaunchKernelGGL(k_change_norm_final, dim3(1), dim3(WG), 0, s, partials, nb, norm2);
 }
 
 void launch_finish_rhs(int n, const double* rhs, const double* lift, const uint8_t* isD,

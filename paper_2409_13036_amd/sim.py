@@ -69,6 +69,51 @@ class DeviceProblem:
                 states.append((self.T.cpu().numpy().copy(), self.V.cpu().numpy().copy()))
         return states, infos
 
+    def step_pc(self, dt: float, T_prev=None, dt_prev=None, corr_tol: float = 1e-10,
+                max_iters: int = 50, tol: float = 1e-12, precision: str = "fp64", **kw):
+        """One predictor-corrector step of size dt (T and V advance only if accepted)."""
+        self.phys.dt = float(dt)
+        try:
+            info = rafem.step_pc(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e,
+                                 self.dir_V, self.dir_T, T_prev, dt_prev, self.T, self.V,
+                                 corr_tol=corr_tol, max_iters=max_iters, tol=tol,
+                                 precision=precision, **kw)
+        finally:
+            self.phys.dt = float(self.p.dt)  # plain steps keep the problem's step; the library
+        self.phys.reuse_bioheat = 1          # rebuilds a bioheat matrix made for another dt
+        return info
+
+    def simulate_pc(self, t_total: float, dt0: float, corr_tol: float = 1e-10,
+                    max_iters: int = 50, tol: float = 1e-12, precision: str = "fp64",
+                    dt_min: float = 1e-6, keep: bool = False):
+        """Predictor-corrector time loop from the current state to t_total: a rejected step is
+        retried with half the step; after an accepted step the step doubles again, up to dt0;
+        the last step ends exactly at t_total.  Returns a list of per-step records
+        (t, dt, corrector iterations, rejections before it[, T, V])."""
+        T_prev, dt_prev = None, None
+        t, dt = 0.0, float(dt0)
+        records, rejected = [], 0
+        while t_total - t > 1e-12 * t_total:
+            h = min(dt, t_total - t)
+            T_n = self.T.clone()
+            info = self.step_pc(h, T_prev, dt_prev, corr_tol, max_iters, tol, precision)
+            if not info["accepted"]:
+                rejected += 1
+                dt = h / 2.0
+                if dt < dt_min:
+                    raise RuntimeError(f"time step fell below {dt_min} s at t = {t} s")
+                continue
+            T_prev, dt_prev = T_n, h
+            t += h
+            rec = {"t": t, "dt": h, "iters": info["iters"], "rejected_before": rejected,
+                   "solver_iters": info["solver_iters"]}
+            if keep:
+                rec["T"], rec["V"] = self.T.cpu().numpy().copy(), self.V.cpu().numpy().copy()
+            records.append(rec)
+            rejected = 0
+            dt = min(float(dt0), 2.0 * h)
+        return records
+
     def close(self):
         self.mesh.close()
 
