@@ -401,6 +401,47 @@ def batch_leg(args) -> dict:
     return out
 
 
+def pc_leg(dp, args) -> dict:
+    """Predictor-corrector workload on the same mesh: the application's outer loop
+    (extrapolated predictor, Picard corrector on sigma(T) until the relative change of T is
+    below eps, at most 50 corrector iterations, halving on rejection) from rest over
+    t_total seconds with nominal step dt0, FP64 and mixed.  Reports accepted steps/s,
+    simulated seconds per wall second, corrector and solver iterations, and the mixed
+    final state against the FP64 one."""
+    import numpy as np
+    import torch
+    out = {"workload": f"predictor-corrector run, {args.pc_t:g} s in steps of {args.pc_dt0:g} s, "
+                       f"eps {args.pc_eps:g}, at most 50 corrector iterations per step",
+           "t_total_s": args.pc_t, "dt0_s": args.pc_dt0, "eps": args.pc_eps}
+    finals = {}
+    for precision in ("fp64", "mixed"):
+        dp.reset()
+        dp.step_pc(args.pc_dt0, corr_tol=args.pc_eps, tol=TOL, precision=precision)  # warm-up
+        dp.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = dp.simulate_pc(args.pc_t, args.pc_dt0, corr_tol=args.pc_eps, max_iters=50, tol=TOL,
+                             precision=precision)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        finals[precision] = (dp.T.clone(), dp.V.clone())
+        its = [r["iters"] for r in rec]
+        out[precision] = {
+            "accepted_steps": len(rec), "rejected": sum(r["rejected_before"] for r in rec),
+            "elapsed_s": el, "accepted_steps_per_s": len(rec) / el,
+            "simulated_s_per_s": args.pc_t / el,
+            "corrector_iters_mean": float(np.mean(its)), "corrector_iters_max": max(its),
+            "corrector_iters_per_s": sum(its) / el,
+            "solver_iters_total": int(sum(r["solver_iters"] for r in rec))}
+        print(f"[bench] predictor-corrector {precision}: {len(rec)} steps in {el:.2f} s, "
+              f"corrector iterations {its}", file=sys.stderr, flush=True)
+    (Tm, Vm), (T64, V64) = finals["mixed"], finals["fp64"]
+    out["mixed_rel_err_vs_fp64"] = {
+        "T": float(torch.linalg.norm(Tm - T64) / torch.linalg.norm(T64)),
+        "V": float(torch.linalg.norm(Vm - V64) / torch.linalg.norm(V64))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,6 +460,11 @@ def main():
     ap.add_argument("--workload", choices=["c1", "c2"], default="c1",
                     help="c1: 101^3 hex (default); c2: 161^3-node jittered Kuhn tets")
     ap.add_argument("--no-batch", action="store_true", help="skip the ensemble leg")
+    ap.add_argument("--no-pc", action="store_true", help="skip the predictor-corrector leg")
+    ap.add_argument("--pc-t", type=float, default=10.0, help="predictor-corrector: total time (s)")
+    ap.add_argument("--pc-dt0", type=float, default=2.0, help="predictor-corrector: nominal step (s)")
+    ap.add_argument("--pc-eps", type=float, default=1e-9,
+                    help="predictor-corrector: relative change of T that ends a corrector")
     ap.add_argument("--batch-only", action="store_true", help="run only the ensemble leg")
     ap.add_argument("--batch-samples", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=30)
@@ -553,6 +599,8 @@ def main():
     }
     if cpu:
         line["speedup_vs_cpu_oracle"] = sps / cpu["value"]
+    if not args.no_pc:
+        line["predictor_corrector"] = pc_leg(dp, args)
     dp.close()
     del dp
     if not args.no_batch and args.workload == "c1":
