@@ -141,3 +141,20 @@ def joule_grad_V(xe: np.ndarray, sigma_e: np.ndarray, Ve: np.ndarray, mu_e: np.n
     gV = np.einsum("ea,eai->ei", Ve, G)
     mubar = mu_e.sum(axis=1) * V / 4.0
     return (2.0 * sigma_e * mubar)[:, None] * np.einsum("ebi,ei->eb", G, gV)
+
+
+def joule_jacobian_V(xe: np.ndarray, sigma_e: np.ndarray, Ve: np.ndarray) -> np.ndarray:
+    """Jacobian of the Joule loads with respect to the element's nodal V:
+
+    d f_{e,a} / d V_{e,b} = int_e 2 sigma_e N_a grad N_b . grad V  -> [E, npe, npe].
+    Hex: 2x2x2 Gauss rule.  Tet: grad N and grad V are constant, int N_a = V/4.
+    """
+    if xe.shape[1] == 8:
+        det, N, grad = hex_gauss_geometry(xe)
+        gV = np.einsum("ea,egai->egi", Ve, grad)               # [E, 8g, 3]
+        gNgV = np.einsum("egbi,egi->egb", grad, gV)            # grad N_b . grad V at Gauss points
+        return 2.0 * sigma_e[:, None, None] * np.einsum("eg,ga,egb->eab", det, N, gNgV)
+    V, G = tet_geometry(xe)
+    gV = np.einsum("ea,eai->ei", Ve, G)
+    row = 2.0 * (sigma_e * V / 4.0)[:, None] * np.einsum("ebi,ei->eb", G, gV)   # same for every a
+    return np.repeat(row[:, None, :], 4, axis=1)
