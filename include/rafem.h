@@ -343,6 +343,95 @@ rafem_status rafem_step_pc(rafem_mesh mesh, const rafem_phys* phys, const double
                            void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Monolithic corrector.  The paper's corrector assembles the element equations, with the
+ * latest values, into one global matrix with two unknowns per node (temperature and
+ * potential; matrix order = 2 x nodes, Table II) that is sparse and structurally
+ * symmetric, and solves it with restarted GMRES(m) (Sec. II-A, Sec. II-B, Sec. III-B,
+ * Fig. 3).  Here that matrix is the Jacobian J of the implicit coupled step
+ *   R_T = sum_e [(rho_c/dt + perf_e) M_e + k_e K_e] T_e - M_e ((rho_c/dt) T^n_e + perf_e T_a)
+ *         - f_e(sigma_e(T), V_e),
+ *   R_V = sum_e sigma_e(T) K_e V_e,   sigma_e(T) = sigma0_e (1 + alpha (mean_e T - T_ref)),
+ * at the free nodes (f_e: Joule loads int N sigma grad V . grad V), 0 at Dirichlet nodes;
+ * its element blocks (c_e = sigma0_e alpha / npe, q_e = f_e at sigma = 1, 1 = all ones):
+ *   dR_T/dT = (rho_c/dt + perf_e) M_e + k_e K_e - c_e q_e 1^T,   dR_T/dV = -df_e/dV_e,
+ *   dR_V/dT = c_e (K_e V_e) 1^T,                                dR_V/dV = sigma_e K_e,
+ * Dirichlet rows and columns replaced by the identity's.  Unknown 2i is T_i, 2i+1 is V_i.
+ * One corrector iteration is one Newton step J delta = -R; its root is the fixed point of
+ * the staggered corrector of rafem_step_pc.  All three calls below need a single-mesh
+ * handle (E_ARG on a batch) and phys->coupled != 0.
+ * ------------------------------------------------------------------------- */
+
+#define RAFEM_GMRES_MAX_M 200
+
+typedef struct {
+    int32_t m;           /* Krylov vectors per restart cycle, 1..RAFEM_GMRES_MAX_M (<= 0: 30) */
+    int32_t max_iters;   /* Arnoldi steps over all cycles (<= 0: 20000) */
+    double  tol;         /* stop when ||b - J x||_2 <= tol ||b||_2 (<= 0: 1e-10) */
+} rafem_gmres_opts;
+
+typedef struct {
+    int32_t status;      /* RAFEM_OK, E_NOCONV (max_iters reached), E_BREAKDOWN (non-finite
+                            value or singular Hessenberg) */
+    int32_t iters;       /* Arnoldi steps over all cycles */
+    int32_t cycles;      /* restart cycles */
+    int32_t pad;
+    double  relres;      /* last Givens-rotated residual estimate / ||b|| */
+    double  relres_true; /* ||b - J x|| / ||b|| at the last restart (the exit) */
+} rafem_gmres_info;
+
+/* The Jacobian and residual at the state (T, V), for inspection and tests.
+ *   T_n_d, T_d, V_d  [n_nodes] device: T^n, and the iterate (T, V), which must carry the
+ *                    Dirichlet values
+ *   planes_d  [4 nnz] device out: TT, TV, VT, VV values, each plane in the CSR order of
+ *             rafem_csr_structure (zero-filled first)
+ *   R_d       [2 n_nodes] device out: R interleaved (R[2i] = R_T,i, R[2i+1] = R_V,i)
+ * Allocates nothing beyond the handle's step buffers. */
+rafem_status rafem_mono_jacobian(rafem_mesh mesh, const rafem_phys* phys, const double* k_e_d,
+                                 const double* perf_e_d, const double* sigma0_e_d,
+                                 const double* T_n_d, const double* T_d, const double* V_d,
+                                 double* planes_d, double* R_d, void* stream);
+
+/* Assemble J and R at (T, V) as above and solve J delta = -R from delta = 0 by restarted
+ * GMRES(opts->m) with right preconditioning by the inverses of J's 2x2 diagonal node
+ * blocks (classical Gram-Schmidt applied twice, Givens rotations; a cycle stops when the
+ * rotated residual meets opts->tol, a restart recomputes the true residual).
+ *   delta_d  [2 n_nodes] device out: the update, interleaved like R
+ *   hist_d   [hist_len] device out or NULL: the rotated residual estimate / ||R|| after
+ *            every Arnoldi step (the first hist_len steps)
+ * Returns info->status.  The first call allocates the handle's monolithic workspace:
+ * 32 B per matrix slot plus (m + 5) vectors of 16 B per node. */
+rafem_status rafem_mono_solve(rafem_mesh mesh, const rafem_phys* phys, const double* k_e_d,
+                              const double* perf_e_d, const double* sigma0_e_d,
+                              const double* T_n_d, const double* T_d, const double* V_d,
+                              const rafem_gmres_opts* opts, double* delta_d, double* hist_d,
+                              int32_t hist_len, rafem_gmres_info* info, void* stream);
+
+typedef struct {
+    int32_t accepted;     /* 1: T and V advanced to t + dt; 0: left at t (rejected or failed) */
+    int32_t iters;        /* Newton (corrector) iterations performed */
+    double  change;       /* last ||delta_T|| / ||T|| */
+    int32_t gmres_iters;  /* Arnoldi steps of all linear solves */
+    int32_t gmres_cycles; /* restart cycles of all linear solves */
+    int32_t status;       /* RAFEM_OK unless a linear solve failed */
+    int32_t pad;
+    double  relres_true_max; /* largest exit residual of the linear solves */
+} rafem_mono_info;
+
+/* One predictor-corrector step of size phys->dt with the monolithic corrector: the
+ * predictor of rafem_step_pc gives T*, the iterate starts at (T*, V^n) with the Dirichlet
+ * values imposed, and Newton steps (each solved as in rafem_mono_solve) run until
+ * ||delta_T|| <= copts->tol ||T|| (accepted) or copts->max_iters steps (rejected).
+ *   T_prev_d, dt_prev, T_d, V_d, copts: as for rafem_step_pc
+ * Returns RAFEM_OK for accepted and rejected steps alike, a solve's status if one failed
+ * (T_d, V_d then restored). */
+rafem_status rafem_step_mono(rafem_mesh mesh, const rafem_phys* phys, const double* k_e_d,
+                             const double* perf_e_d, const double* sigma0_e_d,
+                             const double* dir_V_d, const double* dir_T_d,
+                             const double* T_prev_d, double dt_prev, double* T_d, double* V_d,
+                             const rafem_gmres_opts* opts, const rafem_corrector_opts* copts,
+                             rafem_mono_info* info, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Reverse mode: gradients of a loss on the final temperature with respect to the
  * per-element conductivity k_e and perfusion w_e, by the discrete adjoint of the
  * steps above run backwards in time (the time loop of Sec. II-A, reversed).

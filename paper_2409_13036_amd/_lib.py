@@ -31,7 +31,8 @@ EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafe
            "rafem_solve", "rafem_solve_adjoint", "rafem_spmv", "rafem_profile_enable",
            "rafem_profile_read", "rafem_step", "rafem_step_vjp", "rafem_lesion_loss",
            "rafem_mesh_create_batch", "rafem_mesh_sample_layout", "rafem_mesh_set_graphs",
-           "rafem_sample_info", "rafem_spmv_timing", "rafem_step_pc")
+           "rafem_sample_info", "rafem_spmv_timing", "rafem_step_pc", "rafem_mono_jacobian",
+           "rafem_mono_solve", "rafem_step_mono")
 
 
 class RafemError(RuntimeError):
@@ -73,6 +74,30 @@ class CorrectorInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+GMRES_MAX_M = 200
+
+
+class GmresOpts(C.Structure):
+    _fields_ = [("m", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double)]
+
+
+class GmresInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cycles", C.c_int32),
+                ("pad", C.c_int32), ("relres", C.c_double), ("relres_true", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+class MonoInfo(C.Structure):
+    _fields_ = [("accepted", C.c_int32), ("iters", C.c_int32), ("change", C.c_double),
+                ("gmres_iters", C.c_int32), ("gmres_cycles", C.c_int32), ("status", C.c_int32),
+                ("pad", C.c_int32), ("relres_true_max", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 class Phys(C.Structure):
     _fields_ = [("rho_c", C.c_double), ("dt", C.c_double), ("T_a", C.c_double),
                 ("alpha_sigma", C.c_double), ("T_ref", C.c_double), ("coupled", C.c_int32),
@@ -105,6 +130,12 @@ _lib.rafem_step.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, C.P
 _lib.rafem_step_pc.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, C.c_double, _p, _p,
                                C.POINTER(SolveOpts), C.POINTER(CorrectorOpts),
                                C.POINTER(CorrectorInfo), _p]
+_lib.rafem_mono_jacobian.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, _p, _p]
+_lib.rafem_mono_solve.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p,
+                                  C.POINTER(GmresOpts), _p, _p, _i32, C.POINTER(GmresInfo), _p]
+_lib.rafem_step_mono.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, C.c_double, _p, _p,
+                                 C.POINTER(GmresOpts), C.POINTER(CorrectorOpts),
+                                 C.POINTER(MonoInfo), _p]
 _lib.rafem_step_vjp.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
                                 C.POINTER(SolveOpts), C.POINTER(StepInfo), _p]
 _lib.rafem_lesion_loss.argtypes = [_p, _i64, _p, _p, _p, C.c_double, _p, _p, _p]
@@ -452,6 +483,79 @@ def step_pc(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T_prev,
                             _ptr(dir_V), _ptr(dir_T), _ptr(T_prev),
                             float(dt_prev) if dt_prev else 0.0, _ptr(T), _ptr(V), C.byref(opts),
                             C.byref(copts), C.byref(info), _stream(stream))
+    if check:
+        _check(st)
+    return info.as_dict()
+
+
+def _mono_fields(mesh: Mesh, k_e, perf_e, sigma0_e):
+    torch = _torch()
+    E = mesh.n_elems
+    return (_dev(k_e, torch.float64, E, "k_e"), _dev(perf_e, torch.float64, E, "perf_e"),
+            _dev(sigma0_e, torch.float64, E, "sigma0_e"))
+
+
+def mono_jacobian(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, T_n, T, V, *, stream=None):
+    """rafem_mono_jacobian: the monolithic Jacobian at (T, V) as four planes (TT, TV, VT, VV)
+    in the mesh's CSR order, and the residual R interleaved by node.  Returns (planes
+    [4, nnz], R [2 n]) on the device."""
+    torch = _torch()
+    n = mesh.n_nodes
+    k_e, perf_e, sigma0_e = _mono_fields(mesh, k_e, perf_e, sigma0_e)
+    T_n = _dev(T_n, torch.float64, n, "T_n")
+    T = _dev(T, torch.float64, n, "T")
+    V = _dev(V, torch.float64, n, "V")
+    planes = torch.empty((4, mesh.nnz), dtype=torch.float64, device=T.device)
+    R = torch.empty(2 * n, dtype=torch.float64, device=T.device)
+    _check(_lib.rafem_mono_jacobian(mesh.handle, C.byref(phys), _ptr(k_e), _ptr(perf_e),
+                                    _ptr(sigma0_e), _ptr(T_n), _ptr(T), _ptr(V), _ptr(planes),
+                                    _ptr(R), _stream(stream)))
+    return planes, R
+
+
+def mono_solve(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, T_n, T, V, *, m=30, max_iters=0,
+               tol=1e-10, hist_len=0, stream=None, check=True):
+    """rafem_mono_solve: assemble J, R at (T, V) and solve J delta = -R by GMRES(m).  Returns
+    (delta [2 n] interleaved, info dict, residual history [hist_len] or None)."""
+    torch = _torch()
+    n = mesh.n_nodes
+    k_e, perf_e, sigma0_e = _mono_fields(mesh, k_e, perf_e, sigma0_e)
+    T_n = _dev(T_n, torch.float64, n, "T_n")
+    T = _dev(T, torch.float64, n, "T")
+    V = _dev(V, torch.float64, n, "V")
+    delta = torch.empty(2 * n, dtype=torch.float64, device=T.device)
+    hist = torch.zeros(hist_len, dtype=torch.float64, device=T.device) if hist_len else None
+    opts = GmresOpts(int(m), int(max_iters), float(tol))
+    info = GmresInfo()
+    st = _lib.rafem_mono_solve(mesh.handle, C.byref(phys), _ptr(k_e), _ptr(perf_e),
+                               _ptr(sigma0_e), _ptr(T_n), _ptr(T), _ptr(V), C.byref(opts),
+                               _ptr(delta), _ptr(hist), int(hist_len), C.byref(info),
+                               _stream(stream))
+    if check:
+        _check(st)
+    return delta, info.as_dict(), hist
+
+
+def step_mono(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T_prev, dt_prev, T, V,
+              *, corr_tol=1e-10, max_iters=50, m=30, gmres_max_iters=0, gmres_tol=1e-10,
+              stream=None, check=True):
+    """rafem_step_mono: one predictor-corrector step of size phys.dt with the monolithic
+    Newton-GMRES corrector; T and V advance in place when accepted.  Returns the info dict."""
+    torch = _torch()
+    n = mesh.n_nodes
+    k_e, perf_e, sigma0_e = _mono_fields(mesh, k_e, perf_e, sigma0_e)
+    dir_V = _dev(dir_V, torch.float64, mesh.n_dir, "dir_V")
+    dir_T = _dev(dir_T, torch.float64, mesh.n_dir, "dir_T")
+    T_prev = _dev(T_prev, torch.float64, n, "T_prev", allow_none=True)
+    T = _dev(T, torch.float64, n, "T")
+    V = _dev(V, torch.float64, n, "V")
+    opts = GmresOpts(int(m), int(gmres_max_iters), float(gmres_tol))
+    copts = CorrectorOpts(float(corr_tol), int(max_iters))
+    info = MonoInfo()
+    st = _lib.rafem_step_mono(mesh.handle, C.byref(phys), _ptr(k_e), _ptr(perf_e), _ptr(sigma0_e),
+                              _ptr(dir_V), _ptr(dir_T), _ptr(T_prev),
+                              float(dt_prev) if dt_prev else 0.0, _ptr(T), _ptr(V), C.byref(opts),
+                              C.byref(copts), C.byref(info), _stream(stream))
     if check:
         _check(st)
     return info.as_dict()

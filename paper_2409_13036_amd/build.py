@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librafem.so")
-SOURCES = ["pcg.hip", "kernels.hip", "adjoint.hip", "solver.cpp", "abi.cpp", "structure.cpp"]
+SOURCES = ["pcg.hip", "kernels.hip", "adjoint.hip", "gmres.hip", "solver.cpp", "abi.cpp",
+           "structure.cpp", "mono.cpp"]
 ARCH = "gfx950"
 
 

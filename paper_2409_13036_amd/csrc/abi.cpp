@@ -8,6 +8,7 @@
 #include <new>
 #include <string>
 
+#include "mono.hpp"
 #include "solver.hpp"
 
 namespace rafem {
@@ -65,7 +66,9 @@ void free_mesh(rafem_mesh m) {
     m->graphs.clear();
     if (m->gstream) (void)hipStreamDestroy(m->gstream);
     for (void* p : m->allocations) (void)hipFree(p);
+    if (m->gm_V) (void)hipFree(m->gm_V);
     if (m->st_host) (void)hipHostFree(m->st_host);
+    if (m->gm_st_host) (void)hipHostFree(m->gm_st_host);
     delete m;
 }
 
@@ -351,6 +354,10 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
 }
 
 }  // namespace
+
+void* mesh_alloc(rafem_mesh m, size_t bytes) { return dalloc<char>(m, bytes); }
+Layout mesh_sell_layout(rafem_mesh m) { return sell_layout(m); }
+Layout mesh_csr_layout(rafem_mesh m) { return csr_layout(m); }
 
 void set_error(const std::string& msg) { g_error = msg; }
 void clear_error() { g_error.clear(); }
@@ -861,6 +868,129 @@ rafem_status rafem_step_pc(rafem_mesh m, const rafem_phys* phys, const double* k
             RAFEM_HIP(hipMemcpyAsync(T_d, m->pc_Tn, bytes, hipMemcpyDeviceToDevice, s));
             if (phys->coupled)
                 RAFEM_HIP(hipMemcpyAsync(V_d, m->pc_Vn, bytes, hipMemcpyDeviceToDevice, s));
+            RAFEM_HIP(hipStreamSynchronize(s));
+        }
+        return st;
+    });
+}
+
+namespace {
+
+void check_mono_args(rafem_mesh m, const rafem_phys* phys, const double* k_e_d,
+                     const double* perf_e_d, const double* sigma0_e_d, const double* T_n_d,
+                     const double* T_d, const double* V_d) {
+    check_device(m);
+    require(m->S == 1, "the monolithic corrector runs on single meshes");
+    require(phys != nullptr, "phys is NULL");
+    require(phys->coupled != 0, "the monolithic corrector needs a coupled problem");
+    require(k_e_d && perf_e_d && sigma0_e_d, "NULL k, perfusion or sigma0");
+    require(T_n_d && T_d && V_d, "NULL T^n, T or V");
+    require(phys->dt > 0.0 && std::isfinite(phys->dt), "dt must be > 0");
+    require(std::isfinite(phys->rho_c) && std::isfinite(phys->T_a) &&
+                std::isfinite(phys->alpha_sigma) && std::isfinite(phys->T_ref),
+            "non-finite physics constant");
+}
+
+}  // namespace
+
+rafem_status rafem_mono_jacobian(rafem_mesh m, const rafem_phys* phys, const double* k_e_d,
+                                 const double* perf_e_d, const double* sigma0_e_d,
+                                 const double* T_n_d, const double* T_d, const double* V_d,
+                                 double* planes_d, double* R_d, void* stream) {
+    return guard([&]() -> rafem_status {
+        check_mono_args(m, phys, k_e_d, perf_e_d, sigma0_e_d, T_n_d, T_d, V_d);
+        require(planes_d && R_d, "NULL output");
+        hipStream_t s = (hipStream_t)stream;
+        mono_export(m, phys, k_e_d, perf_e_d, sigma0_e_d, T_n_d, T_d, V_d, planes_d, R_d, s);
+        RAFEM_HIP(hipStreamSynchronize(s));
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_mono_solve(rafem_mesh m, const rafem_phys* phys, const double* k_e_d,
+                              const double* perf_e_d, const double* sigma0_e_d,
+                              const double* T_n_d, const double* T_d, const double* V_d,
+                              const rafem_gmres_opts* opts, double* delta_d, double* hist_d,
+                              int32_t hist_len, rafem_gmres_info* info, void* stream) {
+    return guard([&]() -> rafem_status {
+        check_mono_args(m, phys, k_e_d, perf_e_d, sigma0_e_d, T_n_d, T_d, V_d);
+        require(delta_d != nullptr, "delta is NULL");
+        require(hist_len >= 0 && (hist_len == 0 || hist_d), "bad residual history buffer");
+        const GmresOpts o = resolve_gmres(opts);
+        hipStream_t s = (hipStream_t)stream;
+        mono_ensure(m, o.m);
+        mono_assemble(m, phys, k_e_d, perf_e_d, sigma0_e_d, T_n_d, T_d, V_d, s);
+        rafem_gmres_info local{};
+        const rafem_status st = gmres_solve(m, m->mono_rhs, delta_d, o, hist_len ? hist_d : nullptr,
+                                            hist_len, info ? info : &local, s);
+        if (st != RAFEM_OK) set_error("GMRES did not converge");
+        return st;
+    });
+}
+
+rafem_status rafem_step_mono(rafem_mesh m, const rafem_phys* phys, const double* k_e_d,
+                             const double* perf_e_d, const double* sigma0_e_d,
+                             const double* dir_V_d, const double* dir_T_d,
+                             const double* T_prev_d, double dt_prev, double* T_d, double* V_d,
+                             const rafem_gmres_opts* opts, const rafem_corrector_opts* copts,
+                             rafem_mono_info* info, void* stream) {
+    return guard([&]() -> rafem_status {
+        check_mono_args(m, phys, k_e_d, perf_e_d, sigma0_e_d, T_d, T_d, V_d);
+        require(m->nD == 0 || (dir_V_d && dir_T_d), "dir_V or dir_T is NULL");
+        require(!T_prev_d || (dt_prev > 0.0 && std::isfinite(dt_prev)),
+                "dt_prev must be > 0 when T_prev is given");
+        const double eps = copts && copts->tol > 0.0 ? copts->tol : 1e-10;
+        const int max_iters = copts && copts->max_iters > 0 ? copts->max_iters : 50;
+        require(std::isfinite(eps) && eps < 1.0, "corrector tol must be in (0, 1)");
+        const GmresOpts o = resolve_gmres(opts);
+        hipStream_t s = (hipStream_t)stream;
+        rafem_mono_info local{};
+        rafem_mono_info& mi = info ? *info : local;
+        std::memset(&mi, 0, sizeof(mi));
+        mono_ensure(m, o.m);
+        const size_t bytes = (size_t)m->n * sizeof(double);
+        // keep (T^n, V^n) to restore a rejected step; the iterate starts at (T*, V^n) with
+        // the Dirichlet values
+        RAFEM_HIP(hipMemcpyAsync(m->pc_Tn, T_d, bytes, hipMemcpyDeviceToDevice, s));
+        RAFEM_HIP(hipMemcpyAsync(m->pc_Vn, V_d, bytes, hipMemcpyDeviceToDevice, s));
+        launch_extrapolate((int)m->n, m->pc_Tn, T_prev_d, T_prev_d ? phys->dt / dt_prev : 0.0,
+                           T_d, s);
+        launch_scatter_dirichlet(m->dir_ids, dir_T_d, m->nD, m->gT, s);
+        launch_scatter_dirichlet(m->dir_ids, dir_V_d, m->nD, m->gV, s);
+        launch_set_dirichlet(m->dir_ids, m->gT, m->nD, T_d, s);
+        launch_set_dirichlet(m->dir_ids, m->gV, m->nD, V_d, s);
+        rafem_status st = RAFEM_OK;
+        for (int k = 1; k <= max_iters; ++k) {
+            mono_assemble(m, phys, k_e_d, perf_e_d, sigma0_e_d, m->pc_Tn, T_d, V_d, s);
+            rafem_gmres_info gi{};
+            st = gmres_solve(m, m->mono_rhs, m->mono_delta, o, nullptr, 0, &gi, s);
+            mi.iters = k;
+            mi.gmres_iters += gi.iters;
+            mi.gmres_cycles += gi.cycles;
+            mi.relres_true_max = std::max(mi.relres_true_max, gi.relres_true);
+            if (st != RAFEM_OK) {
+                set_error("GMRES did not converge in the monolithic corrector");
+                break;
+            }
+            double h[2];
+            launch_newton_apply((int)m->n, m->mono_delta, T_d, V_d, m->gm_part, m->pc_norm, s);
+            RAFEM_HIP(hipMemcpyAsync(h, m->pc_norm, sizeof(h), hipMemcpyDeviceToHost, s));
+            RAFEM_HIP(hipStreamSynchronize(s));
+            mi.change = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+            if (!std::isfinite(mi.change)) {
+                st = RAFEM_E_BREAKDOWN;
+                set_error("non-finite temperature change in the monolithic corrector");
+                break;
+            }
+            if (mi.change <= eps) {
+                mi.accepted = 1;
+                break;
+            }
+        }
+        mi.status = st;
+        if (!mi.accepted) {
+            RAFEM_HIP(hipMemcpyAsync(T_d, m->pc_Tn, bytes, hipMemcpyDeviceToDevice, s));
+            RAFEM_HIP(hipMemcpyAsync(V_d, m->pc_Vn, bytes, hipMemcpyDeviceToDevice, s));
             RAFEM_HIP(hipStreamSynchronize(s));
         }
         return st;

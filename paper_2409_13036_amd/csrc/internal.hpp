@@ -251,6 +251,105 @@ void launch_change_norm(int n, const double* x, const double* y, double* partial
 void launch_finish_rhs(int n, const double* rhs, const double* lift, const uint8_t* isD,
                        double* b, hipStream_t s);
 
+
+// Helpers of the C ABI layer (abi.cpp): device memory owned by the handle, and the
+// handle's SELL and CSR layouts.
+void* mesh_alloc(rafem_mesh m, size_t bytes);
+Layout mesh_sell_layout(rafem_mesh m);
+Layout mesh_csr_layout(rafem_mesh m);
+
+// ---------------------------------------------------------------------------
+// Monolithic (T, V) corrector: Jacobian assembly, block SpMV and GMRES(m) (gmres.hip).
+// ---------------------------------------------------------------------------
+constexpr int kGmMaxM = RAFEM_GMRES_MAX_M;
+
+// Device state of one GMRES solve (written by the single-thread kernels only).
+struct GmState {
+    double tol, bnorm, beta, est, relres_true;
+    int32_t iters, cycles, jdone, cyc_done, solved, status, maxit, m;
+};
+
+// The basis (vector i of the interleaved (T, V) pairs at V + i ldv), the per-block
+// partial sums [rows][nb] and the state.
+struct GmVec {
+    int n;
+    double2* V;
+    int64_t ldv;
+    double* part;
+    GmState* st;
+};
+
+// Hessenberg matrix (column-major, leading dimension ldh), rotations, rotated right-hand
+// side, least-squares solution, and the per-step residual estimates (hist, may be NULL).
+struct GmSmall {
+    double* H;
+    int ldh;
+    double *cs, *sn, *g, *y;
+    double* hist;
+    int hist_cap;
+};
+
+struct BsellArgs {
+    int n = 0, nslabs = 0;
+    const int32_t* sptr = nullptr;
+    const int32_t* scol = nullptr;
+    const int16_t* sdel = nullptr;
+    const int32_t* sofs = nullptr;
+    const int32_t* soff = nullptr;
+    const double4* vals = nullptr;  // (TT, TV, VT, VV) per slot
+    const double2* x = nullptr;
+    double2* y = nullptr;
+    const GmState* st = nullptr;    // skip when the solve (or, arnoldi: the cycle) is over
+    int arnoldi = 0;
+};
+
+// One colour of the Jacobian / residual assembly.  Value c (0..3 = TT, TV, VT, VV) of
+// slot k goes to vals[k * slot_mul + c * plane_stride]; R[2i], R[2i+1] += rsign * (R_T, R_V).
+struct JacArgs {
+    const int32_t* elems = nullptr;
+    int count = 0;
+    const int32_t* conn = nullptr;
+    const double* xyz = nullptr;
+    Layout L;
+    const int32_t* e2s = nullptr;
+    const uint8_t* isD = nullptr;
+    const double *Tn = nullptr, *T = nullptr, *V = nullptr;
+    const double *k_e = nullptr, *perf = nullptr, *sigma0 = nullptr;
+    double rho_c_dt = 0.0, T_a = 0.0, alpha = 0.0, T_ref = 0.0;
+    double* vals = nullptr;
+    int64_t plane_stride = 1;
+    int slot_mul = 4;
+    double* R = nullptr;
+    double rsign = 1.0;
+};
+
+void launch_jac_assemble_colour(int npe, int affine, const JacArgs& a, hipStream_t s);
+void launch_jac_dirichlet(const int32_t* dir_ids, int64_t nD, const Layout& L, double* vals,
+                          int slot_mul, int64_t plane_stride, hipStream_t s);
+// binv[4i..4i+3] = inverse of node i's diagonal block (vals4: SELL slots of double4).
+void launch_block_inv(int n, const Layout& L, const double* vals4, double* binv, hipStream_t s);
+void launch_bsell(const BsellArgs& a, hipStream_t s);
+int gm_blocks(int n);  // workgroups (= partial slots) of the per-node GMRES kernels
+void launch_gm_init(GmState* st, double tol, int maxit, int m, hipStream_t s);
+void launch_gm_dots(const GmVec& a, int k, const double* w, hipStream_t s);
+void launch_gm_sum(const double* part, int nb, int rows, double* out, const GmState* st,
+                   hipStream_t s);
+void launch_gm_orth(const GmVec& a, int k, const double* h1, double* w, hipStream_t s);
+void launch_gm_next(const GmVec& a, int k, const double* h2, const double* w, const double* binv,
+                    double* z, hipStream_t s);
+void launch_gm_givens(const GmSmall& sm, int j, const double* h1, const double* h2, GmState* st,
+                      hipStream_t s);
+void launch_gm_solve_y(const GmSmall& sm, const GmState* st, hipStream_t s);
+void launch_gm_xupdate(const GmVec& a, const double* y, const double* binv, double* delta,
+                       hipStream_t s);
+void launch_gm_resid(const GmVec& a, const double* b, const double* w, double* r, hipStream_t s);
+void launch_gm_restart(const double* part, int nb, const GmSmall& sm, GmState* st, int first,
+                       hipStream_t s);
+void launch_gm_v0(const GmVec& a, const double* r, const double* binv, double* z, hipStream_t s);
+// T += delta.T, V += delta.V; norm2 = (||delta_T||^2, ||T||^2) (part: >= 2 gm_blocks(n)).
+void launch_newton_apply(int n, const double* delta, double* T, double* V, double* part,
+                         double* norm2, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // Mesh handle.
 // ---------------------------------------------------------------------------
@@ -314,6 +413,15 @@ struct rafem_mesh_s {
     // iteration counts of the previous solve of each kind and precision (first-chunk guesses)
     std::vector<int> hints[4][2];
 
+    // monolithic corrector (allocated on first use): Jacobian slots as double4 in the SELL
+    // layout, -R, block-Jacobi inverses, the Newton update, GMRES vectors and basis
+    double *mono_vals = nullptr, *mono_rhs = nullptr, *mono_binv = nullptr, *mono_delta = nullptr;
+    double *gm_w = nullptr, *gm_z = nullptr, *gm_r = nullptr, *gm_part = nullptr;
+    double* gm_small = nullptr;        // H, cs, sn, g, y, h1, h2
+    double* gm_V = nullptr;            // basis, (gm_cap + 1) vectors (freed on growth)
+    int gm_cap = 0;
+    rafem::GmState* gm_st = nullptr;
+    rafem::GmState* gm_st_host = nullptr;  // pinned
     // solver workspace
     double *r = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr, *r64 = nullptr;
     float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr, *dinv32 = nullptr;

@@ -83,20 +83,40 @@ class DeviceProblem:
         self.phys.reuse_bioheat = 1          # rebuilds a bioheat matrix made for another dt
         return info
 
+    def step_mono(self, dt: float, T_prev=None, dt_prev=None, corr_tol: float = 1e-10,
+                  max_iters: int = 50, m: int = 30, gmres_tol: float = 1e-10, **kw):
+        """One predictor-corrector step of size dt with the monolithic Newton-GMRES(m)
+        corrector (T and V advance only if accepted)."""
+        self.phys.dt = float(dt)
+        try:
+            info = rafem.step_mono(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e,
+                                   self.dir_V, self.dir_T, T_prev, dt_prev, self.T, self.V,
+                                   corr_tol=corr_tol, max_iters=max_iters, m=m,
+                                   gmres_tol=gmres_tol, **kw)
+        finally:
+            self.phys.dt = float(self.p.dt)
+        return info
+
     def simulate_pc(self, t_total: float, dt0: float, corr_tol: float = 1e-10,
                     max_iters: int = 50, tol: float = 1e-12, precision: str = "fp64",
-                    dt_min: float = 1e-6, keep: bool = False):
+                    dt_min: float = 1e-6, keep: bool = False, corrector: str = "picard",
+                    m: int = 30, gmres_tol: float = 1e-10):
         """Predictor-corrector time loop from the current state to t_total: a rejected step is
         retried with half the step; after an accepted step the step doubles again, up to dt0;
-        the last step ends exactly at t_total.  Returns a list of per-step records
-        (t, dt, corrector iterations, rejections before it[, T, V])."""
+        the last step ends exactly at t_total.  corrector: "picard" (staggered PCG solves,
+        tol / precision) or "newton" (monolithic GMRES(m) solves, gmres_tol).  Returns a list
+        of per-step records (t, dt, corrector iterations, rejections before it[, T, V])."""
         T_prev, dt_prev = None, None
         t, dt = 0.0, float(dt0)
         records, rejected = [], 0
         while t_total - t > 1e-12 * t_total:
             h = min(dt, t_total - t)
             T_n = self.T.clone()
-            info = self.step_pc(h, T_prev, dt_prev, corr_tol, max_iters, tol, precision)
+            if corrector == "newton":
+                info = self.step_mono(h, T_prev, dt_prev, corr_tol, max_iters, m, gmres_tol)
+                info["solver_iters"] = info["gmres_iters"]
+            else:
+                info = self.step_pc(h, T_prev, dt_prev, corr_tol, max_iters, tol, precision)
             if not info["accepted"]:
                 rejected += 1
                 dt = h / 2.0

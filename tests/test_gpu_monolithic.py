@@ -1,0 +1,153 @@
+"""The monolithic (T, V) corrector on the GPU against the oracle: the Jacobian's four
+planes and the residual, GMRES(m) solves (iterations, cycles, residual history, update),
+Newton corrector steps, a rejected step, and the argument checks."""
+import numpy as np
+import pytest
+
+import rafem_inputs as ri
+from oracle import monolithic as mono
+from oracle.rafem import Model
+from gpu_helpers import rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+DT = 20.0
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def _state(p, m, seed=0):
+    """A non-trivial iterate carrying the Dirichlet values: one staggered step plus noise."""
+    rng = np.random.default_rng(seed)
+    T1, V1, _ = m.step(p.initial_T(), p.initial_V(), 1e-14)
+    T = T1 + 0.5 * rng.standard_normal(p.n_nodes)
+    V = V1 + 0.3 * rng.standard_normal(p.n_nodes)
+    T[p.dir_ids], V[p.dir_ids] = p.dir_T, p.dir_V
+    return T, V
+
+
+def _device_problem(p):
+    from paper_2409_13036_amd.sim import DeviceProblem
+    dp = DeviceProblem(p)
+    dp.phys.dt = DT
+    return dp
+
+
+@pytest.mark.parametrize("kind,n", [("hex", 9), ("tet", 8)])
+def test_jacobian_and_residual_match_oracle(torch_cuda, kind, n):
+    from paper_2409_13036_amd import _lib as R
+    p = ri.make_problem(kind, n, 1)
+    m = Model(p)
+    T, V = _state(p, m)
+    T0 = p.initial_T()
+    dp = _device_problem(p)
+    planes, Rg = R.mono_jacobian(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, to_dev(T0),
+                                 to_dev(T), to_dev(V))
+    planes, Rg = to_host(planes), to_host(Rg)
+    dp.close()
+    B = mono.jacobian_blocks(m, T0, DT, T, V)
+    Rr = mono.residual(m, T0, DT, T, V)
+    for k, (name, ref) in enumerate(zip(("TT", "TV", "VT", "VV"), (B.TT, B.TV, B.VT, B.VV))):
+        err = np.abs(planes[k] - ref).max() / np.abs(ref).max()
+        print(f"[mono {kind}{n}] {name}: max err / max {err:.2e}", flush=True)
+        assert err <= 1e-12
+    scale = np.abs(Rr).max()
+    print(f"[mono {kind}{n}] R: max err / max {np.abs(Rg - Rr).max() / scale:.2e}", flush=True)
+    assert np.abs(Rg - Rr).max() <= 1e-11 * scale
+    assert np.all(Rg[2 * p.dir_ids] == 0) and np.all(Rg[2 * p.dir_ids + 1] == 0)
+
+
+@pytest.mark.parametrize("kind,n,mm", [("hex", 9, 10), ("hex", 9, 30), ("tet", 8, 20)])
+def test_gmres_matches_oracle(torch_cuda, kind, n, mm):
+    from paper_2409_13036_amd import _lib as R
+    p = ri.make_problem(kind, n, 2)
+    m = Model(p)
+    T, V = _state(p, m, seed=1)
+    T0 = p.initial_T()
+    tol = 1e-10
+    dp = _device_problem(p)
+    delta, info, hist = R.mono_solve(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e,
+                                     to_dev(T0), to_dev(T), to_dev(V), m=mm, tol=tol,
+                                     hist_len=4000)
+    delta, hist = to_host(delta), to_host(hist)
+    dp.close()
+    J = mono.interleaved_matrix(m, mono.jacobian_blocks(m, T0, DT, T, V))
+    b = -mono.residual(m, T0, DT, T, V)
+    x, ref = mono.gmres(J, b, np.zeros_like(b), mm, tol, precond=mono.block_jacobi(J))
+    print(f"[gmres {kind}{n} m={mm}] GPU iters {info['iters']} cycles {info['cycles']} "
+          f"relres_true {info['relres_true']:.2e}; oracle iters {ref.iters} cycles {ref.cycles} "
+          f"relres_true {ref.relres_true:.2e}; delta err {rel_err(delta, x):.2e}", flush=True)
+    assert info["status"] == 0 and ref.converged
+    assert abs(info["iters"] - ref.iters) <= 1 and abs(info["cycles"] - ref.cycles) <= 1
+    k = min(info["iters"], ref.iters)
+    h_ref = np.array(ref.history[:k])
+    assert np.allclose(hist[:k], h_ref, rtol=1e-6, atol=1e-6 * tol)
+    assert info["relres_true"] <= tol
+    assert np.linalg.norm(b - J @ delta) <= tol * np.linalg.norm(b) * 1.0001
+    assert rel_err(delta, x) <= 1e-8
+    # Dirichlet unknowns do not move
+    assert np.all(delta[2 * p.dir_ids] == 0) and np.all(delta[2 * p.dir_ids + 1] == 0)
+
+
+@pytest.mark.parametrize("kind,n", [("hex", 11), ("tet", 9)])
+def test_newton_corrector_matches_oracle(torch_cuda, kind, n):
+    p = ri.make_problem(kind, n, 1)
+    m = Model(p)
+    T0, V0 = p.initial_T(), p.initial_V()
+    eps = 1e-9
+    dp = _device_problem(p)
+    info = dp.step_mono(DT, corr_tol=eps, m=30, gmres_tol=1e-10)
+    Tg, Vg = to_host(dp.T), to_host(dp.V)
+    ref = mono.newton_step(m, T0, V0, DT, T0.copy(), eps, m=30, lin_tol=1e-10)
+    print(f"[newton {kind}{n}] GPU {info}; oracle iters {ref.iters} change {ref.change:.2e} "
+          f"gmres {[i.iters for i in ref.linear]}; T {rel_err(Tg, ref.T):.2e} "
+          f"V {rel_err(Vg, ref.V):.2e}", flush=True)
+    assert info["accepted"] == 1 and ref.converged and info["iters"] == ref.iters
+    assert abs(info["gmres_iters"] - sum(i.iters for i in ref.linear)) <= info["iters"]
+    assert rel_err(Tg, ref.T) <= 1e-8 and rel_err(Vg, ref.V) <= 1e-8
+    # a second step with the predictor
+    T1, V1 = Tg.copy(), Vg.copy()
+    info2 = dp.step_mono(10.0, T_prev=to_dev(T0), dt_prev=DT, corr_tol=eps, m=30)
+    ref2 = mono.newton_step(m, ref.T, ref.V, 10.0, ref.T + 0.5 * (ref.T - T0), eps, m=30,
+                            lin_tol=1e-10)
+    assert info2["accepted"] == 1 and info2["iters"] == ref2.iters
+    assert rel_err(to_host(dp.T), ref2.T) <= 1e-8 and rel_err(to_host(dp.V), ref2.V) <= 1e-8
+    assert not np.array_equal(T1, to_host(dp.T))
+    dp.close()
+
+
+def test_rejected_newton_step_leaves_the_state(torch_cuda):
+    p = ri.make_problem("hex", 9, 3)
+    dp = _device_problem(p)
+    dp.step(1e-13)
+    T_before, V_before = to_host(dp.T), to_host(dp.V)
+    info = dp.step_mono(60.0, corr_tol=1e-14, max_iters=1)
+    assert info["accepted"] == 0 and info["iters"] == 1 and info["change"] > 1e-14
+    assert np.array_equal(to_host(dp.T), T_before) and np.array_equal(to_host(dp.V), V_before)
+    dp.close()
+
+
+def test_argument_checks(torch_cuda):
+    from paper_2409_13036_amd import _lib as R
+    from paper_2409_13036_amd.sim import BatchProblem
+    p = ri.make_problem("hex", 7, 1)
+    dp = _device_problem(p)
+    T, V = dp.T, dp.V
+    with pytest.raises(R.RafemError, match="E_ARG"):
+        R.mono_solve(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, T, T, V,
+                     m=R.GMRES_MAX_M + 1)
+    dp.phys.coupled = 0
+    with pytest.raises(R.RafemError, match="E_ARG"):
+        R.mono_solve(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, T, T, V)
+    dp.close()
+    bp = BatchProblem([ri.make_problem("hex", 7, 1), ri.make_problem("hex", 8, 2)])
+    with pytest.raises(R.RafemError, match="E_ARG"):
+        R.step_mono(bp.mesh, bp.phys, bp.k_e, bp.perf_e, bp.sigma0_e, bp.dir_V, bp.dir_T, None,
+                    0.0, bp.T, bp.V)
+    bp.close()
