@@ -442,6 +442,97 @@ def pc_leg(dp, args) -> dict:
     return out
 
 
+def arnoldi_bytes(n: int, nnz: int, m: int) -> float:
+    """Algorithmic HBM bytes of one Arnoldi step of GMRES(m), averaged over a cycle: the block
+    SpMV (per node pair 4 FP64 values + an int32 column, row pointers, x and y of 16 B per
+    node) and the three CGS2 passes over the k = j + 1 basis vectors (dots: k + 1 vectors;
+    update with the second dots: k + 2; normalisation with M^-1: k + 5 vector-sized
+    streams), k averaged over j = 0..m-1."""
+    spmv = 36.0 * nnz + 4.0 * (n + 1) + 32.0 * n
+    k_mean = (m + 1) / 2.0
+    return spmv + (3.0 * k_mean + 8.0) * 16.0 * n
+
+
+def mono_leg(dp, args) -> dict:
+    """Monolithic corrector on the same mesh: GMRES(m) solves of one Newton system (the
+    Jacobian at the state after one staggered step, T^n = the initial state) for each m of
+    the sweep -- time, iterations, cycles, slowdown against the best m, and stagnating
+    cycles (residual reduced by less than 2x over a cycle); then the predictor-corrector run
+    of the Picard leg with the Newton corrector at the best m."""
+    import numpy as np
+    import torch
+    from paper_2409_13036_amd import _lib as R
+    p = dp.p
+    N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
+    dp.reset()
+    dp.step(TOL)
+    T1, V1 = dp.T.clone(), dp.V.clone()
+    T0 = torch.as_tensor(p.initial_T(), dtype=torch.float64, device=dp.dev)
+    dt_save = dp.phys.dt
+    dp.phys.dt = args.pc_dt0
+    sweep = []
+    hist_len = 20000
+    # warm-up (a short solve that allocates the workspace for the largest m)
+    R.mono_solve(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, T0, T1, V1, m=max(args.mono_m),
+                 tol=1e-10, max_iters=50, check=False)
+    for mm in args.mono_m:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, hist = R.mono_solve(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, T0, T1, V1,
+                                     m=mm, tol=1e-10, hist_len=hist_len, check=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        h = hist.cpu().numpy()[:min(info["iters"], hist_len)]
+        ends = [min(c * mm, len(h)) - 1 for c in range(1, info["cycles"] + 1)]
+        starts = [1.0] + [h[e] for e in ends[:-1]]
+        stagn = sum(1 for s0, e in zip(starts, ends) if e >= 0 and h[e] > 0.5 * s0)
+        per_step = arnoldi_bytes(N, nnz, mm)
+        row = {"m": mm, "status": info["status"], "iters": info["iters"], "cycles": info["cycles"],
+               "seconds": el, "relres_true": info["relres_true"],
+               "us_per_arnoldi_step": el / max(1, info["iters"]) * 1e6,
+               "arnoldi_GBs": per_step * info["iters"] / el / 1e9,
+               "stagnating_cycles": stagn}
+        sweep.append(row)
+        print(f"[bench] GMRES({mm}): {info['iters']} iterations, {info['cycles']} cycles, "
+              f"{el:.3f} s, {row['us_per_arnoldi_step']:.0f} us/step, "
+              f"{row['arnoldi_GBs']:.0f} GB/s, stagnating cycles {stagn}",
+              file=sys.stderr, flush=True)
+    ok = [r for r in sweep if r["status"] == 0]
+    best = min(ok, key=lambda r: r["seconds"]) if ok else None
+    for r in sweep:
+        r["slowdown_vs_best"] = r["seconds"] / best["seconds"] if best else None
+    dp.phys.dt = dt_save
+    out = {"workload": f"monolithic (T, V) Newton-GMRES corrector, {N}-node hex mesh, "
+                       f"2N = {2 * N} unknowns, {4 * nnz} nonzeros",
+           "unknowns": 2 * N, "nonzeros": 4 * nnz, "gmres_tol": 1e-10, "m_sweep": sweep,
+           "best_m": best["m"] if best else None}
+    if best:
+        r = best
+        out["roofline"] = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                           "achieved": r["arnoldi_GBs"], "frac": r["arnoldi_GBs"] / HBM_PEAK_GBS,
+                           "bytes_per_arnoldi_step": arnoldi_bytes(N, nnz, r["m"]),
+                           "note": "whole Arnoldi steps of the best m (block SpMV + CGS2), "
+                                   "cycle ends and restarts included in the time"}
+        dp.reset()
+        dp.step_mono(args.pc_dt0, corr_tol=args.pc_eps, m=r["m"])  # warm-up
+        dp.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = dp.simulate_pc(args.pc_t, args.pc_dt0, corr_tol=args.pc_eps, max_iters=50,
+                             corrector="newton", m=r["m"], gmres_tol=1e-10)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        its = [x["iters"] for x in rec]
+        out["predictor_corrector"] = {
+            "t_total_s": args.pc_t, "dt0_s": args.pc_dt0, "eps": args.pc_eps,
+            "accepted_steps": len(rec), "rejected": sum(x["rejected_before"] for x in rec),
+            "elapsed_s": el, "accepted_steps_per_s": len(rec) / el,
+            "newton_iters": its, "gmres_iters_total": int(sum(x["solver_iters"] for x in rec))}
+        print(f"[bench] monolithic predictor-corrector: {len(rec)} steps in {el:.2f} s, Newton "
+              f"iterations {its}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -461,6 +552,11 @@ def main():
                     help="c1: 101^3 hex (default); c2: 161^3-node jittered Kuhn tets")
     ap.add_argument("--no-batch", action="store_true", help="skip the ensemble leg")
     ap.add_argument("--no-pc", action="store_true", help="skip the predictor-corrector leg")
+    ap.add_argument("--no-mono", action="store_true", help="skip the monolithic GMRES leg")
+    ap.add_argument("--mono-only", action="store_true",
+                    help="run only the monolithic GMRES leg (on the c1 mesh)")
+    ap.add_argument("--mono-m", type=int, nargs="+", default=[10, 20, 30, 50, 100],
+                    help="restart lengths of the GMRES(m) sweep")
     ap.add_argument("--pc-t", type=float, default=10.0, help="predictor-corrector: total time (s)")
     ap.add_argument("--pc-dt0", type=float, default=2.0, help="predictor-corrector: nominal step (s)")
     ap.add_argument("--pc-eps", type=float, default=1e-9,
@@ -495,6 +591,13 @@ def main():
         return
     if args.batch_only:
         print(json.dumps(batch_leg(args)), flush=True)
+        return
+    if args.mono_only:
+        import rafem_inputs as ri
+        from paper_2409_13036_amd.sim import DeviceProblem
+        dp = DeviceProblem(ri.config1(n=args.n, steps=1))
+        print(json.dumps(mono_leg(dp, args)), flush=True)
+        dp.close()
         return
 
     # CPU oracle first, before this process touches the GPU
@@ -601,6 +704,8 @@ def main():
         line["speedup_vs_cpu_oracle"] = sps / cpu["value"]
     if not args.no_pc:
         line["predictor_corrector"] = pc_leg(dp, args)
+    if not args.no_mono:
+        line["monolithic"] = mono_leg(dp, args)
     dp.close()
     del dp
     if not args.no_batch and args.workload == "c1":

@@ -18,6 +18,10 @@ LIB_PATH = os.path.join(_HERE, "librafem.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_2409_13036_amd.build)")
+# torch ships its own HIP runtime; loading it first makes the library bind to that same
+# runtime, in which the caller's tensors and streams live (loaded the other way round, the
+# library's runtime instance finds no device)
+import torch  # noqa: E402,F401
 _lib = C.CDLL(LIB_PATH)
 
 OK, E_ARG, E_MESH, E_NOCONV, E_BREAKDOWN, E_HIP, E_NOMEM, E_STATE = range(8)
