@@ -83,13 +83,26 @@ rafem_status rafem_csr_structure(int64_t n_nodes, int64_t n_elems, int32_t npe,
 
 /* Element colouring used for race-free assembly: elements of one colour share no
  * node, so their contributions to the global matrix can be added concurrently
- * without atomics.  Greedy first-fit in element order (at most 64 colours).
+ * without atomics.  Greedy first-fit in element order (at most 256 colours).
  *   colour_h       [n_elems] host output, colour of each element
  *   n_colours_out  receives the number of colours
- * Errors: E_ARG, E_MESH (node id out of range; more than 64 colours needed). */
+ * Errors: E_ARG, E_MESH (node id out of range; more than 256 colours needed). */
 rafem_status rafem_colour_elements(int64_t n_nodes, int64_t n_elems, int32_t npe,
                                    const int32_t* conn_h, int32_t* colour_h,
                                    int32_t* n_colours_out);
+
+/* Reverse Cuthill-McKee ordering of the node graph (nodes adjacent when they share an
+ * element), one of the reorderings of a sparse solver's analysis step (Sec. II-B): it
+ * keeps the columns of each row, and so the x entries a slab of rows reads, close to the
+ * row.  Per connected component, in order of its smallest node id: the pseudo-peripheral
+ * start node of George and Liu (least degree, ties by smallest id), breadth-first search
+ * taking unvisited neighbours by increasing degree (ties by smallest id); the
+ * concatenated order reversed.  Host-only; deterministic.
+ *   order_h  [n_nodes] host output: order_h[k] = the node placed at position k
+ * Renumber a mesh by it (new id of node order_h[k] is k) before rafem_mesh_create.
+ * Errors: E_ARG, E_MESH (node id out of range, repeated node in an element). */
+rafem_status rafem_rcm_order(int64_t n_nodes, int64_t n_elems, int32_t npe,
+                             const int32_t* conn_h, int32_t* order_h);
 
 /* ---------------------------------------------------------------------------
  * Mesh handle: structure, colouring, geometry and all device workspaces.

@@ -36,7 +36,7 @@ EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafe
            "rafem_profile_read", "rafem_step", "rafem_step_vjp", "rafem_lesion_loss",
            "rafem_mesh_create_batch", "rafem_mesh_sample_layout", "rafem_mesh_set_graphs",
            "rafem_sample_info", "rafem_spmv_timing", "rafem_step_pc", "rafem_mono_jacobian",
-           "rafem_mono_solve", "rafem_step_mono")
+           "rafem_mono_solve", "rafem_step_mono", "rafem_rcm_order")
 
 
 class RafemError(RuntimeError):
@@ -118,6 +118,7 @@ _lib.rafem_last_error.restype = C.c_char_p
 _lib.rafem_abi_version.restype = C.c_int32
 _lib.rafem_csr_structure.argtypes = [_i64, _i64, _i32, _p, C.POINTER(C.c_int64), _p, _p]
 _lib.rafem_colour_elements.argtypes = [_i64, _i64, _i32, _p, _p, C.POINTER(C.c_int32)]
+_lib.rafem_rcm_order.argtypes = [_i64, _i64, _i32, _p, _p]
 _lib.rafem_mesh_create.argtypes = [_i64, _i64, _i32, _p, _p, _p, _i64, C.POINTER(_p)]
 _lib.rafem_mesh_destroy.argtypes = [_p]
 _lib.rafem_mesh_get_stats.argtypes = [_p, C.POINTER(MeshStats)]
@@ -199,6 +200,15 @@ def colour_elements(conn: np.ndarray, n_nodes: int):
     nc = C.c_int32(0)
     _check(_lib.rafem_colour_elements(n_nodes, E, npe, conn.ctypes.data, col.ctypes.data, C.byref(nc)))
     return col, int(nc.value)
+
+
+def rcm_order(conn: np.ndarray, n_nodes: int) -> np.ndarray:
+    """rafem_rcm_order -> order int32 [n_nodes] (order[k] = node placed at position k)."""
+    conn = _host_i32(conn)
+    E, npe = conn.shape
+    order = np.empty(n_nodes, dtype=np.int32)
+    _check(_lib.rafem_rcm_order(n_nodes, E, npe, conn.ctypes.data, order.ctypes.data))
+    return order
 
 
 # --------------------------------------------------------------------------------------

@@ -399,6 +399,18 @@ rafem_status rafem_colour_elements(int64_t n_nodes, int64_t n_elems, int32_t npe
     });
 }
 
+rafem_status rafem_rcm_order(int64_t n_nodes, int64_t n_elems, int32_t npe,
+                             const int32_t* conn_h, int32_t* order_h) {
+    return guard([&]() -> rafem_status {
+        require(order_h != nullptr, "order is NULL");
+        check_conn(n_nodes, n_elems, npe, conn_h);
+        const HostStructure S = build_structure(n_nodes, n_elems, npe, conn_h);
+        const std::vector<int32_t> order = rcm_order(n_nodes, S);
+        std::memcpy(order_h, order.data(), order.size() * sizeof(int32_t));
+        return RAFEM_OK;
+    });
+}
+
 rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, const double* xyz_h,
                                const int32_t* conn_h, const int32_t* dir_ids_h, int64_t n_dir,
                                rafem_mesh* out) {

@@ -53,8 +53,11 @@ HostSell build_sell(const HostStructure& S, int64_t n, const std::vector<int64_t
 // Throws Error on bad input.
 void check_conn(int64_t n_nodes, int64_t n_elems, int npe, const int32_t* conn);
 HostStructure build_structure(int64_t n_nodes, int64_t n_elems, int npe, const int32_t* conn);
+constexpr int kColourWords = 4;  // colour masks of 4 x 64 bits: at most 256 colours
 int colour_elements(int64_t n_nodes, int64_t n_elems, int npe, const int32_t* conn,
                     int32_t* colour);
+// Reverse Cuthill-McKee order of the node graph: order[k] = node placed at position k.
+std::vector<int32_t> rcm_order(int64_t n, const HostStructure& S);
 // Minimum Jacobian determinant over the quadrature points of every element (hex: 2x2x2
 // Gauss points; tet: the constant determinant).  Throws E_MESH if any is <= 0.
 // Returns true when every element is affine (hex: a parallelepiped; tets always are).

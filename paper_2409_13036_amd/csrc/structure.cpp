@@ -221,21 +221,114 @@ HostSell build_sell(const HostStructure& S, int64_t n, const std::vector<int64_t
 
 int colour_elements(int64_t n, int64_t E, int npe, const int32_t* conn, int32_t* colour) {
     // Greedy first fit in element order.  mask[node] holds the colours of the already
-    // coloured elements that touch the node; an element takes the lowest colour absent
-    // from the union of its nodes' masks, so no two elements of one colour share a node.
-    std::vector<uint64_t> mask(n, 0);
+    // coloured elements that touch the node (kColourWords x 64 bits); an element takes the
+    // lowest colour absent from the union of its nodes' masks, so no two elements of one
+    // colour share a node.
+    std::vector<uint64_t> mask((size_t)n * kColourWords, 0);
     int used = 0;
     for (int64_t e = 0; e < E; ++e) {
         const int32_t* el = conn + e * npe;
-        uint64_t taken = 0;
-        for (int a = 0; a < npe; ++a) taken |= mask[el[a]];
-        if (taken == ~0ull) throw Error{RAFEM_E_MESH, "element colouring needs more than 64 colours"};
-        int c = __builtin_ctzll(~taken);
+        uint64_t taken[kColourWords] = {};
+        for (int a = 0; a < npe; ++a)
+            for (int w = 0; w < kColourWords; ++w) taken[w] |= mask[(size_t)el[a] * kColourWords + w];
+        int c = -1;
+        for (int w = 0; w < kColourWords && c < 0; ++w)
+            if (taken[w] != ~0ull) c = 64 * w + __builtin_ctzll(~taken[w]);
+        if (c < 0)
+            throw Error{RAFEM_E_MESH, "element colouring needs more than " +
+                                          std::to_string(64 * kColourWords) + " colours"};
         colour[e] = c;
         used = std::max(used, c + 1);
-        for (int a = 0; a < npe; ++a) mask[el[a]] |= (1ull << c);
+        for (int a = 0; a < npe; ++a) mask[(size_t)el[a] * kColourWords + c / 64] |= 1ull << (c % 64);
     }
     return used;
+}
+
+std::vector<int32_t> rcm_order(int64_t n, const HostStructure& S) {
+    // Reverse Cuthill-McKee on the node graph (neighbours: the row's columns without the
+    // diagonal).  Per component, in order of its smallest node id: the pseudo-peripheral
+    // start node of George and Liu (from the node of least degree, move to the least-degree
+    // node of the last BFS level while the number of levels grows; ties: smallest id), then
+    // breadth-first search taking unvisited neighbours by increasing degree (ties: smallest
+    // id); finally the whole order is reversed.
+    auto deg = [&](int64_t v) { return S.row_ptr[v + 1] - S.row_ptr[v] - 1; };
+    auto less = [&](int32_t a, int32_t b) { return deg(a) != deg(b) ? deg(a) < deg(b) : a < b; };
+    std::vector<int32_t> order;
+    order.reserve(n);
+    std::vector<char> visited(n, 0);
+    std::vector<int32_t> mark(n, 0);  // BFS stamps
+    int32_t stamp = 0;
+    std::vector<int32_t> comp, cur, nxt;
+    // levels of a BFS from r: returns their number; cur holds the last level
+    auto levels = [&](int32_t r) {
+        ++stamp;
+        mark[r] = stamp;
+        cur.assign(1, r);
+        int nlev = 1;
+        for (;;) {
+            nxt.clear();
+            for (int32_t v : cur)
+                for (int32_t k = S.row_ptr[v]; k < S.row_ptr[v + 1]; ++k) {
+                    const int32_t w = S.col_idx[k];
+                    if (mark[w] != stamp) {
+                        mark[w] = stamp;
+                        nxt.push_back(w);
+                    }
+                }
+            if (nxt.empty()) return nlev;
+            cur.swap(nxt);
+            ++nlev;
+        }
+    };
+    for (int64_t seed = 0; seed < n; ++seed) {
+        if (visited[seed]) continue;
+        // the component of seed
+        ++stamp;
+        mark[seed] = stamp;
+        comp.assign(1, (int32_t)seed);
+        for (size_t i = 0; i < comp.size(); ++i) {
+            const int32_t v = comp[i];
+            for (int32_t k = S.row_ptr[v]; k < S.row_ptr[v + 1]; ++k) {
+                const int32_t w = S.col_idx[k];
+                if (mark[w] != stamp) {
+                    mark[w] = stamp;
+                    comp.push_back(w);
+                }
+            }
+        }
+        int32_t r = *std::min_element(comp.begin(), comp.end(), less);
+        int nlev = levels(r);
+        for (;;) {
+            const int32_t cand = *std::min_element(cur.begin(), cur.end(), less);
+            const int nl = levels(cand);
+            if (nl > nlev) {
+                r = cand;
+                nlev = nl;
+            } else {
+                break;
+            }
+        }
+        // Cuthill-McKee from r
+        size_t head = order.size();
+        visited[r] = 1;
+        order.push_back(r);
+        std::vector<int32_t> fresh;
+        while (head < order.size()) {
+            const int32_t v = order[head++];
+            fresh.clear();
+            for (int32_t k = S.row_ptr[v]; k < S.row_ptr[v + 1]; ++k) {
+                const int32_t w = S.col_idx[k];
+                if (!visited[w]) {
+                    visited[w] = 1;
+                    fresh.push_back(w);
+                }
+            }
+            std::sort(fresh.begin(), fresh.end(), less);
+            order.insert(order.end(), fresh.begin(), fresh.end());
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
 }
 
 bool check_geometry(int64_t E, int npe, const int32_t* conn, const double* xyz) {

@@ -14,6 +14,41 @@ import numpy as np
 from . import _lib as rafem
 
 
+def reorder_nodes(problem, order: np.ndarray):
+    """The same problem with its nodes renumbered: node order[k] becomes node k.  Elements
+    keep their ids; Dirichlet, electrode and loss sets are renumbered and re-sorted with
+    their values.  A state x of the new problem maps back by x_old[order] = x_new."""
+    import dataclasses
+    order = np.asarray(order, dtype=np.int64)
+    n = problem.xyz.shape[0]
+    if order.shape != (n,) or not np.array_equal(np.sort(order), np.arange(n)):
+        raise ValueError("order must be a permutation of the node ids")
+    inv = np.empty(n, dtype=np.int64)
+    inv[order] = np.arange(n)
+
+    def relabel(ids, *vals):
+        new = inv[ids]
+        k = np.argsort(new, kind="stable")
+        return (new[k].astype(np.int32),) + tuple(v[k] for v in vals)
+
+    dir_ids, dir_V, dir_T = relabel(problem.dir_ids, problem.dir_V, problem.dir_T)
+    (electrode,) = relabel(problem.electrode_ids)
+    loss_ids, T_target = problem.loss_ids, problem.T_target
+    if loss_ids is not None:
+        loss_ids, T_target = relabel(loss_ids, T_target)
+    return dataclasses.replace(
+        problem, xyz=np.ascontiguousarray(problem.xyz[order]),
+        conn=np.ascontiguousarray(inv[problem.conn].astype(np.int32)), dir_ids=dir_ids,
+        dir_V=np.ascontiguousarray(dir_V), dir_T=np.ascontiguousarray(dir_T),
+        electrode_ids=electrode, loss_ids=loss_ids, T_target=T_target)
+
+
+def rcm_reordered(problem):
+    """(problem renumbered by the library's reverse Cuthill-McKee order, order)."""
+    order = rafem.rcm_order(problem.conn, problem.xyz.shape[0])
+    return reorder_nodes(problem, order), order
+
+
 class DeviceProblem:
     def __init__(self, problem, device=None):
         import torch

@@ -276,3 +276,120 @@ def config4(seed: int = 0, samples: int = 64, n_lo: int = 41, n_hi: int = 81,
 def random_vector(n: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
     """Seeded test vector for kernel-level parity checks."""
     return np.random.default_rng(seed).uniform(lo, hi, size=n)
+
+
+# --- unstructured liver-like tet meshes (stand-ins for the paper's meshes A and B) -------
+
+# Two overlapping ellipsoidal lobes (centres and semi-axes in m), a liver-like blob of
+# about 58 cm^3; two parallel needle electrodes along z through the main lobe.
+LIVER_LOBES = (((0.0, 0.0, 0.0), (0.030, 0.020, 0.016)),
+               ((-0.018, 0.012, -0.002), (0.018, 0.014, 0.012)))
+NEEDLE_X = (0.010, -0.010)     # needle axes at (x, 0), z in [-15 mm, 15 mm]
+NEEDLE_HALF_M = 0.015
+V_NEEDLES = (10.0, -10.0)      # bipolar: the potential is lower on one side
+LIVER_NODES_A, LIVER_NODES_B = 3548, 8364   # node counts of the paper's meshes (Table II)
+
+
+def _inside_liver(p: np.ndarray) -> np.ndarray:
+    ok = np.zeros(p.shape[0], dtype=bool)
+    for c, ax in LIVER_LOBES:
+        ok |= (((p - np.asarray(c)) / np.asarray(ax)) ** 2).sum(axis=1) <= 1.0
+    return ok
+
+
+def _liver_volume() -> float:
+    """Volume of the blob, counted on a 0.5 mm lattice (deterministic)."""
+    g = 5e-4
+    lo = np.array([-0.036, -0.020, -0.016])
+    hi = np.array([0.030, 0.026, 0.016])
+    axes = [np.arange(lo[d] + g / 2, hi[d], g) for d in range(3)]
+    count = 0
+    for z in axes[2]:
+        y, x = np.meshgrid(axes[1], axes[0], indexing="ij")
+        pts = np.stack([x.ravel(), y.ravel(), np.full(x.size, z)], axis=1)
+        count += int(_inside_liver(pts).sum())
+    return count * g ** 3
+
+
+def make_liver(nodes: int = LIVER_NODES_A, seed: int = 0, *, steps: int = 1, tol: float = 1e-10,
+               shuffle: bool = True, name: Optional[str] = None) -> Problem:
+    """An unstructured tet mesh of the liver-like blob with about ``nodes`` nodes.
+
+    Points: a cubic lattice of spacing h (chosen from the blob's volume) jittered by
+    U(-0.25h, 0.25h) per coordinate, those inside the blob kept; elements: the Delaunay
+    tetrahedra of the points whose centroid lies inside the blob (positively oriented,
+    near-degenerate hull tets dropped, unused points removed).  D = boundary nodes (on
+    faces used by one tet: 0 V, 37 C) united with two needle electrodes (nodes within
+    0.75h of the needle axes over 30 mm: +10 V and -10 V, 90 C).  shuffle: node ids in a
+    seeded random order, as a mesher may deliver them.  Material fields as in
+    make_problem.  Draw order: jitter, eps per element, the shuffle permutation.
+    """
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    h = (_liver_volume() / nodes) ** (1.0 / 3.0)
+    lo = np.array([-0.036, -0.020, -0.016])
+    hi = np.array([0.030, 0.026, 0.016])
+    axes = [np.arange(lo[d], hi[d] + h, h) for d in range(3)]
+    z, y, x = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    pts = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    pts = pts + rng.uniform(-0.25 * h, 0.25 * h, size=pts.shape)
+    pts = pts[_inside_liver(pts)]
+    tets = Delaunay(pts).simplices.astype(np.int64)
+    cen = pts[tets].mean(axis=1)
+    tets = tets[_inside_liver(cen)]
+    # orientation and near-degenerate tets (6 x signed volume)
+    a, b, c, d = (pts[tets[:, i]] for i in range(4))
+    vol6 = np.einsum("ij,ij->i", b - a, np.cross(c - a, d - a))
+    flip = vol6 < 0
+    tets[flip, 2], tets[flip, 3] = tets[flip, 3].copy(), tets[flip, 2].copy()
+    tets = tets[np.abs(vol6) > 1e-3 * h ** 3]
+    used = np.unique(tets)
+    remap = -np.ones(pts.shape[0], dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    xyz = pts[used]
+    conn = remap[tets]
+    N, E = xyz.shape[0], conn.shape[0]
+    # boundary nodes: nodes of faces that belong to one tet
+    faces = np.sort(np.concatenate([conn[:, [1, 2, 3]], conn[:, [0, 2, 3]], conn[:, [0, 1, 3]],
+                                    conn[:, [0, 1, 2]]]), axis=1)
+    uf, cnt = np.unique(faces, axis=0, return_counts=True)
+    boundary = np.unique(uf[cnt == 1])
+    # needle electrodes
+    needles = []
+    for xn in NEEDLE_X:
+        r = np.hypot(xyz[:, 0] - xn, xyz[:, 1])
+        ids = np.nonzero((r <= 0.75 * h) & (np.abs(xyz[:, 2]) <= NEEDLE_HALF_M))[0]
+        needles.append(np.setdiff1d(ids, boundary))
+    eps = rng.uniform(-0.1, 0.1, size=E)
+    perm = rng.permutation(N) if shuffle else np.arange(N)
+    # node old -> new: new id of old node i is inv[i]
+    inv = np.empty(N, dtype=np.int64)
+    inv[perm] = np.arange(N)
+    xyz = np.ascontiguousarray(xyz[perm])
+    conn = np.ascontiguousarray(inv[conn].astype(np.int32))
+    boundary = inv[boundary]
+    needles = [inv[ids] for ids in needles]
+    dir_ids = np.unique(np.concatenate([boundary, *needles])).astype(np.int32)
+    dir_V = np.full(dir_ids.size, V_FACES)
+    dir_T = np.full(dir_ids.size, T_FACES)
+    for ids, v in zip(needles, V_NEEDLES):
+        k = np.searchsorted(dir_ids, ids)
+        dir_V[k] = v
+        dir_T[k] = T_ELECTRODE
+    electrode = np.sort(np.concatenate(needles)).astype(np.int32)
+    return Problem(name=name or f"liver{N}", kind="tet", n=int(round(N ** (1.0 / 3.0))), h=h,
+                   xyz=xyz, conn=conn, electrode_ids=electrode, dir_ids=dir_ids,
+                   dir_V=dir_V.astype(np.float64), dir_T=dir_T.astype(np.float64),
+                   k_e=np.ascontiguousarray(K_TISSUE * (1.0 + eps)),
+                   perf_e=np.full(E, PERFUSION), sigma0_e=np.full(E, SIGMA0), steps=steps,
+                   tol=tol, coupled=True)
+
+
+def liver_mesh_a(seed: int = 0, **kw) -> Problem:
+    """Stand-in for the paper's mesh A (3,548 nodes, 18,363 tets, Table II)."""
+    return make_liver(LIVER_NODES_A, seed, name="liverA", **kw)
+
+
+def liver_mesh_b(seed: int = 0, **kw) -> Problem:
+    """Stand-in for the paper's mesh B (8,364 nodes, 44,811 tets, Table II)."""
+    return make_liver(LIVER_NODES_B, seed, name="liverB", **kw)

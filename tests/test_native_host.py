@@ -96,3 +96,20 @@ def test_mesh_create_without_device_fails_cleanly(rafem):
     p = ri.make_problem("hex", 5, 0)
     with pytest.raises(RuntimeError):
         rafem.Mesh(p.xyz, p.conn, p.dir_ids)
+
+
+@pytest.mark.parametrize("mesh", ["hex7", "tet6", "liverA"])
+def test_rcm_order_bit_exact_vs_oracle(rafem, mesh):
+    from oracle import reorder
+    p = {"hex7": lambda: ri.make_problem("hex", 7, 0), "tet6": lambda: ri.make_problem("tet", 6, 1),
+         "liverA": ri.liver_mesh_a}[mesh]()
+    assert np.array_equal(rafem.rcm_order(p.conn, p.n_nodes), reorder.rcm_order(p.conn, p.n_nodes))
+
+
+def test_colouring_of_unstructured_mesh(rafem):
+    p = ri.liver_mesh_a()
+    col, nc = rafem.colour_elements(p.conn, p.n_nodes)
+    assert 8 < nc <= 256
+    for c in range(nc):
+        nodes = p.conn[col == c].ravel()
+        assert np.unique(nodes).size == nodes.size
