@@ -533,6 +533,54 @@ def mono_leg(dp, args) -> dict:
     return out
 
 
+def liver_leg(args) -> dict:
+    """Unstructured liver-like tet meshes (Delaunay, two needle electrodes): the stand-ins for
+    the paper's meshes A and B (about 3.5k and 8.4k nodes) in RCM order, then one of
+    --liver-nodes nodes in the delivered (shuffled) order and in RCM order -- coupled steps/s
+    (FP64 and mixed) and the PCG SpMV's launch time and CSR-count bandwidth."""
+    import numpy as np
+    import torch
+    import rafem_inputs as ri
+    from paper_2409_13036_amd.sim import DeviceProblem, rcm_reordered
+
+    def bandwidth(conn, order):
+        pos = np.argsort(order) if order is not None else np.arange(conn.max() + 1)
+        c = pos[conn]
+        return int((c.max(axis=1) - c.min(axis=1)).max())
+
+    def measure(prob, steps, warmup, label):
+        dp = DeviceProblem(prob)
+        st = dp.mesh.stats()
+        N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
+        row = {"n_nodes": N, "n_elems": dp.mesh.n_elems, "nnz": nnz, "colours": st.n_colours,
+               "slabs": int(st.slabs), "int16_columns": int(st.int16_columns)}
+        for precision in ("fp64", "mixed"):
+            el, infos, _, (us, cnt) = run_path(dp, precision, steps, warmup, 1)
+            fp32 = precision == "mixed"
+            row[precision] = {
+                "steps_per_s": steps / el,
+                "V_iters": float(np.mean([i["V"]["iters"] for i in infos])),
+                "spmv_us": us, "spmv_GBs": spmv_bytes(N, nnz, fp32) / (us * 1e3) if us else None}
+            print(f"[bench] liver {label} {precision}: {steps / el:.2f} steps/s, spmv {us:.1f} us",
+                  file=sys.stderr, flush=True)
+        dp.close()
+        return row
+
+    out = {"workload": "unstructured liver-like tet meshes, bipolar needle electrodes"}
+    for name, make in (("mesh_A", ri.liver_mesh_a), ("mesh_B", ri.liver_mesh_b)):
+        q, _ = rcm_reordered(make())
+        out[name] = measure(q, args.liver_steps, 3, name)
+    t0 = time.perf_counter()
+    p = ri.make_liver(args.liver_nodes, 0)
+    out["large_mesh_generation_s"] = time.perf_counter() - t0
+    q, order = rcm_reordered(p)
+    for label, prob, o in (("shuffled", p, None), ("rcm", q, order)):
+        row = measure(prob, args.liver_steps, 2, f"{args.liver_nodes} {label}")
+        row["bandwidth"] = bandwidth(p.conn, o)
+        out[f"large_{label}"] = row
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -553,6 +601,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the ensemble leg")
     ap.add_argument("--no-pc", action="store_true", help="skip the predictor-corrector leg")
     ap.add_argument("--no-mono", action="store_true", help="skip the monolithic GMRES leg")
+    ap.add_argument("--liver", action="store_true",
+                    help="run only the unstructured liver-mesh leg (meshes A, B and a large one)")
+    ap.add_argument("--liver-nodes", type=int, default=400000)
+    ap.add_argument("--liver-steps", type=int, default=10)
     ap.add_argument("--mono-only", action="store_true",
                     help="run only the monolithic GMRES leg (on the c1 mesh)")
     ap.add_argument("--mono-m", type=int, nargs="+", default=[10, 20, 30, 50, 100],
@@ -591,6 +643,9 @@ def main():
         return
     if args.batch_only:
         print(json.dumps(batch_leg(args)), flush=True)
+        return
+    if args.liver:
+        print(json.dumps(liver_leg(args)), flush=True)
         return
     if args.mono_only:
         import rafem_inputs as ri
