@@ -133,7 +133,21 @@ def run_path(dp, precision: str, steps: int, warmup: int, profile_steps: int, **
     torch.cuda.synchronize()
     mean_us, count = R.profile_read(dp.mesh, precision, reset=True)
     R.profile_enable(dp.mesh, False)
+    dp.regions = regions_pass(dp, lambda: dp.step(TOL, precision, **kw), 2)
     return elapsed, infos, (T_end, V_end), (mean_us, count)
+
+
+def regions_pass(dp, step, n):
+    """Mean assembly / solve / check milliseconds per step over n more steps, timed by the
+    library's region events (the breakdown of the paper's traced regions)."""
+    from paper_2409_13036_amd import _lib as R
+    R.regions_enable(dp.mesh, True)
+    R.regions_read(dp.mesh, reset=True)
+    for _ in range(n):
+        step()
+    r = R.regions_read(dp.mesh, reset=True)
+    R.regions_enable(dp.mesh, False)
+    return r
 
 
 def adjoint_leg(args) -> dict:
@@ -425,6 +439,8 @@ def pc_leg(dp, args) -> dict:
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         finals[precision] = (dp.T.clone(), dp.V.clone())
+        reg = regions_pass(dp, lambda: dp.step_pc(args.pc_dt0, corr_tol=args.pc_eps, tol=TOL,
+                                                  precision=precision), 1)
         its = [r["iters"] for r in rec]
         out[precision] = {
             "accepted_steps": len(rec), "rejected": sum(r["rejected_before"] for r in rec),
@@ -432,7 +448,8 @@ def pc_leg(dp, args) -> dict:
             "simulated_s_per_s": args.pc_t / el,
             "corrector_iters_mean": float(np.mean(its)), "corrector_iters_max": max(its),
             "corrector_iters_per_s": sum(its) / el,
-            "solver_iters_total": int(sum(r["solver_iters"] for r in rec))}
+            "solver_iters_total": int(sum(r["solver_iters"] for r in rec)),
+            "regions_ms_one_step": reg}
         print(f"[bench] predictor-corrector {precision}: {len(rec)} steps in {el:.2f} s, "
               f"corrector iterations {its}", file=sys.stderr, flush=True)
     (Tm, Vm), (T64, V64) = finals["mixed"], finals["fp64"]
@@ -523,13 +540,43 @@ def mono_leg(dp, args) -> dict:
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         its = [x["iters"] for x in rec]
+        reg = regions_pass(dp, lambda: dp.step_mono(args.pc_dt0, corr_tol=args.pc_eps, m=r["m"]), 1)
         out["predictor_corrector"] = {
+            "regions_ms_one_step": reg,
             "t_total_s": args.pc_t, "dt0_s": args.pc_dt0, "eps": args.pc_eps,
             "accepted_steps": len(rec), "rejected": sum(x["rejected_before"] for x in rec),
             "elapsed_s": el, "accepted_steps_per_s": len(rec) / el,
             "newton_iters": its, "gmres_iters_total": int(sum(x["solver_iters"] for x in rec))}
         print(f"[bench] monolithic predictor-corrector: {len(rec)} steps in {el:.2f} s, Newton "
               f"iterations {its}", file=sys.stderr, flush=True)
+    return out
+
+
+def psnr_leg(dp, args) -> dict:
+    """PSNR per step (the paper's result-quality metric) of GPU runs against the FP64 run at
+    tol 1e-13 from the same initial state: the mixed path, and FP64 at tol 1e-6 (the
+    paper's low-tolerance solver setting); min and median over the steps with the 1e-5 and
+    1e-12 control lines."""
+    from paper_2409_13036_amd import report
+
+    def run(precision, tol):
+        dp.reset()
+        T, V = [], []
+        for _ in range(args.psnr_steps):
+            dp.step(tol, precision)
+            T.append(dp.T.cpu().numpy())
+            V.append(dp.V.cpu().numpy())
+        return T, V
+
+    refT, refV = run("fp64", TOL)
+    out = {"workload": f"{args.psnr_steps} coupled steps from the initial state; reference: "
+                       f"FP64 at tol {TOL:g}"}
+    for label, precision, tol in (("mixed", "mixed", TOL), ("fp64_tol_1e-6", "fp64", 1e-6)):
+        T, V = run(precision, tol)
+        out[label] = {"T": report.summary(refT, T), "V": report.summary(refV, V)}
+        print(f"[bench] PSNR {label}: T min {out[label]['T']['min_db']:.1f} dB, V min "
+              f"{out[label]['V']['min_db']:.1f} dB (controls {out[label]['T']['control_db']})",
+              file=sys.stderr, flush=True)
     return out
 
 
@@ -601,6 +648,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the ensemble leg")
     ap.add_argument("--no-pc", action="store_true", help="skip the predictor-corrector leg")
     ap.add_argument("--no-mono", action="store_true", help="skip the monolithic GMRES leg")
+    ap.add_argument("--no-psnr", action="store_true", help="skip the PSNR leg")
+    ap.add_argument("--psnr-steps", type=int, default=20)
     ap.add_argument("--liver", action="store_true",
                     help="run only the unstructured liver-mesh leg (meshes A, B and a large one)")
     ap.add_argument("--liver-nodes", type=int, default=400000)
@@ -686,6 +735,7 @@ def main():
         it_v = float(np.mean([i["V"]["iters"] for i in infos]))
         it_t = float(np.mean([i["T"]["iters"] for i in infos]))
         res[precision] = {"elapsed": el, "state": state, "spmv_us": mean_us, "spmv_count": count,
+                          "regions": dp.regions,
                           "V_iters": it_v, "T_iters": it_t,
                           "V_outer": float(np.mean([i["V"]["outer"] for i in infos])),
                           "relres_true_max": max(max(i["V"]["relres_true"], i["T"]["relres_true"])
@@ -746,19 +796,23 @@ def main():
                  "spmv_us": res["fp64"]["spmv_us"],
                  "spmv_GBs": spmv_bytes(N, nnz, False) / (res["fp64"]["spmv_us"] * 1e-6) / 1e9
                  if res["fp64"]["spmv_us"] > 0 else None,
-                 "relres_true_max": res["fp64"]["relres_true_max"]},
+                 "relres_true_max": res["fp64"]["relres_true_max"],
+                 "regions_ms_per_step": res["fp64"]["regions"]},
         "mixed": {"steps_per_s": args.steps / res["mixed"]["elapsed"],
                   "V_inner_iters": res["mixed"]["V_iters"], "V_outer": res["mixed"]["V_outer"],
                   "T_inner_iters": res["mixed"]["T_iters"], "spmv_us": res["mixed"]["spmv_us"],
                   "spmv_GBs": spmv_bytes(N, nnz, True) / (res["mixed"]["spmv_us"] * 1e-6) / 1e9
                   if res["mixed"]["spmv_us"] > 0 else None,
                   "relres_true_max": res["mixed"]["relres_true_max"],
-                  "rel_err_vs_fp64": {"T": errT, "V": errV}},
+                  "rel_err_vs_fp64": {"T": errT, "V": errV},
+                  "regions_ms_per_step": res["mixed"]["regions"]},
     }
     if cpu:
         line["speedup_vs_cpu_oracle"] = sps / cpu["value"]
     if not args.no_pc:
         line["predictor_corrector"] = pc_leg(dp, args)
+    if not args.no_psnr:
+        line["psnr"] = psnr_leg(dp, args)
     if not args.no_mono:
         line["monolithic"] = mono_leg(dp, args)
     dp.close()

@@ -279,6 +279,24 @@ rafem_status rafem_profile_read(rafem_mesh mesh, int32_t precision, double* mean
                                 int64_t* count, int32_t reset);
 
 /* ---------------------------------------------------------------------------
+ * Region timing, the breakdown of a time step into the paper's traced regions (Sec. III-C,
+ * Fig. 11: assembly, solve, and the copies of the convergence check).  When enabled, each
+ * rafem_step, rafem_step_pc and rafem_step_mono call records HIP events on its stream at
+ * the boundaries of its regions and, once the step has finished, adds the device time of
+ * every interval to its region.  Off by default (the events cost a few microseconds).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double  assembly_ms;  /* matrix / Jacobian assembly, lifting, right-hand sides */
+    double  solve_ms;     /* linear solves (PCG, mixed refinement, GMRES) with their polls */
+    double  check_ms;     /* corrector convergence checks, state copies, predictor */
+    int64_t steps;        /* step calls measured */
+} rafem_regions;
+
+rafem_status rafem_regions_enable(rafem_mesh mesh, int32_t enable);
+/* Accumulated times since the last reset (reset != 0 clears them after reading). */
+rafem_status rafem_regions_read(rafem_mesh mesh, rafem_regions* out, int32_t reset);
+
+/* ---------------------------------------------------------------------------
  * One coupled time step (Sec. II-A, Fig. 1: assemble + solve for voltage and heat).
  * ------------------------------------------------------------------------- */
 typedef struct {

@@ -36,7 +36,8 @@ EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafe
            "rafem_profile_read", "rafem_step", "rafem_step_vjp", "rafem_lesion_loss",
            "rafem_mesh_create_batch", "rafem_mesh_sample_layout", "rafem_mesh_set_graphs",
            "rafem_sample_info", "rafem_spmv_timing", "rafem_step_pc", "rafem_mono_jacobian",
-           "rafem_mono_solve", "rafem_step_mono", "rafem_rcm_order")
+           "rafem_mono_solve", "rafem_step_mono", "rafem_rcm_order", "rafem_regions_enable",
+           "rafem_regions_read")
 
 
 class RafemError(RuntimeError):
@@ -102,6 +103,11 @@ class MonoInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
+class Regions(C.Structure):
+    _fields_ = [("assembly_ms", C.c_double), ("solve_ms", C.c_double), ("check_ms", C.c_double),
+                ("steps", C.c_int64)]
+
+
 class Phys(C.Structure):
     _fields_ = [("rho_c", C.c_double), ("dt", C.c_double), ("T_a", C.c_double),
                 ("alpha_sigma", C.c_double), ("T_ref", C.c_double), ("coupled", C.c_int32),
@@ -129,6 +135,8 @@ _lib.rafem_solve_adjoint.argtypes = [_p, _p, _p, _p, _p, _p, _p, C.POINTER(Solve
 _lib.rafem_spmv.argtypes = [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
 _lib.rafem_profile_enable.argtypes = [_p, _i32]
 _lib.rafem_profile_read.argtypes = [_p, _i32, C.POINTER(C.c_double), C.POINTER(C.c_int64), _i32]
+_lib.rafem_regions_enable.argtypes = [_p, _i32]
+_lib.rafem_regions_read.argtypes = [_p, C.POINTER(Regions), _i32]
 _lib.rafem_spmv_timing.argtypes = [_p, _i32, _i32, _i32, C.POINTER(C.c_double)]
 _lib.rafem_step.argtypes = [_p, C.POINTER(Phys), _p, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts),
                             C.POINTER(StepInfo), _p]
@@ -200,6 +208,20 @@ def colour_elements(conn: np.ndarray, n_nodes: int):
     nc = C.c_int32(0)
     _check(_lib.rafem_colour_elements(n_nodes, E, npe, conn.ctypes.data, col.ctypes.data, C.byref(nc)))
     return col, int(nc.value)
+
+
+def regions_enable(mesh: "Mesh", enable: bool = True):
+    """rafem_regions_enable: time the assembly / solve / check regions of every step."""
+    _check(_lib.rafem_regions_enable(mesh.handle, 1 if enable else 0))
+
+
+def regions_read(mesh: "Mesh", reset: bool = True) -> dict:
+    """rafem_regions_read -> mean milliseconds per step of each region, and the step count."""
+    r = Regions()
+    _check(_lib.rafem_regions_read(mesh.handle, C.byref(r), 1 if reset else 0))
+    k = max(1, int(r.steps))
+    return {"assembly_ms": r.assembly_ms / k, "solve_ms": r.solve_ms / k,
+            "check_ms": r.check_ms / k, "steps": int(r.steps)}
 
 
 def rcm_order(conn: np.ndarray, n_nodes: int) -> np.ndarray:

@@ -58,10 +58,18 @@ void profile_off(rafem_mesh m) {
     m->prof_on = false;
 }
 
+void regions_off(rafem_mesh m) {
+    for (hipEvent_t e : m->reg_ev) (void)hipEventDestroy(e);
+    m->reg_ev.clear();
+    m->reg_kind.clear();
+    m->reg_on = false;
+}
+
 void free_mesh(rafem_mesh m) {
     if (!m) return;
     (void)hipDeviceSynchronize();
     profile_off(m);
+    regions_off(m);
     for (auto& g : m->graphs) (void)hipGraphExecDestroy(g.exec);
     m->graphs.clear();
     if (m->gstream) (void)hipStreamDestroy(m->gstream);
@@ -77,6 +85,40 @@ void check_device(rafem_mesh m) {
     int d = -1;
     RAFEM_HIP(hipGetDevice(&d));
     if (d != m->device) throw Error{RAFEM_E_ARG, "the current HIP device is not the mesh's device"};
+}
+
+// Region timing: mark() opens an interval of the given region at the current point of
+// the stream; flush() closes the step, waits for its last event and adds up the intervals.
+constexpr int kRegAssembly = 0, kRegSolve = 1, kRegCheck = 2;
+
+void region_mark(rafem_mesh m, int kind, hipStream_t s) {
+    if (!m->reg_on) return;
+    const size_t i = m->reg_kind.size();
+    if (i >= m->reg_ev.size()) {
+        hipEvent_t e;
+        RAFEM_HIP(hipEventCreate(&e));
+        m->reg_ev.push_back(e);
+    }
+    RAFEM_HIP(hipEventRecord(m->reg_ev[i], s));
+    m->reg_kind.push_back(kind);
+}
+
+// Start of a step: drop boundaries left by a step that ended in an error.
+void region_begin(rafem_mesh m) { m->reg_kind.clear(); }
+
+void region_flush(rafem_mesh m, hipStream_t s) {
+    if (!m->reg_on || m->reg_kind.empty()) return;
+    region_mark(m, -1, s);
+    const size_t n = m->reg_kind.size();
+    RAFEM_HIP(hipEventSynchronize(m->reg_ev[n - 1]));
+    for (size_t i = 0; i + 1 < n; ++i) {
+        if (m->reg_kind[i] < 0) continue;
+        float ms = 0.0f;
+        RAFEM_HIP(hipEventElapsedTime(&ms, m->reg_ev[i], m->reg_ev[i + 1]));
+        m->reg_ms[m->reg_kind[i]] += ms;
+    }
+    m->reg_kind.clear();
+    m->reg_steps += 1;
 }
 
 Layout csr_layout(rafem_mesh m) {
@@ -718,6 +760,35 @@ rafem_status rafem_profile_enable(rafem_mesh m, int32_t enable) {
     });
 }
 
+rafem_status rafem_regions_enable(rafem_mesh m, int32_t enable) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        if (enable) {
+            m->reg_on = true;
+            m->reg_kind.clear();
+        } else {
+            RAFEM_HIP(hipDeviceSynchronize());
+            regions_off(m);
+        }
+        return RAFEM_OK;
+    });
+}
+
+rafem_status rafem_regions_read(rafem_mesh m, rafem_regions* out, int32_t reset) {
+    return guard([&]() -> rafem_status {
+        require(m != nullptr && out != nullptr, "NULL argument");
+        out->assembly_ms = m->reg_ms[kRegAssembly];
+        out->solve_ms = m->reg_ms[kRegSolve];
+        out->check_ms = m->reg_ms[kRegCheck];
+        out->steps = m->reg_steps;
+        if (reset) {
+            m->reg_ms[0] = m->reg_ms[1] = m->reg_ms[2] = 0.0;
+            m->reg_steps = 0;
+        }
+        return RAFEM_OK;
+    });
+}
+
 rafem_status rafem_profile_read(rafem_mesh m, int32_t precision, double* mean_us, int64_t* count,
                                 int32_t reset) {
     return guard([&]() -> rafem_status {
@@ -760,6 +831,7 @@ rafem_status step_core(rafem_mesh m, const rafem_phys* phys, bool reuse_bioheat,
                        const double* T_rhs, double* T_out, double* V_d, const SolveOpts& o,
                        rafem_step_info& inf, hipStream_t s) {
     const bool mixed = o.precision == RAFEM_MIXED;
+    region_mark(m, kRegAssembly, s);
     launch_scatter_dirichlet(m->dir_ids, dir_T_d, m->nD, m->gT, s);
     if (!reuse_bioheat) assemble_bioheat(m, phys, k_e_d, perf_e_d, s);
     if (phys->coupled) {
@@ -769,8 +841,10 @@ rafem_status step_core(rafem_mesh m, const rafem_phys* phys, bool reuse_bioheat,
         RAFEM_HIP(hipGetLastError());
         const Mat AV = step_matrix(m, m->valsV, m->valsV32);
         if (!m->tuned) autotune_spmv(m, AV, s);
+        region_mark(m, kRegSolve, s);
         solve_any(m, o, AV, step_samples(m), m->dinvV, m->dinvV32, m->liftV, V_d, &inf.V, s,
                   kSolvePotential);
+        region_mark(m, kRegAssembly, s);
         record_samples(m, true, mixed);
         if (inf.V.status != RAFEM_OK) {
             set_error("potential solve failed");
@@ -790,8 +864,10 @@ rafem_status step_core(rafem_mesh m, const rafem_phys* phys, bool reuse_bioheat,
     RAFEM_HIP(hipGetLastError());
     const Mat AT = step_matrix(m, m->valsT, m->valsT32);
     if (!m->tuned) autotune_spmv(m, AT, s);
+    region_mark(m, kRegSolve, s);
     solve_any(m, o, AT, step_samples(m), m->dinvT, m->dinvT32, m->bT, T_out, &inf.T, s,
               kSolveBioheat);
+    region_mark(m, kRegCheck, s);
     record_samples(m, false, mixed);
     if (inf.T.status != RAFEM_OK) {
         set_error("bioheat solve failed");
@@ -816,8 +892,11 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
         std::memset(&inf, 0, sizeof(inf));
         // a bioheat matrix built for another time step is rebuilt
         const bool reuse = phys->reuse_bioheat && m->bioheat_dt == phys->dt;
-        return step_core(m, phys, reuse, k_e_d, perf_e_d, sigma0_e_d, dir_V_d, dir_T_d, T_d, T_d,
-                         T_d, V_d, o, inf, (hipStream_t)stream);
+        region_begin(m);
+        const rafem_status st = step_core(m, phys, reuse, k_e_d, perf_e_d, sigma0_e_d, dir_V_d,
+                                          dir_T_d, T_d, T_d, T_d, V_d, o, inf, (hipStream_t)stream);
+        region_flush(m, (hipStream_t)stream);
+        return st;
     });
 }
 
@@ -841,6 +920,8 @@ rafem_status rafem_step_pc(rafem_mesh m, const rafem_phys* phys, const double* k
         rafem_corrector_info& ci = info ? *info : local;
         std::memset(&ci, 0, sizeof(ci));
         const size_t bytes = (size_t)m->n * sizeof(double);
+        region_begin(m);
+        region_mark(m, kRegCheck, s);
         // keep (T^n, V^n) to restore a rejected step; predictor into pc_Tk
         RAFEM_HIP(hipMemcpyAsync(m->pc_Tn, T_d, bytes, hipMemcpyDeviceToDevice, s));
         if (phys->coupled)
@@ -882,6 +963,7 @@ rafem_status rafem_step_pc(rafem_mesh m, const rafem_phys* phys, const double* k
                 RAFEM_HIP(hipMemcpyAsync(V_d, m->pc_Vn, bytes, hipMemcpyDeviceToDevice, s));
             RAFEM_HIP(hipStreamSynchronize(s));
         }
+        region_flush(m, s);
         return st;
     });
 }
@@ -961,6 +1043,8 @@ rafem_status rafem_step_mono(rafem_mesh m, const rafem_phys* phys, const double*
         std::memset(&mi, 0, sizeof(mi));
         mono_ensure(m, o.m);
         const size_t bytes = (size_t)m->n * sizeof(double);
+        region_begin(m);
+        region_mark(m, kRegCheck, s);
         // keep (T^n, V^n) to restore a rejected step; the iterate starts at (T*, V^n) with
         // the Dirichlet values
         RAFEM_HIP(hipMemcpyAsync(m->pc_Tn, T_d, bytes, hipMemcpyDeviceToDevice, s));
@@ -973,9 +1057,12 @@ rafem_status rafem_step_mono(rafem_mesh m, const rafem_phys* phys, const double*
         launch_set_dirichlet(m->dir_ids, m->gV, m->nD, V_d, s);
         rafem_status st = RAFEM_OK;
         for (int k = 1; k <= max_iters; ++k) {
+            region_mark(m, kRegAssembly, s);
             mono_assemble(m, phys, k_e_d, perf_e_d, sigma0_e_d, m->pc_Tn, T_d, V_d, s);
             rafem_gmres_info gi{};
+            region_mark(m, kRegSolve, s);
             st = gmres_solve(m, m->mono_rhs, m->mono_delta, o, nullptr, 0, &gi, s);
+            region_mark(m, kRegCheck, s);
             mi.iters = k;
             mi.gmres_iters += gi.iters;
             mi.gmres_cycles += gi.cycles;
@@ -1005,6 +1092,7 @@ rafem_status rafem_step_mono(rafem_mesh m, const rafem_phys* phys, const double*
             RAFEM_HIP(hipMemcpyAsync(V_d, m->pc_Vn, bytes, hipMemcpyDeviceToDevice, s));
             RAFEM_HIP(hipStreamSynchronize(s));
         }
+        region_flush(m, s);
         return st;
     });
 }

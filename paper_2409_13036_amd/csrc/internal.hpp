@@ -444,6 +444,14 @@ struct rafem_mesh_s {
     std::vector<int> mixed_iters;   // per sample: inner (+ FP64 fallback) iterations of the last mixed solve
     std::vector<char> mixed_fell;   // per sample: 1 if that solve was finished by FP64 PCG
 
+    // region timing (rafem_regions_*): events at region boundaries within a step, the
+    // region of the interval each one opens, and the accumulated milliseconds per region
+    bool reg_on = false;
+    std::vector<hipEvent_t> reg_ev;
+    std::vector<int> reg_kind;
+    double reg_ms[3] = {0.0, 0.0, 0.0};
+    int64_t reg_steps = 0;
+
     // measurement of the SpMV kernels (rafem_profile_*)
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;   // 2 per launch, kProfCap launches
