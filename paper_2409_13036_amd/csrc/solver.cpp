@@ -184,16 +184,19 @@ hipGraphExec_t chunk_graph(rafem_mesh m, int kind, const void* k0, const void* k
     return exec;
 }
 
-// Enqueue at least k iterations; returns how many (graphs round up to whole chunks).
+// Enqueue k iterations: whole chunks as replays of the captured graph (one host call per
+// kGraphLen iterations), the rest as stream launches.  Both advance the same device
+// iteration counter, so the mix runs exactly the iterations of stream launches alone.
 template <typename IT>
 int enqueue(int k, const IT& iter, hipGraphExec_t graph, int* itb, ChunkTimer* t, hipStream_t s) {
+    int done = 0;
     if (graph) {
-        const int reps = (k + kGraphLen - 1) / kGraphLen;
-        for (int r = 0; r < reps; ++r) RAFEM_HIP(hipGraphLaunch(graph, s));
-        return reps * kGraphLen;
+        for (; done + kGraphLen <= k; done += kGraphLen) RAFEM_HIP(hipGraphLaunch(graph, s));
+        if (done == k) return k;
     }
-    for (int j = 0; j < k; ++j) iter(j, s, t);
-    launch_advance(itb, k, s);
+    const int rest = k - done;
+    for (int j = 0; j < rest; ++j) iter(j, s, t);
+    launch_advance(itb, rest, s);
     return k;
 }
 
