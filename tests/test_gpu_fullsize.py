@@ -144,3 +144,66 @@ def test_ensemble_step_matches_oracle_for_extreme_samples(torch_cuda):
         eT, eV = rel_err(Tg, T1), rel_err(Vg, V1)
         say(f"sample {q} (n={p.n}): T {eT:.2e} V {eV:.2e}")
         assert eT <= 1e-8 and eV <= 1e-8
+
+
+def _incident_model(p, rows):
+    """The oracle's model of the elements touching the given rows only: its rows of the
+    monolithic J and R are exactly those rows of the full problem's."""
+    import dataclasses
+    mark = np.zeros(p.n_nodes, dtype=bool)
+    mark[rows] = True
+    es = np.nonzero(mark[p.conn].any(axis=1))[0]
+    sub = dataclasses.replace(p, conn=np.ascontiguousarray(p.conn[es]), k_e=p.k_e[es],
+                              perf_e=p.perf_e[es], sigma0_e=p.sigma0_e[es])
+    return Model(sub)
+
+
+def test_hex101_monolithic_solve_and_newton_step_satisfy_sampled_equations(torch_cuda):
+    """101^3 hex in the bench's configuration: the GMRES(20) update of the Newton system at
+    the state after one staggered step (dt = 2 s), and a Newton predictor-corrector step."""
+    from oracle import monolithic as mono
+    from paper_2409_13036_amd import _lib as R
+    from paper_2409_13036_amd.sim import DeviceProblem
+    from gpu_helpers import to_dev
+    p = ri.config1(steps=1)
+    dp = DeviceProblem(p)
+    dp.step(TOL)
+    T1, V1 = to_host(dp.T), to_host(dp.V)
+    T0 = p.initial_T()
+    dt = 2.0
+    dp.phys.dt = dt
+    delta, info, _ = R.mono_solve(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, to_dev(T0),
+                                  dp.T, dp.V, m=20, tol=1e-10)
+    _, Rg = R.mono_jacobian(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, to_dev(T0), dp.T,
+                            dp.V)
+    delta, Rg = to_host(delta), to_host(Rg)
+    say(f"GMRES(20) at 101^3: {info['iters']} steps, {info['cycles']} cycles, relres_true "
+        f"{info['relres_true']:.2e}")
+    assert info["status"] == 0 and info["relres_true"] <= 1e-10
+    free = np.setdiff1d(np.arange(p.n_nodes), p.dir_ids)
+    rows = np.sort(np.random.default_rng(11).choice(free, 2000, replace=False))
+    ms = _incident_model(p, rows)
+    Rr = mono.residual(ms, T0, dt, T1, V1)
+    Js = mono.interleaved_matrix(ms, mono.jacobian_blocks(ms, T0, dt, T1, V1))
+    idx = np.concatenate([2 * rows, 2 * rows + 1])
+    scaleR = np.abs(Rr[idx]).max()
+    assert np.abs(Rg[idx] - Rr[idx]).max() <= 1e-12 * scaleR
+    res = (Js @ delta + Rr)[idx]
+    absrow = (abs(Js) @ np.abs(delta) + np.abs(Rr))[idx]
+    bound = 1.01e-10 * np.linalg.norm(Rg) + 1e-13 * absrow
+    say(f"sampled |J delta + R| max {np.abs(res).max():.2e} (bound {1e-10 * np.linalg.norm(Rg):.2e})")
+    assert np.all(np.abs(res) <= bound)
+    assert np.all(delta[2 * p.dir_ids] == 0) and np.all(delta[2 * p.dir_ids + 1] == 0)
+    # a Newton predictor-corrector step from the initial state: its result satisfies the
+    # implicit coupled equations up to the last Newton update (||delta_T|| <= 1e-9 ||T||)
+    dp.reset()
+    st = dp.step_mono(dt, corr_tol=1e-9, m=20)
+    T2, V2 = to_host(dp.T), to_host(dp.V)
+    dp.close()
+    say(f"Newton step at 101^3: {st}")
+    assert st["accepted"] == 1
+    R2 = mono.residual(ms, T0, dt, T2, V2)[idx]
+    M2 = mono.interleaved_matrix(ms, mono.jacobian_blocks(ms, T0, dt, T2, V2))
+    scale = (abs(M2) @ np.abs(np.ravel(np.column_stack([T2, V2]))))[idx] + 1.0
+    say(f"sampled implicit residual / row scale max {np.abs(R2 / scale).max():.2e}")
+    assert np.all(np.abs(R2) <= 1e-7 * scale)
