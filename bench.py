@@ -459,15 +459,16 @@ def pc_leg(dp, args) -> dict:
     return out
 
 
-def arnoldi_bytes(n: int, nnz: int, m: int) -> float:
+def arnoldi_bytes(n: int, nnz: int, m: int, fp32: bool = False) -> float:
     """Algorithmic HBM bytes of one Arnoldi step of GMRES(m), averaged over a cycle: the block
-    SpMV (per node pair 4 FP64 values + an int32 column, row pointers, x and y of 16 B per
-    node) and the three CGS2 passes over the k = j + 1 basis vectors (dots: k + 1 vectors;
-    update with the second dots: k + 2; normalisation with M^-1: k + 5 vector-sized
-    streams), k averaged over j = 0..m-1."""
-    spmv = 36.0 * nnz + 4.0 * (n + 1) + 32.0 * n
+    SpMV (per node pair 4 values + an int32 column, row pointers, x and y per node) and the
+    three CGS2 passes over the k = j + 1 basis vectors (dots: k + 1 vectors; update with the
+    second dots: k + 2; normalisation with M^-1: k + 5 vector-sized streams), k averaged
+    over j = 0..m-1.  Values and vectors are FP32 in the mixed Arnoldi process."""
+    vb = 4.0 if fp32 else 8.0
+    spmv = (4 * vb + 4.0) * nnz + 4.0 * (n + 1) + 4 * vb * n
     k_mean = (m + 1) / 2.0
-    return spmv + (3.0 * k_mean + 8.0) * 16.0 * n
+    return spmv + (3.0 * k_mean + 8.0) * 2 * vb * n
 
 
 def mono_leg(dp, args) -> dict:
@@ -489,58 +490,68 @@ def mono_leg(dp, args) -> dict:
     dp.phys.dt = args.pc_dt0
     sweep = []
     hist_len = 20000
-    # warm-up (a short solve that allocates the workspace for the largest m)
-    R.mono_solve(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, T0, T1, V1, m=max(args.mono_m),
-                 tol=1e-10, max_iters=50, check=False)
-    for mm in args.mono_m:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, info, hist = R.mono_solve(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, T0, T1, V1,
-                                     m=mm, tol=1e-10, hist_len=hist_len, check=False)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        h = hist.cpu().numpy()[:min(info["iters"], hist_len)]
-        ends = [min(c * mm, len(h)) - 1 for c in range(1, info["cycles"] + 1)]
-        starts = [1.0] + [h[e] for e in ends[:-1]]
-        stagn = sum(1 for s0, e in zip(starts, ends) if e >= 0 and h[e] > 0.5 * s0)
-        per_step = arnoldi_bytes(N, nnz, mm)
-        row = {"m": mm, "status": info["status"], "iters": info["iters"], "cycles": info["cycles"],
-               "seconds": el, "relres_true": info["relres_true"],
-               "us_per_arnoldi_step": el / max(1, info["iters"]) * 1e6,
-               "arnoldi_GBs": per_step * info["iters"] / el / 1e9,
-               "stagnating_cycles": stagn}
-        sweep.append(row)
-        print(f"[bench] GMRES({mm}): {info['iters']} iterations, {info['cycles']} cycles, "
-              f"{el:.3f} s, {row['us_per_arnoldi_step']:.0f} us/step, "
-              f"{row['arnoldi_GBs']:.0f} GB/s, stagnating cycles {stagn}",
-              file=sys.stderr, flush=True)
-    ok = [r for r in sweep if r["status"] == 0]
+    # warm-up (short solves that allocate the workspace for the largest m, both precisions)
+    for precision in ("fp64", "mixed"):
+        R.mono_solve(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, T0, T1, V1,
+                     m=max(args.mono_m), tol=1e-10, max_iters=50, precision=precision,
+                     check=False)
+    for precision in ("fp64", "mixed"):
+        for mm in args.mono_m:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info, hist = R.mono_solve(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, T0, T1,
+                                         V1, m=mm, tol=1e-10, precision=precision,
+                                         hist_len=hist_len, check=False)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            h = hist.cpu().numpy()[:min(info["iters"], hist_len)]
+            ends = [min(c * mm, len(h)) - 1 for c in range(1, info["cycles"] + 1)]
+            starts = [1.0] + [h[e] for e in ends[:-1]]
+            stagn = sum(1 for s0, e in zip(starts, ends) if e >= 0 and h[e] > 0.5 * s0)
+            per_step = arnoldi_bytes(N, nnz, mm, precision == "mixed")
+            row = {"precision": precision, "m": mm, "status": info["status"],
+                   "iters": info["iters"], "cycles": info["cycles"], "seconds": el,
+                   "relres_true": info["relres_true"],
+                   "us_per_arnoldi_step": el / max(1, info["iters"]) * 1e6,
+                   "arnoldi_GBs": per_step * info["iters"] / el / 1e9,
+                   "stagnating_cycles": stagn}
+            sweep.append(row)
+            print(f"[bench] GMRES({mm}) {precision}: {info['iters']} iterations, "
+                  f"{info['cycles']} cycles, {el:.3f} s, {row['us_per_arnoldi_step']:.0f} us/step, "
+                  f"{row['arnoldi_GBs']:.0f} GB/s, stagnating cycles {stagn}",
+                  file=sys.stderr, flush=True)
+    ok = [r for r in sweep if r["status"] == 0 and r["relres_true"] <= 1e-10]
     best = min(ok, key=lambda r: r["seconds"]) if ok else None
     for r in sweep:
-        r["slowdown_vs_best"] = r["seconds"] / best["seconds"] if best else None
+        same = [q for q in ok if q["precision"] == r["precision"]]
+        r["slowdown_vs_best_of_precision"] = (r["seconds"] / min(q["seconds"] for q in same)
+                                              if same else None)
     dp.phys.dt = dt_save
     out = {"workload": f"monolithic (T, V) Newton-GMRES corrector, {N}-node hex mesh, "
                        f"2N = {2 * N} unknowns, {4 * nnz} nonzeros",
            "unknowns": 2 * N, "nonzeros": 4 * nnz, "gmres_tol": 1e-10, "m_sweep": sweep,
-           "best_m": best["m"] if best else None}
+           "best": {"m": best["m"], "precision": best["precision"]} if best else None}
     if best:
         r = best
         out["roofline"] = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                            "achieved": r["arnoldi_GBs"], "frac": r["arnoldi_GBs"] / HBM_PEAK_GBS,
-                           "bytes_per_arnoldi_step": arnoldi_bytes(N, nnz, r["m"]),
-                           "note": "whole Arnoldi steps of the best m (block SpMV + CGS2), "
-                                   "cycle ends and restarts included in the time"}
+                           "bytes_per_arnoldi_step": arnoldi_bytes(N, nnz, r["m"],
+                                                                   r["precision"] == "mixed"),
+                           "note": "whole Arnoldi steps of the best (m, precision) (block SpMV "
+                                   "+ CGS2), cycle ends and restarts included in the time"}
+        gp = r["precision"]
         dp.reset()
-        dp.step_mono(args.pc_dt0, corr_tol=args.pc_eps, m=r["m"])  # warm-up
+        dp.step_mono(args.pc_dt0, corr_tol=args.pc_eps, m=r["m"], gmres_precision=gp)  # warm-up
         dp.reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rec = dp.simulate_pc(args.pc_t, args.pc_dt0, corr_tol=args.pc_eps, max_iters=50,
-                             corrector="newton", m=r["m"], gmres_tol=1e-10)
+                             corrector="newton", m=r["m"], gmres_tol=1e-10, gmres_precision=gp)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         its = [x["iters"] for x in rec]
-        reg = regions_pass(dp, lambda: dp.step_mono(args.pc_dt0, corr_tol=args.pc_eps, m=r["m"]), 1)
+        reg = regions_pass(dp, lambda: dp.step_mono(args.pc_dt0, corr_tol=args.pc_eps, m=r["m"],
+                                                    gmres_precision=gp), 1)
         out["predictor_corrector"] = {
             "regions_ms_one_step": reg,
             "t_total_s": args.pc_t, "dt0_s": args.pc_dt0, "eps": args.pc_eps,

@@ -398,6 +398,10 @@ typedef struct {
     int32_t m;           /* Krylov vectors per restart cycle, 1..RAFEM_GMRES_MAX_M (<= 0: 30) */
     int32_t max_iters;   /* Arnoldi steps over all cycles (<= 0: 20000) */
     double  tol;         /* stop when ||b - J x||_2 <= tol ||b||_2 (<= 0: 1e-10) */
+    int32_t precision;   /* RAFEM_FP64, or RAFEM_MIXED: the Arnoldi process on FP32 copies of
+                            J, the basis and the block inverses (FP64 sums), while every
+                            restart forms the true residual b - J x and the update in FP64 */
+    int32_t pad;
 } rafem_gmres_opts;
 
 typedef struct {

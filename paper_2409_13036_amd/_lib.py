@@ -83,7 +83,8 @@ GMRES_MAX_M = 200
 
 
 class GmresOpts(C.Structure):
-    _fields_ = [("m", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double)]
+    _fields_ = [("m", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double),
+                ("precision", C.c_int32), ("pad", C.c_int32)]
 
 
 class GmresInfo(C.Structure):
@@ -269,9 +270,12 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
+def _precision(precision) -> int:
+    return {"fp64": FP64, "mixed": MIXED}.get(precision, precision)
+
+
 def make_opts(tol=1e-10, maxit=0, precision="fp64", inner_tol=0.0, max_outer=0, poll_every=0):
-    prec = {"fp64": FP64, "mixed": MIXED}.get(precision, precision)
-    return SolveOpts(tol, maxit, prec, inner_tol, max_outer, poll_every)
+    return SolveOpts(tol, maxit, _precision(precision), inner_tol, max_outer, poll_every)
 
 
 class Mesh:
@@ -550,9 +554,10 @@ def mono_jacobian(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, T_n, T, V, *, s
 
 
 def mono_solve(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, T_n, T, V, *, m=30, max_iters=0,
-               tol=1e-10, hist_len=0, stream=None, check=True):
-    """rafem_mono_solve: assemble J, R at (T, V) and solve J delta = -R by GMRES(m).  Returns
-    (delta [2 n] interleaved, info dict, residual history [hist_len] or None)."""
+               tol=1e-10, precision="fp64", hist_len=0, stream=None, check=True):
+    """rafem_mono_solve: assemble J, R at (T, V) and solve J delta = -R by GMRES(m)
+    (precision "mixed": FP32 Arnoldi process inside FP64 restarts).  Returns (delta [2 n]
+    interleaved, info dict, residual history [hist_len] or None)."""
     torch = _torch()
     n = mesh.n_nodes
     k_e, perf_e, sigma0_e = _mono_fields(mesh, k_e, perf_e, sigma0_e)
@@ -561,7 +566,7 @@ def mono_solve(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, T_n, T, V, *, m=30
     V = _dev(V, torch.float64, n, "V")
     delta = torch.empty(2 * n, dtype=torch.float64, device=T.device)
     hist = torch.zeros(hist_len, dtype=torch.float64, device=T.device) if hist_len else None
-    opts = GmresOpts(int(m), int(max_iters), float(tol))
+    opts = GmresOpts(int(m), int(max_iters), float(tol), _precision(precision), 0)
     info = GmresInfo()
     st = _lib.rafem_mono_solve(mesh.handle, C.byref(phys), _ptr(k_e), _ptr(perf_e),
                                _ptr(sigma0_e), _ptr(T_n), _ptr(T), _ptr(V), C.byref(opts),
@@ -574,7 +579,7 @@ def mono_solve(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, T_n, T, V, *, m=30
 
 def step_mono(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T_prev, dt_prev, T, V,
               *, corr_tol=1e-10, max_iters=50, m=30, gmres_max_iters=0, gmres_tol=1e-10,
-              stream=None, check=True):
+              gmres_precision="fp64", stream=None, check=True):
     """rafem_step_mono: one predictor-corrector step of size phys.dt with the monolithic
     Newton-GMRES corrector; T and V advance in place when accepted.  Returns the info dict."""
     torch = _torch()
@@ -585,7 +590,7 @@ def step_mono(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T_pre
     T_prev = _dev(T_prev, torch.float64, n, "T_prev", allow_none=True)
     T = _dev(T, torch.float64, n, "T")
     V = _dev(V, torch.float64, n, "V")
-    opts = GmresOpts(int(m), int(gmres_max_iters), float(gmres_tol))
+    opts = GmresOpts(int(m), int(gmres_max_iters), float(gmres_tol), _precision(gmres_precision), 0)
     copts = CorrectorOpts(float(corr_tol), int(max_iters))
     info = MonoInfo()
     st = _lib.rafem_step_mono(mesh.handle, C.byref(phys), _ptr(k_e), _ptr(perf_e), _ptr(sigma0_e),

@@ -1012,7 +1012,7 @@ rafem_status rafem_mono_solve(rafem_mesh m, const rafem_phys* phys, const double
         require(hist_len >= 0 && (hist_len == 0 || hist_d), "bad residual history buffer");
         const GmresOpts o = resolve_gmres(opts);
         hipStream_t s = (hipStream_t)stream;
-        mono_ensure(m, o.m);
+        mono_ensure(m, o.m, o.precision == RAFEM_MIXED);
         mono_assemble(m, phys, k_e_d, perf_e_d, sigma0_e_d, T_n_d, T_d, V_d, s);
         rafem_gmres_info local{};
         const rafem_status st = gmres_solve(m, m->mono_rhs, delta_d, o, hist_len ? hist_d : nullptr,
@@ -1041,7 +1041,7 @@ rafem_status rafem_step_mono(rafem_mesh m, const rafem_phys* phys, const double*
         rafem_mono_info local{};
         rafem_mono_info& mi = info ? *info : local;
         std::memset(&mi, 0, sizeof(mi));
-        mono_ensure(m, o.m);
+        mono_ensure(m, o.m, o.precision == RAFEM_MIXED);
         const size_t bytes = (size_t)m->n * sizeof(double);
         region_begin(m);
         region_mark(m, kRegCheck, s);

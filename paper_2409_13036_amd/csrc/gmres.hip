@@ -7,7 +7,9 @@
 // layout holds the four values (TT, TV, VT, VV) of its node pair as one double4, so the
 // column offsets (shared lists, int16 deltas or absolute columns) are those of the scalar
 // matrices and a wavefront reads 2 KB of values per entry.  Vectors interleave the two
-// unknowns of a node (double2: x = T, y = V).
+// unknowns of a node (double2: x = T, y = V).  The mixed variant runs the Arnoldi process
+// on float4 / float2 copies (sums in double) and keeps the restarts' true residual and the
+// update in FP64.
 //
 // GMRES.  Arnoldi with classical Gram-Schmidt applied twice (CGS2), which needs three
 // passes over the basis per step -- dots, update with the second dots, and the corrected
@@ -155,6 +157,22 @@ __global__ __launch_bounds__(WG) void k_block_inv(int n, const Layout L,
     binv[i] = make_double4(d.w / det, -d.y / det, -d.z / det, d.x / det);
 }
 
+// Vector element types: the FP64 path keeps double2 (a node's T and V) and double4 (a
+// 2x2 block); the mixed path's Arnoldi process keeps float2 / float4.  Arithmetic on basis
+// values is done in double after loading.
+__device__ __forceinline__ double2 ld2(const double2 v) { return v; }
+__device__ __forceinline__ double2 ld2(const float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ void st2(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ double4 ld4(const double4 v) { return v; }
+// The value a store of v into an X2 element keeps (rounding to float for the FP32 basis).
+template <typename X2>
+__device__ __forceinline__ double2 kept(double2 v) {
+    if constexpr (sizeof(X2) == sizeof(float2)) return make_double2((float)v.x, (float)v.y);
+    else return v;
+}
+__device__ __forceinline__ double4 ld4(const float4 v) { return make_double4(v.x, v.y, v.z, v.w); }
+
 __device__ __forceinline__ double2 bj_apply(const double4 B, const double2 v) {
     return make_double2(B.x * v.x + B.y * v.y, B.z * v.x + B.w * v.y);
 }
@@ -162,20 +180,37 @@ __device__ __forceinline__ double2 bj_apply(const double4 B, const double2 v) {
 __device__ __forceinline__ bool cycle_over(const GmState* st) { return st->cyc_done || st->solved; }
 
 // ---------------------------------------------------------------------------
-// Block SpMV y = A x on the SELL slabs (slabs_per_block slabs per workgroup, two per
-// wavefront).  Skipped when the solve is over, or (arnoldi) when the cycle is.
+// Block SpMV y = A x on the SELL slabs (kBsellSlabs slabs per workgroup, two per
+// wavefront), in the precision of the values (V4: double4 or float4; X2 the matching
+// vector element).  Skipped when the solve is over, or (arnoldi) when the cycle is.
 // ---------------------------------------------------------------------------
 constexpr int kBlockUnroll = 6;
 constexpr int kBsellSlabs = 2 * NWAVES;
 
-template <int MODE>  // 0: shared offsets, 1: int16 deltas, 2: absolute columns
-__device__ __forceinline__ double2 bsell_row(const BsellArgs& a, int base, int width, int so,
-                                             int r, int lane) {
-    double2 acc = make_double2(0.0, 0.0);
+template <typename V4, typename X2>
+struct BsellT {
+    int n, nslabs;
+    const int32_t* sptr;
+    const int32_t* scol;
+    const int16_t* sdel;
+    const int32_t* sofs;
+    const int32_t* soff;
+    const V4* vals;
+    const X2* x;
+    X2* y;
+    const GmState* st;
+    int arnoldi;
+};
+
+template <int MODE, typename V4, typename X2>  // MODE 0: shared offsets, 1: int16 deltas, 2: columns
+__device__ __forceinline__ X2 bsell_row(const BsellT<V4, X2>& a, int base, int width, int so,
+                                        int r, int lane) {
+    using T = decltype(X2::x);
+    T ax = T(0), ay = T(0);
     const int rc = min(r, a.n - 1);
     for (int j = 0; j < width; j += kBlockUnroll) {
         int c[kBlockUnroll];
-        double4 v[kBlockUnroll];
+        V4 v[kBlockUnroll];
 #pragma unroll
         for (int u = 0; u < kBlockUnroll; ++u) {
             const bool in = j + u < width;
@@ -183,21 +218,26 @@ __device__ __forceinline__ double2 bsell_row(const BsellArgs& a, int base, int w
             if constexpr (MODE == 0) c[u] = in ? r + a.soff[so + j + u] : rc;
             else if constexpr (MODE == 1) c[u] = in ? rc + (int)a.sdel[k] : rc;
             else c[u] = in ? a.scol[k] : rc;
-            v[u] = in ? a.vals[k] : make_double4(0.0, 0.0, 0.0, 0.0);
+            if (in) v[u] = a.vals[k];
+            else v[u].x = v[u].y = v[u].z = v[u].w = T(0);
         }
-        double2 x[kBlockUnroll];
+        X2 x[kBlockUnroll];
 #pragma unroll
         for (int u = 0; u < kBlockUnroll; ++u) x[u] = a.x[c[u]];
 #pragma unroll
         for (int u = 0; u < kBlockUnroll; ++u) {
-            acc.x += v[u].x * x[u].x + v[u].y * x[u].y;
-            acc.y += v[u].z * x[u].x + v[u].w * x[u].y;
+            ax += v[u].x * x[u].x + v[u].y * x[u].y;
+            ay += v[u].z * x[u].x + v[u].w * x[u].y;
         }
     }
-    return acc;
+    X2 out;
+    out.x = ax;
+    out.y = ay;
+    return out;
 }
 
-__global__ __launch_bounds__(WG) void k_bsell(BsellArgs a) {
+template <typename V4, typename X2>
+__global__ __launch_bounds__(WG) void k_bsell(BsellT<V4, X2> a) {
     if (a.st && (a.st->solved || (a.arnoldi && a.st->cyc_done))) return;
     const int nblk = gridDim.x;
     const int blk = xcd_block(blockIdx.x, nblk);
@@ -209,7 +249,7 @@ __global__ __launch_bounds__(WG) void k_bsell(BsellArgs a) {
         const int width = (a.sptr[sl + 1] - base) / WAVE;
         const int so = a.sofs[sl];
         const int r = sl * WAVE + lane;
-        double2 y;
+        X2 y;
         if (so >= 0) y = bsell_row<0>(a, base, width, so, r, lane);
         else if (a.sdel) y = bsell_row<1>(a, base, width, so, r, lane);
         else y = bsell_row<2>(a, base, width, so, r, lane);
@@ -218,9 +258,18 @@ __global__ __launch_bounds__(WG) void k_bsell(BsellArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// GMRES vector kernels: one node (double2) per thread, partial sums per workgroup.
+// GMRES vector kernels: one node (two values) per thread, partial sums per workgroup.
 // ---------------------------------------------------------------------------
 constexpr int kChunk = 8;
+
+template <typename X2>
+struct GmV {
+    int n;
+    X2* V;
+    int64_t ldv;
+    double* part;
+    GmState* st;
+};
 
 // Per-block sums of the k values in lds[.][wave] -> part[i * nb + blk].
 __device__ __forceinline__ void store_rows(double (*lds)[NWAVES], int k, double* part, int nb,
@@ -240,20 +289,26 @@ __device__ __forceinline__ void wave_to_lds(double (*lds)[NWAVES], int i, double
     if (threadIdx.x % WAVE == 0) lds[i][threadIdx.x / WAVE] = v;
 }
 
+template <typename X2>
+__device__ __forceinline__ double2 basis(const GmV<X2>& a, int i, int node) {
+    return ld2(a.V[(int64_t)i * a.ldv + node]);
+}
+
 // part[i] = V_i . w (i < k)
-__global__ __launch_bounds__(WG) void k_gm_dots(GmVec a, int k, const double2* __restrict__ w) {
+template <typename X2>
+__global__ __launch_bounds__(WG) void k_gm_dots(GmV<X2> a, int k, const X2* __restrict__ w) {
     if (cycle_over(a.st)) return;
     __shared__ double lds[kGmMaxM + 2][NWAVES];
     const int nb = gridDim.x;
     const int blk = xcd_block(blockIdx.x, nb);
     const int i = blk * WG + threadIdx.x;
     const bool in = i < a.n;
-    const double2 wv = in ? w[i] : make_double2(0.0, 0.0);
+    const double2 wv = in ? ld2(w[i]) : make_double2(0.0, 0.0);
     for (int i0 = 0; i0 < k; i0 += kChunk) {
         double2 v[kChunk];
 #pragma unroll
         for (int u = 0; u < kChunk; ++u)
-            v[u] = (in && i0 + u < k) ? a.V[(int64_t)(i0 + u) * a.ldv + i] : make_double2(0.0, 0.0);
+            v[u] = (in && i0 + u < k) ? basis(a, i0 + u, i) : make_double2(0.0, 0.0);
 #pragma unroll
         for (int u = 0; u < kChunk; ++u)
             if (i0 + u < k) wave_to_lds(lds, i0 + u, v[u].x * wv.x + v[u].y * wv.y);
@@ -274,21 +329,21 @@ __global__ __launch_bounds__(WG) void k_gm_sum(const double* __restrict__ part, 
 
 // w <- w - sum_i h1[i] V_i;  part[i] = V_i . w (i < k), part[k] = w . w.  KC > 0 keeps the
 // basis values of the thread's node in registers between the two loops (k <= KC).
-template <int KC>
-__global__ __launch_bounds__(WG) void k_gm_orth(GmVec a, int k, const double* __restrict__ h1,
-                                                double2* __restrict__ w) {
+template <int KC, typename X2>
+__global__ __launch_bounds__(WG) void k_gm_orth(GmV<X2> a, int k, const double* __restrict__ h1,
+                                                X2* __restrict__ w) {
     if (cycle_over(a.st)) return;
     __shared__ double lds[kGmMaxM + 2][NWAVES];
     const int nb = gridDim.x;
     const int blk = xcd_block(blockIdx.x, nb);
     const int i = blk * WG + threadIdx.x;
     const bool in = i < a.n;
-    double2 wv = in ? w[i] : make_double2(0.0, 0.0);
+    double2 wv = in ? ld2(w[i]) : make_double2(0.0, 0.0);
     if constexpr (KC > 0) {
         double2 v[KC];
 #pragma unroll
         for (int u = 0; u < KC; ++u)
-            v[u] = (in && u < k) ? a.V[(int64_t)u * a.ldv + i] : make_double2(0.0, 0.0);
+            v[u] = (in && u < k) ? basis(a, u, i) : make_double2(0.0, 0.0);
 #pragma unroll
         for (int u = 0; u < KC; ++u) {
             if (u < k) {
@@ -297,6 +352,8 @@ __global__ __launch_bounds__(WG) void k_gm_orth(GmVec a, int k, const double* __
                 wv.y -= h * v[u].y;
             }
         }
+        wv = kept<X2>(wv);  // the dots below use the stored w'
+        if (in) st2(&w[i], wv);
 #pragma unroll
         for (int u = 0; u < KC; ++u)
             if (u < k) wave_to_lds(lds, u, v[u].x * wv.x + v[u].y * wv.y);
@@ -305,8 +362,7 @@ __global__ __launch_bounds__(WG) void k_gm_orth(GmVec a, int k, const double* __
             double2 v[kChunk];
 #pragma unroll
             for (int u = 0; u < kChunk; ++u)
-                v[u] = (in && i0 + u < k) ? a.V[(int64_t)(i0 + u) * a.ldv + i]
-                                          : make_double2(0.0, 0.0);
+                v[u] = (in && i0 + u < k) ? basis(a, i0 + u, i) : make_double2(0.0, 0.0);
 #pragma unroll
             for (int u = 0; u < kChunk; ++u) {
                 if (i0 + u < k) {
@@ -316,19 +372,19 @@ __global__ __launch_bounds__(WG) void k_gm_orth(GmVec a, int k, const double* __
                 }
             }
         }
+        wv = kept<X2>(wv);
+        if (in) st2(&w[i], wv);
         for (int i0 = 0; i0 < k; i0 += kChunk) {
             double2 v[kChunk];
 #pragma unroll
             for (int u = 0; u < kChunk; ++u)
-                v[u] = (in && i0 + u < k) ? a.V[(int64_t)(i0 + u) * a.ldv + i]
-                                          : make_double2(0.0, 0.0);
+                v[u] = (in && i0 + u < k) ? basis(a, i0 + u, i) : make_double2(0.0, 0.0);
 #pragma unroll
             for (int u = 0; u < kChunk; ++u)
                 if (i0 + u < k) wave_to_lds(lds, i0 + u, v[u].x * wv.x + v[u].y * wv.y);
         }
     }
     wave_to_lds(lds, k, wv.x * wv.x + wv.y * wv.y);
-    if (in) w[i] = wv;
     store_rows(lds, k + 1, a.part, nb, blk);
 }
 
@@ -340,23 +396,23 @@ __device__ __forceinline__ double next_norm(const double* __restrict__ h2, int k
     return d > 0.0 ? sqrt(d) : 0.0;
 }
 
-// v_k = (w' - sum_i h2[i] V_i) / h_{k,k-1};  z = M^-1 v_k.
-__global__ __launch_bounds__(WG) void k_gm_next(GmVec a, int k, const double* __restrict__ h2,
-                                                const double2* __restrict__ w,
-                                                const double4* __restrict__ binv,
-                                                double2* __restrict__ z) {
+// v_k = (w' - sum_i h2[i] V_i) / h_{k,k-1};  z = M^-1 v_k (M^-1 in the basis' precision).
+template <typename X2, typename B4>
+__global__ __launch_bounds__(WG) void k_gm_next(GmV<X2> a, int k, const double* __restrict__ h2,
+                                                const X2* __restrict__ w,
+                                                const B4* __restrict__ binv, X2* __restrict__ z) {
     if (cycle_over(a.st)) return;
     const double hn = next_norm(h2, k);
     if (hn == 0.0) return;  // exact breakdown: the cycle ends here
     const int nb = gridDim.x;
     const int i = xcd_block(blockIdx.x, nb) * WG + threadIdx.x;
     if (i >= a.n) return;
-    double2 wv = w[i];
+    double2 wv = ld2(w[i]);
     for (int i0 = 0; i0 < k; i0 += kChunk) {
         double2 v[kChunk];
 #pragma unroll
         for (int u = 0; u < kChunk; ++u)
-            v[u] = i0 + u < k ? a.V[(int64_t)(i0 + u) * a.ldv + i] : make_double2(0.0, 0.0);
+            v[u] = i0 + u < k ? basis(a, i0 + u, i) : make_double2(0.0, 0.0);
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
             if (i0 + u < k) {
@@ -366,9 +422,9 @@ __global__ __launch_bounds__(WG) void k_gm_next(GmVec a, int k, const double* __
             }
         }
     }
-    const double2 vk = make_double2(wv.x / hn, wv.y / hn);
-    a.V[(int64_t)k * a.ldv + i] = vk;
-    z[i] = bj_apply(binv[i], vk);
+    const double2 vk = kept<X2>(make_double2(wv.x / hn, wv.y / hn));
+    st2(&a.V[(int64_t)k * a.ldv + i], vk);
+    st2(&z[i], bj_apply(ld4(binv[i]), vk));
 }
 
 // Hessenberg column j = (h1 + h2, h_{j+1,j}), earlier rotations, a new rotation, the
@@ -421,8 +477,9 @@ __global__ void k_gm_solve_y(GmSmall sm, const GmState* st) {
     }
 }
 
-// delta += M^-1 (sum_{i<k} y_i V_i), k = the cycle's steps.
-__global__ __launch_bounds__(WG) void k_gm_xupdate(GmVec a, const double* __restrict__ y,
+// delta += M^-1 (sum_{i<k} y_i V_i), k = the cycle's steps (FP64 update and M^-1).
+template <typename X2>
+__global__ __launch_bounds__(WG) void k_gm_xupdate(GmV<X2> a, const double* __restrict__ y,
                                                    const double4* __restrict__ binv,
                                                    double2* __restrict__ delta) {
     if (a.st->solved) return;
@@ -435,7 +492,7 @@ __global__ __launch_bounds__(WG) void k_gm_xupdate(GmVec a, const double* __rest
         double2 v[kChunk];
 #pragma unroll
         for (int c = 0; c < kChunk; ++c)
-            v[c] = i0 + c < k ? a.V[(int64_t)(i0 + c) * a.ldv + i] : make_double2(0.0, 0.0);
+            v[c] = i0 + c < k ? basis(a, i0 + c, i) : make_double2(0.0, 0.0);
 #pragma unroll
         for (int c = 0; c < kChunk; ++c) {
             if (i0 + c < k) {
@@ -452,17 +509,18 @@ __global__ __launch_bounds__(WG) void k_gm_xupdate(GmVec a, const double* __rest
     delta[i] = x;
 }
 
-// r = b - w (w NULL: r = b); part[blk] = r . r
-__global__ __launch_bounds__(WG) void k_gm_resid(GmVec a, const double2* __restrict__ b,
+// r = b - w (w NULL: r = b); part[blk] = r . r  (FP64)
+__global__ __launch_bounds__(WG) void k_gm_resid(int n, double* __restrict__ part,
+                                                 const GmState* st, const double2* __restrict__ b,
                                                  const double2* __restrict__ w,
                                                  double2* __restrict__ r) {
-    if (a.st->solved) return;
+    if (st->solved) return;
     __shared__ double lds[1][NWAVES];
     const int nb = gridDim.x;
     const int blk = xcd_block(blockIdx.x, nb);
     const int i = blk * WG + threadIdx.x;
     double2 rv = make_double2(0.0, 0.0);
-    if (i < a.n) {
+    if (i < n) {
         rv = b[i];
         if (w) {
             const double2 wv = w[i];
@@ -472,7 +530,7 @@ __global__ __launch_bounds__(WG) void k_gm_resid(GmVec a, const double2* __restr
         r[i] = rv;
     }
     wave_to_lds(lds, 0, rv.x * rv.x + rv.y * rv.y);
-    store_rows(lds, 1, a.part, nb, blk);
+    store_rows(lds, 1, part, nb, blk);
 }
 
 // Restart decision from the true residual norm (first: it is also ||b||).
@@ -504,18 +562,18 @@ __global__ __launch_bounds__(WG) void k_gm_restart(const double* __restrict__ pa
     }
 }
 
-// v_0 = r / beta;  z = M^-1 v_0.
-__global__ __launch_bounds__(WG) void k_gm_v0(GmVec a, const double2* __restrict__ r,
-                                              const double4* __restrict__ binv,
-                                              double2* __restrict__ z) {
+// v_0 = r / beta (stored in the basis' precision);  z = M^-1 v_0.
+template <typename X2, typename B4>
+__global__ __launch_bounds__(WG) void k_gm_v0(GmV<X2> a, const double2* __restrict__ r,
+                                              const B4* __restrict__ binv, X2* __restrict__ z) {
     if (a.st->solved) return;
     const int i = xcd_block(blockIdx.x, gridDim.x) * WG + threadIdx.x;
     if (i >= a.n) return;
     const double beta = a.st->beta;
     const double2 rv = r[i];
-    const double2 v = make_double2(rv.x / beta, rv.y / beta);
-    a.V[i] = v;
-    z[i] = bj_apply(binv[i], v);
+    const double2 v = kept<X2>(make_double2(rv.x / beta, rv.y / beta));
+    st2(&a.V[i], v);
+    st2(&z[i], bj_apply(ld4(binv[i]), v));
 }
 
 __global__ void k_gm_init(GmState* st, double tol, int maxit, int m) {
@@ -593,20 +651,42 @@ void launch_block_inv(int n, const Layout& L, const double* vals4, double* binv,
                        reinterpret_cast<const double4*>(vals4), reinterpret_cast<double4*>(binv));
 }
 
+template <typename V4, typename X2>
+BsellT<V4, X2> bsell_args(const BsellArgs& a) {
+    return BsellT<V4, X2>{a.n, a.nslabs, a.sptr, a.scol, a.sdel, a.sofs, a.soff,
+                          static_cast<const V4*>(a.vals), static_cast<const X2*>(a.x),
+                          static_cast<X2*>(a.y), a.st, a.arnoldi};
+}
+
 void launch_bsell(const BsellArgs& a, hipStream_t s) {
     const int blocks = (a.nslabs + kBsellSlabs - 1) / kBsellSlabs;
-    hipLaunchKernelGGL(k_bsell, dim3(blocks), dim3(WG), 0, s, a);
+    if (a.fp32)
+        hipLaunchKernelGGL((k_bsell<float4, float2>), dim3(blocks), dim3(WG), 0, s,
+                           bsell_args<float4, float2>(a));
+    else
+        hipLaunchKernelGGL((k_bsell<double4, double2>), dim3(blocks), dim3(WG), 0, s,
+                           bsell_args<double4, double2>(a));
 }
 
 int gm_blocks(int n) { return grid1(n); }
+
+template <typename X2>
+GmV<X2> gmv(const GmVec& a) {
+    return GmV<X2>{a.n, static_cast<X2*>(a.V), a.ldv, a.part, a.st};
+}
 
 void launch_gm_init(GmState* st, double tol, int maxit, int m, hipStream_t s) {
     hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(64), 0, s, st, tol, maxit, m);
 }
 
-void launch_gm_dots(const GmVec& a, int k, const double* w, hipStream_t s) {
-    hipLaunchKernelGGL(k_gm_dots, dim3(grid1(a.n)), dim3(WG), 0, s, a, k,
-                       reinterpret_cast<const double2*>(w));
+void launch_gm_dots(const GmVec& a, int k, const void* w, hipStream_t s) {
+    const dim3 g(grid1(a.n)), b(WG);
+    if (a.fp32)
+        hipLaunchKernelGGL(k_gm_dots<float2>, g, b, 0, s, gmv<float2>(a), k,
+                           static_cast<const float2*>(w));
+    else
+        hipLaunchKernelGGL(k_gm_dots<double2>, g, b, 0, s, gmv<double2>(a), k,
+                           static_cast<const double2*>(w));
 }
 
 void launch_gm_sum(const double* part, int nb, int rows, double* out, const GmState* st,
@@ -614,20 +694,33 @@ void launch_gm_sum(const double* part, int nb, int rows, double* out, const GmSt
     hipLaunchKernelGGL(k_gm_sum, dim3(rows), dim3(WG), 0, s, part, nb, out, st);
 }
 
-void launch_gm_orth(const GmVec& a, int k, const double* h1, double* w, hipStream_t s) {
-    double2* w2 = reinterpret_cast<double2*>(w);
+template <typename X2>
+void orth_kc(const GmVec& a, int k, const double* h1, void* w, hipStream_t s) {
     const dim3 g(grid1(a.n)), b(WG);
-    if (k <= 8) hipLaunchKernelGGL(k_gm_orth<8>, g, b, 0, s, a, k, h1, w2);
-    else if (k <= 16) hipLaunchKernelGGL(k_gm_orth<16>, g, b, 0, s, a, k, h1, w2);
-    else if (k <= 32) hipLaunchKernelGGL(k_gm_orth<32>, g, b, 0, s, a, k, h1, w2);
-    else hipLaunchKernelGGL(k_gm_orth<0>, g, b, 0, s, a, k, h1, w2);
+    const GmV<X2> v = gmv<X2>(a);
+    X2* w2 = static_cast<X2*>(w);
+    if (k <= 8) hipLaunchKernelGGL((k_gm_orth<8, X2>), g, b, 0, s, v, k, h1, w2);
+    else if (k <= 16) hipLaunchKernelGGL((k_gm_orth<16, X2>), g, b, 0, s, v, k, h1, w2);
+    else if (k <= 32) hipLaunchKernelGGL((k_gm_orth<32, X2>), g, b, 0, s, v, k, h1, w2);
+    else hipLaunchKernelGGL((k_gm_orth<0, X2>), g, b, 0, s, v, k, h1, w2);
 }
 
-void launch_gm_next(const GmVec& a, int k, const double* h2, const double* w, const double* binv,
-                    double* z, hipStream_t s) {
-    hipLaunchKernelGGL(k_gm_next, dim3(grid1(a.n)), dim3(WG), 0, s, a, k, h2,
-                       reinterpret_cast<const double2*>(w), reinterpret_cast<const double4*>(binv),
-                       reinterpret_cast<double2*>(z));
+void launch_gm_orth(const GmVec& a, int k, const double* h1, void* w, hipStream_t s) {
+    if (a.fp32) orth_kc<float2>(a, k, h1, w, s);
+    else orth_kc<double2>(a, k, h1, w, s);
+}
+
+void launch_gm_next(const GmVec& a, int k, const double* h2, const void* w, const void* binv,
+                    void* z, hipStream_t s) {
+    const dim3 g(grid1(a.n)), b(WG);
+    if (a.fp32)
+        hipLaunchKernelGGL((k_gm_next<float2, float4>), g, b, 0, s, gmv<float2>(a), k, h2,
+                           static_cast<const float2*>(w), static_cast<const float4*>(binv),
+                           static_cast<float2*>(z));
+    else
+        hipLaunchKernelGGL((k_gm_next<double2, double4>), g, b, 0, s, gmv<double2>(a), k, h2,
+                           static_cast<const double2*>(w), static_cast<const double4*>(binv),
+                           static_cast<double2*>(z));
 }
 
 void launch_gm_givens(const GmSmall& sm, int j, const double* h1, const double* h2, GmState* st,
@@ -641,14 +734,17 @@ void launch_gm_solve_y(const GmSmall& sm, const GmState* st, hipStream_t s) {
 
 void launch_gm_xupdate(const GmVec& a, const double* y, const double* binv, double* delta,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_gm_xupdate, dim3(grid1(a.n)), dim3(WG), 0, s, a, y,
-                       reinterpret_cast<const double4*>(binv), reinterpret_cast<double2*>(delta));
+    const dim3 g(grid1(a.n)), b(WG);
+    const double4* B = reinterpret_cast<const double4*>(binv);
+    double2* d = reinterpret_cast<double2*>(delta);
+    if (a.fp32) hipLaunchKernelGGL(k_gm_xupdate<float2>, g, b, 0, s, gmv<float2>(a), y, B, d);
+    else hipLaunchKernelGGL(k_gm_xupdate<double2>, g, b, 0, s, gmv<double2>(a), y, B, d);
 }
 
 void launch_gm_resid(const GmVec& a, const double* b, const double* w, double* r, hipStream_t s) {
-    hipLaunchKernelGGL(k_gm_resid, dim3(grid1(a.n)), dim3(WG), 0, s, a,
-                       reinterpret_cast<const double2*>(b), reinterpret_cast<const double2*>(w),
-                       reinterpret_cast<double2*>(r));
+    hipLaunchKernelGGL(k_gm_resid, dim3(grid1(a.n)), dim3(WG), 0, s, a.n, a.part,
+                       (const GmState*)a.st, reinterpret_cast<const double2*>(b),
+                       reinterpret_cast<const double2*>(w), reinterpret_cast<double2*>(r));
 }
 
 void launch_gm_restart(const double* part, int nb, const GmSmall& sm, GmState* st, int first,
@@ -656,10 +752,15 @@ void launch_gm_restart(const double* part, int nb, const GmSmall& sm, GmState* s
     hipLaunchKernelGGL(k_gm_restart, dim3(1), dim3(WG), 0, s, part, nb, sm, st, first);
 }
 
-void launch_gm_v0(const GmVec& a, const double* r, const double* binv, double* z, hipStream_t s) {
-    hipLaunchKernelGGL(k_gm_v0, dim3(grid1(a.n)), dim3(WG), 0, s, a,
-                       reinterpret_cast<const double2*>(r), reinterpret_cast<const double4*>(binv),
-                       reinterpret_cast<double2*>(z));
+void launch_gm_v0(const GmVec& a, const double* r, const void* binv, void* z, hipStream_t s) {
+    const dim3 g(grid1(a.n)), b(WG);
+    const double2* r2 = reinterpret_cast<const double2*>(r);
+    if (a.fp32)
+        hipLaunchKernelGGL((k_gm_v0<float2, float4>), g, b, 0, s, gmv<float2>(a), r2,
+                           static_cast<const float4*>(binv), static_cast<float2*>(z));
+    else
+        hipLaunchKernelGGL((k_gm_v0<double2, double4>), g, b, 0, s, gmv<double2>(a), r2,
+                           static_cast<const double4*>(binv), static_cast<double2*>(z));
 }
 
 void launch_newton_apply(int n, const double* delta, double* T, double* V, double* part,

@@ -272,14 +272,15 @@ struct GmState {
     int32_t iters, cycles, jdone, cyc_done, solved, status, maxit, m;
 };
 
-// The basis (vector i of the interleaved (T, V) pairs at V + i ldv), the per-block
-// partial sums [rows][nb] and the state.
+// The basis (vector i of the interleaved (T, V) pairs at V + i ldv; double2 or, fp32,
+// float2 elements), the per-block partial sums [rows][nb] and the state.
 struct GmVec {
     int n;
-    double2* V;
+    void* V;
     int64_t ldv;
     double* part;
     GmState* st;
+    int fp32 = 0;
 };
 
 // Hessenberg matrix (column-major, leading dimension ldh), rotations, rotated right-hand
@@ -299,11 +300,12 @@ struct BsellArgs {
     const int16_t* sdel = nullptr;
     const int32_t* sofs = nullptr;
     const int32_t* soff = nullptr;
-    const double4* vals = nullptr;  // (TT, TV, VT, VV) per slot
-    const double2* x = nullptr;
-    double2* y = nullptr;
+    const void* vals = nullptr;     // (TT, TV, VT, VV) per slot: double4, or float4 if fp32
+    const void* x = nullptr;        // double2 / float2 per node
+    void* y = nullptr;
     const GmState* st = nullptr;    // skip when the solve (or, arnoldi: the cycle) is over
     int arnoldi = 0;
+    int fp32 = 0;
 };
 
 // One colour of the Jacobian / residual assembly.  Value c (0..3 = TT, TV, VT, VV) of
@@ -334,12 +336,14 @@ void launch_block_inv(int n, const Layout& L, const double* vals4, double* binv,
 void launch_bsell(const BsellArgs& a, hipStream_t s);
 int gm_blocks(int n);  // workgroups (= partial slots) of the per-node GMRES kernels
 void launch_gm_init(GmState* st, double tol, int maxit, int m, hipStream_t s);
-void launch_gm_dots(const GmVec& a, int k, const double* w, hipStream_t s);
+// Vector arguments (w, z, r, binv) have the basis' precision (fp32: float2 / float4), except
+// in launch_gm_xupdate (delta, binv: FP64) and launch_gm_resid (b, w, r: FP64).
+void launch_gm_dots(const GmVec& a, int k, const void* w, hipStream_t s);
 void launch_gm_sum(const double* part, int nb, int rows, double* out, const GmState* st,
                    hipStream_t s);
-void launch_gm_orth(const GmVec& a, int k, const double* h1, double* w, hipStream_t s);
-void launch_gm_next(const GmVec& a, int k, const double* h2, const double* w, const double* binv,
-                    double* z, hipStream_t s);
+void launch_gm_orth(const GmVec& a, int k, const double* h1, void* w, hipStream_t s);
+void launch_gm_next(const GmVec& a, int k, const double* h2, const void* w, const void* binv,
+                    void* z, hipStream_t s);
 void launch_gm_givens(const GmSmall& sm, int j, const double* h1, const double* h2, GmState* st,
                       hipStream_t s);
 void launch_gm_solve_y(const GmSmall& sm, const GmState* st, hipStream_t s);
@@ -348,7 +352,7 @@ void launch_gm_xupdate(const GmVec& a, const double* y, const double* binv, doub
 void launch_gm_resid(const GmVec& a, const double* b, const double* w, double* r, hipStream_t s);
 void launch_gm_restart(const double* part, int nb, const GmSmall& sm, GmState* st, int first,
                        hipStream_t s);
-void launch_gm_v0(const GmVec& a, const double* r, const double* binv, double* z, hipStream_t s);
+void launch_gm_v0(const GmVec& a, const double* r, const void* binv, void* z, hipStream_t s);
 // T += delta.T, V += delta.V; norm2 = (||delta_T||^2, ||T||^2) (part: >= 2 gm_blocks(n)).
 void launch_newton_apply(int n, const double* delta, double* T, double* V, double* part,
                          double* norm2, hipStream_t s);
@@ -419,6 +423,7 @@ struct rafem_mesh_s {
     // monolithic corrector (allocated on first use): Jacobian slots as double4 in the SELL
     // layout, -R, block-Jacobi inverses, the Newton update, GMRES vectors and basis
     double *mono_vals = nullptr, *mono_rhs = nullptr, *mono_binv = nullptr, *mono_delta = nullptr;
+    float *mono_vals32 = nullptr, *mono_binv32 = nullptr;  // FP32 copies (mixed GMRES)
     double *gm_w = nullptr, *gm_z = nullptr, *gm_r = nullptr, *gm_part = nullptr;
     double* gm_small = nullptr;        // H, cs, sn, g, y, h1, h2
     double* gm_V = nullptr;            // basis, (gm_cap + 1) vectors (freed on growth)

@@ -80,6 +80,9 @@ GmresOpts resolve_gmres(const rafem_gmres_opts* o) {
         if (o->m > 0) g.m = o->m;
         if (o->max_iters > 0) g.maxit = o->max_iters;
         if (o->tol > 0.0) g.tol = o->tol;
+        if (o->precision != RAFEM_FP64 && o->precision != RAFEM_MIXED)
+            throw Error{RAFEM_E_ARG, "GMRES precision must be RAFEM_FP64 or RAFEM_MIXED"};
+        g.precision = o->precision;
     }
     if (g.m > kGmMaxM) throw Error{RAFEM_E_ARG, "GMRES restart length exceeds RAFEM_GMRES_MAX_M"};
     if (!std::isfinite(g.tol) || g.tol >= 1.0)
@@ -87,9 +90,14 @@ GmresOpts resolve_gmres(const rafem_gmres_opts* o) {
     return g;
 }
 
-void mono_ensure(rafem_mesh m, int mvec) {
+void mono_ensure(rafem_mesh m, int mvec, bool fp32) {
     const int nb = gm_blocks((int)m->n);
     const size_t npad = (size_t)nb * kWG;
+    if (fp32 && !m->mono_vals32) {
+        auto f = [&](size_t count) { return static_cast<float*>(mesh_alloc(m, count * sizeof(float))); };
+        m->mono_vals32 = f(4 * (size_t)m->sell_nnz);
+        m->mono_binv32 = f(4 * npad);
+    }
     if (!m->mono_vals) {
         auto d = [&](size_t count) { return static_cast<double*>(mesh_alloc(m, count * sizeof(double))); };
         m->mono_vals = d(4 * (size_t)m->sell_nnz);
@@ -145,6 +153,10 @@ void mono_assemble(rafem_mesh m, const rafem_phys* phys, const double* k_e, cons
     jac_colours(m, a, s);
     launch_jac_dirichlet(m->dir_ids, m->nD, SL, m->mono_vals, 4, 1, s);
     launch_block_inv((int)m->n, SL, m->mono_vals, m->mono_binv, s);
+    if (m->mono_vals32) {  // FP32 copies for the mixed Arnoldi process
+        launch_cast32(m->mono_vals, m->mono_vals32, 4 * m->sell_nnz, s);
+        launch_cast32(m->mono_binv, m->mono_binv32, 4 * m->n, s);
+    }
     RAFEM_HIP(hipGetLastError());
 }
 
@@ -172,8 +184,12 @@ rafem_status gmres_solve(rafem_mesh m, const double* b, double* x, const GmresOp
     const int n = (int)m->n;
     const int nb = gm_blocks(n);
     const Small sa = small_arrays(m, o.m, hist, hist_cap);
-    GmVec a{n, reinterpret_cast<double2*>(m->gm_V), (int64_t)nb * kWG, m->gm_part, m->gm_st};
-    BsellArgs A;
+    const bool fp32 = o.precision == RAFEM_MIXED;
+    if (fp32 && !m->mono_vals32) throw Error{RAFEM_E_STATE, "no FP32 copy of the Jacobian"};
+    // the basis (and w, z) in the Arnoldi precision; restarts and the update in FP64
+    GmVec a{n, m->gm_V, (int64_t)nb * kWG, m->gm_part, m->gm_st, fp32 ? 1 : 0};
+    const void* binv_k = fp32 ? (const void*)m->mono_binv32 : (const void*)m->mono_binv;
+    BsellArgs A;  // Arnoldi SpMV: z -> w
     A.n = n;
     A.nslabs = m->nslabs;
     A.sptr = m->sptr;
@@ -181,20 +197,26 @@ rafem_status gmres_solve(rafem_mesh m, const double* b, double* x, const GmresOp
     A.sdel = m->sdel;
     A.sofs = m->sofs;
     A.soff = m->soff;
-    A.vals = reinterpret_cast<const double4*>(m->mono_vals);
-    A.y = reinterpret_cast<double2*>(m->gm_w);
+    A.vals = fp32 ? (const void*)m->mono_vals32 : (const void*)m->mono_vals;
+    A.x = m->gm_z;
+    A.y = m->gm_w;
     A.st = m->gm_st;
+    A.arnoldi = 1;
+    A.fp32 = fp32 ? 1 : 0;
+    BsellArgs Ar = A;  // restart SpMV (FP64): x -> w
+    Ar.vals = m->mono_vals;
+    Ar.x = x;
+    Ar.arnoldi = 0;
+    Ar.fp32 = 0;
     launch_gm_init(m->gm_st, o.tol, o.maxit, o.m, s);
     launch_fill(x, 2 * m->n, 0.0, s);
     launch_gm_resid(a, b, nullptr, m->gm_r, s);
     launch_gm_restart(m->gm_part, nb, sa.sm, m->gm_st, 1, s);
-    launch_gm_v0(a, m->gm_r, m->mono_binv, m->gm_z, s);
+    launch_gm_v0(a, m->gm_r, binv_k, m->gm_z, s);
     // the device ends the solve (tolerance, iteration limit or breakdown) within
     // maxit / m + 1 cycles; the bound below only guards the host loop
     const int max_cycles = o.maxit / o.m + 3;
     for (int cyc = 0;; ++cyc) {
-        A.arnoldi = 1;
-        A.x = reinterpret_cast<const double2*>(m->gm_z);
         for (int j = 0; j < o.m; ++j) {
             const int k = j + 1;
             launch_bsell(A, s);
@@ -202,17 +224,15 @@ rafem_status gmres_solve(rafem_mesh m, const double* b, double* x, const GmresOp
             launch_gm_sum(m->gm_part, nb, k, sa.h1, m->gm_st, s);
             launch_gm_orth(a, k, sa.h1, m->gm_w, s);
             launch_gm_sum(m->gm_part, nb, k + 1, sa.h2, m->gm_st, s);
-            if (k < o.m) launch_gm_next(a, k, sa.h2, m->gm_w, m->mono_binv, m->gm_z, s);
+            if (k < o.m) launch_gm_next(a, k, sa.h2, m->gm_w, binv_k, m->gm_z, s);
             launch_gm_givens(sa.sm, j, sa.h1, sa.h2, m->gm_st, s);
         }
         launch_gm_solve_y(sa.sm, m->gm_st, s);
         launch_gm_xupdate(a, sa.sm.y, m->mono_binv, x, s);
-        A.arnoldi = 0;
-        A.x = reinterpret_cast<const double2*>(x);
-        launch_bsell(A, s);
+        launch_bsell(Ar, s);
         launch_gm_resid(a, b, m->gm_w, m->gm_r, s);
         launch_gm_restart(m->gm_part, nb, sa.sm, m->gm_st, 0, s);
-        launch_gm_v0(a, m->gm_r, m->mono_binv, m->gm_z, s);
+        launch_gm_v0(a, m->gm_r, binv_k, m->gm_z, s);
         RAFEM_HIP(hipGetLastError());
         RAFEM_HIP(hipMemcpyAsync(m->gm_st_host, m->gm_st, sizeof(GmState), hipMemcpyDeviceToHost, s));
         RAFEM_HIP(hipStreamSynchronize(s));

@@ -9,13 +9,15 @@ struct GmresOpts {
     int m = 30;
     int maxit = 20000;
     double tol = 1e-10;
+    int precision = RAFEM_FP64;
 };
 
 GmresOpts resolve_gmres(const rafem_gmres_opts* o);
 
 // Workspace of the monolithic corrector for restart length mvec (allocated once, the
-// basis grown when a longer restart is asked for).
-void mono_ensure(rafem_mesh m, int mvec);
+// basis grown when a longer restart is asked for; fp32: also the FP32 copies of J and of
+// the block inverses, which mono_assemble then keeps current).
+void mono_ensure(rafem_mesh m, int mvec, bool fp32);
 
 // J (SELL slots, m->mono_vals), -R (m->mono_rhs) and the block-Jacobi inverses at (T, V).
 void mono_assemble(rafem_mesh m, const rafem_phys* phys, const double* k_e, const double* perf,

@@ -119,7 +119,8 @@ class DeviceProblem:
         return info
 
     def step_mono(self, dt: float, T_prev=None, dt_prev=None, corr_tol: float = 1e-10,
-                  max_iters: int = 50, m: int = 30, gmres_tol: float = 1e-10, **kw):
+                  max_iters: int = 50, m: int = 30, gmres_tol: float = 1e-10,
+                  gmres_precision: str = "fp64", **kw):
         """One predictor-corrector step of size dt with the monolithic Newton-GMRES(m)
         corrector (T and V advance only if accepted)."""
         self.phys.dt = float(dt)
@@ -127,7 +128,7 @@ class DeviceProblem:
             info = rafem.step_mono(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e,
                                    self.dir_V, self.dir_T, T_prev, dt_prev, self.T, self.V,
                                    corr_tol=corr_tol, max_iters=max_iters, m=m,
-                                   gmres_tol=gmres_tol, **kw)
+                                   gmres_tol=gmres_tol, gmres_precision=gmres_precision, **kw)
         finally:
             self.phys.dt = float(self.p.dt)
         return info
@@ -135,7 +136,7 @@ class DeviceProblem:
     def simulate_pc(self, t_total: float, dt0: float, corr_tol: float = 1e-10,
                     max_iters: int = 50, tol: float = 1e-12, precision: str = "fp64",
                     dt_min: float = 1e-6, keep: bool = False, corrector: str = "picard",
-                    m: int = 30, gmres_tol: float = 1e-10):
+                    m: int = 30, gmres_tol: float = 1e-10, gmres_precision: str = "fp64"):
         """Predictor-corrector time loop from the current state to t_total: a rejected step is
         retried with half the step; after an accepted step the step doubles again, up to dt0;
         the last step ends exactly at t_total.  corrector: "picard" (staggered PCG solves,
@@ -148,7 +149,8 @@ class DeviceProblem:
             h = min(dt, t_total - t)
             T_n = self.T.clone()
             if corrector == "newton":
-                info = self.step_mono(h, T_prev, dt_prev, corr_tol, max_iters, m, gmres_tol)
+                info = self.step_mono(h, T_prev, dt_prev, corr_tol, max_iters, m, gmres_tol,
+                                      gmres_precision)
                 info["solver_iters"] = info["gmres_iters"]
             else:
                 info = self.step_pc(h, T_prev, dt_prev, corr_tol, max_iters, tol, precision)

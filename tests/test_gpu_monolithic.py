@@ -151,3 +151,50 @@ def test_argument_checks(torch_cuda):
         R.step_mono(bp.mesh, bp.phys, bp.k_e, bp.perf_e, bp.sigma0_e, bp.dir_V, bp.dir_T, None,
                     0.0, bp.T, bp.V)
     bp.close()
+
+
+@pytest.mark.parametrize("kind,n", [("hex", 9), ("tet", 8)])
+def test_mixed_gmres_reaches_the_fp64_tolerance(torch_cuda, kind, n):
+    """FP32 Arnoldi process inside FP64 restarts: the returned update meets the same FP64
+    residual test as the FP64 solve (checked with the oracle's Jacobian) in a similar number
+    of steps; the two updates differ only within what the tolerance allows."""
+    from paper_2409_13036_amd import _lib as R
+    p = ri.make_problem(kind, n, 2)
+    m = Model(p)
+    T, V = _state(p, m, seed=1)
+    T0 = p.initial_T()
+    tol = 1e-10
+    dp = _device_problem(p)
+    args = (dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, to_dev(T0), to_dev(T), to_dev(V))
+    d64, i64, _ = R.mono_solve(*args, m=20, tol=tol)
+    d32, i32, _ = R.mono_solve(*args, m=20, tol=tol, precision="mixed")
+    d64, d32 = to_host(d64), to_host(d32)
+    dp.close()
+    J = mono.interleaved_matrix(m, mono.jacobian_blocks(m, T0, DT, T, V))
+    b = -mono.residual(m, T0, DT, T, V)
+    rr = np.linalg.norm(b - J @ d32) / np.linalg.norm(b)
+    print(f"[gmres mixed {kind}{n}] iters {i32['iters']} (fp64 {i64['iters']}), cycles "
+          f"{i32['cycles']}, relres_true {i32['relres_true']:.2e}, oracle residual {rr:.2e}, "
+          f"vs fp64 update {rel_err(d32, d64):.2e}", flush=True)
+    assert i32["status"] == 0 and i32["relres_true"] <= tol and rr <= 1.0001 * tol
+    assert i32["iters"] <= 1.5 * i64["iters"] + 10
+    # both updates solve J d = b to 1e-10: they differ by at most cond(J) * 2e-10
+    x = np.linalg.solve(J.toarray(), b)
+    assert rel_err(d32, x) <= 1e-6 and rel_err(d64, x) <= 1e-6
+    assert np.all(d32[2 * p.dir_ids] == 0) and np.all(d32[2 * p.dir_ids + 1] == 0)
+
+
+@pytest.mark.parametrize("kind,n", [("hex", 11), ("tet", 9)])
+def test_newton_with_mixed_gmres_matches_oracle(torch_cuda, kind, n):
+    p = ri.make_problem(kind, n, 1)
+    m = Model(p)
+    T0, V0 = p.initial_T(), p.initial_V()
+    dp = _device_problem(p)
+    info = dp.step_mono(DT, corr_tol=1e-9, m=30, gmres_tol=1e-10, gmres_precision="mixed")
+    ref = mono.newton_step(m, T0, V0, DT, T0.copy(), 1e-9, m=30, lin_tol=1e-10)
+    Tg, Vg = to_host(dp.T), to_host(dp.V)
+    dp.close()
+    print(f"[newton mixed {kind}{n}] GPU {info}; oracle iters {ref.iters}; T "
+          f"{rel_err(Tg, ref.T):.2e} V {rel_err(Vg, ref.V):.2e}", flush=True)
+    assert info["accepted"] == 1 and abs(info["iters"] - ref.iters) <= 1
+    assert rel_err(Tg, ref.T) <= 1e-8 and rel_err(Vg, ref.V) <= 1e-8
