@@ -656,6 +656,9 @@ def main():
     ap.add_argument("--fd-params", type=int, default=32)
     ap.add_argument("--workload", choices=["c1", "c2"], default="c1",
                     help="c1: 101^3 hex (default); c2: 161^3-node jittered Kuhn tets")
+    ap.add_argument("--no-extrapolate", action="store_true",
+                    help="start every solve from the previous state instead of the linear "
+                         "extrapolation of the last two")
     ap.add_argument("--no-batch", action="store_true", help="skip the ensemble leg")
     ap.add_argument("--no-pc", action="store_true", help="skip the predictor-corrector leg")
     ap.add_argument("--no-mono", action="store_true", help="skip the monolithic GMRES leg")
@@ -736,6 +739,7 @@ def main():
         p = ri.config1(n=n, steps=args.steps)
         workload = f"C1 coupled RFA step, {n}^3-node hex cube"
     dp = DeviceProblem(p)
+    dp.extrapolate = not args.no_extrapolate
     N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
     mesh_stats = dp.mesh.stats()
     res = {}

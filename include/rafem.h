@@ -205,7 +205,9 @@ typedef struct {
                             FP64 true residual of the refinement in MIXED) */
     int32_t maxit;       /* limit on (inner) PCG iterations per solve; <= 0 means 20000 */
     int32_t precision;   /* RAFEM_FP64 or RAFEM_MIXED */
-    double  inner_tol;   /* MIXED: relative tolerance of each inner solve (0 means 1e-4) */
+    double  inner_tol;   /* MIXED: relative tolerance of each inner solve (0 means 1e-4); an
+                            inner solve stops earlier when a tenth of the reduction the FP64
+                            tolerance still needs is reached (the last refinement) */
     int32_t max_outer;   /* MIXED: refinement limit (<= 0 means 30) */
     int32_t poll_every;  /* iterations enqueued between host polls (<= 0 means adaptive) */
 } rafem_solve_opts;
@@ -309,6 +311,16 @@ typedef struct {
     int32_t reuse_bioheat;/* nonzero: reuse the bioheat matrix assembled by the previous call
                              (k, perfusion, rho_c unchanged); E_STATE if there is none; a
                              matrix built for another dt is rebuilt regardless */
+    int32_t extrapolate;  /* rafem_step of a coupled problem only.  1: this call continues the
+                             trajectory of the previous rafem_step call on this handle; both
+                             solves start from the linear extrapolation in time
+                             T^n + (dt/dt_prev)(T^n - T^{n-1}), and the same for V (sigma and the
+                             right-hand side still use T^n), the handle keeping T^{n-1}, V^{n-1}
+                             from that call.  2: a new trajectory starts here (solves start from
+                             T_d, V_d; the states are kept for the next call).  0: off.  A call
+                             with 0, a failed call, rafem_step_pc and rafem_step_mono end the
+                             trajectory (the next call with 1 then behaves as 2). */
+    int32_t pad;
 } rafem_phys;
 
 typedef struct {

@@ -892,10 +892,40 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
         std::memset(&inf, 0, sizeof(inf));
         // a bioheat matrix built for another time step is rebuilt
         const bool reuse = phys->reuse_bioheat && m->bioheat_dt == phys->dt;
+        hipStream_t s = (hipStream_t)stream;
         region_begin(m);
+        if (!phys->extrapolate) {
+            m->xg_ready = false;
+            const rafem_status st = step_core(m, phys, reuse, k_e_d, perf_e_d, sigma0_e_d,
+                                              dir_V_d, dir_T_d, T_d, T_d, T_d, V_d, o, inf, s);
+            region_flush(m, s);
+            return st;
+        }
+        // keep (T^n, V^n); start the solves from their extrapolation when the previous call
+        // left (T^{n-1}, V^{n-1})
+        if (phys->extrapolate == 2) m->xg_ready = false;
+        if (!m->xg_T[0])
+            for (int k = 0; k < 2; ++k) {
+                m->xg_T[k] = dalloc<double>(m, m->n);
+                m->xg_V[k] = dalloc<double>(m, m->n);
+            }
+        const size_t bytes = (size_t)m->n * sizeof(double);
+        double* Tn = m->xg_T[m->xg_cur];
+        double* Vn = m->xg_V[m->xg_cur];
+        region_mark(m, kRegCheck, s);
+        RAFEM_HIP(hipMemcpyAsync(Tn, T_d, bytes, hipMemcpyDeviceToDevice, s));
+        if (phys->coupled) RAFEM_HIP(hipMemcpyAsync(Vn, V_d, bytes, hipMemcpyDeviceToDevice, s));
+        if (m->xg_ready) {
+            const double c = phys->dt / m->xg_dt;
+            launch_extrapolate((int)m->n, Tn, m->xg_T[1 - m->xg_cur], c, T_d, s);
+            if (phys->coupled) launch_extrapolate((int)m->n, Vn, m->xg_V[1 - m->xg_cur], c, V_d, s);
+        }
         const rafem_status st = step_core(m, phys, reuse, k_e_d, perf_e_d, sigma0_e_d, dir_V_d,
-                                          dir_T_d, T_d, T_d, T_d, V_d, o, inf, (hipStream_t)stream);
-        region_flush(m, (hipStream_t)stream);
+                                          dir_T_d, Tn, Tn, T_d, V_d, o, inf, s);
+        m->xg_ready = st == RAFEM_OK && phys->coupled;
+        m->xg_cur = 1 - m->xg_cur;
+        m->xg_dt = phys->dt;
+        region_flush(m, s);
         return st;
     });
 }
@@ -920,6 +950,7 @@ rafem_status rafem_step_pc(rafem_mesh m, const rafem_phys* phys, const double* k
         rafem_corrector_info& ci = info ? *info : local;
         std::memset(&ci, 0, sizeof(ci));
         const size_t bytes = (size_t)m->n * sizeof(double);
+        m->xg_ready = false;
         region_begin(m);
         region_mark(m, kRegCheck, s);
         // keep (T^n, V^n) to restore a rejected step; predictor into pc_Tk
@@ -1043,6 +1074,7 @@ rafem_status rafem_step_mono(rafem_mesh m, const rafem_phys* phys, const double*
         std::memset(&mi, 0, sizeof(mi));
         mono_ensure(m, o.m, o.precision == RAFEM_MIXED);
         const size_t bytes = (size_t)m->n * sizeof(double);
+        m->xg_ready = false;
         region_begin(m);
         region_mark(m, kRegCheck, s);
         // keep (T^n, V^n) to restore a rejected step; the iterate starts at (T*, V^n) with

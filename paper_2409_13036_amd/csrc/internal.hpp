@@ -415,6 +415,12 @@ struct rafem_mesh_s {
     // predictor-corrector step: T^n and V^n (restored on rejection), the current iterate,
     // and the two sums of the change norm
     double *pc_Tn = nullptr, *pc_Vn = nullptr, *pc_Tk = nullptr, *pc_norm = nullptr;
+    // extrapolated starting points of rafem_step (phys->extrapolate): the states at the start
+    // of the last two calls (slot xg_cur receives the next), allocated on first use
+    double *xg_T[2] = {nullptr, nullptr}, *xg_V[2] = {nullptr, nullptr};
+    int xg_cur = 0;
+    bool xg_ready = false;
+    double xg_dt = 0.0;
     bool potential_ready = false;  // a step has assembled the potential matrix
     double *adj_mu = nullptr, *adj_nu = nullptr, *adj_sbar = nullptr, *adj_dsig = nullptr;
     // iteration counts of the previous solve of each kind and precision (first-chunk guesses)

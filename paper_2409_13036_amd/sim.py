@@ -64,6 +64,10 @@ class DeviceProblem:
         self.dir_T = torch.as_tensor(problem.dir_T, **f64).contiguous()
         self.phys = rafem.Phys(problem.rho_c, problem.dt, problem.T_a, problem.alpha_sigma,
                                problem.T_ref, 1 if problem.coupled else 0, 0)
+        # extrapolate: start each step's solves from the linear extrapolation of the last two
+        # states (library-side); _chain: the next step continues the previous one
+        self.extrapolate = False
+        self._chain = False
         self.loss_ids = self.T_target = None
         if problem.loss_ids is not None:
             self.loss_ids = torch.as_tensor(problem.loss_ids, dtype=torch.int32, device=self.dev)
@@ -75,23 +79,29 @@ class DeviceProblem:
         self.k_e = k_e.to(self.dev, self.torch.float64).contiguous().clone()
         self.perf_e = perf_e.to(self.dev, self.torch.float64).contiguous().clone()
         self.phys.reuse_bioheat = 0
+        self._chain = False
 
     def restore(self, T, V):
         """Continue from a saved state (the bioheat matrix is kept)."""
         self.T.copy_(T)
         self.V.copy_(V)
+        self._chain = False
 
     def reset(self, T0: Optional[np.ndarray] = None, V0: Optional[np.ndarray] = None):
         torch = self.torch
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.T = torch.as_tensor(self.p.initial_T() if T0 is None else T0, **f64).clone()
         self.V = torch.as_tensor(self.p.initial_V() if V0 is None else V0, **f64).clone()
+        self._chain = False
 
     def step(self, tol: float = 1e-12, precision: str = "fp64", **kw):
         """One coupled step (the bioheat matrix is assembled on the first call only)."""
+        self.phys.extrapolate = (1 if self._chain else 2) if self.extrapolate else 0
+        self._chain = False
         info = rafem.step(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e, self.dir_V,
                           self.dir_T, self.T, self.V, tol=tol, precision=precision, **kw)
         self.phys.reuse_bioheat = 1
+        self._chain = bool(self.extrapolate)
         return info
 
     def simulate(self, steps: int, tol: float = 1e-12, precision: str = "fp64", keep: bool = False,
@@ -107,6 +117,7 @@ class DeviceProblem:
     def step_pc(self, dt: float, T_prev=None, dt_prev=None, corr_tol: float = 1e-10,
                 max_iters: int = 50, tol: float = 1e-12, precision: str = "fp64", **kw):
         """One predictor-corrector step of size dt (T and V advance only if accepted)."""
+        self._chain = False
         self.phys.dt = float(dt)
         try:
             info = rafem.step_pc(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e,
@@ -123,6 +134,7 @@ class DeviceProblem:
                   gmres_precision: str = "fp64", **kw):
         """One predictor-corrector step of size dt with the monolithic Newton-GMRES(m)
         corrector (T and V advance only if accepted)."""
+        self._chain = False
         self.phys.dt = float(dt)
         try:
             info = rafem.step_mono(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e,

@@ -1,0 +1,72 @@
+"""Extrapolated starting points of the step's solves (phys.extrapolate): the states match the
+oracle's steps, the solves need fewer iterations, and a new trajectory (after a reset, or
+after a corrector step) starts from the given state, bit for bit like a step without
+extrapolation."""
+import numpy as np
+import pytest
+
+import rafem_inputs as ri
+from oracle.rafem import Model
+from gpu_helpers import rel_err, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-13
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+@pytest.mark.parametrize("kind,n", [("hex", 15), ("tet", 11)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_extrapolated_steps_match_oracle_with_fewer_iterations(torch_cuda, kind, n, precision):
+    from paper_2409_13036_amd.sim import DeviceProblem
+    p = ri.make_problem(kind, n, 0)
+    ref, _ = Model(p).simulate(6, 1e-15)
+    plain = DeviceProblem(p)
+    _, info0 = plain.simulate(6, tol=TOL, precision=precision)
+    plain.close()
+    dp = DeviceProblem(p)
+    dp.extrapolate = True
+    states, info1 = dp.simulate(6, tol=TOL, precision=precision, keep=True)
+    dp.close()
+    for (T, V), (Tr, Vr) in zip(states, ref):
+        assert rel_err(T, Tr) <= 1e-8 and rel_err(V, Vr) <= 1e-8
+    it0 = sum(i["V"]["iters"] + i["T"]["iters"] for i in info0[2:])
+    it1 = sum(i["V"]["iters"] + i["T"]["iters"] for i in info1[2:])
+    print(f"[extrapolate {kind}{n} {precision}] iterations of steps 3-6: {it1} (plain {it0})",
+          flush=True)
+    assert it1 < it0
+    # the first two steps start a trajectory: identical to plain steps
+    assert info1[0]["V"]["iters"] == info0[0]["V"]["iters"]
+
+
+def test_new_trajectory_starts_from_the_given_state(torch_cuda):
+    from paper_2409_13036_amd.sim import DeviceProblem
+    p = ri.make_problem("hex", 13, 1)
+    ref = DeviceProblem(p)
+    ref.step(TOL)
+    T_ref, V_ref = to_host(ref.T), to_host(ref.V)
+    ref.close()
+    dp = DeviceProblem(p)
+    dp.extrapolate = True
+    for _ in range(3):
+        dp.step(TOL)
+    dp.reset()
+    dp.step(TOL)
+    assert np.array_equal(to_host(dp.T), T_ref) and np.array_equal(to_host(dp.V), V_ref)
+    # a corrector step ends the trajectory as well: the next step starts from its result
+    dp.step_pc(1.0, corr_tol=1e-9, tol=TOL)
+    T_pc, V_pc = to_host(dp.T), to_host(dp.V)
+    dp.step(TOL)
+    other = DeviceProblem(p)
+    other.reset(T_pc, V_pc)
+    other.step(TOL)
+    assert np.array_equal(to_host(dp.T), to_host(other.T))
+    other.close()
+    dp.close()
