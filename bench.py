@@ -369,6 +369,7 @@ def batch_leg(args) -> dict:
     probs = ri.config4(samples=args.batch_samples, steps=args.batch_steps)
     t0 = time.perf_counter()
     bp = BatchProblem(probs)
+    bp.extrapolate = not args.no_extrapolate
     setup = time.perf_counter() - t0
     S = len(probs)
     nnz = sum((3 * p.n - 2) ** 3 for p in probs)

@@ -217,6 +217,8 @@ class BatchProblem:
         self.dir_T = torch.as_tensor(dT, **f64)
         self.phys = rafem.Phys(p0.rho_c, p0.dt, p0.T_a, p0.alpha_sigma, p0.T_ref,
                                1 if p0.coupled else 0, 0)
+        self.extrapolate = False   # as for DeviceProblem
+        self._chain = False
         self.reset()
 
     def _gather(self, per_sample):
@@ -231,6 +233,7 @@ class BatchProblem:
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.T = torch.as_tensor(self._gather([p.initial_T() for p in self.problems]), **f64)
         self.V = torch.as_tensor(self._gather([p.initial_V() for p in self.problems]), **f64)
+        self._chain = False
 
     def sample(self, q: int):
         """(T, V) of sample q as host arrays."""
@@ -239,9 +242,12 @@ class BatchProblem:
         return self.T[a:a + n].cpu().numpy(), self.V[a:a + n].cpu().numpy()
 
     def step(self, tol: float = 1e-12, precision: str = "fp64", **kw):
+        self.phys.extrapolate = (1 if self._chain else 2) if self.extrapolate else 0
+        self._chain = False
         info = rafem.step(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e, self.dir_V,
                           self.dir_T, self.T, self.V, tol=tol, precision=precision, **kw)
         self.phys.reuse_bioheat = 1
+        self._chain = bool(self.extrapolate)
         return info
 
     def close(self):

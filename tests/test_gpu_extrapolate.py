@@ -70,3 +70,23 @@ def test_new_trajectory_starts_from_the_given_state(torch_cuda):
     assert np.array_equal(to_host(dp.T), to_host(other.T))
     other.close()
     dp.close()
+
+
+def test_extrapolated_ensemble_matches_its_samples_alone(torch_cuda):
+    """Batch handles extrapolate every sample from its own history: each sample's states
+    equal those of the same sample stepped alone with extrapolation."""
+    from paper_2409_13036_amd.sim import BatchProblem, DeviceProblem
+    probs = [ri.make_problem("hex", 9, 1), ri.make_problem("hex", 12, 2)]
+    bp = BatchProblem(probs)
+    bp.extrapolate = True
+    for _ in range(4):
+        bp.step(TOL, "mixed")
+    got = [bp.sample(q) for q in range(2)]
+    bp.close()
+    for q, p in enumerate(probs):
+        dp = DeviceProblem(p)
+        dp.extrapolate = True
+        for _ in range(4):
+            dp.step(TOL, "mixed")
+        assert np.array_equal(got[q][0], to_host(dp.T)) and np.array_equal(got[q][1], to_host(dp.V))
+        dp.close()
