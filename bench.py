@@ -594,9 +594,10 @@ def psnr_leg(dp, args) -> dict:
 
 def liver_leg(args) -> dict:
     """Unstructured liver-like tet meshes (Delaunay, two needle electrodes): the stand-ins for
-    the paper's meshes A and B (about 3.5k and 8.4k nodes) in RCM order, then one of
-    --liver-nodes nodes in the delivered (shuffled) order and in RCM order -- coupled steps/s
-    (FP64 and mixed) and the PCG SpMV's launch time and CSR-count bandwidth."""
+    the paper's meshes A and B (about 3.5k and 8.4k nodes) in RCM order, then one of --liver-nodes nodes in the delivered (shuffled) order, in
+    RCM order, and in RCM order with degree-sorted windows -- coupled steps/s (FP64 and
+    mixed, extrapolated starting points unless --no-extrapolate) and the PCG SpMV's launch
+    time and CSR-count bandwidth."""
     import numpy as np
     import torch
     import rafem_inputs as ri
@@ -609,6 +610,7 @@ def liver_leg(args) -> dict:
 
     def measure(prob, steps, warmup, label):
         dp = DeviceProblem(prob)
+        dp.extrapolate = not args.no_extrapolate
         st = dp.mesh.stats()
         N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
         row = {"n_nodes": N, "n_elems": dp.mesh.n_elems, "nnz": nnz, "colours": st.n_colours,
@@ -633,7 +635,9 @@ def liver_leg(args) -> dict:
     p = ri.make_liver(args.liver_nodes, 0)
     out["large_mesh_generation_s"] = time.perf_counter() - t0
     q, order = rcm_reordered(p)
-    for label, prob, o in (("shuffled", p, None), ("rcm", q, order)):
+    qs, order_s = rcm_reordered(p, window=512)
+    for label, prob, o in (("shuffled", p, None), ("rcm", q, order),
+                           ("rcm_degree_sorted", qs, order_s)):
         row = measure(prob, args.liver_steps, 2, f"{args.liver_nodes} {label}")
         row["bandwidth"] = bandwidth(p.conn, o)
         out[f"large_{label}"] = row

@@ -104,6 +104,15 @@ rafem_status rafem_colour_elements(int64_t n_nodes, int64_t n_elems, int32_t npe
 rafem_status rafem_rcm_order(int64_t n_nodes, int64_t n_elems, int32_t npe,
                              const int32_t* conn_h, int32_t* order_h);
 
+/* Within consecutive windows of `window` positions of a node order (e.g. the RCM order),
+ * sort the nodes by increasing degree, ties kept in their order (host-only).  The rows of
+ * each 64-row slab of the solver's layout then have nearly equal lengths, so little of the
+ * slab is padding; the columns stay within about one window of the RCM bandwidth.
+ *   order_h  [n_nodes] host, in: a permutation of the nodes; out: the sorted one
+ * Errors: E_ARG (window < 1, order not a permutation), E_MESH as for rafem_rcm_order. */
+rafem_status rafem_degree_sort(int64_t n_nodes, int64_t n_elems, int32_t npe,
+                               const int32_t* conn_h, int64_t window, int32_t* order_h);
+
 /* ---------------------------------------------------------------------------
  * Mesh handle: structure, colouring, geometry and all device workspaces.
  * ------------------------------------------------------------------------- */

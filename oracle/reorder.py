@@ -107,3 +107,16 @@ def bandwidth(conn: np.ndarray, n_nodes: int, order=None) -> int:
     pos = np.arange(n_nodes) if order is None else np.argsort(order)
     c = pos[np.asarray(conn)]
     return int((c.max(axis=1) - c.min(axis=1)).max())
+
+
+def degree_sort(order: np.ndarray, conn: np.ndarray, n_nodes: int, window: int) -> np.ndarray:
+    """Within consecutive windows of ``window`` positions of ``order``, the nodes sorted by
+    increasing degree (number of graph neighbours), ties kept in their order.  Slabs of 64
+    consecutive rows then hold rows of nearly equal length."""
+    _, deg = _adjacency(np.asarray(conn), n_nodes)
+    out = np.array(order, dtype=np.int32, copy=True)
+    for s in range(0, n_nodes, window):
+        seg = out[s:s + window].copy()
+        keyed = sorted(range(seg.size), key=lambda k: (deg[seg[k]], k))
+        out[s:s + window] = seg[keyed]
+    return out

@@ -37,7 +37,7 @@ EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafe
            "rafem_mesh_create_batch", "rafem_mesh_sample_layout", "rafem_mesh_set_graphs",
            "rafem_sample_info", "rafem_spmv_timing", "rafem_step_pc", "rafem_mono_jacobian",
            "rafem_mono_solve", "rafem_step_mono", "rafem_rcm_order", "rafem_regions_enable",
-           "rafem_regions_read")
+           "rafem_regions_read", "rafem_degree_sort")
 
 
 class RafemError(RuntimeError):
@@ -126,6 +126,7 @@ _lib.rafem_abi_version.restype = C.c_int32
 _lib.rafem_csr_structure.argtypes = [_i64, _i64, _i32, _p, C.POINTER(C.c_int64), _p, _p]
 _lib.rafem_colour_elements.argtypes = [_i64, _i64, _i32, _p, _p, C.POINTER(C.c_int32)]
 _lib.rafem_rcm_order.argtypes = [_i64, _i64, _i32, _p, _p]
+_lib.rafem_degree_sort.argtypes = [_i64, _i64, _i32, _p, _i64, _p]
 _lib.rafem_mesh_create.argtypes = [_i64, _i64, _i32, _p, _p, _p, _i64, C.POINTER(_p)]
 _lib.rafem_mesh_destroy.argtypes = [_p]
 _lib.rafem_mesh_get_stats.argtypes = [_p, C.POINTER(MeshStats)]
@@ -209,6 +210,15 @@ def colour_elements(conn: np.ndarray, n_nodes: int):
     nc = C.c_int32(0)
     _check(_lib.rafem_colour_elements(n_nodes, E, npe, conn.ctypes.data, col.ctypes.data, C.byref(nc)))
     return col, int(nc.value)
+
+
+def degree_sort(order: np.ndarray, conn: np.ndarray, n_nodes: int, window: int) -> np.ndarray:
+    """rafem_degree_sort -> the order with each window of positions sorted by node degree."""
+    conn = _host_i32(conn)
+    E, npe = conn.shape
+    out = np.ascontiguousarray(np.array(order, dtype=np.int32, copy=True))
+    _check(_lib.rafem_degree_sort(n_nodes, E, npe, conn.ctypes.data, int(window), out.ctypes.data))
+    return out
 
 
 def regions_enable(mesh: "Mesh", enable: bool = True):

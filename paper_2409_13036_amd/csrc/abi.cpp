@@ -453,6 +453,24 @@ rafem_status rafem_rcm_order(int64_t n_nodes, int64_t n_elems, int32_t npe,
     });
 }
 
+rafem_status rafem_degree_sort(int64_t n_nodes, int64_t n_elems, int32_t npe,
+                               const int32_t* conn_h, int64_t window, int32_t* order_h) {
+    return guard([&]() -> rafem_status {
+        require(order_h != nullptr, "order is NULL");
+        require(window >= 1, "window must be >= 1");
+        check_conn(n_nodes, n_elems, npe, conn_h);
+        std::vector<char> seen(n_nodes, 0);
+        for (int64_t k = 0; k < n_nodes; ++k) {
+            require(order_h[k] >= 0 && order_h[k] < n_nodes && !seen[order_h[k]],
+                    "order is not a permutation of the nodes");
+            seen[order_h[k]] = 1;
+        }
+        const HostStructure S = build_structure(n_nodes, n_elems, npe, conn_h);
+        degree_sort(n_nodes, S, window, order_h);
+        return RAFEM_OK;
+    });
+}
+
 rafem_status rafem_mesh_create(int64_t n_nodes, int64_t n_elems, int32_t npe, const double* xyz_h,
                                const int32_t* conn_h, const int32_t* dir_ids_h, int64_t n_dir,
                                rafem_mesh* out) {

@@ -58,6 +58,8 @@ int colour_elements(int64_t n_nodes, int64_t n_elems, int npe, const int32_t* co
                     int32_t* colour);
 // Reverse Cuthill-McKee order of the node graph: order[k] = node placed at position k.
 std::vector<int32_t> rcm_order(int64_t n, const HostStructure& S);
+// Stable sort of order[] by node degree within consecutive windows of positions.
+void degree_sort(int64_t n, const HostStructure& S, int64_t window, int32_t* order);
 // Minimum Jacobian determinant over the quadrature points of every element (hex: 2x2x2
 // Gauss points; tet: the constant determinant).  Throws E_MESH if any is <= 0.
 // Returns true when every element is affine (hex: a parallelepiped; tets always are).

@@ -244,6 +244,21 @@ int colour_elements(int64_t n, int64_t E, int npe, const int32_t* conn, int32_t*
     return used;
 }
 
+void degree_sort(int64_t n, const HostStructure& S, int64_t window, int32_t* order) {
+    // Within consecutive windows of positions, nodes by increasing degree (row length less
+    // the diagonal), ties in their current order: each slab of 64 rows then holds rows of
+    // nearly equal length, so little of it is padding.
+    std::vector<int32_t> seg;
+    for (int64_t s0 = 0; s0 < n; s0 += window) {
+        const int64_t s1 = std::min(n, s0 + window);
+        seg.assign(order + s0, order + s1);
+        std::stable_sort(seg.begin(), seg.end(), [&](int32_t a, int32_t b) {
+            return S.row_ptr[a + 1] - S.row_ptr[a] < S.row_ptr[b + 1] - S.row_ptr[b];
+        });
+        std::copy(seg.begin(), seg.end(), order + s0);
+    }
+}
+
 std::vector<int32_t> rcm_order(int64_t n, const HostStructure& S) {
     // Reverse Cuthill-McKee on the node graph (neighbours: the row's columns without the
     // diagonal).  Per component, in order of its smallest node id: the pseudo-peripheral

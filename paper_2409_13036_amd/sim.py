@@ -43,9 +43,13 @@ def reorder_nodes(problem, order: np.ndarray):
         electrode_ids=electrode, loss_ids=loss_ids, T_target=T_target)
 
 
-def rcm_reordered(problem):
-    """(problem renumbered by the library's reverse Cuthill-McKee order, order)."""
-    order = rafem.rcm_order(problem.conn, problem.xyz.shape[0])
+def rcm_reordered(problem, window: int = 0):
+    """(problem renumbered by the library's reverse Cuthill-McKee order, order); window > 0
+    also sorts each window of that many positions by node degree (less slab padding)."""
+    n = problem.xyz.shape[0]
+    order = rafem.rcm_order(problem.conn, n)
+    if window > 0:
+        order = rafem.degree_sort(order, problem.conn, n, window)
     return reorder_nodes(problem, order), order
 
 

@@ -30,12 +30,15 @@ def meshes():
 
 
 @pytest.mark.parametrize("mesh", ["A", "B"])
-@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("reorder", [False, True, "sorted"])
 def test_coupled_steps_match_oracle(torch_cuda, meshes, mesh, reorder):
     from paper_2409_13036_amd.sim import DeviceProblem, rcm_reordered
     p = meshes[mesh]
     ref, _ = Model(p).simulate(3, 1e-15)
-    q, order = rcm_reordered(p) if reorder else (p, np.arange(p.n_nodes))
+    if reorder:
+        q, order = rcm_reordered(p, window=512 if reorder == "sorted" else 0)
+    else:
+        q, order = p, np.arange(p.n_nodes)
     dp = DeviceProblem(q)
     st = dp.mesh.stats()
     for precision in ("fp64", "mixed"):

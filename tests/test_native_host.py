@@ -113,3 +113,16 @@ def test_colouring_of_unstructured_mesh(rafem):
     for c in range(nc):
         nodes = p.conn[col == c].ravel()
         assert np.unique(nodes).size == nodes.size
+
+
+def test_degree_sort_bit_exact_vs_oracle(rafem):
+    from oracle import reorder
+    p = ri.liver_mesh_a()
+    order = reorder.rcm_order(p.conn, p.n_nodes)
+    for w in (1, 64, 512, p.n_nodes + 5):
+        assert np.array_equal(rafem.degree_sort(order, p.conn, p.n_nodes, w),
+                              reorder.degree_sort(order, p.conn, p.n_nodes, w))
+    with pytest.raises(rafem.RafemError, match="E_ARG"):
+        rafem.degree_sort(np.zeros(p.n_nodes, dtype=np.int32), p.conn, p.n_nodes, 64)
+    with pytest.raises(rafem.RafemError, match="E_ARG"):
+        rafem.degree_sort(order, p.conn, p.n_nodes, 0)

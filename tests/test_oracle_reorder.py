@@ -67,3 +67,27 @@ def test_unstructured_bandwidth_matches_scipy(mesh):
     assert bw <= 1.1 * bw_sc
     if mesh.startswith("liver"):   # shuffled node ids: RCM shrinks the bandwidth a lot
         assert bw <= 0.25 * reorder.bandwidth(p.conn, p.n_nodes)
+
+
+def test_degree_sort_windows():
+    p = ri.liver_mesh_a()
+    order = reorder.rcm_order(p.conn, p.n_nodes)
+    w = 256
+    srt = reorder.degree_sort(order, p.conn, p.n_nodes, w)
+    rp, _ = csr_structure(p.conn, p.n_nodes)
+    deg = np.diff(rp) - 1
+    for s in range(0, p.n_nodes, w):
+        a, b = order[s:s + w], srt[s:s + w]
+        assert np.array_equal(np.sort(a), np.sort(b))           # same nodes per window
+        d = deg[b]
+        assert np.all(np.diff(d) >= 0)                           # increasing degree
+        pos = {v: k for k, v in enumerate(a)}                    # ties keep their order
+        for k in range(len(b) - 1):
+            if d[k] == d[k + 1]:
+                assert pos[b[k]] < pos[b[k + 1]]
+    # slabs of 64 rows: fewer padded slots than the plain RCM order
+    def slots(o):
+        dd = np.diff(rp)[o]
+        dd = np.concatenate([dd, np.zeros((-dd.size) % 64, int)]).reshape(-1, 64)
+        return int((dd.max(axis=1) * 64).sum())
+    assert slots(srt) < 0.9 * slots(order)
