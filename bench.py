@@ -108,7 +108,7 @@ def cpu_baseline(n: int) -> dict:
                        f"{r['V_iters']}+{r['T_iters']} iterations) of the {n}^3 hex workload from "
                        f"its initial state, NumPy/SciPy FP64 oracle, 1 thread; mesh setup "
                        f"({r['setup_s']:.1f} s) excluded"),
-            "host_cpus": len(os.sched_getaffinity(0))}
+            "host_cpus": len(os.sched_getaffinity(0)), "host_cpu_count": os.cpu_count()}
 
 
 def run_path(dp, precision: str, steps: int, warmup: int, profile_steps: int, **kw):
@@ -119,11 +119,13 @@ def run_path(dp, precision: str, steps: int, warmup: int, profile_steps: int, **
         dp.step(TOL, precision, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = []
+    infos, marks = [], [t0]
     for _ in range(steps):
         infos.append(dp.step(TOL, precision, **kw))
+        marks.append(time.perf_counter())  # a step ends with a host poll of its last solve
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    dp.step_times = [b - a for a, b in zip(marks, marks[1:])]
     T_end, V_end = dp.T.clone(), dp.V.clone()
     # measurement pass: the same kind of steps again, with every PCG SpMV bracketed by events
     R.profile_enable(dp.mesh, True)
@@ -135,6 +137,17 @@ def run_path(dp, precision: str, steps: int, warmup: int, profile_steps: int, **
     R.profile_enable(dp.mesh, False)
     dp.regions = regions_pass(dp, lambda: dp.step(TOL, precision, **kw), 2)
     return elapsed, infos, (T_end, V_end), (mean_us, count)
+
+
+def step_stats(times) -> dict:
+    """Per-step wall times: median, mean and the half-width of the 99.7% interval of the mean
+    (3 standard errors), in ms."""
+    import statistics
+    ms = [1e3 * t for t in times]
+    mean = statistics.mean(ms)
+    half = 3.0 * statistics.stdev(ms) / len(ms) ** 0.5 if len(ms) > 1 else None
+    return {"median_ms": statistics.median(ms), "mean_ms": mean, "ci997_halfwidth_ms": half,
+            "steps": len(ms)}
 
 
 def regions_pass(dp, step, n):
@@ -755,7 +768,7 @@ def main():
         it_v = float(np.mean([i["V"]["iters"] for i in infos]))
         it_t = float(np.mean([i["T"]["iters"] for i in infos]))
         res[precision] = {"elapsed": el, "state": state, "spmv_us": mean_us, "spmv_count": count,
-                          "regions": dp.regions,
+                          "regions": dp.regions, "step_ms": step_stats(dp.step_times),
                           "V_iters": it_v, "T_iters": it_t,
                           "V_outer": float(np.mean([i["V"]["outer"] for i in infos])),
                           "relres_true_max": max(max(i["V"]["relres_true"], i["T"]["relres_true"])
@@ -817,6 +830,7 @@ def main():
                  "spmv_GBs": spmv_bytes(N, nnz, False) / (res["fp64"]["spmv_us"] * 1e-6) / 1e9
                  if res["fp64"]["spmv_us"] > 0 else None,
                  "relres_true_max": res["fp64"]["relres_true_max"],
+                 "step_ms": res["fp64"]["step_ms"],
                  "regions_ms_per_step": res["fp64"]["regions"]},
         "mixed": {"steps_per_s": args.steps / res["mixed"]["elapsed"],
                   "V_inner_iters": res["mixed"]["V_iters"], "V_outer": res["mixed"]["V_outer"],
@@ -825,6 +839,7 @@ def main():
                   if res["mixed"]["spmv_us"] > 0 else None,
                   "relres_true_max": res["mixed"]["relres_true_max"],
                   "rel_err_vs_fp64": {"T": errT, "V": errV},
+                  "step_ms": res["mixed"]["step_ms"],
                   "regions_ms_per_step": res["mixed"]["regions"]},
     }
     if cpu:

@@ -72,3 +72,12 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_step_stats_interval():
+    import bench
+    s = bench.step_stats([0.010, 0.012, 0.011, 0.013])
+    assert abs(s["median_ms"] - 11.5) < 1e-9 and abs(s["mean_ms"] - 11.5) < 1e-9
+    # 3 sigma / sqrt(n), sigma the sample standard deviation (1.2910 ms)
+    assert abs(s["ci997_halfwidth_ms"] - 3 * 1.2909944487358056 / 2) < 1e-9
+    assert bench.step_stats([0.01])["ci997_halfwidth_ms"] is None
