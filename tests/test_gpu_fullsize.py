@@ -207,3 +207,36 @@ def test_hex101_monolithic_solve_and_newton_step_satisfy_sampled_equations(torch
     scale = (abs(M2) @ np.abs(np.ravel(np.column_stack([T2, V2]))))[idx] + 1.0
     say(f"sampled implicit residual / row scale max {np.abs(R2 / scale).max():.2e}")
     assert np.all(np.abs(R2) <= 1e-7 * scale)
+
+
+def test_hex101_hundred_steps_mixed_tracks_fp64_and_satisfies_oracle_equations(torch_cuda):
+    """The benchmarked 101^3 workload over 100 coupled steps (extrapolated starting points):
+    the mixed state within 1e-8 of the FP64 state at every step, and both paths' 100th step
+    satisfying the oracle's equations of 2,000 sampled rows (given their 99th state)."""
+    from paper_2409_13036_amd.sim import DeviceProblem
+    p = ri.config1(steps=100)
+    runs = {}
+    for precision in ("fp64", "mixed"):
+        dp = DeviceProblem(p)
+        dp.extrapolate = True
+        states = []
+        for _ in range(100):
+            dp.step(TOL, precision)
+            states.append((to_host(dp.T), to_host(dp.V)))
+        dp.close()
+        runs[precision] = states
+        say(f"{precision}: 100 steps done")
+    worst = 0.0
+    for (T6, V6), (Tm, Vm) in zip(runs["fp64"], runs["mixed"]):
+        worst = max(worst, rel_err(Tm, T6), rel_err(Vm, V6))
+    say(f"mixed vs FP64 over 100 steps: max rel err {worst:.2e}")
+    assert worst <= 1e-8
+    free = np.setdiff1d(np.arange(p.n_nodes), p.dir_ids)
+    rows = np.sort(np.random.default_rng(5).choice(free, 2000, replace=False))
+    gV, gT = np.linalg.norm(p.dir_V), np.linalg.norm(p.dir_T)
+    for precision, states in runs.items():
+        T99, (T100, V100) = states[98][0], states[99]
+        rV, sV, rT, sT = _sampled_equations(p, rows, T99, V100, T100)
+        say(f"{precision} step 100: max |rV| {np.abs(rV).max():.2e}, max |rT| {np.abs(rT).max():.2e}")
+        assert np.all(np.abs(rV) <= 10 * TOL * gV + 1e-13 * sV)
+        assert np.all(np.abs(rT) <= 10 * TOL * gT + 1e-13 * sT)
