@@ -275,7 +275,9 @@ def _counter_rows(d: str, counter: str):
 
 
 def _short_kernel(name: str) -> str:
+    import re
     n = name.replace("(anonymous namespace)::", "").replace("rafem::", "").replace("void ", "")
+    n = re.sub(r"HIP_vector_type<(\w+), (\d)u>", r"\1\2", n)
     return n.split("(")[0][:48]
 
 
