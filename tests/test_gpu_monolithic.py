@@ -198,3 +198,33 @@ def test_newton_with_mixed_gmres_matches_oracle(torch_cuda, kind, n):
           f"{rel_err(Tg, ref.T):.2e} V {rel_err(Vg, ref.V):.2e}", flush=True)
     assert info["accepted"] == 1 and abs(info["iters"] - ref.iters) <= 1
     assert rel_err(Tg, ref.T) <= 1e-8 and rel_err(Vg, ref.V) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gmres_edge_cases(torch_cuda, precision):
+    """A Krylov space exhausted within one cycle (hex 5^3: 27 free nodes, 54 free unknowns,
+    m = 100 > 54) solves exactly; the iteration limit returns E_NOCONV with a reduced but
+    unconverged residual; m = 1 (restarted minimal residual) still converges."""
+    from paper_2409_13036_amd import _lib as R
+    p = ri.make_problem("hex", 5, 4)
+    m = Model(p)
+    T, V = _state(p, m, seed=2)
+    T0 = p.initial_T()
+    dp = _device_problem(p)
+    args = (dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, to_dev(T0), to_dev(T), to_dev(V))
+    J = mono.interleaved_matrix(m, mono.jacobian_blocks(m, T0, DT, T, V))
+    b = -mono.residual(m, T0, DT, T, V)
+    x = np.linalg.solve(J.toarray(), b)
+    d, info, _ = R.mono_solve(*args, m=100, tol=1e-12, precision=precision)
+    assert info["status"] == 0 and info["cycles"] == 1 + (precision == "mixed")
+    assert info["iters"] <= 54 * (1 + (precision == "mixed"))
+    assert rel_err(to_host(d), x) <= 1e-9
+    d, info, _ = R.mono_solve(*args, m=10, tol=1e-12, max_iters=5, precision=precision,
+                              check=False)
+    assert info["status"] == R.E_NOCONV and info["iters"] == 5
+    rr = np.linalg.norm(b - J @ to_host(d)) / np.linalg.norm(b)
+    assert 1e-12 < rr < 1.0 and abs(rr - info["relres_true"]) <= 1e-6 * rr
+    d, info, _ = R.mono_solve(*args, m=1, tol=1e-8, max_iters=20000, precision=precision)
+    assert info["status"] == 0 and info["cycles"] == info["iters"]
+    assert np.linalg.norm(b - J @ to_host(d)) <= 1.0001e-8 * np.linalg.norm(b)
+    dp.close()
