@@ -294,24 +294,36 @@ __device__ __forceinline__ double2 basis(const GmV<X2>& a, int i, int node) {
     return ld2(a.V[(int64_t)i * a.ldv + node]);
 }
 
-// part[i] = V_i . w (i < k)
-template <typename X2>
+// part[i] = V_i . w (i < k); NPT nodes per thread (one wavefront sum per vector covers
+// 64 NPT nodes).
+template <typename X2, int NPT>
 __global__ __launch_bounds__(WG) void k_gm_dots(GmV<X2> a, int k, const X2* __restrict__ w) {
     if (cycle_over(a.st)) return;
     __shared__ double lds[kGmMaxM + 2][NWAVES];
     const int nb = gridDim.x;
     const int blk = xcd_block(blockIdx.x, nb);
-    const int i = blk * WG + threadIdx.x;
-    const bool in = i < a.n;
-    const double2 wv = in ? ld2(w[i]) : make_double2(0.0, 0.0);
-    for (int i0 = 0; i0 < k; i0 += kChunk) {
-        double2 v[kChunk];
+    const int i0 = blk * WG * NPT + threadIdx.x;
+    double2 wv[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q)
+        wv[q] = i0 + q * WG < a.n ? ld2(w[i0 + q * WG]) : make_double2(0.0, 0.0);
+    for (int c0 = 0; c0 < k; c0 += kChunk) {
+        double2 v[kChunk][NPT];
 #pragma unroll
         for (int u = 0; u < kChunk; ++u)
-            v[u] = (in && i0 + u < k) ? basis(a, i0 + u, i) : make_double2(0.0, 0.0);
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u)
-            if (i0 + u < k) wave_to_lds(lds, i0 + u, v[u].x * wv.x + v[u].y * wv.y);
+            for (int q = 0; q < NPT; ++q)
+                v[u][q] = (c0 + u < k && i0 + q * WG < a.n) ? basis(a, c0 + u, i0 + q * WG)
+                                                            : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            if (c0 + u < k) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < NPT; ++q) t += v[u][q].x * wv[q].x + v[u][q].y * wv[q].y;
+                wave_to_lds(lds, c0 + u, t);
+            }
+        }
     }
     store_rows(lds, k, a.part, nb, blk);
 }
@@ -328,63 +340,109 @@ __global__ __launch_bounds__(WG) void k_gm_sum(const double* __restrict__ part, 
 }
 
 // w <- w - sum_i h1[i] V_i;  part[i] = V_i . w (i < k), part[k] = w . w.  KC > 0 keeps the
-// basis values of the thread's node in registers between the two loops (k <= KC).
-template <int KC, typename X2>
+// basis values of the thread's NPT nodes in registers between the two loops (k <= KC).
+template <int KC, typename X2, int NPT>
 __global__ __launch_bounds__(WG) void k_gm_orth(GmV<X2> a, int k, const double* __restrict__ h1,
                                                 X2* __restrict__ w) {
     if (cycle_over(a.st)) return;
     __shared__ double lds[kGmMaxM + 2][NWAVES];
     const int nb = gridDim.x;
     const int blk = xcd_block(blockIdx.x, nb);
-    const int i = blk * WG + threadIdx.x;
-    const bool in = i < a.n;
-    double2 wv = in ? ld2(w[i]) : make_double2(0.0, 0.0);
+    const int i0 = blk * WG * NPT + threadIdx.x;
+    bool in[NPT];
+    double2 wv[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        in[q] = i0 + q * WG < a.n;
+        wv[q] = in[q] ? ld2(w[i0 + q * WG]) : make_double2(0.0, 0.0);
+    }
     if constexpr (KC > 0) {
-        double2 v[KC];
+        X2 v[KC][NPT];  // raw basis values (float2 for the FP32 basis)
 #pragma unroll
         for (int u = 0; u < KC; ++u)
-            v[u] = (in && u < k) ? basis(a, u, i) : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < NPT; ++q) {
+                if (u < k && in[q]) v[u][q] = a.V[(int64_t)u * a.ldv + i0 + q * WG];
+                else v[u][q].x = v[u][q].y = 0;
+            }
 #pragma unroll
         for (int u = 0; u < KC; ++u) {
             if (u < k) {
                 const double h = h1[u];
-                wv.x -= h * v[u].x;
-                wv.y -= h * v[u].y;
-            }
-        }
-        wv = kept<X2>(wv);  // the dots below use the stored w'
-        if (in) st2(&w[i], wv);
 #pragma unroll
-        for (int u = 0; u < KC; ++u)
-            if (u < k) wave_to_lds(lds, u, v[u].x * wv.x + v[u].y * wv.y);
-    } else {
-        for (int i0 = 0; i0 < k; i0 += kChunk) {
-            double2 v[kChunk];
-#pragma unroll
-            for (int u = 0; u < kChunk; ++u)
-                v[u] = (in && i0 + u < k) ? basis(a, i0 + u, i) : make_double2(0.0, 0.0);
-#pragma unroll
-            for (int u = 0; u < kChunk; ++u) {
-                if (i0 + u < k) {
-                    const double h = h1[i0 + u];
-                    wv.x -= h * v[u].x;
-                    wv.y -= h * v[u].y;
+                for (int q = 0; q < NPT; ++q) {
+                    const double2 b = ld2(v[u][q]);
+                    wv[q].x -= h * b.x;
+                    wv[q].y -= h * b.y;
                 }
             }
         }
-        wv = kept<X2>(wv);
-        if (in) st2(&w[i], wv);
-        for (int i0 = 0; i0 < k; i0 += kChunk) {
-            double2 v[kChunk];
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+            wv[q] = kept<X2>(wv[q]);  // the dots below use the stored w'
+            if (in[q]) st2(&w[i0 + q * WG], wv[q]);
+        }
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+            if (u < k) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < NPT; ++q) {
+                    const double2 b = ld2(v[u][q]);
+                    t += b.x * wv[q].x + b.y * wv[q].y;
+                }
+                wave_to_lds(lds, u, t);
+            }
+        }
+    } else {
+        for (int c0 = 0; c0 < k; c0 += kChunk) {
+            double2 v[kChunk][NPT];
 #pragma unroll
             for (int u = 0; u < kChunk; ++u)
-                v[u] = (in && i0 + u < k) ? basis(a, i0 + u, i) : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int q = 0; q < NPT; ++q)
+                    v[u][q] = (c0 + u < k && in[q]) ? basis(a, c0 + u, i0 + q * WG)
+                                                    : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                if (c0 + u < k) {
+                    const double h = h1[c0 + u];
+#pragma unroll
+                    for (int q = 0; q < NPT; ++q) {
+                        wv[q].x -= h * v[u][q].x;
+                        wv[q].y -= h * v[u][q].y;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+            wv[q] = kept<X2>(wv[q]);
+            if (in[q]) st2(&w[i0 + q * WG], wv[q]);
+        }
+        for (int c0 = 0; c0 < k; c0 += kChunk) {
+            double2 v[kChunk][NPT];
 #pragma unroll
             for (int u = 0; u < kChunk; ++u)
-                if (i0 + u < k) wave_to_lds(lds, i0 + u, v[u].x * wv.x + v[u].y * wv.y);
+#pragma unroll
+                for (int q = 0; q < NPT; ++q)
+                    v[u][q] = (c0 + u < k && in[q]) ? basis(a, c0 + u, i0 + q * WG)
+                                                    : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                if (c0 + u < k) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NPT; ++q) t += v[u][q].x * wv[q].x + v[u][q].y * wv[q].y;
+                    wave_to_lds(lds, c0 + u, t);
+                }
+            }
         }
     }
-    wave_to_lds(lds, k, wv.x * wv.x + wv.y * wv.y);
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) t += wv[q].x * wv[q].x + wv[q].y * wv[q].y;
+    wave_to_lds(lds, k, t);
     store_rows(lds, k + 1, a.part, nb, blk);
 }
 
@@ -430,20 +488,33 @@ __global__ __launch_bounds__(WG) void k_gm_next(GmV<X2> a, int k, const double* 
 // Hessenberg column j = (h1 + h2, h_{j+1,j}), earlier rotations, a new rotation, the
 // rotated right-hand side and the residual estimate; ends the cycle when the estimate
 // meets the tolerance, at the last column, on breakdown or at the iteration limit.
-__global__ void k_gm_givens(GmSmall sm, int j, const double* __restrict__ h1,
-                            const double* __restrict__ h2, GmState* st) {
-    if (threadIdx.x != 0 || cycle_over(st)) return;
+__global__ __launch_bounds__(WAVE) void k_gm_givens(GmSmall sm, int j,
+                                                    const double* __restrict__ h1,
+                                                    const double* __restrict__ h2, GmState* st) {
+    if (cycle_over(st)) return;
+    // the column, its second-pass part and the earlier rotations, loaded by all lanes at once
+    __shared__ double col[kGmMaxM + 2], sec[kGmMaxM + 2], cs[kGmMaxM], sn[kGmMaxM];
+    for (int i = threadIdx.x; i <= j + 1; i += WAVE) {
+        const double b = h2[i];  // h2[j + 1] is ||w'||^2
+        sec[i] = b;
+        if (i <= j) col[i] = h1[i] + b;
+    }
+    for (int i = threadIdx.x; i < j; i += WAVE) {
+        cs[i] = sm.cs[i];
+        sn[i] = sm.sn[i];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     const int ld = sm.ldh;
     double* Hj = sm.H + (int64_t)j * ld;
-    for (int i = 0; i <= j; ++i) Hj[i] = h1[i] + h2[i];
-    const double hn = next_norm(h2, j + 1);
-    Hj[j + 1] = hn;
+    const double hn = next_norm(sec, j + 1);  // the same sum, in the same order, as k_gm_next
+    col[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
-        const double t = sm.cs[i] * Hj[i] + sm.sn[i] * Hj[i + 1];
-        Hj[i + 1] = -sm.sn[i] * Hj[i] + sm.cs[i] * Hj[i + 1];
-        Hj[i] = t;
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
     }
-    const double den = hypot(Hj[j], Hj[j + 1]);
+    const double den = hypot(col[j], col[j + 1]);
     st->iters += 1;
     if (!(den > 0.0) || !isfinite(den)) {
         st->status = RAFEM_E_BREAKDOWN;
@@ -451,13 +522,16 @@ __global__ void k_gm_givens(GmSmall sm, int j, const double* __restrict__ h1,
         st->cyc_done = 1;
         return;
     }
-    sm.cs[j] = Hj[j] / den;
-    sm.sn[j] = Hj[j + 1] / den;
+    const double c = col[j] / den, sj = col[j + 1] / den;
+    sm.cs[j] = c;
+    sm.sn[j] = sj;
+    for (int i = 0; i < j; ++i) Hj[i] = col[i];
     Hj[j] = den;
     Hj[j + 1] = 0.0;
-    sm.g[j + 1] = -sm.sn[j] * sm.g[j];
-    sm.g[j] = sm.cs[j] * sm.g[j];
-    const double est = fabs(sm.g[j + 1]);
+    const double gj = sm.g[j];
+    sm.g[j + 1] = -sj * gj;
+    sm.g[j] = c * gj;
+    const double est = fabs(sj * gj);
     st->est = est;
     if (st->iters <= sm.hist_cap && sm.hist) sm.hist[st->iters - 1] = est / st->bnorm;
     if (est <= st->tol * st->bnorm || st->iters >= st->maxit || j + 1 == st->m || hn == 0.0) {
@@ -466,10 +540,31 @@ __global__ void k_gm_givens(GmSmall sm, int j, const double* __restrict__ h1,
     }
 }
 
-// y = H(0:k, 0:k)^-1 g(0:k), k = the cycle's steps (back substitution).
-__global__ void k_gm_solve_y(GmSmall sm, const GmState* st) {
-    if (threadIdx.x != 0 || st->solved) return;
+// y = H(0:k, 0:k)^-1 g(0:k), k = the cycle's steps (back substitution).  Up to
+// kStageY steps the triangle is first loaded into LDS by all threads.
+constexpr int kStageY = 64;
+
+__global__ __launch_bounds__(WG) void k_gm_solve_y(GmSmall sm, const GmState* st) {
+    if (st->solved) return;
     const int k = st->jdone;
+    if (k <= kStageY) {
+        __shared__ double H[kStageY][kStageY + 1], g[kStageY], y[kStageY];
+        for (int t = threadIdx.x; t < k * k; t += WG) {
+            const int l = t / k, i = t % k;  // column l, row i
+            if (i <= l) H[i][l] = sm.H[(int64_t)l * sm.ldh + i];
+        }
+        for (int t = threadIdx.x; t < k; t += WG) g[t] = sm.g[t];
+        __syncthreads();
+        if (threadIdx.x != 0) return;
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int l = i + 1; l < k; ++l) s -= H[i][l] * y[l];
+            y[i] = s / H[i][i];
+            sm.y[i] = y[i];
+        }
+        return;
+    }
+    if (threadIdx.x != 0) return;
     for (int i = k - 1; i >= 0; --i) {
         double s = sm.g[i];
         for (int l = i + 1; l < k; ++l) s -= sm.H[(int64_t)l * sm.ldh + i] * sm.y[l];
@@ -679,14 +774,17 @@ void launch_gm_init(GmState* st, double tol, int maxit, int m, hipStream_t s) {
     hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(64), 0, s, st, tol, maxit, m);
 }
 
-void launch_gm_dots(const GmVec& a, int k, const void* w, hipStream_t s) {
-    const dim3 g(grid1(a.n)), b(WG);
+// One node per thread for both bases (two nodes per thread for the FP32 basis, halving the
+// wavefront sums per byte, measured no faster at m = 20 and slower for longer bases).
+int launch_gm_dots(const GmVec& a, int k, const void* w, hipStream_t s) {
+    const int nb = grid1(a.n);
     if (a.fp32)
-        hipLaunchKernelGGL(k_gm_dots<float2>, g, b, 0, s, gmv<float2>(a), k,
+        hipLaunchKernelGGL((k_gm_dots<float2, 1>), dim3(nb), dim3(WG), 0, s, gmv<float2>(a), k,
                            static_cast<const float2*>(w));
     else
-        hipLaunchKernelGGL(k_gm_dots<double2>, g, b, 0, s, gmv<double2>(a), k,
+        hipLaunchKernelGGL((k_gm_dots<double2, 1>), dim3(nb), dim3(WG), 0, s, gmv<double2>(a), k,
                            static_cast<const double2*>(w));
+    return nb;
 }
 
 void launch_gm_sum(const double* part, int nb, int rows, double* out, const GmState* st,
@@ -694,20 +792,24 @@ void launch_gm_sum(const double* part, int nb, int rows, double* out, const GmSt
     hipLaunchKernelGGL(k_gm_sum, dim3(rows), dim3(WG), 0, s, part, nb, out, st);
 }
 
-template <typename X2>
-void orth_kc(const GmVec& a, int k, const double* h1, void* w, hipStream_t s) {
-    const dim3 g(grid1(a.n)), b(WG);
+template <typename X2, int NPT>
+int orth_kc(const GmVec& a, int k, const double* h1, void* w, hipStream_t s) {
+    const int nb = grid1((a.n + NPT - 1) / NPT);
+    const dim3 g(nb), b(WG);
     const GmV<X2> v = gmv<X2>(a);
     X2* w2 = static_cast<X2*>(w);
-    if (k <= 8) hipLaunchKernelGGL((k_gm_orth<8, X2>), g, b, 0, s, v, k, h1, w2);
-    else if (k <= 16) hipLaunchKernelGGL((k_gm_orth<16, X2>), g, b, 0, s, v, k, h1, w2);
-    else if (k <= 32) hipLaunchKernelGGL((k_gm_orth<32, X2>), g, b, 0, s, v, k, h1, w2);
-    else hipLaunchKernelGGL((k_gm_orth<0, X2>), g, b, 0, s, v, k, h1, w2);
+    // register caches up to 32 values per node and thread; longer bases are read twice
+    constexpr int kMaxCache = NPT == 1 ? 32 : 16;
+    if (k <= 8) hipLaunchKernelGGL((k_gm_orth<8, X2, NPT>), g, b, 0, s, v, k, h1, w2);
+    else if (k <= 16) hipLaunchKernelGGL((k_gm_orth<16, X2, NPT>), g, b, 0, s, v, k, h1, w2);
+    else if (k <= kMaxCache) hipLaunchKernelGGL((k_gm_orth<32, X2, NPT>), g, b, 0, s, v, k, h1, w2);
+    else hipLaunchKernelGGL((k_gm_orth<0, X2, NPT>), g, b, 0, s, v, k, h1, w2);
+    return nb;
 }
 
-void launch_gm_orth(const GmVec& a, int k, const double* h1, void* w, hipStream_t s) {
-    if (a.fp32) orth_kc<float2>(a, k, h1, w, s);
-    else orth_kc<double2>(a, k, h1, w, s);
+int launch_gm_orth(const GmVec& a, int k, const double* h1, void* w, hipStream_t s) {
+    if (a.fp32) return orth_kc<float2, 1>(a, k, h1, w, s);
+    return orth_kc<double2, 1>(a, k, h1, w, s);
 }
 
 void launch_gm_next(const GmVec& a, int k, const double* h2, const void* w, const void* binv,
@@ -725,11 +827,11 @@ void launch_gm_next(const GmVec& a, int k, const double* h2, const void* w, cons
 
 void launch_gm_givens(const GmSmall& sm, int j, const double* h1, const double* h2, GmState* st,
                       hipStream_t s) {
-    hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(64), 0, s, sm, j, h1, h2, st);
+    hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(WAVE), 0, s, sm, j, h1, h2, st);
 }
 
 void launch_gm_solve_y(const GmSmall& sm, const GmState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_gm_solve_y, dim3(1), dim3(64), 0, s, sm, st);
+    hipLaunchKernelGGL(k_gm_solve_y, dim3(1), dim3(WG), 0, s, sm, st);
 }
 
 void launch_gm_xupdate(const GmVec& a, const double* y, const double* binv, double* delta,

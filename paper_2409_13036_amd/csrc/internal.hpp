@@ -340,10 +340,12 @@ int gm_blocks(int n);  // workgroups (= partial slots) of the per-node GMRES ker
 void launch_gm_init(GmState* st, double tol, int maxit, int m, hipStream_t s);
 // Vector arguments (w, z, r, binv) have the basis' precision (fp32: float2 / float4), except
 // in launch_gm_xupdate (delta, binv: FP64) and launch_gm_resid (b, w, r: FP64).
-void launch_gm_dots(const GmVec& a, int k, const void* w, hipStream_t s);
+// launch_gm_dots / launch_gm_orth return the number of partial slots they wrote (the nb
+// of the launch_gm_sum that reduces them).
+int launch_gm_dots(const GmVec& a, int k, const void* w, hipStream_t s);
 void launch_gm_sum(const double* part, int nb, int rows, double* out, const GmState* st,
                    hipStream_t s);
-void launch_gm_orth(const GmVec& a, int k, const double* h1, void* w, hipStream_t s);
+int launch_gm_orth(const GmVec& a, int k, const double* h1, void* w, hipStream_t s);
 void launch_gm_next(const GmVec& a, int k, const double* h2, const void* w, const void* binv,
                     void* z, hipStream_t s);
 void launch_gm_givens(const GmSmall& sm, int j, const double* h1, const double* h2, GmState* st,

@@ -220,10 +220,10 @@ rafem_status gmres_solve(rafem_mesh m, const double* b, double* x, const GmresOp
         for (int j = 0; j < o.m; ++j) {
             const int k = j + 1;
             launch_bsell(A, s);
-            launch_gm_dots(a, k, m->gm_w, s);
-            launch_gm_sum(m->gm_part, nb, k, sa.h1, m->gm_st, s);
-            launch_gm_orth(a, k, sa.h1, m->gm_w, s);
-            launch_gm_sum(m->gm_part, nb, k + 1, sa.h2, m->gm_st, s);
+            const int nb1 = launch_gm_dots(a, k, m->gm_w, s);
+            launch_gm_sum(m->gm_part, nb1, k, sa.h1, m->gm_st, s);
+            const int nb2 = launch_gm_orth(a, k, sa.h1, m->gm_w, s);
+            launch_gm_sum(m->gm_part, nb2, k + 1, sa.h2, m->gm_st, s);
             if (k < o.m) launch_gm_next(a, k, sa.h2, m->gm_w, binv_k, m->gm_z, s);
             launch_gm_givens(sa.sm, j, sa.h1, sa.h2, m->gm_st, s);
         }
