@@ -323,6 +323,10 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             m->pc_Tn = dalloc<double>(m, N);
             m->pc_Vn = dalloc<double>(m, N);
             m->pc_Tk = dalloc<double>(m, N);
+            for (int k = 0; k < 2; ++k) {  // extrapolation histories (phys->extrapolate)
+                m->xg_T[k] = dalloc<double>(m, N);
+                m->xg_V[k] = dalloc<double>(m, N);
+            }
             m->pc_norm = dalloc<double>(m, 2);
             m->bT = dalloc<double>(m, N);
             m->r = dalloc<double>(m, N);
@@ -922,11 +926,6 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
         // keep (T^n, V^n); start the solves from their extrapolation when the previous call
         // left (T^{n-1}, V^{n-1})
         if (phys->extrapolate == 2) m->xg_ready = false;
-        if (!m->xg_T[0])
-            for (int k = 0; k < 2; ++k) {
-                m->xg_T[k] = dalloc<double>(m, m->n);
-                m->xg_V[k] = dalloc<double>(m, m->n);
-            }
         const size_t bytes = (size_t)m->n * sizeof(double);
         double* Tn = m->xg_T[m->xg_cur];
         double* Vn = m->xg_V[m->xg_cur];

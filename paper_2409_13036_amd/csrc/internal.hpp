@@ -420,7 +420,7 @@ struct rafem_mesh_s {
     // and the two sums of the change norm
     double *pc_Tn = nullptr, *pc_Vn = nullptr, *pc_Tk = nullptr, *pc_norm = nullptr;
     // extrapolated starting points of rafem_step (phys->extrapolate): the states at the start
-    // of the last two calls (slot xg_cur receives the next), allocated on first use
+    // of the last two calls (slot xg_cur receives the next)
     double *xg_T[2] = {nullptr, nullptr}, *xg_V[2] = {nullptr, nullptr};
     int xg_cur = 0;
     bool xg_ready = false;
