@@ -177,14 +177,50 @@ void assemble_into(rafem_mesh m, const Layout& L, int64_t count, const double* m
     }
 }
 
+// Arguments of the row-wise assembly of one step-path matrix on the SELL layout.
+RowAsm row_asm(rafem_mesh m, const double* mass, const double* stiff, const double* gnode,
+               double* vals, float* vals32, double* lift, double* dinv, float* dinv32) {
+    RowAsm a;
+    a.n = (int)m->n;
+    a.nslabs = m->nslabs;
+    a.sptr = m->sptr;
+    a.scol = m->scol;
+    a.n2e_ptr = m->n2e_ptr;
+    a.n2e = m->n2e;
+    a.r2j = m->r2j;
+    a.dmask = m->dmask;
+    a.jdiag = m->jdiag;
+    a.conn = m->conn;
+    a.xyz = m->xyz;
+    a.geo = m->geo;
+    a.mass = mass;
+    a.stiff = stiff;
+    a.isD = m->isD;
+    a.gnode = gnode;
+    a.do_lift = m->nD > 0;
+    a.vals = vals;
+    a.vals32 = vals32;
+    a.lift = lift;
+    a.dinv = dinv;
+    a.dinv32 = dinv32;
+    return a;
+}
+
 // Bioheat matrix sum_e (rho_c/dt + w_e) M_e + k_e K_e, lifted with the values in m->gT.
 void assemble_bioheat(rafem_mesh m, const rafem_phys* phys, const double* k_e,
                       const double* perf_e, hipStream_t s) {
     const Layout SL = sell_layout(m);
     launch_coef(perf_e, phys->rho_c / phys->dt, m->coefT, m->E, s);
-    assemble_into(m, SL, m->sell_nnz, m->coefT, k_e, m->valsT, s);
-    launch_lift((int)m->n, SL, m->valsT, m->valsT32, m->isD, m->gT, m->liftT, m->dinvT,
-                m->dinvT32, m->nD > 0, s);
+    if (m->row_asm) {
+        launch_assemble_rows(m->npe, m->affine,
+                             row_asm(m, m->coefT, k_e, m->gT, m->valsT, m->valsT32, m->liftT,
+                                     m->dinvT, m->dinvT32),
+                             s);
+    } else {
+        assemble_into(m, SL, m->sell_nnz, m->coefT, k_e, m->valsT, s);
+        launch_lift((int)m->n, SL, m->valsT, m->valsT32, m->isD, m->gT, m->liftT, m->dinvT,
+                    m->dinvT32, m->nD > 0, s);
+    }
     m->bioheat_ready = true;
     m->bioheat_dt = phys->dt;
 }
@@ -194,9 +230,16 @@ void assemble_potential(rafem_mesh m, const rafem_phys* phys, const double* sigm
                         const double* T, hipStream_t s) {
     const Layout SL = sell_layout(m);
     launch_sigma(m->npe, m->E, m->conn, T, sigma0_e, phys->alpha_sigma, phys->T_ref, m->sigma, s);
-    assemble_into(m, SL, m->sell_nnz, nullptr, m->sigma, m->valsV, s);
-    launch_lift((int)m->n, SL, m->valsV, m->valsV32, m->isD, m->gV, m->liftV, m->dinvV,
-                m->dinvV32, m->nD > 0, s);
+    if (m->row_asm) {
+        launch_assemble_rows(m->npe, m->affine,
+                             row_asm(m, nullptr, m->sigma, m->gV, m->valsV, m->valsV32, m->liftV,
+                                     m->dinvV, m->dinvV32),
+                             s);
+    } else {
+        assemble_into(m, SL, m->sell_nnz, nullptr, m->sigma, m->valsV, s);
+        launch_lift((int)m->n, SL, m->valsV, m->valsV32, m->isD, m->gV, m->liftV, m->dinvV,
+                    m->dinvV32, m->nD > 0, s);
+    }
     m->potential_ready = true;
 }
 
@@ -385,6 +428,40 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             m->sample_info.assign(S_, rafem_step_info{});
             m->use_graphs = S_ > 1;
             launch_slot_map(m->E, m->npe, m->conn, sell_layout(m), m->e2s, nullptr);
+            int32_t max_w = 0;
+            for (int64_t b = 0; b < SL.nslabs; ++b)
+                max_w = std::max(max_w, (SL.sptr[b + 1] - SL.sptr[b]) / 64);
+            if (max_w <= kRowAsmMaxW) {
+                std::vector<int32_t> nptr, nlist;
+                node_elements(n_nodes, n_elems, npe, conn_h, nptr, nlist);
+                m->n2e_ptr = dalloc<int32_t>(m, N + 1);
+                m->n2e = dalloc<int32_t>(m, nlist.size());
+                m->r2j = dalloc<uint8_t>(m, nlist.size() * (size_t)npe);
+                RAFEM_HIP(hipMemcpy(m->n2e_ptr, nptr.data(), (N + 1) * 4, hipMemcpyHostToDevice));
+                RAFEM_HIP(hipMemcpy(m->n2e, nlist.data(), nlist.size() * 4,
+                                    hipMemcpyHostToDevice));
+                launch_row_slots((int)m->n, npe, m->n2e_ptr, m->n2e, m->e2s, m->sptr, m->r2j,
+                                 nullptr);
+                std::vector<uint32_t> dmask(N, 0u);
+                std::vector<uint8_t> jdiag(N, 255);  // 255: no diagonal entry
+                for (int64_t r = 0; r < n_nodes; ++r) {
+                    const int64_t b0 = SL.sptr[r / 64] + r % 64;
+                    for (int j = 0; j < SL.rlen[r]; ++j) {
+                        const int32_t c = SL.scol[b0 + (int64_t)j * 64];
+                        if (isD[c]) dmask[r] |= 1u << j;
+                        if (c == r) jdiag[r] = (uint8_t)j;
+                    }
+                }
+                m->dmask = dalloc<uint32_t>(m, N);
+                m->jdiag = dalloc<uint8_t>(m, N);
+                RAFEM_HIP(hipMemcpy(m->dmask, dmask.data(), N * 4, hipMemcpyHostToDevice));
+                RAFEM_HIP(hipMemcpy(m->jdiag, jdiag.data(), N, hipMemcpyHostToDevice));
+                if (npe == 4 || m->affine) {
+                    m->geo = dalloc<double>(m, E * (npe == 8 ? kGeoHex : kGeoTet));
+                    launch_elem_geo(m->E, npe, m->conn, m->xyz, m->geo, nullptr);
+                }
+                m->row_asm = true;
+            }
             // The slab padding of the FP32 values is read by the FP32 SpMV (column = own
             // row) but never written by assembly or lifting: it must hold zeros.  (The FP64
             // values are cleared in full before every assembly.)

@@ -251,16 +251,21 @@ __device__ __forceinline__ double hex_affine_jacobian(const double (&X)[8][3],
     return det;
 }
 
-__device__ inline void hex_rows_affine(const double (&X)[8][3], int a, double (&Kr)[8],
-                                double (&Mr)[8]) {
+// C = detJ J^-1 J^-T of a parallelepiped hex; returns detJ.
+__device__ __forceinline__ double hex_affine_metric(const double (&X)[8][3], double (&C)[3][3]) {
     double Ji[3][3];
     const double det = hex_affine_jacobian(X, Ji);
-    double C[3][3];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int e = 0; e < 3; ++e)
             C[d][e] = det * (Ji[d][0] * Ji[e][0] + Ji[d][1] * Ji[e][1] + Ji[d][2] * Ji[e][2]);
+    return det;
+}
+
+// Row a of K_e and M_e of a parallelepiped hex from its metric C and detJ.
+__device__ __forceinline__ void hex_rows_metric(const double (&C)[3][3], double det, int a,
+                                                double (&Kr)[8], double (&Mr)[8]) {
     const double sa[3] = {hsx(a), hsy(a), hsz(a)};
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -286,6 +291,13 @@ __device__ inline void hex_rows_affine(const double (&X)[8][3], int a, double (&
         Kr[b] = k_ab;
         Mr[b] = det * pk[0] * pk[1] * pk[2] * (1.0 / 64.0);
     }
+}
+
+__device__ inline void hex_rows_affine(const double (&X)[8][3], int a, double (&Kr)[8],
+                                double (&Mr)[8]) {
+    double C[3][3];
+    const double det = hex_affine_metric(X, C);
+    hex_rows_metric(C, det, a, Kr, Mr);
 }
 
 // Tet: volume and constant gradients of the barycentric coordinates.

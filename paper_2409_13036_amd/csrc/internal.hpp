@@ -50,6 +50,10 @@ struct HostSell {
 // row_off: sample boundaries ({0, n} for one mesh); no slab offset crosses them.
 HostSell build_sell(const HostStructure& S, int64_t n, const std::vector<int64_t>& row_off);
 
+// Node -> element incidences as CSR by node: list[k] = e npe + a (conn[e][a] = node), elements
+// ascending.
+void node_elements(int64_t n, int64_t E, int npe, const int32_t* conn, std::vector<int32_t>& ptr,
+                   std::vector<int32_t>& list);
 // Throws Error on bad input.
 void check_conn(int64_t n_nodes, int64_t n_elems, int npe, const int32_t* conn);
 HostStructure build_structure(int64_t n_nodes, int64_t n_elems, int npe, const int32_t* conn);
@@ -216,6 +220,37 @@ void launch_assemble_colour(int npe, int affine, const int32_t* elems, int count
                             double* vals, hipStream_t s);
 void launch_slot_map(int64_t E, int npe, const int32_t* conn, const Layout& L, int32_t* e2s,
                      hipStream_t s);
+// Row-wise assembly on the SELL layout (slabs at most kRowAsmMaxW wide): one wavefront per
+// slab, one lane per row, the row's values summed over the node's incident elements in
+// LDS, then lifted (as launch_lift), copied to FP32 and written once.  r2j[k npe + b] is the
+// entry index within its row of column conn[e][b] for incidence k = (e, a) of the row.
+constexpr int kRowAsmMaxW = 32;
+// Doubles per element of the geometric constants (parallelepiped hex, tet).
+constexpr int kGeoHex = 8, kGeoTet = 16;
+struct RowAsm {
+    int n = 0, nslabs = 0;
+    const int32_t *sptr = nullptr, *scol = nullptr;
+    const int32_t *n2e_ptr = nullptr, *n2e = nullptr;
+    const uint8_t* r2j = nullptr;
+    const uint32_t* dmask = nullptr;  // per row: bit j set when entry j is in a Dirichlet column
+    const uint8_t* jdiag = nullptr;   // per row: index of the diagonal entry
+    const int32_t* conn = nullptr;
+    const double* xyz = nullptr;
+    const double* geo = nullptr;  // geometric constants (tets and parallelepiped hexes)
+    const double *mass = nullptr, *stiff = nullptr;
+    const uint8_t* isD = nullptr;
+    const double* gnode = nullptr;
+    int do_lift = 0;
+    double* vals = nullptr;
+    float* vals32 = nullptr;
+    double *lift = nullptr, *dinv = nullptr;
+    float* dinv32 = nullptr;
+};
+void launch_row_slots(int n, int npe, const int32_t* n2e_ptr, const int32_t* n2e,
+                      const int32_t* e2s, const int32_t* sptr, uint8_t* r2j, hipStream_t s);
+void launch_elem_geo(int64_t E, int npe, const int32_t* conn, const double* xyz, double* geo,
+                     hipStream_t s);
+void launch_assemble_rows(int npe, int affine, const RowAsm& a, hipStream_t s);
 // Lifting with per-node Dirichlet mask/values; writes lifted vals, vals32, lift, dinv, dinv32.
 void launch_lift(int n, const Layout& L, double* vals, float* vals32, const uint8_t* isD,
                  const double* gnode, double* lift, double* dinv, float* dinv32, int do_lift,
@@ -397,6 +432,14 @@ struct rafem_mesh_s {
     int32_t* scol = nullptr;  // SELL column ids
     int32_t* rlen = nullptr;  // SELL row lengths
     int32_t* e2s = nullptr;   // value position in the SELL layout of every (element, a, b)
+    // row-wise assembly (every slab at most kRowAsmMaxW wide): node -> element incidences and
+    // the entry index of every (incidence, b) within its row
+    bool row_asm = false;
+    int32_t *n2e_ptr = nullptr, *n2e = nullptr;
+    uint8_t* r2j = nullptr;
+    uint32_t* dmask = nullptr;
+    uint8_t* jdiag = nullptr;
+    double* geo = nullptr;    // per-element geometric constants of the row-wise assembly
     int affine = 0;           // every hex is a parallelepiped
     int16_t* sdel = nullptr;  // SELL column - row offsets (NULL when the bandwidth exceeds int16)
     int32_t* sofs = nullptr;  // [nslabs] start of a shared-offset slab's list in soff, or -1

@@ -118,6 +118,150 @@ __global__ __launch_bounds__(WG) void k_slot_map(int64_t E, int npe, const int* 
         e2s[t * npe + b] = find_slot(L.cols, start, len, stride, conn[e * npe + b]);
 }
 
+// Entry index within row i of every column of every incident element row (from e2s).
+__global__ __launch_bounds__(WG) void k_row_slots(int n, int npe, const int* __restrict__ n2e_ptr,
+                                                  const int* __restrict__ n2e,
+                                                  const int* __restrict__ e2s,
+                                                  const int* __restrict__ sptr,
+                                                  uint8_t* __restrict__ r2j) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= n) return;
+    const int base = sptr[i / WAVE] + i % WAVE;
+    for (int k = n2e_ptr[i]; k < n2e_ptr[i + 1]; ++k) {
+        const int64_t ea = n2e[k];  // e npe + a
+        for (int b = 0; b < npe; ++b)
+            r2j[(int64_t)k * npe + b] = (uint8_t)((e2s[ea * npe + b] - base) / WAVE);
+    }
+}
+
+// Geometric constants of every element, fixed for the mesh's life: for a parallelepiped
+// hex its metric C = detJ J^-1 J^-T (C00 C01 C02 C11 C12 C22) and detJ; for a tet the
+// gradients of its barycentric coordinates (4 x 3) and its volume.
+template <int NPE>
+__global__ __launch_bounds__(WG) void k_elem_geo(int64_t E, const int* __restrict__ conn,
+                                                 const double* __restrict__ xyz,
+                                                 double* __restrict__ geo) {
+    const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (e >= E) return;
+    double X[NPE][3];
+#pragma unroll
+    for (int b = 0; b < NPE; ++b) {
+        const int node = conn[e * NPE + b];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) X[b][d] = xyz[(int64_t)node * 3 + d];
+    }
+    if constexpr (NPE == 8) {
+        double C[3][3];
+        const double det = hex_affine_metric(X, C);
+        double* g = geo + e * kGeoHex;
+        g[0] = C[0][0];
+        g[1] = C[0][1];
+        g[2] = C[0][2];
+        g[3] = C[1][1];
+        g[4] = C[1][2];
+        g[5] = C[2][2];
+        g[6] = det;
+        g[7] = 0.0;
+    } else {
+        double G[4][3];
+        const double V = tet_geometry(X, G);
+        double* g = geo + e * kGeoTet;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) g[b * 3 + d] = G[b][d];
+        g[12] = V;
+        g[13] = g[14] = g[15] = 0.0;
+    }
+}
+
+// Row-wise assembly: wavefront w of the block takes one slab, lane l its row; every lane
+// adds the rows of its node's incident elements (a M_e + c K_e) into the slab's values kept
+// in LDS (the wavefront's own region, so no barrier), then lifts the row (as k_lift) and
+// writes its values, their FP32 copy, the lift and the Jacobi inverse.  Every slot of the
+// slab is written once, padding included (as 0).
+template <int NPE, bool AFFINE>
+__global__ __launch_bounds__(WG) void k_assemble_rows(RowAsm a) {
+    __shared__ double acc[NWAVES][kRowAsmMaxW][WAVE];
+    const int nb = gridDim.x;
+    const int lane = threadIdx.x % WAVE;
+    const int w = threadIdx.x / WAVE;
+    const int sl = xcd_block(blockIdx.x, nb) * NWAVES + w;
+    if (sl >= a.nslabs) return;
+    const int base = a.sptr[sl];
+    const int width = (a.sptr[sl + 1] - base) / WAVE;
+    const int r = sl * WAVE + lane;
+    for (int j = 0; j < width; ++j) acc[w][j][lane] = 0.0;
+    if (r < a.n) {
+        for (int k = a.n2e_ptr[r]; k < a.n2e_ptr[r + 1]; ++k) {
+            const int ea = a.n2e[k];
+            const int e = ea / NPE, ia = ea % NPE;
+            double Kr[NPE], Mr[NPE];
+            if constexpr (NPE == 8 && AFFINE) {
+                const double2* g = reinterpret_cast<const double2*>(a.geo + (int64_t)e * kGeoHex);
+                const double2 g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3];
+                const double C[3][3] = {{g0.x, g0.y, g1.x}, {g0.y, g1.y, g2.x}, {g1.x, g2.x, g2.y}};
+                hex_rows_metric(C, g3.x, ia, Kr, Mr);
+            } else if constexpr (NPE == 8) {
+                double X[8][3];
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const int node = a.conn[(int64_t)e * 8 + b];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) X[b][d] = a.xyz[(int64_t)node * 3 + d];
+                }
+                hex_rows(X, ia, Kr, Mr);
+            } else {
+                const double* g = a.geo + (int64_t)e * kGeoTet;
+                const double V = g[12];
+                const double ga0 = g[ia * 3], ga1 = g[ia * 3 + 1], ga2 = g[ia * 3 + 2];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    Kr[b] = V * (ga0 * g[b * 3] + ga1 * g[b * 3 + 1] + ga2 * g[b * 3 + 2]);
+                    Mr[b] = (ia == b ? 2.0 : 1.0) * V / 20.0;
+                }
+            }
+            const double m = a.mass ? a.mass[e] : 0.0;
+            const double c = a.stiff ? a.stiff[e] : 0.0;
+            // the NPE entry indices of this incidence, one byte each, read as one word
+            uint64_t jj;
+            if constexpr (NPE == 8) jj = *reinterpret_cast<const uint64_t*>(a.r2j + (int64_t)k * 8);
+            else jj = *reinterpret_cast<const uint32_t*>(a.r2j + (int64_t)k * 4);
+#pragma unroll
+            for (int b = 0; b < NPE; ++b)
+                acc[w][(jj >> (8 * b)) & 0xff][lane] += m * Mr[b] + c * Kr[b];
+        }
+    }
+    // Lifting from the row's precomputed Dirichlet-column mask and diagonal entry index: the
+    // column ids and the values g are read only for entries in Dirichlet columns.
+    const bool drow = r < a.n && a.do_lift && a.isD[r];
+    const uint32_t dm = (r < a.n && a.do_lift) ? a.dmask[r] : 0u;
+    const int jd = r < a.n ? (int)a.jdiag[r] : 255;  // 255: none
+    double diag = 0.0, acc_l = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < width; ++j) {
+        const int64_t pos = base + (int64_t)j * WAVE + lane;
+        double v = acc[w][j][lane];
+        if (drow) {
+            v = j == jd ? 1.0 : 0.0;
+        } else if ((dm >> j) & 1u) {
+            acc_l += v * a.gnode[a.scol[pos]];
+            v = 0.0;
+        }
+        if (j == jd) diag = v;
+        a.vals[pos] = v;
+        if (a.vals32) a.vals32[pos] = (float)v;
+    }
+    if (r >= a.n) return;
+    if (drow) diag = 1.0;
+    if (a.do_lift && a.lift) a.lift[r] = drow ? a.gnode[r] : -acc_l;
+    if (a.dinv) {
+        const double inv = 1.0 / diag;
+        a.dinv[r] = inv;
+        if (a.dinv32) a.dinv32[r] = (float)inv;
+    }
+}
+
 // Symmetric lifting of Dirichlet rows/columns, Jacobi inverse and FP32 copy.
 __global__ __launch_bounds__(WG) void k_lift(int n, const Layout L, double* __restrict__ vals,
                                              float* __restrict__ vals32,
@@ -345,6 +489,28 @@ void launch_assemble_colour(int npe, int affine, const int32_t* elems, int count
 void launch_slot_map(int64_t E, int npe, const int32_t* conn, const Layout& L, int32_t* e2s,
                      hipStream_t s) {
     hipLaunchKernelGGL(k_slot_map, dim3(grid1(E * npe)), dim3(WG), 0, s, E, npe, conn, L, e2s);
+}
+
+void launch_row_slots(int n, int npe, const int32_t* n2e_ptr, const int32_t* n2e,
+                      const int32_t* e2s, const int32_t* sptr, uint8_t* r2j, hipStream_t s) {
+    hipLaunchKernelGGL(k_row_slots, dim3(grid1(n)), dim3(WG), 0, s, n, npe, n2e_ptr, n2e, e2s,
+                       sptr, r2j);
+}
+
+void launch_elem_geo(int64_t E, int npe, const int32_t* conn, const double* xyz, double* geo,
+                     hipStream_t s) {
+    if (npe == 8) hipLaunchKernelGGL(k_elem_geo<8>, dim3(grid1(E)), dim3(WG), 0, s, E, conn, xyz, geo);
+    else hipLaunchKernelGGL(k_elem_geo<4>, dim3(grid1(E)), dim3(WG), 0, s, E, conn, xyz, geo);
+}
+
+void launch_assemble_rows(int npe, int affine, const RowAsm& a, hipStream_t s) {
+    const int blocks = (a.nslabs + NWAVES - 1) / NWAVES;
+    if (npe == 8) {
+        if (affine) hipLaunchKernelGGL((k_assemble_rows<8, true>), dim3(blocks), dim3(WG), 0, s, a);
+        else hipLaunchKernelGGL((k_assemble_rows<8, false>), dim3(blocks), dim3(WG), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_assemble_rows<4, false>), dim3(blocks), dim3(WG), 0, s, a);
+    }
 }
 
 void launch_lift(int n, const Layout& L, double* vals, float* vals32, const uint8_t* isD,

@@ -46,6 +46,25 @@ void node_to_elements(int64_t n, int64_t E, int npe, const int32_t* conn,
 
 }  // namespace
 
+void node_elements(int64_t n, int64_t E, int npe, const int32_t* conn, std::vector<int32_t>& ptr,
+                   std::vector<int32_t>& list) {
+    // CSR by node of the incidences (e, a) with conn[e][a] = node, packed as e npe + a, in
+    // increasing element order
+    std::vector<int64_t> p64;
+    std::vector<int32_t> adj;
+    node_to_elements(n, E, npe, conn, p64, adj);
+    ptr.resize(n + 1);
+    for (int64_t i = 0; i <= n; ++i) ptr[i] = (int32_t)p64[i];
+    list.resize(adj.size());
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = p64[i]; k < p64[i + 1]; ++k) {
+            const int32_t e = adj[k];
+            int a = 0;
+            while (conn[(int64_t)e * npe + a] != i) ++a;
+            list[k] = e * npe + a;
+        }
+}
+
 void check_conn(int64_t n_nodes, int64_t n_elems, int npe, const int32_t* conn) {
     if (n_nodes <= 0 || n_nodes > INT32_MAX - 1) throw Error{RAFEM_E_ARG, "n_nodes out of range"};
     if (n_elems <= 0 || n_elems > INT32_MAX / 8) throw Error{RAFEM_E_ARG, "n_elems out of range"};
