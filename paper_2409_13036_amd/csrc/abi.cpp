@@ -185,7 +185,8 @@ RowAsm row_asm(rafem_mesh m, const double* mass, const double* stiff, const doub
     a.nslabs = m->nslabs;
     a.sptr = m->sptr;
     a.scol = m->scol;
-    a.n2e_ptr = m->n2e_ptr;
+    a.width = m->row_w;
+    a.isptr = m->isptr;
     a.n2e = m->n2e;
     a.r2j = m->r2j;
     a.dmask = m->dmask;
@@ -431,16 +432,36 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             int32_t max_w = 0;
             for (int64_t b = 0; b < SL.nslabs; ++b)
                 max_w = std::max(max_w, (SL.sptr[b + 1] - SL.sptr[b]) / 64);
+            std::vector<int32_t> nptr, nlist, isptr;
             if (max_w <= kRowAsmMaxW) {
-                std::vector<int32_t> nptr, nlist;
                 node_elements(n_nodes, n_elems, npe, conn_h, nptr, nlist);
-                m->n2e_ptr = dalloc<int32_t>(m, N + 1);
-                m->n2e = dalloc<int32_t>(m, nlist.size());
-                m->r2j = dalloc<uint8_t>(m, nlist.size() * (size_t)npe);
-                RAFEM_HIP(hipMemcpy(m->n2e_ptr, nptr.data(), (N + 1) * 4, hipMemcpyHostToDevice));
-                RAFEM_HIP(hipMemcpy(m->n2e, nlist.data(), nlist.size() * 4,
+                // lane-interleaved incidences, each slab as deep as its busiest row
+                isptr.assign(SL.nslabs + 1, 0);
+                int64_t slots = 0;
+                for (int64_t b = 0; b < SL.nslabs; ++b) {
+                    int32_t deep = 0;
+                    for (int64_t r = b * 64; r < std::min<int64_t>(n_nodes, b * 64 + 64); ++r)
+                        deep = std::max(deep, nptr[r + 1] - nptr[r]);
+                    slots += (int64_t)deep * 64;
+                    if (slots > INT32_MAX) break;
+                    isptr[b + 1] = (int32_t)slots;
+                }
+                if (slots > INT32_MAX) max_w = kRowAsmMaxW + 1;  // colour-by-colour instead
+            }
+            if (max_w <= kRowAsmMaxW) {
+                std::vector<int32_t> n2e_s(std::max<int32_t>(1, isptr[SL.nslabs]), -1);
+                for (int64_t r = 0; r < n_nodes; ++r)
+                    for (int32_t k = nptr[r]; k < nptr[r + 1]; ++k)
+                        n2e_s[isptr[r / 64] + (k - nptr[r]) * 64 + r % 64] = nlist[k];
+                const size_t NS = n2e_s.size();
+                m->row_w = max_w;
+                m->isptr = dalloc<int32_t>(m, isptr.size());
+                m->n2e = dalloc<int32_t>(m, NS);
+                m->r2j = dalloc<uint64_t>(m, NS);
+                RAFEM_HIP(hipMemcpy(m->isptr, isptr.data(), isptr.size() * 4,
                                     hipMemcpyHostToDevice));
-                launch_row_slots((int)m->n, npe, m->n2e_ptr, m->n2e, m->e2s, m->sptr, m->r2j,
+                RAFEM_HIP(hipMemcpy(m->n2e, n2e_s.data(), NS * 4, hipMemcpyHostToDevice));
+                launch_row_slots((int64_t)NS, npe, m->n2e, m->conn, m->e2s, m->sptr, m->r2j,
                                  nullptr);
                 std::vector<uint32_t> dmask(N, 0u);
                 std::vector<uint8_t> jdiag(N, 255);  // 255: no diagonal entry

@@ -293,6 +293,41 @@ __device__ __forceinline__ void hex_rows_metric(const double (&C)[3][3], double 
     }
 }
 
+// A signed power of two, 2^e (e within the normal range), built from its bit pattern.
+__device__ __forceinline__ double signed_pow2(int neg, int e) {
+    return __hiloint2double((int)(((unsigned)neg << 31) | ((unsigned)(1023 + e) << 20)), 0);
+}
+
+// Row a of c K_e + m M_e of a parallelepiped hex from its scaled metric Cs = c (C00/72,
+// C11/72, C22/72, C01/24, C02/24, C12/24) and ms = m detJ/216.  With t_k = s_ak s_bk and
+// q_k = 3 + t_k (so p_k = 2 q_k / 3), the integrals above become
+//   K_ab = sum_d (C_dd/72) t_d q_e q_f + sum_{d<e} (C_de/24) (s_ad s_be + s_ae s_bd) q_f,
+//   M_ab = (detJ/216) q_0 q_1 q_2,
+// whose integer factors are 0 or signed powers of two: each entry costs seven FMAs.
+__device__ __forceinline__ void hex_row_scaled(const double (&Cs)[6], double ms, int a,
+                                               double (&R)[8]) {
+    const int ab[3] = {((a + 1) >> 1) & 1, (a >> 1) & 1, (a >> 2) & 1};  // corner sign bits
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int bb[3] = {((b + 1) >> 1) & 1, (b >> 1) & 1, (b >> 2) & 1};
+        int t[3];  // t_k = +1
+#pragma unroll
+        for (int k = 0; k < 3; ++k) t[k] = ab[k] == bb[k];
+        double v = ms * signed_pow2(0, 3 + t[0] + t[1] + t[2]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            v += Cs[d] * signed_pow2(!t[d], 2 + t[(d + 1) % 3] + t[(d + 2) % 3]);
+        constexpr int pd[3] = {0, 0, 1}, pe[3] = {1, 2, 2};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int d = pd[q], e = pe[q], f = 3 - d - e;
+            const bool nz = (ab[d] == bb[e]) == (ab[e] == bb[d]);
+            v += Cs[3 + q] * (nz ? signed_pow2(ab[d] != bb[e], 2 + t[f]) : 0.0);
+        }
+        R[b] = v;
+    }
+}
+
 __device__ inline void hex_rows_affine(const double (&X)[8][3], int a, double (&Kr)[8],
                                 double (&Mr)[8]) {
     double C[3][3];

@@ -222,18 +222,20 @@ void launch_slot_map(int64_t E, int npe, const int32_t* conn, const Layout& L, i
                      hipStream_t s);
 // Row-wise assembly on the SELL layout (slabs at most kRowAsmMaxW wide): one wavefront per
 // slab, one lane per row, the row's values summed over the node's incident elements in
-// LDS, then lifted (as launch_lift), copied to FP32 and written once.  r2j[k npe + b] is the
-// entry index within its row of column conn[e][b] for incidence k = (e, a) of the row.
+// LDS, then lifted (as launch_lift), copied to FP32 and written once.  The incidences of
+// slab b sit lane-interleaved at [isptr[b], isptr[b+1]): slot isptr[b] + k WAVE + l holds
+// e npe + a of the k-th incident element of row 64 b + l (or -1), and byte c of r2j at the
+// same slot the entry index within the row of column conn[e][c].
 constexpr int kRowAsmMaxW = 32;
 // Doubles per element of the geometric constants (parallelepiped hex, tet).
 constexpr int kGeoHex = 8, kGeoTet = 16;
 struct RowAsm {
-    int n = 0, nslabs = 0;
+    int n = 0, nslabs = 0, width = 0;  // width: widest slab (entries per row)
     const int32_t *sptr = nullptr, *scol = nullptr;
-    const int32_t *n2e_ptr = nullptr, *n2e = nullptr;
-    const uint8_t* r2j = nullptr;
+    const int32_t *isptr = nullptr, *n2e = nullptr;
+    const uint64_t* r2j = nullptr;
     const uint32_t* dmask = nullptr;  // per row: bit j set when entry j is in a Dirichlet column
-    const uint8_t* jdiag = nullptr;   // per row: index of the diagonal entry
+    const uint8_t* jdiag = nullptr;   // per row: index of the diagonal entry (255: none)
     const int32_t* conn = nullptr;
     const double* xyz = nullptr;
     const double* geo = nullptr;  // geometric constants (tets and parallelepiped hexes)
@@ -246,8 +248,8 @@ struct RowAsm {
     double *lift = nullptr, *dinv = nullptr;
     float* dinv32 = nullptr;
 };
-void launch_row_slots(int n, int npe, const int32_t* n2e_ptr, const int32_t* n2e,
-                      const int32_t* e2s, const int32_t* sptr, uint8_t* r2j, hipStream_t s);
+void launch_row_slots(int64_t total, int npe, const int32_t* n2e, const int32_t* conn,
+                      const int32_t* e2s, const int32_t* sptr, uint64_t* r2j, hipStream_t s);
 void launch_elem_geo(int64_t E, int npe, const int32_t* conn, const double* xyz, double* geo,
                      hipStream_t s);
 void launch_assemble_rows(int npe, int affine, const RowAsm& a, hipStream_t s);
@@ -435,8 +437,9 @@ struct rafem_mesh_s {
     // row-wise assembly (every slab at most kRowAsmMaxW wide): node -> element incidences and
     // the entry index of every (incidence, b) within its row
     bool row_asm = false;
-    int32_t *n2e_ptr = nullptr, *n2e = nullptr;
-    uint8_t* r2j = nullptr;
+    int row_w = 0;
+    int32_t *isptr = nullptr, *n2e = nullptr;
+    uint64_t* r2j = nullptr;
     uint32_t* dmask = nullptr;
     uint8_t* jdiag = nullptr;
     double* geo = nullptr;    // per-element geometric constants of the row-wise assembly

@@ -118,25 +118,32 @@ __global__ __launch_bounds__(WG) void k_slot_map(int64_t E, int npe, const int* 
         e2s[t * npe + b] = find_slot(L.cols, start, len, stride, conn[e * npe + b]);
 }
 
-// Entry index within row i of every column of every incident element row (from e2s).
-__global__ __launch_bounds__(WG) void k_row_slots(int n, int npe, const int* __restrict__ n2e_ptr,
+// Entry indices of the row-wise assembly: for every incidence slot t holding (e, a) (row
+// conn[e][a]), byte b of r2j[t] is the index within that row of the entry of column
+// conn[e][b], taken from the element-to-value map e2s.  Empty slots (n2e < 0) get 0.
+__global__ __launch_bounds__(WG) void k_row_slots(int64_t total, int npe,
                                                   const int* __restrict__ n2e,
+                                                  const int* __restrict__ conn,
                                                   const int* __restrict__ e2s,
                                                   const int* __restrict__ sptr,
-                                                  uint8_t* __restrict__ r2j) {
-    const int i = blockIdx.x * WG + threadIdx.x;
-    if (i >= n) return;
-    const int base = sptr[i / WAVE] + i % WAVE;
-    for (int k = n2e_ptr[i]; k < n2e_ptr[i + 1]; ++k) {
-        const int64_t ea = n2e[k];  // e npe + a
+                                                  uint64_t* __restrict__ r2j) {
+    const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (t >= total) return;
+    const int ea = n2e[t];
+    uint64_t p = 0;
+    if (ea >= 0) {
+        const int r = conn[ea];
+        const int base = sptr[r / WAVE] + r % WAVE;
         for (int b = 0; b < npe; ++b)
-            r2j[(int64_t)k * npe + b] = (uint8_t)((e2s[ea * npe + b] - base) / WAVE);
+            p |= (uint64_t)((e2s[(int64_t)ea * npe + b] - base) / WAVE) << (8 * b);
     }
+    r2j[t] = p;
 }
 
 // Geometric constants of every element, fixed for the mesh's life: for a parallelepiped
-// hex its metric C = detJ J^-1 J^-T (C00 C01 C02 C11 C12 C22) and detJ; for a tet the
-// gradients of its barycentric coordinates (4 x 3) and its volume.
+// hex its metric C = detJ J^-1 J^-T and detJ, scaled as hex_row_scaled takes them
+// (C00/72 C11/72 C22/72 C01/24 C02/24 C12/24 detJ/216); for a tet the gradients of its
+// barycentric coordinates (4 x 3) and its volume.
 template <int NPE>
 __global__ __launch_bounds__(WG) void k_elem_geo(int64_t E, const int* __restrict__ conn,
                                                  const double* __restrict__ xyz,
@@ -154,13 +161,13 @@ __global__ __launch_bounds__(WG) void k_elem_geo(int64_t E, const int* __restric
         double C[3][3];
         const double det = hex_affine_metric(X, C);
         double* g = geo + e * kGeoHex;
-        g[0] = C[0][0];
-        g[1] = C[0][1];
-        g[2] = C[0][2];
-        g[3] = C[1][1];
-        g[4] = C[1][2];
-        g[5] = C[2][2];
-        g[6] = det;
+        g[0] = C[0][0] / 72.0;
+        g[1] = C[1][1] / 72.0;
+        g[2] = C[2][2] / 72.0;
+        g[3] = C[0][1] / 24.0;
+        g[4] = C[0][2] / 24.0;
+        g[5] = C[1][2] / 24.0;
+        g[6] = det / 216.0;
         g[7] = 0.0;
     } else {
         double G[4][3];
@@ -175,62 +182,122 @@ __global__ __launch_bounds__(WG) void k_elem_geo(int64_t E, const int* __restric
     }
 }
 
-// Row-wise assembly: wavefront w of the block takes one slab, lane l its row; every lane
-// adds the rows of its node's incident elements (a M_e + c K_e) into the slab's values kept
-// in LDS (the wavefront's own region, so no barrier), then lifts the row (as k_lift) and
-// writes its values, their FP32 copy, the lift and the Jacobi inverse.  Every slot of the
-// slab is written once, padding included (as 0).
+// Registers of one incidence's geometric constants: 8 doubles for a parallelepiped hex,
+// 13 (of 16) for a tet; none for a general hex (its rows come from the node coordinates).
 template <int NPE, bool AFFINE>
-__global__ __launch_bounds__(WG) void k_assemble_rows(RowAsm a) {
-    __shared__ double acc[NWAVES][kRowAsmMaxW][WAVE];
-    const int nb = gridDim.x;
-    const int lane = threadIdx.x % WAVE;
-    const int w = threadIdx.x / WAVE;
-    const int sl = xcd_block(blockIdx.x, nb) * NWAVES + w;
+struct IncGeo {
+    static constexpr int W = NPE == 4 ? 7 : (AFFINE ? 4 : 1);
+    double2 v[W];
+    double m, c;
+};
+
+template <int NPE, bool AFFINE>
+__device__ __forceinline__ void load_inc(const RowAsm& a, int ea, IncGeo<NPE, AFFINE>& g) {
+    const int e = ea / NPE;
+    if constexpr (NPE == 4 || AFFINE) {
+        const double2* src = reinterpret_cast<const double2*>(
+            a.geo + (int64_t)e * (NPE == 4 ? kGeoTet : kGeoHex));
+#pragma unroll
+        for (int q = 0; q < IncGeo<NPE, AFFINE>::W; ++q) g.v[q] = src[q];
+    }
+    g.m = a.mass ? a.mass[e] : 0.0;
+    g.c = a.stiff ? a.stiff[e] : 0.0;
+}
+
+// Row a of m M_e + c K_e of the incidence ea = e NPE + a.
+template <int NPE, bool AFFINE>
+__device__ __forceinline__ void inc_row(const RowAsm& a, int ea, const IncGeo<NPE, AFFINE>& g,
+                                        double (&R)[NPE]) {
+    const int ia = ea % NPE;
+    if constexpr (NPE == 8 && AFFINE) {
+        const double Cs[6] = {g.c * g.v[0].x, g.c * g.v[0].y, g.c * g.v[1].x,
+                              g.c * g.v[1].y, g.c * g.v[2].x, g.c * g.v[2].y};
+        hex_row_scaled(Cs, g.m * g.v[3].x, ia, R);
+    } else if constexpr (NPE == 8) {
+        const int e = ea / NPE;
+        double X[8][3];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int node = a.conn[(int64_t)e * 8 + b];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) X[b][d] = a.xyz[(int64_t)node * 3 + d];
+        }
+        double Kr[8], Mr[8];
+        hex_rows(X, ia, Kr, Mr);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) R[b] = g.m * Mr[b] + g.c * Kr[b];
+    } else {
+        double G[4][3];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            G[(2 * q) / 3][(2 * q) % 3] = g.v[q].x;
+            G[(2 * q + 1) / 3][(2 * q + 1) % 3] = g.v[q].y;
+        }
+        const double V = g.v[6].x;
+        double ga[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            ga[d] = ia == 0 ? G[0][d] : ia == 1 ? G[1][d] : ia == 2 ? G[2][d] : G[3][d];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const double K = V * (ga[0] * G[b][0] + ga[1] * G[b][1] + ga[2] * G[b][2]);
+            const double M = (ia == b ? 2.0 : 1.0) * V / 20.0;
+            R[b] = g.m * M + g.c * K;
+        }
+    }
+}
+
+// Row-wise assembly: one wavefront per slab, lane l its row.  The slab's incidences are
+// stored lane-interleaved (slot isptr[slab] + k WAVE + lane holds the k-th (e, a) of the
+// lane's row, or -1), so their loads are coalesced; each lane adds the rows a M_e + c K_e
+// of its incidences into the slab's values kept in LDS ([width][WAVE], sized at launch),
+// loading the next incidence's constants while it computes the current one.  Then the
+// row is lifted (as k_lift) and its values, their FP32 copy, the lift and the Jacobi
+// inverse are written; every slot of the slab is written once, padding included (as 0).
+template <int NPE, bool AFFINE>
+__global__ __launch_bounds__(WAVE) void k_assemble_rows(RowAsm a) {
+    extern __shared__ double acc[];
+    const int lane = threadIdx.x;
+    const int sl = xcd_block(blockIdx.x, gridDim.x);
     if (sl >= a.nslabs) return;
     const int base = a.sptr[sl];
     const int width = (a.sptr[sl + 1] - base) / WAVE;
     const int r = sl * WAVE + lane;
-    for (int j = 0; j < width; ++j) acc[w][j][lane] = 0.0;
-    if (r < a.n) {
-        for (int k = a.n2e_ptr[r]; k < a.n2e_ptr[r + 1]; ++k) {
-            const int ea = a.n2e[k];
-            const int e = ea / NPE, ia = ea % NPE;
-            double Kr[NPE], Mr[NPE];
-            if constexpr (NPE == 8 && AFFINE) {
-                const double2* g = reinterpret_cast<const double2*>(a.geo + (int64_t)e * kGeoHex);
-                const double2 g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3];
-                const double C[3][3] = {{g0.x, g0.y, g1.x}, {g0.y, g1.y, g2.x}, {g1.x, g2.x, g2.y}};
-                hex_rows_metric(C, g3.x, ia, Kr, Mr);
-            } else if constexpr (NPE == 8) {
-                double X[8][3];
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    const int node = a.conn[(int64_t)e * 8 + b];
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) X[b][d] = a.xyz[(int64_t)node * 3 + d];
-                }
-                hex_rows(X, ia, Kr, Mr);
-            } else {
-                const double* g = a.geo + (int64_t)e * kGeoTet;
-                const double V = g[12];
-                const double ga0 = g[ia * 3], ga1 = g[ia * 3 + 1], ga2 = g[ia * 3 + 2];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    Kr[b] = V * (ga0 * g[b * 3] + ga1 * g[b * 3 + 1] + ga2 * g[b * 3 + 2]);
-                    Mr[b] = (ia == b ? 2.0 : 1.0) * V / 20.0;
-                }
-            }
-            const double m = a.mass ? a.mass[e] : 0.0;
-            const double c = a.stiff ? a.stiff[e] : 0.0;
-            // the NPE entry indices of this incidence, one byte each, read as one word
-            uint64_t jj;
-            if constexpr (NPE == 8) jj = *reinterpret_cast<const uint64_t*>(a.r2j + (int64_t)k * 8);
-            else jj = *reinterpret_cast<const uint32_t*>(a.r2j + (int64_t)k * 4);
-#pragma unroll
-            for (int b = 0; b < NPE; ++b)
-                acc[w][(jj >> (8 * b)) & 0xff][lane] += m * Mr[b] + c * Kr[b];
+    for (int j = 0; j < width; ++j) acc[j * WAVE + lane] = 0.0;
+    const int i0 = a.isptr[sl];
+    const int kmax = (a.isptr[sl + 1] - i0) / WAVE;
+    // incidence k (ea, jj, g) and the indices of incidence k + 1 (ea2, jj2)
+    int ea = -1, ea2 = -1;
+    uint64_t jj = 0, jj2 = 0;
+    IncGeo<NPE, AFFINE> g;
+    if (kmax > 0) {
+        ea = a.n2e[i0 + lane];
+        jj = a.r2j[i0 + lane];
+        if (ea >= 0) load_inc(a, ea, g);
+    }
+    if (kmax > 1) {
+        ea2 = a.n2e[i0 + WAVE + lane];
+        jj2 = a.r2j[i0 + WAVE + lane];
+    }
+    for (int k = 0; k < kmax; ++k) {
+        const int ea_n = ea2;
+        const uint64_t jj_n = jj2;
+        IncGeo<NPE, AFFINE> g_n;
+        if (ea_n >= 0) load_inc(a, ea_n, g_n);
+        ea2 = -1;
+        if (k + 2 < kmax) {
+            ea2 = a.n2e[i0 + (k + 2) * WAVE + lane];
+            jj2 = a.r2j[i0 + (k + 2) * WAVE + lane];
         }
+        if (ea >= 0) {
+            double R[NPE];
+            inc_row(a, ea, g, R);
+#pragma unroll
+            for (int b = 0; b < NPE; ++b) acc[((jj >> (8 * b)) & 0xff) * WAVE + lane] += R[b];
+        }
+        ea = ea_n;
+        jj = jj_n;
+        g = g_n;
     }
     // Lifting from the row's precomputed Dirichlet-column mask and diagonal entry index: the
     // column ids and the values g are read only for entries in Dirichlet columns.
@@ -241,7 +308,7 @@ __global__ __launch_bounds__(WG) void k_assemble_rows(RowAsm a) {
 #pragma unroll 4
     for (int j = 0; j < width; ++j) {
         const int64_t pos = base + (int64_t)j * WAVE + lane;
-        double v = acc[w][j][lane];
+        double v = acc[j * WAVE + lane];
         if (drow) {
             v = j == jd ? 1.0 : 0.0;
         } else if ((dm >> j) & 1u) {
@@ -491,10 +558,10 @@ void launch_slot_map(int64_t E, int npe, const int32_t* conn, const Layout& L, i
     hipLaunchKernelGGL(k_slot_map, dim3(grid1(E * npe)), dim3(WG), 0, s, E, npe, conn, L, e2s);
 }
 
-void launch_row_slots(int n, int npe, const int32_t* n2e_ptr, const int32_t* n2e,
-                      const int32_t* e2s, const int32_t* sptr, uint8_t* r2j, hipStream_t s) {
-    hipLaunchKernelGGL(k_row_slots, dim3(grid1(n)), dim3(WG), 0, s, n, npe, n2e_ptr, n2e, e2s,
-                       sptr, r2j);
+void launch_row_slots(int64_t total, int npe, const int32_t* n2e, const int32_t* conn,
+                      const int32_t* e2s, const int32_t* sptr, uint64_t* r2j, hipStream_t s) {
+    hipLaunchKernelGGL(k_row_slots, dim3(grid1(total)), dim3(WG), 0, s, total, npe, n2e, conn,
+                       e2s, sptr, r2j);
 }
 
 void launch_elem_geo(int64_t E, int npe, const int32_t* conn, const double* xyz, double* geo,
@@ -504,12 +571,13 @@ void launch_elem_geo(int64_t E, int npe, const int32_t* conn, const double* xyz,
 }
 
 void launch_assemble_rows(int npe, int affine, const RowAsm& a, hipStream_t s) {
-    const int blocks = (a.nslabs + NWAVES - 1) / NWAVES;
+    const size_t lds = (size_t)a.width * WAVE * sizeof(double);
+    const dim3 grid(a.nslabs), block(WAVE);
     if (npe == 8) {
-        if (affine) hipLaunchKernelGGL((k_assemble_rows<8, true>), dim3(blocks), dim3(WG), 0, s, a);
-        else hipLaunchKernelGGL((k_assemble_rows<8, false>), dim3(blocks), dim3(WG), 0, s, a);
+        if (affine) hipLaunchKernelGGL((k_assemble_rows<8, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_assemble_rows<8, false>), grid, block, lds, s, a);
     } else {
-        hipLaunchKernelGGL((k_assemble_rows<4, false>), dim3(blocks), dim3(WG), 0, s, a);
+        hipLaunchKernelGGL((k_assemble_rows<4, false>), grid, block, lds, s, a);
     }
 }
 
