@@ -131,6 +131,9 @@ typedef struct {
     int32_t int16_columns;       /* 1 if the SpMV reads 16-bit column offsets */
     int64_t slabs;               /* 64-row slabs of the SpMV layout */
     int64_t shared_offset_slabs; /* slabs whose rows share one column-offset list */
+    int32_t row_assembly;        /* 1: step matrices and right-hand side assembled row by row
+                                    (every row has at most 64 entries), 0: colour by colour */
+    int32_t max_row_entries;     /* entries of the longest row of the slab layout */
 } rafem_mesh_stats;
 
 /* Build a mesh on the current device.

@@ -51,7 +51,8 @@ class MeshStats(C.Structure):
                 ("n_dirichlet", C.c_int64), ("nodes_per_elem", C.c_int32), ("n_colours", C.c_int32),
                 ("n_samples", C.c_int32), ("slabs_per_block", C.c_int32),
                 ("slabs_per_block32", C.c_int32), ("int16_columns", C.c_int32),
-                ("slabs", C.c_int64), ("shared_offset_slabs", C.c_int64)]
+                ("slabs", C.c_int64), ("shared_offset_slabs", C.c_int64),
+                ("row_assembly", C.c_int32), ("max_row_entries", C.c_int32)]
 
 
 class SolveOpts(C.Structure):

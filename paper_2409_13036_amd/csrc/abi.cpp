@@ -185,7 +185,7 @@ RowAsm row_asm(rafem_mesh m, const double* mass, const double* stiff, const doub
     a.nslabs = m->nslabs;
     a.sptr = m->sptr;
     a.scol = m->scol;
-    a.width = m->row_w;
+    a.width = m->max_w;
     a.isptr = m->isptr;
     a.n2e = m->n2e;
     a.r2j = m->r2j;
@@ -432,6 +432,7 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             int32_t max_w = 0;
             for (int64_t b = 0; b < SL.nslabs; ++b)
                 max_w = std::max(max_w, (SL.sptr[b + 1] - SL.sptr[b]) / 64);
+            m->max_w = max_w;
             std::vector<int32_t> nptr, nlist, isptr;
             if (max_w <= kRowAsmMaxW) {
                 node_elements(n_nodes, n_elems, npe, conn_h, nptr, nlist);
@@ -454,7 +455,6 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
                     for (int32_t k = nptr[r]; k < nptr[r + 1]; ++k)
                         n2e_s[isptr[r / 64] + (k - nptr[r]) * 64 + r % 64] = nlist[k];
                 const size_t NS = n2e_s.size();
-                m->row_w = max_w;
                 m->isptr = dalloc<int32_t>(m, isptr.size());
                 m->n2e = dalloc<int32_t>(m, NS);
                 m->r2j = dalloc<uint64_t>(m, NS);
@@ -463,24 +463,25 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
                 RAFEM_HIP(hipMemcpy(m->n2e, n2e_s.data(), NS * 4, hipMemcpyHostToDevice));
                 launch_row_slots((int64_t)NS, npe, m->n2e, m->conn, m->e2s, m->sptr, m->r2j,
                                  nullptr);
-                std::vector<uint32_t> dmask(N, 0u);
+                std::vector<uint64_t> dmask(N, 0u);
                 std::vector<uint8_t> jdiag(N, 255);  // 255: no diagonal entry
                 for (int64_t r = 0; r < n_nodes; ++r) {
                     const int64_t b0 = SL.sptr[r / 64] + r % 64;
                     for (int j = 0; j < SL.rlen[r]; ++j) {
                         const int32_t c = SL.scol[b0 + (int64_t)j * 64];
-                        if (isD[c]) dmask[r] |= 1u << j;
+                        if (isD[c]) dmask[r] |= uint64_t{1} << j;
                         if (c == r) jdiag[r] = (uint8_t)j;
                     }
                 }
-                m->dmask = dalloc<uint32_t>(m, N);
+                m->dmask = dalloc<uint64_t>(m, N);
                 m->jdiag = dalloc<uint8_t>(m, N);
-                RAFEM_HIP(hipMemcpy(m->dmask, dmask.data(), N * 4, hipMemcpyHostToDevice));
+                RAFEM_HIP(hipMemcpy(m->dmask, dmask.data(), N * 8, hipMemcpyHostToDevice));
                 RAFEM_HIP(hipMemcpy(m->jdiag, jdiag.data(), N, hipMemcpyHostToDevice));
                 if (npe == 4 || m->affine) {
                     m->geo = dalloc<double>(m, E * (npe == 8 ? kGeoHex : kGeoTet));
                     launch_elem_geo(m->E, npe, m->conn, m->xyz, m->geo, nullptr);
                 }
+                m->erhs = dalloc<double>(m, E * npe);
                 m->row_asm = true;
             }
             // The slab padding of the FP32 values is read by the FP32 SpMV (column = own
@@ -693,6 +694,8 @@ rafem_status rafem_mesh_get_stats(rafem_mesh m, rafem_mesh_stats* out) {
         out->int16_columns = m->sdel ? 1 : 0;
         out->shared_offset_slabs = m->shared_slabs;
         out->slabs = m->nslabs;
+        out->row_assembly = m->row_asm ? 1 : 0;
+        out->max_row_entries = m->max_w;
         return RAFEM_OK;
     });
 }
@@ -971,15 +974,22 @@ rafem_status step_core(rafem_mesh m, const rafem_phys* phys, bool reuse_bioheat,
             return inf.V.status;
         }
     }
-    launch_fill(m->rhs, m->n, 0.0, s);
-    for (int c = 0; c < m->n_colours; ++c) {
-        const int off = m->colour_off[c], cnt = m->colour_off[c + 1] - off;
-        launch_bioheat_rhs_colour(m->npe, m->affine, m->colour_elems + off, cnt, m->conn, m->xyz, T_rhs,
-                                  phys->coupled ? V_d : nullptr, m->sigma, perf_e_d,
-                                  phys->rho_c / phys->dt, phys->T_a, phys->coupled ? 1 : 0,
-                                  m->rhs, s);
+    if (m->row_asm) {
+        launch_bioheat_rhs_rows(m->npe, m->affine, m->E, m->conn, m->xyz, m->geo, T_rhs,
+                                phys->coupled ? V_d : nullptr, m->sigma, perf_e_d,
+                                phys->rho_c / phys->dt, phys->T_a, phys->coupled ? 1 : 0, m->erhs,
+                                (int)m->n, m->isptr, m->n2e, m->liftT, m->isD, m->bT, s);
+    } else {
+        launch_fill(m->rhs, m->n, 0.0, s);
+        for (int c = 0; c < m->n_colours; ++c) {
+            const int off = m->colour_off[c], cnt = m->colour_off[c + 1] - off;
+            launch_bioheat_rhs_colour(m->npe, m->affine, m->colour_elems + off, cnt, m->conn,
+                                      m->xyz, T_rhs, phys->coupled ? V_d : nullptr, m->sigma,
+                                      perf_e_d, phys->rho_c / phys->dt, phys->T_a,
+                                      phys->coupled ? 1 : 0, m->rhs, s);
+        }
+        launch_finish_rhs((int)m->n, m->rhs, m->liftT, m->isD, m->bT, s);
     }
-    launch_finish_rhs((int)m->n, m->rhs, m->liftT, m->isD, m->bT, s);
     launch_set_dirichlet(m->dir_ids, m->gT, m->nD, T_out, s);
     RAFEM_HIP(hipGetLastError());
     const Mat AT = step_matrix(m, m->valsT, m->valsT32);

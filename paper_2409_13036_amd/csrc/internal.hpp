@@ -226,7 +226,7 @@ void launch_slot_map(int64_t E, int npe, const int32_t* conn, const Layout& L, i
 // slab b sit lane-interleaved at [isptr[b], isptr[b+1]): slot isptr[b] + k WAVE + l holds
 // e npe + a of the k-th incident element of row 64 b + l (or -1), and byte c of r2j at the
 // same slot the entry index within the row of column conn[e][c].
-constexpr int kRowAsmMaxW = 32;
+constexpr int kRowAsmMaxW = 64;
 // Doubles per element of the geometric constants (parallelepiped hex, tet).
 constexpr int kGeoHex = 8, kGeoTet = 16;
 struct RowAsm {
@@ -234,7 +234,7 @@ struct RowAsm {
     const int32_t *sptr = nullptr, *scol = nullptr;
     const int32_t *isptr = nullptr, *n2e = nullptr;
     const uint64_t* r2j = nullptr;
-    const uint32_t* dmask = nullptr;  // per row: bit j set when entry j is in a Dirichlet column
+    const uint64_t* dmask = nullptr;  // per row: bit j set when entry j is in a Dirichlet column
     const uint8_t* jdiag = nullptr;   // per row: index of the diagonal entry (255: none)
     const int32_t* conn = nullptr;
     const double* xyz = nullptr;
@@ -253,6 +253,15 @@ void launch_row_slots(int64_t total, int npe, const int32_t* n2e, const int32_t*
 void launch_elem_geo(int64_t E, int npe, const int32_t* conn, const double* xyz, double* geo,
                      hipStream_t s);
 void launch_assemble_rows(int npe, int affine, const RowAsm& a, hipStream_t s);
+// Bioheat right-hand side with the row-wise assembly's incidences: every element's terms
+// into erhs[e npe + a] (one launch over all elements; parallelepiped hexes from geo when
+// given), then per row their sum, lifted into b as launch_finish_rhs does.
+void launch_bioheat_rhs_rows(int npe, int affine, int64_t E, const int32_t* conn,
+                             const double* xyz, const double* geo, const double* T, const double* V,
+                             const double* sigma, const double* perf, double rho_c_dt, double T_a,
+                             int with_joule, double* erhs, int n, const int32_t* isptr,
+                             const int32_t* n2e, const double* lift, const uint8_t* isD,
+                             double* b, hipStream_t s);
 // Lifting with per-node Dirichlet mask/values; writes lifted vals, vals32, lift, dinv, dinv32.
 void launch_lift(int n, const Layout& L, double* vals, float* vals32, const uint8_t* isD,
                  const double* gnode, double* lift, double* dinv, float* dinv32, int do_lift,
@@ -437,12 +446,13 @@ struct rafem_mesh_s {
     // row-wise assembly (every slab at most kRowAsmMaxW wide): node -> element incidences and
     // the entry index of every (incidence, b) within its row
     bool row_asm = false;
-    int row_w = 0;
+    int max_w = 0;  // widest slab (entries per row)
     int32_t *isptr = nullptr, *n2e = nullptr;
     uint64_t* r2j = nullptr;
-    uint32_t* dmask = nullptr;
+    uint64_t* dmask = nullptr;
     uint8_t* jdiag = nullptr;
     double* geo = nullptr;    // per-element geometric constants of the row-wise assembly
+    double* erhs = nullptr;   // per-incidence terms of the bioheat right-hand side
     int affine = 0;           // every hex is a parallelepiped
     int16_t* sdel = nullptr;  // SELL column - row offsets (NULL when the bandwidth exceeds int16)
     int32_t* sofs = nullptr;  // [nslabs] start of a shared-offset slab's list in soff, or -1

@@ -302,7 +302,7 @@ __global__ __launch_bounds__(WAVE) void k_assemble_rows(RowAsm a) {
     // Lifting from the row's precomputed Dirichlet-column mask and diagonal entry index: the
     // column ids and the values g are read only for entries in Dirichlet columns.
     const bool drow = r < a.n && a.do_lift && a.isD[r];
-    const uint32_t dm = (r < a.n && a.do_lift) ? a.dmask[r] : 0u;
+    const uint64_t dm = (r < a.n && a.do_lift) ? a.dmask[r] : 0u;
     const int jd = r < a.n ? (int)a.jdiag[r] : 255;  // 255: none
     double diag = 0.0, acc_l = 0.0;
 #pragma unroll 4
@@ -386,6 +386,8 @@ __global__ __launch_bounds__(WG) void k_sigma(int npe, int64_t E, const int* __r
 
 // Bioheat right-hand side, one thread per (element of this colour, local node a):
 // rhs[node a] += sum_b M_ab (rho_c_dt T_b + perf_e T_a) + int N_a sigma_e |grad V|^2.
+// Without a colour list (elems NULL) the threads cover elements 0 .. count-1 and store the
+// term in rhs[e NPE + a] (per incidence) instead.
 template <int NPE, bool AFFINE>
 __global__ __launch_bounds__(WG) void k_bioheat_rhs(const int* __restrict__ elems, int count,
                                                     const int* __restrict__ conn,
@@ -398,7 +400,7 @@ __global__ __launch_bounds__(WG) void k_bioheat_rhs(const int* __restrict__ elem
                                                     double* __restrict__ rhs) {
     const int t = blockIdx.x * WG + threadIdx.x;
     if (t >= count * NPE) return;
-    const int e = elems[t / NPE];
+    const int e = elems ? elems[t / NPE] : t / NPE;
     const int a = t % NPE;
     int nodes[NPE];
     double X[NPE][3], Tw[NPE], Vb[NPE];
@@ -458,7 +460,90 @@ __global__ __launch_bounds__(WG) void k_bioheat_rhs(const int* __restrict__ elem
         f = vol / 20.0 * (sumw + Tw[a]) +
             sg * (gV[0] * gV[0] + gV[1] * gV[1] + gV[2] * gV[2]) * vol / 4.0;
     }
-    rhs[nodes[a]] += f;
+    if (elems) rhs[nodes[a]] += f;
+    else rhs[t] = f;
+}
+
+// The same per-incidence terms for parallelepiped hexes from their stored constants (as
+// k_elem_geo keeps them): with C = detJ J^-1 J^-T, detJ |grad V|^2 = grad_xi V^T C grad_xi V,
+// so no Jacobian is inverted and no coordinates are read.  Thread (e, a) evaluates the
+// integrand at Gauss point a and forms sum_q N_a(q) s_q from its lane group, as
+// k_bioheat_rhs does.
+__global__ __launch_bounds__(WG) void k_bioheat_rhs_geo(int count, const int* __restrict__ conn,
+                                                        const double* __restrict__ geo,
+                                                        const double* __restrict__ T,
+                                                        const double* __restrict__ V,
+                                                        const double* __restrict__ sigma,
+                                                        const double* __restrict__ perf,
+                                                        double rho_c_dt, double T_a,
+                                                        int with_joule, double* __restrict__ rhs) {
+    const int t = blockIdx.x * WG + threadIdx.x;
+    if (t >= count * 8) return;
+    const int e = t / 8, a = t % 8;
+    const double2* g = reinterpret_cast<const double2*>(geo + (int64_t)e * kGeoHex);
+    const double2 g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3];
+    const double src = perf[e] * T_a;
+    const double sg = with_joule ? sigma[e] : 0.0;
+    double xi, et, ze;
+    gauss_point(a, xi, et, ze);
+    double Nw = 0.0, gv0 = 0.0, gv1 = 0.0, gv2 = 0.0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int node = conn[(int64_t)e * 8 + b];
+        const double Tw = rho_c_dt * T[node] + src;
+        const double Vb = with_joule ? V[node] : 0.0;
+        double Nb, d0, d1, d2;
+        hex_shape(b, xi, et, ze, Nb, d0, d1, d2);
+        Nw += Nb * Tw;
+        gv0 += Vb * d0;
+        gv1 += Vb * d1;
+        gv2 += Vb * d2;
+    }
+    const double C00 = 72.0 * g0.x, C11 = 72.0 * g0.y, C22 = 72.0 * g1.x;
+    const double C01 = 24.0 * g1.y, C02 = 24.0 * g2.x, C12 = 24.0 * g2.y, det = 216.0 * g3.x;
+    const double quad = C00 * gv0 * gv0 + C11 * gv1 * gv1 + C22 * gv2 * gv2 +
+                        2.0 * (C01 * gv0 * gv1 + C02 * gv0 * gv2 + C12 * gv1 * gv2);
+    const double sq = det * Nw + sg * quad;
+    const int lane0 = (int)(threadIdx.x % WAVE) & ~7;
+    double f = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const double s_q = __shfl(sq, lane0 + q, WAVE);
+        double gx, gy, gz;
+        gauss_point(q, gx, gy, gz);
+        double Na, d0, d1, d2;
+        hex_shape(a, gx, gy, gz, Na, d0, d1, d2);
+        f += Na * s_q;
+    }
+    rhs[t] = f;
+}
+
+// Right-hand side by rows from the per-incidence terms of k_bioheat_rhs: row r adds its
+// node's incidences in the lane-interleaved order of the row-wise assembly (ascending
+// element), then b = rhs + lift, or the lifted value on Dirichlet rows.
+__global__ __launch_bounds__(WG) void k_rhs_rows(int n, const int* __restrict__ isptr,
+                                                 const int* __restrict__ n2e,
+                                                 const double* __restrict__ erhs,
+                                                 const double* __restrict__ lift,
+                                                 const uint8_t* __restrict__ isD,
+                                                 double* __restrict__ b) {
+    const int r = blockIdx.x * WG + threadIdx.x;
+    if (r >= n) return;
+    const int sl = r / WAVE, lane = r % WAVE;
+    const int i0 = isptr[sl], kmax = (isptr[sl + 1] - i0) / WAVE;
+    double sum = 0.0;
+    for (int k0 = 0; k0 < kmax; k0 += 8) {  // eight incidences' loads in flight at once
+        int ea[8];
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ea[u] = k0 + u < kmax ? n2e[i0 + (k0 + u) * WAVE + lane] : -1;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = ea[u] >= 0 ? erhs[ea[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (ea[u] >= 0) sum += v[u];
+    }
+    b[r] = isD[r] ? lift[r] : sum + lift[r];
 }
 
 __global__ void k_finish_rhs(int n, const double* __restrict__ rhs,
@@ -592,6 +677,30 @@ void launch_sigma(int npe, int64_t E, const int32_t* conn, const double* T, cons
                   double alpha, double T_ref, double* sigma, hipStream_t s) {
     hipLaunchKernelGGL(k_sigma, dim3(grid1(E)), dim3(WG), 0, s, npe, E, conn, T, sigma0, alpha,
                        T_ref, sigma);
+}
+
+void launch_bioheat_rhs_rows(int npe, int affine, int64_t E, const int32_t* conn,
+                             const double* xyz, const double* geo, const double* T, const double* V,
+                             const double* sigma, const double* perf, double rho_c_dt, double T_a,
+                             int with_joule, double* erhs, int n, const int32_t* isptr,
+                             const int32_t* n2e, const double* lift, const uint8_t* isD,
+                             double* b, hipStream_t s) {
+    const int grid = grid1(E * npe);
+    const int cnt = (int)E;
+    if (npe == 8 && affine && geo)
+        hipLaunchKernelGGL(k_bioheat_rhs_geo, dim3(grid), dim3(WG), 0, s, cnt, conn, geo, T, V,
+                           sigma, perf, rho_c_dt, T_a, with_joule, erhs);
+    else if (npe == 8 && affine)
+        hipLaunchKernelGGL((k_bioheat_rhs<8, true>), dim3(grid), dim3(WG), 0, s, nullptr, cnt,
+                           conn, xyz, T, V, sigma, perf, rho_c_dt, T_a, with_joule, erhs);
+    else if (npe == 8)
+        hipLaunchKernelGGL((k_bioheat_rhs<8, false>), dim3(grid), dim3(WG), 0, s, nullptr, cnt,
+                           conn, xyz, T, V, sigma, perf, rho_c_dt, T_a, with_joule, erhs);
+    else
+        hipLaunchKernelGGL((k_bioheat_rhs<4, false>), dim3(grid), dim3(WG), 0, s, nullptr, cnt,
+                           conn, xyz, T, V, sigma, perf, rho_c_dt, T_a, with_joule, erhs);
+    hipLaunchKernelGGL(k_rhs_rows, dim3(grid1(n)), dim3(WG), 0, s, n, isptr, n2e, erhs, lift, isD,
+                       b);
 }
 
 void launch_bioheat_rhs_colour(int npe, int affine, const int32_t* elems, int count,
