@@ -385,6 +385,7 @@ def batch_leg(args) -> dict:
     t0 = time.perf_counter()
     bp = BatchProblem(probs)
     bp.extrapolate = not args.no_extrapolate
+    bp.extrapolate_order = args.extrapolate_order
     setup = time.perf_counter() - t0
     S = len(probs)
     nnz = sum((3 * p.n - 2) ** 3 for p in probs)
@@ -626,6 +627,7 @@ def liver_leg(args) -> dict:
     def measure(prob, steps, warmup, label):
         dp = DeviceProblem(prob)
         dp.extrapolate = not args.no_extrapolate
+        dp.extrapolate_order = args.extrapolate_order
         st = dp.mesh.stats()
         N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
         row = {"n_nodes": N, "n_elems": dp.mesh.n_elems, "nnz": nnz, "colours": st.n_colours,
@@ -676,6 +678,8 @@ def main():
     ap.add_argument("--fd-params", type=int, default=32)
     ap.add_argument("--workload", choices=["c1", "c2"], default="c1",
                     help="c1: 101^3 hex (default); c2: 161^3-node jittered Kuhn tets")
+    ap.add_argument("--extrapolate-order", type=int, default=2, choices=(1, 2),
+                    help="order of the predictor of the solves' starting points")
     ap.add_argument("--no-extrapolate", action="store_true",
                     help="start every solve from the previous state instead of the linear "
                          "extrapolation of the last two")
@@ -760,6 +764,7 @@ def main():
         workload = f"C1 coupled RFA step, {n}^3-node hex cube"
     dp = DeviceProblem(p)
     dp.extrapolate = not args.no_extrapolate
+    dp.extrapolate_order = args.extrapolate_order
     N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
     mesh_stats = dp.mesh.stats()
     res = {}

@@ -329,9 +329,14 @@ typedef struct {
                              T^n + (dt/dt_prev)(T^n - T^{n-1}), and the same for V (sigma and the
                              right-hand side still use T^n), the handle keeping T^{n-1}, V^{n-1}
                              from that call.  2: a new trajectory starts here (solves start from
-                             T_d, V_d; the states are kept for the next call).  0: off.  A call
-                             with 0, a failed call, rafem_step_pc and rafem_step_mono end the
-                             trajectory (the next call with 1 then behaves as 2). */
+                             T_d, V_d; the states are kept for the next call).  3: as 1, but once
+                             the handle keeps two earlier states of the trajectory the solves start
+                             from the quadratic extrapolation: the Lagrange polynomial through
+                             (t_n, T^n), (t_n - h1, T^{n-1}), (t_n - h1 - h2, T^{n-2}) taken at
+                             t_n + dt, h1 and h2 being the dt of the two previous calls (and the
+                             same for V).  0: off.  A call with 0, a failed call, rafem_step_pc and
+                             rafem_step_mono end the trajectory (the next call with 1 or 3 then
+                             behaves as 2).  Other values: E_ARG. */
     int32_t pad;
 } rafem_phys;
 

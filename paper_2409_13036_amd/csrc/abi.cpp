@@ -367,7 +367,7 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             m->pc_Tn = dalloc<double>(m, N);
             m->pc_Vn = dalloc<double>(m, N);
             m->pc_Tk = dalloc<double>(m, N);
-            for (int k = 0; k < 2; ++k) {  // extrapolation histories (phys->extrapolate)
+            for (int k = 0; k < 3; ++k) {  // extrapolation histories (phys->extrapolate)
                 m->xg_T[k] = dalloc<double>(m, N);
                 m->xg_V[k] = dalloc<double>(m, N);
             }
@@ -1024,31 +1024,47 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
         const bool reuse = phys->reuse_bioheat && m->bioheat_dt == phys->dt;
         hipStream_t s = (hipStream_t)stream;
         region_begin(m);
+        if (phys->extrapolate < 0 || phys->extrapolate > 3)
+            throw Error{RAFEM_E_ARG, "phys.extrapolate must be 0, 1, 2 or 3"};
         if (!phys->extrapolate) {
-            m->xg_ready = false;
+            m->xg_ready = m->xg_ready2 = false;
             const rafem_status st = step_core(m, phys, reuse, k_e_d, perf_e_d, sigma0_e_d,
                                               dir_V_d, dir_T_d, T_d, T_d, T_d, V_d, o, inf, s);
             region_flush(m, s);
             return st;
         }
-        // keep (T^n, V^n); start the solves from their extrapolation when the previous call
-        // left (T^{n-1}, V^{n-1})
-        if (phys->extrapolate == 2) m->xg_ready = false;
+        // keep (T^n, V^n) in slot xg_cur; the slot before it in the ring holds (T^{n-1},
+        // V^{n-1}) when xg_ready, the one before that (T^{n-2}, V^{n-2}) when xg_ready2
+        if (phys->extrapolate == 2) m->xg_ready = m->xg_ready2 = false;
         const size_t bytes = (size_t)m->n * sizeof(double);
-        double* Tn = m->xg_T[m->xg_cur];
-        double* Vn = m->xg_V[m->xg_cur];
+        const int cur = m->xg_cur, prev1 = (cur + 2) % 3, prev2 = (cur + 1) % 3;
+        double* Tn = m->xg_T[cur];
+        double* Vn = m->xg_V[cur];
         region_mark(m, kRegCheck, s);
         RAFEM_HIP(hipMemcpyAsync(Tn, T_d, bytes, hipMemcpyDeviceToDevice, s));
         if (phys->coupled) RAFEM_HIP(hipMemcpyAsync(Vn, V_d, bytes, hipMemcpyDeviceToDevice, s));
-        if (m->xg_ready) {
+        if (phys->extrapolate == 3 && m->xg_ready && m->xg_ready2) {
+            // Lagrange weights of the states at t_n, t_n - h1, t_n - h1 - h2, taken at t_n + dt
+            const double tau = phys->dt, h1 = m->xg_dt, h2 = m->xg_dt2;
+            const double wa = (tau + h1) * (tau + h1 + h2) / (h1 * (h1 + h2));
+            const double wb = -tau * (tau + h1 + h2) / (h1 * h2);
+            const double wc = tau * (tau + h1) / ((h1 + h2) * h2);
+            launch_extrapolate2((int)m->n, Tn, m->xg_T[prev1], m->xg_T[prev2], wa, wb, wc, T_d, s);
+            if (phys->coupled)
+                launch_extrapolate2((int)m->n, Vn, m->xg_V[prev1], m->xg_V[prev2], wa, wb, wc, V_d,
+                                    s);
+        } else if (m->xg_ready) {
             const double c = phys->dt / m->xg_dt;
-            launch_extrapolate((int)m->n, Tn, m->xg_T[1 - m->xg_cur], c, T_d, s);
-            if (phys->coupled) launch_extrapolate((int)m->n, Vn, m->xg_V[1 - m->xg_cur], c, V_d, s);
+            launch_extrapolate((int)m->n, Tn, m->xg_T[prev1], c, T_d, s);
+            if (phys->coupled) launch_extrapolate((int)m->n, Vn, m->xg_V[prev1], c, V_d, s);
         }
         const rafem_status st = step_core(m, phys, reuse, k_e_d, perf_e_d, sigma0_e_d, dir_V_d,
                                           dir_T_d, Tn, Tn, T_d, V_d, o, inf, s);
-        m->xg_ready = st == RAFEM_OK && phys->coupled;
-        m->xg_cur = 1 - m->xg_cur;
+        const bool ok = st == RAFEM_OK && phys->coupled;
+        m->xg_ready2 = ok && m->xg_ready;
+        m->xg_ready = ok;
+        m->xg_dt2 = m->xg_dt;
+        m->xg_cur = (cur + 1) % 3;
         m->xg_dt = phys->dt;
         region_flush(m, s);
         return st;
@@ -1075,7 +1091,7 @@ rafem_status rafem_step_pc(rafem_mesh m, const rafem_phys* phys, const double* k
         rafem_corrector_info& ci = info ? *info : local;
         std::memset(&ci, 0, sizeof(ci));
         const size_t bytes = (size_t)m->n * sizeof(double);
-        m->xg_ready = false;
+        m->xg_ready = m->xg_ready2 = false;
         region_begin(m);
         region_mark(m, kRegCheck, s);
         // keep (T^n, V^n) to restore a rejected step; predictor into pc_Tk
@@ -1199,7 +1215,7 @@ rafem_status rafem_step_mono(rafem_mesh m, const rafem_phys* phys, const double*
         std::memset(&mi, 0, sizeof(mi));
         mono_ensure(m, o.m, o.precision == RAFEM_MIXED);
         const size_t bytes = (size_t)m->n * sizeof(double);
-        m->xg_ready = false;
+        m->xg_ready = m->xg_ready2 = false;
         region_begin(m);
         region_mark(m, kRegCheck, s);
         // keep (T^n, V^n) to restore a rejected step; the iterate starts at (T*, V^n) with

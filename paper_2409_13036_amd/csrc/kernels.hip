@@ -563,6 +563,16 @@ __global__ __launch_bounds__(WG) void k_extrapolate(int n, const double* __restr
     if (i < n) out[i] = b ? a[i] + c * (a[i] - b[i]) : a[i];
 }
 
+// Quadratic predictor: out = wa a + wb b + wc c (Lagrange weights of three past states).
+__global__ __launch_bounds__(WG) void k_extrapolate2(int n, const double* __restrict__ a,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ c, double wa,
+                                                     double wb, double wc,
+                                                     double* __restrict__ out) {
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i < n) out[i] = wa * a[i] + wb * b[i] + wc * c[i];
+}
+
 // Sums of (x - y)^2 and x^2: per-block partials, then one block adds them in order.
 __global__ __launch_bounds__(WG) void k_change_norm_part(int n, const double* __restrict__ x,
                                                          const double* __restrict__ y,
@@ -725,6 +735,13 @@ void launch_extrapolate(int n, const double* a, const double* b, double c, doubl
                         hipStream_t s) {
     if (n > 0)
         hipLaunchKernelGGL(k_extrapolate, dim3(grid1(n)), dim3(WG), 0, s, n, a, b, c, out);
+}
+
+void launch_extrapolate2(int n, const double* a, const double* b, const double* c, double wa,
+                         double wb, double wc, double* out, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_extrapolate2, dim3(grid1(n)), dim3(WG), 0, s, n, a, b, c, wa, wb, wc,
+                           out);
 }
 
 void launch_change_norm(int n, const double* x, const double* y, double* partials,

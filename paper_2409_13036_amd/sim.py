@@ -53,6 +53,18 @@ def rcm_reordered(problem, window: int = 0):
     return reorder_nodes(problem, order), order
 
 
+
+def _extrapolate_mode(on: bool, order: int, chain: bool) -> int:
+    """phys.extrapolate for a step: 0 off, 2 a new trajectory, 1 / 3 continue linearly /
+    quadratically."""
+    if not on:
+        return 0
+    if not chain:
+        return 2
+    if order not in (1, 2):
+        raise ValueError("extrapolate_order must be 1 or 2")
+    return 3 if order == 2 else 1
+
 class DeviceProblem:
     def __init__(self, problem, device=None):
         import torch
@@ -68,9 +80,11 @@ class DeviceProblem:
         self.dir_T = torch.as_tensor(problem.dir_T, **f64).contiguous()
         self.phys = rafem.Phys(problem.rho_c, problem.dt, problem.T_a, problem.alpha_sigma,
                                problem.T_ref, 1 if problem.coupled else 0, 0)
-        # extrapolate: start each step's solves from the linear extrapolation of the last two
-        # states (library-side); _chain: the next step continues the previous one
+        # extrapolate: start each step's solves from the extrapolation of the last states
+        # (library-side), linear (order 1: two states) or quadratic (order 2: three states,
+        # linear until three are kept); _chain: the next step continues the previous one
         self.extrapolate = False
+        self.extrapolate_order = 2
         self._chain = False
         self.loss_ids = self.T_target = None
         if problem.loss_ids is not None:
@@ -100,7 +114,8 @@ class DeviceProblem:
 
     def step(self, tol: float = 1e-12, precision: str = "fp64", **kw):
         """One coupled step (the bioheat matrix is assembled on the first call only)."""
-        self.phys.extrapolate = (1 if self._chain else 2) if self.extrapolate else 0
+        self.phys.extrapolate = _extrapolate_mode(self.extrapolate, self.extrapolate_order,
+                                                  self._chain)
         self._chain = False
         info = rafem.step(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e, self.dir_V,
                           self.dir_T, self.T, self.V, tol=tol, precision=precision, **kw)
@@ -222,6 +237,7 @@ class BatchProblem:
         self.phys = rafem.Phys(p0.rho_c, p0.dt, p0.T_a, p0.alpha_sigma, p0.T_ref,
                                1 if p0.coupled else 0, 0)
         self.extrapolate = False   # as for DeviceProblem
+        self.extrapolate_order = 2
         self._chain = False
         self.reset()
 
@@ -246,7 +262,8 @@ class BatchProblem:
         return self.T[a:a + n].cpu().numpy(), self.V[a:a + n].cpu().numpy()
 
     def step(self, tol: float = 1e-12, precision: str = "fp64", **kw):
-        self.phys.extrapolate = (1 if self._chain else 2) if self.extrapolate else 0
+        self.phys.extrapolate = _extrapolate_mode(self.extrapolate, self.extrapolate_order,
+                                                  self._chain)
         self._chain = False
         info = rafem.step(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e, self.dir_V,
                           self.dir_T, self.T, self.V, tol=tol, precision=precision, **kw)
