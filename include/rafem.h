@@ -324,20 +324,19 @@ typedef struct {
                              (k, perfusion, rho_c unchanged); E_STATE if there is none; a
                              matrix built for another dt is rebuilt regardless */
     int32_t extrapolate;  /* rafem_step of a coupled problem only.  1: this call continues the
-                             trajectory of the previous rafem_step call on this handle; both
-                             solves start from the linear extrapolation in time
-                             T^n + (dt/dt_prev)(T^n - T^{n-1}), and the same for V (sigma and the
-                             right-hand side still use T^n), the handle keeping T^{n-1}, V^{n-1}
-                             from that call.  2: a new trajectory starts here (solves start from
-                             T_d, V_d; the states are kept for the next call).  3: as 1, but once
-                             the handle keeps two earlier states of the trajectory the solves start
-                             from the quadratic extrapolation: the Lagrange polynomial through
-                             (t_n, T^n), (t_n - h1, T^{n-1}), (t_n - h1 - h2, T^{n-2}) taken at
-                             t_n + dt, h1 and h2 being the dt of the two previous calls (and the
-                             same for V).  0: off.  A call with 0, a failed call, rafem_step_pc and
-                             rafem_step_mono end the trajectory (the next call with 1 or 3 then
-                             behaves as 2).  Other values: E_ARG. */
-    int32_t pad;
+                             trajectory of the previous rafem_step call on this handle: both
+                             solves start from the polynomial extrapolation in time of the
+                             states kept from the trajectory's calls (sigma and the right-hand
+                             side still use T^n): the Lagrange polynomial through (t_n, T^n),
+                             (t_n - h1, T^{n-1}), ..., (t_n - h1 - ... - hq, T^{n-q}) taken at
+                             t_n + dt, h_k being the dt of the k-th previous call, q the lesser
+                             of extrapolate_order and the number of earlier states kept (up to 4);
+                             the same for V.  q = 1 is T^n + (dt/h1)(T^n - T^{n-1}).  2: a new
+                             trajectory starts here (solves start from T_d, V_d; the states are
+                             kept for the next call).  0: off.  A call with 0, a failed call,
+                             rafem_step_pc and rafem_step_mono end the trajectory (the next call
+                             with 1 then behaves as 2).  Other values: E_ARG. */
+    int32_t extrapolate_order; /* 1 (linear; also 0) .. 4 (quartic); other values: E_ARG */
 } rafem_phys;
 
 typedef struct {

@@ -113,7 +113,8 @@ class Regions(C.Structure):
 class Phys(C.Structure):
     _fields_ = [("rho_c", C.c_double), ("dt", C.c_double), ("T_a", C.c_double),
                 ("alpha_sigma", C.c_double), ("T_ref", C.c_double), ("coupled", C.c_int32),
-                ("reuse_bioheat", C.c_int32), ("extrapolate", C.c_int32), ("pad", C.c_int32)]
+                ("reuse_bioheat", C.c_int32), ("extrapolate", C.c_int32),
+                ("extrapolate_order", C.c_int32)]
 
 
 class StepInfo(C.Structure):

@@ -367,7 +367,7 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             m->pc_Tn = dalloc<double>(m, N);
             m->pc_Vn = dalloc<double>(m, N);
             m->pc_Tk = dalloc<double>(m, N);
-            for (int k = 0; k < 3; ++k) {  // extrapolation histories (phys->extrapolate)
+            for (int k = 0; k < rafem_mesh_s::kXgSlots; ++k) {  // extrapolation histories
                 m->xg_T[k] = dalloc<double>(m, N);
                 m->xg_V[k] = dalloc<double>(m, N);
             }
@@ -1024,48 +1024,63 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
         const bool reuse = phys->reuse_bioheat && m->bioheat_dt == phys->dt;
         hipStream_t s = (hipStream_t)stream;
         region_begin(m);
-        if (phys->extrapolate < 0 || phys->extrapolate > 3)
-            throw Error{RAFEM_E_ARG, "phys.extrapolate must be 0, 1, 2 or 3"};
+        if (phys->extrapolate < 0 || phys->extrapolate > 2)
+            throw Error{RAFEM_E_ARG, "phys.extrapolate must be 0, 1 or 2"};
+        if (phys->extrapolate_order < 0 || phys->extrapolate_order > rafem_mesh_s::kXgSlots - 1)
+            throw Error{RAFEM_E_ARG, "phys.extrapolate_order must be in [0, 4]"};
         if (!phys->extrapolate) {
-            m->xg_ready = m->xg_ready2 = false;
+            m->xg_kept = 0;
             const rafem_status st = step_core(m, phys, reuse, k_e_d, perf_e_d, sigma0_e_d,
                                               dir_V_d, dir_T_d, T_d, T_d, T_d, V_d, o, inf, s);
             region_flush(m, s);
             return st;
         }
-        // keep (T^n, V^n) in slot xg_cur; the slot before it in the ring holds (T^{n-1},
-        // V^{n-1}) when xg_ready, the one before that (T^{n-2}, V^{n-2}) when xg_ready2
-        if (phys->extrapolate == 2) m->xg_ready = m->xg_ready2 = false;
+        // keep (T^n, V^n) in slot xg_cur; start the solves from the polynomial through it and
+        // the kept earlier states (at most `order` of them), taken at t_n + dt
+        if (phys->extrapolate == 2) m->xg_kept = 0;
+        const int order = std::max(1, phys->extrapolate_order);
+        const int K = rafem_mesh_s::kXgSlots;
         const size_t bytes = (size_t)m->n * sizeof(double);
-        const int cur = m->xg_cur, prev1 = (cur + 2) % 3, prev2 = (cur + 1) % 3;
+        const int cur = m->xg_cur;
         double* Tn = m->xg_T[cur];
         double* Vn = m->xg_V[cur];
         region_mark(m, kRegCheck, s);
         RAFEM_HIP(hipMemcpyAsync(Tn, T_d, bytes, hipMemcpyDeviceToDevice, s));
         if (phys->coupled) RAFEM_HIP(hipMemcpyAsync(Vn, V_d, bytes, hipMemcpyDeviceToDevice, s));
-        if (phys->extrapolate == 3 && m->xg_ready && m->xg_ready2) {
-            // Lagrange weights of the states at t_n, t_n - h1, t_n - h1 - h2, taken at t_n + dt
-            const double tau = phys->dt, h1 = m->xg_dt, h2 = m->xg_dt2;
-            const double wa = (tau + h1) * (tau + h1 + h2) / (h1 * (h1 + h2));
-            const double wb = -tau * (tau + h1 + h2) / (h1 * h2);
-            const double wc = tau * (tau + h1) / ((h1 + h2) * h2);
-            launch_extrapolate2((int)m->n, Tn, m->xg_T[prev1], m->xg_T[prev2], wa, wb, wc, T_d, s);
-            if (phys->coupled)
-                launch_extrapolate2((int)m->n, Vn, m->xg_V[prev1], m->xg_V[prev2], wa, wb, wc, V_d,
-                                    s);
-        } else if (m->xg_ready) {
-            const double c = phys->dt / m->xg_dt;
-            launch_extrapolate((int)m->n, Tn, m->xg_T[prev1], c, T_d, s);
-            if (phys->coupled) launch_extrapolate((int)m->n, Vn, m->xg_V[prev1], c, V_d, s);
+        const int q = std::min(order, m->xg_kept);
+        if (q == 1) {
+            const double c = phys->dt / m->xg_h[0];
+            const int p1 = (cur + K - 1) % K;
+            launch_extrapolate((int)m->n, Tn, m->xg_T[p1], c, T_d, s);
+            if (phys->coupled) launch_extrapolate((int)m->n, Vn, m->xg_V[p1], c, V_d, s);
+        } else if (q >= 2) {
+            // Lagrange weights of the nodes t_k = t_n - (h_1 + ... + h_k), k = 0 .. q
+            double t[rafem_mesh_s::kXgSlots] = {}, w[rafem_mesh_s::kXgSlots];
+            for (int k = 1; k <= q; ++k) t[k] = t[k - 1] - m->xg_h[k - 1];
+            for (int i = 0; i <= q; ++i) {
+                w[i] = 1.0;
+                for (int k = 0; k <= q; ++k)
+                    if (k != i) w[i] *= (phys->dt - t[k]) / (t[i] - t[k]);
+            }
+            const double* xT[rafem_mesh_s::kXgSlots];
+            const double* xV[rafem_mesh_s::kXgSlots];
+            for (int k = 0; k <= q; ++k) {
+                xT[k] = m->xg_T[(cur + K - k) % K];
+                xV[k] = m->xg_V[(cur + K - k) % K];
+            }
+            launch_extrapolate_poly((int)m->n, q + 1, xT, w, T_d, s);
+            if (phys->coupled) launch_extrapolate_poly((int)m->n, q + 1, xV, w, V_d, s);
         }
         const rafem_status st = step_core(m, phys, reuse, k_e_d, perf_e_d, sigma0_e_d, dir_V_d,
                                           dir_T_d, Tn, Tn, T_d, V_d, o, inf, s);
-        const bool ok = st == RAFEM_OK && phys->coupled;
-        m->xg_ready2 = ok && m->xg_ready;
-        m->xg_ready = ok;
-        m->xg_dt2 = m->xg_dt;
-        m->xg_cur = (cur + 1) % 3;
-        m->xg_dt = phys->dt;
+        if (st == RAFEM_OK && phys->coupled) {
+            m->xg_kept = std::min(m->xg_kept + 1, K - 1);
+            for (int k = K - 2; k > 0; --k) m->xg_h[k] = m->xg_h[k - 1];
+            m->xg_h[0] = phys->dt;
+        } else {
+            m->xg_kept = 0;
+        }
+        m->xg_cur = (cur + 1) % K;
         region_flush(m, s);
         return st;
     });
@@ -1091,7 +1106,7 @@ rafem_status rafem_step_pc(rafem_mesh m, const rafem_phys* phys, const double* k
         rafem_corrector_info& ci = info ? *info : local;
         std::memset(&ci, 0, sizeof(ci));
         const size_t bytes = (size_t)m->n * sizeof(double);
-        m->xg_ready = m->xg_ready2 = false;
+        m->xg_kept = 0;
         region_begin(m);
         region_mark(m, kRegCheck, s);
         // keep (T^n, V^n) to restore a rejected step; predictor into pc_Tk
@@ -1215,7 +1230,7 @@ rafem_status rafem_step_mono(rafem_mesh m, const rafem_phys* phys, const double*
         std::memset(&mi, 0, sizeof(mi));
         mono_ensure(m, o.m, o.precision == RAFEM_MIXED);
         const size_t bytes = (size_t)m->n * sizeof(double);
-        m->xg_ready = m->xg_ready2 = false;
+        m->xg_kept = 0;
         region_begin(m);
         region_mark(m, kRegCheck, s);
         // keep (T^n, V^n) to restore a rejected step; the iterate starts at (T*, V^n) with

@@ -296,9 +296,9 @@ void launch_loss(int64_t n, const int32_t* ids, const double* target, const doub
 // out = a + c (a - b) (b may be NULL: out = a); the predictor's linear extrapolation.
 void launch_extrapolate(int n, const double* a, const double* b, double c, double* out,
                         hipStream_t s);
-// Quadratic predictor out = wa a + wb b + wc c.
-void launch_extrapolate2(int n, const double* a, const double* b, const double* c, double wa,
-                         double wb, double wc, double* out, hipStream_t s);
+// Polynomial predictor out = sum_k w[k] x[k], k < terms (3 to 5).
+void launch_extrapolate_poly(int n, int terms, const double* const* x, const double* w,
+                             double* out, hipStream_t s);
 // norm2[0] = sum (x - y)^2, norm2[1] = sum x^2, deterministically (partials: >= n/256 + 1).
 void launch_change_norm(int n, const double* x, const double* y, double* partials,
                         double* norm2, hipStream_t s);
@@ -479,15 +479,15 @@ struct rafem_mesh_s {
     // and the two sums of the change norm
     double *pc_Tn = nullptr, *pc_Vn = nullptr, *pc_Tk = nullptr, *pc_norm = nullptr;
     // extrapolated starting points of rafem_step (phys->extrapolate): the states at the start
-    // of the last two calls (slot xg_cur receives the next)
-    double *xg_T[3] = {nullptr, nullptr, nullptr}, *xg_V[3] = {nullptr, nullptr, nullptr};
+    // of the last calls: slot xg_cur receives the next; the kept earlier states T^{n-k}
+    // (k = 1 .. xg_kept) sit in slot (xg_cur - k) mod kXgSlots, xg_h[k-1] being the time step
+    // that led from T^{n-k} to T^{n-k+1}
+    static constexpr int kXgSlots = 5;
+    double* xg_T[kXgSlots] = {};
+    double* xg_V[kXgSlots] = {};
     int xg_cur = 0;
-    bool xg_ready = false;
-    double xg_dt = 0.0;
-    // a second kept state (T^{n-2}, V^{n-2}) in slot (xg_cur + 1) % 3, and the step before
-    // xg_dt, for the quadratic predictor
-    bool xg_ready2 = false;
-    double xg_dt2 = 0.0;
+    int xg_kept = 0;
+    double xg_h[kXgSlots - 1] = {};
     bool potential_ready = false;  // a step has assembled the potential matrix
     double *adj_mu = nullptr, *adj_nu = nullptr, *adj_sbar = nullptr, *adj_dsig = nullptr;
     // iteration counts of the previous solve of each kind and precision (first-chunk guesses)

@@ -563,14 +563,20 @@ __global__ __launch_bounds__(WG) void k_extrapolate(int n, const double* __restr
     if (i < n) out[i] = b ? a[i] + c * (a[i] - b[i]) : a[i];
 }
 
-// Quadratic predictor: out = wa a + wb b + wc c (Lagrange weights of three past states).
-__global__ __launch_bounds__(WG) void k_extrapolate2(int n, const double* __restrict__ a,
-                                                     const double* __restrict__ b,
-                                                     const double* __restrict__ c, double wa,
-                                                     double wb, double wc,
-                                                     double* __restrict__ out) {
+// Polynomial predictor: out = sum_k w_k x_k over the `terms` (3 to 5) kept states, in order.
+struct PolyArgs {
+    const double* x[5];
+    double w[5];
+};
+
+__global__ __launch_bounds__(WG) void k_extrapolate_poly(int n, int terms, PolyArgs a,
+                                                         double* __restrict__ out) {
     const int i = blockIdx.x * WG + threadIdx.x;
-    if (i < n) out[i] = wa * a[i] + wb * b[i] + wc * c[i];
+    if (i >= n) return;
+    double v = a.w[0] * a.x[0][i] + a.w[1] * a.x[1][i] + a.w[2] * a.x[2][i];
+    if (terms > 3) v += a.w[3] * a.x[3][i];
+    if (terms > 4) v += a.w[4] * a.x[4][i];
+    out[i] = v;
 }
 
 // Sums of (x - y)^2 and x^2: per-block partials, then one block adds them in order.
@@ -737,11 +743,15 @@ void launch_extrapolate(int n, const double* a, const double* b, double c, doubl
         hipLaunchKernelGGL(k_extrapolate, dim3(grid1(n)), dim3(WG), 0, s, n, a, b, c, out);
 }
 
-void launch_extrapolate2(int n, const double* a, const double* b, const double* c, double wa,
-                         double wb, double wc, double* out, hipStream_t s) {
+void launch_extrapolate_poly(int n, int terms, const double* const* x, const double* w,
+                             double* out, hipStream_t s) {
+    PolyArgs a;
+    for (int k = 0; k < 5; ++k) {
+        a.x[k] = k < terms ? x[k] : x[0];
+        a.w[k] = k < terms ? w[k] : 0.0;
+    }
     if (n > 0)
-        hipLaunchKernelGGL(k_extrapolate2, dim3(grid1(n)), dim3(WG), 0, s, n, a, b, c, wa, wb, wc,
-                           out);
+        hipLaunchKernelGGL(k_extrapolate_poly, dim3(grid1(n)), dim3(WG), 0, s, n, terms, a, out);
 }
 
 void launch_change_norm(int n, const double* x, const double* y, double* partials,

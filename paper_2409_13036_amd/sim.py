@@ -54,16 +54,12 @@ def rcm_reordered(problem, window: int = 0):
 
 
 
-def _extrapolate_mode(on: bool, order: int, chain: bool) -> int:
-    """phys.extrapolate for a step: 0 off, 2 a new trajectory, 1 / 3 continue linearly /
-    quadratically."""
+def _extrapolate_mode(on: bool, chain: bool) -> int:
+    """phys.extrapolate for a step: 0 off, 2 a new trajectory, 1 continue it."""
     if not on:
         return 0
-    if not chain:
-        return 2
-    if order not in (1, 2):
-        raise ValueError("extrapolate_order must be 1 or 2")
-    return 3 if order == 2 else 1
+    return 1 if chain else 2
+
 
 class DeviceProblem:
     def __init__(self, problem, device=None):
@@ -80,11 +76,11 @@ class DeviceProblem:
         self.dir_T = torch.as_tensor(problem.dir_T, **f64).contiguous()
         self.phys = rafem.Phys(problem.rho_c, problem.dt, problem.T_a, problem.alpha_sigma,
                                problem.T_ref, 1 if problem.coupled else 0, 0)
-        # extrapolate: start each step's solves from the extrapolation of the last states
-        # (library-side), linear (order 1: two states) or quadratic (order 2: three states,
-        # linear until three are kept); _chain: the next step continues the previous one
+        # extrapolate: start each step's solves from the polynomial extrapolation of the last
+        # states (library-side) of the given order (1 linear .. 4 quartic; lower orders until
+        # enough states are kept); _chain: the next step continues the previous one
         self.extrapolate = False
-        self.extrapolate_order = 2
+        self.extrapolate_order = 3
         self._chain = False
         self.loss_ids = self.T_target = None
         if problem.loss_ids is not None:
@@ -114,8 +110,8 @@ class DeviceProblem:
 
     def step(self, tol: float = 1e-12, precision: str = "fp64", **kw):
         """One coupled step (the bioheat matrix is assembled on the first call only)."""
-        self.phys.extrapolate = _extrapolate_mode(self.extrapolate, self.extrapolate_order,
-                                                  self._chain)
+        self.phys.extrapolate = _extrapolate_mode(self.extrapolate, self._chain)
+        self.phys.extrapolate_order = self.extrapolate_order
         self._chain = False
         info = rafem.step(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e, self.dir_V,
                           self.dir_T, self.T, self.V, tol=tol, precision=precision, **kw)
@@ -237,7 +233,7 @@ class BatchProblem:
         self.phys = rafem.Phys(p0.rho_c, p0.dt, p0.T_a, p0.alpha_sigma, p0.T_ref,
                                1 if p0.coupled else 0, 0)
         self.extrapolate = False   # as for DeviceProblem
-        self.extrapolate_order = 2
+        self.extrapolate_order = 3
         self._chain = False
         self.reset()
 
@@ -262,8 +258,8 @@ class BatchProblem:
         return self.T[a:a + n].cpu().numpy(), self.V[a:a + n].cpu().numpy()
 
     def step(self, tol: float = 1e-12, precision: str = "fp64", **kw):
-        self.phys.extrapolate = _extrapolate_mode(self.extrapolate, self.extrapolate_order,
-                                                  self._chain)
+        self.phys.extrapolate = _extrapolate_mode(self.extrapolate, self._chain)
+        self.phys.extrapolate_order = self.extrapolate_order
         self._chain = False
         info = rafem.step(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e, self.dir_V,
                           self.dir_T, self.T, self.V, tol=tol, precision=precision, **kw)

@@ -25,46 +25,46 @@ def torch_cuda():
 
 @pytest.mark.parametrize("kind,n", [("hex", 15), ("tet", 11)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_extrapolated_steps_match_oracle_with_fewer_iterations(torch_cuda, kind, n, precision,
                                                                order):
     from paper_2409_13036_amd.sim import DeviceProblem
     p = ri.make_problem(kind, n, 0)
-    ref, _ = Model(p).simulate(7, 1e-15)
+    ref, _ = Model(p).simulate(11, 1e-15)
     plain = DeviceProblem(p)
-    _, info0 = plain.simulate(7, tol=TOL, precision=precision)
+    _, info0 = plain.simulate(11, tol=TOL, precision=precision)
     plain.close()
     dp = DeviceProblem(p)
     dp.extrapolate = True
     dp.extrapolate_order = order
-    states, info1 = dp.simulate(7, tol=TOL, precision=precision, keep=True)
+    states, info1 = dp.simulate(11, tol=TOL, precision=precision, keep=True)
     dp.close()
     for (T, V), (Tr, Vr) in zip(states, ref):
         assert rel_err(T, Tr) <= 1e-8 and rel_err(V, Vr) <= 1e-8
-    # from the first step whose kept states are all solver results (the first kept state is
-    # the initial one, whose V is not a solution)
-    first = 2 if order == 1 else 3
+    # from a few steps after the start of the trajectory (the first kept state is the initial
+    # one, whose V is not a solution, and higher orders need a smooth history)
+    first = 2 * order + 1
     it0 = sum(i["V"]["iters"] + i["T"]["iters"] for i in info0[first:])
     it1 = sum(i["V"]["iters"] + i["T"]["iters"] for i in info1[first:])
-    print(f"[extrapolate order {order} {kind}{n} {precision}] iterations of steps {first + 1}-7: "
+    print(f"[extrapolate order {order} {kind}{n} {precision}] iterations of steps {first + 1}-11: "
           f"{it1} (plain {it0})", flush=True)
     assert it1 < it0
     # the first two steps start a trajectory: identical to plain steps
     assert info1[0]["V"]["iters"] == info0[0]["V"]["iters"]
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 def test_predictor_is_the_lagrange_extrapolation_of_the_kept_states(torch_cuda, order):
     """With a tolerance every starting point meets, the solves run no iteration and return
-    their starting points: after steps of 1, 0.5 and 2 s, a step of 1.5 s returns (on the free
-    nodes) the linear extrapolation of the last two kept states, or the quadratic Lagrange
-    extrapolation of the last three, for unequal steps."""
+    their starting points: after steps of 1, 0.5, 2, 0.75 and 1.25 s, a step of 1.5 s returns
+    (on the free nodes) the Lagrange extrapolation of the last order + 1 kept states, for
+    unequal steps."""
     from paper_2409_13036_amd.sim import DeviceProblem
     p = ri.make_problem("hex", 11, 2)
     dp = DeviceProblem(p)
     dp.extrapolate = True
     dp.extrapolate_order = order
-    dts = [1.0, 0.5, 2.0]
+    dts = [1.0, 0.5, 2.0, 0.75, 1.25]
     kept_T, kept_V = [], []
     for dt in dts:
         dp.phys.dt = dt
@@ -73,24 +73,25 @@ def test_predictor_is_the_lagrange_extrapolation_of_the_kept_states(torch_cuda, 
         dp.step(TOL)
     kept_T.append(to_host(dp.T))
     kept_V.append(to_host(dp.V))
-    tau, h1, h2 = 1.5, dts[2], dts[1]
+    tau = 1.5
     dp.phys.dt = tau
     info = dp.step(1e30)
     assert info["V"]["iters"] == 0 and info["T"]["iters"] == 0
+    # nodes t_0 = 0 (the current state), t_k = t_{k-1} - (step that led to state k-1)
+    t = [0.0]
+    for k in range(1, order + 1):
+        t.append(t[-1] - dts[-k])
+    w = [np.prod([(tau - t[k]) / (t[i] - t[k]) for k in range(order + 1) if k != i])
+         for i in range(order + 1)]
     free = np.ones(p.n_nodes, dtype=bool)
     free[p.dir_ids] = False
     for got, kept in ((to_host(dp.T), kept_T), (to_host(dp.V), kept_V)):
-        a, b, c = kept[3], kept[2], kept[1]
-        if order == 1:
-            want = a + (tau / h1) * (a - b)
-        else:
-            # Lagrange basis at t_n + tau for the nodes t_n, t_n - h1, t_n - h1 - h2
-            t = np.array([0.0, -h1, -h1 - h2])
-            w = [np.prod([(tau - t[k]) / (t[i] - t[k]) for k in range(3) if k != i])
-                 for i in range(3)]
-            want = w[0] * a + w[1] * b + w[2] * c
+        want = sum(w[i] * kept[-1 - i] for i in range(order + 1))
         scale = np.abs(want[free]).max()
-        assert np.abs(got[free] - want[free]).max() <= 1e-13 * scale
+        err = np.abs(got[free] - want[free]).max()
+        print(f"[predictor order {order}] max error {err / scale:.1e} of max |value|",
+              flush=True)
+        assert err <= 1e-13 * scale
     dp.close()
 
 
