@@ -678,7 +678,7 @@ def main():
     ap.add_argument("--fd-params", type=int, default=32)
     ap.add_argument("--workload", choices=["c1", "c2"], default="c1",
                     help="c1: 101^3 hex (default); c2: 161^3-node jittered Kuhn tets")
-    ap.add_argument("--extrapolate-order", type=int, default=3, choices=(1, 2, 3, 4),
+    ap.add_argument("--extrapolate-order", type=int, default=2, choices=(1, 2, 3, 4),
                     help="order of the predictor of the solves' starting points")
     ap.add_argument("--no-extrapolate", action="store_true",
                     help="start every solve from the previous state instead of the linear "

@@ -80,7 +80,7 @@ class DeviceProblem:
         # states (library-side) of the given order (1 linear .. 4 quartic; lower orders until
         # enough states are kept); _chain: the next step continues the previous one
         self.extrapolate = False
-        self.extrapolate_order = 3
+        self.extrapolate_order = 2
         self._chain = False
         self.loss_ids = self.T_target = None
         if problem.loss_ids is not None:
@@ -233,7 +233,7 @@ class BatchProblem:
         self.phys = rafem.Phys(p0.rho_c, p0.dt, p0.T_a, p0.alpha_sigma, p0.T_ref,
                                1 if p0.coupled else 0, 0)
         self.extrapolate = False   # as for DeviceProblem
-        self.extrapolate_order = 3
+        self.extrapolate_order = 2
         self._chain = False
         self.reset()
 
