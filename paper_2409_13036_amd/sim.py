@@ -54,9 +54,11 @@ def rcm_reordered(problem, window: int = 0):
 
 
 
-def _extrapolate_mode(on: bool, chain: bool) -> int:
-    """phys.extrapolate for a step: 0 off, 2 a new trajectory, 1 continue it."""
-    if not on:
+def _extrapolate_mode(on: bool, chain: bool, fresh: bool) -> int:
+    """phys.extrapolate for a step: 0 off (also for the first step from the problem's initial
+    state, whose V is not a solution and would spoil the predictor), 2 a new trajectory, 1
+    continue it."""
+    if not on or fresh:
         return 0
     return 1 if chain else 2
 
@@ -100,6 +102,7 @@ class DeviceProblem:
         self.T.copy_(T)
         self.V.copy_(V)
         self._chain = False
+        self._fresh = False
 
     def reset(self, T0: Optional[np.ndarray] = None, V0: Optional[np.ndarray] = None):
         torch = self.torch
@@ -107,16 +110,18 @@ class DeviceProblem:
         self.T = torch.as_tensor(self.p.initial_T() if T0 is None else T0, **f64).clone()
         self.V = torch.as_tensor(self.p.initial_V() if V0 is None else V0, **f64).clone()
         self._chain = False
+        self._fresh = V0 is None  # V is the initial field, not a solution
 
     def step(self, tol: float = 1e-12, precision: str = "fp64", **kw):
         """One coupled step (the bioheat matrix is assembled on the first call only)."""
-        self.phys.extrapolate = _extrapolate_mode(self.extrapolate, self._chain)
+        self.phys.extrapolate = _extrapolate_mode(self.extrapolate, self._chain, self._fresh)
         self.phys.extrapolate_order = self.extrapolate_order
         self._chain = False
         info = rafem.step(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e, self.dir_V,
                           self.dir_T, self.T, self.V, tol=tol, precision=precision, **kw)
         self.phys.reuse_bioheat = 1
-        self._chain = bool(self.extrapolate)
+        self._chain = bool(self.extrapolate) and not self._fresh
+        self._fresh = False
         return info
 
     def simulate(self, steps: int, tol: float = 1e-12, precision: str = "fp64", keep: bool = False,
@@ -142,6 +147,8 @@ class DeviceProblem:
         finally:
             self.phys.dt = float(self.p.dt)  # plain steps keep the problem's step; the library
         self.phys.reuse_bioheat = 1          # rebuilds a bioheat matrix made for another dt
+        if info.get("accepted"):
+            self._fresh = False
         return info
 
     def step_mono(self, dt: float, T_prev=None, dt_prev=None, corr_tol: float = 1e-10,
@@ -158,6 +165,8 @@ class DeviceProblem:
                                    gmres_tol=gmres_tol, gmres_precision=gmres_precision, **kw)
         finally:
             self.phys.dt = float(self.p.dt)
+        if info.get("accepted"):
+            self._fresh = False
         return info
 
     def simulate_pc(self, t_total: float, dt0: float, corr_tol: float = 1e-10,
@@ -250,6 +259,7 @@ class BatchProblem:
         self.T = torch.as_tensor(self._gather([p.initial_T() for p in self.problems]), **f64)
         self.V = torch.as_tensor(self._gather([p.initial_V() for p in self.problems]), **f64)
         self._chain = False
+        self._fresh = True
 
     def sample(self, q: int):
         """(T, V) of sample q as host arrays."""
@@ -258,13 +268,14 @@ class BatchProblem:
         return self.T[a:a + n].cpu().numpy(), self.V[a:a + n].cpu().numpy()
 
     def step(self, tol: float = 1e-12, precision: str = "fp64", **kw):
-        self.phys.extrapolate = _extrapolate_mode(self.extrapolate, self._chain)
+        self.phys.extrapolate = _extrapolate_mode(self.extrapolate, self._chain, self._fresh)
         self.phys.extrapolate_order = self.extrapolate_order
         self._chain = False
         info = rafem.step(self.mesh, self.phys, self.k_e, self.perf_e, self.sigma0_e, self.dir_V,
                           self.dir_T, self.T, self.V, tol=tol, precision=precision, **kw)
         self.phys.reuse_bioheat = 1
-        self._chain = bool(self.extrapolate)
+        self._chain = bool(self.extrapolate) and not self._fresh
+        self._fresh = False
         return info
 
     def close(self):
