@@ -668,8 +668,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=101)
     ap.add_argument("--profile-steps", type=int, default=3)
-    ap.add_argument("--inner-tol", type=float, default=0.0,
-                    help="relative tolerance of each FP32 inner solve (0: library default)")
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="relative tolerance of each FP32 inner solve (default: 1e-4 for the "
+                         "worse-conditioned c2 potential system, else the library's 3e-5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-child", action="store_true")
     ap.add_argument("--adjoint", action="store_true",
@@ -769,7 +770,10 @@ def main():
     mesh_stats = dp.mesh.stats()
     res = {}
     for precision in ("fp64", "mixed"):
-        kw = {"inner_tol": args.inner_tol} if precision == "mixed" else {}
+        inner_tol = args.inner_tol
+        if inner_tol is None:
+            inner_tol = 1e-4 if args.workload == "c2" else 0.0
+        kw = {"inner_tol": inner_tol} if precision == "mixed" else {}
         el, infos, state, (mean_us, count) = run_path(dp, precision, args.steps, args.warmup,
                                                       args.profile_steps, **kw)
         it_v = float(np.mean([i["V"]["iters"] for i in infos]))

@@ -217,7 +217,7 @@ typedef struct {
                             FP64 true residual of the refinement in MIXED) */
     int32_t maxit;       /* limit on (inner) PCG iterations per solve; <= 0 means 20000 */
     int32_t precision;   /* RAFEM_FP64 or RAFEM_MIXED */
-    double  inner_tol;   /* MIXED: relative tolerance of each inner solve (0 means 1e-4); an
+    double  inner_tol;   /* MIXED: relative tolerance of each inner solve (0 means 3e-5); an
                             inner solve stops earlier when a tenth of the reduction the FP64
                             tolerance still needs is reached (the last refinement) */
     int32_t max_outer;   /* MIXED: refinement limit (<= 0 means 30) */

@@ -236,7 +236,7 @@ SolveOpts resolve_opts(const rafem_solve_opts* o, double default_tol) {
         r.tol = o->tol;
         r.maxit = o->maxit > 0 ? o->maxit : 20000;
         r.precision = o->precision;
-        r.inner_tol = o->inner_tol > 0.0 ? o->inner_tol : 1e-4;
+        r.inner_tol = o->inner_tol > 0.0 ? o->inner_tol : 3e-5;
         r.max_outer = o->max_outer > 0 ? o->max_outer : 30;
         r.poll_every = o->poll_every;
     }
