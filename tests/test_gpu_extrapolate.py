@@ -139,3 +139,19 @@ def test_extrapolated_ensemble_matches_its_samples_alone(torch_cuda):
             dp.step(TOL, "mixed")
         assert np.array_equal(got[q][0], to_host(dp.T)) and np.array_equal(got[q][1], to_host(dp.V))
         dp.close()
+
+
+def test_bad_predictor_settings_are_rejected_before_any_work(torch_cuda):
+    from paper_2409_13036_amd import _lib as R
+    from paper_2409_13036_amd.sim import DeviceProblem
+    p = ri.make_problem("hex", 9, 0)
+    dp = DeviceProblem(p)
+    T0, V0 = to_host(dp.T), to_host(dp.V)
+    for mode, order in ((3, 1), (-1, 1), (1, 5), (1, -1)):
+        dp.phys.extrapolate, dp.phys.extrapolate_order = mode, order
+        with pytest.raises(R.RafemError) as e:
+            R.step(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, dp.dir_V, dp.dir_T, dp.T,
+                   dp.V, tol=TOL)
+        assert e.value.status == R.E_ARG
+    assert np.array_equal(to_host(dp.T), T0) and np.array_equal(to_host(dp.V), V0)
+    dp.close()
