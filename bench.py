@@ -823,7 +823,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "bytes_per_launch": per_launch,
                      "mean_launch_us": r["spmv_us"], "launches_measured": r["spmv_count"],
-                     "measured_GBs": traffic / (r["spmv_us"] * 1e3) if traffic else None,
+                     "measured_GBs": (traffic / (r["spmv_us"] * 1e3)
+                                      if traffic and r["spmv_us"] > 0 else None),
                      "values_and_vectors_bytes": min_bytes,
                      "cold_cache": {"copies": copies, "mean_launch_us": t_cold,
                                     "achieved": per_launch / (t_cold * 1e3),
