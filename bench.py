@@ -818,7 +818,10 @@ def main():
         "config": {"workload": workload, "n_nodes": N,
                    "nnz": nnz, "dt_s": p.dt, "tol": TOL, "path": head,
                    "slabs": int(mesh_stats.slabs),
-                   "shared_offset_slabs": int(mesh_stats.shared_offset_slabs)},
+                   "shared_offset_slabs": int(mesh_stats.shared_offset_slabs),
+                   "predictor_order": (None if args.no_extrapolate
+                                       else args.extrapolate_order),
+                   "inner_tol": inner_tol if inner_tol else "library default (3e-5)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "bytes_per_launch": per_launch,
