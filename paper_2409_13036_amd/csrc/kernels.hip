@@ -484,14 +484,18 @@ __global__ __launch_bounds__(WG) void k_bioheat_rhs_geo(int count, const int* __
     const double2 g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3];
     const double src = perf[e] * T_a;
     const double sg = with_joule ? sigma[e] : 0.0;
+    // each lane reads its own node (a coalesced read of conn); the group of 8 exchanges them
+    const int lane0 = (int)(threadIdx.x % WAVE) & ~7;
+    const int node_a = conn[(int64_t)e * 8 + a];
+    const double Tw_a = rho_c_dt * T[node_a] + src;
+    const double V_a = with_joule ? V[node_a] : 0.0;
     double xi, et, ze;
     gauss_point(a, xi, et, ze);
     double Nw = 0.0, gv0 = 0.0, gv1 = 0.0, gv2 = 0.0;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-        const int node = conn[(int64_t)e * 8 + b];
-        const double Tw = rho_c_dt * T[node] + src;
-        const double Vb = with_joule ? V[node] : 0.0;
+        const double Tw = __shfl(Tw_a, lane0 + b, WAVE);
+        const double Vb = __shfl(V_a, lane0 + b, WAVE);
         double Nb, d0, d1, d2;
         hex_shape(b, xi, et, ze, Nb, d0, d1, d2);
         Nw += Nb * Tw;
@@ -504,7 +508,6 @@ __global__ __launch_bounds__(WG) void k_bioheat_rhs_geo(int count, const int* __
     const double quad = C00 * gv0 * gv0 + C11 * gv1 * gv1 + C22 * gv2 * gv2 +
                         2.0 * (C01 * gv0 * gv1 + C02 * gv0 * gv2 + C12 * gv1 * gv2);
     const double sq = det * Nw + sg * quad;
-    const int lane0 = (int)(threadIdx.x % WAVE) & ~7;
     double f = 0.0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
