@@ -81,3 +81,14 @@ def test_step_stats_interval():
     # 3 sigma / sqrt(n), sigma the sample standard deviation (1.2910 ms)
     assert abs(s["ci997_halfwidth_ms"] - 3 * 1.2909944487358056 / 2) < 1e-9
     assert bench.step_stats([0.01])["ci997_halfwidth_ms"] is None
+
+
+def test_predictor_modes_of_the_simulation_driver():
+    """sim's phys.extrapolate per step: off, a new trajectory, continuing it, and no history
+    kept for the first step from a problem's initial state (its V is not a solution)."""
+    from paper_2409_13036_amd.sim import _extrapolate_mode
+    assert _extrapolate_mode(False, True, False) == 0
+    assert _extrapolate_mode(True, False, False) == 2
+    assert _extrapolate_mode(True, True, False) == 1
+    assert _extrapolate_mode(True, False, True) == 0
+    assert _extrapolate_mode(True, True, True) == 0
