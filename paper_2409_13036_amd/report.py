@@ -1,6 +1,6 @@
 """Result-quality and region reports of the paper's methodology.
 
-PSNR per simulation step (Sec. V): with A the reference run and B the run under test,
+PSNR per simulation step (Sec. IV, Eq. 1): with A the reference run and B the run under test,
 each a sequence of per-step nodal fields (temperature or potential),
 
     MSE_i  = (1/n) sum_j (A_ij - B_ij)^2,
