@@ -266,6 +266,27 @@ rafem_status rafem_spmv(rafem_mesh mesh, const int32_t* row_ptr_d, const int32_t
                         const double* vals_d, const double* x_d, double* y_d,
                         const float* vals32_d, const float* x32_d, float* y32_d, void* stream);
 
+/* The product of a time step's solves, y = A x, run by the very kernels the PCG
+ * iterations use on the mesh's own slab layout (Sec. III-A: the solve of the assembled
+ * system; Sec. III-B: the structure analysed once per mesh): 64-row slabs with shared
+ * column offsets, 16-bit or 32-bit per-row column offsets, the tuned slab shape, and the
+ * dot product x.(A x) fused into the product.
+ *   matrix     0: the potential matrix, 1: the bioheat matrix, as the last rafem_step (or
+ *              rafem_step_pc / rafem_step_vjp) on this handle assembled them, Dirichlet
+ *              rows and columns lifted (E_STATE before such a step)
+ *   precision  RAFEM_FP64: x_d, y_d are double [n_nodes] and the FP64 values are used;
+ *              RAFEM_MIXED: x_d, y_d are float [n_nodes], FP32 values (the inner PCG's kernel)
+ *   b_d        NULL, or (FP64 only) double [n_nodes]: then y = b - A x with the kernel of
+ *              the refinement residual instead
+ *   dots_h     NULL, or host output, blocking: without b, [n_samples] sums x.(A x) of each
+ *              sample, from the kernel's per-group partials added in slot order; with b,
+ *              [2 n_samples] pairs (||b - A x||^2, ||b||^2) as the solver state holds them
+ * Node vectors use the handle's layout (a batch handle: every sample with its padding).
+ * Returns without synchronising when dots_h is NULL.  Uses the handle's check-state and
+ * partial-sum workspace, so it must not overlap a solve on the same handle. */
+rafem_status rafem_spmv_step(rafem_mesh mesh, int32_t matrix, int32_t precision, const void* x_d,
+                             void* y_d, const double* b_d, double* dots_h, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Measurement.  While enabled, the SpMV kernel of every PCG iteration that the solves
  * on this mesh enqueue carries a pair of HIP events stamped when the kernel itself

@@ -37,7 +37,7 @@ EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafe
            "rafem_mesh_create_batch", "rafem_mesh_sample_layout", "rafem_mesh_set_graphs",
            "rafem_sample_info", "rafem_spmv_timing", "rafem_step_pc", "rafem_mono_jacobian",
            "rafem_mono_solve", "rafem_step_mono", "rafem_rcm_order", "rafem_regions_enable",
-           "rafem_regions_read", "rafem_degree_sort")
+           "rafem_regions_read", "rafem_degree_sort", "rafem_spmv_step")
 
 
 class RafemError(RuntimeError):
@@ -137,6 +137,7 @@ _lib.rafem_solve.argtypes = [_p, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts), C
 _lib.rafem_solve_adjoint.argtypes = [_p, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts),
                                      C.POINTER(SolveInfo), _p]
 _lib.rafem_spmv.argtypes = [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
+_lib.rafem_spmv_step.argtypes = [_p, _i32, _i32, _p, _p, _p, _p, _p]
 _lib.rafem_profile_enable.argtypes = [_p, _i32]
 _lib.rafem_profile_read.argtypes = [_p, _i32, C.POINTER(C.c_double), C.POINTER(C.c_int64), _i32]
 _lib.rafem_regions_enable.argtypes = [_p, _i32]
@@ -489,6 +490,23 @@ def spmv(mesh: Mesh, row_ptr, col_idx, vals, x, y, *, stream=None):
         x, y = _dev(x, torch.float32, n, "x32"), _dev(y, torch.float32, n, "y32")
         _check(_lib.rafem_spmv(mesh.handle, _ptr(row_ptr), _ptr(col_idx), None, None, None, _ptr(vals),
                                _ptr(x), _ptr(y), _stream(stream)))
+
+
+def spmv_step(mesh: Mesh, x, y, *, matrix="potential", b=None, dots=True, stream=None):
+    """rafem_spmv_step: y = A x (or y = b - A x when b is given) with the PCG kernels on the
+    mesh's slab layout.  x, y float64 (FP64 kernel) or float32 (FP32 kernel).  Returns the
+    per-sample x.(A x) (or (||b - A x||^2, ||b||^2) pairs) as a NumPy array when dots."""
+    torch = _torch()
+    n, S = mesh.n_nodes, mesh.n_samples
+    which = {"potential": 0, "bioheat": 1}[matrix]
+    dt = torch.float64 if x.dtype == torch.float64 else torch.float32
+    x, y = _dev(x, dt, n, "x"), _dev(y, dt, n, "y")
+    b = _dev(b, torch.float64, n, "b", allow_none=True)
+    out = np.zeros(2 * S if b is not None else S) if dots else None
+    prec = FP64 if dt == torch.float64 else MIXED
+    _check(_lib.rafem_spmv_step(mesh.handle, which, prec, _ptr(x), _ptr(y), _ptr(b),
+                                out.ctypes.data if dots else None, _stream(stream)))
+    return out
 
 
 def step(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T, V, *, tol=1e-12,

@@ -797,6 +797,66 @@ rafem_status rafem_spmv(rafem_mesh m, const int32_t* row_ptr_d, const int32_t* c
     });
 }
 
+rafem_status rafem_spmv_step(rafem_mesh m, int32_t matrix, int32_t precision, const void* x_d,
+                             void* y_d, const double* b_d, double* dots_h, void* stream) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        require(matrix == 0 || matrix == 1, "matrix must be 0 (potential) or 1 (bioheat)");
+        require(precision == RAFEM_FP64 || precision == RAFEM_MIXED, "precision");
+        require(x_d && y_d, "NULL x or y");
+        require(!b_d || precision == RAFEM_FP64, "the residual form (b given) is FP64 only");
+        if (matrix == 0 && !m->potential_ready)
+            throw Error{RAFEM_E_STATE, "no step has assembled the potential matrix yet"};
+        if (matrix == 1 && !m->bioheat_ready)
+            throw Error{RAFEM_E_STATE, "no step has assembled the bioheat matrix yet"};
+        hipStream_t s = (hipStream_t)stream;
+        const bool fp32 = precision == RAFEM_MIXED;
+        const Mat A = matrix == 0 ? step_matrix(m, m->valsV, m->valsV32)
+                                  : step_matrix(m, m->valsT, m->valsT32);
+        const int S = m->S;
+        const Samples smp = step_samples(m);
+        PcgState* chk = m->st + 2 * S;
+        launch_state_init(chk, S, 0.0, 0, nullptr, s);  // done = 0: no sample is skipped
+        if (b_d) {
+            launch_residual64(A, m->spmv, b_d, (const double*)x_d, (double*)y_d, m->partials, chk,
+                              smp, 0, s);
+            RAFEM_HIP(hipGetLastError());
+            if (dots_h) {
+                std::vector<PcgState> h(S);
+                RAFEM_HIP(hipMemcpyAsync(h.data(), chk, S * sizeof(PcgState),
+                                         hipMemcpyDeviceToHost, s));
+                RAFEM_HIP(hipStreamSynchronize(s));
+                for (int q = 0; q < S; ++q) {
+                    dots_h[2 * q] = h[q].rr;
+                    dots_h[2 * q + 1] = h[q].bb;
+                }
+            }
+            return RAFEM_OK;
+        }
+        const GridInfo g =
+            fp32 ? launch_spmv_dot32(A, m->spmv32, (const float*)x_d, (float*)y_d, m->part_pq,
+                                     chk, smp, s)
+                 : launch_spmv_dot64(A, m->spmv, (const double*)x_d, (double*)y_d, m->part_pq,
+                                     chk, smp, s);
+        RAFEM_HIP(hipGetLastError());
+        if (dots_h) {
+            // the kernel's own per-group partials of x.(A x), added per sample in slot order
+            std::vector<double> part(std::max(g.nb, 1));
+            RAFEM_HIP(hipMemcpyAsync(part.data(), m->part_pq, g.nb * sizeof(double),
+                                     hipMemcpyDeviceToHost, s));
+            RAFEM_HIP(hipStreamSynchronize(s));
+            for (int q = 0; q < S; ++q) {
+                const int64_t b0 = m->node_off[q] / g.rpb;
+                const int64_t b1 = std::min<int64_t>((m->node_off[q + 1] + g.rpb - 1) / g.rpb, g.nb);
+                double t = 0.0;
+                for (int64_t k = b0; k < b1; ++k) t += part[k];
+                dots_h[q] = t;
+            }
+        }
+        return RAFEM_OK;
+    });
+}
+
 rafem_status rafem_spmv_timing(rafem_mesh m, int32_t precision, int32_t n_copies, int32_t reps,
                                double* mean_us) {
     return guard([&]() -> rafem_status {

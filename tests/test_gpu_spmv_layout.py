@@ -1,0 +1,265 @@
+"""GPU parity of the step path's SpMV kernels on the mesh's own slab layout.
+
+The solves of a time step multiply by the assembled matrix with the SELL kernels (Sec.
+III-A: the assembled system is solved; Sec. III-B: the structure is analysed once per
+mesh), not with the CSR kernel of ``rafem_spmv``.  In mixed precision an FP32 product
+defect would only slow the refinement down, so the kernels are checked here row by row
+against the oracle's lifted matrix times x, in both precisions, through
+``rafem_spmv_step``:
+
+- 101^3 hex (the benchmark workload): shared-offset slabs in the interior, 16-bit
+  per-row offsets on the first and last planes, a partial last slab (1,030,301 rows);
+- 41^3 hex with its nodes shuffled: bandwidth beyond 16 bits, so 32-bit columns, no
+  shared offsets;
+- Kuhn tets 161^3 (4.17M rows, jittered): 2,000 sampled rows assembled by the oracle from
+  their incident elements; and tets 25^3 in full;
+- the liver-like mesh A stand-in, as a mesher delivers it and after RCM;
+- an uneven batch of 4 hex samples (each sample against its own oracle matrix).
+
+Bounds: the oracle's values differ from the device's by assembly rounding (64 eps times
+the row's largest entry, per entry) and the product by at most 64 eps sum_j |A_ij x_j|
+(FP32: eps of FP32, which also covers the rounding of the values and of x to FP32).  The
+fused dot x.(A x) is checked against the oracle's within the same bounds.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import rafem_inputs as ri
+from oracle import elements
+from oracle.rafem import Model
+from gpu_helpers import EPS32, EPS64, spmv_bound, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def say(msg):
+    print(f"[spmv-layout] {msg}", flush=True)
+
+
+def _abs(A):
+    return sp.csr_matrix((np.abs(A.data), A.indices, A.indptr), shape=A.shape)
+
+
+def _entry_bound(A, x):
+    """Per-row effect of the assembly tolerance (64 eps x row max per entry) on A x."""
+    rowmax = np.maximum.reduceat(np.abs(A.data), A.indptr[:-1]) if A.nnz else np.zeros(A.shape[0])
+    pattern = sp.csr_matrix((np.ones_like(A.data), A.indices, A.indptr), shape=A.shape)
+    return 64 * EPS64 * rowmax * (pattern @ np.abs(x))
+
+
+def _check_products(R, torch, mesh, A, which, seed, label, node_off=0):
+    """FP64, FP32 and residual forms of the layout SpMV on `which` against the oracle's A."""
+    n_all = mesh.n_nodes
+    n = A.shape[0]
+    x = ri.random_vector(n, seed)
+    xf = np.zeros(n_all)
+    xf[node_off:node_off + n] = x
+    sl = slice(node_off, node_off + n)
+    # FP64 PCG product with its fused dot
+    y = torch.empty(n_all, dtype=torch.float64, device="cuda")
+    dots = R.spmv_step(mesh, to_dev(xf), y, matrix=which)
+    ref = A @ x
+    bound = spmv_bound(A, x, EPS64) + _entry_bound(A, x)
+    got = to_host(y)[sl]
+    err = np.abs(got - ref)
+    say(f"{label} {which} FP64: max |dy| {err.max():.2e}, max |dy|/bound {np.max(err / bound):.2e}")
+    assert np.all(err <= bound)
+    return x, xf, ref, bound, dots
+
+
+def _check_fp32(R, torch, mesh, A, which, x, xf, label, sl):
+    n_all = mesh.n_nodes
+    x32 = x.astype(np.float32).astype(np.float64)
+    y32 = torch.empty(n_all, dtype=torch.float32, device="cuda")
+    dots = R.spmv_step(mesh, to_dev(xf.astype(np.float32)), y32, matrix=which)
+    ref = A @ x32
+    bound = spmv_bound(A, x32, EPS32) + _entry_bound(A, x32)
+    err = np.abs(to_host(y32).astype(np.float64)[sl] - ref)
+    say(f"{label} {which} FP32: max |dy| {err.max():.2e}, max |dy|/bound {np.max(err / bound):.2e}")
+    assert np.all(err <= bound)
+    return x32, ref, bound, dots
+
+
+def _check_residual(R, torch, mesh, A, which, x, xf, label, sl, seed):
+    n_all = mesh.n_nodes
+    n = A.shape[0]
+    b = ri.random_vector(n, seed + 100, -3.0, 3.0)
+    bf = np.zeros(n_all)
+    bf[sl] = b
+    y = torch.empty(n_all, dtype=torch.float64, device="cuda")
+    dots = R.spmv_step(mesh, to_dev(xf), y, matrix=which, b=to_dev(bf))
+    ref = b - A @ x
+    bound = spmv_bound(A, x, EPS64) + _entry_bound(A, x) + 4 * EPS64 * np.abs(b)
+    err = np.abs(to_host(y)[sl] - ref)
+    say(f"{label} {which} residual: max |dr|/bound {np.max(err / bound):.2e}")
+    assert np.all(err <= bound)
+    return ref, bound, dots
+
+
+def _full_case(R, torch, p, label, seed, expect):
+    """One-step device problem, then every product form on both matrices against the oracle."""
+    from paper_2409_13036_amd.sim import DeviceProblem
+    say(f"{label}: N={p.n_nodes} E={p.n_elems}")
+    dp = DeviceProblem(p)
+    dp.step(1e-10)
+    st = dp.mesh.stats()
+    say(f"{label}: slabs {st.slabs}, shared-offset slabs {st.shared_offset_slabs}, "
+        f"int16 columns {st.int16_columns}, longest row {st.max_row_entries}")
+    for key, val in expect.items():
+        got = {"int16": st.int16_columns, "shared": st.shared_offset_slabs}[key]
+        assert (got > 0) == val, (key, got)
+    m = Model(p)
+    mats = {"potential": m.potential_system(m.sigma(p.initial_T()))[0],
+            "bioheat": m.bioheat_system()[0]}
+    sl = slice(0, p.n_nodes)
+    for k, (which, A) in enumerate(mats.items()):
+        x, xf, ref, bound, dots = _check_products(R, torch, dp.mesh, A, which, seed + k, label)
+        xAx = float(x @ ref)
+        assert abs(dots[0] - xAx) <= float(np.abs(x) @ bound) + 1e-12 * abs(xAx)
+        x32, ref32, b32, d32 = _check_fp32(R, torch, dp.mesh, A, which, x, xf, label, sl)
+        assert abs(d32[0] - float(x32 @ ref32)) <= float(np.abs(x32) @ b32) * 2 + 1e-6 * abs(xAx)
+        ref_r, bound_r, dr = _check_residual(R, torch, dp.mesh, A, which, x, xf, label, sl, seed)
+        rr = float(ref_r @ ref_r)
+        assert abs(dr[0] - rr) <= 2 * float(np.abs(ref_r) @ bound_r) + 1e-12 * rr
+    dp.close()
+
+
+def test_hex101_layout_spmv_matches_oracle(torch_cuda):
+    _full_case(R(), torch_cuda, ri.config1(steps=1), "hex101", 11, {"int16": True, "shared": True})
+
+
+def test_hex41_shuffled_int32_columns_match_oracle(torch_cuda):
+    from paper_2409_13036_amd.sim import reorder_nodes
+    p = ri.make_problem("hex", 41, 3)
+    order = np.random.default_rng(5).permutation(p.n_nodes)
+    _full_case(R(), torch_cuda, reorder_nodes(p, order), "hex41-shuffled", 21,
+               {"int16": False, "shared": False})
+
+
+def test_tet25_layout_spmv_matches_oracle(torch_cuda):
+    _full_case(R(), torch_cuda, ri.make_problem("tet", 25, 4), "tet25", 31, {"int16": True})
+
+
+@pytest.mark.parametrize("rcm", [False, True])
+def test_liver_a_layout_spmv_matches_oracle(torch_cuda, rcm):
+    from paper_2409_13036_amd.sim import rcm_reordered
+    p = ri.liver_mesh_a()
+    if rcm:
+        p, _ = rcm_reordered(p)
+    _full_case(R(), torch_cuda, p, f"liverA{'-rcm' if rcm else ''}", 41, {"shared": False})
+
+
+def R():
+    from paper_2409_13036_amd import _lib
+    return _lib
+
+
+def _sampled_rows(p, rows, coef_mass, coef_stiff, x):
+    """(A x)_i of the lifted matrix for free rows i, from the elements touching them, and
+    the bound sum over elements of |A^e_ab x_b| (x zero on Dirichlet columns)."""
+    isD = np.zeros(p.n_nodes, dtype=bool)
+    isD[p.dir_ids] = True
+    xt = np.where(isD, 0.0, x)
+    mark = np.zeros(p.n_nodes, dtype=bool)
+    mark[rows] = True
+    es = np.nonzero(mark[p.conn].any(axis=1))[0]
+    conn = p.conn[es]
+    K, M = elements.element_matrices(p.xyz[conn])
+    Ae = coef_stiff[es][:, None, None] * K
+    if coef_mass is not None:
+        Ae = Ae + coef_mass[es][:, None, None] * M
+    contrib = np.einsum("eab,eb->ea", Ae, xt[conn])
+    absc = np.einsum("eab,eb->ea", np.abs(Ae), np.abs(xt[conn]))
+    index = -np.ones(p.n_nodes, dtype=np.int64)
+    index[rows] = np.arange(len(rows))
+    y = np.zeros(len(rows))
+    s = np.zeros(len(rows))
+    k = index[conn]
+    ok = k >= 0
+    np.add.at(y, k[ok], contrib[ok])
+    np.add.at(s, k[ok], absc[ok])
+    return y, s
+
+
+def test_tet161_layout_spmv_sampled_rows_match_oracle(torch_cuda):
+    from paper_2409_13036_amd.sim import DeviceProblem
+    torch = torch_cuda
+    p = ri.config2(steps=1)
+    say(f"tet161: N={p.n_nodes} E={p.n_elems}")
+    dp = DeviceProblem(p)
+    dp.step(1e-10, "mixed")
+    st = dp.mesh.stats()
+    say(f"tet161: slabs {st.slabs}, shared {st.shared_offset_slabs}, int16 {st.int16_columns}")
+    x = ri.random_vector(p.n_nodes, 51)
+    free = np.setdiff1d(np.arange(p.n_nodes), p.dir_ids)
+    rows = np.sort(np.concatenate([np.random.default_rng(9).choice(free, 1990, replace=False),
+                                   free[-10:]]))   # the last rows sit in the partial last slab
+    Tbar = p.initial_T()[p.conn].mean(axis=1)
+    sig = p.sigma0_e * (1.0 + p.alpha_sigma * (Tbar - p.T_ref))
+    coefs = {"potential": (None, sig), "bioheat": (p.rho_c / p.dt + p.perf_e, p.k_e)}
+    for which, (cm, cs) in coefs.items():
+        y = torch.empty(p.n_nodes, dtype=torch.float64, device="cuda")
+        R().spmv_step(dp.mesh, to_dev(x), y, matrix=which, dots=False)
+        ref, s = _sampled_rows(p, rows, cm, cs, x)
+        err = np.abs(to_host(y)[rows] - ref)
+        say(f"tet161 {which} FP64: max |dy|/scale {np.max(err / s):.2e}")
+        assert np.all(err <= 128 * EPS64 * s)
+        x32 = x.astype(np.float32)
+        y32 = torch.empty(p.n_nodes, dtype=torch.float32, device="cuda")
+        R().spmv_step(dp.mesh, to_dev(x32), y32, matrix=which, dots=False)
+        ref32, s32 = _sampled_rows(p, rows, cm, cs, x32.astype(np.float64))
+        err32 = np.abs(to_host(y32).astype(np.float64)[rows] - ref32)
+        say(f"tet161 {which} FP32: max |dy|/scale {np.max(err32 / s32):.2e}")
+        assert np.all(err32 <= 64 * EPS32 * s32)
+    # Dirichlet rows are unit rows of the lifted matrices: y = x there, bit for bit
+    y = torch.empty(p.n_nodes, dtype=torch.float64, device="cuda")
+    R().spmv_step(dp.mesh, to_dev(x), y, matrix="potential", dots=False)
+    assert np.array_equal(to_host(y)[p.dir_ids], x[p.dir_ids])
+    dp.close()
+
+
+def test_batch_layout_spmv_matches_each_sample_oracle(torch_cuda):
+    from paper_2409_13036_amd.sim import BatchProblem
+    torch = torch_cuda
+    probs = ri.config4(seed=3, samples=4, n_lo=9, n_hi=23, steps=1)
+    say("batch sizes " + str([q.n for q in probs]))
+    bp = BatchProblem(probs)
+    bp.step(1e-10, "mixed")
+    mesh = bp.mesh
+    xf = ri.random_vector(mesh.n_nodes, 61)
+    for which in ("potential", "bioheat"):
+        y = torch.empty(mesh.n_nodes, dtype=torch.float64, device="cuda")
+        dots = R().spmv_step(mesh, to_dev(xf), y, matrix=which)
+        x32 = xf.astype(np.float32)
+        y32 = torch.empty(mesh.n_nodes, dtype=torch.float32, device="cuda")
+        R().spmv_step(mesh, to_dev(x32), y32, matrix=which, dots=False)
+        yh, y32h = to_host(y), to_host(y32).astype(np.float64)
+        for q, p in enumerate(probs):
+            a, n = int(mesh.node_off[q]), p.n_nodes
+            m = Model(p)
+            A = (m.potential_system(m.sigma(p.initial_T()))[0] if which == "potential"
+                 else m.bioheat_system()[0])
+            x = xf[a:a + n]
+            ref = A @ x
+            bound = spmv_bound(A, x, EPS64) + _entry_bound(A, x)
+            assert np.all(np.abs(yh[a:a + n] - ref) <= bound)
+            xq = x32[a:a + n].astype(np.float64)
+            ref32 = A @ xq
+            assert np.all(np.abs(y32h[a:a + n] - ref32) <= spmv_bound(A, xq, EPS32) + _entry_bound(A, xq))
+            # padding rows are isolated unit rows
+            pad = slice(a + n, int(mesh.node_off[q + 1]))
+            assert np.array_equal(yh[pad], xf[pad])
+            # the sample's fused dot covers its rows and its padding
+            xAx = float(x @ ref) + float(xf[pad] @ xf[pad])
+            assert abs(dots[q] - xAx) <= float(np.abs(x) @ bound) + 1e-12 * abs(xAx)
+        say(f"batch {which}: {len(probs)} samples match")
+    bp.close()
