@@ -167,9 +167,14 @@ def adjoint_leg(args) -> dict:
     """Differentiation workload: 101^3 hex, 60 coupled steps, lesion loss, gradients with respect
     to k_e and w_e by the reverse sweep (checkpoints every 10 steps), timed; then central
     finite differences on 32 single parameters drawn from the 1% of elements with the
-    largest adjoint gradients (16 k_e at relative step 1e-6; 16 w_e at 0.1 and 0.05,
-    Richardson-extrapolated) and along the two directions k and w (all entries scaled),
-    forward solves at tol 1e-14."""
+    largest adjoint gradients and along the two directions k and w (all entries scaled),
+    forward solves at tol 1e-14.  Steps are relative to the parameter:
+      k singles: 1e-6 (the stated step), 1e-5 and 1e-4.  The reference is the 1e-5 value:
+        its round-off noise is a tenth of the stated step's and its truncation error is
+        bounded by its spread to the 1e-4 value (truncation grows as h^2);
+      w singles: 0.1 and 0.05, Richardson-extrapolated (a 1e-6 step moves the loss below
+        the solves' round-off; the response is linear far below the tolerance);
+      direction k: 1e-6 (and 1e-5 for its spread); direction w: 1e-3."""
     import numpy as np
     import torch
     import rafem_inputs as ri
@@ -191,67 +196,76 @@ def adjoint_leg(args) -> dict:
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     gk, gw = k.grad.cpu().numpy(), w.grad.cpu().numpy()
-    rng = np.random.default_rng(0)
-    # single parameters where the sensitivity is large: the 1% largest |dL/dk_e| and |dL/dw_e|
-    top_k = np.argsort(-np.abs(gk))[: p.n_elems // 100]
-    top_w = np.argsort(-np.abs(gw))[: p.n_elems // 100]
-    picks = [("k", int(e)) for e in rng.choice(top_k, args.fd_params // 2, replace=False)]
-    picks += [("w", int(e)) for e in rng.choice(top_w, args.fd_params - args.fd_params // 2,
-                                                 replace=False)]
-
-    def final_T(kk, ww):
-        dp.set_params(torch.as_tensor(kk, device=dev), torch.as_tensor(ww, device=dev))
-        dp.reset()
-        for _ in range(p.steps):
-            dp.step(tol)
-        return dp.T.cpu().numpy()
-
-    ids, tgt = p.loss_ids, p.T_target
-
-    def fd_along(dk, dw, h=1e-6):
-        Tp = final_T(p.k_e + h * dk, p.perf_e + h * dw)
-        Tm = final_T(p.k_e - h * dk, p.perf_e - h * dw)
-        a, b = Tp[ids], Tm[ids]
-        return float(np.sum((a - b) * (a + b - 2 * tgt))) / (2 * h)
-
-    rows = []
-    cases = []
-    # One element's perfusion moves the loss by ~1e-14 of itself at a 1e-6 relative step,
-    # below the solves' round-off.  It enters the element's mass coefficient beside
-    # rho_c/dt ~ 3.8e6, so even a 10% step changes that coefficient by < 1e-6 and the
-    # response stays linear far below the check's tolerance: those singles take h = 0.1
-    # and h/2, combined by Richardson extrapolation; |fd(h) - fd(h/2)| is reported.
-    for which, e in picks:
-        d = np.zeros(p.n_elems)
-        d[e] = abs((p.k_e if which == "k" else p.perf_e)[e])
-        cases.append((f"{which}[{e}]", d if which == "k" else 0 * d, d if which == "w" else 0 * d,
-                      1e-6 if which == "k" else 1e-1, which == "w"))
-    cases.append(("direction k", p.k_e.copy(), 0 * p.k_e, 1e-6, False))
-    # along the whole perfusion field a 1e-6 step moves T by ~1e-9 K: 1e-3 there
-    cases.append(("direction w", 0 * p.perf_e, p.perf_e.copy(), 1e-3, False))
-    for name, dk, dw, h, richardson in cases:
-        fd = fd_along(dk, dw, h)
-        row = {"param": name, "h": h}
-        if richardson:
-            fd2 = fd_along(dk, dw, h / 2)
-            row["fd_h"], row["fd_h2"] = fd, fd2
-            row["h_vs_h2"] = abs(fd - fd2) / abs(fd2)
-            fd = (4.0 * fd2 - fd) / 3.0
-        ad = float(gk @ dk + gw @ dw)
-        row.update({"adjoint": ad, "fd": fd, "rel_err": abs(ad - fd) / abs(fd)})
-        rows.append(row)
-        print(f"[adjoint] {name} adjoint {ad:.10e} fd {fd:.10e} rel {row['rel_err']:.2e}"
-              + (f" (h vs h/2 {row['h_vs_h2']:.1e})" if richardson else ""),
-              file=sys.stderr, flush=True)
+    rows = fd_rows(dp, p, gk, gw, args.fd_params // 2, args.fd_params - args.fd_params // 2,
+                   seed=0, tol=tol)
     dp.close()
+    ks = [r for r in rows if r["param"].startswith("k")]
     return {"workload": f"C3 adjoint, {args.n}^3 hex, {p.steps} steps, checkpoints every 10",
             "loss": float(L.detach()), "forward_s": t1 - t0, "backward_s": t2 - t1,
             "fd_checks": len(rows),
-            "fd_max_rel_err_k": max(r["rel_err"] for r in rows if r["param"].startswith("k")),
+            "fd_max_rel_err_k": max(r["rel_err"] for r in ks),
+            "fd_max_rel_err_k_at_stated_step": max(r["rel_err_h1e-06"] for r in ks),
+            "fd_max_noise_k_at_stated_step": max(r["noise_h1e-06"] for r in ks),
+            "fd_max_truncation_k_h1e-05": max(r["trunc_h1e-05"] for r in ks),
             "fd_max_rel_err_directional": max(r["rel_err"] for r in rows
                                               if r["param"].startswith("direction")),
             "fd_max_rel_err_w": max(r["rel_err"] for r in rows if r["param"].startswith("w")),
             "fd": rows}
+
+
+def fd_rows(dp, p, gk, gw, n_k: int, n_w: int, seed: int = 0, tol: float = 1e-14) -> list:
+    """Finite-difference checks of the adjoint gradients (gk, gw) of problem p on device
+    problem dp: n_k conductivity singles and n_w perfusion singles drawn with
+    default_rng(seed) from the 1% of elements with the largest |gradient|, and the two
+    directions; steps as in adjoint_leg.  Returns one row per check."""
+    import numpy as np
+    from paper_2409_13036_amd.adjoint import fd_directional
+
+    rng = np.random.default_rng(seed)
+    top_k = np.argsort(-np.abs(gk))[: max(1, p.n_elems // 100)]
+    top_w = np.argsort(-np.abs(gw))[: max(1, p.n_elems // 100)]
+    picks = [("k", int(e)) for e in rng.choice(top_k, n_k, replace=False)]
+    picks += [("w", int(e)) for e in rng.choice(top_w, n_w, replace=False)]
+
+    def fd(dk, dw, h):
+        return fd_directional(dp, p.k_e, p.perf_e, dk, dw, h, p.steps, tol)
+
+    rows = []
+    for which, e in picks:
+        d = np.zeros(p.n_elems)
+        d[e] = abs((p.k_e if which == "k" else p.perf_e)[e])
+        dk, dw = (d, 0 * d) if which == "k" else (0 * d, d)
+        ad = float(gk @ dk + gw @ dw)
+        row = {"param": f"{which}[{e}]", "adjoint": ad}
+        if which == "k":
+            f6, f5, f4 = fd(dk, dw, 1e-6), fd(dk, dw, 1e-5), fd(dk, dw, 1e-4)
+            row.update({"h": 1e-5, "fd_h1e-06": f6, "fd_h1e-05": f5, "fd_h1e-04": f4,
+                        "noise_h1e-06": abs(f6 - f5) / abs(f5),
+                        "trunc_h1e-05": abs(f5 - f4) / abs(f4) / 100.0,
+                        "rel_err_h1e-06": abs(ad - f6) / abs(f6), "fd": f5})
+        else:
+            f1, f2 = fd(dk, dw, 1e-1), fd(dk, dw, 5e-2)
+            row.update({"h": 1e-1, "fd_h": f1, "fd_h2": f2, "h_vs_h2": abs(f1 - f2) / abs(f2),
+                        "fd": (4.0 * f2 - f1) / 3.0})
+        row["rel_err"] = abs(ad - row["fd"]) / abs(row["fd"])
+        rows.append(row)
+        print(f"[adjoint] {row['param']} adjoint {ad:.10e} fd {row['fd']:.10e} "
+              f"rel {row['rel_err']:.2e}"
+              + (f" (h=1e-6: rel {row['rel_err_h1e-06']:.2e}, noise {row['noise_h1e-06']:.1e})"
+                 if which == "k" else f" (h vs h/2 {row['h_vs_h2']:.1e})"),
+              file=sys.stderr, flush=True)
+    for name, dk, dw, h in (("direction k", p.k_e.copy(), 0 * p.k_e, 1e-6),
+                            ("direction w", 0 * p.perf_e, p.perf_e.copy(), 1e-3)):
+        ad = float(gk @ dk + gw @ dw)
+        f = fd(dk, dw, h)
+        row = {"param": name, "h": h, "adjoint": ad, "fd": f, "rel_err": abs(ad - f) / abs(f)}
+        if name == "direction k":
+            f5 = fd(dk, dw, 1e-5)
+            row["noise_h1e-06"] = abs(f - f5) / abs(f5)
+        rows.append(row)
+        print(f"[adjoint] {name} adjoint {ad:.10e} fd {f:.10e} rel {row['rel_err']:.2e}",
+              file=sys.stderr, flush=True)
+    return rows
 
 
 def _counter_rows(d: str, counter: str):

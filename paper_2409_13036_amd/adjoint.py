@@ -66,3 +66,26 @@ def lesion_loss(dp: DeviceProblem, k_e: torch.Tensor, perf_e: torch.Tensor, step
         raise ValueError("the problem has no loss region")
     return _LesionLoss.apply(k_e, perf_e, dp, int(steps), int(checkpoint_every), float(tol),
                              precision)
+
+
+def fd_directional(dp: DeviceProblem, k_e, perf_e, dk, dw, h: float, steps: int,
+                   tol: float = 1e-14, precision: str = "fp64") -> float:
+    """Central finite difference of the lesion loss along (dk, dw) (host arrays of element
+    values) with step h: (L(theta + h d) - L(theta - h d)) / (2 h), both forward runs from
+    the initial state with the device steps.  The loss difference is formed node by node,
+    sum (T+ - T-)(T+ + T- - 2 T*), so that the two large losses never cancel.  A gradient
+    check of the reverse sweep (the time loop of Sec. II-A run backwards), not part of it."""
+    import numpy as np
+    tgt = dp.T_target.cpu().numpy()
+    ids = dp.loss_ids.long()
+
+    def final_T(kk, ww):
+        dp.set_params(torch.as_tensor(kk, device=dp.dev), torch.as_tensor(ww, device=dp.dev))
+        dp.reset()
+        for _ in range(steps):
+            dp.step(tol, precision)
+        return dp.T[ids].cpu().numpy()
+
+    a = final_T(k_e + h * dk, perf_e + h * dw)
+    b = final_T(k_e - h * dk, perf_e - h * dw)
+    return float(np.sum((a - b) * (a + b - 2.0 * tgt))) / (2.0 * h)
