@@ -36,10 +36,33 @@ def spmv_bytes(n: int, nnz: int, fp32: bool) -> int:
     return (w + 4) * nnz + 4 * (n + 1) + 2 * w * n
 
 
+def layout_bytes(stats, fp32: bool) -> int:
+    """Bytes one PCG SpMV (fused with p.Ap) must move on the mesh's own slab layout: every
+    stored value slot (padding included), the column data it reads (slab pointers, shared
+    offset lists, 16/32-bit per-slot offsets), x read once, y written once, and the
+    per-group partial sums."""
+    w = 4 if fp32 else 8
+    groups = (int(stats.slabs) + 7) // 8
+    return (w * int(stats.value_slots) + int(stats.index_bytes) + 2 * w * int(stats.n_nodes)
+            + 8 * groups)
+
+
+def traffic_key(kernel: str, workload: str, nnz: int) -> str:
+    """Key of a kernel's byte counters in profiles/traffic.json: the counters depend on the
+    matrix the kernel ran on, not only on its name."""
+    return f"{kernel} | {workload} | nnz={nnz}"
+
+
 def kernel_hash() -> str:
-    """Hash of the source of the PCG kernels (the SpMV whose traffic is quoted)."""
-    with open(os.path.join(ROOT, "paper_2409_13036_amd", "csrc", "pcg.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the source of the row kernels (the SpMV whose traffic is quoted): the text of
+    pcg.hip between its row-kernel markers, so that changes elsewhere in the file do not
+    void the recorded counters."""
+    with open(os.path.join(ROOT, "paper_2409_13036_amd", "csrc", "pcg.hip")) as f:
+        text = f.read()
+    a, b = text.find("[row-kernels-begin]"), text.find("[row-kernels-end]")
+    if a < 0 or b < a:
+        raise RuntimeError("pcg.hip lacks its row-kernel markers")
+    return hashlib.sha256(text[a:b].encode()).hexdigest()[:16]
 
 
 def spmv_kernel_name(mesh, fp32: bool) -> str:
@@ -63,22 +86,25 @@ def copy_probe(mib: int) -> None:
     del a, b
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source (else None)."""
+def measured_traffic(kernel: str, workload: str, nnz: int):
+    """HBM bytes per launch of `kernel` on this workload's matrix (nnz entries) from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel source (else
+    None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         data = json.load(f)
-    entry = data.get(kernel)
+    entry = data.get(traffic_key(kernel, workload, nnz))
     if not isinstance(entry, dict) or entry.get("kernels_sha") != kernel_hash():
         return None
     return entry.get("bytes_per_launch")
 
 
 def cpu_baseline_child(n: int) -> None:
-    """Time one coupled step of the CPU oracle (run in a child process, 1 thread)."""
+    """Time one coupled step of the CPU oracle from the initial state (run in a child
+    process, 1 thread): the whole step, and inside it each PCG solve with its iterations,
+    so that the cost per iteration and the cost outside the solves are known."""
     import numpy as np
     import rafem_inputs as ri
     from oracle.rafem import Model
@@ -87,12 +113,26 @@ def cpu_baseline_child(n: int) -> None:
     t0 = time.perf_counter()
     m = Model(p)
     setup = time.perf_counter() - t0
-    bio = m.bioheat_system()
+    _, lift_T = bio = m.bioheat_system()
+    T0, V0 = p.initial_T(), p.initial_V()
     t0 = time.perf_counter()
-    T, V, info = m.step(p.initial_T(), p.initial_V(), TOL, bioheat=bio)
-    dt = time.perf_counter() - t0
-    print(json.dumps({"step_s": dt, "setup_s": setup, "V_iters": info.V.iters,
-                      "T_iters": info.T.iters}), flush=True)
+    T1, V1, info = m.step(T0, V0, TOL, bioheat=bio)
+    step_s = time.perf_counter() - t0
+    # the same step's two solves timed on their own (the oracle's own routines, same inputs)
+    sig = m.sigma(T0)
+    A_V, b_V = m.potential_system(sig)
+    x0 = V0.copy()
+    t0 = time.perf_counter()
+    V1b, iV = m.solve(A_V, b_V, x0, TOL, "pcg")
+    solve_V = time.perf_counter() - t0
+    b_T = m.bioheat_rhs(T0, m.joule(sig, V1b), lift_T)
+    t0 = time.perf_counter()
+    _, iT = m.solve(bio[0], b_T, T0.copy(), TOL, "pcg")
+    solve_T = time.perf_counter() - t0
+    print(json.dumps({"step_s": step_s, "setup_s": setup, "V_iters": info.V.iters,
+                      "T_iters": info.T.iters, "solve_V_s": solve_V, "solve_T_s": solve_T,
+                      "iter_V_s": solve_V / max(1, iV.iters), "iter_T_s": solve_T / max(1, iT.iters),
+                      "outside_solves_s": max(0.0, step_s - solve_V - solve_T)}), flush=True)
 
 
 def cpu_baseline(n: int) -> dict:
@@ -108,7 +148,71 @@ def cpu_baseline(n: int) -> dict:
                        f"{r['V_iters']}+{r['T_iters']} iterations) of the {n}^3 hex workload from "
                        f"its initial state, NumPy/SciPy FP64 oracle, 1 thread; mesh setup "
                        f"({r['setup_s']:.1f} s) excluded"),
-            "host_cpus": len(os.sched_getaffinity(0)), "host_cpu_count": os.cpu_count()}
+            "raw": r, "host_cpus": len(os.sched_getaffinity(0)), "host_cpu_count": os.cpu_count()}
+
+
+def equal_work_cpu(cpu: dict, v_iters: float, t_iters: float) -> dict:
+    """The oracle's step time scaled to the iterations the device's FP64 path needs per step
+    (its solves start from the predictor, the oracle's from the previous state): the part
+    outside the solves plus the oracle's measured cost per iteration of each solve times
+    the device's mean iteration counts.  Replaces value (the raw figure stays in raw)."""
+    r = cpu["raw"]
+    t = r["outside_solves_s"] + r["iter_V_s"] * v_iters + r["iter_T_s"] * t_iters
+    out = dict(cpu)
+    out["value"] = 1.0 / t
+    out["raw_value"] = cpu["value"]
+    out["sample"] = (cpu["sample"] + f"; value scaled to the device FP64 path's mean "
+                     f"{v_iters:.1f}+{t_iters:.1f} iterations per step: outside the solves "
+                     f"{r['outside_solves_s']:.2f} s + {1e3 * r['iter_V_s']:.1f} ms per "
+                     f"potential iteration + {1e3 * r['iter_T_s']:.1f} ms per bioheat "
+                     f"iteration; raw_value is the unscaled step")
+    return out
+
+
+def spmv_roofline(mesh, kernel: str, wl_key: str, fp32: bool, warm_us: float,
+                  warm_count: int, copies: int = 0) -> dict:
+    """Roofline of the PCG SpMV on this mesh's potential matrix.  achieved = the layout's own
+    bytes per launch (layout_bytes) / the kernel's mean duration with a cold Infinity Cache:
+    rafem_spmv_timing rotates the launches through enough copies of the values (> 1.2 GB in
+    all) that none finds its matrix in the 256 MB cache; each launch is timed by events
+    stamped at the kernel's own start and end.  Beside it: the same bytes over the mean
+    in-solve duration (warm, measured over the PCG iterations of extra steps), the CSR
+    count of the same product, and the counter bytes (FETCH_SIZE + WRITE_SIZE) when
+    profiles/traffic.json holds them for this kernel, workload and matrix."""
+    from paper_2409_13036_amd import _lib as R
+    st = mesh.stats()
+    prec = "mixed" if fp32 else "fp64"
+    nbytes = layout_bytes(st, fp32)
+    value_bytes = int(st.value_slots) * (4 if fp32 else 8)
+    if copies <= 0:
+        copies = max(4, -(-int(1.2e9) // max(1, value_bytes)))
+    t_cold = R.spmv_timing(mesh, prec, copies=copies, reps=max(20, 10 * copies))
+    t_one = R.spmv_timing(mesh, prec, copies=1, reps=max(20, 10 * copies))
+    traffic = measured_traffic(kernel, wl_key, int(st.nnz))
+    csr = spmv_bytes(int(st.n_nodes), int(st.nnz), fp32)
+    print(f"[bench] SpMV {kernel} on {wl_key}: {nbytes / 1e6:.1f} MB per launch; cold "
+          f"({copies} copies) {t_cold:.2f} us, one copy {t_one:.2f} us, in solves "
+          f"{warm_us:.2f} us", file=sys.stderr, flush=True)
+    gbs = lambda b, us: b / (us * 1e3) if us > 0 else None
+    return {"bound": "hbm", "achieved": gbs(nbytes, t_cold), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs(nbytes, t_cold) / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": kernel, "workload": wl_key, "bytes_per_launch": nbytes,
+            "bytes": {"values": value_bytes, "column_data": int(st.index_bytes),
+                      "x_and_y": 2 * (4 if fp32 else 8) * int(st.n_nodes),
+                      "partials": 8 * ((int(st.slabs) + 7) // 8)},
+            "mean_launch_us": t_cold, "cold_cache_copies": copies,
+            "warm": {"mean_launch_us": warm_us, "launches_measured": warm_count,
+                     "achieved": gbs(nbytes, warm_us),
+                     "frac": (gbs(nbytes, warm_us) or 0.0) / HBM_PEAK_GBS,
+                     "one_copy_mean_launch_us": t_one},
+            "csr_equivalent": {"bytes_per_launch": csr, "achieved_cold": gbs(csr, t_cold),
+                               "achieved_warm": gbs(csr, warm_us)},
+            "measured_GBs_cold": gbs(traffic, t_cold) if traffic else None,
+            "note": ("achieved = bytes_per_launch (the slab layout's values with padding, its "
+                     "column data, x once, y once) / mean launch time with a cold Infinity "
+                     "Cache; warm = the same bytes over the in-solve launches, whose matrix "
+                     "can sit in the 256 MB cache; csr_equivalent = the CSR count of the same "
+                     "product; traffic = FETCH_SIZE + WRITE_SIZE bytes per launch")}
 
 
 def run_path(dp, precision: str, steps: int, warmup: int, profile_steps: int, **kw):
@@ -331,6 +435,18 @@ def trace_summary(d: str) -> None:
         if len(v) >= 50:
             print(f"  {a[:36]:36s} -> {b[:36]:36s} n={len(v):5d} "
                   f"median={statistics.median(v):6.2f} mean={statistics.mean(v):6.2f}")
+    print("\nruns of >= 10 back-to-back launches of one kernel (the autotuner's timing and "
+          "the cold-cache rotation of rafem_spmv_timing), mean duration (us):")
+    i = 0
+    while i < len(ks):
+        j = i
+        while j + 1 < len(ks) and ks[j + 1][2] == ks[i][2]:
+            j += 1
+        if j - i + 1 >= 10:
+            d = [(e - s) / 1e3 for s, e, _ in ks[i:j + 1]]
+            print(f"  {ks[i][2]:48s} run of {len(d):4d} mean={statistics.mean(d):8.2f} "
+                  f"median={statistics.median(d):8.2f}")
+        i = j + 1
     print("\nper-kernel durations excluding launches under 5 us (early exits):")
     for n0, v in per.items():
         w = [x for x in v if x >= 5.0]
@@ -339,16 +455,25 @@ def trace_summary(d: str) -> None:
                   f"mean={statistics.mean(w):8.2f}")
 
 
-def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int, out_path: str = "") -> None:
+def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int, workload: str, nnz: int,
+                     out_path: str = "") -> None:
     """HBM bytes per launch of the PCG SpMV kernels from two rocprofv3 --pmc runs of
-    `bench.py --copy-probe-mib M ...` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).
-    Each counter is scaled by what it reads for the probe's plain copy of M MiB (the
-    copy dispatches with the largest values), and a kernel's figure is the mean over
+    `bench.py --copy-probe-mib M ...` on one workload (FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch).  Each counter is scaled by what it reads for the probe's plain copy of M MiB
+    (the copy dispatches with the largest values), and a kernel's figure is the mean over
     its launches that did work (value >= 10% of its largest; launches enqueued past
-    convergence exit at once).  Writes profiles/traffic.json and prints a summary."""
+    convergence exit at once).  Entries are keyed by (kernel, workload, nnz) and merged
+    into profiles/traffic.json (entries of other workloads are kept); prints a summary."""
     import statistics
-    out = {"kernels_sha": kernel_hash(), "probe_mib": probe_mib}
+    path = out_path or os.path.join(ROOT, "profiles", "traffic.json")
+    out = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            old = json.load(f)
+        out = {k: v for k, v in old.items()
+               if isinstance(v, dict) and v.get("workload") not in (None, workload)}
     lines = []
+    factors = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _counter_rows(d, counter)
         copies = [v for _, n, v in rows if "copy" in n.lower()]
@@ -357,7 +482,7 @@ def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int, out_path: s
         top = max(copies)
         probe = [v for v in copies if v >= 0.5 * top]
         factor = statistics.mean(probe) / (probe_mib * 1024.0)
-        out[f"{counter}_copy_factor"] = factor
+        factors[counter] = factor
         lines.append(f"{counter}: copy probe {len(probe)} dispatches, mean "
                      f"{statistics.mean(probe):.0f} KiB for {probe_mib * 1024} KiB moved "
                      f"-> factor {factor:.4f}")
@@ -369,7 +494,10 @@ def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int, out_path: s
         for name, vals in sorted(by.items()):
             busy = [v for v in vals if v >= 0.1 * max(vals)]
             kib = statistics.mean(busy)
-            e = out.setdefault(name, {"kernels_sha": kernel_hash()})
+            e = out.setdefault(traffic_key(name, workload, nnz),
+                               {"kernel": name, "workload": workload, "nnz": nnz,
+                                "kernels_sha": kernel_hash(), "probe_mib": probe_mib})
+            e[counter.lower() + "_copy_factor"] = factor
             e[counter.lower() + "_bytes"] = kib * 1024.0 / factor
             e[counter.lower() + "_launches"] = len(busy)
             lines.append(f"  {name:34s} {len(busy):5d} of {len(vals):5d} launches, mean "
@@ -378,7 +506,7 @@ def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int, out_path: s
         if isinstance(e, dict) and "fetch_size_bytes" in e and "write_size_bytes" in e:
             e["bytes_per_launch"] = e["fetch_size_bytes"] + e["write_size_bytes"]
             lines.append(f"{name}: HBM bytes per launch {e['bytes_per_launch'] / 1e6:.1f} MB")
-    with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+    with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("\n".join(lines))
 
@@ -442,6 +570,14 @@ def batch_leg(args) -> dict:
     mixed_ok = max(eT) <= 1e-8 and max(eV) <= 1e-8
     out["path"] = "mixed" if mixed_ok else "fp64"
     out["sample_steps_per_s"] = out[out["path"]]["sample_steps_per_s"]
+    # the full-ensemble product (every sample active): its values (1.8 GB FP32, 3.5 GB FP64)
+    # exceed the 256 MB Infinity Cache by themselves, so two rotated copies suffice; the
+    # in-solve mean ("warm") also averages launches in which converged samples are skipped
+    for precision in ("mixed", "fp64"):
+        fp32 = precision == "mixed"
+        out[f"roofline_{'fp32' if fp32 else 'fp64'}"] = spmv_roofline(
+            bp.mesh, spmv_kernel_name(bp.mesh, fp32), "C4 ensemble", fp32,
+            out[precision]["spmv_us_mean"], out[precision]["spmv_launches"], copies=2)
     bp.close()
     return out
 
@@ -698,6 +834,9 @@ def main():
     ap.add_argument("--no-extrapolate", action="store_true",
                     help="start every solve from the previous state instead of the linear "
                          "extrapolation of the last two")
+    ap.add_argument("--restart-inner", action="store_true",
+                    help="mixed precision: plain restarted refinement (a new inner Krylov space "
+                         "per refinement) instead of the default reliable updates")
     ap.add_argument("--no-batch", action="store_true", help="skip the ensemble leg")
     ap.add_argument("--no-pc", action="store_true", help="skip the predictor-corrector leg")
     ap.add_argument("--no-mono", action="store_true", help="skip the monolithic GMRES leg")
@@ -723,6 +862,11 @@ def main():
     ap.add_argument("--counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of a "
                          "bench run with --copy-probe-mib into profiles/traffic.json")
+    ap.add_argument("--traffic-workload", default="",
+                    help="with --counters: the workload key of the profiled run (C1 hex101, "
+                         "C2 tet161, C4 ensemble)")
+    ap.add_argument("--traffic-nnz", type=int, default=0,
+                    help="with --counters: nonzeros of the profiled run's matrix")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="summarise a rocprofv3 --kernel-trace --stats output folder")
     args = ap.parse_args()
@@ -730,7 +874,10 @@ def main():
         trace_summary(args.summarize_trace)
         return
     if args.counters:
-        counters_summary(args.counters[0], args.counters[1], args.copy_probe_mib or 1024)
+        if not args.traffic_workload or args.traffic_nnz <= 0:
+            raise SystemExit("--counters needs --traffic-workload and --traffic-nnz")
+        counters_summary(args.counters[0], args.counters[1], args.copy_probe_mib or 1024,
+                         args.traffic_workload, args.traffic_nnz)
         return
     if args.cpu_baseline_child:
         cpu_baseline_child(args.n)
@@ -787,7 +934,8 @@ def main():
         inner_tol = args.inner_tol
         if inner_tol is None:
             inner_tol = 1e-4 if args.workload == "c2" else 0.0
-        kw = {"inner_tol": inner_tol} if precision == "mixed" else {}
+        kw = ({"inner_tol": inner_tol, "restart_inner": int(args.restart_inner)}
+              if precision == "mixed" else {})
         el, infos, state, (mean_us, count) = run_path(dp, precision, args.steps, args.warmup,
                                                       args.profile_steps, **kw)
         it_v = float(np.mean([i["V"]["iters"] for i in infos]))
@@ -810,19 +958,8 @@ def main():
     sps = args.steps / r["elapsed"]
     fp32 = head == "mixed"
     kernel = spmv_kernel_name(dp.mesh, fp32)
-    per_launch = spmv_bytes(N, nnz, fp32)
-    achieved = per_launch / (r["spmv_us"] * 1e-6) / 1e9 if r["spmv_us"] > 0 else 0.0
-    traffic = measured_traffic(kernel)
-    # cold-cache protocol: rotate the SpMV through copies of the matrix values totalling
-    # > 1 GB, so no launch finds its values in the 256 MB Infinity Cache
-    prec = "mixed" if fp32 else "fp64"
-    value_bytes = dp.mesh.stats().slabs * 64 * 27 * (4 if fp32 else 8)  # upper bound
-    copies = max(4, -(-int(1.2e9) // max(1, value_bytes)))
-    t_cold = R.spmv_timing(dp.mesh, prec, copies=copies, reps=10 * copies)
-    t_one = R.spmv_timing(dp.mesh, prec, copies=1, reps=10 * copies)
-    print(f"[bench] SpMV {kernel}: in solves {r['spmv_us']:.1f} us, one copy {t_one:.1f} us, "
-          f"{copies} copies {t_cold:.1f} us", file=sys.stderr, flush=True)
-    min_bytes = (4 if fp32 else 8) * nnz + 2 * (4 if fp32 else 8) * N
+    wl_key = f"C2 tet{n}" if args.workload == "c2" else f"C1 hex{n}"
+    roof = spmv_roofline(dp.mesh, kernel, wl_key, fp32, r["spmv_us"], r["spmv_count"])
     line = {
         "metric": "coupled time-step solves/s at 1M DOF (101^3 hex), FP64 vs mixed at 1e-8 rel err; SpMV HBM GB/s",
         "value": sps, "unit": "coupled steps/s", "n_gpus": 1, "steps": args.steps,
@@ -836,22 +973,7 @@ def main():
                    "predictor_order": (None if args.no_extrapolate
                                        else args.extrapolate_order),
                    "inner_tol": inner_tol if inner_tol else "library default (3e-5)"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kernel, "bytes_per_launch": per_launch,
-                     "mean_launch_us": r["spmv_us"], "launches_measured": r["spmv_count"],
-                     "measured_GBs": (traffic / (r["spmv_us"] * 1e3)
-                                      if traffic and r["spmv_us"] > 0 else None),
-                     "values_and_vectors_bytes": min_bytes,
-                     "cold_cache": {"copies": copies, "mean_launch_us": t_cold,
-                                    "achieved": per_launch / (t_cold * 1e3),
-                                    "frac": per_launch / (t_cold * 1e3) / HBM_PEAK_GBS,
-                                    "measured_GBs": traffic / (t_cold * 1e3) if traffic else None,
-                                    "one_copy_mean_launch_us": t_one},
-                     "note": ("bytes_per_launch is the CSR count (values + int32 columns + row "
-                              "pointers + x + y); the slab layout with shared column offsets "
-                              "reads fewer bytes (traffic, from FETCH_SIZE + WRITE_SIZE), so "
-                              "frac can exceed 1; measured_GBs = traffic / duration")},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "fp64": {"steps_per_s": args.steps / res["fp64"]["elapsed"],
                  "V_iters": res["fp64"]["V_iters"], "T_iters": res["fp64"]["T_iters"],
@@ -872,7 +994,8 @@ def main():
                   "regions_ms_per_step": res["mixed"]["regions"]},
     }
     if cpu:
-        line["speedup_vs_cpu_oracle"] = sps / cpu["value"]
+        line["cpu_baseline"] = equal_work_cpu(cpu, res["fp64"]["V_iters"], res["fp64"]["T_iters"])
+        line["speedup_vs_cpu_oracle"] = sps / line["cpu_baseline"]["value"]
     if not args.no_pc:
         line["predictor_corrector"] = pc_leg(dp, args)
     if not args.no_psnr:

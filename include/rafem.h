@@ -134,6 +134,9 @@ typedef struct {
     int32_t row_assembly;        /* 1: step matrices and right-hand side assembled row by row
                                     (every row has at most 64 entries), 0: colour by colour */
     int32_t max_row_entries;     /* entries of the longest row of the slab layout */
+    int64_t value_slots;         /* stored values per matrix in the slab layout (padding included) */
+    int64_t index_bytes;         /* column data one product reads: slab pointers, the shared
+                                    offset lists, 16- or 32-bit per-slot column offsets */
 } rafem_mesh_stats;
 
 /* Build a mesh on the current device.
@@ -222,6 +225,11 @@ typedef struct {
                             tolerance still needs is reached (the last refinement) */
     int32_t max_outer;   /* MIXED: refinement limit (<= 0 means 30) */
     int32_t poll_every;  /* iterations enqueued between host polls (<= 0 means adaptive) */
+    int32_t restart_inner; /* MIXED: 0 (default): after each refinement the inner FP32
+                            recurrence goes on from the new FP64 residual with its search
+                            direction kept (a reliable update); 1: every refinement starts a
+                            new inner Krylov space (plain iterative refinement) */
+    int32_t pad;
 } rafem_solve_opts;
 
 typedef struct {

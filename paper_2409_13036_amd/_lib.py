@@ -14,7 +14,10 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librafem.so")
+# RAFEM_LIB_VARIANT=asan loads the host-sanitizer build (librafem_asan.so, built by
+# `python -m paper_2409_13036_amd.build --sanitize`; its runtime must be preloaded)
+_VARIANT = os.environ.get("RAFEM_LIB_VARIANT", "")
+LIB_PATH = os.path.join(_HERE, f"librafem_{_VARIANT}.so" if _VARIANT else "librafem.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_2409_13036_amd.build)")
@@ -52,12 +55,14 @@ class MeshStats(C.Structure):
                 ("n_samples", C.c_int32), ("slabs_per_block", C.c_int32),
                 ("slabs_per_block32", C.c_int32), ("int16_columns", C.c_int32),
                 ("slabs", C.c_int64), ("shared_offset_slabs", C.c_int64),
-                ("row_assembly", C.c_int32), ("max_row_entries", C.c_int32)]
+                ("row_assembly", C.c_int32), ("max_row_entries", C.c_int32),
+                ("value_slots", C.c_int64), ("index_bytes", C.c_int64)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("precision", C.c_int32),
-                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("poll_every", C.c_int32)]
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("poll_every", C.c_int32),
+                ("restart_inner", C.c_int32), ("pad", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -287,8 +292,10 @@ def _precision(precision) -> int:
     return {"fp64": FP64, "mixed": MIXED}.get(precision, precision)
 
 
-def make_opts(tol=1e-10, maxit=0, precision="fp64", inner_tol=0.0, max_outer=0, poll_every=0):
-    return SolveOpts(tol, maxit, _precision(precision), inner_tol, max_outer, poll_every)
+def make_opts(tol=1e-10, maxit=0, precision="fp64", inner_tol=0.0, max_outer=0, poll_every=0,
+              restart_inner=0):
+    return SolveOpts(tol, maxit, _precision(precision), inner_tol, max_outer, poll_every,
+                     int(restart_inner), 0)
 
 
 class Mesh:
@@ -434,7 +441,7 @@ def assemble_csr(mesh: Mesh, stiff_coef=None, mass_coef=None, dir_vals=None, *, 
 
 
 def solve(mesh: Mesh, row_ptr, col_idx, vals, b, x, *, vals32=None, tol=1e-10, precision="fp64",
-          maxit=0, inner_tol=0.0, max_outer=0, poll_every=0, stream=None, check=True):
+          maxit=0, inner_tol=0.0, max_outer=0, poll_every=0, restart_inner=0, stream=None, check=True):
     """rafem_solve: Jacobi-PCG (FP64 or mixed) on A x = b, x in/out.  Returns the info dict."""
     torch = _torch()
     n = mesh.n_nodes
@@ -444,7 +451,7 @@ def solve(mesh: Mesh, row_ptr, col_idx, vals, b, x, *, vals32=None, tol=1e-10, p
     vals32 = _dev(vals32, torch.float32, col_idx.numel(), "vals32", allow_none=True)
     b = _dev(b, torch.float64, n, "b")
     x = _dev(x, torch.float64, n, "x")
-    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every)
+    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every, restart_inner)
     info = SolveInfo()
     st = _lib.rafem_solve(mesh.handle, _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(vals32), _ptr(b),
                           _ptr(x), C.byref(opts), C.byref(info), _stream(stream))
@@ -454,7 +461,7 @@ def solve(mesh: Mesh, row_ptr, col_idx, vals, b, x, *, vals32=None, tol=1e-10, p
 
 
 def solve_adjoint(mesh: Mesh, row_ptr, col_idx, vals, g, lam, *, vals32=None, tol=1e-10,
-                  precision="fp64", maxit=0, inner_tol=0.0, max_outer=0, poll_every=0, stream=None,
+                  precision="fp64", maxit=0, inner_tol=0.0, max_outer=0, poll_every=0, restart_inner=0, stream=None,
                   check=True):
     """rafem_solve_adjoint: A^T lambda = g (g zeroed on Dirichlet rows), lambda in/out."""
     torch = _torch()
@@ -465,7 +472,7 @@ def solve_adjoint(mesh: Mesh, row_ptr, col_idx, vals, g, lam, *, vals32=None, to
     vals32 = _dev(vals32, torch.float32, col_idx.numel(), "vals32", allow_none=True)
     g = _dev(g, torch.float64, n, "g")
     lam = _dev(lam, torch.float64, n, "lambda")
-    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every)
+    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every, restart_inner)
     info = SolveInfo()
     st = _lib.rafem_solve_adjoint(mesh.handle, _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(vals32),
                                   _ptr(g), _ptr(lam), C.byref(opts), C.byref(info), _stream(stream))
@@ -510,7 +517,7 @@ def spmv_step(mesh: Mesh, x, y, *, matrix="potential", b=None, dots=True, stream
 
 
 def step(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T, V, *, tol=1e-12,
-         precision="fp64", maxit=0, inner_tol=0.0, max_outer=0, poll_every=0, stream=None, check=True):
+         precision="fp64", maxit=0, inner_tol=0.0, max_outer=0, poll_every=0, restart_inner=0, stream=None, check=True):
     """rafem_step: one coupled step, T and V updated in place.  Returns {"V": info, "T": info}."""
     torch = _torch()
     E, n = mesh.n_elems, mesh.n_nodes
@@ -521,7 +528,7 @@ def step(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T, V, *, t
     dir_T = _dev(dir_T, torch.float64, mesh.n_dir, "dir_T")
     T = _dev(T, torch.float64, n, "T")
     V = _dev(V, torch.float64, n, "V", allow_none=not phys.coupled)
-    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every)
+    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every, restart_inner)
     info = StepInfo()
     st = _lib.rafem_step(mesh.handle, C.byref(phys), _ptr(k_e), _ptr(perf_e), _ptr(sigma0_e),
                          _ptr(dir_V), _ptr(dir_T), _ptr(T), _ptr(V), C.byref(opts), C.byref(info),
@@ -533,7 +540,7 @@ def step(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T, V, *, t
 
 def step_pc(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T_prev, dt_prev, T, V, *,
             corr_tol=1e-10, max_iters=50, tol=1e-12, precision="fp64", maxit=0, inner_tol=0.0,
-            max_outer=0, poll_every=0, stream=None, check=True):
+            max_outer=0, poll_every=0, restart_inner=0, stream=None, check=True):
     """rafem_step_pc: one predictor-corrector step of size phys.dt; T and V are advanced in
     place when the step is accepted.  Returns the corrector info as a dict."""
     torch = _torch()
@@ -546,7 +553,7 @@ def step_pc(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T_prev,
     T_prev = _dev(T_prev, torch.float64, n, "T_prev", allow_none=True)
     T = _dev(T, torch.float64, n, "T")
     V = _dev(V, torch.float64, n, "V", allow_none=not phys.coupled)
-    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every)
+    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every, restart_inner)
     copts = CorrectorOpts(float(corr_tol), int(max_iters))
     info = CorrectorInfo()
     st = _lib.rafem_step_pc(mesh.handle, C.byref(phys), _ptr(k_e), _ptr(perf_e), _ptr(sigma0_e),
@@ -634,7 +641,7 @@ def step_mono(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T_pre
 
 def step_vjp(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T_prev, V, T, lam, grad_k,
              grad_perf, *, tol=1e-12, precision="fp64", maxit=0, inner_tol=0.0, max_outer=0,
-             poll_every=0, stream=None, check=True):
+             poll_every=0, restart_inner=0, stream=None, check=True):
     """rafem_step_vjp: reverse of one step.  lam in: dL/dT^n, out: dL/dT^{n-1}; grads accumulate."""
     torch = _torch()
     E, n = mesh.n_elems, mesh.n_nodes
@@ -649,7 +656,7 @@ def step_vjp(mesh: Mesh, phys: Phys, k_e, perf_e, sigma0_e, dir_V, dir_T, T_prev
     lam = _dev(lam, torch.float64, n, "lambda")
     grad_k = _dev(grad_k, torch.float64, E, "grad_k")
     grad_perf = _dev(grad_perf, torch.float64, E, "grad_perf")
-    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every)
+    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every, restart_inner)
     info = StepInfo()
     st = _lib.rafem_step_vjp(mesh.handle, C.byref(phys), _ptr(k_e), _ptr(perf_e), _ptr(sigma0_e),
                              _ptr(dir_V), _ptr(dir_T), _ptr(T_prev), _ptr(V), _ptr(T), _ptr(lam),

@@ -30,12 +30,35 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build librafem.so)")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    """Compile every source for gfx950 and link librafem.so; returns its path."""
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer (the device code is built as
+# usual): each option applies to the host compilation only.
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
+def asan_runtime() -> str:
+    """The shared sanitizer runtime of hipcc's clang (linked into the sanitizer build, and
+    preloaded into the Python process that loads it)."""
+    import glob
+    root = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    found = sorted(glob.glob(os.path.join(root, "llvm", "lib", "clang", "*", "lib", "linux",
+                                          "libclang_rt.asan-x86_64.so")))
+    if not found:
+        raise RuntimeError("clang's shared AddressSanitizer runtime not found")
+    return found[-1]
+
+
+def build(verbose: bool = False, jobs: int = 4, sanitize: bool = False) -> str:
+    """Compile every source for gfx950 and link librafem.so (librafem_asan.so with the host
+    sanitizers); returns its path."""
     cc = hipcc()
-    flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
+    flags = ["-O3" if not sanitize else "-O1", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+             "-I", INCLUDE, "-I", CSRC,
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+    if sanitize:
+        flags += SANITIZE
+    lib = LIB if not sanitize else os.path.join(HERE, "librafem_asan.so")
     objdir = tempfile.mkdtemp(prefix="rafem_build_")
     try:
         procs = []
@@ -52,17 +75,19 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
                 _wait(procs.pop(0))
         while procs:
             _wait(procs.pop(0))
-        tmp = LIB + ".tmp"
+        tmp = lib + ".tmp"
         cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+        if sanitize:
+            cmd[1:1] = [asan_runtime()]
         if verbose:
             print(" ".join(cmd), flush=True)
         out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
         if out.returncode != 0:
             raise RuntimeError(f"link failed:\n{out.stdout}")
-        os.replace(tmp, LIB)
+        os.replace(tmp, lib)
     finally:
         shutil.rmtree(objdir, ignore_errors=True)
-    return LIB
+    return lib
 
 
 def _wait(item):
@@ -78,4 +103,4 @@ def _wait(item):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

@@ -83,6 +83,7 @@ struct PcgState {
     double tol2;     // tol^2 * bb: stop when rr <= tol2
     double scale;    // mixed refinement: 1 / ||r_outer||
     double rr_first; // ||r||^2 at the start of this solve
+    double scale_prev; // mixed refinement: the scale of the previous refinement
     int32_t iters;
     int32_t maxit;
     int32_t done;
@@ -91,6 +92,7 @@ struct PcgState {
     int32_t pad;
 };
 static_assert(sizeof(PcgState) % 8 == 0, "PcgState layout");
+static_assert(sizeof(PcgState) <= 128, "PcgState size (3 states per sample fill 384 bytes at most)");
 
 // Launch geometry of the row kernels.
 struct SpmvConfig {
@@ -197,10 +199,16 @@ void launch_spmv32(const Mat& A, const SpmvConfig& c, const float* x, float* y, 
 void launch_residual64(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
                        double* r, double* partials, PcgState* st, const Samples& smp,
                        int outer_mode, hipStream_t s);
-// Mixed inner start: r32 = scale * r64; d32 = 0; p32 = D^-1 r32; rz, rr into inner state.
+// Mixed inner start: r32 = scale * r64; d32 = 0; rz, rr into the inner state.  A fresh
+// start (cont = 0) sets p32 = D^-1 r32.  A continuation (cont = 1: a reliable update of the
+// inner recurrence, after the previous inner solve reached its tolerance and x was
+// refined) keeps the search direction: p32 = D^-1 r32 + beta p32 with the beta of the
+// recurrence's next step, the new residual standing in for the recursive one and both
+// brought to the new scale.
 void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,
                         float* p32, const float* dinv32, double inner_tol, int maxit,
-                        double* partials, PcgState* inner, const Samples& smp, hipStream_t s);
+                        double* partials, PcgState* inner, const Samples& smp, int cont,
+                        hipStream_t s);
 // x64 += d32 / scale (samples whose refinement is not finished).
 void launch_refine_update(int n, double* x, const float* d32, const PcgState* outer,
                           const Samples& smp, hipStream_t s);
@@ -461,6 +469,7 @@ struct rafem_mesh_s {
     int32_t* sofs = nullptr;  // [nslabs] start of a shared-offset slab's list in soff, or -1
     int32_t* soff = nullptr;  // offset lists of the shared-offset slabs
     int64_t shared_slabs = 0;
+    int64_t index_bytes = 0;  // column data (offsets, slab pointers) one SpMV reads
     int32_t* conn = nullptr;
     double* xyz = nullptr;
     int32_t* colour_elems = nullptr;

@@ -106,6 +106,7 @@ __global__ void k_state_init(PcgState* st, int S, double tol, int maxit, int* it
     t.tol = tol;
     t.tol2 = 0.0;
     t.scale = 1.0;
+    t.scale_prev = 1.0;
     t.rr_first = 0.0;
     t.iters = 0;
     t.maxit = maxit;
@@ -139,6 +140,8 @@ __global__ __launch_bounds__(WG) void k_diag_inv(const int* __restrict__ rp,
 // ---------------------------------------------------------------------------
 // Row kernels
 // ---------------------------------------------------------------------------
+// [row-kernels-begin] (the text up to the matching end marker is what the recorded byte
+// counters of these kernels refer to)
 enum RowMode : int {
     ROW_PLAIN = 0,  // y = A x
     ROW_DOT = 1,    // y = A x, partials of x.y (PCG step; skipped once the sample is done)
@@ -377,6 +380,8 @@ __global__ __launch_bounds__(WG) void k_sell(RowArgs<T> a) {
     }
 }
 
+// [row-kernels-end]
+
 // Totals of a START / RESID row kernel -> solver scalars (thread 0 of sample s's block).
 template <int MODE>
 __device__ void finish_rows(PcgState* st, const double (&tot)[3], int outer_mode) {
@@ -414,6 +419,7 @@ __device__ void finish_rows(PcgState* st, const double (&tot)[3], int outer_mode
                 st->status = RAFEM_E_NOCONV;
                 st->done = 1;
             } else {
+                st->scale_prev = st->scale;
                 st->scale = 1.0 / sqrt(tot[1]);
                 st->iters += 1;
             }
@@ -568,15 +574,16 @@ __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
     }
 }
 
-// Mixed refinement: inner right-hand side r32 = r64 / ||r64||, d32 = 0, p32 = D^-1 r32,
-// for the samples whose refinement is not finished.
+// Mixed refinement: inner right-hand side r32 = r64 / ||r64||, d32 = 0 and, on a fresh
+// start, p32 = D^-1 r32, for the samples whose refinement is not finished.  A continuation
+// leaves p32 to k_inner_pcont.
 __global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restrict__ r64,
                                                     const PcgState* outer,
                                                     float* __restrict__ r32,
                                                     float* __restrict__ d32,
                                                     float* __restrict__ p32,
                                                     const float* __restrict__ dinv32,
-                                                    double* partials, Samples smp) {
+                                                    double* partials, Samples smp, int cont) {
     const int nb = gridDim.x;
     const int blk = xcd_block(blockIdx.x, nb);
     const int row0 = blk * kVecRowsPerBlock;
@@ -594,7 +601,7 @@ __global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restr
                 const float zi = dinv32[i] * ri;
                 r32[i] = ri;
                 d32[i] = 0.0f;
-                p32[i] = zi;
+                if (!cont) p32[i] = zi;
                 acc[0] += (double)ri * (double)zi;
                 acc[1] += (double)ri * (double)ri;
             }
@@ -603,10 +610,16 @@ __global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restr
     store_partials<2>(acc, partials, blk, nb);
 }
 
-// One block per sample: totals of k_inner_start's partials -> inner solver state.
+// One block per sample: totals of k_inner_start's partials -> inner solver state.  On a
+// continuation the state still holds the finished inner solve: its last iteration it =
+// iters - 1 kept (r, z) of that iteration in rzs[it & 1], and the new direction's
+// coefficient is that recurrence step's beta taken with the new residual,
+// rz_new / rz_old, times scale_prev / scale (rz_old was formed at the old scale, and p32
+// is carried over to the new one).
 __global__ __launch_bounds__(WG) void k_finalize_inner(const double* __restrict__ partials, int nb,
                                                        const PcgState* outer, double inner_tol,
-                                                       int maxit, PcgState* inner, Samples smp) {
+                                                       int maxit, PcgState* inner, Samples smp,
+                                                       int cont) {
     const int s = blockIdx.x;
     int b0, b1;
     sample_blocks(smp, s, kVecRowsPerBlock, b0, b1);
@@ -619,8 +632,16 @@ __global__ __launch_bounds__(WG) void k_finalize_inner(const double* __restrict_
     // test still asks for (tol ||b|| / ||r||): the last refinement stops there
     double tol_in = inner_tol;
     if (!skip && outer[s].rr > 0.0) tol_in = fmax(inner_tol, 0.1 * sqrt(outer[s].tol2 / outer[s].rr));
+    double beta = 0.0;
+    if (cont && !skip) {
+        const int last = S.iters > 0 ? S.iters - 1 : 0;
+        const double rz_old = S.rzs[last & 1];
+        beta = (rz_old > 0.0 && finite(rz_old))
+                   ? tot[0] / rz_old * (outer[s].scale_prev / outer[s].scale) : 0.0;
+    }
     S.rzs[0] = tot[0];
     S.rzs[1] = 0.0;
+    S.beta = beta;
     S.rr = tot[1];
     S.bb = tot[1];
     S.rr_first = tot[1];
@@ -632,12 +653,31 @@ __global__ __launch_bounds__(WG) void k_finalize_inner(const double* __restrict_
     if (skip || !(tot[1] > 0.0)) {
         S.status = RAFEM_OK;
         S.done = 1;
-    } else if (!finite(tot[0]) || !finite(tot[1])) {
+    } else if (!finite(tot[0]) || !finite(tot[1]) || !finite(beta)) {
         S.status = RAFEM_E_BREAKDOWN;
         S.done = 1;
     } else {
         S.status = RAFEM_E_NOCONV;
         S.done = 0;
+    }
+}
+
+// Continuation of the inner recurrence: p32 = D^-1 r32 + beta p32 (beta from
+// k_finalize_inner), for the samples whose inner solve goes on.
+__global__ __launch_bounds__(WG) void k_inner_pcont(int n, const float* __restrict__ r32,
+                                                    const float* __restrict__ dinv32,
+                                                    float* __restrict__ p32,
+                                                    const PcgState* inner, Samples smp) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int row0 = blk * kVecRowsPerBlock;
+    const int s = sample_of(smp, row0);
+    if (inner[s].done) return;
+    const float bt = (float)inner[s].beta;
+    const int i0 = row0 + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int i = i0 + u * WG;
+        if (i < n) p32[i] = dinv32[i] * r32[i] + bt * p32[i];
     }
 }
 
@@ -829,12 +869,16 @@ void launch_pupdate32(int n, float* p, const float* r, const float* dinv, const 
 
 void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,
                         float* p32, const float* dinv32, double inner_tol, int maxit,
-                        double* partials, PcgState* inner, const Samples& smp, hipStream_t s) {
+                        double* partials, PcgState* inner, const Samples& smp, int cont,
+                        hipStream_t s) {
     const int nb = vec_blocks(n);
     hipLaunchKernelGGL(k_inner_start, dim3(nb), dim3(WG), 0, s, n, r64, outer, r32, d32, p32,
-                       dinv32, partials, smp);
+                       dinv32, partials, smp, cont);
     hipLaunchKernelGGL(k_finalize_inner, dim3(smp.S), dim3(WG), 0, s, partials, nb, outer,
-                       inner_tol, maxit, inner, smp);
+                       inner_tol, maxit, inner, smp, cont);
+    if (cont)
+        hipLaunchKernelGGL(k_inner_pcont, dim3(nb), dim3(WG), 0, s, n, r32, dinv32, p32, inner,
+                           smp);
 }
 
 void launch_refine_update(int n, double* x, const float* d32, const PcgState* outer,

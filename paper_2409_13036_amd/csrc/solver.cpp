@@ -239,6 +239,9 @@ SolveOpts resolve_opts(const rafem_solve_opts* o, double default_tol) {
         r.inner_tol = o->inner_tol > 0.0 ? o->inner_tol : 3e-5;
         r.max_outer = o->max_outer > 0 ? o->max_outer : 30;
         r.poll_every = o->poll_every;
+        if (o->restart_inner != 0 && o->restart_inner != 1)
+            throw Error{RAFEM_E_ARG, "opts.restart_inner must be 0 or 1"};
+        r.restart_inner = o->restart_inner;
     }
     return r;
 }
@@ -326,8 +329,11 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
     PcgState* ho = m->st_host + S;
     while (true) {
         launch_residual64(A, m->spmv, b, x, m->r64, m->partials, outer, smp, 1, s);
+        // the first refinement starts the inner recurrence, later ones continue it from the
+        // refined residual (unless plain restarted refinement is asked for)
+        const int cont = (outer_steps > 0 && !o.restart_inner) ? 1 : 0;
         launch_inner_start(n, m->r64, outer, m->r32, m->d32, m->p32, dinv32, o.inner_tol, o.maxit,
-                           m->partials, inner, smp, s);
+                           m->partials, inner, smp, cont, s);
         launch_state_init(nullptr, 0, 0.0, 0, itb, s);  // inner iteration counter = 0
         check_launch();
         poll(m, s);  // outer convergence is decided by the residuals just computed

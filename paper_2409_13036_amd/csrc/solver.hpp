@@ -14,6 +14,7 @@ struct SolveOpts {
     double inner_tol = 1e-4;
     int max_outer = 30;
     int poll_every = 0;
+    int restart_inner = 0;
 };
 
 SolveOpts resolve_opts(const rafem_solve_opts* o, double default_tol);

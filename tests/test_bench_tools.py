@@ -34,11 +34,17 @@ def test_counter_summary_scales_by_the_copy_probe(tmp_path, capsys):
     _counter_csv(str(tmp_path / "f" / "host"), "FETCH_SIZE", fetch)
     _counter_csv(str(tmp_path / "w" / "host"), "WRITE_SIZE", write)
     out = tmp_path / "traffic.json"
-    bench.counters_summary(str(tmp_path / "f"), str(tmp_path / "w"), mib, out_path=str(out))
+    out.write_text(json.dumps({"k_sell<float, 1, true> | C2 tet161 | nnz=5": {
+        "kernel": "k_sell<float, 1, true>", "workload": "C2 tet161", "nnz": 5,
+        "bytes_per_launch": 1.0}}))
+    bench.counters_summary(str(tmp_path / "f"), str(tmp_path / "w"), mib, "C1 hex101", 27270901,
+                           out_path=str(out))
     data = json.loads(out.read_text())
-    assert abs(data["FETCH_SIZE_copy_factor"] - 0.5) < 1e-12
-    assert abs(data["WRITE_SIZE_copy_factor"] - 1.0) < 1e-12
-    e = data["k_sell<float, 1, true>"]
+    # another workload's entry is kept, this one's is keyed by kernel, workload and nnz
+    assert data["k_sell<float, 1, true> | C2 tet161 | nnz=5"]["bytes_per_launch"] == 1.0
+    e = data[bench.traffic_key("k_sell<float, 1, true>", "C1 hex101", 27270901)]
+    assert abs(e["fetch_size_copy_factor"] - 0.5) < 1e-12
+    assert abs(e["write_size_copy_factor"] - 1.0) < 1e-12
     assert e["fetch_size_launches"] == 5 and e["write_size_launches"] == 5  # early exits dropped
     assert abs(e["fetch_size_bytes"] - 60000.0 * 1024 / 0.5) < 1e-6
     assert abs(e["bytes_per_launch"] - (60000.0 * 1024 / 0.5 + 4000.0 * 1024)) < 1e-6

@@ -118,8 +118,12 @@ def _lifted_bioheat(m, p, T=None):
 
 
 @pytest.mark.parametrize("kind,n", [("hex", 21), ("tet", 17)])
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed-restarted"])
 def test_solve_matches_oracle(R, kind, n, precision):
+    """FP64 PCG, mixed refinement with reliable updates (the default: the inner recurrence
+    goes on from each refined residual) and plain restarted refinement, against the oracle."""
+    restart = 1 if precision == "mixed-restarted" else 0
+    precision = "mixed" if restart else precision
     import torch
     p = ri.make_problem(kind, n, 4)
     m = Model(p)
@@ -136,7 +140,7 @@ def test_solve_matches_oracle(R, kind, n, precision):
         vals = A.data.copy()
         out = R.solve(mesh, to_dev(A.indptr.astype(np.int32)), to_dev(A.indices.astype(np.int32)),
                       to_dev(vals), to_dev(b), x, vals32=to_dev(vals.astype(np.float32)), tol=1e-13,
-                      precision=precision)
+                      precision=precision, restart_inner=restart, inner_tol=1e-3)
         err = rel_err(to_host(x), xref)
         print(f"[{sysname} {precision}] iters={out['iters']} outer={out['outer']} relres_true="
               f"{out['relres_true']:.2e} err={err:.2e}", flush=True)
