@@ -256,6 +256,27 @@ rafem_status rafem_solve(rafem_mesh mesh, const int32_t* row_ptr_d, const int32_
                          double* x_d, const rafem_solve_opts* opts, rafem_solve_info* info,
                          void* stream);
 
+/* Allocation-free variant of rafem_solve, for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc): no mesh handle; the solver's
+ * workspace (r, p, A p, D^-1, their FP32 twins, partial sums, solver states) lives in one
+ * file-scope device array of RAFEM_NOALLOC_SCRATCH_BYTES bytes, which every GPU the library
+ * runs on holds from the first such call until the process ends.  The same kernels and
+ * launch shapes as rafem_solve on a handle of the same n_rows and nnz, so the iterates are
+ * the same.  Calls no hipMalloc / hipFree / pinned-host allocation.  Calls on one device are
+ * serialised (each blocks until its solve has finished); the array keeps the last call's
+ * contents, and every value a solve reads from it is written by that solve first.
+ *   n_rows    rows of A, 1 .. RAFEM_NOALLOC_MAX_ROWS (E_ARG beyond)
+ *   nnz       entries of A (row_ptr_d[n_rows]), n_rows .. INT32_MAX
+ *   other arguments as rafem_solve (CSR on the device; vals32_d required for RAFEM_MIXED)
+ * Returns info->status. */
+#define RAFEM_NOALLOC_MAX_ROWS      1048576
+#define RAFEM_NOALLOC_SCRATCH_BYTES 63705088
+rafem_status rafem_solve_noalloc(int64_t n_rows, int64_t nnz, const int32_t* row_ptr_d,
+                                 const int32_t* col_idx_d, const double* vals_d,
+                                 const float* vals32_d, const double* b_d, double* x_d,
+                                 const rafem_solve_opts* opts, rafem_solve_info* info,
+                                 void* stream);
+
 /* Adjoint solve A^T lambda = g for a matrix assembled by rafem_assemble_csr.
  * The lifted matrices are symmetric, so this runs the same PCG on A with the
  * right-hand side g with its Dirichlet rows zeroed (the adjoint of a prescribed

@@ -40,7 +40,8 @@ EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafe
            "rafem_mesh_create_batch", "rafem_mesh_sample_layout", "rafem_mesh_set_graphs",
            "rafem_sample_info", "rafem_spmv_timing", "rafem_step_pc", "rafem_mono_jacobian",
            "rafem_mono_solve", "rafem_step_mono", "rafem_rcm_order", "rafem_regions_enable",
-           "rafem_regions_read", "rafem_degree_sort", "rafem_spmv_step")
+           "rafem_regions_read", "rafem_degree_sort", "rafem_spmv_step",
+           "rafem_solve_noalloc")
 
 
 class RafemError(RuntimeError):
@@ -143,6 +144,8 @@ _lib.rafem_solve_adjoint.argtypes = [_p, _p, _p, _p, _p, _p, _p, C.POINTER(Solve
                                      C.POINTER(SolveInfo), _p]
 _lib.rafem_spmv.argtypes = [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
 _lib.rafem_spmv_step.argtypes = [_p, _i32, _i32, _p, _p, _p, _p, _p]
+_lib.rafem_solve_noalloc.argtypes = [_i64, _i64, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts),
+                                     C.POINTER(SolveInfo), _p]
 _lib.rafem_profile_enable.argtypes = [_p, _i32]
 _lib.rafem_profile_read.argtypes = [_p, _i32, C.POINTER(C.c_double), C.POINTER(C.c_int64), _i32]
 _lib.rafem_regions_enable.argtypes = [_p, _i32]
@@ -455,6 +458,28 @@ def solve(mesh: Mesh, row_ptr, col_idx, vals, b, x, *, vals32=None, tol=1e-10, p
     info = SolveInfo()
     st = _lib.rafem_solve(mesh.handle, _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(vals32), _ptr(b),
                           _ptr(x), C.byref(opts), C.byref(info), _stream(stream))
+    if check:
+        _check(st)
+    return info.as_dict()
+
+
+def solve_noalloc(row_ptr, col_idx, vals, b, x, *, vals32=None, tol=1e-10, precision="fp64",
+                  maxit=0, inner_tol=0.0, max_outer=0, poll_every=0, restart_inner=0, stream=None, check=True):
+    """rafem_solve_noalloc: rafem_solve without a handle, in the library's static device
+    workspace (no device allocation).  Returns the info dict."""
+    torch = _torch()
+    n = int(b.numel())
+    row_ptr = _dev(row_ptr, torch.int32, n + 1, "row_ptr")
+    col_idx = _dev(col_idx, torch.int32, None, "col_idx")
+    vals = _dev(vals, torch.float64, col_idx.numel(), "vals")
+    vals32 = _dev(vals32, torch.float32, col_idx.numel(), "vals32", allow_none=True)
+    b = _dev(b, torch.float64, n, "b")
+    x = _dev(x, torch.float64, n, "x")
+    opts = make_opts(tol, maxit, precision, inner_tol, max_outer, poll_every, restart_inner)
+    info = SolveInfo()
+    st = _lib.rafem_solve_noalloc(n, int(col_idx.numel()), _ptr(row_ptr), _ptr(col_idx), _ptr(vals),
+                                  _ptr(vals32), _ptr(b), _ptr(x), C.byref(opts), C.byref(info),
+                                  _stream(stream))
     if check:
         _check(st)
     return info.as_dict()

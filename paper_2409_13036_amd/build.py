@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librafem.so")
 SOURCES = ["pcg.hip", "kernels.hip", "adjoint.hip", "gmres.hip", "solver.cpp", "abi.cpp",
-           "structure.cpp", "mono.cpp"]
+           "structure.cpp", "mono.cpp", "noalloc.cpp"]
 ARCH = "gfx950"
 
 
