@@ -526,6 +526,8 @@ def batch_leg(args) -> dict:
     probs = ri.config4(samples=args.batch_samples, steps=args.batch_steps)
     t0 = time.perf_counter()
     bp = BatchProblem(probs)
+    if args.device_driven:
+        bp.mesh.set_device_driven(True)
     bp.extrapolate = not args.no_extrapolate
     bp.extrapolate_order = args.extrapolate_order
     setup = time.perf_counter() - t0
@@ -534,18 +536,28 @@ def batch_leg(args) -> dict:
     out = {"workload": f"C4 ensemble, {S} hex samples n~U{{41..81}}, {args.batch_steps} coupled "
                        f"steps, one batch handle",
            "samples": S, "n_nodes_total": int(sum(p.n_nodes for p in probs)), "nnz_total": nnz,
-           "setup_s": setup}
+           "handle_rows": int(bp.mesh.n_nodes), "handle_nnz": int(bp.mesh.nnz), "setup_s": setup}
     finals = {}
-    for precision in ("fp64", "mixed"):
+
+    def timed(precision):
         bp.reset()
-        bp.step(TOL, precision)  # warm-up: bioheat assembly, autotuning, graph capture
+        bp.step(TOL, precision)  # warm-up: bioheat assembly, autotuning, graph capture, counts
         bp.reset()
+        st0 = bp.mesh.stats()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.batch_steps):
             bp.step(TOL, precision)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        st = bp.mesh.stats()
+        dd = {"device_driven": bool(st.device_driven),
+              "accepted_solves": int(st.device_driven_solves - st0.device_driven_solves),
+              "redone_solves": int(st.device_driven_redone - st0.device_driven_redone)}
+        return el, dd
+
+    for precision in ("fp64", "mixed"):
+        el, dd = timed(precision)
         finals[precision] = [bp.sample(q) for q in range(S)]
         its = [bp.mesh.sample_info(q) for q in range(S)]
         R.profile_enable(bp.mesh, True)
@@ -560,9 +572,20 @@ def batch_leg(args) -> dict:
                                           max(i["V"]["iters"] for i in its)],
             "T_iters_last_step_min_max": [min(i["T"]["iters"] for i in its),
                                           max(i["T"]["iters"] for i in its)],
-            "spmv_us_mean": mean_us, "spmv_launches": count}
+            "spmv_us_mean": mean_us, "spmv_launches": count, "device_driven": dd}
         print(f"[bench] batch {precision}: {S * args.batch_steps / el:.1f} sample-steps/s "
-              f"({el:.2f} s), spmv {mean_us:.1f} us x {count}", file=sys.stderr, flush=True)
+              f"({el:.2f} s), spmv {mean_us:.1f} us x {count}, {dd}", file=sys.stderr, flush=True)
+    # the other way of driving the solves, for comparison (same iterates)
+    dd_default = bool(bp.mesh.stats().device_driven)
+    bp.mesh.set_device_driven(not dd_default)
+    for precision in ("fp64", "mixed"):
+        el, dd = timed(precision)
+        key = "host_driven" if dd_default else "device_driven"
+        out[precision][key] = {"sample_steps_per_s": S * args.batch_steps / el, "elapsed_s": el,
+                               **dd}
+        print(f"[bench] batch {precision} ({key}): {S * args.batch_steps / el:.1f} "
+              f"sample-steps/s, {dd}", file=sys.stderr, flush=True)
+    bp.mesh.set_device_driven(dd_default)
     rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
     eT = [rel(m[0], f[0]) for m, f in zip(finals["mixed"], finals["fp64"])]
     eV = [rel(m[1], f[1]) for m, f in zip(finals["mixed"], finals["fp64"])]
@@ -774,21 +797,28 @@ def liver_leg(args) -> dict:
         c = pos[conn]
         return int((c.max(axis=1) - c.min(axis=1)).max())
 
-    def measure(prob, steps, warmup, label):
+    inner_tol = args.inner_tol if args.inner_tol is not None else 1e-3
+
+    def measure(prob, steps, warmup, label, roofline=False):
         dp = DeviceProblem(prob)
         dp.extrapolate = not args.no_extrapolate
         dp.extrapolate_order = args.extrapolate_order
         st = dp.mesh.stats()
         N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
         row = {"n_nodes": N, "n_elems": dp.mesh.n_elems, "nnz": nnz, "colours": st.n_colours,
-               "slabs": int(st.slabs), "int16_columns": int(st.int16_columns)}
+               "slabs": int(st.slabs), "int16_columns": int(st.int16_columns),
+               "mixed_inner_tol": inner_tol}
         for precision in ("fp64", "mixed"):
-            el, infos, _, (us, cnt) = run_path(dp, precision, steps, warmup, 1)
+            kw = {"inner_tol": inner_tol} if precision == "mixed" else {}
+            el, infos, _, (us, cnt) = run_path(dp, precision, steps, warmup, 1, **kw)
             fp32 = precision == "mixed"
             row[precision] = {
                 "steps_per_s": steps / el,
                 "V_iters": float(np.mean([i["V"]["iters"] for i in infos])),
                 "spmv_us": us, "spmv_GBs": spmv_bytes(N, nnz, fp32) / (us * 1e3) if us else None}
+            if roofline:
+                row[precision]["roofline"] = spmv_roofline(
+                    dp.mesh, spmv_kernel_name(dp.mesh, fp32), f"liver {N} {label}", fp32, us, cnt)
             print(f"[bench] liver {label} {precision}: {steps / el:.2f} steps/s, spmv {us:.1f} us",
                   file=sys.stderr, flush=True)
         dp.close()
@@ -805,7 +835,8 @@ def liver_leg(args) -> dict:
     qs, order_s = rcm_reordered(p, window=512)
     for label, prob, o in (("shuffled", p, None), ("rcm", q, order),
                            ("rcm_degree_sorted", qs, order_s)):
-        row = measure(prob, args.liver_steps, 2, f"{args.liver_nodes} {label}")
+        row = measure(prob, args.liver_steps, 2, f"{args.liver_nodes} {label}",
+                      roofline=label == "rcm")
         row["bandwidth"] = bandwidth(p.conn, o)
         out[f"large_{label}"] = row
     return out
@@ -834,6 +865,9 @@ def main():
     ap.add_argument("--no-extrapolate", action="store_true",
                     help="start every solve from the previous state instead of the linear "
                          "extrapolation of the last two")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the mixed refinement's inner tolerance and restart mode with "
+                         "paper_2409_13036_amd.tune (cached on disk) before timing")
     ap.add_argument("--restart-inner", action="store_true",
                     help="mixed precision: plain restarted refinement (a new inner Krylov space "
                          "per refinement) instead of the default reliable updates")
@@ -855,6 +889,9 @@ def main():
     ap.add_argument("--pc-eps", type=float, default=1e-9,
                     help="predictor-corrector: relative change of T that ends a corrector")
     ap.add_argument("--batch-only", action="store_true", help="run only the ensemble leg")
+    ap.add_argument("--device-driven", action="store_true",
+                    help="ensemble leg: time the device-driven solves first (each solve enqueued "
+                         "whole, one poll per solve) and the host-driven default second")
     ap.add_argument("--batch-samples", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=30)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -891,6 +928,8 @@ def main():
         print(json.dumps(adjoint_leg(args)), flush=True)
         return
     if args.batch_only:
+        if args.copy_probe_mib > 0:
+            copy_probe(args.copy_probe_mib)
         print(json.dumps(batch_leg(args)), flush=True)
         return
     if args.liver:
@@ -929,6 +968,13 @@ def main():
     dp.extrapolate_order = args.extrapolate_order
     N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
     mesh_stats = dp.mesh.stats()
+    tuned = None
+    if args.autotune:
+        from paper_2409_13036_amd.tune import tune_mixed
+        tuned = tune_mixed(dp, tol=TOL)
+        args.inner_tol = tuned["inner_tol"]
+        args.restart_inner = bool(tuned["restart_inner"])
+        print(f"[bench] autotune: {tuned}", file=sys.stderr, flush=True)
     res = {}
     for precision in ("fp64", "mixed"):
         inner_tol = args.inner_tol
@@ -972,7 +1018,9 @@ def main():
                    "shared_offset_slabs": int(mesh_stats.shared_offset_slabs),
                    "predictor_order": (None if args.no_extrapolate
                                        else args.extrapolate_order),
-                   "inner_tol": inner_tol if inner_tol else "library default (3e-5)"},
+                   "inner_tol": inner_tol if inner_tol else "library default (3e-5)",
+                   "refinement": "restarted" if args.restart_inner else "reliable updates",
+                   "autotune": tuned},
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp64": {"steps_per_s": args.steps / res["fp64"]["elapsed"],

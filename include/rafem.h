@@ -137,6 +137,12 @@ typedef struct {
     int64_t value_slots;         /* stored values per matrix in the slab layout (padding included) */
     int64_t index_bytes;         /* column data one product reads: slab pointers, the shared
                                     offset lists, 16- or 32-bit per-slot column offsets */
+    int32_t device_driven;       /* 1 if rafem_step's solves run device-driven (see
+                                    rafem_mesh_set_device_driven) */
+    int32_t tuned_from_cache;    /* 1 if the slab shapes came from the autotuner's on-disk cache
+                                    (RAFEM_TUNE_CACHE, else ~/.cache/rafem/spmv_tune.txt) */
+    int64_t device_driven_solves;/* solves of rafem_step completed device-driven */
+    int64_t device_driven_redone;/* device-driven solves redone host-driven (a budget fell short) */
 } rafem_mesh_stats;
 
 /* Build a mesh on the current device.
@@ -177,6 +183,25 @@ rafem_status rafem_mesh_sample_layout(rafem_mesh mesh, int64_t* node_off, int64_
 /* Use (nonzero) or not HIP graphs for the PCG iteration chunks of this mesh's steps.  On by
  * default for batch handles.  Graphs are not used while SpMV profiling is enabled. */
 rafem_status rafem_mesh_set_graphs(rafem_mesh mesh, int32_t enable);
+
+/* Device-driven solves (off by default): each of
+ * rafem_step's two solves is enqueued at once -- the PCG iterations and, in mixed
+ * precision, every refinement with its inner solve -- each (inner) solve with an iteration
+ * budget of ceil(budget_scale x the larger of its counts in the last two solves of its
+ * kind) + 3 (kernels past convergence exit at once), and in mixed precision the residual
+ * check of one refinement more than the last solve needed.  The solver states are logged on
+ * the device after every (inner) solve, and one poll at the end of the solve reads them: it
+ * is accepted if it did exactly what the host-driven solve does (every inner solve finished
+ * within its budget, every sample converged, no refinement stagnated); otherwise its
+ * starting point is restored and it runs host-driven.  Either way the results are bit for
+ * bit the host-driven solve's; an accepted solve synchronises with the host once (two per
+ * coupled step) instead of at every poll.  Solves without counts from a previous solve of
+ * the same kind and precision, and solves while SpMV profiling or region timing is on, run
+ * host-driven; so do rafem_step_pc, rafem_step_mono and rafem_step_vjp.
+ *   enable        nonzero: on (allocates the solver logs and a copy of one node vector on
+ *                 first use)
+ *   budget_scale  0 for the default 1.05, else (0, 16] */
+rafem_status rafem_mesh_set_device_driven(rafem_mesh mesh, int32_t enable, double budget_scale);
 
 /* Free a mesh and its device memory (synchronises the device first).  NULL is a no-op. */
 rafem_status rafem_mesh_destroy(rafem_mesh mesh);

@@ -41,7 +41,7 @@ EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafe
            "rafem_sample_info", "rafem_spmv_timing", "rafem_step_pc", "rafem_mono_jacobian",
            "rafem_mono_solve", "rafem_step_mono", "rafem_rcm_order", "rafem_regions_enable",
            "rafem_regions_read", "rafem_degree_sort", "rafem_spmv_step",
-           "rafem_solve_noalloc")
+           "rafem_solve_noalloc", "rafem_mesh_set_device_driven")
 
 
 class RafemError(RuntimeError):
@@ -57,7 +57,9 @@ class MeshStats(C.Structure):
                 ("slabs_per_block32", C.c_int32), ("int16_columns", C.c_int32),
                 ("slabs", C.c_int64), ("shared_offset_slabs", C.c_int64),
                 ("row_assembly", C.c_int32), ("max_row_entries", C.c_int32),
-                ("value_slots", C.c_int64), ("index_bytes", C.c_int64)]
+                ("value_slots", C.c_int64), ("index_bytes", C.c_int64),
+                ("device_driven", C.c_int32), ("tuned_from_cache", C.c_int32),
+                ("device_driven_solves", C.c_int64), ("device_driven_redone", C.c_int64)]
 
 
 class SolveOpts(C.Structure):
@@ -168,6 +170,7 @@ _lib.rafem_lesion_loss.argtypes = [_p, _i64, _p, _p, _p, C.c_double, _p, _p, _p]
 _lib.rafem_mesh_create_batch.argtypes = [_i32, _p, _p, _i32, _p, _p, _p, _p, C.POINTER(_p)]
 _lib.rafem_mesh_sample_layout.argtypes = [_p, _p, _p, _p]
 _lib.rafem_mesh_set_graphs.argtypes = [_p, _i32]
+_lib.rafem_mesh_set_device_driven.argtypes = [_p, _i32, C.c_double]
 _lib.rafem_sample_info.argtypes = [_p, _i32, C.POINTER(StepInfo)]
 for _name in EXPORTS:
     if _name not in ("rafem_last_error", "rafem_abi_version"):
@@ -371,6 +374,11 @@ class Mesh:
         st = MeshStats()
         _check(_lib.rafem_mesh_get_stats(self.handle, C.byref(st)))
         return st
+
+    def set_device_driven(self, enable: bool, budget_scale: float = 0.0):
+        """rafem_mesh_set_device_driven: whole solves enqueued at once, one poll per solve."""
+        _check(_lib.rafem_mesh_set_device_driven(self.handle, 1 if enable else 0,
+                                                 float(budget_scale)))
 
     def set_graphs(self, enable: bool):
         _check(_lib.rafem_mesh_set_graphs(self.handle, 1 if enable else 0))

@@ -76,6 +76,7 @@ void free_mesh(rafem_mesh m) {
     for (void* p : m->allocations) (void)hipFree(p);
     if (m->gm_V) (void)hipFree(m->gm_V);
     if (m->st_host) (void)hipHostFree(m->st_host);
+    if (m->dd_log_host) (void)hipHostFree(m->dd_log_host);
     if (m->gm_st_host) (void)hipHostFree(m->gm_st_host);
     delete m;
 }
@@ -244,8 +245,32 @@ void assemble_potential(rafem_mesh m, const rafem_phys* phys, const double* sigm
     m->potential_ready = true;
 }
 
-Samples step_samples(rafem_mesh m) { return Samples{m->S, m->row_off}; }
+// The buffers of device-driven steps (allocated once, by the handle's creation for a
+// batch or by the first rafem_mesh_set_device_driven that turns them on).
+void dd_alloc(rafem_mesh m) {
+    if (m->dd_log) return;
+    const size_t n = 3 * (size_t)m->S * kDdSlots;
+    m->dd_log = dalloc<PcgState>(m, n);
+    m->dd_x0 = dalloc<double>(m, (size_t)m->n);
+    if (hipHostMalloc((void**)&m->dd_log_host, n * sizeof(PcgState), hipHostMallocDefault) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        m->dd_log_host = nullptr;
+        throw Error{RAFEM_E_NOMEM, "pinned host allocation failed"};
+    }
+}
+
+Samples step_samples(rafem_mesh m) { return Samples{m->S, m->row_off, m->row_tab}; }
 Samples whole_mesh(rafem_mesh m) { return Samples{1, m->row_off_one}; }
+
+// Iteration counts a device-driven solve of this kind budgets for: per (inner) solve the
+// larger of its counts in the last two solves of the kind.
+std::vector<int> dd_counts(rafem_mesh m, int kind, bool mixed) {
+    std::vector<int> c = m->hints[kind][mixed ? 1 : 0];
+    const std::vector<int>& p = m->hints_prev[kind][mixed ? 1 : 0];
+    for (size_t j = 0; j < c.size() && j < p.size(); ++j) c[j] = std::max(c[j], p[j]);
+    return c;
+}
 
 void solve_any(rafem_mesh m, const SolveOpts& o, const Mat& A, const Samples& smp,
                const double* dinv, const float* dinv32, const double* b, double* x,
@@ -253,16 +278,57 @@ void solve_any(rafem_mesh m, const SolveOpts& o, const Mat& A, const Samples& sm
     // kind: which solve of a step (its own chunk hints per precision), or -1 for none
     const bool mixed = o.precision == RAFEM_MIXED;
     std::vector<int>* hints = kind >= 0 ? &m->hints[kind][mixed ? 1 : 0] : nullptr;
+    if (hints) m->hints_prev[kind][mixed ? 1 : 0] = *hints;
     if (mixed)
         pcg_mixed(m, A, smp, dinv, dinv32, b, x, o, info, s, hints);
     else
         pcg64(m, A, smp, dinv, b, x, o, info, s, hints);
 }
 
+void record_samples(rafem_mesh m, bool potential, bool mixed, const PcgState* h = nullptr);
+
+// One solve of a coupled step (rafem_step's potential or bioheat solve), device-driven when
+// the handle asks for it and the previous solve of this kind left its counts: the starting
+// point is saved, the whole solve enqueued (dd_enqueue) and one poll of its logs decides
+// whether it did exactly what the host-driven solve does; if not, the starting point is
+// restored and the solve runs host-driven.  Either way the result, the info and the
+// per-sample records are the host-driven solve's.
+void solve_step(rafem_mesh m, const SolveOpts& o, const Mat& A, const double* dinv,
+                const float* dinv32, const double* b, double* x, rafem_solve_info* info,
+                hipStream_t s, int kind) {
+    const bool mixed = o.precision == RAFEM_MIXED;
+    const bool potential = kind == kSolvePotential;
+    std::vector<int>& hints = m->hints[kind][mixed ? 1 : 0];
+    m->dd_used = 0;
+    if (m->dd_on && m->tuned && !m->reg_on && dd_ready(m, o, &hints)) {
+        const size_t bytes = (size_t)m->n * sizeof(double);
+        RAFEM_HIP(hipMemcpyAsync(m->dd_x0, x, bytes, hipMemcpyDeviceToDevice, s));
+        const DdRecord r = dd_enqueue(m, A, step_samples(m), dinv, dinv32, b, x, o,
+                                      dd_counts(m, kind, mixed), s);
+        const size_t n = 3 * (size_t)m->S;
+        RAFEM_HIP(hipMemcpyAsync(m->dd_log_host, m->dd_log, m->dd_used * n * sizeof(PcgState),
+                                 hipMemcpyDeviceToHost, s));
+        RAFEM_HIP(hipStreamSynchronize(s));
+        std::vector<int> h = hints;
+        const PcgState* hs = nullptr;
+        if (dd_finish(m, r, o, info, &h, &hs)) {
+            record_samples(m, potential, mixed, hs);
+            m->hints_prev[kind][mixed ? 1 : 0] = hints;
+            hints = h;
+            m->dd_solves += 1;
+            return;
+        }
+        m->dd_redone += 1;
+        RAFEM_HIP(hipMemcpyAsync(x, m->dd_x0, bytes, hipMemcpyDeviceToDevice, s));
+    }
+    solve_any(m, o, A, step_samples(m), dinv, dinv32, b, x, info, s, kind);
+    record_samples(m, potential, mixed);
+}
+
 // Per-sample results of the solve that just finished (its last poll is in st_host).
-void record_samples(rafem_mesh m, bool potential, bool mixed) {
+void record_samples(rafem_mesh m, bool potential, bool mixed, const PcgState* h) {
     const int S = m->S;
-    const PcgState* h = m->st_host;
+    if (!h) h = m->st_host;
     for (int q = 0; q < S; ++q) {
         // a mixed solve's sample that fell back to FP64 PCG ends with that solve's state
         const bool fell = mixed && m->mixed_fell[q];
@@ -429,6 +495,16 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             for (int q = 0; q <= S_; ++q) roff[q] = (int32_t)node_off[q];
             const int32_t one[2] = {0, (int32_t)n_nodes};
             RAFEM_HIP(hipMemcpy(m->row_off, roff.data(), roff.size() * 4, hipMemcpyHostToDevice));
+            if (S_ > 1) {
+                // the sample of every kRowAlign-row block (every sample offset is a multiple)
+                const int64_t nb = (n_nodes + kRowAlign - 1) / kRowAlign;
+                std::vector<int32_t> tab(nb);
+                for (int q = 0; q < S_; ++q)
+                    for (int64_t b = node_off[q] / kRowAlign; b < (node_off[q + 1] + kRowAlign - 1) / kRowAlign && b < nb; ++b)
+                        tab[b] = q;
+                m->row_tab = dalloc<int32_t>(m, nb);
+                RAFEM_HIP(hipMemcpy(m->row_tab, tab.data(), nb * 4, hipMemcpyHostToDevice));
+            }
             RAFEM_HIP(hipMemcpy(m->row_off_one, one, 8, hipMemcpyHostToDevice));
             m->S = S_;
             m->node_off = node_off;
@@ -680,6 +756,18 @@ rafem_status rafem_mesh_set_graphs(rafem_mesh m, int32_t enable) {
     });
 }
 
+rafem_status rafem_mesh_set_device_driven(rafem_mesh m, int32_t enable, double budget_scale) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        require(budget_scale == 0.0 || (budget_scale > 0.0 && budget_scale <= 16.0),
+                "budget_scale must be 0 (default) or in (0, 16]");
+        if (enable) dd_alloc(m);
+        m->dd_on = enable != 0;
+        m->dd_scale = budget_scale > 0.0 ? budget_scale : 1.05;
+        return RAFEM_OK;
+    });
+}
+
 rafem_status rafem_mesh_destroy(rafem_mesh mesh) {
     return guard([&]() -> rafem_status {
         free_mesh(mesh);
@@ -706,6 +794,10 @@ rafem_status rafem_mesh_get_stats(rafem_mesh m, rafem_mesh_stats* out) {
         out->max_row_entries = m->max_w;
         out->value_slots = m->sell_nnz;
         out->index_bytes = m->index_bytes;
+        out->device_driven = m->dd_on ? 1 : 0;
+        out->tuned_from_cache = m->tuned_from_cache ? 1 : 0;
+        out->device_driven_solves = m->dd_solves;
+        out->device_driven_redone = m->dd_redone;
         return RAFEM_OK;
     });
 }
@@ -898,7 +990,7 @@ rafem_status rafem_spmv_timing(rafem_mesh m, int32_t precision, int32_t n_copies
             for (auto& e : ev) RAFEM_HIP(hipEventCreate(&e));
             hipStream_t s = nullptr;
             const int S = m->S;
-            Samples smp{S, m->row_off};
+            Samples smp{S, m->row_off, m->row_tab};
             PcgState* chk = m->st + 2 * S;
             launch_state_init(chk, S, 0.0, 0, nullptr, s);
             launch_fill(m->p, m->n, 1.0, s);
@@ -1035,10 +1127,8 @@ rafem_status step_core(rafem_mesh m, const rafem_phys* phys, bool reuse_bioheat,
         const Mat AV = step_matrix(m, m->valsV, m->valsV32);
         if (!m->tuned) autotune_spmv(m, AV, s);
         region_mark(m, kRegSolve, s);
-        solve_any(m, o, AV, step_samples(m), m->dinvV, m->dinvV32, m->liftV, V_d, &inf.V, s,
-                  kSolvePotential);
+        solve_step(m, o, AV, m->dinvV, m->dinvV32, m->liftV, V_d, &inf.V, s, kSolvePotential);
         region_mark(m, kRegAssembly, s);
-        record_samples(m, true, mixed);
         if (inf.V.status != RAFEM_OK) {
             set_error("potential solve failed");
             return inf.V.status;
@@ -1065,10 +1155,8 @@ rafem_status step_core(rafem_mesh m, const rafem_phys* phys, bool reuse_bioheat,
     const Mat AT = step_matrix(m, m->valsT, m->valsT32);
     if (!m->tuned) autotune_spmv(m, AT, s);
     region_mark(m, kRegSolve, s);
-    solve_any(m, o, AT, step_samples(m), m->dinvT, m->dinvT32, m->bT, T_out, &inf.T, s,
-              kSolveBioheat);
+    solve_step(m, o, AT, m->dinvT, m->dinvT32, m->bT, T_out, &inf.T, s, kSolveBioheat);
     region_mark(m, kRegCheck, s);
-    record_samples(m, false, mixed);
     if (inf.T.status != RAFEM_OK) {
         set_error("bioheat solve failed");
         return inf.T.status;

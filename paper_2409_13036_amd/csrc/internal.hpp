@@ -139,6 +139,7 @@ constexpr int kRowAlign = 1024;
 struct Samples {
     int S;
     const int32_t* row_off;
+    const int32_t* tab = nullptr;  // [rows / kRowAlign] sample of each aligned block, or NULL
 };
 
 // Grid of a row kernel: blocks and rows per block (to locate a sample's partial slots).
@@ -435,6 +436,7 @@ struct rafem_mesh_s {
     rafem::SpmvConfig spmv{4, 512, 8};    // FP64 kernels
     rafem::SpmvConfig spmv32{4, 512, 8};  // FP32 kernels
     bool tuned = false;                   // slab shapes picked by the autotuner
+    bool tuned_from_cache = false;        // ... taken from its on-disk cache
     bool use_graphs = false;              // iteration chunks captured as HIP graphs
     hipStream_t gstream = nullptr;        // capture stream
     struct GraphEntry {
@@ -501,6 +503,7 @@ struct rafem_mesh_s {
     double *adj_mu = nullptr, *adj_nu = nullptr, *adj_sbar = nullptr, *adj_dsig = nullptr;
     // iteration counts of the previous solve of each kind and precision (first-chunk guesses)
     std::vector<int> hints[4][2];
+    std::vector<int> hints_prev[4][2];  // the counts of the solve before (device-driven budgets)
 
     // monolithic corrector (allocated on first use): Jacobian slots as double4 in the SELL
     // layout, -R, block-Jacobi inverses, the Newton update, GMRES vectors and basis
@@ -526,6 +529,7 @@ struct rafem_mesh_s {
     std::vector<int64_t> elem_off;      // host [S + 1]
     std::vector<int64_t> dir_off;       // host [S + 1]
     int32_t* row_off = nullptr;         // device [S + 1]
+    int32_t* row_tab = nullptr;         // device [n / kRowAlign] sample of each 1024-row block
     int32_t* row_off_one = nullptr;     // device {0, n}: the whole mesh as one system
     std::vector<rafem_step_info> sample_info;  // per-sample info of the last step
     std::vector<int> mixed_iters;   // per sample: inner (+ FP64 fallback) iterations of the last mixed solve
@@ -545,9 +549,25 @@ struct rafem_mesh_s {
     double prof_sum_us[2] = {0.0, 0.0};  // [0] FP64 kernel, [1] FP32 kernel
     int64_t prof_cnt[2] = {0, 0};
 
+    // device-driven solves (rafem_mesh_set_device_driven; off by default): each solve
+    // of a step is enqueued whole, its iteration budgets taken from the previous solves'
+    // counts, and the solver states are logged after every (inner) solve; one poll at its
+    // end checks the logs, and a solve whose budgets fell short is redone from its saved
+    // starting point host-driven
+    bool dd_on = false;
+    double dd_scale = 1.05;               // budget = ceil(count * dd_scale) + kDdSlack
+    rafem::PcgState* dd_log = nullptr;       // device [kDdSlots][3 S]
+    rafem::PcgState* dd_log_host = nullptr;  // pinned mirror
+    double* dd_x0 = nullptr;              // the solve's starting point
+    int dd_used = 0;                      // log slots used by the current solve
+    int64_t dd_solves = 0, dd_redone = 0; // device-driven solves accepted / redone
+
     std::vector<void*> allocations;
 };
 
 namespace rafem {
 constexpr int kProfCap = 2048;
+constexpr int kDdMaxRounds = 15;                  // refinements enqueued per mixed solve, at most
+constexpr int kDdSlots = kDdMaxRounds + 1;        // log slots of one solve
+constexpr int kDdSlack = 3;                       // iterations added to every budget
 }

@@ -38,9 +38,12 @@ namespace {
 
 using namespace dev;
 
-// Sample owning `row` (largest s with row_off[s] <= row).
+// Sample owning `row` (largest s with row_off[s] <= row): one load from the table of the
+// sample of every kRowAlign-row block (sample boundaries are multiples of kRowAlign), or a
+// binary search over row_off when there is no table.
 __device__ __forceinline__ int sample_of(const Samples& B, int row) {
     if (B.S == 1) return 0;
+    if (B.tab) return B.tab[row / kRowAlign];
     int lo = 0, hi = B.S - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -64,24 +67,43 @@ __device__ __forceinline__ void sample_blocks(const Samples& B, int s, int rpb, 
 // at once so their latencies overlap.
 constexpr int kRangeUnroll = 8;
 
+// The first batch of a thread's slots, loaded ahead (range_prefetch) so that the vector
+// kernels can issue these loads together with their vector loads and before they read the
+// solver state; range_totals then adds it and any further batches.
+template <int K>
+struct RangeBatch {
+    double v[K][kRangeUnroll];
+};
+
+template <int K>
+__device__ __forceinline__ void range_prefetch(const double* __restrict__ partials, int nb,
+                                               int b0, int b1, RangeBatch<K>& first) {
+    const int base = b0 + (int)threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kRangeUnroll; ++u) {
+        const int i = base + u * WG;
+#pragma unroll
+        for (int k = 0; k < K; ++k) first.v[k][u] = i < b1 ? partials[k * nb + i] : 0.0;
+    }
+}
+
 template <int K>
 __device__ __forceinline__ void range_totals(const double* __restrict__ partials, int nb, int b0,
-                                             int b1, double (&tot)[K]) {
+                                             int b1, double (&tot)[K],
+                                             const RangeBatch<K>* first = nullptr) {
     __shared__ double bcast[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) tot[k] = 0.0;
     for (int base = b0 + (int)threadIdx.x; base < b1; base += kRangeUnroll * WG) {
-        double v[K][kRangeUnroll];
-#pragma unroll
-        for (int u = 0; u < kRangeUnroll; ++u) {
-            const int i = base + u * WG;
-#pragma unroll
-            for (int k = 0; k < K; ++k) v[k][u] = i < b1 ? partials[k * nb + i] : 0.0;
-        }
+        RangeBatch<K> b;
+        if (first && base == b0 + (int)threadIdx.x)
+            b = *first;
+        else
+            range_prefetch<K>(partials, nb, base - (int)threadIdx.x, b1, b);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
 #pragma unroll
-            for (int u = 0; u < kRangeUnroll; ++u) tot[k] += v[k][u];
+            for (int u = 0; u < kRangeUnroll; ++u) tot[k] += b.v[k][u];
         }
     }
     block_sum<K>(tot);
@@ -235,6 +257,7 @@ __global__ __launch_bounds__(WG) void k_csr(RowArgs<T> a) {
 }
 
 constexpr int kSellUnroll = 9;
+
 
 // Sum over the entries of one row in entry order.  COL is int (absolute columns, xr = x)
 // or int16_t (offsets to the row, xr = x + row).
@@ -479,11 +502,13 @@ __global__ __launch_bounds__(WG) void k_update(int n, T* __restrict__ x, T* __re
             dv[u] = dinv[i];
         }
     }
-    if (S.done) return;
     int b0, b1;
     sample_blocks(smp, s, rpb_pq, b0, b1);
+    RangeBatch<1> first;
+    range_prefetch<1>(pq_part, nb_pq, b0, b1, first);
+    if (S.done) return;
     double pq[1];
-    range_totals<1>(pq_part, nb_pq, b0, b1, pq);
+    range_totals<1>(pq_part, nb_pq, b0, b1, pq, &first);
     const bool writer = threadIdx.x == 0 && blk == smp.row_off[s] / kVecRowsPerBlock;
     if (!(pq[0] > 0.0) || !finite(pq[0])) {
         if (writer) {
@@ -538,11 +563,13 @@ __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
             dv[u] = dinv[i];
         }
     }
-    if (S.done) return;
     int b0, b1;
     sample_blocks(smp, s, kVecRowsPerBlock, b0, b1);
+    RangeBatch<2> first;
+    range_prefetch<2>(rz_part, nb_rz, b0, b1, first);
+    if (S.done) return;
     double tot[2];
-    range_totals<2>(rz_part, nb_rz, b0, b1, tot);
+    range_totals<2>(rz_part, nb_rz, b0, b1, tot, &first);
     const double rz = tot[0], rr = tot[1];
     const int iters = it + 1;
     int status = -1;

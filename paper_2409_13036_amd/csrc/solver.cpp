@@ -7,9 +7,14 @@
 // are enqueued past convergence (those exit at once on the device flag) and the host
 // synchronises only a handful of times per solve.  Optionally a chunk is captured once
 // as a HIP graph (its iteration index comes from device memory) and replayed.
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 
 #include "solver.hpp"
 
@@ -410,14 +415,226 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
     return worst_status(ho, S);
 }
 
+bool dd_ready(rafem_mesh m, const SolveOpts& o, const std::vector<int>* hints) {
+    if (!m->dd_on || m->prof_on || !hints || hints->empty() || o.poll_every > 0) return false;
+    const int rounds = o.precision == RAFEM_MIXED ? (int)hints->size() + 1 : 1;
+    if (o.precision == RAFEM_MIXED && rounds > std::min(kDdMaxRounds, o.max_outer + 1)) return false;
+    return m->dd_used + rounds <= kDdSlots;
+}
+
+namespace {
+
+int dd_budget(rafem_mesh m, int count, int maxit) {
+    const int k = (int)std::ceil(count * m->dd_scale) + kDdSlack;
+    return std::max(1, std::min(k, maxit));
+}
+
+
+void dd_log(rafem_mesh m, int slot, hipStream_t s) {
+    const size_t n = 3 * (size_t)m->S;
+    RAFEM_HIP(hipMemcpyAsync(m->dd_log + slot * n, m->st, n * sizeof(PcgState),
+                             hipMemcpyDeviceToDevice, s));
+}
+
+}  // namespace
+
+DdRecord dd_enqueue(rafem_mesh m, const Mat& A, const Samples& smp, const double* dinv,
+                    const float* dinv32, const double* b, double* x, const SolveOpts& o,
+                    const std::vector<int>& hints, hipStream_t s) {
+    const int S = smp.S;
+    DdRecord r;
+    r.slot0 = m->dd_used;
+    r.mixed = o.precision == RAFEM_MIXED;
+    if (!r.mixed) {
+        PcgState* st = m->st;
+        PcgState* chk = m->st + 2 * S;
+        int* itb = m->itb;
+        launch_state_init(st, S, o.tol, o.maxit, itb, s);
+        launch_pcg_start(A, m->spmv, b, x, dinv, m->r, m->p, m->partials, st, smp, s);
+        const Iter64 iter{m, &A, &m->spmv, dinv, x, st, smp, itb};
+        hipGraphExec_t graph = nullptr;
+        if (m->use_graphs)
+            graph = chunk_graph(m, 0, A.v, x, dinv, (const void*)A.sptr, iter, itb);
+        const int k = dd_budget(m, hints[0], o.maxit);
+        enqueue(k, iter, graph, itb, nullptr, s);
+        launch_state_init(chk, S, 0.0, 0, nullptr, s);
+        launch_residual64(A, m->spmv, b, x, m->r, m->partials, chk, smp, 0, s);
+        dd_log(m, r.slot0, s);
+        check_launch();
+        r.rounds = 1;
+        r.budget.push_back(k);
+        m->dd_used += 1;
+        return r;
+    }
+    PcgState* inner = m->st;
+    PcgState* outer = m->st + S;
+    const int n = A.n;
+    int* itb = m->itb + 1;
+    launch_state_init(outer, S, o.tol, o.max_outer, nullptr, s);
+    const Iter32 iter{m, &A, &m->spmv32, dinv32, inner, smp, itb};
+    hipGraphExec_t graph = nullptr;
+    if (m->use_graphs)
+        graph = chunk_graph(m, 1, A.v32, dinv32, (const void*)A.sptr, nullptr, iter, itb);
+    const int rounds = (int)hints.size() + 1;
+    for (int j = 0; j < rounds; ++j) {
+        // the same sequence as pcg_mixed's loop; rounds past a sample's convergence leave its
+        // x alone (every kernel skips a finished refinement)
+        launch_residual64(A, m->spmv, b, x, m->r64, m->partials, outer, smp, 1, s);
+        if (j == (int)hints.size()) {
+            // the check round: the residual of the last refinement decides; a sample that
+            // needs another refinement makes the step be redone
+            dd_log(m, r.slot0 + j, s);
+            r.budget.push_back(0);
+            break;
+        }
+        const int cont = (j > 0 && !o.restart_inner) ? 1 : 0;
+        launch_inner_start(n, m->r64, outer, m->r32, m->d32, m->p32, dinv32, o.inner_tol, o.maxit,
+                           m->partials, inner, smp, cont, s);
+        launch_state_init(nullptr, 0, 0.0, 0, itb, s);
+        const int k = dd_budget(m, hints[j], o.maxit);
+        enqueue(k, iter, graph, itb, nullptr, s);
+        launch_refine_update(n, x, m->d32, outer, smp, s);
+        dd_log(m, r.slot0 + j, s);
+        r.budget.push_back(k);
+    }
+    check_launch();
+    r.rounds = rounds;
+    m->dd_used += rounds;
+    return r;
+}
+
+bool dd_finish(rafem_mesh m, const DdRecord& r, const SolveOpts& o, rafem_solve_info* info,
+               std::vector<int>* hints, const PcgState** h_out) {
+    const int S = m->S;
+    const size_t n = 3 * (size_t)S;
+    const PcgState* log = m->dd_log_host + r.slot0 * n;
+    if (!r.mixed) {
+        const PcgState* h = log;
+        for (int q = 0; q < S; ++q)
+            if (!h[q].done || h[q].status != RAFEM_OK) return false;
+        fill_info(info, h, h + 2 * S, S, r.budget[0], 0);
+        if (hints) hints->assign(1, max_iters(h, S));
+        *h_out = h;
+        return true;
+    }
+    std::vector<double> prev_rr(S, -1.0);
+    std::vector<int> stagnant(S, 0), per_sample(S, 0), counts;
+    int total_inner = 0, launched = 0, outer_steps = 0;
+    for (int j = 0; j < r.rounds; ++j) {
+        const PcgState* in = log + j * n;
+        const PcgState* out = in + S;
+        bool ran = false;
+        for (int q = 0; q < S; ++q) {
+            if (out[q].done) continue;
+            ran = true;
+            if (!in[q].done) return false;  // the inner solve ran out of its budget
+            // the host-driven solve's stagnation rule on the same residuals
+            if (prev_rr[q] > 0.0 && out[q].rr > 0.25 * prev_rr[q]) stagnant[q] += 1;
+            else stagnant[q] = 0;
+            prev_rr[q] = out[q].rr;
+            if (stagnant[q] >= 2) return false;
+        }
+        if (!ran) continue;
+        const int it = max_iters(in, S);
+        counts.push_back(it);
+        total_inner += it;
+        launched += r.budget[j];
+        outer_steps += 1;
+        for (int q = 0; q < S; ++q) per_sample[q] += in[q].iters;
+    }
+    const PcgState* last = log + (r.rounds - 1) * n;
+    for (int q = 0; q < S; ++q)
+        if (!last[S + q].done || last[S + q].status != RAFEM_OK) return false;
+    m->mixed_iters = per_sample;
+    m->mixed_fell.assign(S, 0);
+    fill_info(info, last + S, nullptr, S, launched, outer_steps);
+    if (info) info->iters = total_inner;
+    if (hints) *hints = counts;
+    *h_out = last;
+    return true;
+}
+
+namespace {
+
+// On-disk cache of the tuned slab shapes: one line per (device, layout) key,
+// "<key> <slabs per block FP64> <slabs per block FP32>", in the file named by
+// RAFEM_TUNE_CACHE, else $HOME/.cache/rafem/spmv_tune.txt.  Unreadable or unwritable files
+// are ignored (the shapes are then timed every time).
+std::string tune_cache_path() {
+    if (const char* p = std::getenv("RAFEM_TUNE_CACHE")) return p;
+    if (const char* h = std::getenv("HOME")) return std::string(h) + "/.cache/rafem/spmv_tune.txt";
+    return "";
+}
+
+std::string tune_key(rafem_mesh m) {
+    hipDeviceProp_t prop{};
+    std::string dev = "unknown";
+    if (hipGetDeviceProperties(&prop, m->device) == hipSuccess) dev = prop.gcnArchName;
+    for (char& c : dev)
+        if (c == ' ') c = '_';
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s/n%lld/nnz%lld/slots%lld/slabs%d/shared%lld/S%d/i16%d",
+                  dev.c_str(), (long long)m->n, (long long)m->nnz, (long long)m->sell_nnz,
+                  m->nslabs, (long long)m->shared_slabs, m->S, m->sdel ? 1 : 0);
+    return buf;
+}
+
+bool tune_lookup(const std::string& key, int& spb64, int& spb32) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return false;
+    std::FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return false;
+    char k[512];
+    int a = 0, b = 0;
+    bool found = false;
+    while (std::fscanf(f, "%511s %d %d", k, &a, &b) == 3)
+        if (key == k && (a == 8 || a == 16) && (b == 8 || b == 16)) {  // last entry wins
+            spb64 = a;
+            spb32 = b;
+            found = true;
+        }
+    std::fclose(f);
+    return found;
+}
+
+void tune_store(const std::string& key, int spb64, int spb32) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) {
+        // create the cache's folder and its parent if missing (errors ignored)
+        const std::string dir = path.substr(0, slash);
+        const size_t up = dir.rfind('/');
+        if (up != std::string::npos && up > 0) (void)mkdir(dir.substr(0, up).c_str(), 0755);
+        (void)mkdir(dir.c_str(), 0755);
+    }
+    std::FILE* f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d\n", key.c_str(), spb64, spb32);
+    std::fclose(f);
+}
+
+}  // namespace
+
 void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
     // Slab shapes of the SELL kernels: 2 or 4 slabs per wavefront (one or two groups of
     // partial sums per workgroup, so results do not depend on the choice), chosen by timing
     // the PCG SpMV (with its fused dot product) on this mesh's matrix, for FP64 and FP32
-    // values.  Both candidates keep workgroups inside one sample (kRowAlign is 16 slabs).
+    // values, or taken from the on-disk cache of earlier timings of the same layout on the
+    // same kind of device.  Both candidates keep workgroups inside one sample (kRowAlign is
+    // 16 slabs).
     if (!A.sell) return;
+    const std::string key = tune_key(m);
+    int c64 = 0, c32 = 0;
+    if (tune_lookup(key, c64, c32)) {
+        m->spmv.slabs_per_block = c64;
+        m->spmv32.slabs_per_block = c32;
+        m->tuned = true;
+        m->tuned_from_cache = true;
+        return;
+    }
     const int S = m->S;
-    Samples smp{S, m->row_off};
+    Samples smp{S, m->row_off, m->row_tab};
     PcgState* chk = m->st + 2 * S;
     hipEvent_t e0, e1;
     RAFEM_HIP(hipEventCreate(&e0));
@@ -454,6 +671,7 @@ void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
     (void)hipEventDestroy(e1);
     RAFEM_HIP(hipGetLastError());
     m->tuned = true;
+    tune_store(key, m->spmv.slabs_per_block, m->spmv32.slabs_per_block);
 }
 
 }  // namespace rafem

@@ -38,4 +38,29 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
 // Pick the SELL slab shape of the FP64 and FP32 SpMV by timing them on A (sets m->tuned).
 void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s);
 
+// Device-driven form of a solve: everything is enqueued at once, the iteration budget of
+// each (inner) solve taken from `hints` (the previous solve of the same kind), and the
+// solver states are copied into log slots from m->dd_used on after each of them; no host
+// synchronisation.  A mixed solve enqueues one refinement more than the hints hold, which
+// only checks the last one when the count was right.  The record says where the logs are.
+struct DdRecord {
+    int slot0 = 0;
+    int rounds = 0;          // logged slots (1 for FP64)
+    int mixed = 0;
+    std::vector<int> budget; // iterations enqueued per slot
+};
+// Whether device-driven enqueueing is possible for this solve (hints present, fit the log).
+bool dd_ready(rafem_mesh m, const SolveOpts& o, const std::vector<int>* hints);
+DdRecord dd_enqueue(rafem_mesh m, const Mat& A, const Samples& smp, const double* dinv,
+                    const float* dinv32, const double* b, double* x, const SolveOpts& o,
+                    const std::vector<int>& hints, hipStream_t s);
+// After the caller's poll of the log slots into m->dd_log_host: true if the enqueued solve
+// did exactly what the host-driven solve does (every inner solve finished within its budget,
+// every sample converged, no refinement the host would have judged stagnant); then fills
+// info, the per-sample counters and hints.  h_out receives the log slot holding the final
+// states (main FP64 states at [0, S) and true residuals at [2S, 3S); mixed: refinement
+// states at [S, 2S)).
+bool dd_finish(rafem_mesh m, const DdRecord& r, const SolveOpts& o, rafem_solve_info* info,
+               std::vector<int>* hints, const PcgState** h_out);
+
 }  // namespace rafem

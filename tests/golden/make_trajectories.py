@@ -7,6 +7,7 @@ for the 101^3 workloads), each step warm-started from the previous state.
 
     python tests/golden/make_trajectories.py c1     # 101^3 hex, 100 coupled steps (~1 h, 1 core)
     python tests/golden/make_trajectories.py c4     # 4 ensemble samples, 3 steps each
+    python tests/golden/make_trajectories.py c2     # 161^3 Kuhn tets, 20 coupled steps (~2 h, ~20 GB)
 
 Files (NumPy .npz, no pickled objects):
 
@@ -14,6 +15,9 @@ Files (NumPy .npz, no pickled objects):
   1 s: T and V at 2,000 free nodes (drawn with ``default_rng(2026)``), at steps 1, 10, 20,
   ..., 100, with the 2-norms of the full fields (T, V, T - 37) at those steps and the
   oracle's PCG iteration counts of every step.
+* ``c2_tet161_trajectory.npz`` -- the jittered 161^3 Kuhn-tet workload (seed 0) over 20
+  steps: T and V at 2,000 free nodes (``default_rng(2029)``) after every step, with the
+  full-field norms and the iteration counts.
 * ``c4_ensemble_steps.npz`` -- of the 64-sample ensemble (seed 0), the smallest and the
   largest sample and two more drawn with ``default_rng(2027)``: T and V at 2,000 free nodes
   of each (``default_rng(2028 + q)``) after steps 1, 2 and 3, with the full-field norms.
@@ -37,6 +41,7 @@ from oracle.rafem import Model  # noqa: E402
 TOL = 1e-13
 C1_FILE = os.path.join(HERE, "c1_hex101_trajectory.npz")
 C4_FILE = os.path.join(HERE, "c4_ensemble_steps.npz")
+C2_FILE = os.path.join(HERE, "c2_tet161_trajectory.npz")
 C1_STEPS = [1] + list(range(10, 101, 10))
 N_SAMPLED = 2000
 
@@ -98,7 +103,29 @@ def make_c4(path=C4_FILE):
     print(f"wrote {path}", flush=True)
 
 
+def make_c2(path=C2_FILE):
+    p = ri.config2(steps=20)
+    nodes = free_sample(p, 2029)
+    m = Model(p)
+    bio = m.bioheat_system()
+    T, V = p.initial_T(), p.initial_V()
+    Ts, Vs, nrm, iters = [], [], [], []
+    t0 = time.time()
+    for k in range(1, 21):
+        T, V, info = m.step(T, V, TOL, bioheat=bio)
+        iters.append((info.V.iters, info.T.iters))
+        Ts.append(T[nodes])
+        Vs.append(V[nodes])
+        nrm.append(norms(T, V))
+        print(f"c2 step {k}: V {info.V.iters} T {info.T.iters} iterations, "
+              f"{time.time() - t0:.0f} s", flush=True)
+    np.savez_compressed(path, nodes=nodes, steps=np.arange(1, 21), T=np.array(Ts),
+                        V=np.array(Vs), norms=np.array(nrm), iters=np.array(iters),
+                        tol=np.array(TOL))
+    print(f"wrote {path}", flush=True)
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["c1", "c4"]
     for w in which:
-        {"c1": make_c1, "c4": make_c4}[w]()
+        {"c1": make_c1, "c4": make_c4, "c2": make_c2}[w]()

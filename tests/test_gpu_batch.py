@@ -147,3 +147,67 @@ def test_batch_reverse_sweep_matches_single_adjoints(torch_cuda, kind):
         print(f"[batch adjoint {kind} sample {q}] grad_k {ek:.2e} grad_w {ew:.2e}", flush=True)
         assert ek <= 1e-12 and ew <= 1e-12
         dp.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_device_driven_steps_equal_host_driven_steps(torch_cuda, precision):
+    """Device-driven solves (each solve of a step enqueued whole from the previous solves'
+    counts, one poll per solve; an option of any handle) give the host-driven steps'
+    results bit for bit, on a batch and on a single mesh, with the predictor's starting
+    points; budgets cut to 0.3 of the counts force solves to be redone host-driven, with
+    the same results."""
+    from paper_2409_13036_amd.sim import BatchProblem, DeviceProblem
+    tol, steps = 1e-13, 6
+    probs = _samples("hex") + [ri.make_problem("hex", 17, 47, k_scale=0.9, sigma_scale=1.2,
+                                               perf_scale=1.1, per_element_eps=False, name="s3")]
+
+    def run_batch(mode, scale=0.0):
+        bp = BatchProblem(probs)
+        bp.extrapolate = True
+        bp.mesh.set_device_driven(mode, scale)
+        out = []
+        for _ in range(steps):
+            info = bp.step(tol, precision)
+            assert info["V"]["status"] == 0 and info["T"]["status"] == 0
+            out.append((to_host(bp.T), to_host(bp.V),
+                        [bp.mesh.sample_info(q) for q in range(len(probs))], info))
+        st = bp.mesh.stats()
+        bp.close()
+        return out, st
+
+    host, st_h = run_batch(False)
+    dev, st_d = run_batch(True)
+    cut, st_c = run_batch(True, 0.3)
+    print(f"[device-driven {precision}] solves accepted {st_d.device_driven_solves}, redone "
+          f"{st_d.device_driven_redone}; with budgets x0.3: accepted "
+          f"{st_c.device_driven_solves}, redone {st_c.device_driven_redone}", flush=True)
+    assert st_h.device_driven_solves == 0
+    # both solves of every step after the first (which has no counts yet) run device-driven
+    assert st_d.device_driven_solves + st_d.device_driven_redone == 2 * (steps - 1)
+    assert st_d.device_driven_solves >= steps - 1
+    assert st_c.device_driven_redone >= 1
+    for k, (a, b, c) in enumerate(zip(host, dev, cut)):
+        for other in (b, c):
+            assert np.array_equal(a[0], other[0]) and np.array_equal(a[1], other[1]), k
+            for ia, ib in zip(a[2], other[2]):
+                for f in ("V", "T"):
+                    assert ia[f]["iters"] == ib[f]["iters"] and ia[f]["outer"] == ib[f]["outer"]
+                    assert ia[f]["status"] == ib[f]["status"]
+            assert a[3]["V"]["iters"] == other[3]["V"]["iters"]
+            assert a[3]["T"]["iters"] == other[3]["T"]["iters"]
+    # a single mesh, device-driven on request
+    p = probs[1]
+    runs = []
+    for mode in (False, True):
+        dp = DeviceProblem(p)
+        dp.extrapolate = True
+        dp.mesh.set_device_driven(mode)
+        states = []
+        for _ in range(steps):
+            dp.step(tol, precision)
+            states.append((to_host(dp.T), to_host(dp.V)))
+        runs.append((states, dp.mesh.stats()))
+        dp.close()
+    assert runs[1][1].device_driven_solves >= steps - 1
+    for (Ta, Va), (Tb, Vb) in zip(runs[0][0], runs[1][0]):
+        assert np.array_equal(Ta, Tb) and np.array_equal(Va, Vb)

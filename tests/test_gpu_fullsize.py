@@ -8,7 +8,12 @@
   solver's tolerance.
 - the 64-sample ensemble (16.6M rows): one step of the whole batch; its smallest and its
   largest sample against the oracle's step of that sample.
+- 101^3 hex over 100 steps in the benchmark's configuration: both paths against the
+  oracle's stored 100-step trajectory (tests/golden/make_trajectories.py), the mixed state
+  against the FP64 state at every step, and the 100th step against the oracle's equations.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -20,6 +25,7 @@ from gpu_helpers import rel_err, to_host
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-13
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -211,8 +217,11 @@ def test_hex101_monolithic_solve_and_newton_step_satisfy_sampled_equations(torch
 
 def test_hex101_hundred_steps_mixed_tracks_fp64_and_satisfies_oracle_equations(torch_cuda):
     """The benchmarked 101^3 workload over 100 coupled steps (extrapolated starting points):
-    the mixed state within 1e-8 of the FP64 state at every step, and both paths' 100th step
-    satisfying the oracle's equations of 2,000 sampled rows (given their 99th state)."""
+    each path against the oracle's own 100-step trajectory (stored by
+    tests/golden/make_trajectories.py: 2,000 free nodes at steps 1, 10, ..., 100, sampled
+    relative error <= 1e-8), the mixed state within 1e-8 of the FP64 state at every step,
+    and both paths' 100th step satisfying the oracle's equations of 2,000 sampled rows
+    (given their 99th state)."""
     from paper_2409_13036_amd.sim import DeviceProblem
     p = ri.config1(steps=100)
     runs = {}
@@ -226,6 +235,19 @@ def test_hex101_hundred_steps_mixed_tracks_fp64_and_satisfies_oracle_equations(t
         dp.close()
         runs[precision] = states
         say(f"{precision}: 100 steps done")
+    gold = np.load(os.path.join(GOLDEN, "c1_hex101_trajectory.npz"))
+    nodes = gold["nodes"]
+    for precision, states in runs.items():
+        worst_o = 0.0
+        for j, k in enumerate(gold["steps"]):
+            Tg, Vg = states[k - 1]
+            eT = rel_err(Tg[nodes], gold["T"][j])
+            eV = rel_err(Vg[nodes], gold["V"][j])
+            e37 = rel_err(Tg[nodes] - 37.0, gold["T"][j] - 37.0)
+            worst_o = max(worst_o, eT, eV)
+            say(f"{precision} step {k} vs stored oracle: T {eT:.2e} V {eV:.2e} (T-37 {e37:.2e})")
+            assert eT <= 1e-8 and eV <= 1e-8
+        say(f"{precision}: worst sampled error against the oracle trajectory {worst_o:.2e}")
     worst = 0.0
     for (T6, V6), (Tm, Vm) in zip(runs["fp64"], runs["mixed"]):
         worst = max(worst, rel_err(Tm, T6), rel_err(Vm, V6))

@@ -1,0 +1,69 @@
+"""Autotuning with on-disk caches: the library's SpMV slab shape (cached per layout and
+device in RAFEM_TUNE_CACHE) and the mixed refinement's inner tolerance and restart mode
+(paper_2409_13036_amd.tune, cached in a JSON file).  A cached choice is reused without
+timing, and a tuned shape never changes a result."""
+import os
+
+import numpy as np
+import pytest
+
+import rafem_inputs as ri
+from gpu_helpers import to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def test_spmv_shape_cache_is_written_then_reused(torch_cuda, tmp_path, monkeypatch):
+    from paper_2409_13036_amd.sim import DeviceProblem
+    cache = tmp_path / "spmv_tune.txt"
+    monkeypatch.setenv("RAFEM_TUNE_CACHE", str(cache))
+    p = ri.make_problem("hex", 21, 3)
+    out = []
+    for k in range(2):
+        dp = DeviceProblem(p)
+        dp.step(1e-12, "mixed")
+        st = dp.mesh.stats()
+        out.append((st.tuned_from_cache, st.slabs_per_block, st.slabs_per_block32,
+                    to_host(dp.T), to_host(dp.V)))
+        dp.close()
+    lines = cache.read_text().split("\n")
+    print(f"[tune] cache: {lines[0]}", flush=True)
+    assert out[0][0] == 0 and out[1][0] == 1       # timed first, then read from the cache
+    assert out[0][1:3] == out[1][1:3]
+    assert len([l for l in lines if l.strip()]) == 1
+    assert np.array_equal(out[0][3], out[1][3]) and np.array_equal(out[0][4], out[1][4])
+
+
+def test_mixed_tuner_picks_a_candidate_and_caches_it(torch_cuda, tmp_path):
+    from paper_2409_13036_amd.sim import DeviceProblem
+    from paper_2409_13036_amd.tune import tune_mixed
+    path = str(tmp_path / "mixed.json")
+    p = ri.make_problem("hex", 21, 4, steps=6)
+    dp = DeviceProblem(p)
+    dp.extrapolate = True
+    cands = ((1e-4, 0), (1e-3, 0), (1e-4, 1))
+    first = tune_mixed(dp, warmup=1, steps=2, candidates=cands, path=path)
+    again = tune_mixed(dp, warmup=1, steps=2, candidates=cands, path=path)
+    print(f"[tune] mixed: {first}", flush=True)
+    assert not first["cached"] and again["cached"]
+    assert (first["inner_tol"], first["restart_inner"]) in cands
+    assert (again["inner_tol"], again["restart_inner"]) == (first["inner_tol"], first["restart_inner"])
+    assert len(first["timings"]) == len(cands)
+    # the chosen setting solves the step to the FP64 path's answer
+    dp.reset()
+    dp.step(1e-13, "mixed", inner_tol=first["inner_tol"], restart_inner=first["restart_inner"])
+    Tm = to_host(dp.T)
+    dp.reset()
+    dp.step(1e-13, "fp64")
+    T6 = to_host(dp.T)
+    dp.close()
+    assert np.linalg.norm(Tm - T6) <= 1e-8 * np.linalg.norm(T6)
+    assert os.path.exists(path)
