@@ -460,9 +460,10 @@ def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int, workload: s
     """HBM bytes per launch of the PCG SpMV kernels from two rocprofv3 --pmc runs of
     `bench.py --copy-probe-mib M ...` on one workload (FETCH_SIZE, then WRITE_SIZE; KiB per
     dispatch).  Each counter is scaled by what it reads for the probe's plain copy of M MiB
-    (the copy dispatches with the largest values), and a kernel's figure is the mean over
-    its launches that did work (value >= 10% of its largest; launches enqueued past
-    convergence exit at once).  Entries are keyed by (kernel, workload, nnz) and merged
+    (the first three copy dispatches of the run: the probe runs before anything else), and a
+    kernel's figure is the mean over its full launches (value >= 90% of its largest:
+    launches enqueued past convergence exit at once, and in an ensemble a launch skips the
+    samples that have converged).  Entries are keyed by (kernel, workload, nnz) and merged
     into profiles/traffic.json (entries of other workloads are kept); prints a summary."""
     import statistics
     path = out_path or os.path.join(ROOT, "profiles", "traffic.json")
@@ -476,11 +477,10 @@ def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int, workload: s
     factors = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _counter_rows(d, counter)
-        copies = [v for _, n, v in rows if "copy" in n.lower()]
-        if not copies:
-            raise SystemExit(f"{counter}: no copy dispatch found")
-        top = max(copies)
-        probe = [v for v in copies if v >= 0.5 * top]
+        copies = [v for i, n, v in sorted(rows, key=lambda t: int(t[0])) if "copy" in n.lower()]
+        if len(copies) < 3:
+            raise SystemExit(f"{counter}: the copy probe's three dispatches were not found")
+        probe = copies[:3]
         factor = statistics.mean(probe) / (probe_mib * 1024.0)
         factors[counter] = factor
         lines.append(f"{counter}: copy probe {len(probe)} dispatches, mean "
@@ -492,7 +492,7 @@ def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int, workload: s
             if short.startswith("k_sell") or short.startswith("k_csr"):
                 by.setdefault(short, []).append(v)
         for name, vals in sorted(by.items()):
-            busy = [v for v in vals if v >= 0.1 * max(vals)]
+            busy = [v for v in vals if v >= 0.9 * max(vals)]
             kib = statistics.mean(busy)
             e = out.setdefault(traffic_key(name, workload, nnz),
                                {"kernel": name, "workload": workload, "nnz": nnz,

@@ -260,8 +260,10 @@ void dd_alloc(rafem_mesh m) {
     }
 }
 
-Samples step_samples(rafem_mesh m) { return Samples{m->S, m->row_off, m->row_tab}; }
-Samples whole_mesh(rafem_mesh m) { return Samples{1, m->row_off_one}; }
+Samples step_samples(rafem_mesh m) {
+    return Samples{m->S, m->row_off, m->row_tab, m->max_sample_rows};
+}
+Samples whole_mesh(rafem_mesh m) { return Samples{1, m->row_off_one, nullptr, (int)m->n}; }
 
 // Iteration counts a device-driven solve of this kind budgets for: per (inner) solve the
 // larger of its counts in the last two solves of the kind.
@@ -460,6 +462,10 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             m->partials = dalloc<double>(m, 3 * (N / 64 + 64));
             m->part_pq = dalloc<double>(m, N / 64 + 64);
             m->part_rz = dalloc<double>(m, 2 * (N / 64 + 64));
+            m->part_sum = dalloc<double>(m, 3 * (size_t)S_);
+            for (int q = 0; q < S_; ++q)
+                m->max_sample_rows = std::max<int>(m->max_sample_rows,
+                                                   (int)(node_off[q + 1] - node_off[q]));
             m->st = dalloc<PcgState>(m, 3 * (size_t)S_);
             m->itb = dalloc<int32_t>(m, 2);
             m->row_off = dalloc<int32_t>(m, (size_t)S_ + 1);

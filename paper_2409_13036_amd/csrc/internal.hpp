@@ -140,6 +140,7 @@ struct Samples {
     int S;
     const int32_t* row_off;
     const int32_t* tab = nullptr;  // [rows / kRowAlign] sample of each aligned block, or NULL
+    int max_rows = 0;              // rows of the largest sample (0: unknown)
 };
 
 // Grid of a row kernel: blocks and rows per block (to locate a sample's partial slots).
@@ -178,19 +179,22 @@ GridInfo launch_spmv_dot64(const Mat& A, const SpmvConfig& c, const double* p, d
 GridInfo launch_spmv_dot32(const Mat& A, const SpmvConfig& c, const float* p, float* q,
                            double* pq_part, PcgState* st, const Samples& smp, hipStream_t s,
                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// sums (optional, >= 3 S doubles): where a sample's totals are pre-summed by one block per
+// sample when its partial slots are many (large meshes), so that the vector kernels' blocks
+// do not each read them all; the totals are bitwise the same either way.
 int launch_update64(int n, double* x, double* r, const double* p, const double* q,
                     const double* dinv, const double* pq_part, const GridInfo& gpq,
                     double* rz_part, const int* itb, int j, PcgState* st, const Samples& smp,
-                    hipStream_t s);
+                    double* sums, hipStream_t s);
 int launch_update32(int n, float* x, float* r, const float* p, const float* q, const float* dinv,
                     const double* pq_part, const GridInfo& gpq, double* rz_part, const int* itb,
-                    int j, PcgState* st, const Samples& smp, hipStream_t s);
+                    int j, PcgState* st, const Samples& smp, double* sums, hipStream_t s);
 void launch_pupdate64(int n, double* p, const double* r, const double* dinv,
                       const double* rz_part, int nb_rz, const int* itb, int j, PcgState* st,
-                      const Samples& smp, hipStream_t s);
+                      const Samples& smp, double* sums, hipStream_t s);
 void launch_pupdate32(int n, float* p, const float* r, const float* dinv, const double* rz_part,
                       int nb_rz, const int* itb, int j, PcgState* st, const Samples& smp,
-                      hipStream_t s);
+                      double* sums, hipStream_t s);
 // Plain y = A x (no state).
 void launch_spmv64(const Mat& A, const SpmvConfig& c, const double* x, double* y, hipStream_t s);
 void launch_spmv32(const Mat& A, const SpmvConfig& c, const float* x, float* y, hipStream_t s);
@@ -521,6 +525,8 @@ struct rafem_mesh_s {
     double* partials = nullptr;   // once-per-solve reductions
     double* part_pq = nullptr;    // per-iteration partials of p.Ap
     double* part_rz = nullptr;    // per-iteration partials of r.z and r.r
+    double* part_sum = nullptr;   // [3 S] pre-summed totals of the two (large meshes)
+    int max_sample_rows = 0;      // rows of the largest sample
     rafem::PcgState* st = nullptr;      // device [3 S]: main/inner, outer, check per sample
     rafem::PcgState* st_host = nullptr; // pinned host [3 S]
     int32_t* itb = nullptr;             // device iteration counters [2]: FP64 loop, inner loop

@@ -476,7 +476,8 @@ __global__ __launch_bounds__(WG) void k_update(int n, T* __restrict__ x, T* __re
                                                const T* __restrict__ q,
                                                const T* __restrict__ dinv,
                                                const double* __restrict__ pq_part, int nb_pq,
-                                               int rpb_pq, double* __restrict__ rz_part,
+                                               int rpb_pq, const double* __restrict__ pq_tot,
+                                               double* __restrict__ rz_part,
                                                const int* __restrict__ itb, int j,
                                                PcgState* st, Samples smp) {
     const int nb = gridDim.x;
@@ -502,13 +503,18 @@ __global__ __launch_bounds__(WG) void k_update(int n, T* __restrict__ x, T* __re
             dv[u] = dinv[i];
         }
     }
-    int b0, b1;
-    sample_blocks(smp, s, rpb_pq, b0, b1);
+    // the sample's total of p.Ap: summed by k_sum_partials (many slots), or here
+    int b0 = 0, b1 = 0;
     RangeBatch<1> first;
-    range_prefetch<1>(pq_part, nb_pq, b0, b1, first);
-    if (S.done) return;
     double pq[1];
-    range_totals<1>(pq_part, nb_pq, b0, b1, pq, &first);
+    if (pq_tot) {
+        pq[0] = pq_tot[s];
+    } else {
+        sample_blocks(smp, s, rpb_pq, b0, b1);
+        range_prefetch<1>(pq_part, nb_pq, b0, b1, first);
+    }
+    if (S.done) return;
+    if (!pq_tot) range_totals<1>(pq_part, nb_pq, b0, b1, pq, &first);
     const bool writer = threadIdx.x == 0 && blk == smp.row_off[s] / kVecRowsPerBlock;
     if (!(pq[0] > 0.0) || !finite(pq[0])) {
         if (writer) {
@@ -544,6 +550,7 @@ __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
                                                 const T* __restrict__ r,
                                                 const T* __restrict__ dinv,
                                                 const double* __restrict__ rz_part, int nb_rz,
+                                                const double* __restrict__ rz_tot,
                                                 const int* __restrict__ itb, int j, PcgState* st,
                                                 Samples smp) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -566,10 +573,15 @@ __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
     int b0, b1;
     sample_blocks(smp, s, kVecRowsPerBlock, b0, b1);
     RangeBatch<2> first;
-    range_prefetch<2>(rz_part, nb_rz, b0, b1, first);
-    if (S.done) return;
     double tot[2];
-    range_totals<2>(rz_part, nb_rz, b0, b1, tot, &first);
+    if (rz_tot) {
+        tot[0] = rz_tot[2 * s];
+        tot[1] = rz_tot[2 * s + 1];
+    } else {
+        range_prefetch<2>(rz_part, nb_rz, b0, b1, first);
+    }
+    if (S.done) return;
+    if (!rz_tot) range_totals<2>(rz_part, nb_rz, b0, b1, tot, &first);
     const double rz = tot[0], rr = tot[1];
     const int iters = it + 1;
     int status = -1;
@@ -598,6 +610,24 @@ __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
         S.rr = rr;
         S.beta = beta;
         S.iters = iters;
+    }
+}
+
+// One block per sample: the sample's totals of K partial arrays (range_totals, the same
+// slots in the same order as the vector kernels would add them, so the totals are bitwise
+// theirs), for a next kernel whose every block would otherwise read all the slots.
+template <int K>
+__global__ __launch_bounds__(WG) void k_sum_partials(const double* __restrict__ partials, int nb,
+                                                     int rpb, Samples smp,
+                                                     double* __restrict__ out) {
+    const int s = blockIdx.x;
+    int b0, b1;
+    sample_blocks(smp, s, rpb, b0, b1);
+    double tot[K];
+    range_totals<K>(partials, nb, b0, b1, tot);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[K * s + k] = tot[k];
     }
 }
 
@@ -861,37 +891,58 @@ void launch_residual64(const Mat& A, const SpmvConfig& c, const double* b, const
                        g.rpb, st, outer_mode, smp);
 }
 
+// The sample totals a vector kernel needs, pre-summed by one block per sample when a
+// sample has more than kDirectSlots partial slots (else every block adds them itself: one
+// kernel fewer).  Returns the totals' array, or NULL for the direct form.
+constexpr int kDirectSlots = 2500;
+
+template <int K>
+const double* presum(const double* partials, int nb, int rpb, const Samples& smp, double* sums,
+                     hipStream_t s) {
+    if (!sums || smp.max_rows <= 0 || (smp.max_rows + rpb - 1) / rpb <= kDirectSlots)
+        return nullptr;
+    hipLaunchKernelGGL(k_sum_partials<K>, dim3(smp.S), dim3(WG), 0, s, partials, nb, rpb, smp,
+                       sums);
+    return sums;
+}
+
 int launch_update64(int n, double* x, double* r, const double* p, const double* q,
                     const double* dinv, const double* pq_part, const GridInfo& gpq,
                     double* rz_part, const int* itb, int j, PcgState* st, const Samples& smp,
-                    hipStream_t s) {
+                    double* sums, hipStream_t s) {
     const int nb = vec_blocks(n);
+    const double* tot = presum<1>(pq_part, gpq.nb, gpq.rpb, smp, sums, s);
     hipLaunchKernelGGL(k_update<double>, dim3(nb), dim3(WG), 0, s, n, x, r, p, q, dinv, pq_part,
-                       gpq.nb, gpq.rpb, rz_part, itb, j, st, smp);
+                       gpq.nb, gpq.rpb, tot, rz_part, itb, j, st, smp);
     return nb;
 }
 
 int launch_update32(int n, float* x, float* r, const float* p, const float* q, const float* dinv,
                     const double* pq_part, const GridInfo& gpq, double* rz_part, const int* itb,
-                    int j, PcgState* st, const Samples& smp, hipStream_t s) {
+                    int j, PcgState* st, const Samples& smp, double* sums, hipStream_t s) {
     const int nb = vec_blocks(n);
+    const double* tot = presum<1>(pq_part, gpq.nb, gpq.rpb, smp, sums, s);
     hipLaunchKernelGGL(k_update<float>, dim3(nb), dim3(WG), 0, s, n, x, r, p, q, dinv, pq_part,
-                       gpq.nb, gpq.rpb, rz_part, itb, j, st, smp);
+                       gpq.nb, gpq.rpb, tot, rz_part, itb, j, st, smp);
     return nb;
 }
 
 void launch_pupdate64(int n, double* p, const double* r, const double* dinv,
                       const double* rz_part, int nb_rz, const int* itb, int j, PcgState* st,
-                      const Samples& smp, hipStream_t s) {
+                      const Samples& smp, double* sums, hipStream_t s) {
+    const double* tot =
+        presum<2>(rz_part, nb_rz, kVecRowsPerBlock, smp, sums ? sums + smp.S : nullptr, s);
     hipLaunchKernelGGL(k_pupdate<double>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv,
-                       rz_part, nb_rz, itb, j, st, smp);
+                       rz_part, nb_rz, tot, itb, j, st, smp);
 }
 
 void launch_pupdate32(int n, float* p, const float* r, const float* dinv, const double* rz_part,
                       int nb_rz, const int* itb, int j, PcgState* st, const Samples& smp,
-                      hipStream_t s) {
+                      double* sums, hipStream_t s) {
+    const double* tot =
+        presum<2>(rz_part, nb_rz, kVecRowsPerBlock, smp, sums ? sums + smp.S : nullptr, s);
     hipLaunchKernelGGL(k_pupdate<float>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv,
-                       rz_part, nb_rz, itb, j, st, smp);
+                       rz_part, nb_rz, tot, itb, j, st, smp);
 }
 
 void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,

@@ -132,8 +132,8 @@ struct Iter64 {
         const GridInfo g1 = launch_spmv_dot64(*A, *cfg, m->p, m->q, m->part_pq, st, smp, s,
                                               t ? t->start(j) : nullptr, t ? t->stop(j) : nullptr);
         const int nb2 = launch_update64(n, x, m->r, m->p, m->q, dinv, m->part_pq, g1, m->part_rz,
-                                        itb, j, st, smp, s);
-        launch_pupdate64(n, m->p, m->r, dinv, m->part_rz, nb2, itb, j, st, smp, s);
+                                        itb, j, st, smp, m->part_sum, s);
+        launch_pupdate64(n, m->p, m->r, dinv, m->part_rz, nb2, itb, j, st, smp, m->part_sum, s);
     }
 };
 
@@ -151,8 +151,9 @@ struct Iter32 {
         const GridInfo g1 = launch_spmv_dot32(*A, *cfg, m->p32, m->q32, m->part_pq, st, smp, s,
                                               t ? t->start(j) : nullptr, t ? t->stop(j) : nullptr);
         const int nb2 = launch_update32(n, m->d32, m->r32, m->p32, m->q32, dinv32, m->part_pq, g1,
-                                        m->part_rz, itb, j, st, smp, s);
-        launch_pupdate32(n, m->p32, m->r32, dinv32, m->part_rz, nb2, itb, j, st, smp, s);
+                                        m->part_rz, itb, j, st, smp, m->part_sum, s);
+        launch_pupdate32(n, m->p32, m->r32, dinv32, m->part_rz, nb2, itb, j, st, smp, m->part_sum,
+                         s);
     }
 };
 
