@@ -807,6 +807,7 @@ def liver_leg(args) -> dict:
         N, nnz = dp.mesh.n_nodes, dp.mesh.nnz
         row = {"n_nodes": N, "n_elems": dp.mesh.n_elems, "nnz": nnz, "colours": st.n_colours,
                "slabs": int(st.slabs), "int16_columns": int(st.int16_columns),
+               "int32_column_slabs": int(st.int32_column_slabs),
                "mixed_inner_tol": inner_tol}
         for precision in ("fp64", "mixed"):
             kw = {"inner_tol": inner_tol} if precision == "mixed" else {}

@@ -128,7 +128,7 @@ typedef struct {
     int32_t n_samples;
     int32_t slabs_per_block;     /* SELL shape of the FP64 SpMV (autotuned at the first step) */
     int32_t slabs_per_block32;   /* SELL shape of the FP32 SpMV */
-    int32_t int16_columns;       /* 1 if the SpMV reads 16-bit column offsets */
+    int32_t int16_columns;       /* 1 if the SpMV reads 16-bit column offsets (on some slabs) */
     int64_t slabs;               /* 64-row slabs of the SpMV layout */
     int64_t shared_offset_slabs; /* slabs whose rows share one column-offset list */
     int32_t row_assembly;        /* 1: step matrices and right-hand side assembled row by row
@@ -143,6 +143,9 @@ typedef struct {
                                     (RAFEM_TUNE_CACHE, else ~/.cache/rafem/spmv_tune.txt) */
     int64_t device_driven_solves;/* solves of rafem_step completed device-driven */
     int64_t device_driven_redone;/* device-driven solves redone host-driven (a budget fell short) */
+    int64_t int32_column_slabs;  /* slabs without a shared offset list whose columns lie beyond
+                                    16-bit reach of their rows: they read 32-bit columns, the
+                                    other such slabs 16-bit offsets */
 } rafem_mesh_stats;
 
 /* Build a mesh on the current device.

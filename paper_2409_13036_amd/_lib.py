@@ -59,7 +59,8 @@ class MeshStats(C.Structure):
                 ("row_assembly", C.c_int32), ("max_row_entries", C.c_int32),
                 ("value_slots", C.c_int64), ("index_bytes", C.c_int64),
                 ("device_driven", C.c_int32), ("tuned_from_cache", C.c_int32),
-                ("device_driven_solves", C.c_int64), ("device_driven_redone", C.c_int64)]
+                ("device_driven_solves", C.c_int64), ("device_driven_redone", C.c_int64),
+                ("int32_column_slabs", C.c_int64)]
 
 
 class SolveOpts(C.Structure):

@@ -406,14 +406,17 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             if (!SL.sdel.empty()) m->sdel = dalloc<int16_t>(m, SNNZ);
             m->sofs = dalloc<int32_t>(m, (size_t)m->nslabs);
             m->soff = dalloc<int32_t>(m, std::max<size_t>(1, SL.soff.size()));
-            for (int32_t o : SL.sofs) m->shared_slabs += o >= 0 ? 1 : 0;
+            for (int32_t o : SL.sofs) {
+                m->shared_slabs += o >= 0 ? 1 : 0;
+                m->int32_slabs += (o == -2 || (o == -1 && SL.sdel.empty())) ? 1 : 0;
+            }
             // column data one product reads: per slab its pointers, then the shared offset
             // list (one entry per slot of a row) or a per-slot column offset
             m->index_bytes = 8 * (int64_t)m->nslabs;
             for (int64_t b = 0; b < m->nslabs; ++b) {
                 const int64_t slots = SL.sptr[b + 1] - SL.sptr[b];
                 if (SL.sofs[b] >= 0) m->index_bytes += 4 * (slots / 64);
-                else m->index_bytes += (SL.sdel.empty() ? 4 : 2) * slots;
+                else m->index_bytes += (SL.sofs[b] == -1 && !SL.sdel.empty() ? 2 : 4) * slots;
             }
             m->conn = dalloc<int32_t>(m, E * npe);
             m->xyz = dalloc<double>(m, 3 * N);
@@ -804,6 +807,7 @@ rafem_status rafem_mesh_get_stats(rafem_mesh m, rafem_mesh_stats* out) {
         out->tuned_from_cache = m->tuned_from_cache ? 1 : 0;
         out->device_driven_solves = m->dd_solves;
         out->device_driven_redone = m->dd_redone;
+        out->int32_column_slabs = m->int32_slabs;
         return RAFEM_OK;
     });
 }

@@ -251,7 +251,7 @@ __global__ __launch_bounds__(WG) void k_bsell(BsellT<V4, X2> a) {
         const int r = sl * WAVE + lane;
         X2 y;
         if (so >= 0) y = bsell_row<0>(a, base, width, so, r, lane);
-        else if (a.sdel) y = bsell_row<1>(a, base, width, so, r, lane);
+        else if (a.sdel && so == -1) y = bsell_row<1>(a, base, width, so, r, lane);
         else y = bsell_row<2>(a, base, width, so, r, lane);
         if (r < a.n) a.y[r] = y;
     }

@@ -43,8 +43,10 @@ struct HostSell {
     std::vector<int32_t> sptr;  // [nslabs + 1] element offset of each slab
     std::vector<int32_t> scol;  // [sptr[nslabs]] column ids, slab-major, entry-major within slab
     std::vector<int32_t> rlen;  // [n] entries of each row that may be nonzero (no padding)
-    std::vector<int16_t> sdel;  // column - row offsets, empty if some offset exceeds int16
-    std::vector<int32_t> sofs;  // [nslabs] start of a shared-offset slab's list in soff, or -1
+    std::vector<int16_t> sdel;  // column - row offsets of the slabs with sofs = -1, or empty
+    std::vector<int32_t> sofs;  // [nslabs] start of a shared-offset slab's list in soff; else
+                                // -1: per-slot columns, 16-bit in sdel if it is not empty;
+                                // -2: per-slot 32-bit columns (offsets beyond 16 bits)
     std::vector<int32_t> soff;  // offset lists of the shared-offset slabs, slab by slab
 };
 // row_off: sample boundaries ({0, n} for one mesh); no slab offset crosses them.
@@ -114,8 +116,9 @@ struct Mat {
     int32_t nslabs = 0;
     const int32_t* sptr = nullptr;  // SELL slab offsets [nslabs + 1]
     const int32_t* scol = nullptr;  // SELL column ids [sptr[nslabs]]
-    const int16_t* sdel = nullptr;  // SELL column - row offsets, or NULL if they do not fit
-    const int32_t* sofs = nullptr;  // SELL [nslabs]: start of a slab's shared offsets, or -1
+    const int16_t* sdel = nullptr;  // SELL column - row offsets (slabs with sofs -1), or NULL
+    const int32_t* sofs = nullptr;  // SELL [nslabs]: start of a slab's shared offsets, or -1 / -2
+                                    // (per-slot 16-bit / 32-bit columns, as in HostSell)
     const int32_t* soff = nullptr;  // SELL shared offset lists
     const double* v = nullptr;      // values in the layout's order
     const float* v32 = nullptr;     // FP32 values in the layout's order (mixed precision)
@@ -156,7 +159,8 @@ void launch_advance(int* itb, int k, hipStream_t s);
 // dinv = 1 / diag(A) (CSR matrices, one system); a missing or non-positive diagonal marks
 // st->bad_diag.
 void launch_diag_inv(const Mat& A, double* dinv, float* dinv32, PcgState* st, hipStream_t s);
-// r = b - A x; p = D^-1 r; per-sample r.z, r.r, b.b into st (FP64 PCG start).
+// r = b - A x; z = p = D^-1 r (z into the residual buffer); per-sample r.z, r.r, b.b into
+// st (FP64 PCG start).
 void launch_pcg_start(const Mat& A, const SpmvConfig& c, const double* b, const double* x,
                       const double* dinv, double* r, double* p, double* partials,
                       PcgState* st, const Samples& smp, hipStream_t s);
@@ -168,9 +172,10 @@ void launch_pcg_start(const Mat& A, const SpmvConfig& c, const double* b, const 
 // by its parity, so no kernel reads a slot it also writes.
 //   spmv_dot:  q = A p; partial p.q per block into pq_part.
 //   update:    pq = sum(pq_part); alpha = rz[it&1] / pq (breakdown if pq <= 0);
-//              x += alpha p; r -= alpha q; partials of r.D^-1r and r.r into rz_part.
+//              x += alpha p; z -= alpha D^-1 q (z = D^-1 r); partials of r.z and r.r
+//              (r = z / D^-1) into rz_part.
 //   pupdate:   rz', rr = sum(rz_part); stop on convergence / limit / breakdown, else
-//              beta = rz' / rz[it&1]; p = D^-1 r + beta p; rz[(it+1)&1] = rz'.
+//              beta = rz' / rz[it&1]; p = z + beta p; rz[(it+1)&1] = rz'.
 // All three skip the samples whose st->done is set.
 // ev0 / ev1 (optional): events stamped at the kernel's own start and end
 GridInfo launch_spmv_dot64(const Mat& A, const SpmvConfig& c, const double* p, double* q,
@@ -189,12 +194,12 @@ int launch_update64(int n, double* x, double* r, const double* p, const double* 
 int launch_update32(int n, float* x, float* r, const float* p, const float* q, const float* dinv,
                     const double* pq_part, const GridInfo& gpq, double* rz_part, const int* itb,
                     int j, PcgState* st, const Samples& smp, double* sums, hipStream_t s);
-void launch_pupdate64(int n, double* p, const double* r, const double* dinv,
-                      const double* rz_part, int nb_rz, const int* itb, int j, PcgState* st,
-                      const Samples& smp, double* sums, hipStream_t s);
-void launch_pupdate32(int n, float* p, const float* r, const float* dinv, const double* rz_part,
-                      int nb_rz, const int* itb, int j, PcgState* st, const Samples& smp,
-                      double* sums, hipStream_t s);
+void launch_pupdate64(int n, double* p, const double* z, const double* rz_part, int nb_rz,
+                      const int* itb, int j, PcgState* st, const Samples& smp, double* sums,
+                      hipStream_t s);
+void launch_pupdate32(int n, float* p, const float* z, const double* rz_part, int nb_rz,
+                      const int* itb, int j, PcgState* st, const Samples& smp, double* sums,
+                      hipStream_t s);
 // Plain y = A x (no state).
 void launch_spmv64(const Mat& A, const SpmvConfig& c, const double* x, double* y, hipStream_t s);
 void launch_spmv32(const Mat& A, const SpmvConfig& c, const float* x, float* y, hipStream_t s);
@@ -471,10 +476,11 @@ struct rafem_mesh_s {
     double* geo = nullptr;    // per-element geometric constants of the row-wise assembly
     double* erhs = nullptr;   // per-incidence terms of the bioheat right-hand side
     int affine = 0;           // every hex is a parallelepiped
-    int16_t* sdel = nullptr;  // SELL column - row offsets (NULL when the bandwidth exceeds int16)
-    int32_t* sofs = nullptr;  // [nslabs] start of a shared-offset slab's list in soff, or -1
+    int16_t* sdel = nullptr;  // SELL column - row offsets (NULL when no slab is within int16 reach)
+    int32_t* sofs = nullptr;  // [nslabs] start of a shared-offset slab's list in soff, or -1 / -2
     int32_t* soff = nullptr;  // offset lists of the shared-offset slabs
     int64_t shared_slabs = 0;
+    int64_t int32_slabs = 0;  // slabs that read 32-bit columns
     int64_t index_bytes = 0;  // column data (offsets, slab pointers) one SpMV reads
     int32_t* conn = nullptr;
     double* xyz = nullptr;

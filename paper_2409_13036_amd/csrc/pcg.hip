@@ -167,7 +167,7 @@ __global__ __launch_bounds__(WG) void k_diag_inv(const int* __restrict__ rp,
 enum RowMode : int {
     ROW_PLAIN = 0,  // y = A x
     ROW_DOT = 1,    // y = A x, partials of x.y (PCG step; skipped once the sample is done)
-    ROW_START = 2,  // y = b - A x, p = D^-1 y, partials of y.p, y.y, b.b (PCG start)
+    ROW_START = 2,  // r = b - A x; y = p = D^-1 r, partials of r.p, r.r, b.b (PCG start)
     ROW_RESID = 3,  // y = b - A x, partials of y.y, b.b (refinement / true residual)
 };
 
@@ -207,13 +207,16 @@ __device__ __forceinline__ void row_epilogue(const RowArgs<T>& a, int r, T sum, 
     } else {
         const double bi = a.b[r];
         const double ri = bi - (double)sum;
-        a.y[r] = (T)ri;
         acc[1] += ri * ri;
         acc[2] += bi * bi;
         if constexpr (MODE == ROW_START) {
+            // the PCG keeps z = D^-1 r (r itself is formed where a dot product needs it)
             const double zi = a.dinv[r] * ri;
+            a.y[r] = (T)zi;
             a.pout[r] = zi;
             acc[0] += ri * zi;
+        } else {
+            a.y[r] = (T)ri;
         }
     }
 }
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(WG) void k_sell(RowArgs<T> a) {
         T sum;
         if (so >= 0)
             sum = sell_row_shared<T>(a.soff + so, a.val + base + lane, a.x + r, width);
-        else if constexpr (DELTA)
+        else if (DELTA && so == -1)
             sum = sell_row<T, int16_t>(a.sdel + base + lane, a.val + base + lane,
                                        a.x + min(r, a.n - 1), width);
         else
@@ -469,9 +472,12 @@ __global__ __launch_bounds__(WG) void k_finalize_rows(const double* __restrict__
 // ---------------------------------------------------------------------------
 constexpr int VPT = kVecRowsPerBlock / WG;
 
-// x += alpha p; r -= alpha q, alpha = rz / (sample's total of p.Ap); partials of r.z, r.r.
+// x += alpha p; z -= alpha D^-1 q, alpha = rz / (sample's total of p.Ap); partials of r.z,
+// r.r with r = D z.  The recurrence is carried on the preconditioned residual z = D^-1 r
+// (the same iterates as the one on r, in exact arithmetic), so that the direction update
+// reads z and p only.
 template <typename T>
-__global__ __launch_bounds__(WG) void k_update(int n, T* __restrict__ x, T* __restrict__ r,
+__global__ __launch_bounds__(WG) void k_update(int n, T* __restrict__ x, T* __restrict__ z,
                                                const T* __restrict__ p,
                                                const T* __restrict__ q,
                                                const T* __restrict__ dinv,
@@ -491,13 +497,13 @@ __global__ __launch_bounds__(WG) void k_update(int n, T* __restrict__ x, T* __re
     if (smp.S > 1 && S.done) return;
     const int it = *itb + j;
     const int i0 = row0 + threadIdx.x;
-    T xv[VPT], rv[VPT], pv[VPT], qv[VPT], dv[VPT];
+    T xv[VPT], zv[VPT], pv[VPT], qv[VPT], dv[VPT];
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
         const int i = i0 + u * WG;
         if (i < n) {
             xv[u] = x[i];
-            rv[u] = r[i];
+            zv[u] = z[i];
             pv[u] = p[i];
             qv[u] = q[i];
             dv[u] = dinv[i];
@@ -532,23 +538,27 @@ __global__ __launch_bounds__(WG) void k_update(int n, T* __restrict__ x, T* __re
         const int i = i0 + u * WG;
         if (i < n) {
             const T xi = xv[u] + alpha * pv[u];
-            const T ri = rv[u] - alpha * qv[u];
+            const T zi = zv[u] - alpha * (dv[u] * qv[u]);
             x[i] = xi;
-            r[i] = ri;
-            const T zi = dv[u] * ri;
-            acc[0] += (double)ri * (double)zi;
-            acc[1] += (double)ri * (double)ri;
+            z[i] = zi;
+            // r = z / D^-1 for the two dot products: an FP32 reciprocal (1 ulp) in the
+            // FP32 inner solve, whose scalars carry FP32 rounding anyway; exact in FP64
+            const double zd = (double)zi;
+            double ri;
+            if constexpr (sizeof(T) == 4) ri = (double)(zi * __builtin_amdgcn_rcpf(dv[u]));
+            else ri = zd / (double)dv[u];
+            acc[0] += ri * zd;
+            acc[1] += ri * ri;
         }
     }
     store_partials<2>(acc, rz_part, blk, nb);
     if (writer) S.pq = pq[0];
 }
 
-// Convergence test on the sample's totals of r.z and r.r, then p = D^-1 r + beta p.
+// Convergence test on the sample's totals of r.z and r.r, then p = z + beta p.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
-                                                const T* __restrict__ r,
-                                                const T* __restrict__ dinv,
+                                                const T* __restrict__ z,
                                                 const double* __restrict__ rz_part, int nb_rz,
                                                 const double* __restrict__ rz_tot,
                                                 const int* __restrict__ itb, int j, PcgState* st,
@@ -560,14 +570,13 @@ __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
     if (smp.S > 1 && S.done) return;  // as in k_update
     const int it = *itb + j;
     const int i0 = row0 + threadIdx.x;
-    T rv[VPT], pv[VPT], dv[VPT];
+    T zv[VPT], pv[VPT];
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
         const int i = i0 + u * WG;
         if (i < n) {
-            rv[u] = r[i];
+            zv[u] = z[i];
             pv[u] = p[i];
-            dv[u] = dinv[i];
         }
     }
     int b0, b1;
@@ -603,7 +612,7 @@ __global__ __launch_bounds__(WG) void k_pupdate(int n, T* __restrict__ p,
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
         const int i = i0 + u * WG;
-        if (i < n) p[i] = dv[u] * rv[u] + bt * pv[u];
+        if (i < n) p[i] = zv[u] + bt * pv[u];
     }
     if (writer) {
         S.rzs[(it + 1) & 1] = rz;
@@ -656,7 +665,7 @@ __global__ __launch_bounds__(WG) void k_inner_start(int n, const double* __restr
             if (i < n) {
                 const float ri = (float)(r64[i] * scale);
                 const float zi = dinv32[i] * ri;
-                r32[i] = ri;
+                r32[i] = zi;  // the inner PCG carries z = D^-1 r
                 d32[i] = 0.0f;
                 if (!cont) p32[i] = zi;
                 acc[0] += (double)ri * (double)zi;
@@ -719,10 +728,10 @@ __global__ __launch_bounds__(WG) void k_finalize_inner(const double* __restrict_
     }
 }
 
-// Continuation of the inner recurrence: p32 = D^-1 r32 + beta p32 (beta from
-// k_finalize_inner), for the samples whose inner solve goes on.
-__global__ __launch_bounds__(WG) void k_inner_pcont(int n, const float* __restrict__ r32,
-                                                    const float* __restrict__ dinv32,
+// Continuation of the inner recurrence: p32 = z32 + beta p32 (z32 = D^-1 r32 as
+// k_inner_start left it, beta from k_finalize_inner), for the samples whose inner solve
+// goes on.
+__global__ __launch_bounds__(WG) void k_inner_pcont(int n, const float* __restrict__ z32,
                                                     float* __restrict__ p32,
                                                     const PcgState* inner, Samples smp) {
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -734,7 +743,7 @@ __global__ __launch_bounds__(WG) void k_inner_pcont(int n, const float* __restri
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
         const int i = i0 + u * WG;
-        if (i < n) p32[i] = dinv32[i] * r32[i] + bt * p32[i];
+        if (i < n) p32[i] = z32[i] + bt * p32[i];
     }
 }
 
@@ -927,22 +936,22 @@ int launch_update32(int n, float* x, float* r, const float* p, const float* q, c
     return nb;
 }
 
-void launch_pupdate64(int n, double* p, const double* r, const double* dinv,
-                      const double* rz_part, int nb_rz, const int* itb, int j, PcgState* st,
-                      const Samples& smp, double* sums, hipStream_t s) {
+void launch_pupdate64(int n, double* p, const double* z, const double* rz_part, int nb_rz,
+                      const int* itb, int j, PcgState* st, const Samples& smp, double* sums,
+                      hipStream_t s) {
     const double* tot =
         presum<2>(rz_part, nb_rz, kVecRowsPerBlock, smp, sums ? sums + smp.S : nullptr, s);
-    hipLaunchKernelGGL(k_pupdate<double>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv,
-                       rz_part, nb_rz, tot, itb, j, st, smp);
+    hipLaunchKernelGGL(k_pupdate<double>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, z, rz_part,
+                       nb_rz, tot, itb, j, st, smp);
 }
 
-void launch_pupdate32(int n, float* p, const float* r, const float* dinv, const double* rz_part,
-                      int nb_rz, const int* itb, int j, PcgState* st, const Samples& smp,
-                      double* sums, hipStream_t s) {
+void launch_pupdate32(int n, float* p, const float* z, const double* rz_part, int nb_rz,
+                      const int* itb, int j, PcgState* st, const Samples& smp, double* sums,
+                      hipStream_t s) {
     const double* tot =
         presum<2>(rz_part, nb_rz, kVecRowsPerBlock, smp, sums ? sums + smp.S : nullptr, s);
-    hipLaunchKernelGGL(k_pupdate<float>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, r, dinv,
-                       rz_part, nb_rz, tot, itb, j, st, smp);
+    hipLaunchKernelGGL(k_pupdate<float>, dim3(vec_blocks(n)), dim3(WG), 0, s, n, p, z, rz_part,
+                       nb_rz, tot, itb, j, st, smp);
 }
 
 void launch_inner_start(int n, const double* r64, const PcgState* outer, float* r32, float* d32,
@@ -955,8 +964,7 @@ void launch_inner_start(int n, const double* r64, const PcgState* outer, float* 
     hipLaunchKernelGGL(k_finalize_inner, dim3(smp.S), dim3(WG), 0, s, partials, nb, outer,
                        inner_tol, maxit, inner, smp, cont);
     if (cont)
-        hipLaunchKernelGGL(k_inner_pcont, dim3(nb), dim3(WG), 0, s, n, r32, dinv32, p32, inner,
-                           smp);
+        hipLaunchKernelGGL(k_inner_pcont, dim3(nb), dim3(WG), 0, s, n, r32, p32, inner, smp);
 }
 
 void launch_refine_update(int n, double* x, const float* d32, const PcgState* outer,

@@ -133,7 +133,7 @@ struct Iter64 {
                                               t ? t->start(j) : nullptr, t ? t->stop(j) : nullptr);
         const int nb2 = launch_update64(n, x, m->r, m->p, m->q, dinv, m->part_pq, g1, m->part_rz,
                                         itb, j, st, smp, m->part_sum, s);
-        launch_pupdate64(n, m->p, m->r, dinv, m->part_rz, nb2, itb, j, st, smp, m->part_sum, s);
+        launch_pupdate64(n, m->p, m->r, m->part_rz, nb2, itb, j, st, smp, m->part_sum, s);
     }
 };
 
@@ -152,8 +152,7 @@ struct Iter32 {
                                               t ? t->start(j) : nullptr, t ? t->stop(j) : nullptr);
         const int nb2 = launch_update32(n, m->d32, m->r32, m->p32, m->q32, dinv32, m->part_pq, g1,
                                         m->part_rz, itb, j, st, smp, m->part_sum, s);
-        launch_pupdate32(n, m->p32, m->r32, dinv32, m->part_rz, nb2, itb, j, st, smp, m->part_sum,
-                         s);
+        launch_pupdate32(n, m->p32, m->r32, m->part_rz, nb2, itb, j, st, smp, m->part_sum, s);
     }
 };
 

@@ -212,27 +212,36 @@ HostSell build_sell(const HostStructure& S, int64_t n, const std::vector<int64_t
             }
         }
     });
-    // 16-bit offsets to the row (padding: offset 0) when every column is within reach
-    std::atomic<bool> fits{true};
+    // 16-bit offsets to the row (padding: offset 0) for every slab without a shared list
+    // whose columns are all within reach of its rows; the others keep their 32-bit columns
+    // (sofs = -2).  No such slab within reach: no offsets at all.
+    std::vector<uint8_t> near(L.nslabs, 0);
     parallel_for(L.nslabs, [&](int64_t s_lo, int64_t s_hi) {
-        for (int64_t s = s_lo; s < s_hi && fits.load(std::memory_order_relaxed); ++s)
-            for (int64_t k = L.sptr[s]; k < L.sptr[s + 1]; ++k) {
+        for (int64_t s = s_lo; s < s_hi; ++s) {
+            if (L.sofs[s] >= 0) continue;
+            bool ok = true;
+            for (int64_t k = L.sptr[s]; ok && k < L.sptr[s + 1]; ++k) {
                 const int64_t r = std::min<int64_t>(s * 64 + (k - L.sptr[s]) % 64, n - 1);
                 const int64_t d = (int64_t)L.scol[k] - r;
-                if (d < INT16_MIN || d > INT16_MAX) {
-                    fits = false;
-                    break;
-                }
+                ok = d >= INT16_MIN && d <= INT16_MAX;
             }
+            near[s] = ok ? 1 : 0;
+        }
     });
-    if (fits) {
-        L.sdel.resize(total);
+    if (std::find(near.begin(), near.end(), 1) != near.end()) {
+        L.sdel.assign(total, 0);
         parallel_for(L.nslabs, [&](int64_t s_lo, int64_t s_hi) {
-            for (int64_t s = s_lo; s < s_hi; ++s)
+            for (int64_t s = s_lo; s < s_hi; ++s) {
+                if (L.sofs[s] >= 0) continue;
+                if (!near[s]) {
+                    L.sofs[s] = -2;
+                    continue;
+                }
                 for (int64_t k = L.sptr[s]; k < L.sptr[s + 1]; ++k) {
                     const int64_t r = std::min<int64_t>(s * 64 + (k - L.sptr[s]) % 64, n - 1);
                     L.sdel[k] = (int16_t)((int64_t)L.scol[k] - r);
                 }
+            }
         });
     }
     return L;

@@ -115,7 +115,8 @@ def _full_case(R, torch, p, label, seed, expect):
     say(f"{label}: slabs {st.slabs}, shared-offset slabs {st.shared_offset_slabs}, "
         f"int16 columns {st.int16_columns}, longest row {st.max_row_entries}")
     for key, val in expect.items():
-        got = {"int16": st.int16_columns, "shared": st.shared_offset_slabs}[key]
+        got = {"int16": st.int16_columns, "shared": st.shared_offset_slabs,
+               "int32": st.int32_column_slabs}[key]
         assert (got > 0) == val, (key, got)
     m = Model(p)
     mats = {"potential": m.potential_system(m.sigma(p.initial_T()))[0],
@@ -134,7 +135,8 @@ def _full_case(R, torch, p, label, seed, expect):
 
 
 def test_hex101_layout_spmv_matches_oracle(torch_cuda):
-    _full_case(R(), torch_cuda, ri.config1(steps=1), "hex101", 11, {"int16": True, "shared": True})
+    _full_case(R(), torch_cuda, ri.config1(steps=1), "hex101", 11,
+               {"int16": True, "shared": True, "int32": False})
 
 
 def test_hex41_shuffled_int32_columns_match_oracle(torch_cuda):
@@ -142,7 +144,19 @@ def test_hex41_shuffled_int32_columns_match_oracle(torch_cuda):
     p = ri.make_problem("hex", 41, 3)
     order = np.random.default_rng(5).permutation(p.n_nodes)
     _full_case(R(), torch_cuda, reorder_nodes(p, order), "hex41-shuffled", 21,
-               {"int16": False, "shared": False})
+               {"int16": False, "shared": False, "int32": True})
+
+
+def test_hex41_far_swaps_mix_int16_and_int32_slabs(torch_cuda):
+    """Six nodes swapped with nodes 40,000 positions away: the slabs whose rows reach them
+    read 32-bit columns, the other slabs without a shared list 16-bit offsets."""
+    from paper_2409_13036_amd.sim import reorder_nodes
+    p = ri.make_problem("hex", 41, 3)
+    order = np.arange(p.n_nodes)
+    a = np.sort(np.random.default_rng(7).choice(np.arange(2000, 20000), 6, replace=False))
+    order[a], order[a + 40000] = a + 40000, a
+    _full_case(R(), torch_cuda, reorder_nodes(p, order), "hex41-far-swaps", 27,
+               {"int16": True, "shared": True, "int32": True})
 
 
 def test_tet25_layout_spmv_matches_oracle(torch_cuda):
