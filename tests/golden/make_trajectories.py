@@ -7,7 +7,7 @@ for the 101^3 workloads), each step warm-started from the previous state.
 
     python tests/golden/make_trajectories.py c1     # 101^3 hex, 100 coupled steps (~1 h, 1 core)
     python tests/golden/make_trajectories.py c4     # 4 ensemble samples, 3 steps each
-    python tests/golden/make_trajectories.py c2     # 161^3 Kuhn tets, 20 coupled steps (~2 h, ~20 GB)
+    python tests/golden/make_trajectories.py c2     # 161^3 Kuhn tets, 20 coupled steps (~70 min, ~20 GB)
 
 Files (NumPy .npz, no pickled objects):
 

@@ -7,9 +7,11 @@ other device path:
 - hex 41^3, the coupled workload's configuration (extrapolated starting points, tol
   1e-13), 100 steps, FP64 and mixed: every node of T and V at every step against the
   oracle's 100-step run (computed in the test);
-- Kuhn tets 161^3 (4.17M DOF), 20 coupled steps in the benchmark's configuration: the
-  mixed state within 1e-8 of the FP64 state at every step, and the 20th step of both
-  paths satisfying the oracle's equations of 2,000 sampled rows given their 19th state;
+- Kuhn tets 161^3 (4.17M DOF), 20 coupled steps in the benchmark's configuration: both
+  paths against the oracle's 20-step run at 2,000 stored free nodes after every step
+  (tests/golden/make_trajectories.py), the mixed state within 1e-8 of the FP64 state at
+  every step, and the 20th step of both paths satisfying the oracle's equations of 2,000
+  sampled rows given their 19th state;
 - the 64-sample ensemble, 3 coupled steps, FP64 and mixed: four samples (the smallest, the
   largest and two drawn from the seed) against the oracle's 3-step runs of those samples,
   stored by tests/golden/make_trajectories.py at 2,000 free nodes each.
@@ -87,6 +89,17 @@ def test_tet161_twenty_steps_mixed_tracks_fp64_and_satisfies_oracle_equations(to
         worst = max(worst, eT, eV)
         assert eT <= 1e-8 and eV <= 1e-8, (k + 1, eT, eV)
     say(f"mixed vs FP64 over 20 steps: max rel err {worst:.2e}")
+    gold = np.load(os.path.join(GOLDEN, "c2_tet161_trajectory.npz"))
+    nodes = gold["nodes"]
+    for prec, states in runs.items():
+        worst_o = 0.0
+        for j, k in enumerate(gold["steps"]):
+            Tg, Vg = states[k - 1]
+            eT = rel_err(Tg[nodes], gold["T"][j])
+            eV = rel_err(Vg[nodes], gold["V"][j])
+            worst_o = max(worst_o, eT, eV)
+            assert eT <= 1e-8 and eV <= 1e-8, (prec, int(k), eT, eV)
+        say(f"{prec}: worst sampled error against the stored oracle run {worst_o:.2e}")
     free = np.setdiff1d(np.arange(p.n_nodes), p.dir_ids)
     rows = np.sort(np.random.default_rng(13).choice(free, 2000, replace=False))
     gV, gT = np.linalg.norm(p.dir_V), np.linalg.norm(p.dir_T)
