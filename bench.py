@@ -68,7 +68,10 @@ def kernel_hash() -> str:
 def spmv_kernel_name(mesh, fp32: bool) -> str:
     """rocprofv3's name of the PCG SpMV (fused with p.Ap) that this mesh launches."""
     t = "float" if fp32 else "double"
-    return f"k_sell<{t}, 1, {'true' if mesh.stats().int16_columns else 'false'}>"
+    st = mesh.stats()
+    if st.int16_columns and st.int32_column_slabs:
+        return f"k_sell_wide<{t}, 1>"
+    return f"k_sell<{t}, 1, {'true' if st.int16_columns else 'false'}>"
 
 
 def copy_probe(mib: int) -> None:

@@ -413,7 +413,13 @@ typedef struct {
                              trajectory starts here (solves start from T_d, V_d; the states are
                              kept for the next call).  0: off.  A call with 0, a failed call,
                              rafem_step_pc and rafem_step_mono end the trajectory (the next call
-                             with 1 then behaves as 2).  Other values: E_ARG. */
+                             with 1 then behaves as 2).  Other values: E_ARG.
+                             rafem_step_vjp: 1: this call continues the reverse sweep of the
+                             previous rafem_step_vjp call on this handle: its adjoint solves
+                             start from that call's mu and nu (the adjoint states of the step
+                             after this one); 2: a sweep starts here (solves start from zero;
+                             mu and nu are kept for the next call); 0: from zero, nothing kept.
+                             The solves run to the same tolerance either way. */
     int32_t extrapolate_order; /* 1 (linear; also 0) .. 4 (quartic); other values: E_ARG */
 } rafem_phys;
 

@@ -6,7 +6,9 @@ Forward: ``steps`` coupled steps from the initial state, keeping (T, V) every
 Backward: for each checkpoint segment, last first, recompute the segment's states from
 its checkpoint, then run ``rafem_step_vjp`` from the segment's last step to its first,
 accumulating dL/dk_e and dL/dw_e.  Steps are deterministic, so the recomputed states are
-bitwise the forward states.
+bitwise the forward states.  Each reverse step's adjoint solves start from the adjoint
+states of the step after it (``phys.extrapolate`` 1; 2 on the sweep's first call), as the
+forward solves start from the previous states.
 """
 from __future__ import annotations
 
@@ -44,6 +46,7 @@ class _LesionLoss(torch.autograd.Function):
         gk = torch.zeros(mesh.n_elems, dtype=torch.float64, device=dp.dev)
         gw = torch.zeros_like(gk)
         p.reuse_bioheat = 1
+        first = True
         for s0 in reversed(starts):
             s1 = min(s0 + every, steps)
             dp.restore(*ctx.ckpt[s0])
@@ -53,6 +56,8 @@ class _LesionLoss(torch.autograd.Function):
                 Ts.append(dp.T.clone())
                 Vs.append(dp.V.clone())
             for j in range(s1 - s0, 0, -1):
+                p.extrapolate = 2 if first else 1
+                first = False
                 rafem.step_vjp(mesh, p, dp.k_e, dp.perf_e, dp.sigma0_e, dp.dir_V, dp.dir_T,
                                Ts[j - 1], Vs[j], Ts[j], lam, gk, gw, tol=tol,
                                precision=ctx.precision)

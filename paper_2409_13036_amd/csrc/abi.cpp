@@ -148,6 +148,7 @@ Mat step_matrix(rafem_mesh m, const double* v, const float* v32) {
     A.sptr = m->sptr;
     A.scol = m->scol;
     A.sdel = m->sdel;
+    A.wide = m->sdel && m->int32_slabs > 0 ? 1 : 0;
     A.sofs = m->sofs;
     A.soff = m->soff;
     A.v = v;
@@ -1472,12 +1473,19 @@ rafem_status rafem_step_vjp(rafem_mesh m, const rafem_phys* phys, const double* 
         }
         if (phys->reuse_bioheat && !m->bioheat_ready)
             throw Error{RAFEM_E_STATE, "reuse_bioheat set but no bioheat matrix has been assembled"};
+        if (phys->extrapolate < 0 || phys->extrapolate > 2)
+            throw Error{RAFEM_E_ARG, "phys.extrapolate must be 0, 1 or 2"};
         SolveOpts o = resolve_opts(opts, 1e-12);
         hipStream_t s = (hipStream_t)stream;
         rafem_step_info local{};
         rafem_step_info& inf = info ? *info : local;
         std::memset(&inf, 0, sizeof(inf));
         const int npe = m->npe, aff = m->affine;
+        // adjoint solves of a reverse sweep start from the previous call's mu and nu (the
+        // adjoint states of the step after), else from zero
+        const bool warm = phys->extrapolate == 1 && m->adj_kept;
+        const bool warm_nu = warm && m->adj_kept_nu;
+        m->adj_kept = false;
 
         launch_scatter_dirichlet(m->dir_ids, dir_T_d, m->nD, m->gT, s);
         if (!phys->reuse_bioheat || m->bioheat_dt != phys->dt)
@@ -1486,7 +1494,7 @@ rafem_status rafem_step_vjp(rafem_mesh m, const rafem_phys* phys, const double* 
         launch_fill(m->gtmp, m->n, 0.0, s);
         RAFEM_HIP(hipMemcpyAsync(m->bT, lambda_d, m->n * 8, hipMemcpyDeviceToDevice, s));
         launch_set_dirichlet(m->dir_ids, m->gtmp, m->nD, m->bT, s);
-        launch_fill(m->adj_mu, m->n, 0.0, s);
+        if (!warm) launch_fill(m->adj_mu, m->n, 0.0, s);
         RAFEM_HIP(hipGetLastError());
         solve_any(m, o, step_matrix(m, m->valsT, m->valsT32), step_samples(m), m->dinvT,
                   m->dinvT32, m->bT, m->adj_mu, &inf.T, s, kSolveAdjointBioheat);
@@ -1507,7 +1515,7 @@ rafem_status rafem_step_vjp(rafem_mesh m, const rafem_phys* phys, const double* 
                                         m->adj_mu, m->sigma, m->rhs, m->adj_sbar, s);
             }
             launch_set_dirichlet(m->dir_ids, m->gtmp, m->nD, m->rhs, s);
-            launch_fill(m->adj_nu, m->n, 0.0, s);
+            if (!warm_nu) launch_fill(m->adj_nu, m->n, 0.0, s);
             RAFEM_HIP(hipGetLastError());
             solve_any(m, o, step_matrix(m, m->valsV, m->valsV32), step_samples(m), m->dinvV,
                       m->dinvV32, m->rhs, m->adj_nu, &inf.V, s, kSolveAdjointPotential);
@@ -1526,6 +1534,8 @@ rafem_status rafem_step_vjp(rafem_mesh m, const rafem_phys* phys, const double* 
                                      m->adj_mu, dsig, phys->rho_c / phys->dt, lambda_d, s);
         }
         RAFEM_HIP(hipGetLastError());
+        m->adj_kept = phys->extrapolate != 0;
+        m->adj_kept_nu = m->adj_kept && phys->coupled;
         return RAFEM_OK;
     });
 }

@@ -117,6 +117,7 @@ struct Mat {
     const int32_t* sptr = nullptr;  // SELL slab offsets [nslabs + 1]
     const int32_t* scol = nullptr;  // SELL column ids [sptr[nslabs]]
     const int16_t* sdel = nullptr;  // SELL column - row offsets (slabs with sofs -1), or NULL
+    int wide = 0;                   // SELL: some slabs have sofs -2 (32-bit columns) as well
     const int32_t* sofs = nullptr;  // SELL [nslabs]: start of a slab's shared offsets, or -1 / -2
                                     // (per-slot 16-bit / 32-bit columns, as in HostSell)
     const int32_t* soff = nullptr;  // SELL shared offset lists
@@ -511,6 +512,7 @@ struct rafem_mesh_s {
     double xg_h[kXgSlots - 1] = {};
     bool potential_ready = false;  // a step has assembled the potential matrix
     double *adj_mu = nullptr, *adj_nu = nullptr, *adj_sbar = nullptr, *adj_dsig = nullptr;
+    bool adj_kept = false, adj_kept_nu = false;  // mu (nu) of the last reverse step kept
     // iteration counts of the previous solve of each kind and precision (first-chunk guesses)
     std::vector<int> hints[4][2];
     std::vector<int> hints_prev[4][2];  // the counts of the solve before (device-driven budgets)

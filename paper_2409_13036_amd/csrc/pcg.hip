@@ -362,8 +362,11 @@ __device__ __forceinline__ void store_group_partials(double (&v)[kMaxGroups][K],
     }
 }
 
-template <typename T, int MODE, bool DELTA>
-__global__ __launch_bounds__(WG) void k_sell(RowArgs<T> a) {
+// Column kinds of the slabs without a shared offset list: COLS 0: 32-bit columns, 1: 16-bit
+// offsets to the row, 2: either, per slab (sofs -1 / -2).  Separate instantiations keep the
+// common layouts' kernels free of the third path (its registers lowered their occupancy).
+template <typename T, int MODE, int COLS>
+__device__ __forceinline__ void sell_rows(const RowArgs<T>& a) {
     const int nblk = gridDim.x;
     const int blk = xcd_block(blockIdx.x, nblk);
     const int s0 = blk * a.slabs_per_block;
@@ -385,7 +388,7 @@ __global__ __launch_bounds__(WG) void k_sell(RowArgs<T> a) {
         T sum;
         if (so >= 0)
             sum = sell_row_shared<T>(a.soff + so, a.val + base + lane, a.x + r, width);
-        else if (DELTA && so == -1)
+        else if (COLS == 1 || (COLS == 2 && so == -1))
             sum = sell_row<T, int16_t>(a.sdel + base + lane, a.val + base + lane,
                                        a.x + min(r, a.n - 1), width);
         else
@@ -404,6 +407,18 @@ __global__ __launch_bounds__(WG) void k_sell(RowArgs<T> a) {
             store_group_partials<3>(acc, ng, a.partials, g0, nb);
         }
     }
+}
+
+// DELTA: the layout's slabs read 16-bit offsets (else 32-bit columns).
+template <typename T, int MODE, bool DELTA>
+__global__ __launch_bounds__(WG) void k_sell(RowArgs<T> a) {
+    sell_rows<T, MODE, DELTA ? 1 : 0>(a);
+}
+
+// Layouts with both kinds of per-slot columns.
+template <typename T, int MODE>
+__global__ __launch_bounds__(WG) void k_sell_wide(RowArgs<T> a) {
+    sell_rows<T, MODE, 2>(a);
 }
 
 // [row-kernels-end]
@@ -803,7 +818,9 @@ GridInfo launch_rows(const Mat& A, const T* vals, const SpmvConfig& c, const T* 
         g.nb = blocks_for(A.nslabs, kSlabGroup);  // partial slots: one per group of slabs
         g.rpb = kSlabGroup * WAVE;
         if (nblk > 0) {
-            if (A.sdel)
+            if (A.sdel && A.wide)
+                launch_timed(k_sell_wide<T, MODE>, nblk, s, ev0, ev1, a);
+            else if (A.sdel)
                 launch_timed(k_sell<T, MODE, true>, nblk, s, ev0, ev1, a);
             else
                 launch_timed(k_sell<T, MODE, false>, nblk, s, ev0, ev1, a);

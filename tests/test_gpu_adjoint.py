@@ -155,3 +155,43 @@ def test_c3_size_gradients_match_central_differences(torch_cuda):
           f"{max(r['rel_err_h1e-06'] for r in rows if 'rel_err_h1e-06' in r):.2e} with noise "
           f"{max(r['noise_h1e-06'] for r in rows if r['param'].startswith('k[')):.2e}", flush=True)
     assert worst <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_reverse_sweep_started_from_the_next_steps_adjoint_states(torch_cuda, precision):
+    """A reverse sweep whose adjoint solves start from the following step's mu and nu
+    (phys.extrapolate 2, then 1) gives the gradients of the sweep started from zero to the
+    solves' tolerance, with fewer iterations."""
+    torch = torch_cuda
+    from paper_2409_13036_amd import _lib as R
+    from paper_2409_13036_amd.sim import DeviceProblem
+    steps, tol = 8, 1e-13
+    p = ri.make_problem("hex", 21, 3, steps=steps, with_loss=True)
+    dp = DeviceProblem(p)
+    Ts, Vs = [dp.T.clone()], [dp.V.clone()]
+    for _ in range(steps):
+        dp.step(tol)
+        Ts.append(dp.T.clone())
+        Vs.append(dp.V.clone())
+    out = {}
+    for mode in ("zero", "warm"):
+        lam = torch.zeros(p.n_nodes, dtype=torch.float64, device="cuda")
+        R.lesion_loss(dp.mesh, dp.loss_ids, dp.T_target, Ts[-1], grad=lam)
+        gk = torch.zeros(p.n_elems, dtype=torch.float64, device="cuda")
+        gw = torch.zeros_like(gk)
+        dp.phys.reuse_bioheat = 1
+        iters = 0
+        for n in range(steps, 0, -1):
+            dp.phys.extrapolate = 0 if mode == "zero" else (2 if n == steps else 1)
+            info = R.step_vjp(dp.mesh, dp.phys, dp.k_e, dp.perf_e, dp.sigma0_e, dp.dir_V,
+                              dp.dir_T, Ts[n - 1], Vs[n], Ts[n], lam, gk, gw, tol=tol,
+                              precision=precision)
+            iters += info["T"]["iters"] + info["V"]["iters"]
+        out[mode] = (to_host(gk), to_host(gw), iters)
+    dp.close()
+    ek = rel_err(out["warm"][0], out["zero"][0])
+    ew = rel_err(out["warm"][1], out["zero"][1])
+    print(f"[adjoint warm start {precision}] iterations {out['zero'][2]} -> {out['warm'][2]}, "
+          f"grad_k {ek:.2e} grad_w {ew:.2e}", flush=True)
+    assert ek <= 1e-9 and ew <= 1e-9
+    assert out["warm"][2] < out["zero"][2]
