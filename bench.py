@@ -517,9 +517,10 @@ def counters_summary(fetch_dir: str, write_dir: str, probe_mib: int, workload: s
 def batch_leg(args) -> dict:
     """Ensemble workload: 64 hex samples of side n ~ U{41..81} nodes with per-sample lognormal
     k, sigma0 and w, advanced together through one batch handle (graph-captured iteration
-    chunks, autotuned SpMV slab shape) for 30 coupled steps, FP64 and mixed.  Reports
-    sample-steps/s and, per sample, the relative error of the mixed state against the FP64
-    state after the last step."""
+    chunks, autotuned SpMV slab shape, device-driven solves: one host poll per solve once
+    two alike solves have left their counts) for 30 coupled steps, FP64 and mixed, then the
+    same host-driven.  Reports sample-steps/s and, per sample, the relative error of the
+    mixed state against the FP64 state after the last step."""
     import numpy as np
     import torch
     import rafem_inputs as ri
@@ -529,8 +530,8 @@ def batch_leg(args) -> dict:
     probs = ri.config4(samples=args.batch_samples, steps=args.batch_steps)
     t0 = time.perf_counter()
     bp = BatchProblem(probs)
-    if args.device_driven:
-        bp.mesh.set_device_driven(True)
+    if args.host_driven:
+        bp.mesh.set_device_driven(False)
     bp.extrapolate = not args.no_extrapolate
     bp.extrapolate_order = args.extrapolate_order
     setup = time.perf_counter() - t0
@@ -893,9 +894,9 @@ def main():
     ap.add_argument("--pc-eps", type=float, default=1e-9,
                     help="predictor-corrector: relative change of T that ends a corrector")
     ap.add_argument("--batch-only", action="store_true", help="run only the ensemble leg")
-    ap.add_argument("--device-driven", action="store_true",
-                    help="ensemble leg: time the device-driven solves first (each solve enqueued "
-                         "whole, one poll per solve) and the host-driven default second")
+    ap.add_argument("--host-driven", action="store_true",
+                    help="ensemble leg: time the host-driven solves first (host polls inside each "
+                         "solve) and the device-driven default second")
     ap.add_argument("--batch-samples", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=30)
     ap.add_argument("--copy-probe-mib", type=int, default=0,

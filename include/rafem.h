@@ -187,7 +187,7 @@ rafem_status rafem_mesh_sample_layout(rafem_mesh mesh, int64_t* node_off, int64_
  * default for batch handles.  Graphs are not used while SpMV profiling is enabled. */
 rafem_status rafem_mesh_set_graphs(rafem_mesh mesh, int32_t enable);
 
-/* Device-driven solves (off by default): each of
+/* Device-driven solves (on by default for batch handles, off for single meshes): each of
  * rafem_step's two solves is enqueued at once -- the PCG iterations and, in mixed
  * precision, every refinement with its inner solve -- each (inner) solve with an iteration
  * budget of ceil(budget_scale x the larger of its counts in the last two solves of its
@@ -198,9 +198,11 @@ rafem_status rafem_mesh_set_graphs(rafem_mesh mesh, int32_t enable);
  * within its budget, every sample converged, no refinement stagnated); otherwise its
  * starting point is restored and it runs host-driven.  Either way the results are bit for
  * bit the host-driven solve's; an accepted solve synchronises with the host once (two per
- * coupled step) instead of at every poll.  Solves without counts from a previous solve of
- * the same kind and precision, and solves while SpMV profiling or region timing is on, run
- * host-driven; so do rafem_step_pc, rafem_step_mono and rafem_step_vjp.
+ * coupled step) instead of at every poll.  Solves without counts from the last two solves of
+ * the same kind and precision started the same way (the same predictor order: at the start
+ * of a trajectory the order, and with it the counts, still change), and solves while SpMV
+ * profiling or region timing is on, run host-driven; so do rafem_step_pc, rafem_step_mono
+ * and rafem_step_vjp.
  *   enable        nonzero: on (allocates the solver logs and a copy of one node vector on
  *                 first use)
  *   budget_scale  0 for the default 1.05, else (0, 16] */

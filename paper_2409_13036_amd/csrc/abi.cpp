@@ -281,7 +281,12 @@ void solve_any(rafem_mesh m, const SolveOpts& o, const Mat& A, const Samples& sm
     // kind: which solve of a step (its own chunk hints per precision), or -1 for none
     const bool mixed = o.precision == RAFEM_MIXED;
     std::vector<int>* hints = kind >= 0 ? &m->hints[kind][mixed ? 1 : 0] : nullptr;
-    if (hints) m->hints_prev[kind][mixed ? 1 : 0] = *hints;
+    if (hints) {
+        const int k2 = mixed ? 1 : 0;
+        m->hints_prev[kind][k2] = *hints;
+        m->hints_prev_q[kind][k2] = m->hints_q[kind][k2];
+        m->hints_q[kind][k2] = m->step_q;
+    }
     if (mixed)
         pcg_mixed(m, A, smp, dinv, dinv32, b, x, o, info, s, hints);
     else
@@ -301,9 +306,13 @@ void solve_step(rafem_mesh m, const SolveOpts& o, const Mat& A, const double* di
                 hipStream_t s, int kind) {
     const bool mixed = o.precision == RAFEM_MIXED;
     const bool potential = kind == kSolvePotential;
-    std::vector<int>& hints = m->hints[kind][mixed ? 1 : 0];
+    const int k2 = mixed ? 1 : 0;
+    std::vector<int>& hints = m->hints[kind][k2];
     m->dd_used = 0;
-    if (m->dd_on && m->tuned && !m->reg_on && dd_ready(m, o, &hints)) {
+    // budgets only from the last two solves of the kind when they started as this one does
+    // (at a trajectory's start the predictor's order still rises and the counts move)
+    const bool alike = m->hints_q[kind][k2] == m->step_q && m->hints_prev_q[kind][k2] == m->step_q;
+    if (m->dd_on && m->tuned && !m->reg_on && alike && dd_ready(m, o, &hints)) {
         const size_t bytes = (size_t)m->n * sizeof(double);
         RAFEM_HIP(hipMemcpyAsync(m->dd_x0, x, bytes, hipMemcpyDeviceToDevice, s));
         const DdRecord r = dd_enqueue(m, A, step_samples(m), dinv, dinv32, b, x, o,
@@ -316,7 +325,9 @@ void solve_step(rafem_mesh m, const SolveOpts& o, const Mat& A, const double* di
         const PcgState* hs = nullptr;
         if (dd_finish(m, r, o, info, &h, &hs)) {
             record_samples(m, potential, mixed, hs);
-            m->hints_prev[kind][mixed ? 1 : 0] = hints;
+            m->hints_prev[kind][k2] = hints;
+            m->hints_prev_q[kind][k2] = m->hints_q[kind][k2];
+            m->hints_q[kind][k2] = m->step_q;
             hints = h;
             m->dd_solves += 1;
             return;
@@ -522,6 +533,10 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             m->dir_off = dir_off;
             m->sample_info.assign(S_, rafem_step_info{});
             m->use_graphs = S_ > 1;
+            if (S_ > 1) {  // ensembles solve device-driven by default
+                dd_alloc(m);
+                m->dd_on = true;
+            }
             launch_slot_map(m->E, m->npe, m->conn, sell_layout(m), m->e2s, nullptr);
             int32_t max_w = 0;
             for (int64_t b = 0; b < SL.nslabs; ++b)
@@ -1199,6 +1214,7 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
             throw Error{RAFEM_E_ARG, "phys.extrapolate_order must be in [0, 4]"};
         if (!phys->extrapolate) {
             m->xg_kept = 0;
+            m->step_q = -1;
             const rafem_status st = step_core(m, phys, reuse, k_e_d, perf_e_d, sigma0_e_d,
                                               dir_V_d, dir_T_d, T_d, T_d, T_d, V_d, o, inf, s);
             region_flush(m, s);
@@ -1217,6 +1233,7 @@ rafem_status rafem_step(rafem_mesh m, const rafem_phys* phys, const double* k_e_
         RAFEM_HIP(hipMemcpyAsync(Tn, T_d, bytes, hipMemcpyDeviceToDevice, s));
         if (phys->coupled) RAFEM_HIP(hipMemcpyAsync(Vn, V_d, bytes, hipMemcpyDeviceToDevice, s));
         const int q = std::min(order, m->xg_kept);
+        m->step_q = q;
         if (q == 1) {
             const double c = phys->dt / m->xg_h[0];
             const int p1 = (cur + K - 1) % K;
@@ -1264,6 +1281,7 @@ rafem_status rafem_step_pc(rafem_mesh m, const rafem_phys* phys, const double* k
     return guard([&]() -> rafem_status {
         check_step_args(m, phys, k_e_d, perf_e_d, sigma0_e_d, dir_V_d, dir_T_d, T_d, V_d);
         require(m->S == 1, "the predictor-corrector step runs on single meshes");
+        m->step_q = -2;
         require(!T_prev_d || (dt_prev > 0.0 && std::isfinite(dt_prev)),
                 "dt_prev must be > 0 when T_prev is given");
         const double eps = copts && copts->tol > 0.0 ? copts->tol : 1e-10;
@@ -1386,6 +1404,7 @@ rafem_status rafem_step_mono(rafem_mesh m, const rafem_phys* phys, const double*
                              rafem_mono_info* info, void* stream) {
     return guard([&]() -> rafem_status {
         check_mono_args(m, phys, k_e_d, perf_e_d, sigma0_e_d, T_d, T_d, V_d);
+        m->step_q = -2;
         require(m->nD == 0 || (dir_V_d && dir_T_d), "dir_V or dir_T is NULL");
         require(!T_prev_d || (dt_prev > 0.0 && std::isfinite(dt_prev)),
                 "dt_prev must be > 0 when T_prev is given");
@@ -1465,6 +1484,7 @@ rafem_status rafem_step_vjp(rafem_mesh m, const rafem_phys* phys, const double* 
         require(phys != nullptr, "phys is NULL");
         require(k_e_d && perf_e_d && T_d && lambda_d && grad_k_d && grad_perf_d,
                 "NULL k, perfusion, T, lambda or gradient");
+        m->step_q = -2;
         require(m->nD == 0 || dir_T_d != nullptr, "dir_T is NULL");
         require(phys->dt > 0.0 && std::isfinite(phys->dt), "dt must be > 0");
         if (phys->coupled) {

@@ -516,6 +516,12 @@ struct rafem_mesh_s {
     // iteration counts of the previous solve of each kind and precision (first-chunk guesses)
     std::vector<int> hints[4][2];
     std::vector<int> hints_prev[4][2];  // the counts of the solve before (device-driven budgets)
+    // how the solves of the current step start (rafem_step: the predictor's order q, or -1
+    // from the previous state; -2 other entry points), and how the solves behind hints and
+    // hints_prev started: device-driven budgets come only from solves that started alike
+    int step_q = -2;
+    int hints_q[4][2] = {{-3, -3}, {-3, -3}, {-3, -3}, {-3, -3}};
+    int hints_prev_q[4][2] = {{-3, -3}, {-3, -3}, {-3, -3}, {-3, -3}};
 
     // monolithic corrector (allocated on first use): Jacobian slots as double4 in the SELL
     // layout, -R, block-Jacobi inverses, the Newton update, GMRES vectors and basis
