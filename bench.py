@@ -69,9 +69,10 @@ def spmv_kernel_name(mesh, fp32: bool) -> str:
     """rocprofv3's name of the PCG SpMV (fused with p.Ap) that this mesh launches."""
     t = "float" if fp32 else "double"
     st = mesh.stats()
+    nt = "_nt" if (st.streamed_values32 if fp32 else st.streamed_values) else ""
     if st.int16_columns and st.int32_column_slabs:
-        return f"k_sell_wide<{t}, 1>"
-    return f"k_sell<{t}, 1, {'true' if st.int16_columns else 'false'}>"
+        return f"k_sell_wide{nt}<{t}, 1>"
+    return f"k_sell{nt}<{t}, 1, {'true' if st.int16_columns else 'false'}>"
 
 
 def copy_probe(mib: int) -> None:
@@ -87,6 +88,33 @@ def copy_probe(mib: int) -> None:
     print(f"[bench] copy probe: {mib} MiB read + {mib} MiB written per launch, 3 launches",
           file=sys.stderr, flush=True)
     del a, b
+
+
+_COPY_GBS = None
+
+
+def copy_ceiling() -> float:
+    """On-box device copy bandwidth (GB/s): a plain copy of 1 GiB (torch's copy kernel),
+    read + write bytes over the mean of 10 event-timed launches after 3 untimed ones;
+    measured once per process."""
+    global _COPY_GBS
+    if _COPY_GBS is None:
+        import torch
+        n = (1 << 30) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        _COPY_GBS = 2 * 4 * n / (ms * 1e6)
+        del a, b
+    return _COPY_GBS
 
 
 def measured_traffic(kernel: str, workload: str, nnz: int):
@@ -197,6 +225,7 @@ def spmv_roofline(mesh, kernel: str, wl_key: str, fp32: bool, warm_us: float,
           f"({copies} copies) {t_cold:.2f} us, one copy {t_one:.2f} us, in solves "
           f"{warm_us:.2f} us", file=sys.stderr, flush=True)
     gbs = lambda b, us: b / (us * 1e3) if us > 0 else None
+    copy_gbs = copy_ceiling()
     return {"bound": "hbm", "achieved": gbs(nbytes, t_cold), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": gbs(nbytes, t_cold) / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": kernel, "workload": wl_key, "bytes_per_launch": nbytes,
@@ -211,6 +240,9 @@ def spmv_roofline(mesh, kernel: str, wl_key: str, fp32: bool, warm_us: float,
             "csr_equivalent": {"bytes_per_launch": csr, "achieved_cold": gbs(csr, t_cold),
                                "achieved_warm": gbs(csr, warm_us)},
             "measured_GBs_cold": gbs(traffic, t_cold) if traffic else None,
+            "copy_ceiling": {"GBs": copy_gbs, "frac_of_copy": gbs(nbytes, t_cold) / copy_gbs,
+                             "how": "plain device copy of 1 GiB on this box, read + write "
+                                    "bytes over the event-timed mean of 10 launches"},
             "note": ("achieved = bytes_per_launch (the slab layout's values with padding, its "
                      "column data, x once, y once) / mean launch time with a cold Infinity "
                      "Cache; warm = the same bytes over the in-solve launches, whose matrix "

@@ -126,7 +126,8 @@ typedef struct {
     int32_t nodes_per_elem;
     int32_t n_colours;
     int32_t n_samples;
-    int32_t slabs_per_block;     /* SELL shape of the FP64 SpMV (autotuned at the first step) */
+    int32_t slabs_per_block;     /* SELL shape of the FP64 SpMV (autotuned at the first step,
+                                    with the choice of streamed value loads below) */
     int32_t slabs_per_block32;   /* SELL shape of the FP32 SpMV */
     int32_t int16_columns;       /* 1 if the SpMV reads 16-bit column offsets (on some slabs) */
     int64_t slabs;               /* 64-row slabs of the SpMV layout */
@@ -146,6 +147,9 @@ typedef struct {
     int64_t int32_column_slabs;  /* slabs without a shared offset list whose columns lie beyond
                                     16-bit reach of their rows: they read 32-bit columns, the
                                     other such slabs 16-bit offsets */
+    int32_t streamed_values;     /* 1 if the FP64 SpMV reads its values with nontemporal loads
+                                    (autotuned: matrices beyond the Infinity Cache) */
+    int32_t streamed_values32;   /* the same for the FP32 SpMV */
 } rafem_mesh_stats;
 
 /* Build a mesh on the current device.

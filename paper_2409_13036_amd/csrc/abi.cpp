@@ -824,6 +824,8 @@ rafem_status rafem_mesh_get_stats(rafem_mesh m, rafem_mesh_stats* out) {
         out->device_driven_solves = m->dd_solves;
         out->device_driven_redone = m->dd_redone;
         out->int32_column_slabs = m->int32_slabs;
+        out->streamed_values = m->spmv.stream;
+        out->streamed_values32 = m->spmv32.stream;
         return RAFEM_OK;
     });
 }

@@ -268,7 +268,15 @@ constexpr int kSellUnroll = 9;
 // last, shorter batch is masked (its missing entries add nothing), so a row of any width
 // keeps a whole batch of loads in flight (the 15-entry rows of the tet meshes: 9 + 6).
 // COL is int (absolute columns, xr = x) or int16_t (offsets to the row, xr = x + row).
-template <typename T, typename COL, bool MASKED>
+// A matrix value; NT: a nontemporal load (the values stream through the caches once, which
+// pays when the matrix does not fit the Infinity Cache and costs when it does).
+template <typename T, bool NT>
+__device__ __forceinline__ T load_value(const T* __restrict__ p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <typename T, typename COL, bool MASKED, bool NT>
 __device__ __forceinline__ void sell_batch(const COL* __restrict__ cp, const T* __restrict__ vp,
                                            const T* __restrict__ xr, int j, int width, T& sum) {
     int c[kSellUnroll];
@@ -277,7 +285,7 @@ __device__ __forceinline__ void sell_batch(const COL* __restrict__ cp, const T* 
     for (int u = 0; u < kSellUnroll; ++u) {
         const bool in = !MASKED || j + u < width;
         c[u] = in ? (int)cp[(j + u) * WAVE] : 0;
-        v[u] = in ? vp[(j + u) * WAVE] : T(0);
+        v[u] = in ? load_value<T, NT>(vp + (j + u) * WAVE) : T(0);
     }
     T g[kSellUnroll];
 #pragma unroll
@@ -287,13 +295,14 @@ __device__ __forceinline__ void sell_batch(const COL* __restrict__ cp, const T* 
         if (!MASKED || j + u < width) sum += v[u] * g[u];
 }
 
-template <typename T, typename COL>
+template <typename T, typename COL, bool NT>
 __device__ __forceinline__ T sell_row(const COL* __restrict__ cp, const T* __restrict__ vp,
                                       const T* __restrict__ xr, int width) {
     T sum = T(0);
     int j = 0;
-    for (; j + kSellUnroll <= width; j += kSellUnroll) sell_batch<T, COL, false>(cp, vp, xr, j, width, sum);
-    if (j < width) sell_batch<T, COL, true>(cp, vp, xr, j, width, sum);
+    for (; j + kSellUnroll <= width; j += kSellUnroll)
+        sell_batch<T, COL, false, NT>(cp, vp, xr, j, width, sum);
+    if (j < width) sell_batch<T, COL, true, NT>(cp, vp, xr, j, width, sum);
     return sum;
 }
 
@@ -301,7 +310,7 @@ __device__ __forceinline__ T sell_row(const COL* __restrict__ cp, const T* __res
 // off being one list for the whole wavefront (read through the scalar cache), so the x
 // reads of one entry are 64 consecutive words.  Same order of operations as sell_row; the
 // entries that are not in the matrix hold 0 and add exactly nothing.
-template <typename T, bool MASKED>
+template <typename T, bool MASKED, bool NT>
 __device__ __forceinline__ void shared_batch(const int* __restrict__ off, const T* __restrict__ vp,
                                              const T* __restrict__ xr, int j, int width, T& sum) {
     int c[kSellUnroll];
@@ -310,7 +319,7 @@ __device__ __forceinline__ void shared_batch(const int* __restrict__ off, const 
     for (int u = 0; u < kSellUnroll; ++u) {
         const bool in = !MASKED || j + u < width;
         c[u] = in ? off[j + u] : 0;
-        v[u] = in ? vp[(j + u) * WAVE] : T(0);
+        v[u] = in ? load_value<T, NT>(vp + (j + u) * WAVE) : T(0);
     }
     T g[kSellUnroll];
 #pragma unroll
@@ -320,13 +329,14 @@ __device__ __forceinline__ void shared_batch(const int* __restrict__ off, const 
         if (!MASKED || j + u < width) sum += v[u] * g[u];
 }
 
-template <typename T>
+template <typename T, bool NT>
 __device__ __forceinline__ T sell_row_shared(const int* __restrict__ off, const T* __restrict__ vp,
                                              const T* __restrict__ xr, int width) {
     T sum = T(0);
     int j = 0;
-    for (; j + kSellUnroll <= width; j += kSellUnroll) shared_batch<T, false>(off, vp, xr, j, width, sum);
-    if (j < width) shared_batch<T, true>(off, vp, xr, j, width, sum);
+    for (; j + kSellUnroll <= width; j += kSellUnroll)
+        shared_batch<T, false, NT>(off, vp, xr, j, width, sum);
+    if (j < width) shared_batch<T, true, NT>(off, vp, xr, j, width, sum);
     return sum;
 }
 
@@ -365,7 +375,7 @@ __device__ __forceinline__ void store_group_partials(double (&v)[kMaxGroups][K],
 // Column kinds of the slabs without a shared offset list: COLS 0: 32-bit columns, 1: 16-bit
 // offsets to the row, 2: either, per slab (sofs -1 / -2).  Separate instantiations keep the
 // common layouts' kernels free of the third path (its registers lowered their occupancy).
-template <typename T, int MODE, int COLS>
+template <typename T, int MODE, int COLS, bool NT>
 __device__ __forceinline__ void sell_rows(const RowArgs<T>& a) {
     const int nblk = gridDim.x;
     const int blk = xcd_block(blockIdx.x, nblk);
@@ -387,12 +397,12 @@ __device__ __forceinline__ void sell_rows(const RowArgs<T>& a) {
         const int r = sl * WAVE + lane;
         T sum;
         if (so >= 0)
-            sum = sell_row_shared<T>(a.soff + so, a.val + base + lane, a.x + r, width);
+            sum = sell_row_shared<T, NT>(a.soff + so, a.val + base + lane, a.x + r, width);
         else if (COLS == 1 || (COLS == 2 && so == -1))
-            sum = sell_row<T, int16_t>(a.sdel + base + lane, a.val + base + lane,
-                                       a.x + min(r, a.n - 1), width);
+            sum = sell_row<T, int16_t, NT>(a.sdel + base + lane, a.val + base + lane,
+                                           a.x + min(r, a.n - 1), width);
         else
-            sum = sell_row<T, int>(a.scol + base + lane, a.val + base + lane, a.x, width);
+            sum = sell_row<T, int, NT>(a.scol + base + lane, a.val + base + lane, a.x, width);
         if (r < a.n) row_epilogue<T, MODE>(a, r, sum, acc[i / 2]);
     }
     if constexpr (MODE != ROW_PLAIN) {
@@ -412,13 +422,24 @@ __device__ __forceinline__ void sell_rows(const RowArgs<T>& a) {
 // DELTA: the layout's slabs read 16-bit offsets (else 32-bit columns).
 template <typename T, int MODE, bool DELTA>
 __global__ __launch_bounds__(WG) void k_sell(RowArgs<T> a) {
-    sell_rows<T, MODE, DELTA ? 1 : 0>(a);
+    sell_rows<T, MODE, DELTA ? 1 : 0, false>(a);
 }
 
 // Layouts with both kinds of per-slot columns.
 template <typename T, int MODE>
 __global__ __launch_bounds__(WG) void k_sell_wide(RowArgs<T> a) {
-    sell_rows<T, MODE, 2>(a);
+    sell_rows<T, MODE, 2, false>(a);
+}
+
+// The same with the matrix values read by nontemporal loads (chosen by the autotuner).
+template <typename T, int MODE, bool DELTA>
+__global__ __launch_bounds__(WG) void k_sell_nt(RowArgs<T> a) {
+    sell_rows<T, MODE, DELTA ? 1 : 0, true>(a);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(WG) void k_sell_wide_nt(RowArgs<T> a) {
+    sell_rows<T, MODE, 2, true>(a);
 }
 
 // [row-kernels-end]
@@ -819,11 +840,14 @@ GridInfo launch_rows(const Mat& A, const T* vals, const SpmvConfig& c, const T* 
         g.rpb = kSlabGroup * WAVE;
         if (nblk > 0) {
             if (A.sdel && A.wide)
-                launch_timed(k_sell_wide<T, MODE>, nblk, s, ev0, ev1, a);
+                launch_timed(c.stream ? k_sell_wide_nt<T, MODE> : k_sell_wide<T, MODE>, nblk, s,
+                             ev0, ev1, a);
             else if (A.sdel)
-                launch_timed(k_sell<T, MODE, true>, nblk, s, ev0, ev1, a);
+                launch_timed(c.stream ? k_sell_nt<T, MODE, true> : k_sell<T, MODE, true>, nblk, s,
+                             ev0, ev1, a);
             else
-                launch_timed(k_sell<T, MODE, false>, nblk, s, ev0, ev1, a);
+                launch_timed(c.stream ? k_sell_nt<T, MODE, false> : k_sell<T, MODE, false>, nblk,
+                             s, ev0, ev1, a);
         }
     } else {
         g.nb = blocks_for(A.n, c.rows_per_block);

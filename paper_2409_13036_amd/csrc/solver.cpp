@@ -556,10 +556,11 @@ bool dd_finish(rafem_mesh m, const DdRecord& r, const SolveOpts& o, rafem_solve_
 
 namespace {
 
-// On-disk cache of the tuned slab shapes: one line per (device, layout) key,
-// "<key> <slabs per block FP64> <slabs per block FP32>", in the file named by
-// RAFEM_TUNE_CACHE, else $HOME/.cache/rafem/spmv_tune.txt.  Unreadable or unwritable files
-// are ignored (the shapes are then timed every time).
+// On-disk cache of the tuned SpMV configurations: one line per (device, layout) key,
+// "<key> <slabs per block FP64> <slabs per block FP32> <streamed FP64> <streamed FP32>", in
+// the file named by RAFEM_TUNE_CACHE, else $HOME/.cache/rafem/spmv_tune.txt.  Unreadable or
+// unwritable files, and lines of another form, are ignored (the configurations are then
+// timed).
 std::string tune_cache_path() {
     if (const char* p = std::getenv("RAFEM_TUNE_CACHE")) return p;
     if (const char* h = std::getenv("HOME")) return std::string(h) + "/.cache/rafem/spmv_tune.txt";
@@ -579,25 +580,30 @@ std::string tune_key(rafem_mesh m) {
     return buf;
 }
 
-bool tune_lookup(const std::string& key, int& spb64, int& spb32) {
+bool tune_lookup(const std::string& key, SpmvConfig& c64, SpmvConfig& c32) {
     const std::string path = tune_cache_path();
     if (path.empty()) return false;
     std::FILE* f = std::fopen(path.c_str(), "r");
     if (!f) return false;
-    char k[512];
-    int a = 0, b = 0;
+    char line[640], k[512];
+    int a = 0, b = 0, na = 0, nb = 0;
     bool found = false;
-    while (std::fscanf(f, "%511s %d %d", k, &a, &b) == 3)
-        if (key == k && (a == 8 || a == 16) && (b == 8 || b == 16)) {  // last entry wins
-            spb64 = a;
-            spb32 = b;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (std::sscanf(line, "%511s %d %d %d %d", k, &a, &b, &na, &nb) != 5) continue;
+        if (key == k && (a == 8 || a == 16) && (b == 8 || b == 16) && (na == 0 || na == 1) &&
+            (nb == 0 || nb == 1)) {  // last entry wins
+            c64.slabs_per_block = a;
+            c32.slabs_per_block = b;
+            c64.stream = na;
+            c32.stream = nb;
             found = true;
         }
+    }
     std::fclose(f);
     return found;
 }
 
-void tune_store(const std::string& key, int spb64, int spb32) {
+void tune_store(const std::string& key, const SpmvConfig& c64, const SpmvConfig& c32) {
     const std::string path = tune_cache_path();
     if (path.empty()) return;
     const size_t slash = path.rfind('/');
@@ -610,25 +616,26 @@ void tune_store(const std::string& key, int spb64, int spb32) {
     }
     std::FILE* f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d\n", key.c_str(), spb64, spb32);
+    std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), c64.slabs_per_block, c32.slabs_per_block,
+                 c64.stream, c32.stream);
     std::fclose(f);
 }
 
 }  // namespace
 
 void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
-    // Slab shapes of the SELL kernels: 2 or 4 slabs per wavefront (one or two groups of
-    // partial sums per workgroup, so results do not depend on the choice), chosen by timing
-    // the PCG SpMV (with its fused dot product) on this mesh's matrix, for FP64 and FP32
-    // values, or taken from the on-disk cache of earlier timings of the same layout on the
-    // same kind of device.  Both candidates keep workgroups inside one sample (kRowAlign is
-    // 16 slabs).
+    // SELL kernel configuration: 2 or 4 slabs per wavefront (one or two groups of partial
+    // sums per workgroup, so results do not depend on the choice), and the matrix values
+    // read with ordinary or nontemporal loads (the latter pay when the values do not fit the
+    // Infinity Cache, and lose when they do, since the solve's back-to-back products then
+    // re-read them from it), chosen by timing the PCG SpMV (with its fused dot product)
+    // back to back on this mesh's matrix, as the solve runs it, for FP64 and FP32 values;
+    // or taken from the on-disk cache of earlier timings of the same layout on the same
+    // kind of device.  Every candidate keeps workgroups inside one sample (kRowAlign is 16
+    // slabs) and gives the same bits.
     if (!A.sell) return;
     const std::string key = tune_key(m);
-    int c64 = 0, c32 = 0;
-    if (tune_lookup(key, c64, c32)) {
-        m->spmv.slabs_per_block = c64;
-        m->spmv32.slabs_per_block = c32;
+    if (tune_lookup(key, m->spmv, m->spmv32)) {
         m->tuned = true;
         m->tuned_from_cache = true;
         return;
@@ -645,10 +652,11 @@ void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
     for (int prec = 0; prec < 2; ++prec) {
         SpmvConfig& target = prec ? m->spmv32 : m->spmv;
         double best = 1e30;
-        int best_spb = target.slabs_per_block;
-        for (int spw : {2, 4}) {
+        SpmvConfig best_c = target;
+        for (int cand = 0; cand < 4; ++cand) {
             SpmvConfig c = target;
-            c.slabs_per_block = 4 * spw;
+            c.slabs_per_block = 4 * (cand % 2 ? 4 : 2);
+            c.stream = cand / 2;
             auto run = [&]() {
                 if (prec) launch_spmv_dot32(A, c, m->p32, m->q32, m->part_pq, chk, smp, s);
                 else launch_spmv_dot64(A, c, m->p, m->q, m->part_pq, chk, smp, s);
@@ -662,16 +670,16 @@ void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
             RAFEM_HIP(hipEventElapsedTime(&ms, e0, e1));
             if (ms < best) {
                 best = ms;
-                best_spb = c.slabs_per_block;
+                best_c = c;
             }
         }
-        target.slabs_per_block = best_spb;
+        target = best_c;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     RAFEM_HIP(hipGetLastError());
     m->tuned = true;
-    tune_store(key, m->spmv.slabs_per_block, m->spmv32.slabs_per_block);
+    tune_store(key, m->spmv, m->spmv32);
 }
 
 }  // namespace rafem

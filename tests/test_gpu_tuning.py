@@ -67,3 +67,34 @@ def test_mixed_tuner_picks_a_candidate_and_caches_it(torch_cuda, tmp_path):
     dp.close()
     assert np.linalg.norm(Tm - T6) <= 1e-8 * np.linalg.norm(T6)
     assert os.path.exists(path)
+
+
+def test_streamed_value_loads_give_the_same_bits(torch_cuda, tmp_path, monkeypatch):
+    """The SpMV configuration read from the cache is used as written, and the nontemporal
+    reads of the matrix values (the autotuner's choice for matrices beyond the Infinity
+    Cache) change no bit of a coupled step, in FP64 and mixed precision."""
+    from paper_2409_13036_amd.sim import DeviceProblem
+    cache = tmp_path / "spmv_tune.txt"
+    monkeypatch.setenv("RAFEM_TUNE_CACHE", str(cache))
+    p = ri.make_problem("hex", 21, 3)
+    dp = DeviceProblem(p)
+    dp.step(1e-12, "mixed")
+    dp.close()
+    key, spb64, spb32, _, _ = cache.read_text().split()
+    out = {}
+    for nt in (0, 1):
+        cache.write_text(f"{key} {spb64} {spb32} {nt} {nt}\n")
+        dp = DeviceProblem(p)
+        states = []
+        for prec in ("fp64", "mixed"):
+            dp.reset()
+            for _ in range(2):
+                dp.step(1e-12, prec)
+            states.append((to_host(dp.T), to_host(dp.V)))
+        st = dp.mesh.stats()
+        assert st.tuned_from_cache == 1
+        assert st.streamed_values == nt and st.streamed_values32 == nt
+        out[nt] = states
+        dp.close()
+    for (Ta, Va), (Tb, Vb) in zip(out[0], out[1]):
+        assert np.array_equal(Ta, Tb) and np.array_equal(Va, Vb)
