@@ -46,7 +46,8 @@
 extern "C" {
 #endif
 
-#define RAFEM_ABI_VERSION 1
+/* Raised whenever a declaration below changes (a struct's layout, a signature). */
+#define RAFEM_ABI_VERSION 2
 
 typedef int32_t rafem_status;
 #define RAFEM_OK            0  /* success */

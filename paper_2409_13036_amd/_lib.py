@@ -178,6 +178,12 @@ for _name in EXPORTS:
     if _name not in ("rafem_last_error", "rafem_abi_version"):
         getattr(_lib, _name).restype = C.c_int32
 
+# the structures above mirror include/rafem.h at this version
+ABI_VERSION = 2
+if _lib.rafem_abi_version() != ABI_VERSION:
+    raise ImportError(f"{_lib._name} has ABI version {_lib.rafem_abi_version()}, the binding "
+                      f"expects {ABI_VERSION}: rebuild the library")
+
 
 def lib():
     return _lib
