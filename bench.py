@@ -240,6 +240,11 @@ def spmv_roofline(mesh, kernel: str, wl_key: str, fp32: bool, warm_us: float,
             "csr_equivalent": {"bytes_per_launch": csr, "achieved_cold": gbs(csr, t_cold),
                                "achieved_warm": gbs(csr, warm_us)},
             "measured_GBs_cold": gbs(traffic, t_cold) if traffic else None,
+            "value_loads": ({"streamed_past_MiB": (int(st.resident_slots32 if fp32 else
+                                                       st.resident_slots) * (4 if fp32 else 8)
+                                                   / 1048576)}
+                            if (st.streamed_values32 if fp32 else st.streamed_values)
+                            else "ordinary"),
             "copy_ceiling": {"GBs": copy_gbs, "frac_of_copy": gbs(nbytes, t_cold) / copy_gbs,
                              "how": "plain device copy of 1 GiB on this box, read + write "
                                     "bytes over the event-timed mean of 10 launches"},

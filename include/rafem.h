@@ -149,8 +149,10 @@ typedef struct {
                                     16-bit reach of their rows: they read 32-bit columns, the
                                     other such slabs 16-bit offsets */
     int32_t streamed_values;     /* 1 if the FP64 SpMV reads its values with nontemporal loads
-                                    (autotuned: matrices beyond the Infinity Cache) */
+                                    past a prefix (autotuned: matrices beyond the Infinity Cache) */
     int32_t streamed_values32;   /* the same for the FP32 SpMV */
+    int64_t resident_slots;      /* that prefix: value slots read with ordinary loads (FP64) */
+    int64_t resident_slots32;    /* the same for the FP32 SpMV */
 } rafem_mesh_stats;
 
 /* Build a mesh on the current device.

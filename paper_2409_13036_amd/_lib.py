@@ -61,7 +61,8 @@ class MeshStats(C.Structure):
                 ("device_driven", C.c_int32), ("tuned_from_cache", C.c_int32),
                 ("device_driven_solves", C.c_int64), ("device_driven_redone", C.c_int64),
                 ("int32_column_slabs", C.c_int64), ("streamed_values", C.c_int32),
-                ("streamed_values32", C.c_int32)]
+                ("streamed_values32", C.c_int32), ("resident_slots", C.c_int64),
+                ("resident_slots32", C.c_int64)]
 
 
 class SolveOpts(C.Structure):

@@ -826,6 +826,8 @@ rafem_status rafem_mesh_get_stats(rafem_mesh m, rafem_mesh_stats* out) {
         out->int32_column_slabs = m->int32_slabs;
         out->streamed_values = m->spmv.stream;
         out->streamed_values32 = m->spmv32.stream;
+        out->resident_slots = m->spmv.stream ? m->spmv.resident : 0;
+        out->resident_slots32 = m->spmv32.stream ? m->spmv32.resident : 0;
         return RAFEM_OK;
     });
 }

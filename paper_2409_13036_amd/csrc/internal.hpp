@@ -101,7 +101,8 @@ struct SpmvConfig {
     int lanes;            // CSR kernels: lanes per row (2, 4, 8 or 16)
     int rows_per_block;   // CSR kernels: multiple of 256 / lanes
     int slabs_per_block;  // SELL kernels: 64-row slabs per 256-thread workgroup (multiple of 4)
-    int stream = 0;       // SELL kernels: 1 = matrix values read with nontemporal loads
+    int stream = 0;       // SELL kernels: 1 = matrix values read with nontemporal loads...
+    int resident = 0;     // ...past this many value slots (the prefix with ordinary loads)
 };
 
 SpmvConfig choose_spmv_config(int64_t n, int64_t nnz);

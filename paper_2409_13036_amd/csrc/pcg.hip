@@ -194,6 +194,8 @@ struct RowArgs {
     int rows_per_block;   // CSR: rows per workgroup
     int slabs_per_block;  // SELL: slabs per workgroup
     int outer_mode;
+    int resident;         // SELL, streaming kernels: slabs starting below this value slot
+                          // read their values with ordinary loads, the others stream them
 };
 
 // Per-row epilogue of every row mode; acc receives this lane's dot-product terms.
@@ -372,6 +374,18 @@ __device__ __forceinline__ void store_group_partials(double (&v)[kMaxGroups][K],
     }
 }
 
+// One row of a slab, by the slab's column kind.
+template <typename T, int COLS, bool NT>
+__device__ __forceinline__ T slab_row(const RowArgs<T>& a, int so, int base, int lane, int r,
+                                      int width) {
+    if (so >= 0)
+        return sell_row_shared<T, NT>(a.soff + so, a.val + base + lane, a.x + r, width);
+    if (COLS == 1 || (COLS == 2 && so == -1))
+        return sell_row<T, int16_t, NT>(a.sdel + base + lane, a.val + base + lane,
+                                        a.x + min(r, a.n - 1), width);
+    return sell_row<T, int, NT>(a.scol + base + lane, a.val + base + lane, a.x, width);
+}
+
 // Column kinds of the slabs without a shared offset list: COLS 0: 32-bit columns, 1: 16-bit
 // offsets to the row, 2: either, per slab (sofs -1 / -2).  Separate instantiations keep the
 // common layouts' kernels free of the third path (its registers lowered their occupancy).
@@ -396,13 +410,10 @@ __device__ __forceinline__ void sell_rows(const RowArgs<T>& a) {
         const int so = i == 0 ? so0 : a.sofs[sl];
         const int r = sl * WAVE + lane;
         T sum;
-        if (so >= 0)
-            sum = sell_row_shared<T, NT>(a.soff + so, a.val + base + lane, a.x + r, width);
-        else if (COLS == 1 || (COLS == 2 && so == -1))
-            sum = sell_row<T, int16_t, NT>(a.sdel + base + lane, a.val + base + lane,
-                                           a.x + min(r, a.n - 1), width);
+        if (NT && base >= a.resident)
+            sum = slab_row<T, COLS, true>(a, so, base, lane, r, width);
         else
-            sum = sell_row<T, int, NT>(a.scol + base + lane, a.val + base + lane, a.x, width);
+            sum = slab_row<T, COLS, false>(a, so, base, lane, r, width);
         if (r < a.n) row_epilogue<T, MODE>(a, r, sum, acc[i / 2]);
     }
     if constexpr (MODE != ROW_PLAIN) {
@@ -431,7 +442,9 @@ __global__ __launch_bounds__(WG) void k_sell_wide(RowArgs<T> a) {
     sell_rows<T, MODE, 2, false>(a);
 }
 
-// The same with the matrix values read by nontemporal loads (chosen by the autotuner).
+// The same with the matrix values read by nontemporal loads past the first `resident`
+// value slots (chosen by the autotuner): the prefix can stay in the Infinity Cache from one
+// product to the next while the rest streams past it.
 template <typename T, int MODE, bool DELTA>
 __global__ __launch_bounds__(WG) void k_sell_nt(RowArgs<T> a) {
     sell_rows<T, MODE, DELTA ? 1 : 0, true>(a);
@@ -832,7 +845,7 @@ GridInfo launch_rows(const Mat& A, const T* vals, const SpmvConfig& c, const T* 
     RowArgs<T> a{A.rp,   A.ci, A.sptr, A.scol,   A.sdel, A.sofs, A.soff,
                  vals,   x,    y,      b,        dinv,   pout,   partials,
                  st,     smp,  A.n,    A.nslabs, c.rows_per_block, c.slabs_per_block,
-                 outer_mode};
+                 outer_mode, c.resident};
     GridInfo g;
     if (A.sell) {
         const int nblk = blocks_for(A.nslabs, c.slabs_per_block);

@@ -557,10 +557,10 @@ bool dd_finish(rafem_mesh m, const DdRecord& r, const SolveOpts& o, rafem_solve_
 namespace {
 
 // On-disk cache of the tuned SpMV configurations: one line per (device, layout) key,
-// "<key> <slabs per block FP64> <slabs per block FP32> <streamed FP64> <streamed FP32>", in
-// the file named by RAFEM_TUNE_CACHE, else $HOME/.cache/rafem/spmv_tune.txt.  Unreadable or
-// unwritable files, and lines of another form, are ignored (the configurations are then
-// timed).
+// "<key> <slabs per block FP64> <slabs per block FP32> <streamed FP64> <streamed FP32>
+// <resident slots FP64> <resident slots FP32>", in the file named by RAFEM_TUNE_CACHE, else
+// $HOME/.cache/rafem/spmv_tune.txt.  Unreadable or unwritable files, and lines of another
+// form, are ignored (the configurations are then timed).
 std::string tune_cache_path() {
     if (const char* p = std::getenv("RAFEM_TUNE_CACHE")) return p;
     if (const char* h = std::getenv("HOME")) return std::string(h) + "/.cache/rafem/spmv_tune.txt";
@@ -586,16 +586,19 @@ bool tune_lookup(const std::string& key, SpmvConfig& c64, SpmvConfig& c32) {
     std::FILE* f = std::fopen(path.c_str(), "r");
     if (!f) return false;
     char line[640], k[512];
-    int a = 0, b = 0, na = 0, nb = 0;
+    int a = 0, b = 0, na = 0, nb = 0, ra = 0, rb = 0;
     bool found = false;
     while (std::fgets(line, sizeof(line), f)) {
-        if (std::sscanf(line, "%511s %d %d %d %d", k, &a, &b, &na, &nb) != 5) continue;
+        if (std::sscanf(line, "%511s %d %d %d %d %d %d", k, &a, &b, &na, &nb, &ra, &rb) != 7)
+            continue;
         if (key == k && (a == 8 || a == 16) && (b == 8 || b == 16) && (na == 0 || na == 1) &&
-            (nb == 0 || nb == 1)) {  // last entry wins
+            (nb == 0 || nb == 1) && ra >= 0 && rb >= 0) {  // last entry wins
             c64.slabs_per_block = a;
             c32.slabs_per_block = b;
             c64.stream = na;
             c32.stream = nb;
+            c64.resident = ra;
+            c32.resident = rb;
             found = true;
         }
     }
@@ -616,8 +619,8 @@ void tune_store(const std::string& key, const SpmvConfig& c64, const SpmvConfig&
     }
     std::FILE* f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), c64.slabs_per_block, c32.slabs_per_block,
-                 c64.stream, c32.stream);
+    std::fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), c64.slabs_per_block,
+                 c32.slabs_per_block, c64.stream, c32.stream, c64.resident, c32.resident);
     std::fclose(f);
 }
 
@@ -626,13 +629,15 @@ void tune_store(const std::string& key, const SpmvConfig& c64, const SpmvConfig&
 void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
     // SELL kernel configuration: 2 or 4 slabs per wavefront (one or two groups of partial
     // sums per workgroup, so results do not depend on the choice), and the matrix values
-    // read with ordinary or nontemporal loads (the latter pay when the values do not fit the
-    // Infinity Cache, and lose when they do, since the solve's back-to-back products then
-    // re-read them from it), chosen by timing the PCG SpMV (with its fused dot product)
-    // back to back on this mesh's matrix, as the solve runs it, for FP64 and FP32 values;
-    // or taken from the on-disk cache of earlier timings of the same layout on the same
-    // kind of device.  Every candidate keeps workgroups inside one sample (kRowAlign is 16
-    // slabs) and gives the same bits.
+    // read with ordinary loads, or with nontemporal loads past a prefix of 0 or 96 MiB read
+    // with ordinary ones (streaming pays when the values do not fit the Infinity Cache and
+    // loses when they do, since the solve's products then re-read them from it; a prefix
+    // can stay there while the rest streams past), chosen by timing the PCG SpMV (with its
+    // fused dot product) on this mesh's matrix with a PCG iteration's vector traffic
+    // between the products, as in the solve, for FP64 and FP32 values; or taken from the
+    // on-disk cache of earlier timings of the same layout on the same kind of device.
+    // Every candidate keeps workgroups inside one sample (kRowAlign is 16 slabs) and gives
+    // the same bits.
     if (!A.sell) return;
     const std::string key = tune_key(m);
     if (tune_lookup(key, m->spmv, m->spmv32)) {
@@ -643,9 +648,9 @@ void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
     const int S = m->S;
     Samples smp{S, m->row_off, m->row_tab};
     PcgState* chk = m->st + 2 * S;
-    hipEvent_t e0, e1;
-    RAFEM_HIP(hipEventCreate(&e0));
-    RAFEM_HIP(hipEventCreate(&e1));
+    constexpr int kTuneReps = 5;
+    hipEvent_t ev[2 * kTuneReps];
+    for (hipEvent_t& e : ev) RAFEM_HIP(hipEventCreate(&e));
     launch_fill(m->p, m->n, 0.0, s);
     launch_fill32(m->p32, m->n, 0.0f, s);
     launch_state_init(chk, S, 0.0, 0, nullptr, s);
@@ -653,21 +658,49 @@ void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
         SpmvConfig& target = prec ? m->spmv32 : m->spmv;
         double best = 1e30;
         SpmvConfig best_c = target;
-        for (int cand = 0; cand < 4; ++cand) {
+        // value-load candidates: ordinary; streamed past a prefix of 0 or 96 MiB (a prefix
+        // that holds the whole matrix is the ordinary candidate again)
+        const int64_t value_bytes = m->sell_nnz * (prec ? 4 : 8);
+        std::vector<std::pair<int, int>> loads{{0, 0}};
+        for (int64_t mib : {0, 96})
+            if (mib * 1048576 < value_bytes)
+                loads.push_back({1, (int)(mib * 1048576 / (prec ? 4 : 8))});
+        for (int cand = 0; cand < 2 * (int)loads.size(); ++cand) {
             SpmvConfig c = target;
             c.slabs_per_block = 4 * (cand % 2 ? 4 : 2);
-            c.stream = cand / 2;
-            auto run = [&]() {
-                if (prec) launch_spmv_dot32(A, c, m->p32, m->q32, m->part_pq, chk, smp, s);
-                else launch_spmv_dot64(A, c, m->p, m->q, m->part_pq, chk, smp, s);
+            c.stream = loads[cand / 2].first;
+            c.resident = loads[cand / 2].second;
+            auto run = [&](hipEvent_t a0, hipEvent_t a1) {
+                if (prec) launch_spmv_dot32(A, c, m->p32, m->q32, m->part_pq, chk, smp, s, a0, a1);
+                else launch_spmv_dot64(A, c, m->p, m->q, m->part_pq, chk, smp, s, a0, a1);
             };
-            for (int w = 0; w < 2; ++w) run();
-            RAFEM_HIP(hipEventRecord(e0, s));
-            for (int r = 0; r < 5; ++r) run();
-            RAFEM_HIP(hipEventRecord(e1, s));
-            RAFEM_HIP(hipEventSynchronize(e1));
+            // between products, the vector traffic of a PCG iteration (four copies of a
+            // vector: 8 words per row against the iteration's 10), which competes with the
+            // matrix for the Infinity Cache as in the solve; only the products are timed
+            auto sweep = [&]() {
+                const size_t bytes = (size_t)m->n * (prec ? 4 : 8);
+                void* v0 = prec ? (void*)m->r32 : (void*)m->r;
+                void* v1 = prec ? (void*)m->q32 : (void*)m->q;
+                for (int k = 0; k < 2; ++k) {
+                    RAFEM_HIP(hipMemcpyAsync(v1, v0, bytes, hipMemcpyDeviceToDevice, s));
+                    RAFEM_HIP(hipMemcpyAsync(v0, v1, bytes, hipMemcpyDeviceToDevice, s));
+                }
+            };
+            for (int w = 0; w < 2; ++w) {
+                run(nullptr, nullptr);
+                sweep();
+            }
+            for (int r = 0; r < kTuneReps; ++r) {
+                run(ev[2 * r], ev[2 * r + 1]);
+                sweep();
+            }
+            RAFEM_HIP(hipEventSynchronize(ev[2 * kTuneReps - 1]));
             float ms = 0.f;
-            RAFEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            for (int r = 0; r < kTuneReps; ++r) {
+                float one = 0.f;
+                RAFEM_HIP(hipEventElapsedTime(&one, ev[2 * r], ev[2 * r + 1]));
+                ms += one;
+            }
             if (ms < best) {
                 best = ms;
                 best_c = c;
@@ -675,8 +708,7 @@ void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
         }
         target = best_c;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     RAFEM_HIP(hipGetLastError());
     m->tuned = true;
     tune_store(key, m->spmv, m->spmv32);

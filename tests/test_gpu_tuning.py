@@ -72,18 +72,20 @@ def test_mixed_tuner_picks_a_candidate_and_caches_it(torch_cuda, tmp_path):
 def test_streamed_value_loads_give_the_same_bits(torch_cuda, tmp_path, monkeypatch):
     """The SpMV configuration read from the cache is used as written, and the nontemporal
     reads of the matrix values (the autotuner's choice for matrices beyond the Infinity
-    Cache) change no bit of a coupled step, in FP64 and mixed precision."""
+    Cache), whole or past a prefix read with ordinary loads, change no bit of a coupled
+    step, in FP64 and mixed precision."""
     from paper_2409_13036_amd.sim import DeviceProblem
     cache = tmp_path / "spmv_tune.txt"
     monkeypatch.setenv("RAFEM_TUNE_CACHE", str(cache))
     p = ri.make_problem("hex", 21, 3)
     dp = DeviceProblem(p)
     dp.step(1e-12, "mixed")
+    half = int(dp.mesh.stats().value_slots) // 2
     dp.close()
-    key, spb64, spb32, _, _ = cache.read_text().split()
+    key, spb64, spb32 = cache.read_text().split()[:3]
     out = {}
-    for nt in (0, 1):
-        cache.write_text(f"{key} {spb64} {spb32} {nt} {nt}\n")
+    for nt, res in ((0, 0), (1, 0), (1, half)):
+        cache.write_text(f"{key} {spb64} {spb32} {nt} {nt} {res} {res}\n")
         dp = DeviceProblem(p)
         states = []
         for prec in ("fp64", "mixed"):
@@ -94,7 +96,10 @@ def test_streamed_value_loads_give_the_same_bits(torch_cuda, tmp_path, monkeypat
         st = dp.mesh.stats()
         assert st.tuned_from_cache == 1
         assert st.streamed_values == nt and st.streamed_values32 == nt
-        out[nt] = states
+        assert st.resident_slots == res and st.resident_slots32 == res
+        out[(nt, res)] = states
         dp.close()
-    for (Ta, Va), (Tb, Vb) in zip(out[0], out[1]):
-        assert np.array_equal(Ta, Tb) and np.array_equal(Va, Vb)
+    ref = out[(0, 0)]
+    for key2, states in out.items():
+        for (Ta, Va), (Tb, Vb) in zip(ref, states):
+            assert np.array_equal(Ta, Tb) and np.array_equal(Va, Vb), key2
