@@ -94,7 +94,7 @@ _COPY_GBS = None
 
 
 def copy_ceiling() -> float:
-    """On-box device copy bandwidth (GB/s): a plain copy of 1 GiB (torch's copy kernel),
+    """Device copy bandwidth of this GPU (GB/s): a plain copy of 1 GiB (torch's copy kernel),
     read + write bytes over the mean of 10 event-timed launches after 3 untimed ones;
     measured once per process."""
     global _COPY_GBS
@@ -246,7 +246,7 @@ def spmv_roofline(mesh, kernel: str, wl_key: str, fp32: bool, warm_us: float,
                             if (st.streamed_values32 if fp32 else st.streamed_values)
                             else "ordinary"),
             "copy_ceiling": {"GBs": copy_gbs, "frac_of_copy": gbs(nbytes, t_cold) / copy_gbs,
-                             "how": "plain device copy of 1 GiB on this box, read + write "
+                             "how": "plain device copy of 1 GiB on this GPU, read + write "
                                     "bytes over the event-timed mean of 10 launches"},
             "note": ("achieved = bytes_per_launch (the slab layout's values with padding, its "
                      "column data, x once, y once) / mean launch time with a cold Infinity "
