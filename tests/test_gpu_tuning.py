@@ -69,15 +69,35 @@ def test_mixed_tuner_picks_a_candidate_and_caches_it(torch_cuda, tmp_path):
     assert os.path.exists(path)
 
 
-def test_streamed_value_loads_give_the_same_bits(torch_cuda, tmp_path, monkeypatch):
+def _far_swaps(p, dist):
+    from paper_2409_13036_amd.sim import reorder_nodes
+    order = np.arange(p.n_nodes)
+    a = np.sort(np.random.default_rng(7).choice(np.arange(200, p.n_nodes - dist), 6,
+                                                replace=False))
+    order[a], order[a + dist] = a + dist, a
+    return reorder_nodes(p, order)
+
+
+def _shuffled(p):
+    from paper_2409_13036_amd.sim import reorder_nodes
+    return reorder_nodes(p, np.random.default_rng(5).permutation(p.n_nodes))
+
+
+@pytest.mark.parametrize("mesh", ["hex21", "tet13", "hex41-shuffled", "hex41-far-swaps"])
+def test_streamed_value_loads_give_the_same_bits(torch_cuda, tmp_path, monkeypatch, mesh):
     """The SpMV configuration read from the cache is used as written, and the nontemporal
     reads of the matrix values (the autotuner's choice for matrices beyond the Infinity
     Cache), whole or past a prefix read with ordinary loads, change no bit of a coupled
-    step, in FP64 and mixed precision."""
+    step, in FP64 and mixed precision, on every slab kind: shared offset lists and 16-bit
+    offsets (hex21, tet13), 32-bit columns (shuffled), and both widths in one layout (nodes
+    swapped 40,000 positions apart)."""
     from paper_2409_13036_amd.sim import DeviceProblem
     cache = tmp_path / "spmv_tune.txt"
     monkeypatch.setenv("RAFEM_TUNE_CACHE", str(cache))
-    p = ri.make_problem("hex", 21, 3)
+    p = {"hex21": lambda: ri.make_problem("hex", 21, 3),
+         "tet13": lambda: ri.make_problem("tet", 13, 3),
+         "hex41-shuffled": lambda: _shuffled(ri.make_problem("hex", 41, 3)),
+         "hex41-far-swaps": lambda: _far_swaps(ri.make_problem("hex", 41, 3), 40000)}[mesh]()
     dp = DeviceProblem(p)
     dp.step(1e-12, "mixed")
     half = int(dp.mesh.stats().value_slots) // 2
@@ -94,6 +114,10 @@ def test_streamed_value_loads_give_the_same_bits(torch_cuda, tmp_path, monkeypat
                 dp.step(1e-12, prec)
             states.append((to_host(dp.T), to_host(dp.V)))
         st = dp.mesh.stats()
+        if mesh == "hex41-far-swaps":
+            assert st.int16_columns == 1 and st.int32_column_slabs > 0
+        if mesh == "hex41-shuffled":
+            assert st.int16_columns == 0
         assert st.tuned_from_cache == 1
         assert st.streamed_values == nt and st.streamed_values32 == nt
         assert st.resident_slots == res and st.resident_slots32 == res
