@@ -293,6 +293,42 @@ rafem_status rafem_solve(rafem_mesh mesh, const int32_t* row_ptr_d, const int32_
                          double* x_d, const rafem_solve_opts* opts, rafem_solve_info* info,
                          void* stream);
 
+/* The result of rafem_solve_enqueue, written to device memory by its last kernel. */
+typedef struct {
+    int32_t status;      /* RAFEM_OK; RAFEM_E_NOCONV when the enqueued budget ran out first;
+                            RAFEM_E_BREAKDOWN */
+    int32_t iters;       /* PCG iterations (FP64) or total inner iterations (MIXED) */
+    int32_t outer;       /* refinement steps (MIXED), 0 for FP64 */
+    int32_t pad;
+    double  relres_true; /* ||b - A x||_2 / ||b||_2 of the returned x, recomputed in FP64 */
+} rafem_device_info;
+
+/* rafem_solve with its result kept on the device (Sec. III-A: the solution stays on the
+ * device; here the solver's report too): the whole solve is enqueued on `stream` at once
+ * and the call returns without synchronising with the host, so that a caller can chain
+ * further work, or capture the solve in a graph, and read info_d when it needs it.  With no
+ * host poll inside, the budget is fixed beforehand:
+ *   FP64:  `iterations` PCG iterations;
+ *   MIXED: `refinements` refinement steps, each with an inner solve of at most `iterations`
+ *          FP32 iterations, then the residual check of the last one.
+ * Iterations and refinements enqueued past convergence exit at their first instruction
+ * (each still costs a launch of a few microseconds), so budgets near the expected counts
+ * are cheapest.  While the budget suffices the iterates are those of rafem_solve with the
+ * same options; a MIXED solve whose refinement stagnates is not handed to FP64 PCG as
+ * rafem_solve does, it ends with RAFEM_E_NOCONV.
+ *   iterations   [1, 100000]
+ *   refinements  MIXED: [1, 14]; ignored for FP64
+ *   info_d       device, receives the rafem_device_info (stream-ordered)
+ * Other arguments as for rafem_solve.  The first call on a handle allocates the solver-state
+ * logs it shares with rafem_mesh_set_device_driven.  Single-mesh handles only (E_ARG on a
+ * batch).  Argument errors are returned before anything is enqueued; numerical outcomes
+ * only reach info_d. */
+rafem_status rafem_solve_enqueue(rafem_mesh mesh, const int32_t* row_ptr_d,
+                                 const int32_t* col_idx_d, const double* vals_d,
+                                 const float* vals32_d, const double* b_d, double* x_d,
+                                 const rafem_solve_opts* opts, int32_t iterations,
+                                 int32_t refinements, rafem_device_info* info_d, void* stream);
+
 /* Allocation-free variant of rafem_solve, for callers that cannot allocate device memory
  * (tight serving loops, harnesses that forbid hipMalloc): no mesh handle; the solver's
  * workspace (r, p, A p, D^-1, their FP32 twins, partial sums, solver states) lives in one

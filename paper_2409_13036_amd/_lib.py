@@ -41,7 +41,7 @@ EXPORTS = ("rafem_last_error", "rafem_abi_version", "rafem_csr_structure", "rafe
            "rafem_sample_info", "rafem_spmv_timing", "rafem_step_pc", "rafem_mono_jacobian",
            "rafem_mono_solve", "rafem_step_mono", "rafem_rcm_order", "rafem_regions_enable",
            "rafem_regions_read", "rafem_degree_sort", "rafem_spmv_step",
-           "rafem_solve_noalloc", "rafem_mesh_set_device_driven")
+           "rafem_solve_noalloc", "rafem_mesh_set_device_driven", "rafem_solve_enqueue")
 
 
 class RafemError(RuntimeError):
@@ -145,6 +145,8 @@ _lib.rafem_mesh_destroy.argtypes = [_p]
 _lib.rafem_mesh_get_stats.argtypes = [_p, C.POINTER(MeshStats)]
 _lib.rafem_assemble_csr.argtypes = [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
 _lib.rafem_solve.argtypes = [_p, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _p]
+_lib.rafem_solve_enqueue.argtypes = [_p, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts), _i32, _i32,
+                                     _p, _p]
 _lib.rafem_solve_adjoint.argtypes = [_p, _p, _p, _p, _p, _p, _p, C.POINTER(SolveOpts),
                                      C.POINTER(SolveInfo), _p]
 _lib.rafem_spmv.argtypes = [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
@@ -478,6 +480,51 @@ def solve(mesh: Mesh, row_ptr, col_idx, vals, b, x, *, vals32=None, tol=1e-10, p
     if check:
         _check(st)
     return info.as_dict()
+
+
+class DeviceInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("outer", C.c_int32),
+                ("pad", C.c_int32), ("relres_true", C.c_double)]
+
+
+def device_info_buffer(device=None):
+    """A device buffer for rafem_solve_enqueue's report (uint8 tensor of its size)."""
+    torch = _torch()
+    return torch.zeros(C.sizeof(DeviceInfo), dtype=torch.uint8,
+                       device=device if device is not None else "cuda")
+
+
+def read_device_info(buf) -> dict:
+    """The report in a device_info_buffer, read back (a stream-ordered copy)."""
+    raw = bytes(buf.cpu().numpy().tobytes())
+    d = DeviceInfo.from_buffer_copy(raw)
+    return {"status": d.status, "iters": d.iters, "outer": d.outer, "relres_true": d.relres_true}
+
+
+def solve_enqueue(mesh: Mesh, row_ptr, col_idx, vals, b, x, info_buf, *, iterations: int,
+                  refinements: int = 1, vals32=None, tol=1e-10, precision="fp64", maxit=0,
+                  inner_tol=0.0, restart_inner=0, stream=None, check=True):
+    """rafem_solve_enqueue: the whole solve enqueued with fixed budgets and its report
+    written to info_buf (device_info_buffer); no host synchronisation.  Returns the call's
+    status (argument errors only)."""
+    torch = _torch()
+    n = mesh.n_nodes
+    row_ptr = _dev(row_ptr, torch.int32, n + 1, "row_ptr")
+    col_idx = _dev(col_idx, torch.int32, None, "col_idx")
+    vals = _dev(vals, torch.float64, col_idx.numel(), "vals")
+    vals32 = _dev(vals32, torch.float32, col_idx.numel(), "vals32", allow_none=True)
+    b = _dev(b, torch.float64, n, "b")
+    x = _dev(x, torch.float64, n, "x")
+    if not (info_buf.is_cuda and info_buf.dtype == torch.uint8
+            and info_buf.numel() >= C.sizeof(DeviceInfo) and info_buf.is_contiguous()):
+        raise ValueError("info_buf must be a contiguous device uint8 tensor from device_info_buffer")
+    opts = make_opts(tol, maxit, precision, inner_tol, 0, 0, restart_inner)
+    st = _lib.rafem_solve_enqueue(mesh.handle, _ptr(row_ptr), _ptr(col_idx), _ptr(vals),
+                                  _ptr(vals32), _ptr(b), _ptr(x), C.byref(opts), int(iterations),
+                                  int(refinements), _ptr(info_buf), _stream(stream))
+    if check:
+        _check(st)
+    return st
 
 
 def solve_noalloc(row_ptr, col_idx, vals, b, x, *, vals32=None, tol=1e-10, precision="fp64",

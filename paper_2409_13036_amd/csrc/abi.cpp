@@ -881,6 +881,28 @@ rafem_status rafem_solve(rafem_mesh m, const int32_t* row_ptr_d, const int32_t* 
     return rc;
 }
 
+rafem_status rafem_solve_enqueue(rafem_mesh m, const int32_t* row_ptr_d,
+                                 const int32_t* col_idx_d, const double* vals_d,
+                                 const float* vals32_d, const double* b_d, double* x_d,
+                                 const rafem_solve_opts* opts, int32_t iterations,
+                                 int32_t refinements, rafem_device_info* info_d, void* stream) {
+    return guard([&]() -> rafem_status {
+        check_device(m);
+        require(m->S == 1, "rafem_solve_enqueue runs on single-mesh handles");
+        require(row_ptr_d && col_idx_d && vals_d && b_d && x_d && info_d,
+                "NULL matrix, vector or info argument");
+        SolveOpts o = resolve_opts(opts, 1e-10);
+        require(o.precision != RAFEM_MIXED || vals32_d != nullptr, "MIXED precision needs vals32");
+        require(iterations >= 1 && iterations <= 100000, "iterations must be in [1, 100000]");
+        require(o.precision != RAFEM_MIXED || (refinements >= 1 && refinements < kDdMaxRounds),
+                "refinements must be in [1, 14]");
+        hipStream_t s = (hipStream_t)stream;
+        const Mat A = csr_matrix(m, row_ptr_d, col_idx_d, vals_d, vals32_d);
+        solve_enqueue(m, A, whole_mesh(m), b_d, x_d, o, iterations, refinements, info_d, s);
+        return RAFEM_OK;
+    });
+}
+
 rafem_status rafem_solve_adjoint(rafem_mesh m, const int32_t* row_ptr_d, const int32_t* col_idx_d,
                                  const double* vals_d, const float* vals32_d, const double* g_d,
                                  double* lambda_d, const rafem_solve_opts* opts,

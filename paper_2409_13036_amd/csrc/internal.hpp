@@ -225,6 +225,13 @@ void launch_inner_start(int n, const double* r64, const PcgState* outer, float* 
 // x64 += d32 / scale (samples whose refinement is not finished).
 void launch_refine_update(int n, double* x, const float* d32, const PcgState* outer,
                           const Samples& smp, hipStream_t s);
+// The device-side report of rafem_solve_enqueue (one sample): cleared; inner iterations
+// added after each refinement; completed from the final state and the true residual
+// (chk: rr, bb of b - A x).
+void launch_info_begin(rafem_device_info* info, hipStream_t s);
+void launch_info_add_inner(const PcgState* inner, rafem_device_info* info, hipStream_t s);
+void launch_info_finish(const PcgState* st, const PcgState* chk, int mixed,
+                        rafem_device_info* info, hipStream_t s);
 
 // Assembly.
 void launch_fill(double* v, int64_t n, double value, hipStream_t s);

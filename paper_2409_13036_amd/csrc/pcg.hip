@@ -812,6 +812,33 @@ __global__ __launch_bounds__(WG) void k_refine_update(int n, double* __restrict_
     }
 }
 
+// The report of a solve enqueued without host synchronisation (one sample): cleared first,
+// the inner iterations of each refinement added after it, completed from the final state
+// (the solve's, or the refinement's) and the true residual of the returned x.
+__global__ void k_info_begin(rafem_device_info* info) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        info->status = RAFEM_E_NOCONV;
+        info->iters = 0;
+        info->outer = 0;
+        info->pad = 0;
+        info->relres_true = 0.0;
+    }
+}
+
+__global__ void k_info_add_inner(const PcgState* inner, rafem_device_info* info) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) info->iters += inner->iters;
+}
+
+__global__ void k_info_finish(const PcgState* st, const PcgState* chk, int mixed,
+                              rafem_device_info* info) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    info->status = st->done ? st->status : RAFEM_E_NOCONV;
+    if (mixed) info->outer = st->iters;
+    else info->iters = st->iters;
+    const double bb = chk->bb;
+    info->relres_true = bb > 0.0 ? sqrt(chk->rr / bb) : sqrt(chk->rr);
+}
+
 inline int grid1(int64_t n) { return (int)((n + WG - 1) / WG); }
 inline int vec_blocks(int n) { return (n + kVecRowsPerBlock - 1) / kVecRowsPerBlock; }
 
@@ -1025,6 +1052,19 @@ void launch_refine_update(int n, double* x, const float* d32, const PcgState* ou
                           const Samples& smp, hipStream_t s) {
     hipLaunchKernelGGL(k_refine_update, dim3(vec_blocks(n)), dim3(WG), 0, s, n, x, d32, outer,
                        smp);
+}
+
+void launch_info_begin(rafem_device_info* info, hipStream_t s) {
+    hipLaunchKernelGGL(k_info_begin, dim3(1), dim3(64), 0, s, info);
+}
+
+void launch_info_add_inner(const PcgState* inner, rafem_device_info* info, hipStream_t s) {
+    hipLaunchKernelGGL(k_info_add_inner, dim3(1), dim3(64), 0, s, inner, info);
+}
+
+void launch_info_finish(const PcgState* st, const PcgState* chk, int mixed,
+                        rafem_device_info* info, hipStream_t s) {
+    hipLaunchKernelGGL(k_info_finish, dim3(1), dim3(64), 0, s, st, chk, mixed, info);
 }
 
 }  // namespace rafem

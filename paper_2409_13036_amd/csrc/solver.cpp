@@ -415,6 +415,49 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
     return worst_status(ho, S);
 }
 
+void solve_enqueue(rafem_mesh m, const Mat& A, const Samples& smp, const double* b, double* x,
+                   const SolveOpts& o, int iterations, int refinements,
+                   rafem_device_info* info_d, hipStream_t s) {
+    // the sequence of pcg64 / pcg_mixed with the host polls taken out: kernels of a solve,
+    // inner solve or refinement that has finished exit at their first instruction
+    launch_info_begin(info_d, s);
+    PcgState* chk = m->st + 2;
+    if (o.precision != RAFEM_MIXED) {
+        PcgState* st = m->st;
+        int* itb = m->itb;
+        launch_state_init(st, 1, o.tol, iterations, itb, s);
+        launch_diag_inv(A, m->dinv, nullptr, st, s);
+        launch_pcg_start(A, m->spmv, b, x, m->dinv, m->r, m->p, m->partials, st, smp, s);
+        const Iter64 iter{m, &A, &m->spmv, m->dinv, x, st, smp, itb};
+        enqueue(iterations, iter, nullptr, itb, nullptr, s);
+        launch_state_init(chk, 1, 0.0, 0, nullptr, s);
+        launch_residual64(A, m->spmv, b, x, m->r, m->partials, chk, smp, 0, s);
+        launch_info_finish(st, chk, 0, info_d, s);
+        check_launch();
+        return;
+    }
+    PcgState* inner = m->st;
+    PcgState* outer = m->st + 1;
+    int* itb = m->itb + 1;
+    const int n = A.n;
+    launch_state_init(outer, 1, o.tol, refinements, nullptr, s);
+    launch_diag_inv(A, m->dinv, m->dinv32, outer, s);
+    const Iter32 iter{m, &A, &m->spmv32, m->dinv32, inner, smp, itb};
+    for (int j = 0;; ++j) {
+        launch_residual64(A, m->spmv, b, x, m->r64, m->partials, outer, smp, 1, s);
+        if (j == refinements) break;  // the residual check of the last refinement
+        const int cont = (j > 0 && !o.restart_inner) ? 1 : 0;
+        launch_inner_start(n, m->r64, outer, m->r32, m->d32, m->p32, m->dinv32, o.inner_tol,
+                           o.maxit, m->partials, inner, smp, cont, s);
+        launch_state_init(nullptr, 0, 0.0, 0, itb, s);
+        enqueue(iterations, iter, nullptr, itb, nullptr, s);
+        launch_refine_update(n, x, m->d32, outer, smp, s);
+        launch_info_add_inner(inner, info_d, s);
+    }
+    launch_info_finish(outer, outer, 1, info_d, s);
+    check_launch();
+}
+
 bool dd_ready(rafem_mesh m, const SolveOpts& o, const std::vector<int>* hints) {
     if (!m->dd_on || m->prof_on || !hints || hints->empty() || o.poll_every > 0) return false;
     const int rounds = o.precision == RAFEM_MIXED ? (int)hints->size() + 1 : 1;

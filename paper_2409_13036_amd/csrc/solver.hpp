@@ -35,6 +35,14 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
                        const float* dinv32, const double* b, double* x, const SolveOpts& o,
                        rafem_solve_info* info, hipStream_t s, std::vector<int>* hints);
 
+// A whole solve of one system enqueued with fixed budgets and no host synchronisation
+// (rafem_solve_enqueue): FP64, `iterations` PCG iterations; mixed, `refinements` refinements
+// of at most `iterations` inner iterations each and the residual check of the last; the
+// report written to info_d.  A is a CSR matrix (D^-1 computed from its diagonal).
+void solve_enqueue(rafem_mesh m, const Mat& A, const Samples& smp, const double* b, double* x,
+                   const SolveOpts& o, int iterations, int refinements,
+                   rafem_device_info* info_d, hipStream_t s);
+
 // Pick the SELL slab shape of the FP64 and FP32 SpMV by timing them on A (sets m->tuned).
 void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s);
 
