@@ -191,7 +191,9 @@ rafem_status rafem_mesh_sample_layout(rafem_mesh mesh, int64_t* node_off, int64_
                                       int64_t* dir_off);
 
 /* Use (nonzero) or not HIP graphs for the PCG iteration chunks of this mesh's steps.  On by
- * default for batch handles.  Graphs are not used while SpMV profiling is enabled. */
+ * default for batch handles, and for rafem_step's solves on single meshes of at most 262,144
+ * nodes, whose iterations are launch-bound (a call here replaces that rule).  Graphs are not
+ * used while SpMV profiling is enabled; they never change a result. */
 rafem_status rafem_mesh_set_graphs(rafem_mesh mesh, int32_t enable);
 
 /* Device-driven solves (on by default for batch handles, off for single meshes): each of

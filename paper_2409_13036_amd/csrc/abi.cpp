@@ -533,6 +533,8 @@ rafem_mesh build_mesh(int64_t n_nodes, int64_t n_elems, int32_t npe, const doubl
             m->dir_off = dir_off;
             m->sample_info.assign(S_, rafem_step_info{});
             m->use_graphs = S_ > 1;
+            // a small mesh's iterations are launch-bound: its step solves replay graphs too
+            m->graphs_small = S_ == 1 && n_nodes <= kGraphSmallRows;
             if (S_ > 1) {  // ensembles solve device-driven by default
                 dd_alloc(m);
                 m->dd_on = true;
@@ -777,6 +779,7 @@ rafem_status rafem_mesh_set_graphs(rafem_mesh m, int32_t enable) {
     return guard([&]() -> rafem_status {
         check_device(m);
         m->use_graphs = enable != 0;
+        m->graphs_small = false;  // an explicit choice replaces the size rule
         return RAFEM_OK;
     });
 }

@@ -457,6 +457,7 @@ struct rafem_mesh_s {
     bool tuned = false;                   // slab shapes picked by the autotuner
     bool tuned_from_cache = false;        // ... taken from its on-disk cache
     bool use_graphs = false;              // iteration chunks captured as HIP graphs
+    bool graphs_small = false;            // ...in rafem_step's solves of a small single mesh
     hipStream_t gstream = nullptr;        // capture stream
     struct GraphEntry {
         int kind;
@@ -596,6 +597,7 @@ struct rafem_mesh_s {
 
 namespace rafem {
 constexpr int kProfCap = 2048;
+constexpr int64_t kGraphSmallRows = 262144;     // single meshes up to this size replay graphs
 constexpr int kDdMaxRounds = 15;                  // refinements enqueued per mixed solve, at most
 constexpr int kDdSlots = kDdMaxRounds + 1;        // log slots of one solve
 constexpr int kDdSlack = 3;                       // iterations added to every budget

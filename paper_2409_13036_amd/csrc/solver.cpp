@@ -271,7 +271,7 @@ rafem_status pcg64(rafem_mesh m, const Mat& A, const Samples& smp, const double*
 
     const Iter64 iter{m, &A, &cfg, dinv, x, st, smp, itb};
     hipGraphExec_t graph = nullptr;
-    if (m->use_graphs && !m->prof_on)
+    if ((m->use_graphs || (m->graphs_small && hints)) && !m->prof_on)
         graph = chunk_graph(m, 0, A.v, x, dinv, A.sell ? (const void*)A.sptr : (const void*)A.rp,
                             iter, itb);
     int launched = 0;
@@ -320,7 +320,7 @@ rafem_status pcg_mixed(rafem_mesh m, const Mat& A, const Samples& smp, const dou
     }
     const Iter32 iter{m, &A, &m->spmv32, dinv32, inner, smp, itb};
     hipGraphExec_t graph = nullptr;
-    if (m->use_graphs && !m->prof_on)
+    if ((m->use_graphs || (m->graphs_small && hints)) && !m->prof_on)
         graph = chunk_graph(m, 1, A.v32, dinv32, A.sell ? (const void*)A.sptr : (const void*)A.rp,
                             nullptr, iter, itb);
     int total_inner = 0, launched_total = 0, outer_steps = 0;
