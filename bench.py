@@ -357,6 +357,38 @@ def adjoint_leg(args) -> dict:
             "fd": rows}
 
 
+def adjoint_timing_leg(args) -> dict:
+    """The differentiation workload's timing alone (101^3 hex, 60 coupled steps, lesion
+    loss, reverse sweep with checkpoints every 10 steps, tol 1e-14), for the default run;
+    `--adjoint` adds the finite-difference checks."""
+    import torch
+    import rafem_inputs as ri
+    from paper_2409_13036_amd.adjoint import lesion_loss
+    from paper_2409_13036_amd.sim import DeviceProblem
+
+    p = ri.config3(n=args.n, steps=args.adj_steps)
+    dp = DeviceProblem(p)
+    k = torch.tensor(p.k_e, dtype=torch.float64, device=dp.dev, requires_grad=True)
+    w = torch.tensor(p.perf_e, dtype=torch.float64, device=dp.dev, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = lesion_loss(dp, k, w, p.steps, checkpoint_every=10, tol=1e-14)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = {"workload": f"C3 adjoint, {args.n}^3 hex, {p.steps} steps, checkpoints every 10",
+           "loss": float(L.detach()), "forward_s": t1 - t0, "backward_s": t2 - t1,
+           "grad_k_norm": float(torch.linalg.norm(k.grad)),
+           "grad_w_norm": float(torch.linalg.norm(w.grad)),
+           "fd_checks": "tests/test_gpu_adjoint.py at this size; bench.py --adjoint for 32"}
+    dp.close()
+    print(f"[bench] adjoint: forward {t1 - t0:.2f} s, backward {t2 - t1:.2f} s",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def fd_rows(dp, p, gk, gw, n_k: int, n_w: int, seed: int = 0, tol: float = 1e-14) -> list:
     """Finite-difference checks of the adjoint gradients (gk, gw) of problem p on device
     problem dp: n_k conductivity singles and n_w perfusion singles drawn with
@@ -899,6 +931,8 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="run only the differentiation workload (timing + finite-difference check)")
     ap.add_argument("--adj-steps", type=int, default=60)
+    ap.add_argument("--no-adjoint-timing", action="store_true",
+                    help="leave the differentiation timing out of the default run")
     ap.add_argument("--fd-params", type=int, default=32)
     ap.add_argument("--workload", choices=["c1", "c2"], default="c1",
                     help="c1: 101^3 hex (default); c2: 161^3-node jittered Kuhn tets")
@@ -1094,6 +1128,8 @@ def main():
         line["monolithic"] = mono_leg(dp, args)
     dp.close()
     del dp
+    if not args.no_adjoint_timing and args.workload == "c1":
+        line["adjoint"] = adjoint_timing_leg(args)
     if not args.no_batch and args.workload == "c1":
         line["batch"] = batch_leg(args)
     print(json.dumps(line), flush=True)
