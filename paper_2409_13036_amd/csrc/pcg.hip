@@ -430,15 +430,20 @@ __device__ __forceinline__ void sell_rows(const RowArgs<T>& a) {
     }
 }
 
+// Every product kernel asks for room for 6 workgroups of WG lanes per CU, i.e. 6 wavefronts
+// per SIMD: that caps the FP64 products at 80 VGPRs (74 used, no spills) and lifts them from
+// 5 to 6 resident wavefronts, more value loads in flight; the FP32 ones hold 7 either way.
+constexpr int kSellMinBlocks = 6;
+
 // DELTA: the layout's slabs read 16-bit offsets (else 32-bit columns).
 template <typename T, int MODE, bool DELTA>
-__global__ __launch_bounds__(WG) void k_sell(RowArgs<T> a) {
+__global__ __launch_bounds__(WG, kSellMinBlocks) void k_sell(RowArgs<T> a) {
     sell_rows<T, MODE, DELTA ? 1 : 0, false>(a);
 }
 
 // Layouts with both kinds of per-slot columns.
 template <typename T, int MODE>
-__global__ __launch_bounds__(WG) void k_sell_wide(RowArgs<T> a) {
+__global__ __launch_bounds__(WG, kSellMinBlocks) void k_sell_wide(RowArgs<T> a) {
     sell_rows<T, MODE, 2, false>(a);
 }
 
@@ -446,12 +451,12 @@ __global__ __launch_bounds__(WG) void k_sell_wide(RowArgs<T> a) {
 // value slots (chosen by the autotuner): the prefix can stay in the Infinity Cache from one
 // product to the next while the rest streams past it.
 template <typename T, int MODE, bool DELTA>
-__global__ __launch_bounds__(WG) void k_sell_nt(RowArgs<T> a) {
+__global__ __launch_bounds__(WG, kSellMinBlocks) void k_sell_nt(RowArgs<T> a) {
     sell_rows<T, MODE, DELTA ? 1 : 0, true>(a);
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(WG) void k_sell_wide_nt(RowArgs<T> a) {
+__global__ __launch_bounds__(WG, kSellMinBlocks) void k_sell_wide_nt(RowArgs<T> a) {
     sell_rows<T, MODE, 2, true>(a);
 }
 
