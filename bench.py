@@ -70,9 +70,10 @@ def spmv_kernel_name(mesh, fp32: bool) -> str:
     t = "float" if fp32 else "double"
     st = mesh.stats()
     nt = "_nt" if (st.streamed_values32 if fp32 else st.streamed_values) else ""
+    mb = st.launch_bound32 if fp32 else st.launch_bound
     if st.int16_columns and st.int32_column_slabs:
-        return f"k_sell_wide{nt}<{t}, 1>"
-    return f"k_sell{nt}<{t}, 1, {'true' if st.int16_columns else 'false'}>"
+        return f"k_sell_wide{nt}<{t}, 1, {mb}>"
+    return f"k_sell{nt}<{t}, 1, {'true' if st.int16_columns else 'false'}, {mb}>"
 
 
 def copy_probe(mib: int) -> None:

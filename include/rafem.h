@@ -47,7 +47,7 @@ extern "C" {
 #endif
 
 /* Raised whenever a declaration below changes (a struct's layout, a signature). */
-#define RAFEM_ABI_VERSION 2
+#define RAFEM_ABI_VERSION 3
 
 typedef int32_t rafem_status;
 #define RAFEM_OK            0  /* success */
@@ -153,6 +153,10 @@ typedef struct {
     int32_t streamed_values32;   /* the same for the FP32 SpMV */
     int64_t resident_slots;      /* that prefix: value slots read with ordinary loads (FP64) */
     int64_t resident_slots32;    /* the same for the FP32 SpMV */
+    int32_t launch_bound;        /* resident workgroups per CU the FP64 SpMV kernel is compiled
+                                    for: 1 (the compiler's register budget) or 6 (registers
+                                    capped so that 6 fit); autotuned, the same bits either way */
+    int32_t launch_bound32;      /* the same for the FP32 SpMV */
 } rafem_mesh_stats;
 
 /* Build a mesh on the current device.

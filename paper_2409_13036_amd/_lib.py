@@ -62,7 +62,8 @@ class MeshStats(C.Structure):
                 ("device_driven_solves", C.c_int64), ("device_driven_redone", C.c_int64),
                 ("int32_column_slabs", C.c_int64), ("streamed_values", C.c_int32),
                 ("streamed_values32", C.c_int32), ("resident_slots", C.c_int64),
-                ("resident_slots32", C.c_int64)]
+                ("resident_slots32", C.c_int64), ("launch_bound", C.c_int32),
+                ("launch_bound32", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -182,7 +183,7 @@ for _name in EXPORTS:
         getattr(_lib, _name).restype = C.c_int32
 
 # the structures above mirror include/rafem.h at this version
-ABI_VERSION = 2
+ABI_VERSION = 3
 if _lib.rafem_abi_version() != ABI_VERSION:
     raise ImportError(f"{_lib._name} has ABI version {_lib.rafem_abi_version()}, the binding "
                       f"expects {ABI_VERSION}: rebuild the library")

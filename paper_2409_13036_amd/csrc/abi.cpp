@@ -831,6 +831,8 @@ rafem_status rafem_mesh_get_stats(rafem_mesh m, rafem_mesh_stats* out) {
         out->streamed_values32 = m->spmv32.stream;
         out->resident_slots = m->spmv.stream ? m->spmv.resident : 0;
         out->resident_slots32 = m->spmv32.stream ? m->spmv32.resident : 0;
+        out->launch_bound = m->spmv.min_blocks;
+        out->launch_bound32 = m->spmv32.min_blocks;
         return RAFEM_OK;
     });
 }

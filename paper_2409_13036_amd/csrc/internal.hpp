@@ -103,7 +103,9 @@ struct SpmvConfig {
     int slabs_per_block;  // SELL kernels: 64-row slabs per 256-thread workgroup (multiple of 4)
     int stream = 0;       // SELL kernels: 1 = matrix values read with nontemporal loads...
     int resident = 0;     // ...past this many value slots (the prefix with ordinary loads)
+    int min_blocks = 1;   // SELL kernels: launch bound in workgroups per CU, 1 or kSellMinBlocks
 };
+constexpr int kSellMinBlocks = 6;
 
 SpmvConfig choose_spmv_config(int64_t n, int64_t nnz);
 int blocks_for(int64_t n, int rows_per_block);

@@ -430,33 +430,34 @@ __device__ __forceinline__ void sell_rows(const RowArgs<T>& a) {
     }
 }
 
-// Every product kernel asks for room for 6 workgroups of WG lanes per CU, i.e. 6 wavefronts
-// per SIMD: that caps the FP64 products at 80 VGPRs (74 used, no spills) and lifts them from
-// 5 to 6 resident wavefronts, more value loads in flight; the FP32 ones hold 7 either way.
-constexpr int kSellMinBlocks = 6;
-
-// DELTA: the layout's slabs read 16-bit offsets (else 32-bit columns).
-template <typename T, int MODE, bool DELTA>
-__global__ __launch_bounds__(WG, kSellMinBlocks) void k_sell(RowArgs<T> a) {
+// MB: the resident workgroups per CU the kernel is compiled for (launch bound).  1 leaves
+// the register budget to the compiler (FP64 products: 84-98 VGPRs, 4-5 wavefronts per SIMD);
+// kSellMinBlocks (6) caps it at 80 VGPRs, so 6 wavefronts per SIMD with fewer loads in
+// flight in each (no spills in any variant).  Which one is faster depends on the layout
+// (more resident wavefronts pay on some orderings and lose on others), so the autotuner
+// picks per matrix; both give the same bits.
+template <typename T, int MODE, bool DELTA, int MB>
+__global__ __launch_bounds__(WG, MB) void k_sell(RowArgs<T> a) {
+    // DELTA: the layout's slabs read 16-bit offsets (else 32-bit columns)
     sell_rows<T, MODE, DELTA ? 1 : 0, false>(a);
 }
 
 // Layouts with both kinds of per-slot columns.
-template <typename T, int MODE>
-__global__ __launch_bounds__(WG, kSellMinBlocks) void k_sell_wide(RowArgs<T> a) {
+template <typename T, int MODE, int MB>
+__global__ __launch_bounds__(WG, MB) void k_sell_wide(RowArgs<T> a) {
     sell_rows<T, MODE, 2, false>(a);
 }
 
 // The same with the matrix values read by nontemporal loads past the first `resident`
 // value slots (chosen by the autotuner): the prefix can stay in the Infinity Cache from one
 // product to the next while the rest streams past it.
-template <typename T, int MODE, bool DELTA>
-__global__ __launch_bounds__(WG, kSellMinBlocks) void k_sell_nt(RowArgs<T> a) {
+template <typename T, int MODE, bool DELTA, int MB>
+__global__ __launch_bounds__(WG, MB) void k_sell_nt(RowArgs<T> a) {
     sell_rows<T, MODE, DELTA ? 1 : 0, true>(a);
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(WG, kSellMinBlocks) void k_sell_wide_nt(RowArgs<T> a) {
+template <typename T, int MODE, int MB>
+__global__ __launch_bounds__(WG, MB) void k_sell_wide_nt(RowArgs<T> a) {
     sell_rows<T, MODE, 2, true>(a);
 }
 
@@ -868,6 +869,14 @@ void launch_csr_kernel(int lanes, int nb, const RowArgs<T>& a, hipStream_t s, hi
     }
 }
 
+// The slab kernel for this layout's column kinds and the configured value loads.
+template <typename T, int MODE, int MB>
+void (*sell_kernel(const Mat& A, int stream))(RowArgs<T>) {
+    if (A.sdel && A.wide) return stream ? k_sell_wide_nt<T, MODE, MB> : k_sell_wide<T, MODE, MB>;
+    if (A.sdel) return stream ? k_sell_nt<T, MODE, true, MB> : k_sell<T, MODE, true, MB>;
+    return stream ? k_sell_nt<T, MODE, false, MB> : k_sell<T, MODE, false, MB>;
+}
+
 // One launcher for both layouts.  Returns {grid size, rows per block}.
 template <typename T, int MODE>
 GridInfo launch_rows(const Mat& A, const T* vals, const SpmvConfig& c, const T* x, T* y,
@@ -884,15 +893,10 @@ GridInfo launch_rows(const Mat& A, const T* vals, const SpmvConfig& c, const T* 
         g.nb = blocks_for(A.nslabs, kSlabGroup);  // partial slots: one per group of slabs
         g.rpb = kSlabGroup * WAVE;
         if (nblk > 0) {
-            if (A.sdel && A.wide)
-                launch_timed(c.stream ? k_sell_wide_nt<T, MODE> : k_sell_wide<T, MODE>, nblk, s,
-                             ev0, ev1, a);
-            else if (A.sdel)
-                launch_timed(c.stream ? k_sell_nt<T, MODE, true> : k_sell<T, MODE, true>, nblk, s,
-                             ev0, ev1, a);
-            else
-                launch_timed(c.stream ? k_sell_nt<T, MODE, false> : k_sell<T, MODE, false>, nblk,
-                             s, ev0, ev1, a);
+            void (*k)(RowArgs<T>) = c.min_blocks == kSellMinBlocks
+                                        ? sell_kernel<T, MODE, kSellMinBlocks>(A, c.stream)
+                                        : sell_kernel<T, MODE, 1>(A, c.stream);
+            launch_timed(k, nblk, s, ev0, ev1, a);
         }
     } else {
         g.nb = blocks_for(A.n, c.rows_per_block);

@@ -601,7 +601,8 @@ namespace {
 
 // On-disk cache of the tuned SpMV configurations: one line per (device, layout) key,
 // "<key> <slabs per block FP64> <slabs per block FP32> <streamed FP64> <streamed FP32>
-// <resident slots FP64> <resident slots FP32>", in the file named by RAFEM_TUNE_CACHE, else
+// <resident slots FP64> <resident slots FP32> <launch bound FP64> <launch bound FP32>", in the
+// file named by RAFEM_TUNE_CACHE, else
 // $HOME/.cache/rafem/spmv_tune.txt.  Unreadable or unwritable files, and lines of another
 // form, are ignored (the configurations are then timed).
 std::string tune_cache_path() {
@@ -629,19 +630,24 @@ bool tune_lookup(const std::string& key, SpmvConfig& c64, SpmvConfig& c32) {
     std::FILE* f = std::fopen(path.c_str(), "r");
     if (!f) return false;
     char line[640], k[512];
-    int a = 0, b = 0, na = 0, nb = 0, ra = 0, rb = 0;
+    int a = 0, b = 0, na = 0, nb = 0, ra = 0, rb = 0, ma = 0, mb = 0;
     bool found = false;
+    auto bound_ok = [](int v) { return v == 1 || v == kSellMinBlocks; };
     while (std::fgets(line, sizeof(line), f)) {
-        if (std::sscanf(line, "%511s %d %d %d %d %d %d", k, &a, &b, &na, &nb, &ra, &rb) != 7)
+        if (std::sscanf(line, "%511s %d %d %d %d %d %d %d %d", k, &a, &b, &na, &nb, &ra, &rb, &ma,
+                        &mb) != 9)
             continue;
         if (key == k && (a == 8 || a == 16) && (b == 8 || b == 16) && (na == 0 || na == 1) &&
-            (nb == 0 || nb == 1) && ra >= 0 && rb >= 0) {  // last entry wins
+            (nb == 0 || nb == 1) && ra >= 0 && rb >= 0 && bound_ok(ma) &&
+            bound_ok(mb)) {  // last entry wins
             c64.slabs_per_block = a;
             c32.slabs_per_block = b;
             c64.stream = na;
             c32.stream = nb;
             c64.resident = ra;
             c32.resident = rb;
+            c64.min_blocks = ma;
+            c32.min_blocks = mb;
             found = true;
         }
     }
@@ -662,8 +668,9 @@ void tune_store(const std::string& key, const SpmvConfig& c64, const SpmvConfig&
     }
     std::FILE* f = std::fopen(path.c_str(), "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), c64.slabs_per_block,
-                 c32.slabs_per_block, c64.stream, c32.stream, c64.resident, c32.resident);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %d\n", key.c_str(), c64.slabs_per_block,
+                 c32.slabs_per_block, c64.stream, c32.stream, c64.resident, c32.resident,
+                 c64.min_blocks, c32.min_blocks);
     std::fclose(f);
 }
 
@@ -671,7 +678,8 @@ void tune_store(const std::string& key, const SpmvConfig& c64, const SpmvConfig&
 
 void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
     // SELL kernel configuration: 2 or 4 slabs per wavefront (one or two groups of partial
-    // sums per workgroup, so results do not depend on the choice), and the matrix values
+    // sums per workgroup, so results do not depend on the choice), the kernel's launch bound
+    // (the compiler's register budget, or one that keeps 6 workgroups per CU), and the matrix values
     // read with ordinary loads, or with nontemporal loads past a prefix of 0 or 96 MiB read
     // with ordinary ones (streaming pays when the values do not fit the Infinity Cache and
     // loses when they do, since the solve's products then re-read them from it; a prefix
@@ -708,11 +716,12 @@ void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
         for (int64_t mib : {0, 96})
             if (mib * 1048576 < value_bytes)
                 loads.push_back({1, (int)(mib * 1048576 / (prec ? 4 : 8))});
-        for (int cand = 0; cand < 2 * (int)loads.size(); ++cand) {
+        for (int cand = 0; cand < 4 * (int)loads.size(); ++cand) {
             SpmvConfig c = target;
             c.slabs_per_block = 4 * (cand % 2 ? 4 : 2);
-            c.stream = loads[cand / 2].first;
-            c.resident = loads[cand / 2].second;
+            c.min_blocks = (cand / 2) % 2 ? kSellMinBlocks : 1;
+            c.stream = loads[cand / 4].first;
+            c.resident = loads[cand / 4].second;
             auto run = [&](hipEvent_t a0, hipEvent_t a1) {
                 if (prec) launch_spmv_dot32(A, c, m->p32, m->q32, m->part_pq, chk, smp, s, a0, a1);
                 else launch_spmv_dot64(A, c, m->p, m->q, m->part_pq, chk, smp, s, a0, a1);

@@ -32,14 +32,16 @@ def test_spmv_shape_cache_is_written_then_reused(torch_cuda, tmp_path, monkeypat
         dp.step(1e-12, "mixed")
         st = dp.mesh.stats()
         out.append((st.tuned_from_cache, st.slabs_per_block, st.slabs_per_block32,
-                    to_host(dp.T), to_host(dp.V)))
+                    st.launch_bound, st.launch_bound32, to_host(dp.T), to_host(dp.V)))
         dp.close()
     lines = cache.read_text().split("\n")
     print(f"[tune] cache: {lines[0]}", flush=True)
     assert out[0][0] == 0 and out[1][0] == 1       # timed first, then read from the cache
-    assert out[0][1:3] == out[1][1:3]
+    assert out[0][1:5] == out[1][1:5]
+    assert out[0][3] in (1, 6) and out[0][4] in (1, 6)
+    assert len(lines[0].split()) == 9
     assert len([l for l in lines if l.strip()]) == 1
-    assert np.array_equal(out[0][3], out[1][3]) and np.array_equal(out[0][4], out[1][4])
+    assert np.array_equal(out[0][5], out[1][5]) and np.array_equal(out[0][6], out[1][6])
 
 
 def test_mixed_tuner_picks_a_candidate_and_caches_it(torch_cuda, tmp_path):
@@ -85,12 +87,13 @@ def _shuffled(p):
 
 @pytest.mark.parametrize("mesh", ["hex21", "tet13", "hex41-shuffled", "hex41-far-swaps"])
 def test_streamed_value_loads_give_the_same_bits(torch_cuda, tmp_path, monkeypatch, mesh):
-    """The SpMV configuration read from the cache is used as written, and the nontemporal
-    reads of the matrix values (the autotuner's choice for matrices beyond the Infinity
-    Cache), whole or past a prefix read with ordinary loads, change no bit of a coupled
-    step, in FP64 and mixed precision, on every slab kind: shared offset lists and 16-bit
-    offsets (hex21, tet13), 32-bit columns (shuffled), and both widths in one layout (nodes
-    swapped 40,000 positions apart)."""
+    """The SpMV configuration read from the cache is used as written, and neither the
+    nontemporal reads of the matrix values (the autotuner's choice for matrices beyond the
+    Infinity Cache), whole or past a prefix read with ordinary loads, nor the kernels' launch
+    bound (1 or 6 resident workgroups per CU) changes a bit of a coupled step, in FP64 and
+    mixed precision, on every slab kind: shared offset lists and 16-bit offsets (hex21,
+    tet13), 32-bit columns (shuffled), and both widths in one layout (nodes swapped 40,000
+    positions apart)."""
     from paper_2409_13036_amd.sim import DeviceProblem
     cache = tmp_path / "spmv_tune.txt"
     monkeypatch.setenv("RAFEM_TUNE_CACHE", str(cache))
@@ -104,8 +107,8 @@ def test_streamed_value_loads_give_the_same_bits(torch_cuda, tmp_path, monkeypat
     dp.close()
     key, spb64, spb32 = cache.read_text().split()[:3]
     out = {}
-    for nt, res in ((0, 0), (1, 0), (1, half)):
-        cache.write_text(f"{key} {spb64} {spb32} {nt} {nt} {res} {res}\n")
+    for nt, res, mb in ((0, 0, 1), (1, 0, 6), (1, half, 1), (0, 0, 6)):
+        cache.write_text(f"{key} {spb64} {spb32} {nt} {nt} {res} {res} {mb} {mb}\n")
         dp = DeviceProblem(p)
         states = []
         for prec in ("fp64", "mixed"):
@@ -121,9 +124,10 @@ def test_streamed_value_loads_give_the_same_bits(torch_cuda, tmp_path, monkeypat
         assert st.tuned_from_cache == 1
         assert st.streamed_values == nt and st.streamed_values32 == nt
         assert st.resident_slots == res and st.resident_slots32 == res
-        out[(nt, res)] = states
+        assert st.launch_bound == mb and st.launch_bound32 == mb
+        out[(nt, res, mb)] = states
         dp.close()
-    ref = out[(0, 0)]
+    ref = out[(0, 0, 1)]
     for key2, states in out.items():
         for (Ta, Va), (Tb, Vb) in zip(ref, states):
             assert np.array_equal(Ta, Tb) and np.array_equal(Va, Vb), key2

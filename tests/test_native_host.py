@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol(rafem):
     for name in declared:
         assert hasattr(lib, name), name
     assert set(declared) == set(rafem.EXPORTS)
-    assert rafem.abi_version() == rafem.ABI_VERSION == 2
+    assert rafem.abi_version() == rafem.ABI_VERSION == 3
 
 
 @pytest.mark.parametrize("kind,n", [("hex", 5), ("hex", 21), ("tet", 5), ("tet", 17)])
