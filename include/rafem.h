@@ -377,8 +377,8 @@ rafem_status rafem_spmv(rafem_mesh mesh, const int32_t* row_ptr_d, const int32_t
 /* The product of a time step's solves, y = A x, run by the very kernels the PCG
  * iterations use on the mesh's own slab layout (Sec. III-A: the solve of the assembled
  * system; Sec. III-B: the structure analysed once per mesh): 64-row slabs with shared
- * column offsets, 16-bit or 32-bit per-row column offsets, the tuned slab shape, and the
- * dot product x.(A x) fused into the product.
+ * column offsets, 16-bit or 32-bit per-row column offsets, the tuned slab shape, launch
+ * bound and value loads, and the dot product x.(A x) fused into the product.
  *   matrix     0: the potential matrix, 1: the bioheat matrix, as the last rafem_step (or
  *              rafem_step_pc / rafem_step_vjp) on this handle assembled them, Dirichlet
  *              rows and columns lifted (E_STATE before such a step)

@@ -700,6 +700,7 @@ void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
     Samples smp{S, m->row_off, m->row_tab};
     PcgState* chk = m->st + 2 * S;
     constexpr int kTuneReps = 5;
+    constexpr double kTuneMargin = 0.98;
     hipEvent_t ev[2 * kTuneReps];
     for (hipEvent_t& e : ev) RAFEM_HIP(hipEventCreate(&e));
     launch_fill(m->p, m->n, 0.0, s);
@@ -753,8 +754,12 @@ void autotune_spmv(rafem_mesh m, const Mat& A, hipStream_t s) {
                 RAFEM_HIP(hipEventElapsedTime(&one, ev[2 * r], ev[2 * r + 1]));
                 ms += one;
             }
-            if (ms < best) {
-                best = ms;
+            // the capped launch bound must be 2% faster to be taken, so that timing noise
+            // between kernels of equal occupancy (the FP32 ones hold 7 wavefronts per SIMD
+            // either way) keeps the compiler's register budget
+            const double eff = c.min_blocks == 1 ? ms : ms / kTuneMargin;
+            if (eff < best) {
+                best = eff;
                 best_c = c;
             }
         }
