@@ -42,6 +42,17 @@ def test_spmv_shape_cache_is_written_then_reused(torch_cuda, tmp_path, monkeypat
     assert len(lines[0].split()) == 9
     assert len([l for l in lines if l.strip()]) == 1
     assert np.array_equal(out[0][5], out[1][5]) and np.array_equal(out[0][6], out[1][6])
+    # a line of the right key with a launch bound the library does not build (3) is
+    # ignored: the shapes are timed again and a valid line is appended
+    f = lines[0].split()
+    cache.write_text(" ".join(f[:7] + ["3", "3"]) + "\n")
+    dp = DeviceProblem(p)
+    dp.step(1e-12, "mixed")
+    st = dp.mesh.stats()
+    assert st.tuned_from_cache == 0 and st.launch_bound in (1, 6)
+    dp.close()
+    lines = [l for l in cache.read_text().split("\n") if l.strip()]
+    assert len(lines) == 2 and lines[1].split()[0] == f[0] and lines[1].split()[7] in ("1", "6")
 
 
 def test_mixed_tuner_picks_a_candidate_and_caches_it(torch_cuda, tmp_path):
